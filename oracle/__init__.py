@@ -1,0 +1,182 @@
+"""FP64 CPU oracle of the Laplace-domain elastodynamic BEM hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's CPU
+baseline may import this package; the product library neither imports nor links it and
+shares no code with it.
+
+* ``bem_oracle.c`` (plain C99, FP64, optional OpenMP): kernel U and T of the paper's
+  Appendix A / Sec. 2.1, collocation entries with the quadrature rules, dense products.
+* ``aca3d.py`` (numpy): the matrix-valued 3D-ACA of Algorithm 1 (Sec. 3) and the
+  matrix-valued ACA with QR/SVD recompression of eq. (ACA) (Sec. 3.1), for small tensors.
+* ``partition.py`` (numpy): the PCA cluster tree and admissibility of Sec. 3.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bem_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile bem_oracle.c with gcc (-O2, OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=gnu99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.oracle_entries.restype = ctypes.c_int
+        L.oracle_entries.argtypes = [dp, ctypes.c_int64, ip, ctypes.c_int64,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int32,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int64, ip, ip, ip, dp]
+        L.oracle_matvec_rows.restype = ctypes.c_int
+        L.oracle_matvec_rows.argtypes = [dp, ctypes.c_int64, ip, ctypes.c_int64,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int32,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int64, ip, ctypes.c_int32, dp, dp]
+        L.oracle_point_entries.restype = ctypes.c_int
+        L.oracle_point_entries.argtypes = [dp, ctypes.c_int64, ip, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int32,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int64, dp, ctypes.c_int64, ip, ip, ip, dp]
+        L.oracle_kernel_point.restype = ctypes.c_int
+        L.oracle_kernel_point.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_tri7.restype = None
+        L.oracle_tri7.argtypes = [dp, dp]
+        L.oracle_gauss_legendre.restype = None
+        L.oracle_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+OP_V, OP_K, OP_HK = 0, 1, 2
+
+
+class Problem:
+    """Mesh + material + frequencies + quadrature options of one oracle evaluation."""
+
+    def __init__(self, nodes, tris, s, rho=1.0, cp=1.0, cs=0.5, near_on=False,
+                 r1=1.5, r2=3.0, self_nt=8, self_nr=8):
+        self.nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        self.tris = np.ascontiguousarray(tris, dtype=np.int32)
+        s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+        self.s = np.ascontiguousarray(np.stack([s.real, s.imag], axis=-1))
+        self.L = int(s.shape[0])
+        self.K = int(self.tris.shape[0])
+        self.rho, self.cp, self.cs = float(rho), float(cp), float(cs)
+        self.near_on = int(bool(near_on))
+        self.r1, self.r2 = float(r1), float(r2)
+        self.self_nt, self.self_nr = int(self_nt), int(self_nr)
+
+    def _common(self):
+        return (_d(self.nodes), self.nodes.shape[0], _i(self.tris), self.K,
+                self.rho, self.cp, self.cs, _d(self.s), self.L)
+
+    def _quad(self, op):
+        return (int(op), self.near_on, self.r1, self.r2, self.self_nt, self.self_nr)
+
+    def entries(self, op, i, j, l):
+        """ENTRY(op, i, j, l) for index arrays -> complex128 [n, 3, 3]."""
+        i, j, l = (np.ascontiguousarray(np.ravel(a), dtype=np.int32) for a in np.broadcast_arrays(i, j, l))
+        n = i.size
+        out = np.zeros((n, 9, 2), dtype=np.float64)
+        rc = lib().oracle_entries(*self._common(), *self._quad(op), n, _i(i), _i(j), _i(l), _d(out))
+        if rc != 0:
+            raise RuntimeError("oracle_entries failed with code %d" % rc)
+        return (out[..., 0] + 1j * out[..., 1]).reshape(n, 3, 3)
+
+    def dense(self, op):
+        """All entries as a complex128 array [L, 3K, 3K] (small meshes only)."""
+        K, L = self.K, self.L
+        ii, jj, ll = np.meshgrid(np.arange(K), np.arange(K), np.arange(L), indexing="ij")
+        E = self.entries(op, ii.ravel(), jj.ravel(), ll.ravel()).reshape(K, K, L, 3, 3)
+        return np.ascontiguousarray(E.transpose(2, 0, 3, 1, 4).reshape(L, 3 * K, 3 * K))
+
+    def point_entries(self, op, pts, p, j, l):
+        """int_{gamma_j} kernel(pts[p], y) dy for field points off the boundary -> [n, 3, 3]."""
+        pts = np.ascontiguousarray(np.reshape(pts, (-1, 3)), dtype=np.float64)
+        p, j, l = (np.ascontiguousarray(np.ravel(a), dtype=np.int32) for a in np.broadcast_arrays(p, j, l))
+        n = p.size
+        out = np.zeros((n, 9, 2), dtype=np.float64)
+        rc = lib().oracle_point_entries(*self._common(), int(op), self.near_on, self.r1, self.r2,
+                                        pts.shape[0], _d(pts), n, _i(p), _i(j), _i(l), _d(out))
+        if rc != 0:
+            raise RuntimeError("oracle_point_entries failed with code %d" % rc)
+        return (out[..., 0] + 1j * out[..., 1]).reshape(n, 3, 3)
+
+    def matvec_rows(self, op, rows, x):
+        """y[r, l, 3q + a] = (A_l x[r, l])[3 rows[q] + a] without storing A; x: [nrhs, L, 3K]."""
+        x = np.asarray(x, dtype=np.complex128)
+        if x.ndim == 2:
+            x = x[None]
+        nrhs = x.shape[0]
+        assert x.shape == (nrhs, self.L, 3 * self.K)
+        rows = np.ascontiguousarray(np.ravel(rows), dtype=np.int32)
+        xr = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
+        y = np.zeros((nrhs, self.L, 3 * rows.size, 2), dtype=np.float64)
+        rc = lib().oracle_matvec_rows(*self._common(), *self._quad(op), rows.size, _i(rows), nrhs, _d(xr), _d(y))
+        if rc != 0:
+            raise RuntimeError("oracle_matvec_rows failed with code %d" % rc)
+        return y[..., 0] + 1j * y[..., 1]
+
+
+def kernel_point(which, x, y, n, s, rho=1.0, cp=1.0, cs=0.5):
+    """U (which=0) or T (which=1) at one point pair -> complex128 [3, 3]."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n = np.ascontiguousarray(n if n is not None else [0.0, 0.0, 1.0], dtype=np.float64)
+    out = np.zeros((9, 2))
+    rc = lib().oracle_kernel_point(int(which), _d(x), _d(y), _d(n), float(np.real(s)), float(np.imag(s)),
+                                   float(rho), float(cp), float(cs), _d(out))
+    if rc != 0:
+        raise RuntimeError("oracle_kernel_point failed")
+    return (out[:, 0] + 1j * out[:, 1]).reshape(3, 3)
+
+
+def tri7():
+    b = np.zeros(21)
+    w = np.zeros(7)
+    lib().oracle_tri7(_d(b), _d(w))
+    return b.reshape(7, 3), w
+
+
+def gauss_legendre(n):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    lib().oracle_gauss_legendre(int(n), _d(x), _d(w))
+    return x, w
+
+
+def num_threads():
+    return int(lib().oracle_num_threads())

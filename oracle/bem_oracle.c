@@ -1,0 +1,535 @@
+/*
+ * bem_oracle.c -- plain, slow, FP64 reference of the Laplace-domain collocation BEM
+ * entries and dense products.  TEST INFRASTRUCTURE ONLY: tests, the smoke check and the
+ * CPU baseline of the benchmark call it; the product library never links or calls it.
+ *
+ * What it computes (Keshava & Schanz, "A 3D-ACA accelerated time domain BEM for
+ * elastodynamics"):
+ *   - U(r, s): Laplace transform of the full-space displacement tensor of Appendix A,
+ *     eq. (A.2), taken with an impulse source:
+ *         4 pi rho U_ij = f0_ij I1 + f1_ij e1 + f2_ij e2,
+ *         f0 = (3 rh_i rh_j - d_ij)/r, f1 = rh_i rh_j/(r c1^2), f2 = (d_ij - rh_i rh_j)/(r c2^2),
+ *         e_a = exp(-s r / c_a),  I1 = int_{1/c1}^{1/c2} lam exp(-s lam r) dlam.
+ *     (In the printed f0, f1, f2 the symbol r_i is the unit vector; dimensions require it.)
+ *   - T(x, y, n, s): traction at y (normal n) of the field U_i.(y - x) of a unit load in
+ *     direction i at x, from the stress law of Sec. 2.1,
+ *         sigma = rho (c1^2 - 2 c2^2) div(u) I + rho c2^2 (grad u + grad u^T),  t = sigma n.
+ *     The double layer acts as (K u)_i = sum_j int T_ij u_j (eq. (DLP)).
+ *   - Collocation entries at element centroids with piecewise-constant trial functions
+ *     (eq. (discrVK), collocation points at midpoints, Sec. 2.3):
+ *         V[i,j](s) = int_{gamma_j} U(y - x_i, s) dy,   K[i,j](s) = PV int_{gamma_j} T dy.
+ *   - Quadrature (Sec. 2.3 names Duffy for the singular collocation integrals; the rest
+ *     is this project's reading, identical on both sides of every parity test):
+ *       regular pair : 7-point degree-5 triangle rule;
+ *       near pair    : the same rule on 4^m congruent sub-triangles, m = 2 if
+ *                      |x_i - c_j| < r1 * lmax_j, m = 1 if < r2 * lmax_j (switchable);
+ *       self pair V  : polar Duffy about the centroid, 3 sub-triangles, n_theta x n_rho
+ *                      Gauss-Legendre points;
+ *       self pair K  : Cauchy principal value in the same polar coordinates with the
+ *                      leading 1/rho^2 part g(theta) = c2^2/(4 pi c1^2) (rh_i n_j - rh_j n_i)
+ *                      integrated analytically in rho (its log terms cancel over 2 pi).
+ *   - op 2 adds the free term C = I/2 of eq. (SBIE) at smooth points to K.
+ *
+ * Everything is written per entry, per quadrature point, per frequency; no blocking,
+ * no reuse across frequencies, no shared tables with the GPU library.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+typedef struct {
+    double rho, c1, c2;
+} material;
+
+typedef struct {
+    int near_on;
+    double r1, r2;
+    int self_nt, self_nr;
+} quadopts;
+
+/* ---------------------------------------------------------------- quadrature rules */
+
+/* 7-point degree-5 rule on a triangle in barycentric coordinates; weights sum to 1. */
+void oracle_tri7(double *bary, double *w)
+{
+    const double s15 = sqrt(15.0);
+    const double a = (6.0 - s15) / 21.0, b = (6.0 + s15) / 21.0;
+    const double wa = (155.0 - s15) / 1200.0, wb = (155.0 + s15) / 1200.0;
+    double B[7][3] = {
+        {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0},
+        {a, a, 1.0 - 2.0 * a}, {a, 1.0 - 2.0 * a, a}, {1.0 - 2.0 * a, a, a},
+        {b, b, 1.0 - 2.0 * b}, {b, 1.0 - 2.0 * b, b}, {1.0 - 2.0 * b, b, b},
+    };
+    double W[7] = {9.0 / 40.0, wa, wa, wa, wb, wb, wb};
+    for (int q = 0; q < 7; ++q) {
+        for (int k = 0; k < 3; ++k) bary[3 * q + k] = B[q][k];
+        w[q] = W[q];
+    }
+}
+
+/* Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on the three-term
+ * Legendre recurrence. */
+void oracle_gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        /* recompute derivative at the converged node */
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) { p1 = z; p0 = 1.0; }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* ------------------------------------------------------------------ the kernel */
+
+/* int_{1/c1}^{1/c2} lam^p exp(-alpha lam) dlam for p = 1, 2 and alpha = s r. */
+static cplx lam_integral(int p, cplx alpha, double c1, double c2)
+{
+    const double a = 1.0 / c1, b = 1.0 / c2;
+    if (cabs(alpha) * b < 2.0) {
+        /* Taylor series of the exponential, integrated term by term */
+        cplx sum = 0.0, term = 1.0; /* term = (-alpha)^n / n! */
+        for (int n = 0; n < 400; ++n) {
+            double e = n + p + 1.0;
+            cplx add = term * (pow(b, e) - pow(a, e)) / e;
+            sum += add;
+            if (n > 4 && cabs(add) < 1e-19 * cabs(sum)) break;
+            term *= -alpha / (n + 1.0);
+        }
+        return sum;
+    }
+    /* closed form of the antiderivative F(lam) = -exp(-alpha lam) * poly */
+    cplx Fa, Fb;
+    if (p == 1) {
+        Fb = -cexp(-alpha * b) * (b / alpha + 1.0 / (alpha * alpha));
+        Fa = -cexp(-alpha * a) * (a / alpha + 1.0 / (alpha * alpha));
+    } else {
+        Fb = -cexp(-alpha * b) * (b * b / alpha + 2.0 * b / (alpha * alpha) + 2.0 / (alpha * alpha * alpha));
+        Fa = -cexp(-alpha * a) * (a * a / alpha + 2.0 * a / (alpha * alpha) + 2.0 / (alpha * alpha * alpha));
+    }
+    return Fb - Fa;
+}
+
+/* U(y - x, s), 3x3 row-major. */
+static void kernel_U(const double *rv, cplx s, const material *m, cplx *U)
+{
+    double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+    double rh[3] = {rv[0] / r, rv[1] / r, rv[2] / r};
+    cplx I1 = lam_integral(1, s * r, m->c1, m->c2);
+    cplx e1 = cexp(-s * r / m->c1), e2 = cexp(-s * r / m->c2);
+    double pref = 1.0 / (4.0 * M_PI * m->rho);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double dij = (i == j) ? 1.0 : 0.0;
+            double P = rh[i] * rh[j];
+            double f0 = (3.0 * P - dij) / r;
+            double f1 = P / (r * m->c1 * m->c1);
+            double f2 = (dij - P) / (r * m->c2 * m->c2);
+            U[3 * i + j] = pref * (f0 * I1 + f1 * e1 + f2 * e2);
+        }
+}
+
+/* Gradient dU_ij/dy_k (r = y - x) by the product rule on the form of kernel_U. */
+static void kernel_gradU(const double *rv, cplx s, const material *m, cplx *G /* [i][j][k] */)
+{
+    double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+    double rh[3] = {rv[0] / r, rv[1] / r, rv[2] / r};
+    double c1 = m->c1, c2 = m->c2;
+    cplx I1 = lam_integral(1, s * r, c1, c2);
+    cplx I2 = lam_integral(2, s * r, c1, c2);
+    cplx e1 = cexp(-s * r / c1), e2 = cexp(-s * r / c2);
+    /* radial scalar factors and their r-derivatives */
+    cplx a = I1 / r;
+    cplx da = (-s * I2) / r - I1 / (r * r);               /* dI1/dr = -s I2 */
+    cplx b = e1 / (c1 * c1 * r);
+    cplx db = e1 / (c1 * c1) * (-(s / c1) / r - 1.0 / (r * r));
+    cplx c = e2 / (c2 * c2 * r);
+    cplx dc = e2 / (c2 * c2) * (-(s / c2) / r - 1.0 / (r * r));
+    double pref = 1.0 / (4.0 * M_PI * m->rho);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) {
+                double dij = (i == j) ? 1.0 : 0.0, dik = (i == k) ? 1.0 : 0.0, djk = (j == k) ? 1.0 : 0.0;
+                double P = rh[i] * rh[j];
+                double dP = (dik * rh[j] + djk * rh[i] - 2.0 * rh[i] * rh[j] * rh[k]) / r;
+                cplx v = (3.0 * P - dij) * da * rh[k] + 3.0 * a * dP
+                       + P * db * rh[k] + b * dP
+                       + (dij - P) * dc * rh[k] - c * dP;
+                G[9 * i + 3 * j + k] = pref * v;
+            }
+}
+
+/* T_ij(x, y, n, s): traction component j at y of the field of a unit load in direction i. */
+static void kernel_T(const double *x, const double *y, const double *n, cplx s, const material *m, cplx *T)
+{
+    double rv[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+    cplx G[27];
+    kernel_gradU(rv, s, m, G);
+    double lam = m->rho * (m->c1 * m->c1 - 2.0 * m->c2 * m->c2);
+    double mu = m->rho * m->c2 * m->c2;
+    for (int i = 0; i < 3; ++i) {
+        /* displacement field u_j = U_ij, gradient du_j/dy_k = G[i][j][k] */
+        cplx div = G[9 * i + 0] + G[9 * i + 4] + G[9 * i + 8];
+        for (int j = 0; j < 3; ++j) {
+            cplx t = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                cplx eps = 0.5 * (G[9 * i + 3 * j + k] + G[9 * i + 3 * k + j]);
+                cplx sig = ((j == k) ? lam * div : 0.0) + 2.0 * mu * eps;
+                t += sig * n[k];
+            }
+            T[3 * i + j] = t;
+        }
+    }
+}
+
+int oracle_kernel_point(int which, const double *x, const double *y, const double *n,
+                        double sr, double si, double rho, double cp, double cs, double *out)
+{
+    material m = {rho, cp, cs};
+    cplx s = sr + I * si;
+    cplx R[9];
+    if (which == 0) {
+        double rv[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+        kernel_U(rv, s, &m, R);
+    } else if (which == 1) {
+        kernel_T(x, y, n, s, &m, R);
+    } else {
+        return -1;
+    }
+    for (int k = 0; k < 9; ++k) {
+        out[2 * k] = creal(R[k]);
+        out[2 * k + 1] = cimag(R[k]);
+    }
+    return 0;
+}
+
+/* --------------------------------------------------------------- element geometry */
+
+typedef struct {
+    double v[3][3];   /* vertices */
+    double c[3];      /* centroid */
+    double n[3];      /* unit normal (v1-v0)x(v2-v0) */
+    double area;
+    double lmax2;     /* squared longest edge */
+} element;
+
+static void make_element(const double *nodes, const int32_t *tri, element *e)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) e->v[a][k] = nodes[3 * (int64_t)tri[a] + k];
+    for (int k = 0; k < 3; ++k) e->c[k] = (e->v[0][k] + e->v[1][k] + e->v[2][k]) / 3.0;
+    double u[3], w[3], nn[3];
+    for (int k = 0; k < 3; ++k) { u[k] = e->v[1][k] - e->v[0][k]; w[k] = e->v[2][k] - e->v[0][k]; }
+    nn[0] = u[1] * w[2] - u[2] * w[1];
+    nn[1] = u[2] * w[0] - u[0] * w[2];
+    nn[2] = u[0] * w[1] - u[1] * w[0];
+    double len = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    e->area = 0.5 * len;
+    for (int k = 0; k < 3; ++k) e->n[k] = nn[k] / len;
+    double l2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        int b = (a + 1) % 3;
+        double dx = e->v[b][0] - e->v[a][0], dy = e->v[b][1] - e->v[a][1], dz = e->v[b][2] - e->v[a][2];
+        double q = dx * dx + dy * dy + dz * dz;
+        if (q > l2) l2 = q;
+    }
+    e->lmax2 = l2;
+}
+
+/* ----------------------------------------------------------------- integration */
+
+typedef struct {
+    const element *el;     /* all elements */
+    material mat;
+    quadopts qo;
+    double tri_bary[21], tri_w[7];
+    double gl_t[64], gl_tw[64], gl_r[64], gl_rw[64];
+} ctx;
+
+/* integrand value at y for collocation point x and element normal n (op 0: U, else T) */
+static void integrand(int op, const double *x, const double *y, const double *n, cplx s, const material *m, cplx *R)
+{
+    if (op == 0) {
+        double rv[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+        kernel_U(rv, s, m, R);
+    } else {
+        kernel_T(x, y, n, s, m, R);
+    }
+}
+
+/* 7-point rule over the triangle (p0, p1, p2) of area A, accumulated into acc. */
+static void tri_rule(const ctx *C, int op, const double *x, const double *p0, const double *p1, const double *p2,
+                     double A, const double *n, cplx s, cplx *acc)
+{
+    for (int q = 0; q < 7; ++q) {
+        const double *B = &C->tri_bary[3 * q];
+        double y[3];
+        for (int k = 0; k < 3; ++k) y[k] = B[0] * p0[k] + B[1] * p1[k] + B[2] * p2[k];
+        cplx R[9];
+        integrand(op, x, y, n, s, &C->mat, R);
+        for (int t = 0; t < 9; ++t) acc[t] += C->tri_w[q] * A * R[t];
+    }
+}
+
+/* 7-point rule on the 4^m sub-triangles obtained by repeated edge-midpoint splitting. */
+static void subdivided_rule(const ctx *C, int op, const double *x, const double *p0, const double *p1,
+                            const double *p2, double A, const double *n, cplx s, int m, cplx *acc)
+{
+    if (m == 0) {
+        tri_rule(C, op, x, p0, p1, p2, A, n, s, acc);
+        return;
+    }
+    double m01[3], m12[3], m20[3];
+    for (int k = 0; k < 3; ++k) {
+        m01[k] = 0.5 * (p0[k] + p1[k]);
+        m12[k] = 0.5 * (p1[k] + p2[k]);
+        m20[k] = 0.5 * (p2[k] + p0[k]);
+    }
+    subdivided_rule(C, op, x, p0, m01, m20, 0.25 * A, n, s, m - 1, acc);
+    subdivided_rule(C, op, x, m01, p1, m12, 0.25 * A, n, s, m - 1, acc);
+    subdivided_rule(C, op, x, m20, m12, p2, 0.25 * A, n, s, m - 1, acc);
+    subdivided_rule(C, op, x, m01, m12, m20, 0.25 * A, n, s, m - 1, acc);
+}
+
+/* Self element: polar coordinates about the centroid x on the three sub-triangles
+ * (x, v_a, v_b); theta is measured from the foot of the perpendicular onto edge v_a v_b. */
+static void self_rule(const ctx *C, int op, const element *e, cplx s, cplx *acc)
+{
+    const double *x = e->c;
+    const double *n = e->n;
+    const material *m = &C->mat;
+    const double gpref = (m->c2 * m->c2) / (4.0 * M_PI * m->c1 * m->c1);
+    for (int a = 0; a < 3; ++a) {
+        const double *va = e->v[a], *vb = e->v[(a + 1) % 3];
+        double t[3], le = 0.0;
+        for (int k = 0; k < 3; ++k) { t[k] = vb[k] - va[k]; le += t[k] * t[k]; }
+        le = sqrt(le);
+        for (int k = 0; k < 3; ++k) t[k] /= le;
+        double proj = 0.0;
+        for (int k = 0; k < 3; ++k) proj += (x[k] - va[k]) * t[k];
+        double foot[3], p[3], d = 0.0;
+        for (int k = 0; k < 3; ++k) { foot[k] = va[k] + proj * t[k]; p[k] = foot[k] - x[k]; d += p[k] * p[k]; }
+        d = sqrt(d);
+        for (int k = 0; k < 3; ++k) p[k] /= d;
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < 3; ++k) { sa += (va[k] - foot[k]) * t[k]; sb += (vb[k] - foot[k]) * t[k]; }
+        double ta = atan2(sa, d), tb = atan2(sb, d);
+        for (int it = 0; it < C->qo.self_nt; ++it) {
+            double th = 0.5 * (ta + tb) + 0.5 * (tb - ta) * C->gl_t[it];
+            double wth = 0.5 * (tb - ta) * C->gl_tw[it];
+            double R = d / cos(th);
+            double dir[3];
+            for (int k = 0; k < 3; ++k) dir[k] = cos(th) * p[k] + sin(th) * t[k];
+            cplx g[9];
+            if (op != 0) {
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) g[3 * i + j] = gpref * (dir[i] * n[j] - dir[j] * n[i]);
+                for (int q = 0; q < 9; ++q) acc[q] += wth * g[q] * log(R);
+            }
+            for (int ir = 0; ir < C->qo.self_nr; ++ir) {
+                double rho = 0.5 * R * (1.0 + C->gl_r[ir]);
+                double wr = 0.5 * R * C->gl_rw[ir];
+                double y[3];
+                for (int k = 0; k < 3; ++k) y[k] = x[k] + rho * dir[k];
+                cplx Rv[9];
+                integrand(op, x, y, n, s, m, Rv);
+                for (int q = 0; q < 9; ++q) {
+                    cplx f = rho * Rv[q];
+                    if (op != 0) f -= g[q] / rho;
+                    acc[q] += wth * wr * f;
+                }
+            }
+        }
+    }
+}
+
+/* One 3x3 entry: collocation at the centroid of element i, element j, frequency s. */
+static void entry(const ctx *C, int op, int64_t i, int64_t j, cplx s, cplx *out)
+{
+    for (int t = 0; t < 9; ++t) out[t] = 0.0;
+    const element *ei = &C->el[i], *ej = &C->el[j];
+    int kop = (op == 0) ? 0 : 1;
+    if (i == j) {
+        self_rule(C, kop, ej, s, out);
+    } else {
+        int m = 0;
+        if (C->qo.near_on) {
+            double dx = ei->c[0] - ej->c[0], dy = ei->c[1] - ej->c[1], dz = ei->c[2] - ej->c[2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < C->qo.r1 * C->qo.r1 * ej->lmax2) m = 2;
+            else if (d2 < C->qo.r2 * C->qo.r2 * ej->lmax2) m = 1;
+        }
+        subdivided_rule(C, kop, ei->c, ej->v[0], ej->v[1], ej->v[2], ej->area, ej->n, s, m, out);
+    }
+    if (op == 2 && i == j) {
+        out[0] += 0.5;
+        out[4] += 0.5;
+        out[8] += 0.5;
+    }
+}
+
+static int setup(ctx *C, const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
+                 double rho, double cp, double cs, int near_on, double r1, double r2, int self_nt, int self_nr)
+{
+    if (K < 1 || self_nt < 1 || self_nt > 64 || self_nr < 1 || self_nr > 64) return -1;
+    for (int64_t e = 0; e < 3 * K; ++e)
+        if (tris[e] < 0 || tris[e] >= n_nodes) return -2;
+    element *el = (element *)malloc(sizeof(element) * (size_t)K);
+    if (!el) return -3;
+    for (int64_t e = 0; e < K; ++e) make_element(nodes, tris + 3 * e, &el[e]);
+    C->el = el;
+    C->mat.rho = rho;
+    C->mat.c1 = cp;
+    C->mat.c2 = cs;
+    C->qo.near_on = near_on;
+    C->qo.r1 = r1;
+    C->qo.r2 = r2;
+    C->qo.self_nt = self_nt;
+    C->qo.self_nr = self_nr;
+    oracle_tri7(C->tri_bary, C->tri_w);
+    oracle_gauss_legendre(self_nt, C->gl_t, C->gl_tw);
+    oracle_gauss_legendre(self_nr, C->gl_r, C->gl_rw);
+    return 0;
+}
+
+/* Entries out[e] = ENTRY(op, ii[e], jj[e], ll[e]) as [n][9][re, im]. */
+int oracle_entries(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
+                   double rho, double cp, double cs, const double *s, int32_t L,
+                   int op, int near_on, double r1, double r2, int self_nt, int self_nr,
+                   int64_t n, const int32_t *ii, const int32_t *jj, const int32_t *ll, double *out)
+{
+    ctx C;
+    int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, near_on, r1, r2, self_nt, self_nr);
+    if (rc) return rc;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t e = 0; e < n; ++e) {
+        if (ii[e] < 0 || ii[e] >= K || jj[e] < 0 || jj[e] >= K || ll[e] < 0 || ll[e] >= L) { bad = 1; continue; }
+        cplx R[9];
+        entry(&C, op, ii[e], jj[e], s[2 * ll[e]] + I * s[2 * ll[e] + 1], R);
+        for (int t = 0; t < 9; ++t) {
+            out[18 * e + 2 * t] = creal(R[t]);
+            out[18 * e + 2 * t + 1] = cimag(R[t]);
+        }
+    }
+    free((void *)C.el);
+    return bad ? -4 : 0;
+}
+
+/* Dense product on selected rows: y[r][l][3*q + a] = sum_j sum_b ENTRY(rows[q], j, l)[a][b]
+ * x[r][l][3 j + b] for every right-hand side r and frequency l.
+ * x: [nrhs][L][3K] complex, y: [nrhs][L][3*nrows] complex (interleaved re, im). */
+int oracle_matvec_rows(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
+                       double rho, double cp, double cs, const double *s, int32_t L,
+                       int op, int near_on, double r1, double r2, int self_nt, int self_nr,
+                       int64_t nrows, const int32_t *rows, int32_t nrhs, const double *x, double *y)
+{
+    ctx C;
+    int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, near_on, r1, r2, self_nt, self_nr);
+    if (rc) return rc;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) collapse(2) reduction(| : bad)
+    for (int64_t q = 0; q < nrows; ++q) {
+        for (int32_t l = 0; l < L; ++l) {
+            int64_t i = rows[q];
+            if (i < 0 || i >= K) { bad = 1; continue; }
+            cplx s_l = s[2 * l] + I * s[2 * l + 1];
+            cplx acc[64][3];
+            for (int r = 0; r < nrhs && r < 64; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
+            for (int64_t j = 0; j < K; ++j) {
+                cplx E[9];
+                entry(&C, op, i, j, s_l, E);
+                for (int r = 0; r < nrhs && r < 64; ++r) {
+                    const double *xv = x + 2 * (((int64_t)r * L + l) * 3 * K + 3 * j);
+                    cplx xb[3] = {xv[0] + I * xv[1], xv[2] + I * xv[3], xv[4] + I * xv[5]};
+                    for (int a = 0; a < 3; ++a)
+                        acc[r][a] += E[3 * a + 0] * xb[0] + E[3 * a + 1] * xb[1] + E[3 * a + 2] * xb[2];
+                }
+            }
+            for (int r = 0; r < nrhs && r < 64; ++r)
+                for (int a = 0; a < 3; ++a) {
+                    double *yv = y + 2 * (((int64_t)r * L + l) * 3 * nrows + 3 * q + a);
+                    yv[0] = creal(acc[r][a]);
+                    yv[1] = cimag(acc[r][a]);
+                }
+        }
+    }
+    free((void *)C.el);
+    if (nrhs > 64) return -5;
+    return bad ? -4 : 0;
+}
+
+/* Layer integrals from arbitrary field points (not on the boundary):
+ * out[e] = int_{gamma_jj[e]} kernel(pts[pp[e]], y) dy, kernel U (op 0) or T (op 1),
+ * with the regular rule, or the subdivided rule when near_on and the point is close. */
+int oracle_point_entries(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
+                         double rho, double cp, double cs, const double *s, int32_t L,
+                         int op, int near_on, double r1, double r2,
+                         int64_t npts, const double *pts,
+                         int64_t n, const int32_t *pp, const int32_t *jj, const int32_t *ll, double *out)
+{
+    ctx C;
+    int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, near_on, r1, r2, 8, 8);
+    if (rc) return rc;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t e = 0; e < n; ++e) {
+        if (pp[e] < 0 || pp[e] >= npts || jj[e] < 0 || jj[e] >= K || ll[e] < 0 || ll[e] >= L) { bad = 1; continue; }
+        const double *x = pts + 3 * (int64_t)pp[e];
+        const element *ej = &C.el[jj[e]];
+        cplx s_l = s[2 * ll[e]] + I * s[2 * ll[e] + 1];
+        int m = 0;
+        if (near_on) {
+            double dx = x[0] - ej->c[0], dy = x[1] - ej->c[1], dz = x[2] - ej->c[2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < r1 * r1 * ej->lmax2) m = 2;
+            else if (d2 < r2 * r2 * ej->lmax2) m = 1;
+        }
+        cplx R[9];
+        for (int t = 0; t < 9; ++t) R[t] = 0.0;
+        subdivided_rule(&C, op == 0 ? 0 : 1, x, ej->v[0], ej->v[1], ej->v[2], ej->area, ej->n, s_l, m, R);
+        for (int t = 0; t < 9; ++t) {
+            out[18 * e + 2 * t] = creal(R[t]);
+            out[18 * e + 2 * t + 1] = cimag(R[t]);
+        }
+    }
+    free((void *)C.el);
+    return bad ? -4 : 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,211 @@
+"""Seeded synthetic inputs: boundary meshes, gCQ contour points and right-hand sides.
+
+This module holds input generators only.  It computes no kernel entry, quadrature,
+compression or product of the boundary element method, so that the product path and
+the independent oracle can both be fed from it without sharing any of the method's
+arithmetic.
+
+Meshes are flat-triangle surfaces (the boundary approximation of Sec. 2.3, eq. (tri)).
+Triangles are oriented so that (v1 - v0) x (v2 - v0) points out of the bounded body.
+
+* ``cube_grid(n, half)``   -- cube [-half, half]^3, n x n squares per face, each square
+  split along its (0,0)-(1,1) diagonal.  n = 4, half = 1 gives 192 triangles / 98 nodes.
+* ``paper_cube(level)``    -- the unit-cube family of Table 1 (Sec. 4.1): 2 x 2 squares per
+  face, every square cut into 4 triangles about its centre (50 nodes / 96 elements), then
+  uniform red refinement (194/384, 770/1536, 3074/6144).
+* ``icosphere(level, radius)`` -- icosahedron with midpoint subdivision projected to the
+  sphere: 20 * 4**level triangles (1280, 5120, 20480 for levels 3, 4, 5).
+* ``bdf2_contour(L, dt)`` -- the L contour points s_l = (3 - 4 z + z^2) / (2 dt),
+  z = R exp(2 pi i l / L), R = (1e-10)**(1 / (2 L)); they come in conjugate pairs
+  (Sec. 4.1 notes this property of the gCQ points).
+* ``random_rhs(seed, shape)`` -- complex128 a + i b, a, b ~ N(0, 1) i.i.d.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "cube_grid",
+    "paper_cube",
+    "icosphere",
+    "bdf2_contour",
+    "random_rhs",
+    "mesh_summary",
+]
+
+
+class _NodeTable:
+    """Deduplicates nodes by an exact integer key."""
+
+    def __init__(self):
+        self.key_to_id = {}
+        self.coords = []
+
+    def get(self, key, xyz):
+        nid = self.key_to_id.get(key)
+        if nid is None:
+            nid = len(self.coords)
+            self.key_to_id[key] = nid
+            self.coords.append(xyz)
+        return nid
+
+
+# (normal axis, sign, u axis, v axis) with u x v = outward normal.
+_CUBE_FACES = (
+    (0, -1, 2, 1),  # -x : e_z x e_y = -e_x
+    (0, +1, 1, 2),  # +x : e_y x e_z = +e_x
+    (1, -1, 0, 2),  # -y : e_x x e_z = -e_y
+    (1, +1, 2, 0),  # +y : e_z x e_x = +e_y
+    (2, -1, 1, 0),  # -z : e_y x e_x = -e_z
+    (2, +1, 0, 1),  # +z : e_x x e_y = +e_z
+)
+
+
+def cube_grid(n: int = 4, half: float = 1.0):
+    """Cube [-half, half]^3 with n x n squares per face, 2 triangles per square.
+
+    Faces come in the order -x, +x, -y, +y, -z, +z; squares in (u, v) row-major order;
+    each square (p00, p10, p11, p01) gives triangles (p00, p10, p11) and (p00, p11, p01).
+    Returns (nodes float64 [N, 3], tris int32 [K, 3]).
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    nodes = _NodeTable()
+    tris = []
+    for axis, sign, ua, va in _CUBE_FACES:
+        ids = np.empty((n + 1, n + 1), dtype=np.int64)
+        for a in range(n + 1):
+            for b in range(n + 1):
+                g = [0, 0, 0]
+                g[axis] = sign * n
+                g[ua] = 2 * a - n
+                g[va] = 2 * b - n
+                key = tuple(g)  # integer lattice in units of half / n
+                xyz = [half * gi / n for gi in g]
+                ids[a, b] = nodes.get(key, xyz)
+        for a in range(n):
+            for b in range(n):
+                p00, p10, p11, p01 = ids[a, b], ids[a + 1, b], ids[a + 1, b + 1], ids[a, b + 1]
+                tris.append((p00, p10, p11))
+                tris.append((p00, p11, p01))
+    return np.asarray(nodes.coords, dtype=np.float64), np.asarray(tris, dtype=np.int32)
+
+
+def _red_refine(nodes: np.ndarray, tris: np.ndarray, project=None):
+    """Split every triangle into 4 through its edge midpoints (shared between neighbours)."""
+    nodes = [tuple(p) for p in nodes]
+    mid = {}
+
+    def midpoint(a, b):
+        key = (a, b) if a < b else (b, a)
+        nid = mid.get(key)
+        if nid is None:
+            p = [(nodes[a][k] + nodes[b][k]) * 0.5 for k in range(3)]
+            if project is not None:
+                p = project(p)
+            nid = len(nodes)
+            nodes.append(tuple(p))
+            mid[key] = nid
+        return nid
+
+    out = []
+    for a, b, c in tris.tolist():
+        ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+        out += [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
+    return np.asarray(nodes, dtype=np.float64), np.asarray(out, dtype=np.int32)
+
+
+def paper_cube(level: int = 1, half: float = 0.5):
+    """Unit-cube family of Table 1: level 1 = 50 nodes / 96 elements, then red refinement."""
+    if level < 1:
+        raise ValueError("level must be >= 1")
+    nodes = _NodeTable()
+    tris = []
+    m = 2  # squares per face edge
+    for axis, sign, ua, va in _CUBE_FACES:
+        def node(ga, gb, gn=None):
+            g = [0, 0, 0]
+            g[axis] = sign * 2 * m
+            g[ua] = ga
+            g[va] = gb
+            key = tuple(g)  # lattice in units of half / (2 m)
+            return nodes.get(key, [half * gi / (2 * m) for gi in g])
+
+        for a in range(m):
+            for b in range(m):
+                # corners on the lattice -2m..2m in steps of 2, centre at odd offsets
+                c00 = node(4 * a - 2 * m, 4 * b - 2 * m)
+                c10 = node(4 * (a + 1) - 2 * m, 4 * b - 2 * m)
+                c11 = node(4 * (a + 1) - 2 * m, 4 * (b + 1) - 2 * m)
+                c01 = node(4 * a - 2 * m, 4 * (b + 1) - 2 * m)
+                cc = node(4 * a + 2 - 2 * m, 4 * b + 2 - 2 * m)
+                # counter-clockwise in (u, v) => normal along u x v (outward)
+                tris += [(c00, c10, cc), (c10, c11, cc), (c11, c01, cc), (c01, c00, cc)]
+    X = np.asarray(nodes.coords, dtype=np.float64)
+    T = np.asarray(tris, dtype=np.int32)
+    for _ in range(level - 1):
+        X, T = _red_refine(X, T)
+    return X, T
+
+
+def icosphere(level: int = 3, radius: float = 1.0):
+    """Icosahedron refined `level` times by edge midpoints projected onto the sphere."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    verts = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
+             (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+             (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+             (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+             (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+             (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+
+    def project(p):
+        nrm = math.sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2])
+        return [radius * p[k] / nrm for k in range(3)]
+
+    X = np.asarray([project(v) for v in verts], dtype=np.float64)
+    T = np.asarray(faces, dtype=np.int32)
+    for _ in range(level):
+        X, T = _red_refine(X, T, project)
+    # orient outward
+    v0, v1, v2 = X[T[:, 0]], X[T[:, 1]], X[T[:, 2]]
+    nrm = np.cross(v1 - v0, v2 - v0)
+    flip = np.einsum("ij,ij->i", nrm, (v0 + v1 + v2)) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    return X, T
+
+
+def bdf2_contour(L: int, dt: float = 0.1):
+    """BDF2 gCQ contour points as a complex128 array of length L."""
+    if L < 1:
+        raise ValueError("L must be >= 1")
+    R = 1e-10 ** (1.0 / (2 * L))
+    ell = np.arange(L)
+    z = R * np.exp(2j * np.pi * ell / L)
+    s = (3.0 - 4.0 * z + z * z) / (2.0 * dt)
+    # exact conjugate pairs: s_{L-l} = conj(s_l)
+    for l in range(1, (L + 1) // 2):
+        s[L - l] = np.conj(s[l])
+    s[0] = s[0].real
+    if L % 2 == 0:
+        s[L // 2] = s[L // 2].real
+    return s.astype(np.complex128)
+
+
+def random_rhs(seed: int, shape):
+    """complex128 a + i b with a, b ~ N(0, 1) from numpy's default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(shape)
+    b = rng.standard_normal(shape)
+    return (a + 1j * b).astype(np.complex128)
+
+
+def mesh_summary(nodes: np.ndarray, tris: np.ndarray):
+    """Counts and edge statistics used by tests and reports (no method arithmetic)."""
+    edges = set()
+    for a, b, c in tris.tolist():
+        for p, q in ((a, b), (b, c), (c, a)):
+            edges.add((p, q) if p < q else (q, p))
+    return {"nodes": int(nodes.shape[0]), "elements": int(tris.shape[0]), "edges": len(edges)}

@@ -1,0 +1,62 @@
+"""Seeded input generators: the mesh families and contour points the workloads are built from.
+
+Pins: node/element counts of the paper's unit-cube family (Table 1: 50/96, 194/384, 770/1536,
+3074/6144), the icosphere and cube-grid counts, closed surfaces (Euler characteristic 2 and
+enclosed volume by the divergence theorem), outward orientation, and the BDF2 contour points
+(conjugate pairs, Re s > 0, min/max modulus).
+"""
+import numpy as np
+import pytest
+
+from paper_2607_15292_amd import workloads as W
+
+
+@pytest.mark.parametrize("level,nodes,elems", [(1, 50, 96), (2, 194, 384), (3, 770, 1536), (4, 3074, 6144)])
+def test_paper_cube_table1_counts(level, nodes, elems):
+    X, T = W.paper_cube(level)
+    s = W.mesh_summary(X, T)
+    assert (s["nodes"], s["elements"]) == (nodes, elems)
+    assert s["nodes"] - s["edges"] + s["elements"] == 2
+
+
+def _volume(X, T):
+    v0, v1, v2 = X[T[:, 0]], X[T[:, 1]], X[T[:, 2]]
+    return np.einsum("ij,ij->i", v0, np.cross(v1, v2)).sum() / 6.0
+
+
+def test_cube_grid_counts_and_orientation():
+    X, T = W.cube_grid(4, 1.0)
+    assert X.shape == (98, 3) and T.shape == (192, 3)
+    assert abs(_volume(X, T) - 8.0) < 1e-12
+    for n in (1, 2, 8):
+        X, T = W.cube_grid(n, 0.5)
+        assert T.shape[0] == 12 * n * n and abs(_volume(X, T) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("level,nodes,elems", [(3, 642, 1280), (4, 2562, 5120), (5, 10242, 20480)])
+def test_icosphere_counts(level, nodes, elems):
+    X, T = W.icosphere(level)
+    assert X.shape[0] == nodes and T.shape[0] == elems
+    assert np.allclose(np.linalg.norm(X, axis=1), 1.0)
+    vol = _volume(X, T)
+    assert 0.98 * 4 * np.pi / 3 < vol < 4 * np.pi / 3
+
+
+@pytest.mark.parametrize("L,smin,smax", [(16, 6.446, 25.93), (64, 1.782, 35.20), (128, 0.897, 37.46)])
+def test_bdf2_contour(L, smin, smax):
+    s = W.bdf2_contour(L, 0.1)
+    assert s.shape == (L,)
+    assert np.all(s.real > 0)
+    assert abs(abs(s).min() - smin) < 1e-3 and abs(abs(s).max() - smax) < 1e-2
+    for l in range(1, L):
+        assert s[L - l] == np.conj(s[l])
+    R = 1e-10 ** (1.0 / (2 * L))
+    z = R * np.exp(2j * np.pi * np.arange(L) / L)
+    assert np.allclose(s, (3 - 4 * z + z * z) / 0.2, rtol=1e-14, atol=1e-14)
+
+
+def test_random_rhs_seeded():
+    a = W.random_rhs(0, (2, 5))
+    b = W.random_rhs(0, (2, 5))
+    assert a.dtype == np.complex128 and np.array_equal(a, b)
+    assert not np.array_equal(a, W.random_rhs(1, (2, 5)))
