@@ -1,0 +1,223 @@
+/*
+ * bem.h -- C-ABI of libbem, the MI355X (gfx950) hot path of the 3D-ACA / H-matrix
+ * accelerated Laplace-domain boundary element method for 3D elastodynamics
+ * (Keshava & Schanz, "A 3D-ACA accelerated time domain boundary element method for
+ * elastodynamics using FMM and H-matrix techniques").
+ *
+ * What the library computes
+ *   Collocation BEM with flat triangles (Sec. 2.3, eq. (tri)), piecewise-constant trial
+ *   functions and collocation at element centroids (Sec. 2.3), for the Laplace-domain
+ *   single layer V and double layer K (eqs. (SLP), (DLP), (discrVK) with U* replaced by
+ *   its Laplace transform U(y - x, s), Sec. 2.4) at the complex frequencies s_l of the
+ *   gCQ contour.  The three-dimensional array of 3x3 blocks ENTRY(i, j, l) (Sec. 2.4,
+ *   "M x M x N_Q") is either assembled densely or compressed with the matrix-valued
+ *   3D-ACA of Algorithm 1 (Sec. 3) on the blocks of an H-matrix partition (Sec. 3.1,
+ *   eqs. (cluster), (adm)), far-field faces being approximated per slice by matrix-valued
+ *   ACA with QR/SVD recompression (eq. (ACA)).  Products apply the compressed array at
+ *   every frequency (the face-fibre form of eq. (3DacaMult)).
+ *
+ * Conventions (all entry points)
+ *   - Every function returns int: BEM_OK (0) on success, a negative BEM_ERR_* code on
+ *     failure, a positive BEM_WARN_* code for success with a warning.  On failure no
+ *     output buffer is guaranteed to be written; bem_last_error() gives a message.
+ *   - Complex numbers are interleaved (re, im) pairs of double (complex128) or float
+ *     (complex64), compatible with C99 _Complex and numpy/torch complex layouts.
+ *   - Indices are 0-based.  DOF index = 3 * element + component.  The ABI always speaks
+ *     mesh order; the cluster permutation is internal.
+ *   - Triangle orientation: the unit normal is (v1 - v0) x (v2 - v0) normalised and must
+ *     point out of the domain Omega (into the exterior for a bounded body, into the
+ *     cavity for an exterior problem).
+ *   - Buffers: BEM_DEVICE_PTR in `flags` means the pointers are device pointers on the
+ *     context's device (e.g. torch tensor data_ptr()); otherwise they are host pointers
+ *     and the library stages them through device memory.  Work is issued on the stream
+ *     set by bem_set_stream (default: the null stream); calls with host buffers return
+ *     after the results are in the host buffer; calls with device buffers return after
+ *     enqueueing (synchronise the stream before reading).
+ *   - Inputs are copied; the caller keeps ownership of everything it passes.  Opaque
+ *     objects (bem_ctx, bem_op) are owned by the library and released by *_destroy.
+ *   - A context is not thread-safe; distinct contexts are independent.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bem_ctx bem_ctx;
+typedef struct bem_op bem_op;
+
+/* return codes */
+#define BEM_OK 0
+#define BEM_ERR_ARG (-1)       /* invalid argument (null pointer, size, enum value) */
+#define BEM_ERR_MESH (-2)      /* node index out of range, degenerate triangle, K < 1 */
+#define BEM_ERR_MATERIAL (-3)  /* rho <= 0, cs <= 0 or cp <= cs, non-finite values */
+#define BEM_ERR_FREQ (-4)      /* Re s <= 0, non-finite, L < 1 */
+#define BEM_ERR_STATE (-5)     /* mesh, material or frequencies not set yet */
+#define BEM_ERR_HIP (-6)       /* a HIP runtime call failed */
+#define BEM_ERR_NOMEM (-7)     /* device allocation failed or the compression pool overflowed */
+#define BEM_ERR_NODEVICE (-8)  /* GPU call on a host-only context (device = -1) */
+#define BEM_WARN_BULK 1        /* cp^2 < 4/3 cs^2: negative bulk modulus (still computed) */
+
+/* operators */
+#define BEM_OP_V 0     /* single layer V (eq. (SLP)), kernel U */
+#define BEM_OP_K 1     /* double layer K (eq. (DLP)), kernel T, Cauchy principal value */
+#define BEM_OP_HK 2    /* C + K with the free term C = I/2 at smooth points (eq. (SBIE)) */
+#define BEM_OP_TABLE 3 /* ENTRY read from a user table (bem_set_entry_table); for tests */
+
+/* precision of entry generation and storage */
+#define BEM_PREC_F64 0   /* complex128 everywhere */
+#define BEM_PREC_MIXED 1 /* far field complex64 (entries, factors, products); near field,
+                            singular/near-singular quadrature, pivots and norms complex128 */
+
+/* flags */
+#define BEM_DEVICE_PTR 1   /* buffers are device pointers */
+#define BEM_SHARED_X 2     /* bem_apply: x has shape [nrhs][3K], the same for every frequency */
+
+/* Quadrature options (Sec. 2.3: Duffy for the singular collocation integrals; the rest is
+ * this library's documented reading).  regular pairs: 7-point degree-5 rule; near pairs
+ * (near_on): the same rule on 4^2 sub-triangles if |x_i - c_j| < near_r1 * lmax_j, on 4^1
+ * if < near_r2 * lmax_j (lmax_j = longest edge of element j); self pairs: polar Duffy
+ * about the centroid on 3 sub-triangles with self_nt x self_nr Gauss-Legendre points
+ * (principal value for K, with the leading 1/rho^2 part integrated analytically). */
+typedef struct {
+    int32_t near_on;     /* default 0 */
+    double near_r1;      /* default 1.5 */
+    double near_r2;      /* default 3.0 */
+    int32_t self_nt;     /* default 8, 1..16 */
+    int32_t self_nr;     /* default 8, 1..16 */
+} bem_quad;
+
+/* Options of bem_compress (Sec. 3, Sec. 3.1, Table 2). */
+typedef struct {
+    double eps3d;        /* 3D-ACA tolerance epsilon of eq. (precision) */
+    double eps_aca;      /* per-slice ACA tolerance; <= 0 selects eps3d / 100 (Sec. 4.1) */
+    double eta;          /* admissibility parameter of eq. (adm); default 1.5 */
+    int32_t leaf;        /* b_min: largest leaf cluster (elements); default 64 */
+    int32_t prec;        /* BEM_PREC_F64 or BEM_PREC_MIXED */
+    double mixed_eps_floor; /* MIXED only: far-field tolerances are raised to at least this
+                               value (complex64 entries cannot resolve less); default 1e-5 */
+    int64_t pool_bytes;  /* device bytes reserved for faces, fibres and factors; 0 = auto */
+} bem_aca_opts;
+
+/* Statistics of an operator (compression rate as defined in Sec. 4.1: memory of the
+ * compressed representation over the memory of the dense M x M x L array). */
+typedef struct {
+    int64_t n_blocks, n_near, n_far, n_dense_fallback;
+    int32_t rank_min, rank_max;   /* 3D-ACA ranks r_b over blocks (Fig. 5 reports these) */
+    double rank_mean;
+    int32_t aca_rank_max;         /* largest per-slice ACA rank of a far face (columns) */
+    double aca_rank_mean;
+    int64_t bytes;                /* device bytes of faces, factors and fibres */
+    double compression_rate;      /* bytes / (L * (3K)^2 * 16) */
+    int64_t entries_generated;    /* ENTRY(i, j, l) 3x3 blocks evaluated during compression */
+    int64_t freq_hist_offset;     /* reserved (0) */
+    double seconds;               /* wall time of the compression call */
+} bem_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`; device = -1 gives a host-only context (mesh,
+ * material, frequency validation and partition queries; GPU calls return
+ * BEM_ERR_NODEVICE).  *out is set to NULL on failure. */
+int bem_create(bem_ctx **out, int32_t device);
+/* Releases the context and all its device memory (operators must be destroyed first). */
+int bem_destroy(bem_ctx *ctx);
+/* Message of the last error on this context (never NULL; empty when none). */
+const char *bem_last_error(const bem_ctx *ctx);
+/* HIP stream (hipStream_t as void*) for all subsequent work of this context. */
+int bem_set_stream(bem_ctx *ctx, void *hip_stream);
+
+/* Flat triangle mesh Gamma^h = union of K triangles (Sec. 2.3, eq. (tri)).
+ * nodes: [n_nodes][3] double (host), tris: [K][3] int32 (host).
+ * Errors: BEM_ERR_MESH for K < 1, an index outside [0, n_nodes) or a zero-area triangle. */
+int bem_set_mesh(bem_ctx *ctx, const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K);
+
+/* Material (Sec. 2.1, eq. (lame)): density rho, compression and shear wave speeds
+ * cp = c1 > cs = c2 > 0.  Returns BEM_WARN_BULK if cp^2 < 4/3 cs^2. */
+int bem_set_material(bem_ctx *ctx, double rho, double cp, double cs);
+
+/* Contour points s_l, l = 0..L-1 (Sec. 2.4, eq. (laptrans): Re s > 0), [L][2] double host.
+ * Conjugate pairs (Sec. 4.1) are allowed and detected (see bem_freq_pairs). */
+int bem_set_frequencies(bem_ctx *ctx, const double *s, int32_t L);
+/* Number of l with s_l = conj(s_m) for some m != l (diagnostic). */
+int bem_freq_pairs(const bem_ctx *ctx, int32_t *n_pairs);
+
+/* Quadrature options; NULL restores the defaults. */
+int bem_set_quadrature(bem_ctx *ctx, const bem_quad *q);
+
+/* Table source for BEM_OP_TABLE: ENTRY(i, j, l) = table[((l * K + i) * K + j)][3][3]
+ * complex128, device pointer, valid until replaced; the context does not own it.  Used by
+ * tests to run the compression on synthetic tensors of known rank. */
+int bem_set_entry_table(bem_ctx *ctx, const void *table_dev);
+
+/* ---------------------------------------------------------------- generators */
+
+/* Raw generator (Sec. 2.3 eq. (discrVK) at s_l; Algorithm 1's ENTRY):
+ * out[e] = ENTRY(op, i[e], j[e], l[e]) as [n][3][3] complex (row = load direction /
+ * collocation component, column = trial component).  prec: BEM_PREC_F64 gives complex128
+ * output; BEM_PREC_MIXED gives complex128 output whose regular pairs were computed in
+ * float (near and self pairs stay FP64).  i, j, l, out: host or device per flags.
+ * n = 0 is a no-op.  Errors: BEM_ERR_ARG for an index out of range (checked on the host
+ * for host buffers, by the kernel for device buffers: offending entries are then NaN). */
+int bem_entries(bem_ctx *ctx, int32_t op, int32_t prec, int64_t n, const int32_t *i, const int32_t *j,
+                const int32_t *l, void *out, int32_t flags);
+
+/* Dense assembly of all L slices (the uncompressed array of Sec. 2.4), complex128,
+ * layout [L][3K][3K] row-major, kept on the device inside *out. */
+int bem_assemble_dense(bem_ctx *ctx, int32_t op, int32_t prec, bem_op **out);
+
+/* Copies the dense slices of an operator made by bem_assemble_dense to `dst`
+ * ([L][3K][3K] complex128, host or device per flags). */
+int bem_op_dense_copy(const bem_op *op, void *dst, int32_t flags);
+
+/* Compression (Sec. 3, Algorithm 1 with matrix-valued pivots, eq. (SVD); Sec. 3.1):
+ * PCA cluster tree with leaf size opts->leaf, admissibility eq. (adm) with opts->eta,
+ * 3D-ACA on every block, per-slice ACA + recompression (eq. (ACA)) on far-field faces,
+ * dense faces on near-field blocks, dense fallback when no regular pivot exists.
+ * opts may be NULL (eps3d = 1e-6, eps_aca = eps3d / 100, eta = 1.5, leaf = 64, F64). */
+int bem_compress(bem_ctx *ctx, int32_t op, const bem_aca_opts *opts, bem_op **out);
+
+/* Statistics of a compressed or dense operator. */
+int bem_op_stats(const bem_op *op, bem_stats *st);
+
+/* All-frequency product (the face-fibre form of eq. (3DacaMult) per frequency):
+ * y[r][l] = A(s_l) x[r][l] for r < nrhs and every l, where A is the dense or compressed
+ * operator.  x, y: [nrhs][L][3K] complex128 (complex64 is not accepted: the product
+ * accumulates near field in complex128 and converts far-field partial sums).  With
+ * BEM_SHARED_X, x is [nrhs][3K] and used for every l.  x and y must not overlap. */
+int bem_apply(bem_op *op, int32_t nrhs, const void *x, void *y, int32_t flags);
+
+/* gCQ weighted sum (eq. (gCQ) / eq. (3DacaMult)): y = sum_l A(s_l) W[l], computed as
+ * sum_k H_k (sum_l f_k[l] W[l]) on a compressed operator (plain sum on a dense one).
+ * W: [L][3K] complex128, y: [3K] complex128. */
+int bem_apply_weighted(bem_op *op, const void *W, void *y, int32_t flags);
+
+/* Per-block description of a compressed operator for tests and reports:
+ * rows (int64 x 8 per block): row_begin, row_size, col_begin, col_size (cluster order),
+ * is_far, rank, dense_fallback, aca_cols_total.  perm: [K] int32, cluster position ->
+ * mesh element.  Either pointer may be NULL.  n_blocks gets the number of blocks. */
+int bem_op_blocks(const bem_op *op, int64_t *n_blocks, int64_t *rows, int32_t *perm);
+
+/* Partition only (host; works on a host-only context): fills the same block table as
+ * bem_op_blocks for the current mesh with the given eta and leaf; rank columns are 0. */
+int bem_partition(bem_ctx *ctx, double eta, int32_t leaf, int64_t *n_blocks, int64_t *rows, int32_t *perm);
+
+/* Frequencies selected by 3D-ACA: hist[l] = number of compressed (non-fallback) blocks
+ * whose face list contains slice l (Fig. 6 of the paper plots this). */
+int bem_op_freq_hist(const bem_op *op, int64_t *hist);
+
+/* Releases an operator and its device memory. */
+int bem_op_destroy(bem_op *op);
+
+/* Library version string. */
+const char *bem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEM_H */

@@ -1,0 +1,309 @@
+"""ctypes binding of libbem.so (argument marshalling only; every step of the path runs in
+the library's HIP kernels).  Names follow include/bem.h.
+
+Buffers: numpy arrays are passed as host pointers; torch CUDA tensors as device pointers
+(BEM_DEVICE_PTR), with the context's stream set to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbem.so")
+
+BEM_OK = 0
+ERR_NAMES = {-1: "BEM_ERR_ARG", -2: "BEM_ERR_MESH", -3: "BEM_ERR_MATERIAL", -4: "BEM_ERR_FREQ",
+             -5: "BEM_ERR_STATE", -6: "BEM_ERR_HIP", -7: "BEM_ERR_NOMEM", -8: "BEM_ERR_NODEVICE"}
+OP_V, OP_K, OP_HK, OP_TABLE = 0, 1, 2, 3
+PREC_F64, PREC_MIXED = 0, 1
+DEVICE_PTR, SHARED_X = 1, 2
+
+_lib = None
+
+
+class BemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERR_NAMES.get(code, "error"), code, msg))
+        self.code = code
+
+
+class bem_quad(ctypes.Structure):
+    _fields_ = [("near_on", ctypes.c_int32), ("near_r1", ctypes.c_double), ("near_r2", ctypes.c_double),
+                ("self_nt", ctypes.c_int32), ("self_nr", ctypes.c_int32)]
+
+
+class bem_aca_opts(ctypes.Structure):
+    _fields_ = [("eps3d", ctypes.c_double), ("eps_aca", ctypes.c_double), ("eta", ctypes.c_double),
+                ("leaf", ctypes.c_int32), ("prec", ctypes.c_int32), ("mixed_eps_floor", ctypes.c_double),
+                ("pool_bytes", ctypes.c_int64)]
+
+
+class bem_stats(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int64), ("n_near", ctypes.c_int64), ("n_far", ctypes.c_int64),
+                ("n_dense_fallback", ctypes.c_int64), ("rank_min", ctypes.c_int32), ("rank_max", ctypes.c_int32),
+                ("rank_mean", ctypes.c_double), ("aca_rank_max", ctypes.c_int32), ("aca_rank_mean", ctypes.c_double),
+                ("bytes", ctypes.c_int64), ("compression_rate", ctypes.c_double),
+                ("entries_generated", ctypes.c_int64), ("freq_hist_offset", ctypes.c_int64),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# exported symbols and their signatures (also checked by the CPU tests)
+_P = ctypes.c_void_p
+_SIGS = {
+    "bem_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
+    "bem_destroy": (ctypes.c_int, [_P]),
+    "bem_last_error": (ctypes.c_char_p, [_P]),
+    "bem_set_stream": (ctypes.c_int, [_P, _P]),
+    "bem_set_mesh": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64]),
+    "bem_set_material": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "bem_set_frequencies": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "bem_freq_pairs": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "bem_set_quadrature": (ctypes.c_int, [_P, ctypes.POINTER(bem_quad)]),
+    "bem_set_entry_table": (ctypes.c_int, [_P, _P]),
+    "bem_entries": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32]),
+    "bem_assemble_dense": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "bem_op_dense_copy": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "bem_compress": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(bem_aca_opts), ctypes.POINTER(ctypes.c_void_p)]),
+    "bem_op_stats": (ctypes.c_int, [_P, ctypes.POINTER(bem_stats)]),
+    "bem_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
+    "bem_apply_weighted": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "bem_op_blocks": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), _P, _P]),
+    "bem_partition": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), _P, _P]),
+    "bem_op_freq_hist": (ctypes.c_int, [_P, _P]),
+    "bem_op_destroy": (ctypes.c_int, [_P]),
+    "bem_version": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Loads libbem.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbem.so is not built (run __graft_entry__.build() or "
+                              "python paper_2607_15292_amd/build.py); no fallback path exists")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """(pointer, flags) of a numpy array (host) or torch CUDA tensor (device)."""
+    if _is_torch(a):
+        if not a.is_cuda:
+            raise ValueError("torch tensors must live on the GPU; use numpy for host buffers")
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), DEVICE_PTR
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return ctypes.c_void_p(a.ctypes.data), 0
+
+
+class Context:
+    """Owns a bem_ctx (one device)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib().bem_create(ctypes.byref(h), int(device))
+        if rc != BEM_OK:
+            raise BemError(rc, "bem_create(device=%d) failed" % device)
+        self.h = h
+        self.device = device
+        self._keep = []
+
+    def _check(self, rc):
+        if rc < 0:
+            raise BemError(rc, lib().bem_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if self.h:
+            self._check(lib().bem_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().bem_destroy(self.h)
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        """stream: torch.cuda.Stream, a raw hipStream_t as int, or None (null stream)."""
+        raw = 0 if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        self._check(lib().bem_set_stream(self.h, ctypes.c_void_p(raw)))
+
+    def _sync_torch_stream(self):
+        import torch
+        self.set_stream(torch.cuda.current_stream())
+
+    def set_mesh(self, nodes, tris):
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        tris = np.ascontiguousarray(tris, dtype=np.int32)
+        self.K = int(tris.shape[0])
+        return self._check(lib().bem_set_mesh(self.h, nodes.ctypes.data, nodes.shape[0], tris.ctypes.data, tris.shape[0]))
+
+    def set_material(self, rho, cp, cs):
+        return self._check(lib().bem_set_material(self.h, float(rho), float(cp), float(cs)))
+
+    def set_frequencies(self, s):
+        s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+        a = np.ascontiguousarray(np.stack([s.real, s.imag], axis=-1))
+        self.L = int(s.shape[0])
+        return self._check(lib().bem_set_frequencies(self.h, a.ctypes.data, self.L))
+
+    def freq_pairs(self):
+        n = ctypes.c_int32()
+        self._check(lib().bem_freq_pairs(self.h, ctypes.byref(n)))
+        return n.value
+
+    def set_quadrature(self, near_on=False, near_r1=1.5, near_r2=3.0, self_nt=8, self_nr=8):
+        q = bem_quad(int(bool(near_on)), float(near_r1), float(near_r2), int(self_nt), int(self_nr))
+        return self._check(lib().bem_set_quadrature(self.h, ctypes.byref(q)))
+
+    def set_entry_table(self, table):
+        """table: torch complex128 CUDA tensor [L, K, K, 3, 3] (kept alive by the context)."""
+        p, fl = _ptr(table)
+        if not fl & DEVICE_PTR:
+            raise ValueError("the entry table must be a device tensor")
+        self._keep.append(table)
+        return self._check(lib().bem_set_entry_table(self.h, p))
+
+    def entries(self, op, i, j, l, prec=PREC_F64, out=None):
+        """ENTRY(op, i, j, l) -> complex128 [n, 3, 3] (numpy for numpy indices, torch for torch)."""
+        if _is_torch(i):
+            import torch
+            n = i.numel()
+            if out is None:
+                out = torch.empty((n, 3, 3), dtype=torch.complex128, device=i.device)
+            self._sync_torch_stream()
+        else:
+            i, j, l = (np.ascontiguousarray(np.ravel(a), dtype=np.int32) for a in np.broadcast_arrays(i, j, l))
+            n = i.size
+            if out is None:
+                out = np.empty((n, 3, 3), dtype=np.complex128)
+        pi, fl = _ptr(i)
+        pj, _ = _ptr(j)
+        pl, _ = _ptr(l)
+        po, _ = _ptr(out)
+        self._check(lib().bem_entries(self.h, int(op), int(prec), int(n), pi, pj, pl, po, fl))
+        return out
+
+    def assemble_dense(self, op, prec=PREC_F64):
+        h = ctypes.c_void_p()
+        self._check(lib().bem_assemble_dense(self.h, int(op), int(prec), ctypes.byref(h)))
+        return Operator(self, h)
+
+    def compress(self, op, eps3d=1e-6, eps_aca=0.0, eta=1.5, leaf=64, prec=PREC_F64, mixed_eps_floor=1e-5,
+                 pool_bytes=0):
+        o = bem_aca_opts(float(eps3d), float(eps_aca), float(eta), int(leaf), int(prec), float(mixed_eps_floor),
+                         int(pool_bytes))
+        h = ctypes.c_void_p()
+        self._check(lib().bem_compress(self.h, int(op), ctypes.byref(o), ctypes.byref(h)))
+        return Operator(self, h)
+
+    def partition(self, eta=1.5, leaf=64):
+        n = ctypes.c_int64()
+        self._check(lib().bem_partition(self.h, float(eta), int(leaf), ctypes.byref(n), None, None))
+        rows = np.zeros((n.value, 8), dtype=np.int64)
+        perm = np.zeros(self.K, dtype=np.int32)
+        self._check(lib().bem_partition(self.h, float(eta), int(leaf), ctypes.byref(n), rows.ctypes.data,
+                                        perm.ctypes.data))
+        return rows, perm
+
+
+class Operator:
+    """Owns a bem_op (dense or compressed)."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+
+    def destroy(self):
+        if self.h:
+            self.ctx._check(lib().bem_op_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().bem_op_destroy(self.h)
+        except Exception:
+            pass
+
+    def stats(self):
+        st = bem_stats()
+        self.ctx._check(lib().bem_op_stats(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def dense(self, out=None):
+        K, L = self.ctx.K, self.ctx.L
+        if out is None:
+            out = np.empty((L, 3 * K, 3 * K), dtype=np.complex128)
+        p, fl = _ptr(out)
+        if fl & DEVICE_PTR:
+            self.ctx._sync_torch_stream()
+        self.ctx._check(lib().bem_op_dense_copy(self.h, p, fl))
+        return out
+
+    def apply(self, x, y=None, shared_x=False):
+        """y[r, l] = A(s_l) x[r, l]; x: [nrhs, L, 3K] (or [nrhs, 3K] with shared_x)."""
+        K, L = self.ctx.K, self.ctx.L
+        nrhs = x.shape[0]
+        if _is_torch(x):
+            import torch
+            if y is None:
+                y = torch.empty((nrhs, L, 3 * K), dtype=torch.complex128, device=x.device)
+            self.ctx._sync_torch_stream()
+        elif y is None:
+            y = np.empty((nrhs, L, 3 * K), dtype=np.complex128)
+        px, fl = _ptr(x)
+        py, _ = _ptr(y)
+        self.ctx._check(lib().bem_apply(self.h, int(nrhs), px, py, fl | (SHARED_X if shared_x else 0)))
+        return y
+
+    def apply_weighted(self, W, y=None):
+        K = self.ctx.K
+        if _is_torch(W):
+            import torch
+            if y is None:
+                y = torch.empty((3 * K,), dtype=torch.complex128, device=W.device)
+            self.ctx._sync_torch_stream()
+        elif y is None:
+            y = np.empty((3 * K,), dtype=np.complex128)
+        pw, fl = _ptr(W)
+        py, _ = _ptr(y)
+        self.ctx._check(lib().bem_apply_weighted(self.h, pw, py, fl))
+        return y
+
+    def blocks(self):
+        n = ctypes.c_int64()
+        self.ctx._check(lib().bem_op_blocks(self.h, ctypes.byref(n), None, None))
+        rows = np.zeros((n.value, 8), dtype=np.int64)
+        perm = np.zeros(self.ctx.K, dtype=np.int32)
+        self.ctx._check(lib().bem_op_blocks(self.h, ctypes.byref(n), rows.ctypes.data, perm.ctypes.data))
+        return rows, perm
+
+    def freq_hist(self):
+        h = np.zeros(self.ctx.L, dtype=np.int64)
+        self.ctx._check(lib().bem_op_freq_hist(self.h, h.ctypes.data))
+        return h
+
+
+def version():
+    return lib().bem_version().decode()

@@ -1,0 +1,227 @@
+// common.hpp -- complex arithmetic, 3x3 complex block helpers and HIP error plumbing
+// shared by the libbem translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BEM_HD __host__ __device__ __forceinline__
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T> BEM_HD cx<T> mkc(T r, T i) { return cx<T>{r, i}; }
+template <typename T> BEM_HD cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> BEM_HD cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> BEM_HD cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T> BEM_HD cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> BEM_HD cx<T> operator*(T a, cx<T> b) { return {a * b.re, a * b.im}; }
+template <typename T> BEM_HD cx<T> operator*(cx<T> b, T a) { return {a * b.re, a * b.im}; }
+template <typename T> BEM_HD cx<T>& operator+=(cx<T>& a, cx<T> b)
+{
+    a.re += b.re;
+    a.im += b.im;
+    return a;
+}
+template <typename T> BEM_HD cx<T>& operator-=(cx<T>& a, cx<T> b)
+{
+    a.re -= b.re;
+    a.im -= b.im;
+    return a;
+}
+template <typename T> BEM_HD cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T> BEM_HD T abs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+// a * conj(b)
+template <typename T> BEM_HD cx<T> mul_conj(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * b
+template <typename T> BEM_HD cx<T> conj_mul(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T> BEM_HD cx<T> fma_c(cx<T> a, cx<T> b, cx<T> c)  // a * b + c
+{
+    return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
+}
+
+template <typename To, typename Ti> BEM_HD cx<To> cvt(cx<Ti> a) { return {(To)a.re, (To)a.im}; }
+
+typedef cx<double> zd;
+typedef cx<float> zf;
+
+// ---------------------------------------------------------------- 3x3 complex blocks
+// Row-major 3x3 blocks of complex<double>.
+
+struct blk {
+    zd a[9];
+};
+
+BEM_HD blk blk_zero()
+{
+    blk b;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) b.a[t] = {0.0, 0.0};
+    return b;
+}
+
+// C = A * B
+BEM_HD blk blk_mul(const blk& A, const blk& B)
+{
+    blk C;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            zd s = A.a[3 * i] * B.a[j];
+            s = fma_c(A.a[3 * i + 1], B.a[3 + j], s);
+            s = fma_c(A.a[3 * i + 2], B.a[6 + j], s);
+            C.a[3 * i + j] = s;
+        }
+    return C;
+}
+
+// C += A * B
+BEM_HD void blk_mul_add(blk& C, const blk& A, const blk& B)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            zd s = C.a[3 * i + j];
+            s = fma_c(A.a[3 * i], B.a[j], s);
+            s = fma_c(A.a[3 * i + 1], B.a[3 + j], s);
+            s = fma_c(A.a[3 * i + 2], B.a[6 + j], s);
+            C.a[3 * i + j] = s;
+        }
+}
+
+// C -= A * B
+BEM_HD void blk_mul_sub(blk& C, const blk& A, const blk& B)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            zd s = A.a[3 * i] * B.a[j];
+            s = fma_c(A.a[3 * i + 1], B.a[3 + j], s);
+            s = fma_c(A.a[3 * i + 2], B.a[6 + j], s);
+            C.a[3 * i + j] -= s;
+        }
+}
+
+BEM_HD double blk_fro2(const blk& A)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) s += abs2(A.a[t]);
+    return s;
+}
+
+// determinant and adjugate (transpose of the cofactor matrix): A * adj(A) = det(A) I
+BEM_HD zd blk_det_adj(const blk& A, blk& adj)
+{
+    const zd* m = A.a;
+    adj.a[0] = m[4] * m[8] - m[5] * m[7];
+    adj.a[1] = m[2] * m[7] - m[1] * m[8];
+    adj.a[2] = m[1] * m[5] - m[2] * m[4];
+    adj.a[3] = m[5] * m[6] - m[3] * m[8];
+    adj.a[4] = m[0] * m[8] - m[2] * m[6];
+    adj.a[5] = m[2] * m[3] - m[0] * m[5];
+    adj.a[6] = m[3] * m[7] - m[4] * m[6];
+    adj.a[7] = m[1] * m[6] - m[0] * m[7];
+    adj.a[8] = m[0] * m[4] - m[1] * m[3];
+    return m[0] * adj.a[0] + m[1] * adj.a[3] + m[2] * adj.a[6];
+}
+
+BEM_HD zd zdiv(zd a, zd b)
+{
+    double d = 1.0 / (b.re * b.re + b.im * b.im);
+    return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
+}
+
+BEM_HD blk blk_inv(const blk& A)
+{
+    blk adj;
+    zd det = blk_det_adj(A, adj);
+    zd inv = zdiv(zd{1.0, 0.0}, det);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) adj.a[t] = adj.a[t] * inv;
+    return adj;
+}
+
+// Largest eigenvalue of a 3x3 Hermitian positive semidefinite matrix M (row-major),
+// trigonometric solution of the characteristic cubic (accurate in relative terms for the
+// largest eigenvalue).
+BEM_HD double herm3_lambda_max(const blk& M)
+{
+    double a = M.a[0].re, b = M.a[4].re, c = M.a[8].re;
+    double p1 = abs2(M.a[1]) + abs2(M.a[2]) + abs2(M.a[5]);
+    double q = (a + b + c) / 3.0;
+    double aq = a - q, bq = b - q, cq = c - q;
+    double p2 = aq * aq + bq * bq + cq * cq + 2.0 * p1;
+    if (!(p2 > 1e-300 * (q * q + 1e-300))) return q;  // multiple of the identity
+    double p = sqrt(p2 / 6.0);
+    double ip = 1.0 / p;
+    // B = (M - q I) / p; det(B) / 2
+    zd b00 = {aq * ip, 0.0}, b11 = {bq * ip, 0.0}, b22 = {cq * ip, 0.0};
+    zd b01 = M.a[1] * ip, b02 = M.a[2] * ip, b12 = M.a[5] * ip;
+    zd b10 = conj(b01), b20 = conj(b02), b21 = conj(b12);
+    zd det = b00 * (b11 * b22 - b12 * b21) - b01 * (b10 * b22 - b12 * b20) + b02 * (b10 * b21 - b11 * b20);
+    double r = 0.5 * det.re;
+    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+    double phi = acos(r) / 3.0;
+    return q + 2.0 * p * cos(phi);
+}
+
+// Smallest singular value of a 3x3 complex block: sigma_3 = |det A| / sigma_1(adj A),
+// since the singular values of adj(A) are sigma_2 sigma_3, sigma_1 sigma_3, sigma_1 sigma_2.
+BEM_HD double blk_sigma3(const blk& A)
+{
+    blk adj;
+    zd det = blk_det_adj(A, adj);
+    double ad = sqrt(abs2(det));
+    if (!(ad > 0.0)) return 0.0;
+    // G = adj^H adj
+    blk G;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            zd s = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s += conj_mul(adj.a[3 * k + i], adj.a[3 * k + j]);
+            G.a[3 * i + j] = s;
+        }
+    double l = herm3_lambda_max(G);
+    if (!(l > 0.0)) return 0.0;
+    return ad / sqrt(l);
+}
+
+// ---------------------------------------------------------------- host error plumbing
+
+#define BEM_HIP_TRY(expr)                                  \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) {                            \
+            throw bem_hip_error(e_, #expr, __FILE__, __LINE__); \
+        }                                                  \
+    } while (0)
+
+#include <stdexcept>
+#include <string>
+struct bem_hip_error : std::runtime_error {
+    hipError_t code;
+    bem_hip_error(hipError_t e, const char* what, const char* file, int line)
+        : std::runtime_error(std::string("HIP error ") + hipGetErrorString(e) + " in " + what + " (" + file + ":" +
+                             std::to_string(line) + ")"),
+          code(e)
+    {
+    }
+};

@@ -1,0 +1,344 @@
+// compress.cpp -- host driver of the compression (partition, cluster-ordered tables,
+// persistent 3D-ACA launch, statistics) and of the compressed products (apply plan).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "aca3d.hpp"
+#include "host.hpp"
+
+namespace bem {
+
+struct CompressedOp {
+    Partition part;
+    DevGeo geo;                 // element tables in cluster order
+    DevBuf perm_dev;            // [K] cluster position -> mesh element
+    DevBuf blocks_dev;          // BlockIn[nb]
+    DevBuf faces_dev;           // FaceDesc[nb][L]
+    DevBuf out_dev;             // BlockOut[nb]
+    DevBuf pool;                // faces, factors, fibres
+    std::vector<BlockIn> blocks;
+    std::vector<FaceDesc> faces;
+    std::vector<BlockOut> outs;
+    // apply plan
+    std::vector<ApplyFace> af;
+    DevBuf af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev;
+    int ngroups = 0;
+    long long far_rows = 0;     // sum of kk over far faces
+    long long zw_total = 0;     // sum of 3 cs over faces
+    DevBuf work;                // apply workspace (grown on demand)
+    int mixed = 0, L = 0, K = 0;
+};
+
+void destroy_compressed(CompressedOp* c) { delete c; }
+
+namespace {
+
+using Err = ApiError;
+
+void build_apply_plan(CompressedOp& C, hipStream_t st)
+{
+    const int L = C.L;
+    const int nb = (int)C.blocks.size();
+    C.af.clear();
+    std::vector<std::vector<int>> faces_of_block(nb);
+    long long trow = 0, zw = 0;
+    for (int b = 0; b < nb; ++b) {
+        for (int d = 0; d < C.outs[b].rank; ++d) {
+            const FaceDesc& f = C.faces[(size_t)b * L + d];
+            if (f.kk < 0) continue;
+            ApplyFace a;
+            a.face_off = f.face_off;
+            a.fib_off = f.fib_off;
+            a.kk = f.kk;
+            a.sel = f.sel;
+            a.ksel = f.k;
+            a.block = b;
+            a.t_off = 0;
+            if (f.kk > 0) {
+                a.t_off = trow;
+                trow += f.kk;
+            }
+            a.zw_off = zw;
+            zw += 3LL * C.blocks[b].cs;
+            faces_of_block[b].push_back((int)C.af.size());
+            C.af.push_back(a);
+        }
+    }
+    C.far_rows = trow;
+    C.zw_total = zw;
+    // row chunks: leaves of the cluster tree cut into pieces of at most 16 elements
+    std::vector<int> cstart, csize;
+    for (const Cluster& n : C.part.nodes)
+        if (n.child[0] < 0)
+            for (int s = 0; s < n.size; s += 16) {
+                cstart.push_back(n.begin + s);
+                csize.push_back(std::min(16, n.size - s));
+            }
+    std::vector<int> order(cstart.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return cstart[a] < cstart[b]; });
+    std::vector<int> s2(order.size()), z2(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+        s2[i] = cstart[order[i]];
+        z2[i] = csize[order[i]];
+    }
+    C.ngroups = (int)s2.size();
+    std::vector<std::vector<int>> lists(C.ngroups);
+    for (int b = 0; b < nb; ++b) {
+        const BlockIn& B = C.blocks[b];
+        auto it = std::lower_bound(s2.begin(), s2.end(), B.rb);
+        for (; it != s2.end() && *it < B.rb + B.rs; ++it) {
+            int g = (int)(it - s2.begin());
+            for (int fi : faces_of_block[b]) lists[g].push_back(fi);
+        }
+    }
+    std::vector<int> ptr(C.ngroups + 1, 0), flat;
+    for (int g = 0; g < C.ngroups; ++g) {
+        ptr[g + 1] = ptr[g] + (int)lists[g].size();
+        flat.insert(flat.end(), lists[g].begin(), lists[g].end());
+    }
+    auto up = [&](DevBuf& d, const void* src, size_t bytes) {
+        d.alloc(std::max<size_t>(bytes, 16));
+        if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    up(C.af_dev, C.af.data(), C.af.size() * sizeof(ApplyFace));
+    up(C.rowfaces_dev, flat.data(), flat.size() * sizeof(int));
+    up(C.rowptr_dev, ptr.data(), ptr.size() * sizeof(int));
+    up(C.rowstart_dev, s2.data(), s2.size() * sizeof(int));
+    up(C.rowsize_dev, z2.data(), z2.size() * sizeof(int));
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+}
+
+ApplyArgs plan_args(const CompressedOp& C, int nrhs)
+{
+    ApplyArgs A{};
+    A.blocks = C.blocks_dev.as<BlockIn>();
+    A.faces = C.af_dev.as<ApplyFace>();
+    A.nfaces = (int)C.af.size();
+    A.row_faces = C.rowfaces_dev.as<int>();
+    A.row_ptr = C.rowptr_dev.as<int>();
+    A.row_start = C.rowstart_dev.as<int>();
+    A.row_size = C.rowsize_dev.as<int>();
+    A.nrow_groups = C.ngroups;
+    A.pool = C.pool.as<char>();
+    A.mixed = C.mixed;
+    A.K = C.K;
+    A.L = C.L;
+    A.nrhs = nrhs;
+    return A;
+}
+
+}  // namespace
+
+int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = ctx->stream;
+    const int K = ctx->hgeo.K, L = ctx->freq.L;
+    if (L > MAX_L) throw Err(BEM_ERR_ARG, "compression supports at most 256 frequencies");
+    CompressedOp* C = new CompressedOp();
+    out->comp = C;
+    C->mixed = o.prec == BEM_PREC_MIXED;
+    C->L = L;
+    C->K = K;
+    build_partition(ctx->hgeo, o.eta, o.leaf, C->part);
+    C->geo.upload(ctx->hgeo, C->part.perm.data(), st);
+    C->perm_dev.alloc(sizeof(int) * K);
+    BEM_HIP_TRY(hipMemcpyAsync(C->perm_dev.p, C->part.perm.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
+    const int nb = (int)C->part.blocks.size();
+    C->blocks.resize(nb);
+    int mmax = 1, nmax = 1, minmax = 1;
+    int64_t n_far = 0;
+    for (int b = 0; b < nb; ++b) {
+        const BlockDesc& d = C->part.blocks[b];
+        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far};
+        if (d.far) {
+            ++n_far;
+            mmax = std::max(mmax, d.rs);
+            nmax = std::max(nmax, d.cs);
+            minmax = std::max(minmax, std::min(d.rs, d.cs));
+        }
+    }
+    // processing order: most work first (far blocks by perimeter x frequencies, near by area)
+    std::vector<int> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(nb);
+    for (int b = 0; b < nb; ++b) {
+        const BlockIn& B = C->blocks[b];
+        cost[b] = B.far ? 40.0 * (B.rs + B.cs) + 2.0 * B.rs * B.cs : 12.0 * B.rs * B.cs;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    const int kmax = 3 * std::max(1, std::min(64, minmax));
+    const int slots = std::max(1, std::min(nb, 1024));
+    size_t per_slot = n_far ? aca_scratch_doubles(mmax, nmax, kmax) : 64;
+    per_slot = (per_slot + 31) & ~(size_t)31;
+    DevBuf scratch, blocks_aux;
+    scratch.alloc(per_slot * slots * sizeof(double));
+    C->blocks_dev.alloc(sizeof(BlockIn) * nb);
+    BEM_HIP_TRY(hipMemcpyAsync(C->blocks_dev.p, C->blocks.data(), sizeof(BlockIn) * nb, hipMemcpyHostToDevice, st));
+    // small device state: order, queue, err, pool_top
+    blocks_aux.alloc(sizeof(int) * nb + 256);
+    int* order_dev = blocks_aux.as<int>();
+    char* aux = blocks_aux.as<char>() + ((sizeof(int) * nb + 63) & ~(size_t)63);
+    int* queue_dev = (int*)aux;
+    int* err_dev = (int*)(aux + 64);
+    unsigned long long* top_dev = (unsigned long long*)(aux + 128);
+    BEM_HIP_TRY(hipMemcpyAsync(order_dev, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+    BEM_HIP_TRY(hipMemsetAsync(aux, 0, 192, st));
+    C->faces_dev.alloc(sizeof(FaceDesc) * (size_t)nb * L);
+    BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
+    C->out_dev.alloc(sizeof(BlockOut) * nb);
+    // pool
+    size_t pool_bytes = (size_t)o.pool_bytes;
+    if (pool_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
+        size_t dense = (size_t)L * 9 * (size_t)K * K * 16;  // dense array size
+        pool_bytes = std::min<size_t>((size_t)(0.6 * (double)fr), std::max<size_t>(dense / 4 + ((size_t)1 << 28), (size_t)1 << 30));
+    }
+    C->pool.alloc(pool_bytes);
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+
+    CompressArgs A;
+    A.c = ctx->devctx(C->geo.geo, C->perm_dev.as<int>());
+    A.op = op;
+    A.mixed = C->mixed;
+    A.L = L;
+    A.nblocks = nb;
+    A.kmax = kmax;
+    A.blocks = C->blocks_dev.as<BlockIn>();
+    A.order = order_dev;
+    A.faces = C->faces_dev.as<FaceDesc>();
+    A.out = C->out_dev.as<BlockOut>();
+    A.pool = C->pool.as<char>();
+    A.pool_cap = pool_bytes;
+    A.pool_top = top_dev;
+    A.queue = queue_dev;
+    A.err = err_dev;
+    A.scratch = scratch.as<double>();
+    A.scratch_per_slot = per_slot;
+    A.eps3d = o.eps3d;
+    A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
+    A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
+    launch_aca3d(A, slots, st);
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    int err = 0;
+    unsigned long long top = 0;
+    BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
+    BEM_HIP_TRY(hipMemcpy(&top, top_dev, sizeof(top), hipMemcpyDeviceToHost));
+    if (err & 2) throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes overflowed (" +
+                                              std::to_string(top) + " requested); raise pool_bytes");
+    C->faces.resize((size_t)nb * L);
+    C->outs.resize(nb);
+    BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L, hipMemcpyDeviceToHost));
+    BEM_HIP_TRY(hipMemcpy(C->outs.data(), C->out_dev.p, sizeof(BlockOut) * nb, hipMemcpyDeviceToHost));
+    build_apply_plan(*C, st);
+
+    // statistics
+    bem_stats& S = out->stats;
+    std::memset(&S, 0, sizeof(S));
+    S.n_blocks = nb;
+    S.n_far = n_far;
+    S.n_near = nb - n_far;
+    S.rank_min = L + 1;
+    double rsum = 0, acasum = 0;
+    int64_t nfarfaces = 0, bytes = 0, ent = 0;
+    size_t zsz = C->mixed ? sizeof(zf) : sizeof(zd);
+    for (int b = 0; b < nb; ++b) {
+        const BlockOut& bo = C->outs[b];
+        const BlockIn& B = C->blocks[b];
+        S.n_dense_fallback += bo.fallback;
+        S.rank_min = std::min(S.rank_min, bo.rank);
+        S.rank_max = std::max(S.rank_max, bo.rank);
+        rsum += bo.rank;
+        ent += bo.entries;
+        S.aca_rank_max = std::max(S.aca_rank_max, bo.aca_cols);
+        for (int d = 0; d < bo.rank; ++d) {
+            const FaceDesc& f = C->faces[(size_t)b * L + d];
+            bytes += (int64_t)L * 9 * sizeof(zd);
+            if (f.kk == 0) {
+                bytes += (int64_t)9 * B.rs * B.cs * sizeof(zd);
+            } else if (f.kk > 0) {
+                bytes += (int64_t)3 * (B.rs + B.cs) * f.kk * (int64_t)(B.far ? zsz : sizeof(zd));
+                acasum += f.kk;
+                ++nfarfaces;
+            }
+        }
+    }
+    S.rank_mean = nb ? rsum / nb : 0.0;
+    S.aca_rank_mean = nfarfaces ? acasum / nfarfaces : 0.0;
+    S.bytes = bytes;
+    S.compression_rate = (double)bytes / ((double)L * 9.0 * (double)K * (double)K * 16.0);
+    S.entries_generated = ent;
+    S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return BEM_OK;
+}
+
+void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride, zd* y_dev, hipStream_t st)
+{
+    CompressedOp& C = *op->comp;
+    const size_t M = 3 * (size_t)C.K;
+    const size_t ncols = (size_t)C.L * nrhs;
+    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + 16) * sizeof(zd);
+    if (C.work.bytes < need) C.work.alloc(need);
+    zd* xp = C.work.as<zd>();
+    zd* yp = xp + ncols * M;
+    zd* tb = yp + ncols * M;
+    launch_permute(x_dev, xp, C.perm_dev.as<int>(), C.K, C.L, nrhs, x_l_stride, true, st);
+    ApplyArgs A = plan_args(C, nrhs);
+    A.x = xp;
+    A.y = yp;
+    A.tbuf = tb;
+    launch_apply(A, st);
+    launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, C.L, nrhs, (int64_t)M, false, st);
+}
+
+void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream_t st)
+{
+    CompressedOp& C = *op->comp;
+    const size_t M = 3 * (size_t)C.K;
+    size_t need = ((size_t)C.L * M + M + (size_t)C.zw_total + (size_t)C.far_rows + 16) * sizeof(zd);
+    if (C.work.bytes < need) C.work.alloc(need);
+    zd* Wp = C.work.as<zd>();
+    zd* yp = Wp + (size_t)C.L * M;
+    zd* zw = yp + M;
+    zd* tb = zw + C.zw_total;
+    launch_permute(W_dev, Wp, C.perm_dev.as<int>(), C.K, C.L, 1, (int64_t)M, true, st);
+    ApplyArgs A = plan_args(C, 1);
+    A.x = Wp;
+    A.y = yp;
+    A.tbuf = tb;
+    launch_weighted(A, Wp, zw, yp, st);
+    launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, 1, 1, (int64_t)M, false, st);
+}
+
+void compressed_blocks(const bem_op* op, int64_t* n, int64_t* rows, int32_t* perm)
+{
+    const CompressedOp& C = *op->comp;
+    *n = (int64_t)C.blocks.size();
+    if (rows)
+        for (size_t b = 0; b < C.blocks.size(); ++b) {
+            const BlockIn& B = C.blocks[b];
+            int64_t cols = 0;
+            for (int d = 0; d < C.outs[b].rank; ++d) cols += std::max(0, C.faces[b * C.L + d].kk);
+            int64_t r[8] = {B.rb, B.rs, B.cb, B.cs, B.far, C.outs[b].rank, C.outs[b].fallback, cols};
+            std::memcpy(rows + 8 * b, r, sizeof(r));
+        }
+    if (perm)
+        for (int e = 0; e < C.K; ++e) perm[e] = C.part.perm[e];
+}
+
+void compressed_freq_hist(const bem_op* op, int64_t* hist)
+{
+    const CompressedOp& C = *op->comp;
+    for (int l = 0; l < C.L; ++l) hist[l] = 0;
+    for (size_t b = 0; b < C.blocks.size(); ++b) {
+        if (C.outs[b].fallback) continue;
+        for (int d = 0; d < C.outs[b].rank; ++d) hist[C.faces[b * C.L + d].k]++;
+    }
+}
+
+}  // namespace bem

@@ -1,0 +1,135 @@
+// host.hpp -- host-side state of a context and an operator (shared by api.cpp,
+// partition.cpp and compress.cpp).
+#pragma once
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/bem.h"
+#include "lib.hpp"
+
+namespace bem {
+
+// Error with a BEM_ERR_* code, thrown by host code and turned into the return value at the
+// C-ABI boundary.
+struct ApiError : std::runtime_error {
+    int code;
+    ApiError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// Owning device allocation.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n)
+    {
+        release();
+        if (n == 0) return;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw bem_nomem(n);
+        }
+        bytes = n;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return (T*)p; }
+    struct bem_nomem : std::runtime_error {
+        explicit bem_nomem(size_t n) : std::runtime_error("device allocation of " + std::to_string(n) + " bytes failed") {}
+    };
+};
+
+// Host copy of the element tables (structure of arrays, FP64).
+struct HostGeo {
+    int K = 0;
+    std::vector<double> cx, cy, cz, nx, ny, nz, area, lmax2, vx, vy, vz, gx, gy, gz, gw;
+};
+
+// Geometry tables uploaded to the device in one allocation.
+struct DevGeo {
+    DevBuf buf;
+    Geo geo{};
+    void upload(const HostGeo& h, const int* perm /* cluster pos -> mesh elem, or null */, hipStream_t st);
+};
+
+// Cluster tree node and block of the H-matrix partition (cluster order indices).
+struct Cluster {
+    int begin, size;
+    int child[2];
+    double bmin[3], bmax[3];  // box of the element vertices
+};
+
+struct BlockDesc {
+    int rb, rs, cb, cs;  // row begin/size, column begin/size (elements, cluster order)
+    int far;
+};
+
+struct Partition {
+    std::vector<int> perm;        // cluster position -> mesh element
+    std::vector<Cluster> nodes;   // node 0 = root
+    std::vector<BlockDesc> blocks;
+};
+
+void build_partition(const HostGeo& g, double eta, int leaf, Partition& out);
+
+struct CompressedOp;  // compress.cpp
+
+}  // namespace bem
+
+struct bem_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // mesh
+    bool mesh_set = false;
+    std::vector<double> nodes;
+    std::vector<int32_t> tris;
+    bem::HostGeo hgeo;
+    bem::DevGeo dgeo;
+    // material
+    bool mat_set = false;
+    double rho = 1, cp = 1, cs = 0.5;
+    // frequencies
+    bool freq_set = false;
+    std::vector<zd> s;
+    bem::DevBuf fbuf;
+    bem::Freq freq{};
+    // quadrature
+    bem_quad quad{0, 1.5, 3.0, 8, 8};
+    bem::QuadTab qtab{};
+    const zd* table = nullptr;
+    int live_ops = 0;
+
+    bem::DevCtx devctx(const bem::Geo& g, const int* perm) const;
+};
+
+struct bem_op {
+    bem_ctx* ctx = nullptr;
+    int op = 0, prec = 0;
+    int kind = 0;  // 0 dense, 1 compressed
+    int K = 0, L = 0;
+    bem::DevBuf dense;                               // kind 0: [L][3K][3K]
+    bem::CompressedOp* comp = nullptr;               // kind 1 (owned)
+    bem_stats stats{};
+    ~bem_op();
+};
+
+namespace bem {
+int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out);
+void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride, zd* y_dev, hipStream_t st);
+void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream_t st);
+void compressed_blocks(const bem_op* op, int64_t* n, int64_t* rows, int32_t* perm);
+void compressed_freq_hist(const bem_op* op, int64_t* hist);
+void destroy_compressed(CompressedOp* c);
+}  // namespace bem
