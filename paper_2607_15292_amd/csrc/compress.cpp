@@ -171,7 +171,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         cost[b] = B.far ? 40.0 * (B.rs + B.cs) + 2.0 * B.rs * B.cs : 12.0 * B.rs * B.cs;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    const int kmax = 3 * std::max(1, std::min(64, minmax));
+    const int kmax = 3 * std::max(2, std::min(64, minmax));
     const int slots = std::max(1, std::min(nb, 1024));
     size_t per_slot = n_far ? aca_scratch_doubles(mmax, nmax, kmax) : 64;
     per_slot = (per_slot + 31) & ~(size_t)31;
