@@ -1,0 +1,218 @@
+"""Benchmark of the hot path on one MI355X.
+
+Workload (the metric's configuration): exterior pulsating-sphere problem on an icosphere of
+5120 flat triangles (15360 DOF), rho = 1, c_p = 1, c_s = 0.5, 64 BDF2 gCQ contour points
+(dt = 0.1), collocation at centroids with the near-singular rule on, single layer V and
+I/2 + K compressed by 3D-ACA (eps = 1e-6) on an H-matrix partition (leaf 64, eta 1.5), far
+field complex64, near field complex128.
+
+One step = the whole hot path on resident inputs: partition, compression of V and I/2 + K
+(entries, pivots, fibres, per-slice ACA + recompression), and the all-frequency products
+y_l = V(s_l) x_l and (I/2 + K)(s_l) x_l for one right-hand side.
+
+value = kernel entries (3x3 ENTRY(i, j, l) blocks) generated per second over the step.
+Extra fields: all-frequency H-matvecs/s (apply only), the FP64 path's step time and the
+mixed vs FP64 speedup, the relative error against the FP64 oracle on sampled rows, the
+roofline of the compression kernel and the oracle's CPU throughput.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kernel entries/s and all-frequency H-matvecs/s at 1e-6 rel err; mixed vs FP64 speedup"
+# Algorithmic flops of one kernel evaluation (one quadrature point, one frequency) of the
+# regular rule, counted from the formulas: U -> 125, T -> 236.
+FLOPS_EVAL = {0: 125.0, 2: 236.0}
+QPTS_REGULAR = 7
+PEAK_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, non-packed FP32)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(level=4, L=64):
+    from paper_2607_15292_amd import workloads as W
+    X, T = W.icosphere(level)
+    T = T[:, [0, 2, 1]].copy()  # exterior domain: normals point into the sphere
+    s = W.bdf2_contour(L, 0.1)
+    return X, T, s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--level", type=int, default=4)
+    ap.add_argument("--freqs", type=int, default=64)
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--pool-gb", type=float, default=0.0, help="0 = library default")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the sharded design is described in "
+              "DESIGN.md); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_15292_amd import binding as B
+    from paper_2607_15292_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    X, T, s = workload(args.level, args.freqs)
+    K, L = len(T), len(s)
+    M = 3 * K
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(1.0, 1.0, 0.5)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=True)
+    stream = torch.cuda.current_stream()
+    c.set_stream(stream)
+    x_h = W.random_rhs(1, (1, L, M))
+    x = torch.tensor(x_h, device=dev)
+    ops_list = (B.OP_V, B.OP_HK)
+    pool = int(args.pool_gb * (1 << 30))
+
+    def step(prec, measure=False):
+        """One pass of the hot path; with measure, also times repeated applies and returns
+        the products on the host."""
+        st, ys, ams = [], [], []
+        for opk in ops_list:
+            op = c.compress(opk, eps3d=args.eps, leaf=64, eta=1.5, prec=prec, pool_bytes=pool)
+            y = op.apply(x)
+            st.append(op.stats())
+            if measure:
+                torch.cuda.synchronize()
+                ys.append(y.cpu().numpy())
+                y_buf = torch.empty_like(x)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
+                for _ in range(10):
+                    op.apply(x, y=y_buf)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                ams.append(ev0.elapsed_time(ev1) / 10)
+            op.destroy()
+        torch.cuda.synchronize()
+        return st, ys, ams
+
+    log("workload: K=%d L=%d; warmup %d" % (K, L, args.warmup))
+    for w in range(args.warmup):
+        st, _, _ = step(B.PREC_MIXED)
+        log("warmup step %d: kernel_ms=%s" % (w, [round(v["kernel_ms"], 2) for v in st]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats_steps = []
+    for k in range(args.steps):
+        st, _, _ = step(B.PREC_MIXED)
+        stats_steps.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec_step = (t1 - t0) / args.steps
+    ents = sum(v["entries_generated"] for v in stats_steps[-1])
+    log("timed: %.3f s/step, entries/step %d" % (sec_step, ents))
+
+    # one more mixed pass keeping the products and timing the applies alone
+    st_m, ymix, ams = step(B.PREC_MIXED, measure=True)
+    apply_ms = dict(zip(ops_list, ams))
+    log("apply ms:", apply_ms)
+
+    fp64 = None
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st_d, _, _ = step(B.PREC_F64)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        st_d2, ys_d, ams_d = step(B.PREC_F64, measure=True)
+        fp64 = {"sec_per_step": t3 - t2, "stats": st_d, "apply_ms": dict(zip(ops_list, ams_d)), "ys": ys_d}
+        log("fp64 step %.3f s" % (t3 - t2))
+
+    # roofline of the compression kernel (one launch per operator)
+    kern_ms = sum(v["kernel_ms"] for v in st_m)
+    flops = sum(v["entries_generated"] * QPTS_REGULAR * FLOPS_EVAL[opk] for v, opk in zip(st_m, ops_list))
+    achieved = flops / (kern_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_VALU, "traffic": None,
+                "kernel": "k_aca3d (compression, one launch per operator)", "kernel_ms": kern_ms}
+
+    # CPU baseline (oracle) on sampled rows; its results are also the accuracy reference
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        P = oracle.Problem(X, T, s, 1.0, 1.0, 0.5, near_on=True)
+        rng = np.random.default_rng(11)
+        rows = np.sort(rng.choice(K, size=args.cpu_rows, replace=False))
+        tc0 = time.perf_counter()
+        refs = {}
+        for opk in ops_list:
+            refs[opk] = P.matvec_rows(opk, rows, x_h)
+        tc1 = time.perf_counter()
+        n_ent = len(ops_list) * len(rows) * K * L
+        cpu = {"value": n_ent / (tc1 - tc0), "unit": "entries/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d element rows x %d elements x %d frequencies for V and I/2+K (%d entries), "
+                         "FP64 C oracle with OpenMP" % (len(rows), K, L, n_ent),
+               "seconds": tc1 - tc0}
+
+        def rel(y, ref):
+            yg = y.reshape(1, L, K, 3)[:, :, rows, :].reshape(1, L, -1)
+            return float(np.max(np.linalg.norm(yg - ref, axis=-1) / np.linalg.norm(ref, axis=-1)))
+
+        errs["mixed"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, ymix)}
+        if fp64:
+            errs["fp64"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, fp64["ys"])}
+    hmv = {str(k): 1e3 / v for k, v in apply_ms.items()}
+    out = {
+        "metric": METRIC,
+        "value": ents / sec_step,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed-f32-f64",
+        "data": "synthetic",
+        "config": {"workload": "pulsating sphere, icosphere %d triangles (%d DOF), V and I/2+K, %d BDF2 gCQ points, "
+                               "3D-ACA eps %.0e + H-matrix leaf 64 eta 1.5, complex64 far / complex128 near"
+                               % (K, M, L, args.eps),
+                   "elements": K, "frequencies": L, "rhs": 1},
+        "hmatvecs_per_s": hmv,
+        "matvecs_per_s_single_freq": {k: v * L for k, v in hmv.items()},
+        "compress_stats": [{k: v[k] for k in ("n_blocks", "n_near", "n_far", "n_dense_fallback", "rank_mean",
+                                               "rank_max", "aca_rank_mean", "aca_rank_max", "compression_rate",
+                                               "entries_generated", "kernel_ms")} for v in st_m],
+        "rel_err": errs,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if fp64:
+        out["fp64"] = {"ms_per_step": fp64["sec_per_step"] * 1e3,
+                       "hmatvecs_per_s": {str(k): 1e3 / v for k, v in fp64["apply_ms"].items()},
+                       "kernel_ms": [v["kernel_ms"] for v in fp64["stats"]],
+                       "rank_mean": [v["rank_mean"] for v in fp64["stats"]],
+                       "compression_rate": [v["compression_rate"] for v in fp64["stats"]]}
+        out["mixed_vs_fp64_speedup"] = fp64["sec_per_step"] / sec_step
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -101,6 +101,9 @@ typedef struct {
     double mixed_eps_floor; /* MIXED only: far-field tolerances are raised to at least this
                                value (complex64 entries cannot resolve less); default 1e-5 */
     int64_t pool_bytes;  /* device bytes reserved for faces, fibres and factors; 0 = auto */
+    int32_t far_dense_max; /* admissible blocks whose smaller side has at most this many
+                              elements keep dense faces (their per-slice ACA rank is close to
+                              full); 0 = per-slice ACA on every admissible block; default 48 */
 } bem_aca_opts;
 
 /* Statistics of an operator (compression rate as defined in Sec. 4.1: memory of the
@@ -114,8 +117,10 @@ typedef struct {
     int64_t bytes;                /* device bytes of faces, factors and fibres */
     double compression_rate;      /* bytes / (L * (3K)^2 * 16) */
     int64_t entries_generated;    /* ENTRY(i, j, l) 3x3 blocks evaluated during compression */
-    int64_t freq_hist_offset;     /* reserved (0) */
+    int64_t n_far_faces;          /* far faces stored as factors */
     double seconds;               /* wall time of the compression call */
+    double kernel_ms;             /* duration of the compression kernel (HIP events on the
+                                     context stream around its launch) */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */

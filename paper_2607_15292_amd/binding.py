@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbem.so")
+LIB_PATH = os.environ.get("BEM_LIBRARY", os.path.join(_HERE, "libbem.so"))
 
 BEM_OK = 0
 ERR_NAMES = {-1: "BEM_ERR_ARG", -2: "BEM_ERR_MESH", -3: "BEM_ERR_MATERIAL", -4: "BEM_ERR_FREQ",
@@ -38,7 +38,7 @@ class bem_quad(ctypes.Structure):
 class bem_aca_opts(ctypes.Structure):
     _fields_ = [("eps3d", ctypes.c_double), ("eps_aca", ctypes.c_double), ("eta", ctypes.c_double),
                 ("leaf", ctypes.c_int32), ("prec", ctypes.c_int32), ("mixed_eps_floor", ctypes.c_double),
-                ("pool_bytes", ctypes.c_int64)]
+                ("pool_bytes", ctypes.c_int64), ("far_dense_max", ctypes.c_int32)]
 
 
 class bem_stats(ctypes.Structure):
@@ -46,8 +46,8 @@ class bem_stats(ctypes.Structure):
                 ("n_dense_fallback", ctypes.c_int64), ("rank_min", ctypes.c_int32), ("rank_max", ctypes.c_int32),
                 ("rank_mean", ctypes.c_double), ("aca_rank_max", ctypes.c_int32), ("aca_rank_mean", ctypes.c_double),
                 ("bytes", ctypes.c_int64), ("compression_rate", ctypes.c_double),
-                ("entries_generated", ctypes.c_int64), ("freq_hist_offset", ctypes.c_int64),
-                ("seconds", ctypes.c_double)]
+                ("entries_generated", ctypes.c_int64), ("n_far_faces", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -210,9 +210,9 @@ class Context:
         return Operator(self, h)
 
     def compress(self, op, eps3d=1e-6, eps_aca=0.0, eta=1.5, leaf=64, prec=PREC_F64, mixed_eps_floor=1e-5,
-                 pool_bytes=0):
+                 pool_bytes=0, far_dense_max=48):
         o = bem_aca_opts(float(eps3d), float(eps_aca), float(eta), int(leaf), int(prec), float(mixed_eps_floor),
-                         int(pool_bytes))
+                         int(pool_bytes), int(far_dense_max))
         h = ctypes.c_void_p()
         self._check(lib().bem_compress(self.h, int(op), ctypes.byref(o), ctypes.byref(h)))
         return Operator(self, h)

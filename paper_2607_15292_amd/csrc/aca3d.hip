@@ -17,6 +17,15 @@
 // selector fibre), as Sec. 3 prescribes.  Pivots, inverses, norms: FP64.
 #include "aca3d.hpp"
 
+#ifdef BEM_PHASE_PROF
+#define PROF_T0(v) long long v = (threadIdx.x == 0) ? (long long)__builtin_readcyclecounter() : 0
+#define PROF_ADD(A, ph, v) \
+    do { if (threadIdx.x == 0) atomicAdd((unsigned long long*)(A).prof + (ph), (unsigned long long)((long long)__builtin_readcyclecounter() - v)); } while (0)
+#else
+#define PROF_T0(v) (void)0
+#define PROF_ADD(A, ph, v) (void)0
+#endif
+
 namespace bem {
 
 namespace {
@@ -131,12 +140,12 @@ __device__ __forceinline__ blk face_block(const char* pool, const FaceDesc& f, i
 {
     blk b;
     if (f.kk == 0) {
-        const zd* H = (const zd*)(pool + f.face_off);
+        const cx<T>* H = (const cx<T>*)(pool + f.face_off);
         size_t ld = 3 * (size_t)n;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) b.a[3 * a + c] = H[(size_t)(3 * i + a) * ld + 3 * j + c];
+            for (int c = 0; c < 3; ++c) b.a[3 * a + c] = ldz(H + (size_t)(3 * i + a) * ld + 3 * j + c);
         return b;
     }
     const cx<T>* U = (const cx<T>*)(pool + f.face_off);
@@ -287,22 +296,28 @@ __device__ void fibre_and_norm(const CompressArgs& A, const BlockIn& bi, FaceDes
 
 // ---------------------------------------------------------------- near blocks
 
+template <typename T, bool MIXED>
 __device__ void near_face(const CompressArgs& A, const BlockIn& bi, FaceDesc* fd, int d, int k, bool residual,
                           double& s3max, int& pidx, double& fmax2, double& hn2, Lds& S, long long& nent)
 {
     const int m = bi.rs, n = bi.cs;
-    zd* H = (zd*)(A.pool + fd[d].face_off);
+    cx<T>* H = (cx<T>*)(A.pool + fd[d].face_off);
     size_t ld = 3 * (size_t)n;
     double best = -1.0, fm = 0.0, h2 = 0.0;
     int bidx = 0x7fffffff;
     for (int p = threadIdx.x; p < m * n; p += WG) {
         int i = p / n, j = p - i * n;
-        blk E = entry_dispatch<false>(A.c, A.op, bi.rb + i, bi.cb + j, k);
-        if (residual) sub_residual<double>(E, A, fd, d, m, n, i, j, k);
+        blk E = entry_dispatch<MIXED>(A.c, A.op, bi.rb + i, bi.cb + j, k);
+        if (residual) sub_residual<T>(E, A, fd, d, m, n, i, j, k);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) H[(size_t)(3 * i + a) * ld + 3 * j + c] = E.a[3 * a + c];
+            for (int c = 0; c < 3; ++c) stz(H + (size_t)(3 * i + a) * ld + 3 * j + c, E.a[3 * a + c]);
+        if (sizeof(T) == 4) {
+            // pivot search and norms on the stored (rounded) face
+#pragma unroll
+            for (int t = 0; t < 9; ++t) E.a[t] = {(double)(float)E.a[t].re, (double)(float)E.a[t].im};
+        }
         double e2 = blk_fro2(E);
         h2 += e2;
         fm = fmax(fm, e2);
@@ -600,16 +615,20 @@ __device__ void wg_qr(zd* X, int rows, int kc, zd* G, zd* Rtmp, zd* Rout, double
 }
 
 // One-sided Jacobi SVD of M (kc x kc, column-major): M VJ = W with orthogonal columns.
+// Round-robin ordering; every column pair of a round is handled by a group of JG lanes of
+// one wavefront (dot products reduced by lane shuffles within the group).
+constexpr int JG = 8;
 __device__ void wg_jacobi(zd* M, zd* VJ, int kc, Lds& S)
 {
     for (int q = threadIdx.x; q < kc * kc; q += WG) VJ[q] = (q % kc == q / kc) ? zd{1.0, 0.0} : zd{0.0, 0.0};
     __syncthreads();
-    int np = kc + (kc & 1);
+    const int np = kc + (kc & 1);
+    const int g = threadIdx.x / JG, gl = threadIdx.x % JG;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (threadIdx.x == 0) S.flag = 0;
         __syncthreads();
         for (int rnd = 0; rnd < np - 1; ++rnd) {
-            for (int pr = threadIdx.x; pr < np / 2; pr += WG) {
+            for (int pr = g; pr < np / 2; pr += WG / JG) {
                 int p, q;
                 if (pr == 0) {
                     p = rnd;
@@ -623,27 +642,35 @@ __device__ void wg_jacobi(zd* M, zd* VJ, int kc, Lds& S)
                     p = q;
                     q = t;
                 }
-                if (q >= kc) continue;
+                if (q >= kc) continue;  // uniform within the group
                 zd* mp = M + (size_t)p * kc;
                 zd* mq = M + (size_t)q * kc;
-                double al = 0.0, be = 0.0;
-                zd ga = {0.0, 0.0};
-                for (int r = 0; r < kc; ++r) {
+                double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+                for (int r = gl; r < kc; r += JG) {
                     al += abs2(mp[r]);
                     be += abs2(mq[r]);
-                    ga += conj_mul(mp[r], mq[r]);
+                    zd c = conj_mul(mp[r], mq[r]);
+                    gr += c.re;
+                    gi += c.im;
                 }
-                double g = sqrt(abs2(ga));
-                if (!(g > 1e-15 * sqrt(al * be)) || g == 0.0) continue;
-                S.flag = 1;
-                zd e = ga * (1.0 / g);  // phase of gamma
-                double zeta = (be - al) / (2.0 * g);
+#pragma unroll
+                for (int o = 1; o < JG; o <<= 1) {
+                    al += __shfl_xor(al, o, 64);
+                    be += __shfl_xor(be, o, 64);
+                    gr += __shfl_xor(gr, o, 64);
+                    gi += __shfl_xor(gi, o, 64);
+                }
+                double gabs = sqrt(gr * gr + gi * gi);
+                if (!(gabs > 1e-15 * sqrt(al * be)) || gabs == 0.0) continue;
+                if (gl == 0) S.flag = 1;
+                zd e = {gr / gabs, gi / gabs};  // phase of gamma
+                double zeta = (be - al) / (2.0 * gabs);
                 double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
                 zd ce = conj(e);
                 zd* vp = VJ + (size_t)p * kc;
                 zd* vq = VJ + (size_t)q * kc;
-                for (int r = 0; r < kc; ++r) {
+                for (int r = gl; r < kc; r += JG) {
                     zd a = mp[r], b = mq[r] * ce;
                     mp[r] = c * a - s * b;
                     mq[r] = (s * a + c * b) * e;
@@ -774,11 +801,13 @@ __device__ void far_scan(const CompressArgs& A, const BlockIn& bi, const FaceDes
 template <typename T, bool MIXED>
 __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
 {
+    PROF_T0(tpall);
     const BlockIn bi = A.blocks[b];
     const int m = bi.rs, n = bi.cs, L = A.L;
-    const bool far = bi.far != 0;
+    const bool far = bi.lowrank != 0;  // faces by per-slice ACA
+    const long long fbytes = ((long long)sizeof(cx<T>) * 9 * m * n + 15) & ~15LL;
     FaceDesc* fd = A.faces + (size_t)b * L;
-    const double eps = far ? A.eps3d_far : A.eps3d;
+    const double eps = bi.far ? A.eps3d_far : A.eps3d;
     const double eps_aca = A.eps_aca_far;
     const int kmax = A.kmax;
     AcaWork w = aca_work(scratch, m, n, kmax);
@@ -794,7 +823,7 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
         int pidx = 0;
         if (!far) {
             if (threadIdx.x == 0) {
-                long long off = pool_alloc(A, (long long)sizeof(zd) * 9 * ((long long)m * n + L));
+                long long off = pool_alloc(A, fbytes + (long long)sizeof(zd) * 9 * L);
                 S.off = off;
             }
             __syncthreads();
@@ -806,15 +835,20 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
             }
             if (threadIdx.x == 0) {
                 fd[d].face_off = off;
-                fd[d].fib_off = off + (long long)sizeof(zd) * 9 * m * n;
+                fd[d].fib_off = off + fbytes;
                 fd[d].kk = 0;
                 fd[d].k = k;
                 fd[d].sel = 0;
+                fd[d].fp32 = sizeof(T) == 4;
             }
             __syncthreads();
-            near_face(A, bi, fd, d, k, true, s3max, pidx, fmax2, hn2, S, nent);
+            PROF_T0(tp0);
+            near_face<T, MIXED>(A, bi, fd, d, k, true, s3max, pidx, fmax2, hn2, S, nent);
+            PROF_ADD(A, 0, tp0);
         } else {
+            PROF_T0(tp1);
             int kc = far_aca<T, MIXED>(A, bi, fd, d, k, true, w, kmax, eps_aca, S, nent);
+            PROF_ADD(A, 1, tp1);
             if (threadIdx.x == 0) {
                 long long off = pool_alloc(A, (long long)sizeof(zd) * 9 * L);
                 S.off = off;
@@ -829,7 +863,9 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
             int kk = 0;
             FaceDesc f{0, foff, 0, k, 0, 0};
             if (kc > 0) {
+                PROF_T0(tp2);
                 kk = far_recompress<T>(A, bi, f, w, kc, eps_aca, S);
+                PROF_ADD(A, 2, tp2);
                 if (kk < 0) {
                     status = 2;
                     break;
@@ -841,7 +877,9 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
             }
             __syncthreads();
             aca_cols = max(aca_cols, kk);
+            PROF_T0(tp3);
             if (kk > 0) far_scan<T>(A, bi, fd[d], s3max, pidx, fmax2, hn2, S);
+            PROF_ADD(A, 3, tp3);
         }
         // ---- converged residual / no regular pivot
         if (d > 0 && sqrt(hn2) <= eps * sqrt(fmax(norm2, 0.0))) {
@@ -862,7 +900,9 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
         }
         __syncthreads();
         double cross = 0.0, tdd = 0.0;
+        PROF_T0(tp4);
         fibre_and_norm<T, MIXED>(A, bi, fd, d, k, pi, pj, norm2, cross, tdd, S, nent);
+        PROF_ADD(A, far ? 5 : 4, tp4);
         double fn2 = S.fnorm;
         int nk = S.nextk;
         __syncthreads();
@@ -878,7 +918,7 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
         // dense storage: one face per frequency, selector fibres
         for (int kf = 0; kf < L; ++kf) {
             if (!far) {
-                if (threadIdx.x == 0) S.off = pool_alloc(A, (long long)sizeof(zd) * 9 * ((long long)m * n + L));
+                if (threadIdx.x == 0) S.off = pool_alloc(A, fbytes + (long long)sizeof(zd) * 9 * L);
                 __syncthreads();
                 long long off = S.off;
                 __syncthreads();
@@ -886,11 +926,11 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
                     status = 2;
                     break;
                 }
-                if (threadIdx.x == 0) fd[kf] = FaceDesc{off, off + (long long)sizeof(zd) * 9 * m * n, 0, kf, 1, 0};
+                if (threadIdx.x == 0) fd[kf] = FaceDesc{off, off + fbytes, 0, kf, 1, (int)(sizeof(T) == 4)};
                 __syncthreads();
                 double s3, fm2, h2;
                 int pdx;
-                near_face(A, bi, fd, kf, kf, false, s3, pdx, fm2, h2, S, nent);
+                near_face<T, MIXED>(A, bi, fd, kf, kf, false, s3, pdx, fm2, h2, S, nent);
             } else {
                 int kc = far_aca<T, MIXED>(A, bi, fd, kf, kf, false, w, kmax, eps_aca, S, nent);
                 if (threadIdx.x == 0) S.off = pool_alloc(A, (long long)sizeof(zd) * 9 * L);
@@ -937,6 +977,7 @@ __device__ void run_block(const CompressArgs& A, int b, double* scratch, Lds& S)
         A.out[b] = o;
         if (status) atomicOr(A.err, status);
     }
+    PROF_ADD(A, bi.far ? 7 : 6, tpall);
     __syncthreads();
 }
 
@@ -953,7 +994,7 @@ __global__ __launch_bounds__(WG) void k_aca3d(CompressArgs A)
         if (q >= A.nblocks) break;
         int b = A.order[q];
         if (A.blocks[b].far)
-            run_block<T, MIXED>(A, b, scratch, S);
+            run_block<T, MIXED>(A, b, scratch, S);  // admissible: precision of the far field
         else
             run_block<double, false>(A, b, scratch, S);
     }

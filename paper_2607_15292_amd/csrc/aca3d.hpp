@@ -9,11 +9,12 @@ constexpr int MAX_L = 256;  // largest number of frequencies of one compression
 
 struct BlockIn {
     int rb, rs, cb, cs;  // rows [rb, rb + rs), columns [cb, cb + cs) in cluster order
-    int far;
+    int far;             // admissible (far field): mixed precision applies
+    int lowrank;         // faces by per-slice ACA + recompression (else dense faces)
 };
 
-// One face-fibre pair of a block.  kk == 0: dense face (3m x 3n complex128 row-major at
-// face_off); kk > 0: factors Ubar (3m x kk) then Vbar (3n x kk), column-major, complex64
+// One face-fibre pair of a block.  kk == 0: dense face (3m x 3n row-major at face_off,
+// complex128, or complex64 when fp32); kk > 0: factors Ubar (3m x kk) then Vbar (3n x kk), column-major, complex64
 // (MIXED) or complex128; kk < 0: empty face.  fib_off: fibre f[L][3][3] complex128.
 // sel = 1: dense-fallback face, its fibre selects frequency k only.
 struct FaceDesc {
@@ -22,7 +23,7 @@ struct FaceDesc {
     int kk;
     int k;
     int sel;
-    int pad;
+    int fp32;  // dense face stored as complex64 (far-field blocks of the mixed path)
 };
 
 struct BlockOut {
@@ -52,6 +53,7 @@ struct CompressArgs {
     double* scratch;
     size_t scratch_per_slot;  // doubles
     double eps3d, eps3d_far, eps_aca_far;
+    long long* prof;          // per-phase cycle sums (built with BEM_PHASE_PROF only)
 };
 
 size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
@@ -66,6 +68,7 @@ struct ApplyFace {
     int sel;       // selector fibre (frequency ksel only)
     int ksel;
     int block;     // index into the block table
+    int fp32;      // dense face in complex64
     long long t_off;  // far faces: first row of this face's kk rows of V^H Z in the workspace [rows][ncols]
     long long zw_off; // weighted sum: offset (in zd) of this face's contracted vector (3 * cs entries)
 };

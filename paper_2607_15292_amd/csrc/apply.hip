@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void k_rows(ApplyArgs A, const zd* zw_all, int
         const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
         if (F.kk == 0) {
             const zd* H = (const zd*)(A.pool + F.face_off);
+            const zf* Hf = (const zf*)(A.pool + F.face_off);
             const size_t ld = 3 * (size_t)n;
             for (int j0 = 0; j0 < n; j0 += MAXN) {
                 int nj = min(MAXN, n - j0);
@@ -113,11 +114,19 @@ __global__ __launch_bounds__(256) void k_rows(ApplyArgs A, const zd* zw_all, int
                 }
                 __syncthreads();
                 if (slot < rsz) {
-                    const zd* h0 = H + (size_t)(3 * (ioff + slot)) * ld + 3 * j0;
-                    for (int jc = 0; jc < 3 * nj; ++jc) {
-                        zd z = Zs[jc * CW + col_l];
+                    const size_t o0 = (size_t)(3 * (ioff + slot)) * ld + 3 * j0;
+                    if (F.fp32) {
+                        for (int jc = 0; jc < 3 * nj; ++jc) {
+                            zd z = Zs[jc * CW + col_l];
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) acc[a] = fma_c(h0[(size_t)a * ld + jc], z, acc[a]);
+                            for (int a = 0; a < 3; ++a) acc[a] = fma_c(ldz(Hf + o0 + (size_t)a * ld + jc), z, acc[a]);
+                        }
+                    } else {
+                        for (int jc = 0; jc < 3 * nj; ++jc) {
+                            zd z = Zs[jc * CW + col_l];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) acc[a] = fma_c(H[o0 + (size_t)a * ld + jc], z, acc[a]);
+                        }
                     }
                 }
             }

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <cstdio>
 
 #include "aca3d.hpp"
 #include "host.hpp"
@@ -54,6 +55,7 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
             a.fib_off = f.fib_off;
             a.kk = f.kk;
             a.sel = f.sel;
+            a.fp32 = f.fp32;
             a.ksel = f.k;
             a.block = b;
             a.t_off = 0;
@@ -151,12 +153,14 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     const int nb = (int)C->part.blocks.size();
     C->blocks.resize(nb);
     int mmax = 1, nmax = 1, minmax = 1;
-    int64_t n_far = 0;
+    int64_t n_far = 0, n_lowrank = 0;
     for (int b = 0; b < nb; ++b) {
         const BlockDesc& d = C->part.blocks[b];
-        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far};
-        if (d.far) {
-            ++n_far;
+        int lowrank = d.far && std::min(d.rs, d.cs) > o.far_dense_max;
+        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, lowrank};
+        n_far += d.far;
+        if (lowrank) {
+            ++n_lowrank;
             mmax = std::max(mmax, d.rs);
             nmax = std::max(nmax, d.cs);
             minmax = std::max(minmax, std::min(d.rs, d.cs));
@@ -168,12 +172,12 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     std::vector<double> cost(nb);
     for (int b = 0; b < nb; ++b) {
         const BlockIn& B = C->blocks[b];
-        cost[b] = B.far ? 40.0 * (B.rs + B.cs) + 2.0 * B.rs * B.cs : 12.0 * B.rs * B.cs;
+        cost[b] = B.lowrank ? 400.0 * (B.rs + B.cs) + 2.0 * B.rs * B.cs : 12.0 * B.rs * B.cs;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     const int kmax = 3 * std::max(2, std::min(64, minmax));
     const int slots = std::max(1, std::min(nb, 1024));
-    size_t per_slot = n_far ? aca_scratch_doubles(mmax, nmax, kmax) : 64;
+    size_t per_slot = n_lowrank ? aca_scratch_doubles(mmax, nmax, kmax) : 64;
     per_slot = (per_slot + 31) & ~(size_t)31;
     DevBuf scratch, blocks_aux;
     scratch.alloc(per_slot * slots * sizeof(double));
@@ -187,50 +191,86 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     int* err_dev = (int*)(aux + 64);
     unsigned long long* top_dev = (unsigned long long*)(aux + 128);
     BEM_HIP_TRY(hipMemcpyAsync(order_dev, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
-    BEM_HIP_TRY(hipMemsetAsync(aux, 0, 192, st));
     C->faces_dev.alloc(sizeof(FaceDesc) * (size_t)nb * L);
-    BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
     C->out_dev.alloc(sizeof(BlockOut) * nb);
-    // pool
+    // pool: caller-sized, or auto-sized with up to three attempts (growing on overflow)
     size_t pool_bytes = (size_t)o.pool_bytes;
-    if (pool_bytes == 0) {
+    const bool auto_pool = pool_bytes == 0;
+    if (auto_pool) {
         size_t fr = 0, tot = 0;
         BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
-        size_t dense = (size_t)L * 9 * (size_t)K * K * 16;  // dense array size
-        pool_bytes = std::min<size_t>((size_t)(0.6 * (double)fr), std::max<size_t>(dense / 4 + ((size_t)1 << 28), (size_t)1 << 30));
+        double dense = (double)L * 9.0 * (double)K * (double)K * 16.0;  // dense array size
+        double want = std::max(0.3 * dense + (double)(1 << 30), (double)(1 << 30));
+        pool_bytes = (size_t)std::min(0.45 * (double)fr, want);
     }
-    C->pool.alloc(pool_bytes);
     BEM_HIP_TRY(hipStreamSynchronize(st));
-
-    CompressArgs A;
-    A.c = ctx->devctx(C->geo.geo, C->perm_dev.as<int>());
-    A.op = op;
-    A.mixed = C->mixed;
-    A.L = L;
-    A.nblocks = nb;
-    A.kmax = kmax;
-    A.blocks = C->blocks_dev.as<BlockIn>();
-    A.order = order_dev;
-    A.faces = C->faces_dev.as<FaceDesc>();
-    A.out = C->out_dev.as<BlockOut>();
-    A.pool = C->pool.as<char>();
-    A.pool_cap = pool_bytes;
-    A.pool_top = top_dev;
-    A.queue = queue_dev;
-    A.err = err_dev;
-    A.scratch = scratch.as<double>();
-    A.scratch_per_slot = per_slot;
-    A.eps3d = o.eps3d;
-    A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
-    A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
-    launch_aca3d(A, slots, st);
-    BEM_HIP_TRY(hipStreamSynchronize(st));
+    float kms = 0.f;
     int err = 0;
-    unsigned long long top = 0;
-    BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
-    BEM_HIP_TRY(hipMemcpy(&top, top_dev, sizeof(top), hipMemcpyDeviceToHost));
-    if (err & 2) throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes overflowed (" +
-                                              std::to_string(top) + " requested); raise pool_bytes");
+    for (int attempt = 0;; ++attempt) {
+        C->pool.release();
+        C->pool.alloc(pool_bytes);
+        BEM_HIP_TRY(hipMemsetAsync(aux, 0, 192, st));
+        BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
+        CompressArgs A;
+        A.c = ctx->devctx(C->geo.geo, C->perm_dev.as<int>());
+        A.op = op;
+        A.mixed = C->mixed;
+        A.L = L;
+        A.nblocks = nb;
+        A.kmax = kmax;
+        A.blocks = C->blocks_dev.as<BlockIn>();
+        A.order = order_dev;
+        A.faces = C->faces_dev.as<FaceDesc>();
+        A.out = C->out_dev.as<BlockOut>();
+        A.pool = C->pool.as<char>();
+        A.pool_cap = pool_bytes;
+        A.pool_top = top_dev;
+        A.queue = queue_dev;
+        A.err = err_dev;
+        A.scratch = scratch.as<double>();
+        A.scratch_per_slot = per_slot;
+        A.eps3d = o.eps3d;
+        A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
+        A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
+#ifdef BEM_PHASE_PROF
+        DevBuf profbuf;
+        profbuf.alloc(16 * sizeof(long long));
+        BEM_HIP_TRY(hipMemsetAsync(profbuf.p, 0, 16 * sizeof(long long), st));
+        A.prof = profbuf.as<long long>();
+#else
+        A.prof = nullptr;
+#endif
+        hipEvent_t ev0, ev1;
+        BEM_HIP_TRY(hipEventCreate(&ev0));
+        BEM_HIP_TRY(hipEventCreate(&ev1));
+        BEM_HIP_TRY(hipEventRecord(ev0, st));
+        launch_aca3d(A, slots, st);
+        BEM_HIP_TRY(hipEventRecord(ev1, st));
+        BEM_HIP_TRY(hipStreamSynchronize(st));
+        BEM_HIP_TRY(hipEventElapsedTime(&kms, ev0, ev1));
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+#ifdef BEM_PHASE_PROF
+        {
+            long long pr[16];
+            BEM_HIP_TRY(hipMemcpy(pr, profbuf.p, sizeof(pr), hipMemcpyDeviceToHost));
+            const char* names[8] = {"near_face", "far_aca", "far_recompress", "far_scan", "fibre_norm_near",
+                                    "fibre_norm_far", "block_near", "block_far"};
+            for (int q = 0; q < 8; ++q) fprintf(stderr, "phase %-16s %.3e cycles\n", names[q], (double)pr[q]);
+        }
+#endif
+        unsigned long long top = 0;
+        BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
+        BEM_HIP_TRY(hipMemcpy(&top, top_dev, sizeof(top), hipMemcpyDeviceToHost));
+        if (!(err & 2)) break;
+        if (!auto_pool || attempt >= 2)
+            throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes overflowed (" +
+                                         std::to_string(top) + " requested); raise pool_bytes");
+        C->pool.release();
+        size_t fr = 0, tot = 0;
+        BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
+        pool_bytes = (size_t)std::min(0.85 * (double)fr, 2.5 * (double)top + (double)(1 << 28));
+    }
     C->faces.resize((size_t)nb * L);
     C->outs.resize(nb);
     BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L, hipMemcpyDeviceToHost));
@@ -260,7 +300,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             const FaceDesc& f = C->faces[(size_t)b * L + d];
             bytes += (int64_t)L * 9 * sizeof(zd);
             if (f.kk == 0) {
-                bytes += (int64_t)9 * B.rs * B.cs * sizeof(zd);
+                bytes += (int64_t)9 * B.rs * B.cs * (int64_t)((B.far && C->mixed) ? sizeof(zf) : sizeof(zd));
             } else if (f.kk > 0) {
                 bytes += (int64_t)3 * (B.rs + B.cs) * f.kk * (int64_t)(B.far ? zsz : sizeof(zd));
                 acasum += f.kk;
@@ -273,6 +313,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     S.bytes = bytes;
     S.compression_rate = (double)bytes / ((double)L * 9.0 * (double)K * (double)K * 16.0);
     S.entries_generated = ent;
+    S.n_far_faces = nfarfaces;
+    S.kernel_ms = kms;
     S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BEM_OK;
 }
