@@ -1,4 +1,5 @@
-// aca3d.hpp -- device-side data of the compressed operator and the compression launch.
+// aca3d.hpp -- device-side data of the compressed operator and the launches of the
+// compression pipeline and of the products.
 #pragma once
 
 #include "lib.hpp"
@@ -6,32 +7,45 @@
 namespace bem {
 
 constexpr int MAX_L = 256;  // largest number of frequencies of one compression
+constexpr int TILE = 256;   // pairs (i, j) per workgroup in the tiled phases
 
 struct BlockIn {
     int rb, rs, cb, cs;  // rows [rb, rb + rs), columns [cb, cb + cs) in cluster order
-    int far;             // admissible (far field): mixed precision applies
+    int far;             // admissible (far field): the mixed path computes it in FP32
     int lowrank;         // faces by per-slice ACA + recompression (else dense faces)
+    int tile0, ntile;    // range of this block's pair tiles
 };
 
 // One face-fibre pair of a block.  kk == 0: dense face (3m x 3n row-major at face_off,
-// complex128, or complex64 when fp32); kk > 0: factors Ubar (3m x kk) then Vbar (3n x kk), column-major, complex64
-// (MIXED) or complex128; kk < 0: empty face.  fib_off: fibre f[L][3][3] complex128.
-// sel = 1: dense-fallback face, its fibre selects frequency k only.
+// complex128, or complex64 when fp32); kk > 0: factors Ubar (3m x kk) then Vbar (3n x kk),
+// row-major, complex64 (mixed) or complex128, with H = Ubar Vbar^H; kk < 0: empty face.
+// fib_off: fibre f[L][3][3] complex128.  sel = 1: dense-fallback face, its fibre selects
+// frequency k only.
 struct FaceDesc {
     long long face_off;
     long long fib_off;
     int kk;
     int k;
     int sel;
-    int fp32;  // dense face stored as complex64 (far-field blocks of the mixed path)
+    int fp32;
 };
 
-struct BlockOut {
-    int rank;
-    int fallback;
-    int status;    // 0 ok, 2 pool overflow
-    int aca_cols;  // largest far-face rank
+// Per-block state of Algorithm 1 between the phases of one step.
+struct BlockState {
+    int k;          // current frequency k_d
+    int rank;       // kept face-fibre pairs
+    int active;     // iterating
+    int fallback;   // dense storage requested
+    int stop;       // this step ends the block (no fibre, no norm update)
+    int piv;        // pivot pair of the current face
+    int nextk;      // next frequency
+    int kc;         // ACA columns of the current face
+    int aca_max;    // largest stored far-face rank
+    int pad;
+    double norm2;   // ||C^(d)||_F^2
+    double hn2, fmax2, s3max, fn2;
     long long entries;
+    zd pinv[9];
 };
 
 struct CompressArgs {
@@ -41,23 +55,36 @@ struct CompressArgs {
     int L;
     int nblocks;
     int kmax;               // column capacity of the per-slice ACA (multiple of 3)
+    int d;                  // current step
     const BlockIn* blocks;
-    const int* order;       // processing order (largest work first)
     FaceDesc* faces;        // [nblocks][L]
-    BlockOut* out;          // [nblocks]
+    BlockState* st;         // [nblocks]
+    unsigned char* used;    // [nblocks][L]
+    zd* Fda;                // [nblocks][L][9]: F_{d,a} = sum_k f_d[k] f_a[k]^H
+    double* tp;             // tile partials [ntiles][8]
+    const int* list;        // work list of this launch: block ids, or tiles packed as (block << 12) | tile
+    int nlist;
     char* pool;
     unsigned long long pool_cap;
     unsigned long long* pool_top;
-    int* queue;
     int* err;
     double* scratch;
     size_t scratch_per_slot;  // doubles
     double eps3d, eps3d_far, eps_aca_far;
-    long long* prof;          // per-phase cycle sums (built with BEM_PHASE_PROF only)
 };
 
 size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
-void launch_aca3d(const CompressArgs& A, int slots, hipStream_t st);
+void launch_init(const CompressArgs& A, hipStream_t st);
+void launch_face_dense(const CompressArgs& A, hipStream_t st);
+void launch_aca(const CompressArgs& A, hipStream_t st);
+void launch_scan_lr(const CompressArgs& A, hipStream_t st);
+void launch_pivot(const CompressArgs& A, hipStream_t st);
+void launch_fibre(const CompressArgs& A, hipStream_t st);
+void launch_cross_dense(const CompressArgs& A, hipStream_t st);
+void launch_cross_lr(const CompressArgs& A, hipStream_t st);
+void launch_final(const CompressArgs& A, hipStream_t st);
+void launch_fallback(const CompressArgs& A, int kf, hipStream_t st);
+void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st);
 
 // ---------------------------------------------------------------- apply (apply.hip)
 
@@ -69,6 +96,7 @@ struct ApplyFace {
     int ksel;
     int block;     // index into the block table
     int fp32;      // dense face in complex64
+    int pad;
     long long t_off;  // far faces: first row of this face's kk rows of V^H Z in the workspace [rows][ncols]
     long long zw_off; // weighted sum: offset (in zd) of this face's contracted vector (3 * cs entries)
 };
@@ -77,9 +105,9 @@ struct ApplyArgs {
     const BlockIn* blocks;
     const ApplyFace* faces;
     int nfaces;
-    const int* row_faces;      // faces grouped by leaf row cluster: CSR over row_ptr
+    const int* row_faces;      // faces grouped by row chunk: CSR over row_ptr
     const int* row_ptr;
-    const int* row_start;      // leaf row cluster start (cluster order) per group
+    const int* row_start;      // row chunk start (cluster order) per group
     const int* row_size;
     int nrow_groups;
     const char* pool;

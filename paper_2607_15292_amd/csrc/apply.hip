@@ -53,33 +53,39 @@ __device__ __forceinline__ void z_entry(const ApplyArgs& A, const ApplyFace& F, 
     mul3(f, v, z);
 }
 
-// far faces: T[t][col] = sum_{j, c} conj(Vbar[3j + c, t]) Z[3j + c][col]
+// far faces: T[t][col] = sum_{j, c} conj(Vbar[3j + c, t]) Z[3j + c][col]   (Vbar row-major)
 template <typename T, bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_far_products(ApplyArgs A, const zd* zw_all, int ncols)
+__device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const zd* zw_all, int ncols)
 {
-    int fi = blockIdx.x;
-    const ApplyFace F = A.faces[fi];
-    if (F.kk <= 0) return;
     const BlockIn B = A.blocks[F.block];
     const int m = B.rs, n = B.cs, kk = F.kk;
     const cx<T>* V = (const cx<T>*)(A.pool + F.face_off) + (size_t)3 * m * kk;
     const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
     zd* Tout = A.tbuf + F.t_off * (size_t)ncols;
     for (int q = threadIdx.x; q < kk * ncols; q += 256) {
-        int t = q / ncols, col = q - t * ncols;
+        int col = q / kk, t = q - col * kk;  // consecutive threads: consecutive t (contiguous Vbar rows)
         zd acc = {0.0, 0.0};
         for (int j = 0; j < n; ++j) {
             zd z[3];
             z_entry<WEIGHTED>(A, F, B, zw, j, col, z);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc += conj_mul(ldz(V + (size_t)t * 3 * n + 3 * j + c), z[c]);
+            for (int c = 0; c < 3; ++c) acc += conj_mul(ldz(V + (size_t)(3 * j + c) * kk + t), z[c]);
         }
         Tout[(size_t)t * ncols + col] = acc;
     }
 }
 
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_far_products(ApplyArgs A, const zd* zw_all, int ncols)
+{
+    const ApplyFace F = A.faces[blockIdx.x];
+    if (F.kk <= 0) return;
+    if (F.fp32) far_products_face<float, WEIGHTED>(A, F, zw_all, ncols);
+    else far_products_face<double, WEIGHTED>(A, F, zw_all, ncols);
+}
+
 // rows: one workgroup per (row chunk, column chunk); thread = (row slot, column)
-template <typename T, bool WEIGHTED>
+template <bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_rows(ApplyArgs A, const zd* zw_all, int ncols, zd* yout)
 {
     __shared__ zd Zs[3 * MAXN * CW];
@@ -131,14 +137,26 @@ __global__ __launch_bounds__(256) void k_rows(ApplyArgs A, const zd* zw_all, int
                 }
             }
         } else if (slot < rsz && col < ncols) {
-            const cx<T>* U = (const cx<T>*)(A.pool + F.face_off);
+            const int kk = F.kk;
             const zd* Tf = A.tbuf + F.t_off * (size_t)ncols;
-            for (int t = 0; t < F.kk; ++t) {
-                zd tv = Tf[(size_t)t * ncols + col];
+            const size_t r0 = (size_t)(3 * (ioff + slot)) * kk;
+            if (F.fp32) {
+                const zf* U = (const zf*)(A.pool + F.face_off) + r0;
+                for (int t = 0; t < kk; ++t) {
+                    zd tv = Tf[(size_t)t * ncols + col];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) acc[a] = fma_c(ldz(U + (size_t)t * 3 * m + 3 * (ioff + slot) + a), tv, acc[a]);
+                    for (int a = 0; a < 3; ++a) acc[a] = fma_c(ldz(U + (size_t)a * kk + t), tv, acc[a]);
+                }
+            } else {
+                const zd* U = (const zd*)(A.pool + F.face_off) + r0;
+                for (int t = 0; t < kk; ++t) {
+                    zd tv = Tf[(size_t)t * ncols + col];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) acc[a] = fma_c(U[(size_t)a * kk + t], tv, acc[a]);
+                }
             }
         }
+        (void)m;
     }
     if (slot < rsz && col < ncols) {
         size_t M = 3 * (size_t)A.K;
@@ -221,34 +239,24 @@ void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nr
 void launch_apply(const ApplyArgs& A, hipStream_t st)
 {
     int ncols = A.L * A.nrhs;
-    if (A.mixed)
-        hipLaunchKernelGGL((k_far_products<float, false>), dim3(A.nfaces), dim3(256), 0, st, A, nullptr, ncols);
-    else
-        hipLaunchKernelGGL((k_far_products<double, false>), dim3(A.nfaces), dim3(256), 0, st, A, nullptr, ncols);
+    if (A.nfaces > 0) hipLaunchKernelGGL((k_far_products<false>), dim3(A.nfaces), dim3(256), 0, st, A, nullptr, ncols);
     BEM_HIP_TRY(hipGetLastError());
     dim3 grid(A.nrow_groups, (ncols + CW - 1) / CW);
-    if (A.mixed)
-        hipLaunchKernelGGL((k_rows<float, false>), grid, dim3(256), 0, st, A, nullptr, ncols, A.y);
-    else
-        hipLaunchKernelGGL((k_rows<double, false>), grid, dim3(256), 0, st, A, nullptr, ncols, A.y);
+    hipLaunchKernelGGL((k_rows<false>), grid, dim3(256), 0, st, A, nullptr, ncols, A.y);
     BEM_HIP_TRY(hipGetLastError());
 }
 
 // W in cluster order [L][3K]; zw: [nfaces][3K] workspace; y in cluster order [3K].
 void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_contract, dim3(A.nfaces), dim3(256), 0, st, A, W, zw);
-    BEM_HIP_TRY(hipGetLastError());
-    if (A.mixed)
-        hipLaunchKernelGGL((k_far_products<float, true>), dim3(A.nfaces), dim3(256), 0, st, A, zw, 1);
-    else
-        hipLaunchKernelGGL((k_far_products<double, true>), dim3(A.nfaces), dim3(256), 0, st, A, zw, 1);
-    BEM_HIP_TRY(hipGetLastError());
+    if (A.nfaces > 0) {
+        hipLaunchKernelGGL(k_contract, dim3(A.nfaces), dim3(256), 0, st, A, W, zw);
+        BEM_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_far_products<true>), dim3(A.nfaces), dim3(256), 0, st, A, zw, 1);
+        BEM_HIP_TRY(hipGetLastError());
+    }
     dim3 grid(A.nrow_groups, 1);
-    if (A.mixed)
-        hipLaunchKernelGGL((k_rows<float, true>), grid, dim3(256), 0, st, A, zw, 1, y);
-    else
-        hipLaunchKernelGGL((k_rows<double, true>), grid, dim3(256), 0, st, A, zw, 1, y);
+    hipLaunchKernelGGL((k_rows<true>), grid, dim3(256), 0, st, A, zw, 1, y);
     BEM_HIP_TRY(hipGetLastError());
 }
 

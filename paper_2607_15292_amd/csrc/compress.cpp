@@ -18,11 +18,10 @@ struct CompressedOp {
     DevBuf perm_dev;            // [K] cluster position -> mesh element
     DevBuf blocks_dev;          // BlockIn[nb]
     DevBuf faces_dev;           // FaceDesc[nb][L]
-    DevBuf out_dev;             // BlockOut[nb]
     DevBuf pool;                // faces, factors, fibres
     std::vector<BlockIn> blocks;
     std::vector<FaceDesc> faces;
-    std::vector<BlockOut> outs;
+    std::vector<BlockState> st;
     // apply plan
     std::vector<ApplyFace> af;
     DevBuf af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev;
@@ -47,7 +46,7 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
     std::vector<std::vector<int>> faces_of_block(nb);
     long long trow = 0, zw = 0;
     for (int b = 0; b < nb; ++b) {
-        for (int d = 0; d < C.outs[b].rank; ++d) {
+        for (int d = 0; d < C.st[b].rank; ++d) {
             const FaceDesc& f = C.faces[(size_t)b * L + d];
             if (f.kk < 0) continue;
             ApplyFace a;
@@ -55,9 +54,10 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
             a.fib_off = f.fib_off;
             a.kk = f.kk;
             a.sel = f.sel;
-            a.fp32 = f.fp32;
             a.ksel = f.k;
             a.block = b;
+            a.fp32 = f.fp32;
+            a.pad = 0;
             a.t_off = 0;
             if (f.kk > 0) {
                 a.t_off = trow;
@@ -133,6 +133,14 @@ ApplyArgs plan_args(const CompressedOp& C, int nrhs)
     return A;
 }
 
+// Upload a host list into the device list buffer at element offset `at`; returns pointer.
+const int* put_list(DevBuf& buf, size_t at, const std::vector<int>& v, hipStream_t st)
+{
+    int* p = buf.as<int>() + at;
+    if (!v.empty()) BEM_HIP_TRY(hipMemcpyAsync(p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    return p;
+}
+
 }  // namespace
 
 int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
@@ -151,13 +159,18 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     C->perm_dev.alloc(sizeof(int) * K);
     BEM_HIP_TRY(hipMemcpyAsync(C->perm_dev.p, C->part.perm.data(), sizeof(int) * K, hipMemcpyHostToDevice, st));
     const int nb = (int)C->part.blocks.size();
+    if (nb >= (1 << 19)) throw Err(BEM_ERR_ARG, "too many blocks for the compression work lists");
     C->blocks.resize(nb);
     int mmax = 1, nmax = 1, minmax = 1;
     int64_t n_far = 0, n_lowrank = 0;
+    int ntiles = 0;
     for (int b = 0; b < nb; ++b) {
         const BlockDesc& d = C->part.blocks[b];
         int lowrank = d.far && std::min(d.rs, d.cs) > o.far_dense_max;
-        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, lowrank};
+        int nt = (d.rs * d.cs + TILE - 1) / TILE;
+        if (nt >= 4096) throw Err(BEM_ERR_ARG, "block too large for the tile lists (raise leaf or lower eta)");
+        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, lowrank, ntiles, nt};
+        ntiles += nt;
         n_far += d.far;
         if (lowrank) {
             ++n_lowrank;
@@ -166,33 +179,23 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             minmax = std::max(minmax, std::min(d.rs, d.cs));
         }
     }
-    // processing order: most work first (far blocks by perimeter x frequencies, near by area)
-    std::vector<int> order(nb);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(nb);
-    for (int b = 0; b < nb; ++b) {
-        const BlockIn& B = C->blocks[b];
-        cost[b] = B.lowrank ? 400.0 * (B.rs + B.cs) + 2.0 * B.rs * B.cs : 12.0 * B.rs * B.cs;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     const int kmax = 3 * std::max(2, std::min(64, minmax));
-    const int slots = std::max(1, std::min(nb, 1024));
+    const int slots = (int)std::max<int64_t>(1, std::min<int64_t>(n_lowrank, 1024));
     size_t per_slot = n_lowrank ? aca_scratch_doubles(mmax, nmax, kmax) : 64;
     per_slot = (per_slot + 31) & ~(size_t)31;
-    DevBuf scratch, blocks_aux;
+    DevBuf scratch, aux, st_dev, used_dev, fda_dev, tp_dev, list_dev;
     scratch.alloc(per_slot * slots * sizeof(double));
     C->blocks_dev.alloc(sizeof(BlockIn) * nb);
     BEM_HIP_TRY(hipMemcpyAsync(C->blocks_dev.p, C->blocks.data(), sizeof(BlockIn) * nb, hipMemcpyHostToDevice, st));
-    // small device state: order, queue, err, pool_top
-    blocks_aux.alloc(sizeof(int) * nb + 256);
-    int* order_dev = blocks_aux.as<int>();
-    char* aux = blocks_aux.as<char>() + ((sizeof(int) * nb + 63) & ~(size_t)63);
-    int* queue_dev = (int*)aux;
-    int* err_dev = (int*)(aux + 64);
-    unsigned long long* top_dev = (unsigned long long*)(aux + 128);
-    BEM_HIP_TRY(hipMemcpyAsync(order_dev, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+    aux.alloc(256);
+    int* err_dev = aux.as<int>();
+    unsigned long long* top_dev = (unsigned long long*)(aux.as<char>() + 64);
     C->faces_dev.alloc(sizeof(FaceDesc) * (size_t)nb * L);
-    C->out_dev.alloc(sizeof(BlockOut) * nb);
+    st_dev.alloc(sizeof(BlockState) * nb);
+    used_dev.alloc((size_t)nb * L);
+    fda_dev.alloc(sizeof(zd) * 9 * (size_t)nb * L);
+    tp_dev.alloc(sizeof(double) * 8 * (size_t)ntiles);
+    list_dev.alloc(sizeof(int) * (3 * (size_t)ntiles + 2 * (size_t)nb + 64));
     // pool: caller-sized, or auto-sized with up to three attempts (growing on overflow)
     size_t pool_bytes = (size_t)o.pool_bytes;
     const bool auto_pool = pool_bytes == 0;
@@ -204,12 +207,17 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         pool_bytes = (size_t)std::min(0.45 * (double)fr, want);
     }
     BEM_HIP_TRY(hipStreamSynchronize(st));
+    hipEvent_t ev0, ev1;
+    BEM_HIP_TRY(hipEventCreate(&ev0));
+    BEM_HIP_TRY(hipEventCreate(&ev1));
     float kms = 0.f;
     int err = 0;
+    std::vector<BlockState>& S = C->st;
+    S.resize(nb);
     for (int attempt = 0;; ++attempt) {
         C->pool.release();
         C->pool.alloc(pool_bytes);
-        BEM_HIP_TRY(hipMemsetAsync(aux, 0, 192, st));
+        BEM_HIP_TRY(hipMemsetAsync(aux.p, 0, 256, st));
         BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
         CompressArgs A;
         A.c = ctx->devctx(C->geo.geo, C->perm_dev.as<int>());
@@ -218,104 +226,162 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         A.L = L;
         A.nblocks = nb;
         A.kmax = kmax;
+        A.d = 0;
         A.blocks = C->blocks_dev.as<BlockIn>();
-        A.order = order_dev;
         A.faces = C->faces_dev.as<FaceDesc>();
-        A.out = C->out_dev.as<BlockOut>();
+        A.st = st_dev.as<BlockState>();
+        A.used = used_dev.as<unsigned char>();
+        A.Fda = fda_dev.as<zd>();
+        A.tp = tp_dev.as<double>();
+        A.list = nullptr;
+        A.nlist = 0;
         A.pool = C->pool.as<char>();
         A.pool_cap = pool_bytes;
         A.pool_top = top_dev;
-        A.queue = queue_dev;
         A.err = err_dev;
         A.scratch = scratch.as<double>();
         A.scratch_per_slot = per_slot;
         A.eps3d = o.eps3d;
         A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
         A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
-#ifdef BEM_PHASE_PROF
-        DevBuf profbuf;
-        profbuf.alloc(16 * sizeof(long long));
-        BEM_HIP_TRY(hipMemsetAsync(profbuf.p, 0, 16 * sizeof(long long), st));
-        A.prof = profbuf.as<long long>();
-#else
-        A.prof = nullptr;
-#endif
-        hipEvent_t ev0, ev1;
-        BEM_HIP_TRY(hipEventCreate(&ev0));
-        BEM_HIP_TRY(hipEventCreate(&ev1));
         BEM_HIP_TRY(hipEventRecord(ev0, st));
-        launch_aca3d(A, slots, st);
+        launch_init(A, st);
+        std::vector<int> dense_tiles, lr_blocks, lr_tiles, act;
+        for (int d = 0; d < L; ++d) {
+            BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
+            BEM_HIP_TRY(hipStreamSynchronize(st));
+            dense_tiles.clear();
+            lr_blocks.clear();
+            lr_tiles.clear();
+            act.clear();
+            for (int b = 0; b < nb; ++b) {
+                if (!S[b].active) continue;
+                const BlockIn& B = C->blocks[b];
+                act.push_back(b);
+                std::vector<int>& tl = B.lowrank ? lr_tiles : dense_tiles;
+                for (int t = 0; t < B.ntile; ++t) tl.push_back((b << 12) | t);
+                if (B.lowrank) lr_blocks.push_back(b);
+            }
+            if (act.empty()) break;
+            size_t at = 0;
+            const int* p_dense = put_list(list_dev, at, dense_tiles, st);
+            at += dense_tiles.size();
+            const int* p_lrb = put_list(list_dev, at, lr_blocks, st);
+            at += lr_blocks.size();
+            const int* p_lrt = put_list(list_dev, at, lr_tiles, st);
+            at += lr_tiles.size();
+            const int* p_act = put_list(list_dev, at, act, st);
+            A.d = d;
+            A.list = p_dense;
+            A.nlist = (int)dense_tiles.size();
+            launch_face_dense(A, st);
+            for (size_t c0 = 0; c0 < lr_blocks.size(); c0 += (size_t)slots) {
+                A.list = p_lrb + c0;
+                A.nlist = (int)std::min<size_t>((size_t)slots, lr_blocks.size() - c0);
+                launch_aca(A, st);
+            }
+            A.list = p_lrt;
+            A.nlist = (int)lr_tiles.size();
+            launch_scan_lr(A, st);
+            A.list = p_act;
+            A.nlist = (int)act.size();
+            launch_pivot(A, st);
+            launch_fibre(A, st);
+            A.list = p_dense;
+            A.nlist = (int)dense_tiles.size();
+            launch_cross_dense(A, st);
+            A.list = p_lrb;
+            A.nlist = (int)lr_blocks.size();
+            launch_cross_lr(A, st);
+            A.list = p_act;
+            A.nlist = (int)act.size();
+            launch_final(A, st);
+        }
+        // dense fallback of the blocks without a regular pivot
+        BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
+        BEM_HIP_TRY(hipStreamSynchronize(st));
+        std::vector<int> fb_blocks, fb_tiles;
+        for (int b = 0; b < nb; ++b)
+            if (S[b].fallback) {
+                fb_blocks.push_back(b);
+                for (int t = 0; t < C->blocks[b].ntile; ++t) fb_tiles.push_back((b << 12) | t);
+            }
+        if (!fb_blocks.empty()) {
+            const int* p_fb = put_list(list_dev, 0, fb_blocks, st);
+            const int* p_ft = put_list(list_dev, fb_blocks.size(), fb_tiles, st);
+            for (int kf = 0; kf < L; ++kf) {
+                A.list = p_fb;
+                A.nlist = (int)fb_blocks.size();
+                launch_fallback(A, kf, st);
+                A.list = p_ft;
+                A.nlist = (int)fb_tiles.size();
+                launch_fallback_faces(A, kf, st);
+            }
+        }
         BEM_HIP_TRY(hipEventRecord(ev1, st));
         BEM_HIP_TRY(hipStreamSynchronize(st));
         BEM_HIP_TRY(hipEventElapsedTime(&kms, ev0, ev1));
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
-#ifdef BEM_PHASE_PROF
-        {
-            long long pr[16];
-            BEM_HIP_TRY(hipMemcpy(pr, profbuf.p, sizeof(pr), hipMemcpyDeviceToHost));
-            const char* names[8] = {"near_face", "far_aca", "far_recompress", "far_scan", "fibre_norm_near",
-                                    "fibre_norm_far", "block_near", "block_far"};
-            for (int q = 0; q < 8; ++q) fprintf(stderr, "phase %-16s %.3e cycles\n", names[q], (double)pr[q]);
-        }
-#endif
         unsigned long long top = 0;
         BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
         BEM_HIP_TRY(hipMemcpy(&top, top_dev, sizeof(top), hipMemcpyDeviceToHost));
         if (!(err & 2)) break;
-        if (!auto_pool || attempt >= 2)
+        if (!auto_pool || attempt >= 2) {
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
             throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes overflowed (" +
                                          std::to_string(top) + " requested); raise pool_bytes");
+        }
         C->pool.release();
         size_t fr = 0, tot = 0;
         BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
         pool_bytes = (size_t)std::min(0.85 * (double)fr, 2.5 * (double)top + (double)(1 << 28));
     }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    BEM_HIP_TRY(hipMemcpy(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost));
     C->faces.resize((size_t)nb * L);
-    C->outs.resize(nb);
     BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L, hipMemcpyDeviceToHost));
-    BEM_HIP_TRY(hipMemcpy(C->outs.data(), C->out_dev.p, sizeof(BlockOut) * nb, hipMemcpyDeviceToHost));
     build_apply_plan(*C, st);
 
     // statistics
-    bem_stats& S = out->stats;
-    std::memset(&S, 0, sizeof(S));
-    S.n_blocks = nb;
-    S.n_far = n_far;
-    S.n_near = nb - n_far;
-    S.rank_min = L + 1;
+    bem_stats& R = out->stats;
+    std::memset(&R, 0, sizeof(R));
+    R.n_blocks = nb;
+    R.n_far = n_far;
+    R.n_near = nb - n_far;
+    R.rank_min = L + 1;
     double rsum = 0, acasum = 0;
     int64_t nfarfaces = 0, bytes = 0, ent = 0;
-    size_t zsz = C->mixed ? sizeof(zf) : sizeof(zd);
     for (int b = 0; b < nb; ++b) {
-        const BlockOut& bo = C->outs[b];
+        const BlockState& s = S[b];
         const BlockIn& B = C->blocks[b];
-        S.n_dense_fallback += bo.fallback;
-        S.rank_min = std::min(S.rank_min, bo.rank);
-        S.rank_max = std::max(S.rank_max, bo.rank);
-        rsum += bo.rank;
-        ent += bo.entries;
-        S.aca_rank_max = std::max(S.aca_rank_max, bo.aca_cols);
-        for (int d = 0; d < bo.rank; ++d) {
+        R.n_dense_fallback += s.fallback;
+        R.rank_min = std::min(R.rank_min, s.rank);
+        R.rank_max = std::max(R.rank_max, s.rank);
+        rsum += s.rank;
+        ent += s.entries;
+        for (int d = 0; d < s.rank; ++d) {
             const FaceDesc& f = C->faces[(size_t)b * L + d];
             bytes += (int64_t)L * 9 * sizeof(zd);
+            size_t zs = f.fp32 ? sizeof(zf) : sizeof(zd);
             if (f.kk == 0) {
-                bytes += (int64_t)9 * B.rs * B.cs * (int64_t)((B.far && C->mixed) ? sizeof(zf) : sizeof(zd));
+                bytes += (int64_t)9 * B.rs * B.cs * (int64_t)zs;
             } else if (f.kk > 0) {
-                bytes += (int64_t)3 * (B.rs + B.cs) * f.kk * (int64_t)(B.far ? zsz : sizeof(zd));
+                bytes += (int64_t)3 * (B.rs + B.cs) * f.kk * (int64_t)zs;
                 acasum += f.kk;
                 ++nfarfaces;
+                R.aca_rank_max = std::max(R.aca_rank_max, f.kk);
             }
         }
     }
-    S.rank_mean = nb ? rsum / nb : 0.0;
-    S.aca_rank_mean = nfarfaces ? acasum / nfarfaces : 0.0;
-    S.bytes = bytes;
-    S.compression_rate = (double)bytes / ((double)L * 9.0 * (double)K * (double)K * 16.0);
-    S.entries_generated = ent;
-    S.n_far_faces = nfarfaces;
-    S.kernel_ms = kms;
-    S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    R.rank_mean = nb ? rsum / nb : 0.0;
+    R.aca_rank_mean = nfarfaces ? acasum / nfarfaces : 0.0;
+    R.bytes = bytes;
+    R.compression_rate = (double)bytes / ((double)L * 9.0 * (double)K * (double)K * 16.0);
+    R.entries_generated = ent;
+    R.n_far_faces = nfarfaces;
+    R.kernel_ms = kms;
+    R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BEM_OK;
 }
 
@@ -365,8 +431,8 @@ void compressed_blocks(const bem_op* op, int64_t* n, int64_t* rows, int32_t* per
         for (size_t b = 0; b < C.blocks.size(); ++b) {
             const BlockIn& B = C.blocks[b];
             int64_t cols = 0;
-            for (int d = 0; d < C.outs[b].rank; ++d) cols += std::max(0, C.faces[b * C.L + d].kk);
-            int64_t r[8] = {B.rb, B.rs, B.cb, B.cs, B.far, C.outs[b].rank, C.outs[b].fallback, cols};
+            for (int d = 0; d < C.st[b].rank; ++d) cols += std::max(0, C.faces[b * C.L + d].kk);
+            int64_t r[8] = {B.rb, B.rs, B.cb, B.cs, B.far, C.st[b].rank, C.st[b].fallback, cols};
             std::memcpy(rows + 8 * b, r, sizeof(r));
         }
     if (perm)
@@ -378,8 +444,8 @@ void compressed_freq_hist(const bem_op* op, int64_t* hist)
     const CompressedOp& C = *op->comp;
     for (int l = 0; l < C.L; ++l) hist[l] = 0;
     for (size_t b = 0; b < C.blocks.size(); ++b) {
-        if (C.outs[b].fallback) continue;
-        for (int d = 0; d < C.outs[b].rank; ++d) hist[C.faces[b * C.L + d].k]++;
+        if (C.st[b].fallback) continue;
+        for (int d = 0; d < C.st[b].rank; ++d) hist[C.faces[b * C.L + d].k]++;
     }
 }
 
