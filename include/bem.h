@@ -112,15 +112,21 @@ typedef struct {
     int64_t n_blocks, n_near, n_far, n_dense_fallback;
     int32_t rank_min, rank_max;   /* 3D-ACA ranks r_b over blocks (Fig. 5 reports these) */
     double rank_mean;
-    int32_t aca_rank_max;         /* largest per-slice ACA rank of a far face (columns) */
-    double aca_rank_mean;
+    int32_t aca_rank_max;         /* largest rank kk of a far face stored as factors */
+    double aca_rank_mean;         /* mean kk over the far faces stored as factors */
     int64_t bytes;                /* device bytes of faces, factors and fibres */
     double compression_rate;      /* bytes / (L * (3K)^2 * 16) */
     int64_t entries_generated;    /* ENTRY(i, j, l) 3x3 blocks evaluated during compression */
     int64_t n_far_faces;          /* far faces stored as factors */
     double seconds;               /* wall time of the compression call */
-    double kernel_ms;             /* duration of the compression kernel (HIP events on the
-                                     context stream around its launch) */
+    double kernel_ms;             /* device time of the compression (HIP events on the context
+                                     stream from the first to the last launch) */
+    int64_t n_aca_dense;          /* far faces of ACA blocks kept dense: the per-slice ACA did
+                                     not resolve them within its column cap, or the factors
+                                     would not take less memory than the face */
+    double aca_cols_mean;         /* ACA columns before recompression, mean over the faces
+                                     stored as factors */
+    double aca_ms;                /* device time of the per-slice ACA + recompression pass */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -181,10 +187,30 @@ int bem_op_dense_copy(const bem_op *op, void *dst, int32_t flags);
 
 /* Compression (Sec. 3, Algorithm 1 with matrix-valued pivots, eq. (SVD); Sec. 3.1):
  * PCA cluster tree with leaf size opts->leaf, admissibility eq. (adm) with opts->eta,
- * 3D-ACA on every block, per-slice ACA + recompression (eq. (ACA)) on far-field faces,
- * dense faces on near-field blocks, dense fallback when no regular pivot exists.
+ * 3D-ACA on every block over exact dense residual faces, then per-slice ACA +
+ * recompression (eq. (ACA)) of every face of the admissible blocks whose smaller side
+ * exceeds opts->far_dense_max, to the absolute tolerance eps_aca ||C^(r)||_F / ||f_d||_F
+ * (each face-fibre term errs by at most about eps_aca ||C^(r)||_F); a face stays dense when
+ * its ACA does not resolve it within the column cap or its factors would not save memory.
+ * Dense fallback when no regular pivot exists.
  * opts may be NULL (eps3d = 1e-6, eps_aca = eps3d / 100, eta = 1.5, leaf = 64, F64). */
 int bem_compress(bem_ctx *ctx, int32_t op, const bem_aca_opts *opts, bem_op **out);
+
+/* The per-slice ACA + recompression (Sec. 3.1, eq. (ACA)) that bem_compress applies to a
+ * far face, run on one given matrix (for tests).  A: [3m][3n] row-major host matrix of m x n
+ * 3x3 blocks, complex128 (prec BEM_PREC_F64) or complex64 (BEM_PREC_MIXED); copied.
+ * tol: absolute tolerance of the ACA stop test (||U_k||_F ||V_k||_F <= tol for the newest
+ * 3 columns) and of the truncation (dropped singular values: sqrt(sum s^2) <= tol).
+ * max_cols: ACA column cap (multiple of 3 after rounding down; <= 0 selects the library's
+ * cap 3 ceil(2 m n / (m + n))); at most 3 min(m, n) and 192.
+ * Out: *kc = ACA columns, -1 when the ACA did not resolve the matrix (it would stay dense);
+ * *kk = rank of the factors, 0 when they would not take less memory than the matrix.
+ * U ([3m][kk]) and V ([3n][kk]), row-major host buffers of the precision of A holding at
+ * least 9 m min(m, n) and 9 n min(m, n) entries, receive Ubar and Vbar with
+ * A ~= Ubar Vbar^H when kk > 0 (either may be NULL).
+ * Errors: BEM_ERR_ARG for m, n < 1, m * n > 2^22, bad prec, tol < 0 or A NULL. */
+int bem_aca_matrix(bem_ctx *ctx, int32_t prec, int32_t m, int32_t n, const void *A, double tol, int32_t max_cols,
+                   int32_t *kc, int32_t *kk, void *U, void *V);
 
 /* Statistics of a compressed or dense operator. */
 int bem_op_stats(const bem_op *op, bem_stats *st);

@@ -21,6 +21,21 @@ Readings of the paper taken here (the same readings bind the GPU library):
     face itself is below eps ||C^(d-1)||_F, which means the tensor is already reproduced
     (then r = d - 1).
   * Ties of an argmax go to the smallest index (row-major (i, j); smallest k).
+  * Per-slice ACA (Sec. 3.1) is a pass over the faces of the finished 3D-ACA: the 3D-ACA
+    runs on exact residual faces, then each face H_d of an admissible block is compressed
+    by the matrix-valued ACA + QR/SVD recompression with the absolute tolerance
+        tol_d = eps_aca ||C^(r)||_F / ||f_d||_F,
+    i.e. each face-fibre term errs by at most about eps_aca ||C^(r)||_F (the paper sets
+    eps = 100 eps_aca, room for the errors of many terms).  ||C^(r)||_F is the recursive
+    norm of the last step (it includes a dropped sub-tolerance pair).
+  * The ACA stops when ||U_k||_F ||V_k||_F <= tol for the newest 3 columns, or when a
+    residual row without a regular block is itself below tol.  It fails (the face stays
+    dense) when it reaches its column cap short of 3 min(m, n) columns, after MAX_FAIL rows in a row without a regular
+    pivot, or when every row was visited and a skipped row remains.  The cap is
+    3 ceil(2 m n / (m + n)) columns (ACA columns at twice the memory of the dense face:
+    rank-3 steps overshoot the recompressed rank about twofold), at most 3 min(m, n) and
+    KMAX_ACA; recompressed factors that do not take less memory than the dense face are
+    dropped as well (kk (m + n) >= 3 m n).
 """
 from __future__ import annotations
 
@@ -28,6 +43,7 @@ import numpy as np
 
 PIVOT_RTOL = 1e-14
 MAX_FAIL = 8
+KMAX_ACA = 192
 
 
 def sigma3(B):
@@ -42,12 +58,14 @@ def _fro2(A):
 class Approx3D:
     """Result of 3D-ACA on one block: faces H[d] (m, n, 3, 3) and fibres f[d] (L, 3, 3)."""
 
-    def __init__(self, faces, fibres, pivots, ks, dense):
+    def __init__(self, faces, fibres, pivots, ks, dense, norm2=0.0):
         self.faces = faces
         self.fibres = fibres
         self.pivots = pivots
         self.ks = ks
         self.dense = dense
+        self.norm2 = norm2          # recursive ||C^(r)||_F^2 of the last step
+        self.factors = [None] * len(faces)  # per face: (Ubar, Vbar) after the ACA pass, or None
 
     @property
     def rank(self):
@@ -59,18 +77,15 @@ class Approx3D:
         m, n = self.faces[0].shape[:2]
         L = self.fibres[0].shape[0]
         C = np.zeros((L, m, n, 3, 3), dtype=np.complex128)
-        for H, f in zip(self.faces, self.fibres):
+        for H, f, uv in zip(self.faces, self.fibres, self.factors):
+            if uv is not None:
+                H = matrix_to_blocks(uv[0] @ uv[1].conj().T)
             C += np.einsum("ijab,kbc->kijac", H, f)
         return C
 
 
-def aca3d(C, eps, face_approx=None):
-    """Algorithm 1 on a dense block tensor C[L, m, n, 3, 3].
-
-    face_approx(Hres) -> Hd optionally replaces the exact residual face by an approximation
-    (the per-slice ACA of far-field blocks); the pivot is then searched on the reconstructed
-    approximation, as Sec. 3.1 describes.
-    """
+def aca3d(C, eps):
+    """Algorithm 1 on a dense block tensor C[L, m, n, 3, 3] (exact residual faces)."""
     L, m, n = C.shape[:3]
     faces, fibres, pivots, ks = [], [], [], []
     G = {}  # G[(a, b)] = sum_ij H_a^H H_b
@@ -86,7 +101,7 @@ def aca3d(C, eps, face_approx=None):
         R = C[k].copy()
         for Ha, fa in zip(faces, fibres):
             R -= np.einsum("ijab,bc->ijac", Ha, fa[k])
-        Hd = R if face_approx is None else face_approx(R)
+        Hd = R
         s3 = sigma3(Hd)
         flat = int(np.argmax(s3))
         i_d, j_d = divmod(flat, n)
@@ -95,7 +110,7 @@ def aca3d(C, eps, face_approx=None):
                 return Approx3D([], [], [], [], dense=False)
             if d > 1 and np.sqrt(_fro2(Hd)) <= eps * np.sqrt(max(norm2, 0.0)):
                 # the residual face vanishes: the tensor is reproduced, stop with r = d - 1
-                return Approx3D(faces, fibres, pivots, ks, dense=False)
+                return Approx3D(faces, fibres, pivots, ks, dense=False, norm2=norm2)
             return dense_fallback(C)
         P = Hd[i_d, j_d]
         # fibre at (i_d, j_d) over all frequencies, residual, times the pivot inverse
@@ -119,9 +134,9 @@ def aca3d(C, eps, face_approx=None):
         fn = np.sqrt(max(np.real(np.trace(F[(b, b)])), 0.0))
         if not (hn * fn > eps * np.sqrt(max(norm2, 0.0))):
             faces.pop(), fibres.pop(), pivots.pop(), ks.pop()
-            return Approx3D(faces, fibres, pivots, ks, dense=False)
+            return Approx3D(faces, fibres, pivots, ks, dense=False, norm2=norm2)
         if used.all():
-            return Approx3D(faces, fibres, pivots, ks, dense=False)
+            return Approx3D(faces, fibres, pivots, ks, dense=False, norm2=norm2)
         s3f = sigma3(fd)
         s3f[used] = -1.0
         k = int(np.argmax(s3f))
@@ -156,39 +171,51 @@ def matrix_to_blocks(A):
     return A.reshape(m3 // 3, 3, n3 // 3, 3).transpose(0, 2, 1, 3)
 
 
-def aca_matrix(A, eps, max_steps=None):
+def face_aca_cap(m, n):
+    """Column cap of the per-slice ACA of an m x n (elements) face."""
+    s = -(-2 * m * n // (m + n))
+    return 3 * min(s, m, n)
+
+
+def aca_matrix(A, tol, max_cols=None):
     """Matrix-valued partial-pivot ACA of A (3m x 3n) with rank-3 steps and sigma_3 pivots.
 
-    Rows and columns of the residual are read from A minus the current approximation.
-    Returns U (3m x 3r), V (3n x 3r) with A ~= U V^H.  Stops when
-    ||U_k||_F ||V_k||_F <= eps ||S_k||_F (the update norm against the approximation norm).
-    A residual row without a regular 3x3 block is skipped (next unused row); the iteration
-    also stops when such a row is itself below eps ||S_k||_F or after MAX_FAIL skips in a row.
+    Rows and columns of the residual are read from A minus the current approximation
+    U V^H; the pivot block of a row is its block of largest sigma_3, and the next row is
+    the unused row whose new U block has the largest sigma_3.  Returns (U, V, ok) with
+    A ~= U V^H; see the module docstring for the stopping and failure rules.
     """
     m, n = A.shape[0] // 3, A.shape[1] // 3
-    if max_steps is None:
-        max_steps = min(m, n)
+    if max_cols is None:
+        max_cols = 3 * min(m, n)
     Us, Vs = [], []
     used_rows = np.zeros(m, dtype=bool)
-    i = 0
-    norm2 = 0.0
     scale = np.abs(A).max() if A.size else 0.0
-    steps = 0
-    fails = 0
-    while steps < max_steps:
+    i, kc, fails, skipped = 0, 0, 0, 0
+
+    def result(ok):
+        if not Us:
+            return np.zeros((3 * m, 0), dtype=A.dtype), np.zeros((3 * n, 0), dtype=A.dtype), ok
+        return np.concatenate(Us, axis=1), np.concatenate(Vs, axis=1), ok
+
+    while True:
+        if kc + 3 > max_cols:
+            # all min(m, n) block rows or columns interpolated: the residual is zero
+            return result(kc >= 3 * min(m, n))
         row = A[3 * i:3 * i + 3].copy()
         for Uk, Vk in zip(Us, Vs):
             row -= Uk[3 * i:3 * i + 3] @ Vk.conj().T
         used_rows[i] = True
         s3 = sigma3(row.reshape(3, n, 3).transpose(1, 0, 2))
         j = int(np.argmax(s3))
-        if not (s3[j] > PIVOT_RTOL * max(scale, 1e-300)):
-            if np.linalg.norm(row) <= eps * np.sqrt(max(norm2, 0.0)):
-                break
+        if not (s3[j] > PIVOT_RTOL * scale):
+            if np.linalg.norm(row) <= tol:
+                return result(True)
+            skipped += 1
             fails += 1
             free = np.flatnonzero(~used_rows)
-            if free.size == 0 or fails >= MAX_FAIL:
-                break
+            if fails >= MAX_FAIL or free.size == 0:
+                return result(False)
             i = int(free[0])
             continue
         fails = 0
@@ -198,26 +225,21 @@ def aca_matrix(A, eps, max_steps=None):
             col -= Uk @ Vk[3 * j:3 * j + 3].conj().T
         Un = col @ np.linalg.inv(P)
         Vn = row.conj().T
-        cross = sum(np.trace((Uk.conj().T @ Un) @ (Vn.conj().T @ Vk)) for Uk, Vk in zip(Us, Vs))
-        norm2 += 2.0 * np.real(cross) + np.real(np.trace((Un.conj().T @ Un) @ (Vn.conj().T @ Vn)))
         Us.append(Un)
         Vs.append(Vn)
-        steps += 1
-        if np.linalg.norm(Un) * np.linalg.norm(Vn) <= eps * np.sqrt(max(norm2, 0.0)):
-            break
-        if used_rows.all():
-            break
+        kc += 3
+        if np.linalg.norm(Un) * np.linalg.norm(Vn) <= tol:
+            return result(True)
         s3u = sigma3(Un.reshape(m, 3, 3))
         s3u[used_rows] = -1.0
+        if used_rows.all():
+            return result(skipped == 0)
         i = int(np.argmax(s3u))
-    if not Us:
-        return np.zeros((3 * m, 0), dtype=A.dtype), np.zeros((3 * n, 0), dtype=A.dtype)
-    return np.concatenate(Us, axis=1), np.concatenate(Vs, axis=1)
 
 
-def recompress(U, V, eps):
-    """eq. (ACA): U V^H = Q_U (R_U R_V^H) Q_V^H = Q_U (Uc S Vc^H) Q_V^H, truncated so that
-    the dropped singular values satisfy sqrt(sum_{i>k} s_i^2) <= eps ||s||.
+def recompress(U, V, tol):
+    """eq. (ACA): U V^H = Q_U (R_U R_V^H) Q_V^H = Q_U (Uc S Vc^H) Q_V^H, truncated to the
+    smallest k with sqrt(sum_{i>=k} s_i^2) <= tol (at least 1 when U V^H != 0).
     Returns Ubar (3m x k, scaled by the singular values) and Vbar (3n x k)."""
     if U.shape[1] == 0:
         return U, V
@@ -226,17 +248,36 @@ def recompress(U, V, eps):
     Uc, S, Vch = np.linalg.svd(RU @ RV.conj().T)
     tot = np.sqrt(np.sum(S**2))
     k = len(S)
-    while k > 0 and np.sqrt(np.sum(S[k - 1:] ** 2)) <= eps * tot:
+    while k > 0 and np.sqrt(np.sum(S[k - 1:] ** 2)) <= tol:
         k -= 1
     k = max(k, 1) if tot > 0 else 0
     return (QU @ Uc[:, :k]) * S[:k], QV @ Vch[:k].conj().T
 
 
-def aca_face(eps_aca):
-    """face_approx for aca3d: per-slice ACA + recompression, reconstructed densely."""
-    def f(Hres):
-        A = blocks_to_matrix(Hres)
-        U, V = aca_matrix(A, eps_aca)
-        Ub, Vb = recompress(U, V, eps_aca)
-        return matrix_to_blocks(Ub @ Vb.conj().T)
-    return f
+def compress_face(H, tol, max_cols=KMAX_ACA):
+    """Per-slice ACA + recompression of one face H (m, n, 3, 3) with absolute tolerance tol.
+    Returns (Ubar, Vbar, kc): the factors, or None when the face stays dense, and the ACA
+    column count (-1 when the ACA failed)."""
+    m, n = H.shape[:2]
+    A = blocks_to_matrix(H)
+    if not np.any(A):
+        return None, -1
+    U, V, ok = aca_matrix(A, tol, min(max_cols, face_aca_cap(m, n)))
+    if not ok:
+        return None, -1
+    Ub, Vb = recompress(U, V, tol)
+    if Ub.shape[1] * (m + n) >= 3 * m * n:
+        return None, U.shape[1]
+    return (Ub, Vb), U.shape[1]
+
+
+def compress_faces(ap, eps_aca, max_cols=KMAX_ACA):
+    """The per-slice ACA pass over the faces of a 3D-ACA result (in place); returns ap."""
+    if ap.dense:
+        return ap
+    cn = np.sqrt(max(ap.norm2, 0.0))
+    for d, (H, f) in enumerate(zip(ap.faces, ap.fibres)):
+        fn = np.sqrt(_fro2(f))
+        tol = eps_aca * cn / fn if fn > 0 else 0.0
+        ap.factors[d] = compress_face(H, tol, max_cols)[0]
+    return ap

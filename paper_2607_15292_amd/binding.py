@@ -47,7 +47,8 @@ class bem_stats(ctypes.Structure):
                 ("rank_mean", ctypes.c_double), ("aca_rank_max", ctypes.c_int32), ("aca_rank_mean", ctypes.c_double),
                 ("bytes", ctypes.c_int64), ("compression_rate", ctypes.c_double),
                 ("entries_generated", ctypes.c_int64), ("n_far_faces", ctypes.c_int64),
-                ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("n_aca_dense", ctypes.c_int64), ("aca_cols_mean", ctypes.c_double), ("aca_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -70,6 +71,9 @@ _SIGS = {
     "bem_assemble_dense": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bem_op_dense_copy": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "bem_compress": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(bem_aca_opts), ctypes.POINTER(ctypes.c_void_p)]),
+    "bem_aca_matrix": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_double,
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      _P, _P]),
     "bem_op_stats": (ctypes.c_int, [_P, ctypes.POINTER(bem_stats)]),
     "bem_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "bem_apply_weighted": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
@@ -216,6 +220,23 @@ class Context:
         h = ctypes.c_void_p()
         self._check(lib().bem_compress(self.h, int(op), ctypes.byref(o), ctypes.byref(h)))
         return Operator(self, h)
+
+    def aca_matrix(self, A, tol, max_cols=0, prec=PREC_F64):
+        """Per-slice ACA + recompression of one [3m][3n] host matrix; returns
+        (kc, kk, Ubar, Vbar) with Ubar/Vbar None unless kk > 0."""
+        dt = np.complex64 if prec == PREC_MIXED else np.complex128
+        A = np.ascontiguousarray(A, dtype=dt)
+        m, n = A.shape[0] // 3, A.shape[1] // 3
+        cap = 3 * min(m, n)
+        U = np.zeros(3 * m * cap, dtype=dt)
+        V = np.zeros(3 * n * cap, dtype=dt)
+        kc, kk = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().bem_aca_matrix(self.h, int(prec), m, n, A.ctypes.data, float(tol), int(max_cols),
+                                         ctypes.byref(kc), ctypes.byref(kk), U.ctypes.data, V.ctypes.data))
+        k = kk.value
+        if k <= 0:
+            return kc.value, k, None, None
+        return kc.value, k, U[:3 * m * k].reshape(3 * m, k), V[:3 * n * k].reshape(3 * n, k)
 
     def partition(self, eta=1.5, leaf=64):
         n = ctypes.c_int64()

@@ -124,51 +124,25 @@ __device__ __forceinline__ blk ld_blk9(const zd* p)
     return b;
 }
 
-template <typename T>
-__device__ __forceinline__ blk lowrank_block(const char* pool, const FaceDesc& f, int m, int i, int j)
+// block (i, j) of a stored dense face (row-major 3m x 3n, complex64 or complex128)
+__device__ __forceinline__ blk face_block(const char* pool, const FaceDesc& f, int n, int i, int j)
 {
-    const int kk = f.kk;
-    const cx<T>* U = (const cx<T>*)(pool + f.face_off) + (size_t)(3 * i) * kk;
-    const cx<T>* V = (const cx<T>*)(pool + f.face_off) + (size_t)3 * m * kk + (size_t)(3 * j) * kk;
-    blk b = blk_zero();
-    for (int t = 0; t < kk; ++t) {
-        zd u[3], v[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            u[a] = ldz(U + (size_t)a * kk + t);
-            v[a] = ldz(V + (size_t)a * kk + t);
-        }
+    blk b;
+    const size_t ld = 3 * (size_t)n;
+    if (f.fp32) {
+        const zf* H = (const zf*)(pool + f.face_off);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) b.a[3 * a + c] += mul_conj(u[a], v[c]);
+            for (int c = 0; c < 3; ++c) b.a[3 * a + c] = ldz(H + (size_t)(3 * i + a) * ld + 3 * j + c);
+    } else {
+        const zd* H = (const zd*)(pool + f.face_off);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) b.a[3 * a + c] = H[(size_t)(3 * i + a) * ld + 3 * j + c];
     }
     return b;
-}
-
-// block (i, j) of a stored face
-__device__ __forceinline__ blk face_block(const char* pool, const FaceDesc& f, int m, int n, int i, int j)
-{
-    blk b;
-    if (f.kk == 0) {
-        size_t ld = 3 * (size_t)n;
-        if (f.fp32) {
-            const zf* H = (const zf*)(pool + f.face_off);
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) b.a[3 * a + c] = ldz(H + (size_t)(3 * i + a) * ld + 3 * j + c);
-        } else {
-            const zd* H = (const zd*)(pool + f.face_off);
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) b.a[3 * a + c] = H[(size_t)(3 * i + a) * ld + 3 * j + c];
-        }
-        return b;
-    }
-    if (f.kk < 0) return blk_zero();
-    return f.fp32 ? lowrank_block<float>(pool, f, m, i, j) : lowrank_block<double>(pool, f, m, i, j);
 }
 
 __device__ __forceinline__ blk fibre_at(const char* pool, const FaceDesc& f, int k)
@@ -177,13 +151,13 @@ __device__ __forceinline__ blk fibre_at(const char* pool, const FaceDesc& f, int
 }
 
 // E -= sum_{a<d} H_a[i,j] f_a[k]   (the 3D approximation C^(d-1) at (i, j, k))
-__device__ __forceinline__ void sub_residual(blk& E, const CompressArgs& A, const FaceDesc* fd, int d, int m, int n,
-                                             int i, int j, int k)
+__device__ __forceinline__ void sub_residual(blk& E, const CompressArgs& A, const FaceDesc* fd, int d, int n, int i,
+                                             int j, int k)
 {
     for (int a = 0; a < d; ++a) {
         const FaceDesc f = fd[a];
-        if (f.sel && f.k != k) continue;
-        blk H = face_block(A.pool, f, m, n, i, j);
+        if (f.kk < 0 || (f.sel && f.k != k)) continue;
+        blk H = face_block(A.pool, f, n, i, j);
         blk fk = fibre_at(A.pool, f, k);
         blk_mul_sub(E, H, fk);
     }
@@ -206,30 +180,20 @@ __device__ __forceinline__ long long dense_face_bytes(const CompressArgs& A, con
     return ((long long)zs * 9 * B.rs * B.cs + 15) & ~15LL;
 }
 
-// Reserve the storage of step d of block b: dense face + fibre, or the fibre of a low-rank
-// face (its factors are reserved when their rank is known).  False on pool overflow.
+// Reserve the storage of step d of block b (dense face + fibre); false on pool overflow.
 __device__ bool alloc_step(const CompressArgs& A, int b, int d, int k)
 {
     const BlockIn B = A.blocks[b];
+    const long long fb = dense_face_bytes(A, B);
+    const long long off = pool_alloc(A, fb + (long long)sizeof(zd) * 9 * A.L);
+    if (off < 0) return false;
     FaceDesc f;
+    f.face_off = off;
+    f.fib_off = off + fb;
+    f.kk = 0;
     f.k = k;
     f.sel = 0;
-    if (!B.lowrank) {
-        long long fb = dense_face_bytes(A, B);
-        long long off = pool_alloc(A, fb + (long long)sizeof(zd) * 9 * A.L);
-        if (off < 0) return false;
-        f.face_off = off;
-        f.fib_off = off + fb;
-        f.kk = 0;
-        f.fp32 = (A.mixed && B.far) ? 1 : 0;
-    } else {
-        long long off = pool_alloc(A, (long long)sizeof(zd) * 9 * A.L);
-        if (off < 0) return false;
-        f.face_off = 0;
-        f.fib_off = off;
-        f.kk = -1;
-        f.fp32 = A.mixed ? 1 : 0;
-    }
+    f.fp32 = (A.mixed && B.far) ? 1 : 0;
     A.faces[(size_t)b * A.L + d] = f;
     return true;
 }
@@ -248,9 +212,9 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
     s.stop = 0;
     s.piv = 0;
     s.nextk = -1;
-    s.kc = 0;
-    s.aca_max = 0;
+    s.aca_dense = 0;
     s.pad = 0;
+    s.aca_cols = 0;
     s.norm2 = 0.0;
     s.hn2 = s.fmax2 = s.s3max = s.fn2 = 0.0;
     s.entries = 0;
@@ -262,10 +226,64 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
 
 // ---------------------------------------------------------------- dense faces
 
+// Entry of a pair for the face kernels.  PATH 0: any pair class, FP64; PATH 1 / 2: block
+// whose pairs are all regular (checked on the host), FP32 / FP64 regular rule; PATH 3: any
+// pair class with the FP32 regular rule (admissible blocks of the mixed path that contain
+// near pairs).  KOP: 0 = V, 1 = K or I/2 + K, 2 = entry table.
+template <int KOP, int PATH>
+__device__ __forceinline__ blk pair_entry(const CompressArgs& A, int gi, int gj, int k)
+{
+    if constexpr (KOP == 2) {
+        return entry_dispatch<false>(A.c, OP_TABLE, gi, gj, k);
+    } else if constexpr (PATH == 0) {
+        return entry_dispatch<false>(A.c, A.op, gi, gj, k);
+    } else if constexpr (PATH == 3) {
+        return entry_dispatch<true>(A.c, A.op, gi, gj, k);
+    } else {
+        blk out;
+        if constexpr (PATH == 1)
+            entry_regular<float>(A.c.geo, KOP, gi, gj, A.c.fr.sf[k], A.c.fr.sinvf[k], A.c.mf, out);
+        else
+            entry_regular<double>(A.c.geo, KOP, gi, gj, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, out);
+        return out;
+    }
+}
+
+// E -= sum_{a<d} H_a[i,j] f_a[k] over the dense faces of an iterating block (precision of
+// the faces known at compile time).
+template <bool F32>
+__device__ __forceinline__ void sub_residual_t(blk& E, const char* pool, const FaceDesc* fd, int d, int n, int i,
+                                               int j, int k)
+{
+    const size_t ld = 3 * (size_t)n;
+#pragma unroll 2
+    for (int a = 0; a < d; ++a) {
+        const FaceDesc f = fd[a];
+        blk H;
+        if constexpr (F32) {
+            const zf* Hp = (const zf*)(pool + f.face_off);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) H.a[3 * x + c] = ldz(Hp + (size_t)(3 * i + x) * ld + 3 * j + c);
+        } else {
+            const zd* Hp = (const zd*)(pool + f.face_off);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) H.a[3 * x + c] = Hp[(size_t)(3 * i + x) * ld + 3 * j + c];
+        }
+        const blk fk = fibre_at(pool, f, k);
+        blk_mul_sub(E, H, fk);
+    }
+}
+
 // tile partials: [0] sigma_3 max, [1] pivot pair, [2] sum |H|^2, [3] max block |H|^2,
 //                [4] cross re, [5] t_dd re
+template <int KOP, int PATH>
 __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
 {
+    constexpr bool F32 = PATH == 1 || PATH == 3;
     __shared__ Red S;
     const int item = A.list[blockIdx.x];
     const int b = item >> 12, t = item & 4095;
@@ -280,17 +298,17 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
     int pi = 0x7fffffff;
     if (p < m * n) {
         const int i = p / n, j = p - (p / n) * n;
-        blk E = entry_of(A, B, i, j, k);
-        sub_residual(E, A, fd, d, m, n, i, j, k);
-        size_t ld = 3 * (size_t)n;
-        if (F.fp32) {
+        blk E = pair_entry<KOP, PATH>(A, B.rb + i, B.cb + j, k);
+        sub_residual_t<F32>(E, A.pool, fd, d, n, i, j, k);
+        const size_t ld = 3 * (size_t)n;
+        if constexpr (F32) {
             zf* H = (zf*)(A.pool + F.face_off);
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    zd v = E.a[3 * a + c];
-                    zf w = {(float)v.re, (float)v.im};
+                    const zd v = E.a[3 * a + c];
+                    const zf w = {(float)v.re, (float)v.im};
                     H[(size_t)(3 * i + a) * ld + 3 * j + c] = w;
                     E.a[3 * a + c] = {(double)w.re, (double)w.im};  // search on the stored face
                 }
@@ -320,8 +338,9 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
     }
 }
 
-// ---------------------------------------------------------------- low-rank faces: ACA
+// ---------------------------------------------------------------- per-slice ACA of far faces
 
+// Scratch of one face: ACA columns and the small matrices of the recompression.
 struct AcaWork {
     zd *U, *V;        // 3m x kmax, 3n x kmax column-major
     zd *G, *RU, *RV;  // kmax x kmax
@@ -329,6 +348,7 @@ struct AcaWork {
     double* dn;       // kmax
     int* usedrow;     // m
     int* order;       // kmax
+    int* info;        // [0]: ACA columns of the face in this slot (-1: not resolved)
 };
 
 __device__ AcaWork aca_work(double* base, int m, int n, int kmax)
@@ -352,6 +372,7 @@ __device__ AcaWork aca_work(double* base, int m, int n, int kmax)
     w.dn = (double*)z;
     w.usedrow = (int*)(w.dn + kmax);
     w.order = w.usedrow + m;
+    w.info = w.order + kmax;
     return w;
 }
 
@@ -359,17 +380,19 @@ struct AcaShared {
     Red r;
     zd pinv[9];
     double s;
-    long long off;
     int piv, flag;
 };
 
-// residual of the face at block (i, j): ENTRY - C^(d-1) - current ACA terms
-__device__ __forceinline__ blk aca_residual(const CompressArgs& A, const BlockIn& B, const FaceDesc* fd, int d, int k,
-                                            const AcaWork& w, int kc, int i, int j)
+// block (i, j) of the stored face H (3m x 3n row-major) minus the cross approximation U V^H
+template <typename T>
+__device__ __forceinline__ blk aca_residual(const cx<T>* H, int m, int n, const AcaWork& w, int kc, int i, int j)
 {
-    const int m = B.rs, n = B.cs;
-    blk E = entry_of(A, B, i, j, k);
-    sub_residual(E, A, fd, d, m, n, i, j, k);
+    blk E;
+    const size_t ld = 3 * (size_t)n;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) E.a[3 * a + c] = ldz(H + (size_t)(3 * i + a) * ld + 3 * j + c);
     for (int c = 0; c < kc; ++c) {
         zd u[3], v[3];
 #pragma unroll
@@ -385,54 +408,52 @@ __device__ __forceinline__ blk aca_residual(const CompressArgs& A, const BlockIn
     return E;
 }
 
-// Matrix-valued partial-pivot ACA of the residual face; returns the number of columns.
-__device__ int far_aca(const CompressArgs& A, const BlockIn& B, const FaceDesc* fd, int d, int k, const AcaWork& w,
-                       int kmax, double eps, AcaShared& S, long long& nent)
+// Matrix-valued partial-pivot ACA of the stored face with rank-3 steps and sigma_3 pivots
+// (the matrix form of the pivoting of Algorithm 1).  Stops once the newest 3 columns satisfy
+// ||U_k||_F ||V_k||_F <= tol, or when a residual row without a regular block is itself
+// below tol.  Returns the number of columns, or -1 when the face is not resolved within cap
+// columns short of 3 min(m, n) (or MAX_FAIL rows in a row have no regular pivot, or a row skipped that way is
+// left at the end): the caller keeps the face dense.
+template <typename T>
+__device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax,
+                        AcaShared& S)
 {
-    const int m = B.rs, n = B.cs;
     for (int i = threadIdx.x; i < m; i += WG) w.usedrow[i] = 0;
     __syncthreads();
-    int kc = 0, fails = 0, irow = 0;
-    double norm2S = 0.0, scale2 = 0.0;
-    const int maxsteps = min(min(m, n), kmax / 3);
-    while (kc + 3 <= 3 * maxsteps) {
-        // residual row irow -> V columns kc..kc+2 (as row^H)
-        double best = -1.0, rn2 = 0.0, fm = 0.0;
+    int kc = 0, fails = 0, skipped = 0, irow = 0;
+    for (;;) {
+        if (kc + 3 > cap) return kc >= 3 * min(m, n) ? kc : -1;  // all of min(m, n) interpolated: exact
+        // residual row block irow -> V columns kc..kc+2 (row^H)
+        double best = -1.0, rn2 = 0.0;
         int bj = 0x7fffffff;
         for (int j = threadIdx.x; j < n; j += WG) {
-            blk E = aca_residual(A, B, fd, d, k, w, kc, irow, j);
+            blk E = aca_residual(H, m, n, w, kc, irow, j);
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
                 for (int x = 0; x < 3; ++x) w.V[(size_t)(kc + y) * 3 * n + 3 * j + x] = conj(E.a[3 * y + x]);
-            double e2 = blk_fro2(E);
-            rn2 += e2;
-            fm = fmax(fm, e2);
+            rn2 += blk_fro2(E);
             double s3 = blk_sigma3(E);
             if (s3 > best || (s3 == best && j < bj)) {
                 best = s3;
                 bj = j;
             }
         }
-        if (threadIdx.x == 0) {
-            nent += n;
-            w.usedrow[irow] = 1;
-        }
+        if (threadIdx.x == 0) w.usedrow[irow] = 1;
         double v1[1] = {rn2};
         wg_sum<1>(v1, S.r);
         rn2 = v1[0];
-        fm = wg_max(fm, S.r);
-        scale2 = fmax(scale2, fm);
         wg_argmax(best, bj, S.r);
-        if (!(best > PIVOT_RTOL * sqrt(scale2))) {
-            if (rn2 <= eps * eps * norm2S) break;
-            ++fails;
+        if (!(best > PIVOT_RTOL * amax)) {
+            if (sqrt(rn2) <= tol) return kc;  // negligible residual row
+            ++skipped;
+            if (++fails >= MAX_FAIL) return -1;
             int cand = 0x7fffffff;
             for (int i = threadIdx.x; i < m; i += WG)
                 if (!w.usedrow[i] && i < cand) cand = i;
             double cv = cand == 0x7fffffff ? -1.0 : 1.0;
             wg_argmax(cv, cand, S.r);
-            if (cv < 0.0 || fails >= MAX_FAIL) break;
+            if (cv < 0.0) return -1;  // every row visited, a skipped row remains
             irow = cand;
             continue;
         }
@@ -448,11 +469,11 @@ __device__ int far_aca(const CompressArgs& A, const BlockIn& B, const FaceDesc* 
             for (int t = 0; t < 9; ++t) S.pinv[t] = Pi.a[t];
         }
         __syncthreads();
-        // residual column bj -> U columns kc..kc+2 = column * P^{-1}
-        double best2 = -1.0;
+        // residual column block bj -> U columns kc..kc+2 = column * P^{-1}
+        double best2 = -1.0, un2 = 0.0;
         int bi2 = 0x7fffffff;
         for (int i = threadIdx.x; i < m; i += WG) {
-            blk E = aca_residual(A, B, fd, d, k, w, kc, i, bj);
+            blk E = aca_residual(H, m, n, w, kc, i, bj);
             blk Pi;
 #pragma unroll
             for (int t = 0; t < 9; ++t) Pi.a[t] = S.pinv[t];
@@ -461,61 +482,21 @@ __device__ int far_aca(const CompressArgs& A, const BlockIn& B, const FaceDesc* 
             for (int y = 0; y < 3; ++y)
 #pragma unroll
                 for (int x = 0; x < 3; ++x) w.U[(size_t)(kc + x) * 3 * m + 3 * i + y] = Un.a[3 * y + x];
+            un2 += blk_fro2(Un);
             double s3 = w.usedrow[i] ? -1.0 : blk_sigma3(Un);
             if (s3 > best2 || (s3 == best2 && i < bi2)) {
                 best2 = s3;
                 bi2 = i;
             }
         }
-        if (threadIdx.x == 0) nent += m;
-        __syncthreads();
-        // ||S_k||^2 update: cross = tr(A1^H A2), A1 = Uold^H Un, A2 = Vold^H Vn, and
-        // ||Un Vn^H||^2 = tr((Un^H Un)(Vn^H Vn)); one wavefront per (column, new column)
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        double acc = 0.0;
-        for (int q = wv; q < 3 * (kc + 3); q += WG / 64) {
-            int c = q / 3, x = q - 3 * c;
-            double r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0;
-            for (int r = lane; r < 3 * m; r += 64) {
-                zd t = conj_mul(w.U[(size_t)c * 3 * m + r], w.U[(size_t)(kc + x) * 3 * m + r]);
-                r1 += t.re;
-                i1 += t.im;
-            }
-            for (int r = lane; r < 3 * n; r += 64) {
-                zd t = conj_mul(w.V[(size_t)c * 3 * n + r], w.V[(size_t)(kc + x) * 3 * n + r]);
-                r2 += t.re;
-                i2 += t.im;
-            }
-            r1 = wsum(r1);
-            i1 = wsum(i1);
-            r2 = wsum(r2);
-            i2 = wsum(i2);
-            zd a1 = {r1, i1}, a2 = {r2, i2};
-            if (c < kc) {
-                if (lane == 0) acc += conj_mul(a1, a2).re;
-            } else if (lane == 0) {
-                w.G[(c - kc) * 3 + x] = a1;
-                w.G[9 + (c - kc) * 3 + x] = a2;
-            }
-        }
-        double accv[1] = {acc};
-        wg_sum<1>(accv, S.r);
-        double cross = accv[0];
-        double nn = 0.0, un2 = 0.0, vn2 = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            un2 += w.G[c * 3 + c].re;
-            vn2 += w.G[9 + c * 3 + c].re;
-            for (int x = 0; x < 3; ++x) nn += (w.G[c * 3 + x] * w.G[9 + x * 3 + c]).re;
-        }
-        __syncthreads();
-        norm2S += 2.0 * cross + nn;
+        double v2[1] = {un2};
+        wg_sum<1>(v2, S.r);
         kc += 3;
-        if (sqrt(un2 * vn2) <= eps * sqrt(fmax(norm2S, 0.0))) break;
+        if (sqrt(v2[0] * rn2) <= tol) return kc;
         wg_argmax(best2, bi2, S.r);
-        if (best2 < 0.0) break;  // all rows used
+        if (best2 < 0.0) return skipped ? -1 : kc;  // every row is a pivot row: exact
         irow = bi2;
     }
-    return kc;
 }
 
 // Cholesky G = R^H R (R upper, column-major ld = kc); dependent columns get a zero row.
@@ -688,13 +669,14 @@ __device__ void wg_jacobi(zd* M, zd* VJ, int kc, AcaShared& S)
     }
 }
 
-// Recompression (eq. (ACA)) of U (3m x kc), V (3n x kc) into row-major pool factors
-// Ubar = QU Uc Sigma, Vbar = QV Vc of rank kk (precision T); returns kk, -1 on overflow.
+// Recompression (eq. (ACA)) of U (3m x kc), V (3n x kc): QR of both, SVD of R_U R_V^H,
+// truncation to the smallest kk with sqrt(sum_{t >= kk} s_t^2) <= tol.  When the
+// factors Ubar = Q_U Uc Sigma (3m x kk) and Vbar = Q_V Vc (3n x kk) take less memory than
+// the dense face, they are written row-major over the face storage Hout (precision T)
+// and kk is returned; otherwise 0 (the face stays dense).
 template <typename T>
-__device__ int far_recompress(const CompressArgs& A, const BlockIn& B, FaceDesc& f, const AcaWork& w, int kc,
-                              double eps, AcaShared& S)
+__device__ int face_recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, AcaShared& S)
 {
-    const int m = B.rs, n = B.cs;
     wg_qr(w.U, 3 * m, kc, w.G, w.M, w.RU, w.dn, S);
     wg_qr(w.V, 3 * n, kc, w.G, w.M, w.RV, w.dn, S);
     for (int q = threadIdx.x; q < kc * kc; q += WG) {
@@ -727,7 +709,7 @@ __device__ int far_recompress(const CompressArgs& A, const BlockIn& B, FaceDesc&
         double tail = 0.0;
         while (kk > 0) {
             double s = w.dn[w.order[kk - 1]];
-            if (sqrt(tail + s * s) <= eps * sqrt(tot)) {
+            if (sqrt(tail + s * s) <= tol) {
                 tail += s * s;
                 --kk;
             } else {
@@ -735,17 +717,14 @@ __device__ int far_recompress(const CompressArgs& A, const BlockIn& B, FaceDesc&
             }
         }
         if (tot > 0.0 && kk == 0) kk = 1;
+        if ((long long)kk * (m + n) >= 3LL * m * n) kk = 0;  // no saving over the dense face
         S.piv = kk;
-        S.off = kk > 0 ? pool_alloc(A, (long long)sizeof(cx<T>) * (3 * (long long)m + 3 * (long long)n) * kk) : 0;
     }
     __syncthreads();
     const int kk = S.piv;
-    const long long off = S.off;
-    if (off < 0) return -1;
-    f.face_off = off;
-    f.kk = kk;
-    cx<T>* Ub = (cx<T>*)(A.pool + off);
-    cx<T>* Vb = Ub + (size_t)3 * m * kk;
+    if (kk <= 0) return 0;
+    cx<T>* Ub = Hout;
+    cx<T>* Vb = Hout + (size_t)3 * m * kk;
     for (int q = threadIdx.x; q < 3 * m * kk; q += WG) {
         int r = q / kk, s = q - r * kk;
         int c = w.order[s];
@@ -764,65 +743,465 @@ __device__ int far_recompress(const CompressArgs& A, const BlockIn& B, FaceDesc&
     return kk;
 }
 
-// one workgroup per low-rank block of the list (scratch slot = position in the list)
-__global__ __launch_bounds__(WG) void k_aca(CompressArgs A)
+// ---------------------------------------------------------------- recompression in LDS
+
+// Faces with kc <= KF columns recompress with their kc x kc matrices in LDS (one workgroup
+// per face, kc^2 complex128 = 144 KiB at kc = 96); larger ones take the global-memory path.
+constexpr int KF = 96;
+constexpr int GCH = 4;  // rows of a Gram chunk staged in LDS
+
+struct RecompShared {
+    zd m[KF * KF];          // kc x kc column-major working matrix
+    zd stage[GCH * KF];  // Gram row chunk; later small vectors
+    double sv[KF];       // column norms / singular values
+    int order[KF];
+};
+
+// Lm (kc x kc, column-major, full Hermitian) = X^H X for X (rows x kc, column-major, global).
+// 4 x 4 output tiles per thread over the upper tile triangle; X streamed through LDS.
+__device__ void lds_gram(const zd* X, int rows, int kc, zd* Lm, zd* stage)
 {
-    __shared__ AcaShared S;
-    const int b = A.list[blockIdx.x];
-    if (!A.st[b].active) return;
-    const BlockIn B = A.blocks[b];
-    const int d = A.d, k = A.st[b].k;
-    FaceDesc* fd = A.faces + (size_t)b * A.L;
-    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, B.rs, B.cs, A.kmax);
-    long long nent = 0;
-    const double eps = A.eps_aca_far;
-    int kc = far_aca(A, B, fd, d, k, w, A.kmax, eps, S, nent);
-    FaceDesc f = fd[d];
-    int kk = 0;
-    if (kc > 0) kk = A.mixed ? far_recompress<float>(A, B, f, w, kc, eps, S) : far_recompress<double>(A, B, f, w, kc, eps, S);
-    if (threadIdx.x == 0) {
-        if (kk < 0) {
-            A.st[b].active = 0;
-        } else {
-            f.kk = kk > 0 ? kk : -1;
-            f.fp32 = A.mixed ? 1 : 0;
-            fd[d] = f;
+    const int nt = (kc + 3) >> 2, ntri = nt * (nt + 1) / 2;
+    for (int base = 0; base < ntri; base += WG) {
+        const int tt = base + threadIdx.x;
+        const bool act = tt < ntri;
+        int tj = 0, ti = 0;
+        if (act) {
+            tj = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+            while ((tj + 1) * (tj + 2) / 2 <= tt) ++tj;
+            while (tj * (tj + 1) / 2 > tt) --tj;
+            ti = tt - tj * (tj + 1) / 2;
         }
-        A.st[b].kc = kc;
-        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)nent);
+        zd acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = {0.0, 0.0};
+        for (int r0 = 0; r0 < rows; r0 += GCH) {
+            const int nr = min(GCH, rows - r0);
+            __syncthreads();
+            for (int q = threadIdx.x; q < GCH * kc; q += WG) {
+                const int c = q / GCH, r = q - c * GCH;
+                stage[r * kc + c] = r < nr ? X[(size_t)c * rows + r0 + r] : zd{0.0, 0.0};
+            }
+            __syncthreads();
+            if (act) {
+                for (int r = 0; r < nr; ++r) {
+                    zd a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int ca = 4 * ti + u, cb = 4 * tj + u;
+                        a[u] = ca < kc ? stage[r * kc + ca] : zd{0.0, 0.0};
+                        b[u] = cb < kc ? stage[r * kc + cb] : zd{0.0, 0.0};
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] += conj_mul(a[u], b[v]);
+                }
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 4 * ti + u, j = 4 * tj + v;
+                    if (i < kc && j < kc && i <= j) {
+                        Lm[(size_t)j * kc + i] = acc[u][v];
+                        Lm[(size_t)i * kc + j] = conj(acc[u][v]);
+                    }
+                }
+        }
+    }
+    __syncthreads();
+}
+
+// Cholesky in place: Lm = R^H R with R upper (stored in the upper triangle, lower zeroed);
+// a pivot without positive mass gives a zero row.
+__device__ void lds_cholesky(zd* Lm, int kc, AcaShared& S)
+{
+    for (int k = 0; k < kc; ++k) {
+        if (threadIdx.x == 0) {
+            const double p = Lm[(size_t)k * kc + k].re;
+            S.s = p > 1e-24 ? sqrt(p) : 0.0;
+        }
+        __syncthreads();
+        const double rkk = S.s;
+        for (int j = k + threadIdx.x; j < kc; j += WG) {
+            const zd g = Lm[(size_t)j * kc + k];
+            Lm[(size_t)j * kc + k] = (j == k) ? zd{rkk, 0.0} : (rkk > 0.0 ? g * (1.0 / rkk) : zd{0.0, 0.0});
+        }
+        __syncthreads();
+        const int rem = kc - k - 1;
+        for (int q = threadIdx.x; q < rem * rem; q += WG) {
+            const int jj = k + 1 + q / rem, ii = k + 1 + q % rem;
+            if (ii <= jj) Lm[(size_t)jj * kc + ii] -= conj_mul(Lm[(size_t)ii * kc + k], Lm[(size_t)jj * kc + k]);
+        }
+        __syncthreads();
+    }
+    for (int q = threadIdx.x; q < kc * kc; q += WG)
+        if (q % kc > q / kc) Lm[q] = {0.0, 0.0};
+    __syncthreads();
+}
+
+// X (rows x kc, column-major, global) <- X R^{-1}, R upper in Lm; blocks of 8 columns per
+// pass, one row per thread; zero pivots give zero columns.
+__device__ void lds_trsm(zd* X, int rows, const zd* Lm, int kc)
+{
+    constexpr int NB = 8;
+    for (int r = threadIdx.x; r < rows; r += WG) {
+        for (int j0 = 0; j0 < kc; j0 += NB) {
+            const int nb = min(NB, kc - j0);
+            zd acc[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) acc[t] = t < nb ? X[(size_t)(j0 + t) * rows + r] : zd{0.0, 0.0};
+            for (int i = 0; i < j0; ++i) {
+                const zd x = X[(size_t)i * rows + r];
+#pragma unroll
+                for (int t = 0; t < NB; ++t)
+                    if (t < nb) acc[t] -= x * Lm[(size_t)(j0 + t) * kc + i];
+            }
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                if (t >= nb) break;
+#pragma unroll
+                for (int u = 0; u < t; ++u) acc[t] -= acc[u] * Lm[(size_t)(j0 + t) * kc + j0 + u];
+                const double d = Lm[(size_t)(j0 + t) * kc + j0 + t].re;
+                acc[t] = d > 0.0 ? acc[t] * (1.0 / d) : zd{0.0, 0.0};
+            }
+#pragma unroll
+            for (int t = 0; t < NB; ++t)
+                if (t < nb) X[(size_t)(j0 + t) * rows + r] = acc[t];
+        }
+    }
+    __syncthreads();
+}
+
+// column scaling + CholeskyQR2 of X (rows x kc): X <- Q1 = (X D^-1) R1^-1 in place,
+// R2 (upper, global R2out) with Q = Q1 R2^-1, and R = R2 R1 D (upper, global Rout).
+__device__ void lds_qr(zd* X, int rows, int kc, zd* Rout, zd* R2out, zd* Lm, RecompShared& L, AcaShared& S)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = wv; c < kc; c += WG / 64) {
+        double s = 0.0;
+        for (int r = lane; r < rows; r += 64) s += abs2(X[(size_t)c * rows + r]);
+        s = wsum(s);
+        if (lane == 0) L.sv[c] = sqrt(s);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < rows * kc; q += WG) {
+        const double dc = L.sv[q / rows];
+        X[q] = dc > 0.0 ? X[q] * (1.0 / dc) : zd{0.0, 0.0};
+    }
+    __syncthreads();
+    lds_gram(X, rows, kc, Lm, L.stage);
+    lds_cholesky(Lm, kc, S);
+    lds_trsm(X, rows, Lm, kc);
+    for (int q = threadIdx.x; q < kc * kc; q += WG) R2out[q] = Lm[q];  // R1 (temporarily)
+    __syncthreads();
+    lds_gram(X, rows, kc, Lm, L.stage);
+    lds_cholesky(Lm, kc, S);
+    // Rout = R2 R1 D, then R2out = R2
+    for (int q = threadIdx.x; q < kc * kc; q += WG) {
+        const int i = q % kc, j = q / kc;
+        zd s = {0.0, 0.0};
+        for (int t = i; t <= j; ++t) s += Lm[(size_t)t * kc + i] * R2out[(size_t)j * kc + t];
+        Rout[q] = i <= j ? s * L.sv[j] : zd{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kc * kc; q += WG) R2out[q] = Lm[q];
+    __syncthreads();
+}
+
+// One-sided Jacobi on Lm (kc x kc, column-major): Lm <- M VJ with orthogonal columns; the
+// rotations are not accumulated.  JGL lanes of a wavefront per column pair.
+constexpr int JGL = 4;
+__device__ void lds_jacobi(zd* Lm, int kc, AcaShared& S)
+{
+    const int np = kc + (kc & 1);
+    const int g = threadIdx.x / JGL, gl = threadIdx.x % JGL;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (threadIdx.x == 0) S.flag = 0;
+        __syncthreads();
+        for (int rnd = 0; rnd < np - 1; ++rnd) {
+            for (int pr = g; pr < np / 2; pr += WG / JGL) {
+                int p, q;
+                if (pr == 0) {
+                    p = rnd;
+                    q = np - 1;
+                } else {
+                    p = (rnd + pr) % (np - 1);
+                    q = (rnd - pr + np - 1) % (np - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                if (q >= kc) continue;  // uniform within the lane group
+                zd* mp = Lm + (size_t)p * kc;
+                zd* mq = Lm + (size_t)q * kc;
+                double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+                for (int r = gl; r < kc; r += JGL) {
+                    const zd a = mp[r], b = mq[r];
+                    al += abs2(a);
+                    be += abs2(b);
+                    const zd c = conj_mul(a, b);
+                    gr += c.re;
+                    gi += c.im;
+                }
+#pragma unroll
+                for (int o = 1; o < JGL; o <<= 1) {
+                    al += __shfl_xor(al, o, 64);
+                    be += __shfl_xor(be, o, 64);
+                    gr += __shfl_xor(gr, o, 64);
+                    gi += __shfl_xor(gi, o, 64);
+                }
+                const double gabs = sqrt(gr * gr + gi * gi);
+                if (!(gabs > 1e-14 * sqrt(al * be)) || gabs == 0.0) continue;
+                if (gl == 0) S.flag = 1;
+                const zd e = {gr / gabs, gi / gabs};
+                const double zeta = (be - al) / (2.0 * gabs);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                const zd ce = conj(e);
+                for (int r = gl; r < kc; r += JGL) {
+                    const zd a = mp[r], b = mq[r] * ce;
+                    mp[r] = c * a - s * b;
+                    mq[r] = (s * a + c * b) * e;
+                }
+            }
+            __syncthreads();
+        }
+        const int f = S.flag;
+        __syncthreads();
+        if (!f) break;
     }
 }
 
-// pivot search on the reconstructed low-rank face (one workgroup per tile)
-__global__ __launch_bounds__(WG) void k_scan_lr(CompressArgs A)
+// Recompression of U (3m x kc), V (3n x kc) with kc <= KF (see face_recompress for the
+// contract).  Scratch use: G = R2_U, VJ = R2_V, RU = R_U then VJ-tilde, RV = R_V then Y_U,
+// M = M (original).
+template <typename T>
+__device__ int face_recompress_lds(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol,
+                                   RecompShared& L, AcaShared& S)
 {
-    __shared__ Red S;
-    const int item = A.list[blockIdx.x];
-    const int b = item >> 12, t = item & 4095;
-    if (!A.st[b].active) return;
-    const BlockIn B = A.blocks[b];
-    const int m = B.rs, n = B.cs;
-    const FaceDesc F = A.faces[(size_t)b * A.L + A.d];
-    const int p = t * TILE + threadIdx.x;
-    double s3 = -1.0, e2 = 0.0;
-    int pi = 0x7fffffff;
-    if (p < m * n && F.kk > 0) {
-        const int i = p / n, j = p - (p / n) * n;
-        blk H = face_block(A.pool, F, m, n, i, j);
-        e2 = blk_fro2(H);
-        s3 = blk_sigma3(H);
-        pi = p;
+    zd* Lm = L.m;
+    lds_qr(w.U, 3 * m, kc, w.RU, w.G, Lm, L, S);
+    lds_qr(w.V, 3 * n, kc, w.RV, w.VJ, Lm, L, S);
+    // M = R_U R_V^H into LDS and the scratch copy
+    for (int q = threadIdx.x; q < kc * kc; q += WG) {
+        const int i = q % kc, j = q / kc;
+        zd s = {0.0, 0.0};
+        for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
+        Lm[q] = s;
+        w.M[q] = s;
     }
-    double v[1] = {e2};
-    wg_sum<1>(v, S);
-    double fm = wg_max(e2, S);
-    wg_argmax(s3, pi, S);
+    __syncthreads();
+    lds_jacobi(Lm, kc, S);
+    // singular values, descending order (ties to the smaller column), truncation
+    for (int c = threadIdx.x; c < kc; c += WG) {
+        double s = 0.0;
+        for (int r = 0; r < kc; ++r) s += abs2(Lm[(size_t)c * kc + r]);
+        L.sv[c] = sqrt(s);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kc; c += WG) {
+        const double sc = L.sv[c];
+        int rank = 0;
+        for (int c2 = 0; c2 < kc; ++c2) {
+            const double s2 = L.sv[c2];
+            rank += (s2 > sc || (s2 == sc && c2 < c)) ? 1 : 0;
+        }
+        L.order[rank] = c;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
-        tp[0] = s3;
-        tp[1] = (double)pi;
-        tp[2] = v[0];
-        tp[3] = fm;
+        double tot = 0.0;
+        for (int c = 0; c < kc; ++c) tot += L.sv[c] * L.sv[c];
+        int kk = kc;
+        double tail = 0.0;
+        while (kk > 0) {
+            const double s = L.sv[L.order[kk - 1]];
+            if (sqrt(tail + s * s) <= tol) {
+                tail += s * s;
+                --kk;
+            } else {
+                break;
+            }
+        }
+        if (tot > 0.0 && kk == 0) kk = 1;
+        if ((long long)kk * (m + n) >= 3LL * m * n) kk = 0;
+        S.piv = kk;
+    }
+    __syncthreads();
+    const int kk = S.piv;
+    if (kk <= 0) return 0;
+    // right singular vectors of M for the kept columns: VJ_s = M^H W_s / sigma_s^2 -> RU
+    for (int q = threadIdx.x; q < kc * kk; q += WG) {
+        const int r = q % kc, s = q / kc;
+        const int c = L.order[s];
+        const double sg = L.sv[c];
+        zd acc = {0.0, 0.0};
+        for (int t = 0; t < kc; ++t) acc += conj_mul(w.M[(size_t)r * kc + t], Lm[(size_t)c * kc + t]);
+        w.RU[(size_t)s * kc + r] = sg > 0.0 ? acc * (1.0 / (sg * sg)) : zd{0.0, 0.0};
+    }
+    // Y_U = R2_U^{-1} W_kept -> RV (one thread per kept column, back substitution)
+    for (int s = threadIdx.x; s < kk; s += WG) {
+        const int c = L.order[s];
+        zd* y = w.RV + (size_t)s * kc;
+        for (int i = kc - 1; i >= 0; --i) {
+            zd v = Lm[(size_t)c * kc + i];
+            for (int t = i + 1; t < kc; ++t) v -= w.G[(size_t)t * kc + i] * y[t];
+            const double d = w.G[(size_t)i * kc + i].re;
+            y[i] = d > 0.0 ? v * (1.0 / d) : zd{0.0, 0.0};
+        }
+    }
+    __syncthreads();
+    // Y_V = R2_V^{-1} VJ_kept -> LDS columns [kc x kk] after moving Y_U there is not needed:
+    // Ubar first (Y_U staged in LDS), then Y_V into LDS and Vbar.
+    for (int q = threadIdx.x; q < kc * kk; q += WG) Lm[q] = w.RV[q];
+    __syncthreads();
+    cx<T>* Ub = Hout;
+    cx<T>* Vb = Hout + (size_t)3 * m * kk;
+    constexpr int CH = 16;
+    for (int r = threadIdx.x; r < 3 * m; r += WG) {
+        for (int s0 = 0; s0 < kk; s0 += CH) {
+            zd acc[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) acc[u] = {0.0, 0.0};
+            for (int t = 0; t < kc; ++t) {
+                const zd x = w.U[(size_t)t * 3 * m + r];
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+                    if (s0 + u < kk) acc[u] += x * Lm[(size_t)(s0 + u) * kc + t];
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (s0 + u < kk) stz(Ub + (size_t)r * kk + s0 + u, acc[u]);
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < kk; s += WG) {
+        zd* y = Lm + (size_t)s * kc;
+        const zd* vj = w.RU + (size_t)s * kc;
+        for (int i = kc - 1; i >= 0; --i) {
+            zd v = vj[i];
+            for (int t = i + 1; t < kc; ++t) v -= w.VJ[(size_t)t * kc + i] * y[t];
+            const double d = w.VJ[(size_t)i * kc + i].re;
+            y[i] = d > 0.0 ? v * (1.0 / d) : zd{0.0, 0.0};
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < 3 * n; r += WG) {
+        for (int s0 = 0; s0 < kk; s0 += CH) {
+            zd acc[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) acc[u] = {0.0, 0.0};
+            for (int t = 0; t < kc; ++t) {
+                const zd x = w.V[(size_t)t * 3 * n + r];
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+                    if (s0 + u < kk) acc[u] += x * Lm[(size_t)(s0 + u) * kc + t];
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (s0 + u < kk) stz(Vb + (size_t)r * kk + s0 + u, acc[u]);
+        }
+    }
+    __syncthreads();
+    return kk;
+}
+
+// ACA stage of one stored dense face: ||H||_F, the pivot scale max |H|, then face_aca;
+// returns the column count (-1: not resolved, or a zero face).
+template <typename T>
+__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, AcaShared& S)
+{
+    double s2 = 0.0, amax = 0.0;
+    const size_t cnt = (size_t)9 * m * n;
+    for (size_t q = threadIdx.x; q < cnt; q += WG) {
+        const double a2 = abs2(ldz(H + q));
+        s2 += a2;
+        amax = fmax(amax, a2);
+    }
+    double v1[1] = {s2};
+    wg_sum<1>(v1, S.r);
+    amax = sqrt(wg_max(amax, S.r));
+    return v1[0] > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, S) : -1;
+}
+
+// Recompression stage: kk > 0 (factors written over the face) or 0 (kept dense).
+template <typename T>
+__device__ int face_recompress_stage(cx<T>* H, int m, int n, const AcaWork& w, int kc, double tol, RecompShared& L,
+                                     AcaShared& S)
+{
+    if (kc <= 0) return 0;
+    if (kc <= KF) return face_recompress_lds(H, m, n, w, kc, tol, L, S);
+    return face_recompress(H, m, n, w, kc, tol, S);
+}
+
+// Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
+// face-fibre term errs by at most about eps_aca ||C^(r)||_F.
+__device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f, AcaShared& S)
+{
+    double fn2 = 0.0;
+    const zd* fib = (const zd*)(A.pool + f.fib_off);
+    for (int q = threadIdx.x; q < 9 * A.L; q += WG) fn2 += abs2(fib[q]);
+    double v1[1] = {fn2};
+    wg_sum<1>(v1, S.r);
+    return v1[0] > 0.0 ? A.eps_aca_far * sqrt(fmax(A.st[b].norm2, 0.0) / v1[0]) : 0.0;
+}
+
+// Per-slice ACA pass, one workgroup per listed face (items (block << 8) | d, scratch slot =
+// position in the list): k_face_aca leaves the ACA columns in the slot, k_face_recomp
+// recompresses them and rewrites the face descriptor.
+__global__ __launch_bounds__(WG) void k_face_aca(CompressArgs A)
+{
+    __shared__ AcaShared S;
+    const int item = A.list[blockIdx.x];
+    const int b = item >> 8, d = item & 255;
+    const BlockIn B = A.blocks[b];
+    const FaceDesc f = A.faces[(size_t)b * A.L + d];
+    const int m = B.rs, n = B.cs;
+    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
+    int kc = -1;
+    if (f.kk == 0 && !f.sel) {
+        const int cap = min(A.kmax, face_aca_cap(m, n));
+        const double tol = face_tol(A, b, f, S);
+        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, S)
+                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, S);
+    }
+    if (threadIdx.x == 0) w.info[0] = kc;
+}
+
+__global__ __launch_bounds__(WG) void k_face_recomp(CompressArgs A)
+{
+    __shared__ AcaShared S;
+    __shared__ RecompShared L;
+    const int item = A.list[blockIdx.x];
+    const int b = item >> 8, d = item & 255;
+    const BlockIn B = A.blocks[b];
+    FaceDesc* fp = A.faces + (size_t)b * A.L + d;
+    const FaceDesc f = *fp;
+    if (f.kk != 0 || f.sel) return;
+    const int m = B.rs, n = B.cs;
+    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
+    const int kc = w.info[0];
+    int kk = 0;
+    if (kc > 0) {
+        const double tol = face_tol(A, b, f, S);
+        kk = f.fp32 ? face_recompress_stage((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L, S)
+                    : face_recompress_stage((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L, S);
+    }
+    if (threadIdx.x == 0) {
+        if (kk > 0) {
+            fp->kk = kk;
+            atomicAdd((unsigned long long*)&A.st[b].aca_cols, (unsigned long long)kc);
+        } else {
+            atomicAdd(&A.st[b].aca_dense, 1);
+        }
     }
 }
 
@@ -868,7 +1247,7 @@ __global__ __launch_bounds__(64) void k_pivot(CompressArgs A)
     } else {
         s.piv = pi;
         const int n = B.cs;
-        blk P = face_block(A.pool, A.faces[(size_t)b * A.L + d], B.rs, n, pi / n, pi - (pi / n) * n);
+        blk P = face_block(A.pool, A.faces[(size_t)b * A.L + d], n, pi / n, pi - (pi / n) * n);
         blk Pi = blk_inv(P);
         for (int t = 0; t < 9; ++t) s.pinv[t] = Pi.a[t];
         A.used[(size_t)b * A.L + s.k] = 1;
@@ -896,7 +1275,7 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
     int bk = 0x7fffffff;
     for (int k = threadIdx.x; k < L; k += WG) {
         blk E = entry_of(A, B, pi, pj, k);
-        sub_residual(E, A, fd, d, m, n, pi, pj, k);
+        sub_residual(E, A, fd, d, n, pi, pj, k);
         blk Pi;
 #pragma unroll
         for (int t = 0; t < 9; ++t) Pi.a[t] = Pi_s[t];
@@ -962,13 +1341,13 @@ __global__ __launch_bounds__(WG) void k_cross_dense(CompressArgs A)
     zd cross = {0.0, 0.0}, tdd = {0.0, 0.0};
     if (p < m * n) {
         const int i = p / n, j = p - (p / n) * n;
-        blk Hd = face_block(A.pool, fd[d], m, n, i, j);
+        blk Hd = face_block(A.pool, fd[d], n, i, j);
         for (int a = 0; a <= d; ++a) {
             blk F;
 #pragma unroll
             for (int q = 0; q < 9; ++q) F.a[q] = Fs[9 * a + q];
             blk HF = blk_mul(Hd, F);
-            blk Ha = (a == d) ? Hd : face_block(A.pool, fd[a], m, n, i, j);
+            blk Ha = (a == d) ? Hd : face_block(A.pool, fd[a], n, i, j);
             zd s = {0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < 9; ++q) s += conj_mul(Ha.a[q], HF.a[q]);
@@ -985,74 +1364,6 @@ __global__ __launch_bounds__(WG) void k_cross_dense(CompressArgs A)
     }
 }
 
-// low-rank faces: tr(X Y) with X = Ua^H Ud (ka x kd), Y = Vd^H (I (x) F_da) Va (kd x ka)
-template <typename T>
-__device__ void cross_lr_block(const CompressArgs& A, int b, Red& S, const zd* Fs)
-{
-    const BlockIn B = A.blocks[b];
-    const int m = B.rs, n = B.cs, d = A.d, L = A.L;
-    const FaceDesc* fd = A.faces + (size_t)b * L;
-    const FaceDesc Fd = fd[d];
-    double cross = 0.0, tdd = 0.0;
-    if (Fd.kk > 0) {
-        const int kd = Fd.kk;
-        const cx<T>* Ud = (const cx<T>*)(A.pool + Fd.face_off);
-        const cx<T>* Vd = Ud + (size_t)3 * m * kd;
-        for (int a = 0; a <= d; ++a) {
-            const FaceDesc Fa = fd[a];
-            double acc = 0.0;
-            if (Fa.kk > 0) {
-                const int ka = Fa.kk;
-                const cx<T>* Ua = (const cx<T>*)(A.pool + Fa.face_off);
-                const cx<T>* Va = Ua + (size_t)3 * m * ka;
-                blk F;
-#pragma unroll
-                for (int q = 0; q < 9; ++q) F.a[q] = Fs[9 * a + q];
-                for (int q = threadIdx.x; q < ka * kd; q += WG) {
-                    const int s = q / kd, tt = q - s * kd;
-                    zd X = {0.0, 0.0}, Y = {0.0, 0.0};
-                    for (int r = 0; r < 3 * m; ++r) X += conj_mul(ldz(Ua + (size_t)r * ka + s), ldz(Ud + (size_t)r * kd + tt));
-                    for (int j = 0; j < n; ++j) {
-                        zd va[3], vd[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            va[c] = ldz(Va + (size_t)(3 * j + c) * ka + s);
-                            vd[c] = ldz(Vd + (size_t)(3 * j + c) * kd + tt);
-                        }
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            zd fv = F.a[3 * c] * va[0] + F.a[3 * c + 1] * va[1] + F.a[3 * c + 2] * va[2];
-                            Y += conj_mul(vd[c], fv);
-                        }
-                    }
-                    acc += (X * Y).re;
-                }
-            }
-            double v[1] = {acc};
-            wg_sum<1>(v, S);
-            if (a < d) cross += v[0];
-            else tdd = v[0];
-        }
-    }
-    if (threadIdx.x == 0) {
-        double* tp = A.tp + (size_t)B.tile0 * 8;
-        tp[4] = cross;
-        tp[5] = tdd;
-    }
-}
-
-__global__ __launch_bounds__(WG) void k_cross_lr(CompressArgs A)
-{
-    __shared__ Red S;
-    __shared__ zd Fs[MAX_L * 9];
-    const int b = A.list[blockIdx.x];
-    if (!A.st[b].active || A.st[b].stop) return;
-    for (int q = threadIdx.x; q < 9 * (A.d + 1); q += WG) Fs[q] = A.Fda[(size_t)b * A.L * 9 + q];
-    __syncthreads();
-    if (A.mixed) cross_lr_block<float>(A, b, S, Fs);
-    else cross_lr_block<double>(A, b, S, Fs);
-}
-
 // ---------------------------------------------------------------- finalize the step
 
 __global__ __launch_bounds__(64) void k_final(CompressArgs A)
@@ -1065,8 +1376,7 @@ __global__ __launch_bounds__(64) void k_final(CompressArgs A)
     const BlockIn B = A.blocks[b];
     const int d = A.d;
     double cross = 0.0, tdd = 0.0;
-    int nt = B.lowrank ? 1 : B.ntile;
-    for (int t = 0; t < nt; ++t) {
+    for (int t = 0; t < B.ntile; ++t) {
         const double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
         cross += tp[4];
         tdd += tp[5];
@@ -1078,8 +1388,6 @@ __global__ __launch_bounds__(64) void k_final(CompressArgs A)
         s.active = 0;
     } else {
         s.rank = d + 1;
-        const FaceDesc f = A.faces[(size_t)b * A.L + d];
-        if (f.kk > s.aca_max) s.aca_max = f.kk;
         if (s.nextk < 0 || d + 1 == A.L) {
             s.active = 0;
         } else {
@@ -1146,12 +1454,49 @@ __global__ __launch_bounds__(WG) void k_fallback_face(CompressArgs A, int kf)
         atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)min(TILE, m * n - t * TILE));
 }
 
+// the same pass on one given matrix: out[0] = ACA columns, out[1] = kk
+__global__ __launch_bounds__(WG) void k_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax,
+                                                   double* scratch, int* out)
+{
+    __shared__ AcaShared S;
+    __shared__ RecompShared L;
+    AcaWork w = aca_work(scratch, m, n, kmax);
+    int kc, kk;
+    if (fp32) {
+        kc = face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, S);
+        kk = face_recompress_stage((cx<float>*)H, m, n, w, kc, tol, L, S);
+    } else {
+        kc = face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, S);
+        kk = face_recompress_stage((cx<double>*)H, m, n, w, kc, tol, L, S);
+    }
+    if (threadIdx.x == 0) {
+        out[0] = kc;
+        out[1] = kk;
+    }
+}
+
+// ---------------------------------------------------------------- compaction
+
+// copy segment q (src offset, dst offset, bytes; offsets 256-aligned, bytes a multiple of 8)
+__global__ __launch_bounds__(WG) void k_copy_segments(const char* src, char* dst, const long long* seg, int nseg)
+{
+    const int q = blockIdx.x;
+    if (q >= nseg) return;
+    const long long so = seg[3 * q], dof = seg[3 * q + 1], bytes = seg[3 * q + 2];
+    const long long n16 = bytes >> 4;
+    const uint4* s4 = (const uint4*)(src + so);
+    uint4* d4 = (uint4*)(dst + dof);
+    for (long long t = threadIdx.x; t < n16; t += WG) d4[t] = s4[t];
+    if ((bytes & 8) && threadIdx.x == 0)
+        *(unsigned long long*)(dst + dof + 16 * n16) = *(const unsigned long long*)(src + so + 16 * n16);
+}
+
 }  // namespace
 
 size_t aca_scratch_doubles(int m, int n, int kmax)
 {
     return (size_t)2 * (3 * (size_t)m * kmax + 3 * (size_t)n * kmax + 5 * (size_t)kmax * kmax) + kmax +
-           (m + kmax + 1) / 2 + 8;
+           (m + kmax + 4 + 1) / 2 + 8;
 }
 
 #define BEM_LAUNCH(kern, grid, block, ...)                                                     \
@@ -1161,13 +1506,30 @@ size_t aca_scratch_doubles(int m, int n, int kmax)
     } while (0)
 
 void launch_init(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_init, (A.nblocks + 255) / 256, 256, A); }
-void launch_face_dense(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_face_dense, A.nlist, WG, A); }
-void launch_aca(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_aca, A.nlist, WG, A); }
-void launch_scan_lr(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_scan_lr, A.nlist, WG, A); }
+template <int PATH>
+void launch_face_dense_path(const CompressArgs& A, hipStream_t st)
+{
+    if (A.op == OP_TABLE) BEM_LAUNCH((k_face_dense<2, PATH>), A.nlist, WG, A);
+    else if (A.op == OP_V) BEM_LAUNCH((k_face_dense<0, PATH>), A.nlist, WG, A);
+    else BEM_LAUNCH((k_face_dense<1, PATH>), A.nlist, WG, A);
+}
+void launch_face_dense(const CompressArgs& A, int path, hipStream_t st)
+{
+    switch (path) {
+        case 0: launch_face_dense_path<0>(A, st); break;
+        case 1: launch_face_dense_path<1>(A, st); break;
+        case 2: launch_face_dense_path<2>(A, st); break;
+        default: launch_face_dense_path<3>(A, st); break;
+    }
+}
+void launch_face_aca(const CompressArgs& A, hipStream_t st)
+{
+    BEM_LAUNCH(k_face_aca, A.nlist, WG, A);
+    BEM_LAUNCH(k_face_recomp, A.nlist, WG, A);
+}
 void launch_pivot(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_pivot, (A.nlist + 63) / 64, 64, A); }
 void launch_fibre(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_fibre, A.nlist, WG, A); }
 void launch_cross_dense(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_cross_dense, A.nlist, WG, A); }
-void launch_cross_lr(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_cross_lr, A.nlist, WG, A); }
 void launch_final(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_final, (A.nlist + 63) / 64, 64, A); }
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st)
 {
@@ -1176,6 +1538,15 @@ void launch_fallback(const CompressArgs& A, int kf, hipStream_t st)
 void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st)
 {
     BEM_LAUNCH(k_fallback_face, A.nlist, WG, A, kf);
+}
+void launch_copy_segments(const char* src, char* dst, const long long* seg, int nseg, hipStream_t st)
+{
+    BEM_LAUNCH(k_copy_segments, nseg, WG, src, dst, seg, nseg);
+}
+void launch_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax, double* scratch, int* out,
+                       hipStream_t st)
+{
+    BEM_LAUNCH(k_aca_matrix, 1, WG, H, m, n, fp32, tol, cap, kmax, scratch, out);
 }
 
 }  // namespace bem

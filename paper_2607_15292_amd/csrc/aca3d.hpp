@@ -12,13 +12,15 @@ constexpr int TILE = 256;   // pairs (i, j) per workgroup in the tiled phases
 struct BlockIn {
     int rb, rs, cb, cs;  // rows [rb, rb + rs), columns [cb, cb + cs) in cluster order
     int far;             // admissible (far field): the mixed path computes it in FP32
-    int lowrank;         // faces by per-slice ACA + recompression (else dense faces)
+    int aca;             // faces compressed by the per-slice ACA + recompression pass
     int tile0, ntile;    // range of this block's pair tiles
+    int path;            // face kernel: 0 any pair class FP64, 1 / 2 all pairs regular FP32 / FP64,
+                         // 3 any pair class with FP32 regular pairs (mixed far field)
 };
 
 // One face-fibre pair of a block.  kk == 0: dense face (3m x 3n row-major at face_off,
 // complex128, or complex64 when fp32); kk > 0: factors Ubar (3m x kk) then Vbar (3n x kk),
-// row-major, complex64 (mixed) or complex128, with H = Ubar Vbar^H; kk < 0: empty face.
+// row-major, in the same precision, with H = Ubar Vbar^H; kk < 0: empty face.
 // fib_off: fibre f[L][3][3] complex128.  sel = 1: dense-fallback face, its fibre selects
 // frequency k only.
 struct FaceDesc {
@@ -39,9 +41,9 @@ struct BlockState {
     int stop;       // this step ends the block (no fibre, no norm update)
     int piv;        // pivot pair of the current face
     int nextk;      // next frequency
-    int kc;         // ACA columns of the current face
-    int aca_max;    // largest stored far-face rank
+    int aca_dense;  // faces of this block left dense by the per-slice ACA pass
     int pad;
+    long long aca_cols;  // ACA columns (before recompression) over the faces stored as factors
     double norm2;   // ||C^(d)||_F^2
     double hn2, fmax2, s3max, fn2;
     long long entries;
@@ -54,7 +56,7 @@ struct CompressArgs {
     int mixed;
     int L;
     int nblocks;
-    int kmax;               // column capacity of the per-slice ACA (multiple of 3)
+    int kmax;               // column capacity of the per-slice ACA scratch (multiple of 3)
     int d;                  // current step
     const BlockIn* blocks;
     FaceDesc* faces;        // [nblocks][L]
@@ -62,7 +64,8 @@ struct CompressArgs {
     unsigned char* used;    // [nblocks][L]
     zd* Fda;                // [nblocks][L][9]: F_{d,a} = sum_k f_d[k] f_a[k]^H
     double* tp;             // tile partials [ntiles][8]
-    const int* list;        // work list of this launch: block ids, or tiles packed as (block << 12) | tile
+    const int* list;        // work list of this launch: block ids, tiles packed as (block << 12) | tile,
+                            // or faces packed as (block << 8) | d
     int nlist;
     char* pool;
     unsigned long long pool_cap;
@@ -73,18 +76,29 @@ struct CompressArgs {
     double eps3d, eps3d_far, eps_aca_far;
 };
 
+// Column cap of the per-slice ACA of an m x n (elements) face: 3 ceil(2 m n / (m + n)), the
+// rank at which the ACA columns would take twice the memory of the dense face (rank-3 ACA
+// steps overshoot the recompressed rank about twofold), at most 3 min(m, n).
+__host__ __device__ inline int face_aca_cap(int m, int n)
+{
+    int s = (2 * m * n + (m + n) - 1) / (m + n);
+    return 3 * (s < m ? (s < n ? s : n) : (m < n ? m : n));
+}
+
 size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
 void launch_init(const CompressArgs& A, hipStream_t st);
-void launch_face_dense(const CompressArgs& A, hipStream_t st);
-void launch_aca(const CompressArgs& A, hipStream_t st);
-void launch_scan_lr(const CompressArgs& A, hipStream_t st);
+// all listed tiles belong to blocks of the given face-kernel path (BlockIn::path)
+void launch_face_dense(const CompressArgs& A, int path, hipStream_t st);
 void launch_pivot(const CompressArgs& A, hipStream_t st);
 void launch_fibre(const CompressArgs& A, hipStream_t st);
 void launch_cross_dense(const CompressArgs& A, hipStream_t st);
-void launch_cross_lr(const CompressArgs& A, hipStream_t st);
 void launch_final(const CompressArgs& A, hipStream_t st);
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st);
 void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st);
+void launch_face_aca(const CompressArgs& A, hipStream_t st);
+void launch_copy_segments(const char* src, char* dst, const long long* seg, int nseg, hipStream_t st);
+void launch_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax, double* scratch, int* out,
+                       hipStream_t st);
 
 // ---------------------------------------------------------------- apply (apply.hip)
 

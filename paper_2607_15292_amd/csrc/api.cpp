@@ -604,6 +604,23 @@ int bem_compress(bem_ctx* ctx, int32_t op, const bem_aca_opts* opts, bem_op** ou
     });
 }
 
+int bem_aca_matrix(bem_ctx* ctx, int32_t prec, int32_t m, int32_t n, const void* A, double tol, int32_t max_cols,
+                   int32_t* kc, int32_t* kk, void* U, void* V)
+{
+    if (!ctx) return BEM_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        if (m < 1 || n < 1 || (int64_t)m * n > (1 << 22) || (prec != BEM_PREC_F64 && prec != BEM_PREC_MIXED) ||
+            !(tol >= 0) || !A)
+            throw api_error(BEM_ERR_ARG, "bad bem_aca_matrix arguments");
+        need_device(ctx);
+        int c = 0, k = 0;
+        aca_matrix_impl(ctx, prec == BEM_PREC_MIXED, m, n, A, tol, max_cols, &c, &k, U, V);
+        if (kc) *kc = c;
+        if (kk) *kk = k;
+        return BEM_OK;
+    });
+}
+
 int bem_op_stats(const bem_op* op, bem_stats* st)
 {
     if (!op || !st) return BEM_ERR_ARG;

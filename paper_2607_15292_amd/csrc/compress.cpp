@@ -37,6 +37,8 @@ void destroy_compressed(CompressedOp* c) { delete c; }
 namespace {
 
 using Err = ApiError;
+constexpr int KMAX_ACA = 96;       // column capacity of the per-slice ACA scratch
+constexpr size_t ACA_SLOTS = 512;  // faces per launch of the per-slice ACA pass
 
 void build_apply_plan(CompressedOp& C, hipStream_t st)
 {
@@ -133,6 +135,40 @@ ApplyArgs plan_args(const CompressedOp& C, int nrhs)
     return A;
 }
 
+// True when no pair (i, j) of the admissible block d can take the self or a near rule:
+// the boxes of the collocation points (rows) and of the element centroids (columns) are
+// farther apart than near_r2 times the longest edge of any column element.  Same
+// comparison as the pair classification, conservatively on the boxes.
+bool all_pairs_regular(const HostGeo& g, const std::vector<int>& perm, const bem_quad& q, const BlockDesc& d)
+{
+    if (d.rb < d.cb + d.cs && d.cb < d.rb + d.rs) return false;  // shared elements: self pairs
+    if (!q.near_on) return true;
+    double lo[2][3], hi[2][3], l2 = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        const int b0 = s ? d.cb : d.rb, n = s ? d.cs : d.rs;
+        for (int c = 0; c < 3; ++c) {
+            lo[s][c] = 1e300;
+            hi[s][c] = -1e300;
+        }
+        for (int t = 0; t < n; ++t) {
+            const int e = perm[b0 + t];
+            const double x[3] = {g.cx[e], g.cy[e], g.cz[e]};
+            for (int c = 0; c < 3; ++c) {
+                lo[s][c] = std::min(lo[s][c], x[c]);
+                hi[s][c] = std::max(hi[s][c], x[c]);
+            }
+            if (s) l2 = std::max(l2, g.lmax2[e]);
+        }
+    }
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double gap = std::max({0.0, lo[0][c] - hi[1][c], lo[1][c] - hi[0][c]});
+        d2 += gap * gap;
+    }
+    const double r2 = std::max(q.near_r1, q.near_r2);
+    return d2 > 1.0001 * r2 * r2 * l2;
+}
+
 // Upload a host list into the device list buffer at element offset `at`; returns pointer.
 const int* put_list(DevBuf& buf, size_t at, const std::vector<int>& v, hipStream_t st)
 {
@@ -161,30 +197,30 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     const int nb = (int)C->part.blocks.size();
     if (nb >= (1 << 19)) throw Err(BEM_ERR_ARG, "too many blocks for the compression work lists");
     C->blocks.resize(nb);
-    int mmax = 1, nmax = 1, minmax = 1;
-    int64_t n_far = 0, n_lowrank = 0;
+    int mmax = 1, nmax = 1, kmax = 6;
+    int64_t n_far = 0, n_aca = 0;
     int ntiles = 0;
     for (int b = 0; b < nb; ++b) {
         const BlockDesc& d = C->part.blocks[b];
-        int lowrank = d.far && std::min(d.rs, d.cs) > o.far_dense_max;
+        int aca = d.far && std::min(d.rs, d.cs) > o.far_dense_max;
         int nt = (d.rs * d.cs + TILE - 1) / TILE;
         if (nt >= 4096) throw Err(BEM_ERR_ARG, "block too large for the tile lists (raise leaf or lower eta)");
-        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, lowrank, ntiles, nt};
+        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, aca, ntiles, nt, 0};
+        if (d.far) {
+            const bool reg = all_pairs_regular(ctx->hgeo, C->part.perm, ctx->quad, d);
+            C->blocks[b].path = reg ? (C->mixed ? 1 : 2) : (C->mixed ? 3 : 0);
+        }
         ntiles += nt;
         n_far += d.far;
-        if (lowrank) {
-            ++n_lowrank;
+        if (aca) {
+            ++n_aca;
             mmax = std::max(mmax, d.rs);
             nmax = std::max(nmax, d.cs);
-            minmax = std::max(minmax, std::min(d.rs, d.cs));
+            kmax = std::max(kmax, face_aca_cap(d.rs, d.cs));
         }
     }
-    const int kmax = 3 * std::max(2, std::min(64, minmax));
-    const int slots = (int)std::max<int64_t>(1, std::min<int64_t>(n_lowrank, 1024));
-    size_t per_slot = n_lowrank ? aca_scratch_doubles(mmax, nmax, kmax) : 64;
-    per_slot = (per_slot + 31) & ~(size_t)31;
-    DevBuf scratch, aux, st_dev, used_dev, fda_dev, tp_dev, list_dev;
-    scratch.alloc(per_slot * slots * sizeof(double));
+    kmax = std::min(kmax, KMAX_ACA);
+    DevBuf aux, st_dev, used_dev, fda_dev, tp_dev, list_dev;
     C->blocks_dev.alloc(sizeof(BlockIn) * nb);
     BEM_HIP_TRY(hipMemcpyAsync(C->blocks_dev.p, C->blocks.data(), sizeof(BlockIn) * nb, hipMemcpyHostToDevice, st));
     aux.alloc(256);
@@ -195,7 +231,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     used_dev.alloc((size_t)nb * L);
     fda_dev.alloc(sizeof(zd) * 9 * (size_t)nb * L);
     tp_dev.alloc(sizeof(double) * 8 * (size_t)ntiles);
-    list_dev.alloc(sizeof(int) * (3 * (size_t)ntiles + 2 * (size_t)nb + 64));
+    list_dev.alloc(sizeof(int) * std::max<size_t>(3 * (size_t)ntiles + 2 * (size_t)nb + 64, (size_t)n_aca * L + 64));
     // pool: caller-sized, or auto-sized with up to three attempts (growing on overflow)
     size_t pool_bytes = (size_t)o.pool_bytes;
     const bool auto_pool = pool_bytes == 0;
@@ -207,19 +243,21 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         pool_bytes = (size_t)std::min(0.45 * (double)fr, want);
     }
     BEM_HIP_TRY(hipStreamSynchronize(st));
-    hipEvent_t ev0, ev1;
+    hipEvent_t ev0, ev1, ev2;
     BEM_HIP_TRY(hipEventCreate(&ev0));
     BEM_HIP_TRY(hipEventCreate(&ev1));
-    float kms = 0.f;
+    BEM_HIP_TRY(hipEventCreate(&ev2));
+    float kms = 0.f, aca_ms = 0.f;
     int err = 0;
     std::vector<BlockState>& S = C->st;
     S.resize(nb);
+    CompressArgs A;
     for (int attempt = 0;; ++attempt) {
         C->pool.release();
         C->pool.alloc(pool_bytes);
         BEM_HIP_TRY(hipMemsetAsync(aux.p, 0, 256, st));
         BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
-        CompressArgs A;
+        A = CompressArgs{};
         A.c = ctx->devctx(C->geo.geo, C->perm_dev.as<int>());
         A.op = op;
         A.mixed = C->mixed;
@@ -239,60 +277,49 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         A.pool_cap = pool_bytes;
         A.pool_top = top_dev;
         A.err = err_dev;
-        A.scratch = scratch.as<double>();
-        A.scratch_per_slot = per_slot;
+        A.scratch = nullptr;
+        A.scratch_per_slot = 0;
         A.eps3d = o.eps3d;
         A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
         A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
         BEM_HIP_TRY(hipEventRecord(ev0, st));
         launch_init(A, st);
-        std::vector<int> dense_tiles, lr_blocks, lr_tiles, act;
+        // phase A: 3D-ACA of every block on dense residual faces, one step d per pass
+        std::vector<int> tiles, act;
         for (int d = 0; d < L; ++d) {
             BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
             BEM_HIP_TRY(hipStreamSynchronize(st));
-            dense_tiles.clear();
-            lr_blocks.clear();
-            lr_tiles.clear();
+            tiles.clear();
             act.clear();
-            for (int b = 0; b < nb; ++b) {
-                if (!S[b].active) continue;
-                const BlockIn& B = C->blocks[b];
-                act.push_back(b);
-                std::vector<int>& tl = B.lowrank ? lr_tiles : dense_tiles;
-                for (int t = 0; t < B.ntile; ++t) tl.push_back((b << 12) | t);
-                if (B.lowrank) lr_blocks.push_back(b);
+            // tiles grouped by face-kernel path (one instantiation per group)
+            size_t pstart[5] = {0, 0, 0, 0, 0};
+            for (int path = 0; path < 4; ++path) {
+                pstart[path] = tiles.size();
+                for (int b = 0; b < nb; ++b) {
+                    const BlockIn& B = C->blocks[b];
+                    if (!S[b].active || B.path != path) continue;
+                    for (int t = 0; t < B.ntile; ++t) tiles.push_back((b << 12) | t);
+                }
             }
+            pstart[4] = tiles.size();
+            for (int b = 0; b < nb; ++b)
+                if (S[b].active) act.push_back(b);
             if (act.empty()) break;
-            size_t at = 0;
-            const int* p_dense = put_list(list_dev, at, dense_tiles, st);
-            at += dense_tiles.size();
-            const int* p_lrb = put_list(list_dev, at, lr_blocks, st);
-            at += lr_blocks.size();
-            const int* p_lrt = put_list(list_dev, at, lr_tiles, st);
-            at += lr_tiles.size();
-            const int* p_act = put_list(list_dev, at, act, st);
+            const int* p_tiles = put_list(list_dev, 0, tiles, st);
+            const int* p_act = put_list(list_dev, tiles.size(), act, st);
             A.d = d;
-            A.list = p_dense;
-            A.nlist = (int)dense_tiles.size();
-            launch_face_dense(A, st);
-            for (size_t c0 = 0; c0 < lr_blocks.size(); c0 += (size_t)slots) {
-                A.list = p_lrb + c0;
-                A.nlist = (int)std::min<size_t>((size_t)slots, lr_blocks.size() - c0);
-                launch_aca(A, st);
+            for (int path = 0; path < 4; ++path) {
+                A.list = p_tiles + pstart[path];
+                A.nlist = (int)(pstart[path + 1] - pstart[path]);
+                launch_face_dense(A, path, st);
             }
-            A.list = p_lrt;
-            A.nlist = (int)lr_tiles.size();
-            launch_scan_lr(A, st);
             A.list = p_act;
             A.nlist = (int)act.size();
             launch_pivot(A, st);
             launch_fibre(A, st);
-            A.list = p_dense;
-            A.nlist = (int)dense_tiles.size();
+            A.list = p_tiles;
+            A.nlist = (int)tiles.size();
             launch_cross_dense(A, st);
-            A.list = p_lrb;
-            A.nlist = (int)lr_blocks.size();
-            launch_cross_lr(A, st);
             A.list = p_act;
             A.nlist = (int)act.size();
             launch_final(A, st);
@@ -318,9 +345,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
                 launch_fallback_faces(A, kf, st);
             }
         }
-        BEM_HIP_TRY(hipEventRecord(ev1, st));
         BEM_HIP_TRY(hipStreamSynchronize(st));
-        BEM_HIP_TRY(hipEventElapsedTime(&kms, ev0, ev1));
         unsigned long long top = 0;
         BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
         BEM_HIP_TRY(hipMemcpy(&top, top_dev, sizeof(top), hipMemcpyDeviceToHost));
@@ -328,6 +353,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         if (!auto_pool || attempt >= 2) {
             (void)hipEventDestroy(ev0);
             (void)hipEventDestroy(ev1);
+            (void)hipEventDestroy(ev2);
             throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes overflowed (" +
                                          std::to_string(top) + " requested); raise pool_bytes");
         }
@@ -336,11 +362,89 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
         pool_bytes = (size_t)std::min(0.85 * (double)fr, 2.5 * (double)top + (double)(1 << 28));
     }
+    BEM_HIP_TRY(hipMemcpy(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost));
+    // phase B: per-slice ACA + recompression of the far faces of the ACA blocks, in place
+    std::vector<int> items;
+    for (int b = 0; b < nb; ++b)
+        if (C->blocks[b].aca && !S[b].fallback)
+            for (int d = 0; d < S[b].rank; ++d) items.push_back((b << 8) | d);
+    BEM_HIP_TRY(hipEventRecord(ev1, st));
+    if (!items.empty()) {
+        const int slots = (int)std::min<size_t>(items.size(), ACA_SLOTS);
+        size_t per_slot = (aca_scratch_doubles(mmax, nmax, kmax) + 31) & ~(size_t)31;
+        DevBuf scratch;
+        scratch.alloc(per_slot * slots * sizeof(double));
+        A.scratch = scratch.as<double>();
+        A.scratch_per_slot = per_slot;
+        const int* p_items = put_list(list_dev, 0, items, st);
+        for (size_t c0 = 0; c0 < items.size(); c0 += (size_t)slots) {
+            A.list = p_items + c0;
+            A.nlist = (int)std::min<size_t>((size_t)slots, items.size() - c0);
+            launch_face_aca(A, st);
+        }
+        BEM_HIP_TRY(hipStreamSynchronize(st));
+    }
+    BEM_HIP_TRY(hipEventRecord(ev2, st));
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    BEM_HIP_TRY(hipEventElapsedTime(&kms, ev0, ev2));
+    BEM_HIP_TRY(hipEventElapsedTime(&aca_ms, ev1, ev2));
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
+    (void)hipEventDestroy(ev2);
     BEM_HIP_TRY(hipMemcpy(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost));
     C->faces.resize((size_t)nb * L);
     BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L, hipMemcpyDeviceToHost));
+
+    // phase C: compaction of the kept faces, factors and fibres into a pool of exact size
+    {
+        auto face_bytes = [&](const FaceDesc& f, const BlockIn& B) -> long long {
+            const long long zs = f.fp32 ? (long long)sizeof(zf) : (long long)sizeof(zd);
+            if (f.kk == 0) return zs * 9 * B.rs * B.cs;
+            if (f.kk > 0) return zs * 3 * (B.rs + B.cs) * f.kk;
+            return 0;
+        };
+        auto up256 = [](long long v) { return (v + 255) & ~255LL; };
+        std::vector<long long> seg;
+        long long top = 0;
+        for (int b = 0; b < nb; ++b) {
+            const BlockIn& B = C->blocks[b];
+            for (int d = 0; d < S[b].rank; ++d) {
+                FaceDesc& f = C->faces[(size_t)b * L + d];
+                const long long fb = face_bytes(f, B);
+                if (fb > 0) {
+                    seg.insert(seg.end(), {f.face_off, top, fb});
+                    f.face_off = top;
+                    top = up256(top + fb);
+                }
+                const long long nbf = (long long)sizeof(zd) * 9 * L;
+                seg.insert(seg.end(), {f.fib_off, top, nbf});
+                f.fib_off = top;
+                top = up256(top + nbf);
+            }
+        }
+        DevBuf np, segd;
+        bool ok = true;
+        try {
+            np.alloc(std::max<long long>(top, 256));
+            segd.alloc(std::max<size_t>(seg.size(), 3) * sizeof(long long));
+        } catch (const DevBuf::bem_nomem&) {
+            ok = false;  // not enough memory for the copy: keep the working pool
+        }
+        if (ok) {
+            const int nseg = (int)(seg.size() / 3);
+            if (nseg) {
+                BEM_HIP_TRY(hipMemcpyAsync(segd.p, seg.data(), seg.size() * sizeof(long long), hipMemcpyHostToDevice, st));
+                launch_copy_segments(C->pool.as<char>(), np.as<char>(), segd.as<long long>(), nseg, st);
+            }
+            BEM_HIP_TRY(hipStreamSynchronize(st));
+            C->pool.swap(np);
+            np.release();
+        } else {
+            BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L,
+                                  hipMemcpyDeviceToHost));
+        }
+    }
+    C->faces_dev.release();
     build_apply_plan(*C, st);
 
     // statistics
@@ -350,7 +454,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.n_far = n_far;
     R.n_near = nb - n_far;
     R.rank_min = L + 1;
-    double rsum = 0, acasum = 0;
+    double rsum = 0, acasum = 0, colsum = 0;
     int64_t nfarfaces = 0, bytes = 0, ent = 0;
     for (int b = 0; b < nb; ++b) {
         const BlockState& s = S[b];
@@ -360,6 +464,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         R.rank_max = std::max(R.rank_max, s.rank);
         rsum += s.rank;
         ent += s.entries;
+        R.n_aca_dense += s.aca_dense;
+        colsum += (double)s.aca_cols;
         for (int d = 0; d < s.rank; ++d) {
             const FaceDesc& f = C->faces[(size_t)b * L + d];
             bytes += (int64_t)L * 9 * sizeof(zd);
@@ -376,13 +482,43 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     }
     R.rank_mean = nb ? rsum / nb : 0.0;
     R.aca_rank_mean = nfarfaces ? acasum / nfarfaces : 0.0;
+    R.aca_cols_mean = nfarfaces ? colsum / nfarfaces : 0.0;
     R.bytes = bytes;
     R.compression_rate = (double)bytes / ((double)L * 9.0 * (double)K * (double)K * 16.0);
     R.entries_generated = ent;
     R.n_far_faces = nfarfaces;
     R.kernel_ms = kms;
+    R.aca_ms = aca_ms;
     R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BEM_OK;
+}
+
+void aca_matrix_impl(bem_ctx* ctx, bool fp32, int m, int n, const void* A, double tol, int max_cols, int* kc, int* kk,
+                     void* U, void* V)
+{
+    hipStream_t st = ctx->stream;
+    int cap = max_cols > 0 ? max_cols : face_aca_cap(m, n);
+    cap = std::min({cap, 3 * std::min(m, n), KMAX_ACA});
+    cap -= cap % 3;
+    const int kmax = std::max(cap, 3);
+    const size_t zs = fp32 ? sizeof(zf) : sizeof(zd);
+    const size_t bytes = zs * 9 * (size_t)m * n;
+    DevBuf h, scratch, out;
+    h.alloc(bytes);
+    scratch.alloc(((aca_scratch_doubles(m, n, kmax) + 31) & ~(size_t)31) * sizeof(double));
+    out.alloc(64);
+    BEM_HIP_TRY(hipMemcpyAsync(h.p, A, bytes, hipMemcpyHostToDevice, st));
+    launch_aca_matrix(h.as<char>(), m, n, fp32 ? 1 : 0, tol, cap, kmax, scratch.as<double>(), out.as<int>(), st);
+    int r[2] = {0, 0};
+    BEM_HIP_TRY(hipMemcpyAsync(r, out.p, sizeof(r), hipMemcpyDeviceToHost, st));
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    *kc = r[0];
+    *kk = r[1];
+    if (r[1] > 0) {
+        const size_t ub = zs * 3 * (size_t)m * r[1], vb = zs * 3 * (size_t)n * r[1];
+        if (U) BEM_HIP_TRY(hipMemcpy(U, h.p, ub, hipMemcpyDeviceToHost));
+        if (V) BEM_HIP_TRY(hipMemcpy(V, h.as<char>() + ub, vb, hipMemcpyDeviceToHost));
+    }
 }
 
 void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride, zd* y_dev, hipStream_t st)

@@ -4,6 +4,7 @@
 
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/bem.h"
@@ -45,6 +46,11 @@ struct DevBuf {
         bytes = 0;
     }
     template <typename T> T* as() const { return (T*)p; }
+    void swap(DevBuf& o)
+    {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
     struct bem_nomem : std::runtime_error {
         explicit bem_nomem(size_t n) : std::runtime_error("device allocation of " + std::to_string(n) + " bytes failed") {}
     };
@@ -127,6 +133,8 @@ struct bem_op {
 
 namespace bem {
 int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out);
+void aca_matrix_impl(bem_ctx* ctx, bool fp32, int m, int n, const void* A, double tol, int max_cols, int* kc, int* kk,
+                     void* U, void* V);
 void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride, zd* y_dev, hipStream_t st);
 void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream_t st);
 void compressed_blocks(const bem_op* op, int64_t* n, int64_t* rows, int32_t* perm);

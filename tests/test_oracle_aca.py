@@ -41,13 +41,13 @@ def test_exact_rank_recovery(r):
     assert err < 1e-12
 
 
-def _kernel_block(L=16, op=oracle.OP_V):
-    X, T = workloads.cube_grid(4, 1.0)
+def _kernel_block(L=16, op=oracle.OP_V, grid=4, nr=12, nc=10):
+    X, T = workloads.cube_grid(grid, 1.0)
     s = workloads.bdf2_contour(L, 0.1)
     P = oracle.Problem(X, T, s)
     C = X[T].mean(axis=1)
-    rows = np.flatnonzero(C[:, 0] < -0.99)[:12]      # on the -x face
-    cols = np.flatnonzero(C[:, 0] > 0.99)[:10]       # on the +x face
+    rows = np.flatnonzero(C[:, 0] < -0.99)[:nr]      # on the -x face
+    cols = np.flatnonzero(C[:, 0] > 0.99)[:nc]       # on the +x face
     ii, jj, ll = np.meshgrid(rows, cols, np.arange(L), indexing="ij")
     E = P.entries(op, ii.ravel(), jj.ravel(), ll.ravel()).reshape(len(rows), len(cols), L, 3, 3)
     return E.transpose(2, 0, 1, 3, 4).copy()
@@ -93,8 +93,8 @@ def test_aca_exact_low_rank_and_recompression():
     m, n, r = 20, 15, 6  # matrix-valued ACA captures rank in steps of 3
     A = (rng.standard_normal((3 * m, r)) + 1j * rng.standard_normal((3 * m, r))) @ \
         (rng.standard_normal((r, 3 * n)) + 1j * rng.standard_normal((r, 3 * n)))
-    U, V = A3.aca_matrix(A, 1e-12)
-    assert U.shape[1] == r
+    U, V, ok = A3.aca_matrix(A, 1e-12 * np.linalg.norm(A))
+    assert ok and U.shape[1] == r
     assert np.linalg.norm(U @ V.conj().T - A) < 1e-10 * np.linalg.norm(A)
     # recompression of a redundant factorisation (rank 4 written with 9 columns)
     B = rng.standard_normal((3 * m, 4)) + 1j * rng.standard_normal((3 * m, 4))
@@ -102,24 +102,58 @@ def test_aca_exact_low_rank_and_recompression():
     mix = rng.standard_normal((4, 9))
     U9, V9 = B @ mix, Cm @ np.linalg.pinv(mix).conj().T
     M = U9 @ V9.conj().T
-    Ub, Vb = A3.recompress(U9, V9, 1e-10)
+    Ub, Vb = A3.recompress(U9, V9, 1e-10 * np.linalg.norm(M))
     assert Ub.shape[1] == 4
     assert np.linalg.norm(Ub @ Vb.conj().T - M) < 1e-10 * np.linalg.norm(M)
 
 
 def test_aca_on_kernel_face_meets_tolerance():
-    C = _kernel_block(L=4)
+    C = _kernel_block(L=4, grid=8, nr=48, nc=40)
     Amat = A3.blocks_to_matrix(C[0])
     for eps in (1e-4, 1e-8):
-        U, V = A3.aca_matrix(Amat, eps)
-        Ub, Vb = A3.recompress(U, V, eps)
+        tol = eps * np.linalg.norm(Amat)
+        U, V, ok = A3.aca_matrix(Amat, tol)
+        assert ok
+        Ub, Vb = A3.recompress(U, V, tol)
         err = np.linalg.norm(Ub @ Vb.conj().T - Amat) / np.linalg.norm(Amat)
         assert err < 20 * eps
         assert Ub.shape[1] <= U.shape[1]
 
 
 def test_aca3d_with_aca_faces_error():
-    C = _kernel_block()
-    ap = A3.aca3d(C, 1e-6, face_approx=A3.aca_face(1e-8))
+    """The ACA pass over the faces (tol_d = eps_aca ||C|| / ||f_d||) keeps the tensor error
+    within a small multiple of eps + rank * eps_aca, and every face it keeps as factors
+    takes less memory than the dense face."""
+    C = _kernel_block(L=16, grid=8, nr=48, nc=40)
+    ap = A3.aca3d(C, 1e-4)
+    exact = ap.tensor()
+    A3.compress_faces(ap, 1e-6)
+    nf = sum(uv is not None for uv in ap.factors)
+    assert nf > 0
+    m, n = C.shape[1:3]
+    for uv in ap.factors:
+        if uv is not None:
+            assert uv[0].shape[1] * (m + n) < 3 * m * n
     err = np.linalg.norm(ap.tensor() - C) / np.linalg.norm(C)
-    assert err < 1e-5
+    assert err < 1e-3
+    # each face-fibre term moves by at most about eps_aca ||C||
+    dev = np.linalg.norm(ap.tensor() - exact) / np.linalg.norm(C)
+    assert dev < 2e-6 * ap.rank
+
+
+def test_aca_cap_and_failure_rules():
+    """A full-rank face does not resolve within a small column cap (ok False: kept dense);
+    an all-zero face is kept dense; the cap is twice the break-even rank."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((30, 24)) + 1j * rng.standard_normal((30, 24))
+    U, V, ok = A3.aca_matrix(A, 1e-12 * np.linalg.norm(A), max_cols=9)
+    assert not ok and U.shape[1] == 9
+    U, V, ok = A3.aca_matrix(A, 1e-12 * np.linalg.norm(A))
+    assert ok and np.linalg.norm(U @ V.conj().T - A) < 1e-9 * np.linalg.norm(A)
+    assert A3.compress_face(np.zeros((4, 5, 3, 3), complex), 1.0) == (None, -1)
+    assert A3.face_aca_cap(80, 80) == 240 and A3.face_aca_cap(160, 80) == 240
+    assert A3.face_aca_cap(2, 2) == 6  # at most 3 min(m, n)
+    # factors that would not save memory are dropped: random 10 x 10 blocks need full rank
+    H = A3.matrix_to_blocks(rng.standard_normal((30, 30)) + 1j * rng.standard_normal((30, 30)))
+    uv, kc = A3.compress_face(H, 1e-10)
+    assert uv is None
