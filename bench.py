@@ -29,11 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "kernel entries/s and all-frequency H-matvecs/s at 1e-6 rel err; mixed vs FP64 speedup"
-# Algorithmic flops of one kernel evaluation (one quadrature point, one frequency) of the
-# regular rule, counted from the formulas: U -> 125, T -> 236.
-FLOPS_EVAL = {0: 125.0, 2: 236.0}
-QPTS_REGULAR = 7
-PEAK_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, non-packed FP32)
+PEAK_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: FP64 and non-packed FP32
 
 
 def log(*a):
@@ -95,6 +91,8 @@ def main():
             op = c.compress(opk, eps3d=args.eps, leaf=64, eta=1.5, prec=prec, pool_bytes=pool)
             y = op.apply(x)
             st.append(op.stats())
+            log("  op %d prec %d: compress %.0f ms (faces %.0f ms, per-slice ACA %.0f ms), rate %.4f"
+                % (opk, prec, st[-1]["kernel_ms"], st[-1]["face_ms"], st[-1]["aca_ms"], st[-1]["compression_rate"]))
             if measure:
                 torch.cuda.synchronize()
                 ys.append(y.cpu().numpy())
@@ -142,13 +140,17 @@ def main():
         fp64 = {"sec_per_step": t3 - t2, "stats": st_d, "apply_ms": dict(zip(ops_list, ams_d)), "ys": ys_d}
         log("fp64 step %.3f s" % (t3 - t2))
 
-    # roofline of the compression kernel (one launch per operator)
-    kern_ms = sum(v["kernel_ms"] for v in st_m)
-    flops = sum(v["entries_generated"] * QPTS_REGULAR * FLOPS_EVAL[opk] for v, opk in zip(st_m, ops_list))
-    achieved = flops / (kern_ms * 1e-3)
+    # roofline of the dominant kernel: the face kernels of the 3D-ACA steps (k_face_dense),
+    # algorithmic flops over their event-timed device time, summed over the timed steps
+    face_ms = sum(v["face_ms"] for stp in stats_steps for v in stp)
+    face_flop = sum(v["face_flop"] for stp in stats_steps for v in stp)
+    launches = sum(v["face_launches"] for stp in stats_steps for v in stp)
+    achieved = face_flop / (face_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_VALU, "traffic": None,
-                "kernel": "k_aca3d (compression, one launch per operator)", "kernel_ms": kern_ms}
+                "kernel": "k_face_dense (3D-ACA face kernels, all instantiations)",
+                "launches": launches, "avg_launch_ms": face_ms / max(launches, 1),
+                "flop_per_launch": face_flop / max(launches, 1)}
 
     # CPU baseline (oracle) on sampled rows; its results are also the accuracy reference
     cpu = None
@@ -198,8 +200,10 @@ def main():
         "hmatvecs_per_s": hmv,
         "matvecs_per_s_single_freq": {k: v * L for k, v in hmv.items()},
         "compress_stats": [{k: v[k] for k in ("n_blocks", "n_near", "n_far", "n_dense_fallback", "rank_mean",
-                                               "rank_max", "aca_rank_mean", "aca_rank_max", "compression_rate",
-                                               "entries_generated", "kernel_ms")} for v in st_m],
+                                               "rank_max", "aca_rank_mean", "aca_rank_max", "aca_cols_mean",
+                                               "n_far_faces", "n_aca_dense", "compression_rate",
+                                               "entries_generated", "kernel_ms", "face_ms", "aca_ms")}
+                           for v in st_m],
         "rel_err": errs,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -127,6 +127,13 @@ typedef struct {
     double aca_cols_mean;         /* ACA columns before recompression, mean over the faces
                                      stored as factors */
     double aca_ms;                /* device time of the per-slice ACA + recompression pass */
+    double face_ms;               /* device time of the face kernels of the 3D-ACA steps (HIP
+                                     events around each step's face launches) */
+    int64_t face_launches;        /* face kernel launches */
+    int64_t face_pairs;           /* (i, j) pairs generated by the face kernels */
+    double face_flop;             /* algorithmic flops of the face kernels: per pair of step d,
+                                     7 regular-rule kernel evaluations (125 flops for U, 236 for
+                                     T) and d residual updates (216 flops) */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -176,7 +176,7 @@ __device__ __forceinline__ double block_eps(const CompressArgs& A, const BlockIn
 
 __device__ __forceinline__ long long dense_face_bytes(const CompressArgs& A, const BlockIn& B)
 {
-    size_t zs = (A.mixed && B.far) ? sizeof(zf) : sizeof(zd);
+    size_t zs = B.f32 ? sizeof(zf) : sizeof(zd);
     return ((long long)zs * 9 * B.rs * B.cs + 15) & ~15LL;
 }
 
@@ -193,7 +193,7 @@ __device__ bool alloc_step(const CompressArgs& A, int b, int d, int k)
     f.kk = 0;
     f.k = k;
     f.sel = 0;
-    f.fp32 = (A.mixed && B.far) ? 1 : 0;
+    f.fp32 = B.f32;
     A.faces[(size_t)b * A.L + d] = f;
     return true;
 }
@@ -278,6 +278,21 @@ __device__ __forceinline__ void sub_residual_t(blk& E, const char* pool, const F
     }
 }
 
+// pair number p of lane `lane` in tile t of block B, or -1
+__device__ __forceinline__ int tile_pair(const CompressArgs& A, const BlockIn& B, int t, int lane)
+{
+    const int mn = B.rs * B.cs;
+    int q;
+    if (t < B.ntr) {
+        q = t * TILE + lane;
+        if (q >= B.nreg) return -1;
+    } else {
+        q = B.nreg + (t - B.ntr) * TILE + lane;
+        if (q >= mn) return -1;
+    }
+    return B.pair0 < 0 ? q : A.pairs[B.pair0 + q];
+}
+
 // tile partials: [0] sigma_3 max, [1] pivot pair, [2] sum |H|^2, [3] max block |H|^2,
 //                [4] cross re, [5] t_dd re
 template <int KOP, int PATH>
@@ -293,10 +308,10 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
     const int k = A.st[b].k;
     const FaceDesc* fd = A.faces + (size_t)b * A.L;
     const FaceDesc F = fd[d];
-    const int p = t * TILE + threadIdx.x;
+    const int p = tile_pair(A, B, t, threadIdx.x);
     double s3 = -1.0, e2 = 0.0;
     int pi = 0x7fffffff;
-    if (p < m * n) {
+    if (p >= 0) {
         const int i = p / n, j = p - (p / n) * n;
         blk E = pair_entry<KOP, PATH>(A, B.rb + i, B.cb + j, k);
         sub_residual_t<F32>(E, A.pool, fd, d, n, i, j, k);
@@ -333,8 +348,19 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
         tp[1] = (double)pi;
         tp[2] = v[0];
         tp[3] = fm;
-        int cnt = min(TILE, m * n - t * TILE);
-        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)cnt);
+        const int cnt = t < B.ntr ? min(TILE, B.nreg - t * TILE) : min(TILE, m * n - B.nreg - (t - B.ntr) * TILE);
+        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(cnt, 0));
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_classify(DevCtx c, const BlockIn* blocks, const int* list,
+                                                 const long long* off, unsigned char* cls)
+{
+    const BlockIn B = blocks[list[blockIdx.x]];
+    unsigned char* o = cls + off[blockIdx.x];
+    for (int p = threadIdx.x; p < B.rs * B.cs; p += WG) {
+        const int i = p / B.cs, j = p - i * B.cs;
+        o[p] = (unsigned char)pair_class(c.geo, B.rb + i, B.cb + j, c.qt);
     }
 }
 
@@ -1415,7 +1441,7 @@ __global__ __launch_bounds__(64) void k_fallback_alloc(CompressArgs A, int kf)
     f.kk = off < 0 ? -1 : 0;
     f.k = kf;
     f.sel = 1;
-    f.fp32 = (A.mixed && B.far) ? 1 : 0;
+    f.fp32 = B.f32;
     A.faces[(size_t)b * A.L + kf] = f;
     if (off >= 0) {
         zd* fib = (zd*)(A.pool + f.fib_off);
@@ -1451,7 +1477,7 @@ __global__ __launch_bounds__(WG) void k_fallback_face(CompressArgs A, int kf)
         }
     }
     if (threadIdx.x == 0)
-        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)min(TILE, m * n - t * TILE));
+        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(TILE, m * n - t * TILE)));
 }
 
 // the same pass on one given matrix: out[0] = ACA columns, out[1] = kk
@@ -1526,6 +1552,11 @@ void launch_face_aca(const CompressArgs& A, hipStream_t st)
 {
     BEM_LAUNCH(k_face_aca, A.nlist, WG, A);
     BEM_LAUNCH(k_face_recomp, A.nlist, WG, A);
+}
+void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
+                     unsigned char* cls, hipStream_t st)
+{
+    BEM_LAUNCH(k_classify, n, WG, c, blocks, list, off, cls);
 }
 void launch_pivot(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_pivot, (A.nlist + 63) / 64, 64, A); }
 void launch_fibre(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_fibre, A.nlist, WG, A); }

@@ -9,13 +9,18 @@ namespace bem {
 constexpr int MAX_L = 256;  // largest number of frequencies of one compression
 constexpr int TILE = 256;   // pairs (i, j) per workgroup in the tiled phases
 
+// Pairs (i, j) of a block are numbered p = i * cs + j.  The face kernels take them in
+// tiles of TILE: the first ntr tiles hold the nreg pairs of the regular rule, the others the
+// remaining pairs (near and self rules, sorted by class), so that a wavefront runs one rule.
 struct BlockIn {
     int rb, rs, cb, cs;  // rows [rb, rb + rs), columns [cb, cb + cs) in cluster order
     int far;             // admissible (far field): the mixed path computes it in FP32
     int aca;             // faces compressed by the per-slice ACA + recompression pass
     int tile0, ntile;    // range of this block's pair tiles
-    int path;            // face kernel: 0 any pair class FP64, 1 / 2 all pairs regular FP32 / FP64,
-                         // 3 any pair class with FP32 regular pairs (mixed far field)
+    int ntr, nreg;       // tiles of regular pairs, number of regular pairs
+    int pair0;           // offset of the block's pair order in the pair list; -1: p = position
+                         // (every pair regular)
+    int f32;             // faces stored in complex64 (admissible block, mixed path)
 };
 
 // One face-fibre pair of a block.  kk == 0: dense face (3m x 3n row-major at face_off,
@@ -73,6 +78,7 @@ struct CompressArgs {
     int* err;
     double* scratch;
     size_t scratch_per_slot;  // doubles
+    const int* pairs;       // pair orders of the blocks with pair0 >= 0
     double eps3d, eps3d_far, eps_aca_far;
 };
 
@@ -87,8 +93,12 @@ __host__ __device__ inline int face_aca_cap(int m, int n)
 
 size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
 void launch_init(const CompressArgs& A, hipStream_t st);
-// all listed tiles belong to blocks of the given face-kernel path (BlockIn::path)
+// path: 0 general pairs FP64, 1 / 2 regular pairs FP32 / FP64, 3 general pairs with FP32
+// regular rule and complex64 faces; every listed tile must be of that kind
 void launch_face_dense(const CompressArgs& A, int path, hipStream_t st);
+// cls[off[q] + p] = pair class of pair p of block list[q] (one workgroup per listed block)
+void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
+                     unsigned char* cls, hipStream_t st);
 void launch_pivot(const CompressArgs& A, hipStream_t st);
 void launch_fibre(const CompressArgs& A, hipStream_t st);
 void launch_cross_dense(const CompressArgs& A, hipStream_t st);

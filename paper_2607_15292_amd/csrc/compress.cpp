@@ -38,6 +38,13 @@ namespace {
 
 using Err = ApiError;
 constexpr int KMAX_ACA = 96;       // column capacity of the per-slice ACA scratch
+// Algorithmic flop counts of the face kernels: one kernel evaluation at one quadrature
+// point (distance, A and B or A', B', the tensor terms; complex mul = 6, add = 2, exp /
+// sin / cos counted as one flop each), and one residual update H_a[i,j] f_a[k] (27 complex
+// multiply-adds = 216 flops).
+constexpr double QPTS_REGULAR = 7.0;
+constexpr double FLOPS_RESIDUAL = 216.0;
+double flops_eval(int op) { return op == BEM_OP_V ? 125.0 : (op == BEM_OP_TABLE ? 0.0 : 236.0); }
 constexpr size_t ACA_SLOTS = 512;  // faces per launch of the per-slice ACA pass
 
 void build_apply_plan(CompressedOp& C, hipStream_t st)
@@ -200,17 +207,14 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     int mmax = 1, nmax = 1, kmax = 6;
     int64_t n_far = 0, n_aca = 0;
     int ntiles = 0;
+    std::vector<int> cls_blocks;  // blocks with near or self pairs: classified on the device
     for (int b = 0; b < nb; ++b) {
         const BlockDesc& d = C->part.blocks[b];
-        int aca = d.far && std::min(d.rs, d.cs) > o.far_dense_max;
-        int nt = (d.rs * d.cs + TILE - 1) / TILE;
-        if (nt >= 4096) throw Err(BEM_ERR_ARG, "block too large for the tile lists (raise leaf or lower eta)");
-        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, aca, ntiles, nt, 0};
-        if (d.far) {
-            const bool reg = all_pairs_regular(ctx->hgeo, C->part.perm, ctx->quad, d);
-            C->blocks[b].path = reg ? (C->mixed ? 1 : 2) : (C->mixed ? 3 : 0);
-        }
-        ntiles += nt;
+        const int aca = d.far && std::min(d.rs, d.cs) > o.far_dense_max;
+        const int f32 = C->mixed && d.far;
+        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, aca, 0, 0, 0, d.rs * d.cs, -1, f32};
+        const bool reg = op == BEM_OP_TABLE || (d.far && all_pairs_regular(ctx->hgeo, C->part.perm, ctx->quad, d));
+        if (!reg) cls_blocks.push_back(b);
         n_far += d.far;
         if (aca) {
             ++n_aca;
@@ -218,6 +222,53 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             nmax = std::max(nmax, d.cs);
             kmax = std::max(kmax, face_aca_cap(d.rs, d.cs));
         }
+    }
+    // pair orders: regular pairs first, then the near and self pairs sorted by class
+    DevBuf pairs_dev;
+    std::vector<int> pair_order;
+    if (!cls_blocks.empty()) {
+        std::vector<long long> off(cls_blocks.size() + 1, 0);
+        for (size_t q = 0; q < cls_blocks.size(); ++q) {
+            const BlockIn& B = C->blocks[cls_blocks[q]];
+            off[q + 1] = off[q] + (long long)B.rs * B.cs;
+        }
+        DevBuf cls_d, off_d, lst_d;
+        cls_d.alloc(std::max<long long>(off.back(), 16));
+        off_d.alloc(sizeof(long long) * off.size());
+        lst_d.alloc(sizeof(int) * cls_blocks.size());
+        C->blocks_dev.alloc(sizeof(BlockIn) * nb);
+        BEM_HIP_TRY(hipMemcpyAsync(C->blocks_dev.p, C->blocks.data(), sizeof(BlockIn) * nb, hipMemcpyHostToDevice, st));
+        BEM_HIP_TRY(hipMemcpyAsync(off_d.p, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice, st));
+        BEM_HIP_TRY(hipMemcpyAsync(lst_d.p, cls_blocks.data(), sizeof(int) * cls_blocks.size(), hipMemcpyHostToDevice, st));
+        launch_classify(ctx->devctx(C->geo.geo, C->perm_dev.as<int>()), C->blocks_dev.as<BlockIn>(), lst_d.as<int>(),
+                        off_d.as<long long>(), (int)cls_blocks.size(), cls_d.as<unsigned char>(), st);
+        std::vector<unsigned char> cls(off.back());
+        BEM_HIP_TRY(hipMemcpyAsync(cls.data(), cls_d.p, cls.size(), hipMemcpyDeviceToHost, st));
+        BEM_HIP_TRY(hipStreamSynchronize(st));
+        pair_order.reserve(off.back());
+        for (size_t q = 0; q < cls_blocks.size(); ++q) {
+            BlockIn& B = C->blocks[cls_blocks[q]];
+            const unsigned char* c = cls.data() + off[q];
+            const int mn = B.rs * B.cs;
+            if ((long long)pair_order.size() + mn >= (1LL << 31)) throw Err(BEM_ERR_ARG, "pair list too long");
+            B.pair0 = (int)pair_order.size();
+            for (int k = 0; k < 4; ++k)
+                for (int p = 0; p < mn; ++p)
+                    if (c[p] == k) pair_order.push_back(p);
+            B.nreg = 0;
+            for (int p = 0; p < mn; ++p) B.nreg += c[p] == 0;
+        }
+        pairs_dev.alloc(sizeof(int) * pair_order.size());
+        BEM_HIP_TRY(hipMemcpyAsync(pairs_dev.p, pair_order.data(), sizeof(int) * pair_order.size(),
+                                   hipMemcpyHostToDevice, st));
+    }
+    for (int b = 0; b < nb; ++b) {
+        BlockIn& B = C->blocks[b];
+        B.ntr = (B.nreg + TILE - 1) / TILE;
+        B.ntile = B.ntr + (B.rs * B.cs - B.nreg + TILE - 1) / TILE;
+        if (B.ntile >= 4096) throw Err(BEM_ERR_ARG, "block too large for the tile lists (raise leaf or lower eta)");
+        B.tile0 = ntiles;
+        ntiles += B.ntile;
     }
     kmax = std::min(kmax, KMAX_ACA);
     DevBuf aux, st_dev, used_dev, fda_dev, tp_dev, list_dev;
@@ -243,10 +294,14 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         pool_bytes = (size_t)std::min(0.45 * (double)fr, want);
     }
     BEM_HIP_TRY(hipStreamSynchronize(st));
-    hipEvent_t ev0, ev1, ev2;
+    hipEvent_t ev0, ev1, ev2, evf0, evf1;
     BEM_HIP_TRY(hipEventCreate(&ev0));
     BEM_HIP_TRY(hipEventCreate(&ev1));
     BEM_HIP_TRY(hipEventCreate(&ev2));
+    BEM_HIP_TRY(hipEventCreate(&evf0));
+    BEM_HIP_TRY(hipEventCreate(&evf1));
+    double face_ms = 0.0, face_flop = 0.0;
+    int64_t face_launches = 0, face_pairs = 0;
     float kms = 0.f, aca_ms = 0.f;
     int err = 0;
     std::vector<BlockState>& S = C->st;
@@ -279,26 +334,44 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         A.err = err_dev;
         A.scratch = nullptr;
         A.scratch_per_slot = 0;
+        A.pairs = pairs_dev.as<int>();
         A.eps3d = o.eps3d;
         A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
         A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
         BEM_HIP_TRY(hipEventRecord(ev0, st));
         launch_init(A, st);
-        // phase A: 3D-ACA of every block on dense residual faces, one step d per pass
+        // phase A: 3D-ACA of every block on dense residual faces, one step d per pass; the
+        // face kernels of each step are bracketed by events (read after the next sync)
         std::vector<int> tiles, act;
+        face_ms = 0.0;
+        face_launches = 0;
+        face_pairs = 0;
+        face_flop = 0.0;
+        bool face_pending = false;
         for (int d = 0; d < L; ++d) {
             BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
             BEM_HIP_TRY(hipStreamSynchronize(st));
+            if (face_pending) {
+                float ms = 0.f;
+                BEM_HIP_TRY(hipEventElapsedTime(&ms, evf0, evf1));
+                face_ms += ms;
+                face_pending = false;
+            }
             tiles.clear();
             act.clear();
-            // tiles grouped by face-kernel path (one instantiation per group)
+            // tiles grouped by face-kernel path (one instantiation per group): regular tiles
+            // of complex64 / complex128 blocks -> 1 / 2, the others -> 3 / 0
             size_t pstart[5] = {0, 0, 0, 0, 0};
             for (int path = 0; path < 4; ++path) {
                 pstart[path] = tiles.size();
                 for (int b = 0; b < nb; ++b) {
                     const BlockIn& B = C->blocks[b];
-                    if (!S[b].active || B.path != path) continue;
-                    for (int t = 0; t < B.ntile; ++t) tiles.push_back((b << 12) | t);
+                    if (!S[b].active) continue;
+                    const int preg = B.f32 ? 1 : 2, pgen = B.f32 ? 3 : 0;
+                    if (path == preg)
+                        for (int t = 0; t < B.ntr; ++t) tiles.push_back((b << 12) | t);
+                    if (path == pgen)
+                        for (int t = B.ntr; t < B.ntile; ++t) tiles.push_back((b << 12) | t);
                 }
             }
             pstart[4] = tiles.size();
@@ -308,11 +381,19 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             const int* p_tiles = put_list(list_dev, 0, tiles, st);
             const int* p_act = put_list(list_dev, tiles.size(), act, st);
             A.d = d;
+            int64_t pairs = 0;
+            for (int b : act) pairs += (int64_t)C->blocks[b].rs * C->blocks[b].cs;
+            face_pairs += pairs;
+            face_flop += (double)pairs * (QPTS_REGULAR * flops_eval(op) + FLOPS_RESIDUAL * d);
+            BEM_HIP_TRY(hipEventRecord(evf0, st));
             for (int path = 0; path < 4; ++path) {
                 A.list = p_tiles + pstart[path];
                 A.nlist = (int)(pstart[path + 1] - pstart[path]);
+                if (A.nlist) ++face_launches;
                 launch_face_dense(A, path, st);
             }
+            BEM_HIP_TRY(hipEventRecord(evf1, st));
+            face_pending = true;
             A.list = p_act;
             A.nlist = (int)act.size();
             launch_pivot(A, st);
@@ -327,6 +408,11 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         // dense fallback of the blocks without a regular pivot
         BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
         BEM_HIP_TRY(hipStreamSynchronize(st));
+        if (face_pending) {
+            float ms = 0.f;
+            BEM_HIP_TRY(hipEventElapsedTime(&ms, evf0, evf1));
+            face_ms += ms;
+        }
         std::vector<int> fb_blocks, fb_tiles;
         for (int b = 0; b < nb; ++b)
             if (S[b].fallback) {
@@ -354,6 +440,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             (void)hipEventDestroy(ev0);
             (void)hipEventDestroy(ev1);
             (void)hipEventDestroy(ev2);
+            (void)hipEventDestroy(evf0);
+            (void)hipEventDestroy(evf1);
             throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes overflowed (" +
                                          std::to_string(top) + " requested); raise pool_bytes");
         }
@@ -391,6 +479,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
     (void)hipEventDestroy(ev2);
+    (void)hipEventDestroy(evf0);
+    (void)hipEventDestroy(evf1);
     BEM_HIP_TRY(hipMemcpy(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost));
     C->faces.resize((size_t)nb * L);
     BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L, hipMemcpyDeviceToHost));
@@ -489,6 +579,10 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.n_far_faces = nfarfaces;
     R.kernel_ms = kms;
     R.aca_ms = aca_ms;
+    R.face_ms = face_ms;
+    R.face_launches = face_launches;
+    R.face_pairs = face_pairs;
+    R.face_flop = face_flop;
     R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BEM_OK;
 }
