@@ -777,10 +777,12 @@ constexpr int KF = 96;
 constexpr int GCH = 4;  // rows of a Gram chunk staged in LDS
 
 struct RecompShared {
-    zd m[KF * KF];          // kc x kc column-major working matrix
-    zd stage[GCH * KF];  // Gram row chunk; later small vectors
+    zd m[KF * KF];       // kc x kc column-major working matrix
+    zd stage[GCH * KF];  // Gram row chunk
+    zd tau[KF];          // reflector coefficients of the pivoted QR
     double sv[KF];       // column norms / singular values
     int order[KF];
+    int perm[KF];        // column order of the pivoted QR
 };
 
 // Lm (kc x kc, column-major, full Hermitian) = X^H X for X (rows x kc, column-major, global).
@@ -844,12 +846,15 @@ __device__ void lds_gram(const zd* X, int rows, int kc, zd* Lm, zd* stage)
 }
 
 // Cholesky in place: Lm = R^H R with R upper (stored in the upper triangle, lower zeroed);
-// a pivot without positive mass gives a zero row.
-__device__ void lds_cholesky(zd* Lm, int kc, AcaShared& S)
+// a pivot without positive mass gives a zero row.  Returns the smallest pivot (before the
+// square root) to every thread.
+__device__ double lds_cholesky(zd* Lm, int kc, AcaShared& S)
 {
+    double pmin = 1e300;
     for (int k = 0; k < kc; ++k) {
         if (threadIdx.x == 0) {
             const double p = Lm[(size_t)k * kc + k].re;
+            pmin = fmin(pmin, p);
             S.s = p > 1e-24 ? sqrt(p) : 0.0;
         }
         __syncthreads();
@@ -868,7 +873,11 @@ __device__ void lds_cholesky(zd* Lm, int kc, AcaShared& S)
     }
     for (int q = threadIdx.x; q < kc * kc; q += WG)
         if (q % kc > q / kc) Lm[q] = {0.0, 0.0};
+    if (threadIdx.x == 0) S.s = pmin;
     __syncthreads();
+    pmin = S.s;
+    __syncthreads();
+    return pmin;
 }
 
 // X (rows x kc, column-major, global) <- X R^{-1}, R upper in Lm; blocks of 8 columns per
@@ -904,9 +913,15 @@ __device__ void lds_trsm(zd* X, int rows, const zd* Lm, int kc)
     __syncthreads();
 }
 
-// column scaling + CholeskyQR2 of X (rows x kc): X <- Q1 = (X D^-1) R1^-1 in place,
-// R2 (upper, global R2out) with Q = Q1 R2^-1, and R = R2 R1 D (upper, global Rout).
-__device__ void lds_qr(zd* X, int rows, int kc, zd* Rout, zd* R2out, zd* Lm, RecompShared& L, AcaShared& S)
+// Smallest Cholesky pivot of the column-scaled Gram (unit diagonal) that a single CholeskyQR
+// accepts: below it (cond above ~1e5) the factor is refined by a second pass.
+constexpr double CQ2_PIVOT = 1e-10;
+
+// Column scaling + CholeskyQR of X (rows x kc), repeated once (CholeskyQR2) when the first
+// pass meets a pivot below CQ2_PIVOT.  On return Q = X T^{-1} with T upper in Tout (X holds
+// X D^{-1}, or Q1 = X D^{-1} R1^{-1} after two passes) and R = R_fact D in Rout, R_fact the
+// triangular factor of X D^{-1}; both kc x kc column-major in global scratch.
+__device__ void lds_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, zd* Lm, RecompShared& L, AcaShared& S)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int c = wv; c < kc; c += WG / 64) {
@@ -922,31 +937,162 @@ __device__ void lds_qr(zd* X, int rows, int kc, zd* Rout, zd* R2out, zd* Lm, Rec
     }
     __syncthreads();
     lds_gram(X, rows, kc, Lm, L.stage);
-    lds_cholesky(Lm, kc, S);
+    const double pmin = lds_cholesky(Lm, kc, S);
+    if (pmin >= CQ2_PIVOT) {
+        for (int q = threadIdx.x; q < kc * kc; q += WG) {
+            Tout[q] = Lm[q];
+            Rout[q] = Lm[q] * L.sv[q / kc];
+        }
+        __syncthreads();
+        return;
+    }
     lds_trsm(X, rows, Lm, kc);
-    for (int q = threadIdx.x; q < kc * kc; q += WG) R2out[q] = Lm[q];  // R1 (temporarily)
+    for (int q = threadIdx.x; q < kc * kc; q += WG) Tout[q] = Lm[q];  // R1 (temporarily)
     __syncthreads();
     lds_gram(X, rows, kc, Lm, L.stage);
     lds_cholesky(Lm, kc, S);
-    // Rout = R2 R1 D, then R2out = R2
+    // Rout = R2 R1 D, then Tout = R2
     for (int q = threadIdx.x; q < kc * kc; q += WG) {
         const int i = q % kc, j = q / kc;
         zd s = {0.0, 0.0};
-        for (int t = i; t <= j; ++t) s += Lm[(size_t)t * kc + i] * R2out[(size_t)j * kc + t];
+        for (int t = i; t <= j; ++t) s += Lm[(size_t)t * kc + i] * Tout[(size_t)j * kc + t];
         Rout[q] = i <= j ? s * L.sv[j] : zd{0.0, 0.0};
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kc * kc; q += WG) R2out[q] = Lm[q];
+    for (int q = threadIdx.x; q < kc * kc; q += WG) Tout[q] = Lm[q];
     __syncthreads();
 }
 
-// One-sided Jacobi on Lm (kc x kc, column-major): Lm <- M VJ with orthogonal columns; the
-// rotations are not accumulated.  JGL lanes of a wavefront per column pair.
-constexpr int JGL = 4;
-__device__ void lds_jacobi(zd* Lm, int kc, AcaShared& S)
+// Householder QR with column pivoting of A = Lm (kc x kc, column-major) in place (complex
+// reflectors H = I - tau v v^H, v[0] = 1, v below the diagonal), stopped at the first step
+// whose remaining columns have Frobenius norm <= delta.  Returns the number of steps k;
+// tau in L.tau, the column order in L.perm, the remaining squared norm in *rest2.
+__device__ int lds_qrcp(zd* Lm, int kc, double delta, RecompShared& L, AcaShared& S, double* rest2)
 {
-    const int np = kc + (kc & 1);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = wv; c < kc; c += WG / 64) {
+        double s = 0.0;
+        for (int r = lane; r < kc; r += 64) s += abs2(Lm[(size_t)c * kc + r]);
+        s = wsum(s);
+        if (lane == 0) {
+            L.sv[c] = s;
+            L.perm[c] = c;
+        }
+    }
+    __syncthreads();
+    int j = 0;
+    for (; j < kc; ++j) {
+        // remaining norm and pivot column (wavefront 0)
+        if (wv == 0) {
+            double t = 0.0, best = -1.0;
+            int bi = 0x7fffffff;
+            for (int c = j + lane; c < kc; c += 64) {
+                t += L.sv[c];
+                if (L.sv[c] > best || (L.sv[c] == best && c < bi)) {
+                    best = L.sv[c];
+                    bi = c;
+                }
+            }
+            t = wsum(t);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double ob = __shfl_xor(best, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                S.s = t;
+                S.piv = bi;
+            }
+        }
+        __syncthreads();
+        const double rest = S.s;
+        const int p = S.piv;
+        if (sqrt(fmax(rest, 0.0)) <= delta) break;
+        if (p != j) {
+            for (int r = threadIdx.x; r < kc; r += WG) {
+                const zd a = Lm[(size_t)j * kc + r];
+                Lm[(size_t)j * kc + r] = Lm[(size_t)p * kc + r];
+                Lm[(size_t)p * kc + r] = a;
+            }
+            if (threadIdx.x == 0) {
+                const double sv = L.sv[j];
+                L.sv[j] = L.sv[p];
+                L.sv[p] = sv;
+                const int pm = L.perm[j];
+                L.perm[j] = L.perm[p];
+                L.perm[p] = pm;
+            }
+        }
+        __syncthreads();
+        // reflector of column j (wavefront 0): beta = -sign(Re alpha) ||x||
+        zd* aj = Lm + (size_t)j * kc;
+        if (wv == 0) {
+            double x2 = 0.0;
+            for (int r = j + 1 + lane; r < kc; r += 64) x2 += abs2(aj[r]);
+            x2 = wsum(x2);
+            if (lane == 0) {
+                const zd al = aj[j];
+                zd tau = {0.0, 0.0}, sc = {0.0, 0.0};
+                if (x2 > 0.0 || al.im != 0.0) {
+                    const double nrm = sqrt(abs2(al) + x2);
+                    const double beta = al.re >= 0.0 ? -nrm : nrm;
+                    tau = {(beta - al.re) / beta, -al.im / beta};
+                    sc = zdiv(zd{1.0, 0.0}, al - zd{beta, 0.0});
+                    aj[j] = {beta, 0.0};
+                }
+                L.tau[j] = tau;
+                S.pinv[0] = sc;
+            }
+        }
+        __syncthreads();
+        const zd sc = S.pinv[0];
+        for (int r = j + 1 + threadIdx.x; r < kc; r += WG) aj[r] = aj[r] * sc;
+        __syncthreads();
+        // apply H^H to the columns j + 1 .. kc - 1 (one wavefront per column), refresh norms
+        const zd tc = conj(L.tau[j]);
+        for (int c = j + 1 + wv; c < kc; c += WG / 64) {
+            zd* ac = Lm + (size_t)c * kc;
+            double wr = 0.0, wi = 0.0;
+            for (int r = j + lane; r < kc; r += 64) {
+                const zd v = r == j ? zd{1.0, 0.0} : aj[r];
+                const zd t = conj_mul(v, ac[r]);
+                wr += t.re;
+                wi += t.im;
+            }
+            wr = wsum(wr);
+            wi = wsum(wi);
+            const zd wv2 = tc * zd{wr, wi};
+            double s = 0.0;
+            for (int r = j + lane; r < kc; r += 64) {
+                const zd v = r == j ? zd{1.0, 0.0} : aj[r];
+                const zd a = ac[r] - v * wv2;
+                ac[r] = a;
+                if (r > j) s += abs2(a);
+            }
+            s = wsum(s);
+            if (lane == 0) L.sv[c] = s;
+        }
+        __syncthreads();
+    }
+    double rs = 0.0;
+    for (int c = j; c < kc; ++c) rs += L.sv[c];
+    *rest2 = j < kc ? rs : 0.0;
+    __syncthreads();
+    return j;
+}
+
+// One-sided Jacobi on the ncol columns (length rows, stride ld) at Lm: Lm <- B VJ with
+// orthogonal columns, rotations not accumulated.  JGL lanes of a wavefront per column pair.
+constexpr int JGL = 8;
+__device__ void lds_jacobi(zd* Lm, int rows, int ncol, int ld, AcaShared& S)
+{
+    const int np = ncol + (ncol & 1);
     const int g = threadIdx.x / JGL, gl = threadIdx.x % JGL;
+    if (ncol < 2) return;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (threadIdx.x == 0) S.flag = 0;
         __syncthreads();
@@ -965,11 +1111,11 @@ __device__ void lds_jacobi(zd* Lm, int kc, AcaShared& S)
                     p = q;
                     q = t;
                 }
-                if (q >= kc) continue;  // uniform within the lane group
-                zd* mp = Lm + (size_t)p * kc;
-                zd* mq = Lm + (size_t)q * kc;
+                if (q >= ncol) continue;  // uniform within the lane group
+                zd* mp = Lm + (size_t)p * ld;
+                zd* mq = Lm + (size_t)q * ld;
                 double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-                for (int r = gl; r < kc; r += JGL) {
+                for (int r = gl; r < rows; r += JGL) {
                     const zd a = mp[r], b = mq[r];
                     al += abs2(a);
                     be += abs2(b);
@@ -985,14 +1131,14 @@ __device__ void lds_jacobi(zd* Lm, int kc, AcaShared& S)
                     gi += __shfl_xor(gi, o, 64);
                 }
                 const double gabs = sqrt(gr * gr + gi * gi);
-                if (!(gabs > 1e-14 * sqrt(al * be)) || gabs == 0.0) continue;
+                if (!(gabs > 1e-12 * sqrt(al * be)) || gabs == 0.0) continue;
                 if (gl == 0) S.flag = 1;
                 const zd e = {gr / gabs, gi / gabs};
                 const double zeta = (be - al) / (2.0 * gabs);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
                 const zd ce = conj(e);
-                for (int r = gl; r < kc; r += JGL) {
+                for (int r = gl; r < rows; r += JGL) {
                     const zd a = mp[r], b = mq[r] * ce;
                     mp[r] = c * a - s * b;
                     mq[r] = (s * a + c * b) * e;
@@ -1006,9 +1152,60 @@ __device__ void lds_jacobi(zd* Lm, int kc, AcaShared& S)
     }
 }
 
-// Recompression of U (3m x kc), V (3n x kc) with kc <= KF (see face_recompress for the
-// contract).  Scratch use: G = R2_U, VJ = R2_V, RU = R_U then VJ-tilde, RV = R_V then Y_U,
-// M = M (original).
+// Y <- R^{-1} Y in place for kk columns (column s at Y + s * ldy, kc rows; LDS or global),
+// R upper (kc x kc, column-major, global): right-looking, all threads per step.
+__device__ void backsub_cols(const zd* R, int kc, zd* Y, int ldy, int kk)
+{
+    for (int i = kc - 1; i >= 0; --i) {
+        const double d = R[(size_t)i * kc + i].re;
+        for (int s = threadIdx.x; s < kk; s += WG) {
+            const zd v = Y[(size_t)s * ldy + i];
+            Y[(size_t)s * ldy + i] = d > 0.0 ? v * (1.0 / d) : zd{0.0, 0.0};
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < i * kk; q += WG) {
+            const int t = q % i, s = q / i;
+            Y[(size_t)s * ldy + t] -= R[(size_t)i * kc + t] * Y[(size_t)s * ldy + i];
+        }
+        __syncthreads();
+    }
+}
+
+// out (rows x kk, row-major, precision T) = X (rows x kc, column-major, global) Y (kc x kk,
+// column-major in LDS); one row per thread, 16 columns per pass.
+template <typename T>
+__device__ void out_gemm(cx<T>* out, const zd* X, int rows, int kc, const zd* Y, int kk)
+{
+    constexpr int CH = 16;
+    for (int r = threadIdx.x; r < rows; r += WG) {
+        for (int s0 = 0; s0 < kk; s0 += CH) {
+            zd acc[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) acc[u] = {0.0, 0.0};
+            for (int t = 0; t < kc; ++t) {
+                const zd x = X[(size_t)t * rows + r];
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+                    if (s0 + u < kk) acc[u] += x * Y[(size_t)(s0 + u) * kc + t];
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (s0 + u < kk) stz(out + (size_t)r * kk + s0 + u, acc[u]);
+        }
+    }
+    __syncthreads();
+}
+
+// Recompression (eq. (ACA)) of U (3m x kc), V (3n x kc), kc <= KF, in LDS:
+//   U = Q_U R_U, V = Q_V R_V (CholeskyQR, column-scaled), M = R_U R_V^H,
+//   M P = Q_M R (Householder QR with column pivoting, stopped when the remaining columns
+//   are below 1e-3 tol: M ~ Q_M B with B = R_top P^T, k' rows),
+//   B^H VJ = W (one-sided Jacobi, W with orthogonal columns sigma_s), VJ_s = B W_s / sigma_s^2,
+//   so M ~ sum_s (Q_M VJ_s) sigma_s (W_s / sigma_s)^H, truncated at tol (the dropped QR part
+//   counted in the tail); Ubar_s = Q_U Q_M VJ_s sigma_s, Vbar_s = Q_V W_s / sigma_s.
+// Factors are written row-major over the face storage Hout when they take less memory than
+// the dense face (returns kk), else 0.  Scratch: G = T_U, VJ = T_V, RU = R_U then B^H then
+// Vbar coefficients, RV = R_V then Ubar coefficients, M = the pivoted QR.
 template <typename T>
 __device__ int face_recompress_lds(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol,
                                    RecompShared& L, AcaShared& S)
@@ -1016,27 +1213,37 @@ __device__ int face_recompress_lds(cx<T>* Hout, int m, int n, const AcaWork& w, 
     zd* Lm = L.m;
     lds_qr(w.U, 3 * m, kc, w.RU, w.G, Lm, L, S);
     lds_qr(w.V, 3 * n, kc, w.RV, w.VJ, Lm, L, S);
-    // M = R_U R_V^H into LDS and the scratch copy
     for (int q = threadIdx.x; q < kc * kc; q += WG) {
         const int i = q % kc, j = q / kc;
         zd s = {0.0, 0.0};
         for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
         Lm[q] = s;
-        w.M[q] = s;
     }
     __syncthreads();
-    lds_jacobi(Lm, kc, S);
-    // singular values, descending order (ties to the smaller column), truncation
-    for (int c = threadIdx.x; c < kc; c += WG) {
+    double rest2 = 0.0;
+    const int kq = lds_qrcp(Lm, kc, 1e-3 * tol, L, S, &rest2);
+    if (kq == 0) return 0;
+    // keep the pivoted QR, form B^H (kc x kq): B^H[perm[c]][i] = conj(R[i][c]), i <= c
+    for (int q = threadIdx.x; q < kc * kc; q += WG) w.M[q] = Lm[q];
+    __syncthreads();
+    for (int q = threadIdx.x; q < kc * kq; q += WG) {
+        const int c = q % kc, i = q / kc;
+        const zd v = i <= c ? conj(w.M[(size_t)c * kc + i]) : zd{0.0, 0.0};
+        Lm[(size_t)i * kc + L.perm[c]] = v;
+        w.RU[(size_t)i * kc + L.perm[c]] = v;
+    }
+    __syncthreads();
+    lds_jacobi(Lm, kc, kq, kc, S);
+    for (int c = threadIdx.x; c < kq; c += WG) {
         double s = 0.0;
         for (int r = 0; r < kc; ++r) s += abs2(Lm[(size_t)c * kc + r]);
         L.sv[c] = sqrt(s);
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < kc; c += WG) {
+    for (int c = threadIdx.x; c < kq; c += WG) {
         const double sc = L.sv[c];
         int rank = 0;
-        for (int c2 = 0; c2 < kc; ++c2) {
+        for (int c2 = 0; c2 < kq; ++c2) {
             const double s2 = L.sv[c2];
             rank += (s2 > sc || (s2 == sc && c2 < c)) ? 1 : 0;
         }
@@ -1044,10 +1251,10 @@ __device__ int face_recompress_lds(cx<T>* Hout, int m, int n, const AcaWork& w, 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int c = 0; c < kc; ++c) tot += L.sv[c] * L.sv[c];
-        int kk = kc;
-        double tail = 0.0;
+        double tot = rest2;
+        for (int c = 0; c < kq; ++c) tot += L.sv[c] * L.sv[c];
+        int kk = kq;
+        double tail = rest2;
         while (kk > 0) {
             const double s = L.sv[L.order[kk - 1]];
             if (sqrt(tail + s * s) <= tol) {
@@ -1064,79 +1271,60 @@ __device__ int face_recompress_lds(cx<T>* Hout, int m, int n, const AcaWork& w, 
     __syncthreads();
     const int kk = S.piv;
     if (kk <= 0) return 0;
-    // right singular vectors of M for the kept columns: VJ_s = M^H W_s / sigma_s^2 -> RU
+    // Ubar coefficients -> RV: sigma_s Q_M [VJ_s; 0], VJ_s = B W_s / sigma_s^2 (kq entries)
+    for (int q = threadIdx.x; q < kc * kk; q += WG) {
+        const int i = q % kc, s = q / kc;
+        zd v = {0.0, 0.0};
+        if (i < kq) {
+            const int c = L.order[s];
+            const double sg = L.sv[c];
+            for (int r = 0; r < kc; ++r) v += conj_mul(w.RU[(size_t)i * kc + r], Lm[(size_t)c * kc + r]);
+            v = sg > 0.0 ? v * (1.0 / sg) : zd{0.0, 0.0};
+        }
+        w.RV[(size_t)s * kc + i] = v;
+    }
+    __syncthreads();
+    // Vbar coefficients -> RU: W_s / sigma_s
     for (int q = threadIdx.x; q < kc * kk; q += WG) {
         const int r = q % kc, s = q / kc;
         const int c = L.order[s];
         const double sg = L.sv[c];
-        zd acc = {0.0, 0.0};
-        for (int t = 0; t < kc; ++t) acc += conj_mul(w.M[(size_t)r * kc + t], Lm[(size_t)c * kc + t]);
-        w.RU[(size_t)s * kc + r] = sg > 0.0 ? acc * (1.0 / (sg * sg)) : zd{0.0, 0.0};
+        w.RU[(size_t)s * kc + r] = sg > 0.0 ? Lm[(size_t)c * kc + r] * (1.0 / sg) : zd{0.0, 0.0};
     }
-    // Y_U = R2_U^{-1} W_kept -> RV (one thread per kept column, back substitution)
-    for (int s = threadIdx.x; s < kk; s += WG) {
-        const int c = L.order[s];
-        zd* y = w.RV + (size_t)s * kc;
-        for (int i = kc - 1; i >= 0; --i) {
-            zd v = Lm[(size_t)c * kc + i];
-            for (int t = i + 1; t < kc; ++t) v -= w.G[(size_t)t * kc + i] * y[t];
-            const double d = w.G[(size_t)i * kc + i].re;
-            y[i] = d > 0.0 ? v * (1.0 / d) : zd{0.0, 0.0};
-        }
-    }
-    __syncthreads();
-    // Y_V = R2_V^{-1} VJ_kept -> LDS columns [kc x kk] after moving Y_U there is not needed:
-    // Ubar first (Y_U staged in LDS), then Y_V into LDS and Vbar.
-    for (int q = threadIdx.x; q < kc * kk; q += WG) Lm[q] = w.RV[q];
     __syncthreads();
     cx<T>* Ub = Hout;
     cx<T>* Vb = Hout + (size_t)3 * m * kk;
-    constexpr int CH = 16;
-    for (int r = threadIdx.x; r < 3 * m; r += WG) {
-        for (int s0 = 0; s0 < kk; s0 += CH) {
-            zd acc[CH];
-#pragma unroll
-            for (int u = 0; u < CH; ++u) acc[u] = {0.0, 0.0};
-            for (int t = 0; t < kc; ++t) {
-                const zd x = w.U[(size_t)t * 3 * m + r];
-#pragma unroll
-                for (int u = 0; u < CH; ++u)
-                    if (s0 + u < kk) acc[u] += x * Lm[(size_t)(s0 + u) * kc + t];
+    for (int q = threadIdx.x; q < kc * kk; q += WG) Lm[q] = w.RV[q];
+    __syncthreads();
+    // apply Q_M = H_0 ... H_{kq-1} (H = I - tau v v^H) to the Ubar coefficients, one
+    // wavefront per column
+    {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int jq = kq - 1; jq >= 0; --jq) {
+            const zd tj = L.tau[jq];
+            const zd* vj = w.M + (size_t)jq * kc;
+            for (int s = wv; s < kk; s += WG / 64) {
+                zd* y = Lm + (size_t)s * kc;
+                double dr = 0.0, di = 0.0;
+                for (int r = jq + lane; r < kc; r += 64) {
+                    const zd t = r == jq ? y[r] : conj_mul(vj[r], y[r]);
+                    dr += t.re;
+                    di += t.im;
+                }
+                dr = wsum(dr);
+                di = wsum(di);
+                const zd f = tj * zd{dr, di};
+                for (int r = jq + lane; r < kc; r += 64) y[r] -= (r == jq ? zd{1.0, 0.0} : vj[r]) * f;
             }
-#pragma unroll
-            for (int u = 0; u < CH; ++u)
-                if (s0 + u < kk) stz(Ub + (size_t)r * kk + s0 + u, acc[u]);
+            __syncthreads();
         }
     }
+    backsub_cols(w.G, kc, Lm, kc, kk);
+    out_gemm(Ub, w.U, 3 * m, kc, Lm, kk);
+    for (int q = threadIdx.x; q < kc * kk; q += WG) Lm[q] = w.RU[q];
     __syncthreads();
-    for (int s = threadIdx.x; s < kk; s += WG) {
-        zd* y = Lm + (size_t)s * kc;
-        const zd* vj = w.RU + (size_t)s * kc;
-        for (int i = kc - 1; i >= 0; --i) {
-            zd v = vj[i];
-            for (int t = i + 1; t < kc; ++t) v -= w.VJ[(size_t)t * kc + i] * y[t];
-            const double d = w.VJ[(size_t)i * kc + i].re;
-            y[i] = d > 0.0 ? v * (1.0 / d) : zd{0.0, 0.0};
-        }
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < 3 * n; r += WG) {
-        for (int s0 = 0; s0 < kk; s0 += CH) {
-            zd acc[CH];
-#pragma unroll
-            for (int u = 0; u < CH; ++u) acc[u] = {0.0, 0.0};
-            for (int t = 0; t < kc; ++t) {
-                const zd x = w.V[(size_t)t * 3 * n + r];
-#pragma unroll
-                for (int u = 0; u < CH; ++u)
-                    if (s0 + u < kk) acc[u] += x * Lm[(size_t)(s0 + u) * kc + t];
-            }
-#pragma unroll
-            for (int u = 0; u < CH; ++u)
-                if (s0 + u < kk) stz(Vb + (size_t)r * kk + s0 + u, acc[u]);
-        }
-    }
-    __syncthreads();
+    backsub_cols(w.VJ, kc, Lm, kc, kk);
+    out_gemm(Vb, w.V, 3 * n, kc, Lm, kk);
     return kk;
 }
 

@@ -140,7 +140,11 @@ struct ApplyArgs {
     const zd* x;               // permuted input [nrhs][L][3K] (cluster order)
     zd* y;                     // permuted output
     zd* tbuf;                  // far products workspace
+    const int* far_list;       // faces with kk > 0 (at most 96)
+    int nfar;
 };
+
+constexpr int APPLY_ROW_CHUNK = 8;  // element rows per workgroup of the product (row chunks)
 
 void launch_apply(const ApplyArgs& A, hipStream_t st);
 void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nrhs, int64_t in_l_stride, bool to_cluster,

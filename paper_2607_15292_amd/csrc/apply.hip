@@ -2,17 +2,26 @@
 //
 // y_l = sum_b sum_d H_{b,d} (I (x) f_{b,d}[l]) x_l      (per frequency l and right-hand side)
 // y   = sum_b sum_d H_{b,d} sum_l (I (x) f_{b,d}[l]) W_l  (eq. (3DacaMult))
-// Far faces H = Ubar Vbar^H are applied as Ubar (Vbar^H Z); near faces densely.  Rows are
-// owned by one thread per (row, column) so the sums are formed in a fixed order (no atomics).
+//
+// Per face the product is a small GEMM: Y[I, :] += H[I, J] Z, with Z[3j + c, col] the
+// fibre-weighted input of column col = (rhs, l).  Factored faces H = Ubar Vbar^H go through
+// T = Vbar^H Z (k_far_products, once per face and column tile) and Y += Ubar T.  The row
+// kernel owns a chunk of RCE element rows and a tile of NC columns, walks the faces of its
+// block row in a fixed order (sums in a fixed order, no atomics) and reads each stored face
+// tile once per column tile.  Operands are staged in LDS; arithmetic is FP64 (faces stored
+// in complex64 are widened on load).
 #include "aca3d.hpp"
 
 namespace bem {
 
 namespace {
 
-constexpr int CW = 16;    // columns (frequency x rhs) per workgroup
-constexpr int RCH = 16;   // elements per row chunk (48 rows)
-constexpr int MAXN = 64;  // largest near-field column cluster staged at once (elements)
+constexpr int RCE = 8;   // elements per row chunk (24 rows)
+constexpr int NC = 64;   // columns (rhs x frequency) per tile
+constexpr int KT = 48;   // scalar columns of a face (16 elements) per staged tile
+constexpr int KTF = 24;  // rows of Vbar per staged tile in the far products
+constexpr int KMAXF = 96;  // largest rank of a factored face
+constexpr int WGA = 256;
 
 template <typename T> __device__ __forceinline__ zd ldz(const cx<T>* p) { return {(double)p->re, (double)p->im}; }
 
@@ -23,7 +32,8 @@ __device__ __forceinline__ void mul3(const zd* f, const zd* v, zd* z)
     for (int a = 0; a < 3; ++a) z[a] = f[3 * a] * v[0] + f[3 * a + 1] * v[1] + f[3 * a + 2] * v[2];
 }
 
-// Z[3j + c][col] for a face: col = (l, r) -> (f[l] x_r,l[J])_c, or the contracted vector.
+// Z[3j + c][col] of a face: (f[l] x_{r,l}[J])_c with col = r L + l, or the contracted
+// vector of the weighted sum (ncols = 1).
 template <bool WEIGHTED>
 __device__ __forceinline__ void z_entry(const ApplyArgs& A, const ApplyFace& F, const BlockIn& B, const zd* zw, int j,
                                         int col, zd* z)
@@ -35,8 +45,8 @@ __device__ __forceinline__ void z_entry(const ApplyArgs& A, const ApplyFace& F, 
         z[2] = v[2];
         return;
     }
-    int L = A.L;
-    int l = col % L, r = col / L;
+    const int L = A.L;
+    const int l = col % L, r = col / L;
     const zd* xv = A.x + ((size_t)r * L + l) * 3 * A.K + 3 * (size_t)(B.cb + j);
     if (F.sel) {
         if (l == F.ksel) {
@@ -49,124 +59,178 @@ __device__ __forceinline__ void z_entry(const ApplyArgs& A, const ApplyFace& F, 
         return;
     }
     const zd* f = (const zd*)(A.pool + F.fib_off) + (size_t)l * 9;
-    zd v[3] = {xv[0], xv[1], xv[2]};
+    const zd v[3] = {xv[0], xv[1], xv[2]};
     mul3(f, v, z);
 }
 
-// far faces: T[t][col] = sum_{j, c} conj(Vbar[3j + c, t]) Z[3j + c][col]   (Vbar row-major)
+// Zs[k][c] for the scalar columns k0 .. k0 + KTL of the face and the columns c0 .. c0 + NC
+template <bool WEIGHTED, int KTL>
+__device__ __forceinline__ void stage_z(const ApplyArgs& A, const ApplyFace& F, const BlockIn& B, const zd* zw, int k0,
+                                        int c0, int ncols, zd (*Zs)[NC])
+{
+    const int j0 = k0 / 3, nj = min(KTL / 3, B.cs - j0);
+    for (int e = threadIdx.x; e < (KTL / 3) * NC; e += WGA) {
+        const int jj = e / NC, cl = e - jj * NC;
+        zd z[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        if (jj < nj && c0 + cl < ncols) z_entry<WEIGHTED>(A, F, B, zw, j0 + jj, c0 + cl, z);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Zs[3 * jj + c][cl] = z[c];
+    }
+}
+
+// far faces: T[t][col] = sum_k conj(Vbar[k][t]) Z[k][col]; one workgroup per (face, column
+// tile); thread = 3 ranks (t, t + 32, t + 64) x 8 columns.
 template <typename T, bool WEIGHTED>
-__device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const zd* zw_all, int ncols)
+__device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const zd* zw_all, int ncols, int c0,
+                                  zd (*Vs)[KMAXF], zd (*Zs)[NC])
 {
     const BlockIn B = A.blocks[F.block];
     const int m = B.rs, n = B.cs, kk = F.kk;
     const cx<T>* V = (const cx<T>*)(A.pool + F.face_off) + (size_t)3 * m * kk;
     const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
-    zd* Tout = A.tbuf + F.t_off * (size_t)ncols;
-    for (int q = threadIdx.x; q < kk * ncols; q += 256) {
-        int col = q / kk, t = q - col * kk;  // consecutive threads: consecutive t (contiguous Vbar rows)
-        zd acc = {0.0, 0.0};
-        for (int j = 0; j < n; ++j) {
-            zd z[3];
-            z_entry<WEIGHTED>(A, F, B, zw, j, col, z);
+    const int tr = threadIdx.x & 31, cg = threadIdx.x >> 5;
+    zd acc[3][8];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc += conj_mul(ldz(V + (size_t)(3 * j + c) * kk + t), z[c]);
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = {0.0, 0.0};
+    for (int k0 = 0; k0 < 3 * n; k0 += KTF) {
+        const int nk = min(KTF, 3 * n - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < KTF * kk; e += WGA) {
+            const int kr = e / kk, t = e - kr * kk;
+            Vs[kr][t] = kr < nk ? ldz(V + (size_t)(k0 + kr) * kk + t) : zd{0.0, 0.0};
         }
-        Tout[(size_t)t * ncols + col] = acc;
+        stage_z<WEIGHTED, KTF>(A, F, B, zw, k0, c0, ncols, Zs);
+        __syncthreads();
+        for (int k = 0; k < nk; ++k) {
+            zd vv[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) vv[u] = tr + 32 * u < kk ? conj(Vs[k][tr + 32 * u]) : zd{0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const zd z = Zs[k][8 * cg + v];
+#pragma unroll
+                for (int u = 0; u < 3; ++u) acc[u][v] = fma_c(vv[u], z, acc[u][v]);
+            }
+        }
+    }
+    zd* Tout = A.tbuf + F.t_off * (size_t)ncols;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int t = tr + 32 * u;
+        if (t >= kk) continue;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int col = c0 + 8 * cg + v;
+            if (col < ncols) Tout[(size_t)t * ncols + col] = acc[u][v];
+        }
     }
 }
 
 template <bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_far_products(ApplyArgs A, const zd* zw_all, int ncols)
+__global__ __launch_bounds__(WGA) void k_far_products(ApplyArgs A, const int* far_list, const zd* zw_all, int ncols)
 {
-    const ApplyFace F = A.faces[blockIdx.x];
-    if (F.kk <= 0) return;
-    if (F.fp32) far_products_face<float, WEIGHTED>(A, F, zw_all, ncols);
-    else far_products_face<double, WEIGHTED>(A, F, zw_all, ncols);
+    __shared__ zd Vs[KTF][KMAXF];
+    __shared__ zd Zs[KTF][NC];
+    const ApplyFace F = A.faces[far_list[blockIdx.x]];
+    const int c0 = blockIdx.y * NC;
+    if (F.fp32) far_products_face<float, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs);
+    else far_products_face<double, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs);
 }
 
-// rows: one workgroup per (row chunk, column chunk); thread = (row slot, column)
-template <bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_rows(ApplyArgs A, const zd* zw_all, int ncols, zd* yout)
+// Y[rows][cols] += Hs[rows][k] Ts[k][cols] over one staged tile; thread = element row er
+// (3 rows) x 2 columns
+__device__ __forceinline__ void tile_mac(const zd (*Hs)[KT], const zd (*Ts)[NC], int nk, int er, int cp, zd (*acc)[2])
 {
-    __shared__ zd Zs[3 * MAXN * CW];
+    for (int k = 0; k < nk; ++k) {
+        const zd z0 = Ts[k][2 * cp], z1 = Ts[k][2 * cp + 1];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const zd h = Hs[3 * er + a][k];
+            acc[a][0] = fma_c(h, z0, acc[a][0]);
+            acc[a][1] = fma_c(h, z1, acc[a][1]);
+        }
+    }
+}
+
+// rows: one workgroup per (row chunk of RCE elements, column tile)
+template <bool WEIGHTED>
+__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int ncols, zd* yout)
+{
+    __shared__ zd Hs[3 * RCE][KT];
+    __shared__ zd Zs[KT][NC];
     const int g = blockIdx.x;
-    const int c0 = blockIdx.y * CW;
-    const int col_l = threadIdx.x % CW, slot = threadIdx.x / CW;  // 16 slots x 16 columns
-    const int col = c0 + col_l;
+    const int c0 = blockIdx.y * NC;
+    const int er = threadIdx.x >> 5, cp = threadIdx.x & 31;  // element row, column pair
     const int rs0 = A.row_start[g], rsz = A.row_size[g];
-    zd acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    // each slot owns element row (rs0 + slot) if slot < rsz: 3 rows a = 0..2
+    zd acc[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[a][0] = acc[a][1] = {0.0, 0.0};
     for (int q = A.row_ptr[g]; q < A.row_ptr[g + 1]; ++q) {
-        const int fi = A.row_faces[q];
-        const ApplyFace F = A.faces[fi];
+        const ApplyFace F = A.faces[A.row_faces[q]];
         if (F.kk < 0) continue;
         const BlockIn B = A.blocks[F.block];
         const int m = B.rs, n = B.cs;
         const int ioff = rs0 - B.rb;  // first element row of the chunk inside the block
-        const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
         if (F.kk == 0) {
-            const zd* H = (const zd*)(A.pool + F.face_off);
-            const zf* Hf = (const zf*)(A.pool + F.face_off);
+            const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
             const size_t ld = 3 * (size_t)n;
-            for (int j0 = 0; j0 < n; j0 += MAXN) {
-                int nj = min(MAXN, n - j0);
+            for (int k0 = 0; k0 < 3 * n; k0 += KT) {
+                const int nk = min(KT, 3 * n - k0);
                 __syncthreads();
-                for (int e = threadIdx.x; e < nj * CW; e += 256) {
-                    int jj = e / CW, cl = e - jj * CW;
-                    zd z[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-                    if (c0 + cl < ncols) z_entry<WEIGHTED>(A, F, B, zw, j0 + jj, c0 + cl, z);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) Zs[(3 * jj + c) * CW + cl] = z[c];
-                }
-                __syncthreads();
-                if (slot < rsz) {
-                    const size_t o0 = (size_t)(3 * (ioff + slot)) * ld + 3 * j0;
-                    if (F.fp32) {
-                        for (int jc = 0; jc < 3 * nj; ++jc) {
-                            zd z = Zs[jc * CW + col_l];
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) acc[a] = fma_c(ldz(Hf + o0 + (size_t)a * ld + jc), z, acc[a]);
-                        }
-                    } else {
-                        for (int jc = 0; jc < 3 * nj; ++jc) {
-                            zd z = Zs[jc * CW + col_l];
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) acc[a] = fma_c(H[o0 + (size_t)a * ld + jc], z, acc[a]);
-                        }
+                for (int e = threadIdx.x; e < 3 * RCE * KT; e += WGA) {
+                    const int r = e / KT, kc = e - r * KT;
+                    zd h = {0.0, 0.0};
+                    if (r < 3 * rsz && kc < nk) {
+                        const size_t o = (size_t)(3 * ioff + r) * ld + k0 + kc;
+                        h = F.fp32 ? ldz((const zf*)(A.pool + F.face_off) + o) : ((const zd*)(A.pool + F.face_off))[o];
                     }
+                    Hs[r][kc] = h;
                 }
+                stage_z<WEIGHTED, KT>(A, F, B, zw, k0, c0, ncols, Zs);
+                __syncthreads();
+                tile_mac(Hs, Zs, nk, er, cp, acc);
             }
-        } else if (slot < rsz && col < ncols) {
+        } else {
             const int kk = F.kk;
             const zd* Tf = A.tbuf + F.t_off * (size_t)ncols;
-            const size_t r0 = (size_t)(3 * (ioff + slot)) * kk;
-            if (F.fp32) {
-                const zf* U = (const zf*)(A.pool + F.face_off) + r0;
-                for (int t = 0; t < kk; ++t) {
-                    zd tv = Tf[(size_t)t * ncols + col];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) acc[a] = fma_c(ldz(U + (size_t)a * kk + t), tv, acc[a]);
+            for (int k0 = 0; k0 < kk; k0 += KT) {
+                const int nk = min(KT, kk - k0);
+                __syncthreads();
+                for (int e = threadIdx.x; e < 3 * RCE * KT; e += WGA) {
+                    const int r = e / KT, kc = e - r * KT;
+                    zd h = {0.0, 0.0};
+                    if (r < 3 * rsz && kc < nk) {
+                        const size_t o = (size_t)(3 * ioff + r) * kk + k0 + kc;
+                        h = F.fp32 ? ldz((const zf*)(A.pool + F.face_off) + o) : ((const zd*)(A.pool + F.face_off))[o];
+                    }
+                    Hs[r][kc] = h;
                 }
-            } else {
-                const zd* U = (const zd*)(A.pool + F.face_off) + r0;
-                for (int t = 0; t < kk; ++t) {
-                    zd tv = Tf[(size_t)t * ncols + col];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) acc[a] = fma_c(U[(size_t)a * kk + t], tv, acc[a]);
+                for (int e = threadIdx.x; e < KT * NC; e += WGA) {
+                    const int kr = e / NC, cl = e - kr * NC;
+                    Zs[kr][cl] = (kr < nk && c0 + cl < ncols) ? Tf[(size_t)(k0 + kr) * ncols + c0 + cl] : zd{0.0, 0.0};
                 }
+                __syncthreads();
+                tile_mac(Hs, Zs, nk, er, cp, acc);
             }
         }
         (void)m;
     }
-    if (slot < rsz && col < ncols) {
-        size_t M = 3 * (size_t)A.K;
-        if (WEIGHTED) {
+    if (er < rsz) {
+        const size_t M = 3 * (size_t)A.K;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) yout[3 * (size_t)(rs0 + slot) + a] = acc[a];
-        } else {
-            int l = col % A.L, r = col / A.L;
+        for (int v = 0; v < 2; ++v) {
+            const int col = c0 + 2 * cp + v;
+            if (col >= ncols) continue;
+            if (WEIGHTED) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) yout[((size_t)r * A.L + l) * M + 3 * (size_t)(rs0 + slot) + a] = acc[a];
+                for (int a = 0; a < 3; ++a) yout[3 * (size_t)(rs0 + er) + a] = acc[a][v];
+            } else {
+                const int l = col % A.L, r = col / A.L;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) yout[((size_t)r * A.L + l) * M + 3 * (size_t)(rs0 + er) + a] = acc[a][v];
+            }
         }
     }
 }
@@ -238,11 +302,12 @@ void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nr
 
 void launch_apply(const ApplyArgs& A, hipStream_t st)
 {
-    int ncols = A.L * A.nrhs;
-    if (A.nfaces > 0) hipLaunchKernelGGL((k_far_products<false>), dim3(A.nfaces), dim3(256), 0, st, A, nullptr, ncols);
+    const int ncols = A.L * A.nrhs;
+    const unsigned ct = (unsigned)((ncols + NC - 1) / NC);
+    if (A.nfar > 0) hipLaunchKernelGGL((k_far_products<false>), dim3(A.nfar, ct), dim3(WGA), 0, st, A, A.far_list,
+                                       nullptr, ncols);
     BEM_HIP_TRY(hipGetLastError());
-    dim3 grid(A.nrow_groups, (ncols + CW - 1) / CW);
-    hipLaunchKernelGGL((k_rows<false>), grid, dim3(256), 0, st, A, nullptr, ncols, A.y);
+    hipLaunchKernelGGL((k_rows<false>), dim3(A.nrow_groups, ct), dim3(WGA), 0, st, A, nullptr, ncols, A.y);
     BEM_HIP_TRY(hipGetLastError());
 }
 
@@ -252,11 +317,12 @@ void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t
     if (A.nfaces > 0) {
         hipLaunchKernelGGL(k_contract, dim3(A.nfaces), dim3(256), 0, st, A, W, zw);
         BEM_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL((k_far_products<true>), dim3(A.nfaces), dim3(256), 0, st, A, zw, 1);
+    }
+    if (A.nfar > 0) {
+        hipLaunchKernelGGL((k_far_products<true>), dim3(A.nfar, 1), dim3(WGA), 0, st, A, A.far_list, zw, 1);
         BEM_HIP_TRY(hipGetLastError());
     }
-    dim3 grid(A.nrow_groups, 1);
-    hipLaunchKernelGGL((k_rows<true>), grid, dim3(256), 0, st, A, zw, 1, y);
+    hipLaunchKernelGGL((k_rows<true>), dim3(A.nrow_groups, 1), dim3(WGA), 0, st, A, zw, 1, y);
     BEM_HIP_TRY(hipGetLastError());
 }
 

@@ -24,8 +24,9 @@ struct CompressedOp {
     std::vector<BlockState> st;
     // apply plan
     std::vector<ApplyFace> af;
-    DevBuf af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev;
+    DevBuf af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev, farlist_dev;
     int ngroups = 0;
+    int nfar = 0;               // factored faces
     long long far_rows = 0;     // sum of kk over far faces
     long long zw_total = 0;     // sum of 3 cs over faces
     DevBuf work;                // apply workspace (grown on demand)
@@ -80,14 +81,21 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
     }
     C.far_rows = trow;
     C.zw_total = zw;
-    // row chunks: leaves of the cluster tree cut into pieces of at most 16 elements
+    // row chunks: leaves of the cluster tree cut into pieces of at most APPLY_ROW_CHUNK
     std::vector<int> cstart, csize;
     for (const Cluster& n : C.part.nodes)
         if (n.child[0] < 0)
-            for (int s = 0; s < n.size; s += 16) {
+            for (int s = 0; s < n.size; s += APPLY_ROW_CHUNK) {
                 cstart.push_back(n.begin + s);
-                csize.push_back(std::min(16, n.size - s));
+                csize.push_back(std::min(APPLY_ROW_CHUNK, n.size - s));
             }
+    std::vector<int> far;
+    for (size_t f = 0; f < C.af.size(); ++f)
+        if (C.af[f].kk > 0) {
+            if (C.af[f].kk > 96) throw ApiError(BEM_ERR_ARG, "factored face rank above 96");
+            far.push_back((int)f);
+        }
+    C.nfar = (int)far.size();
     std::vector<int> order(cstart.size());
     std::iota(order.begin(), order.end(), 0);
     std::sort(order.begin(), order.end(), [&](int a, int b) { return cstart[a] < cstart[b]; });
@@ -120,6 +128,7 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
     up(C.rowptr_dev, ptr.data(), ptr.size() * sizeof(int));
     up(C.rowstart_dev, s2.data(), s2.size() * sizeof(int));
     up(C.rowsize_dev, z2.data(), z2.size() * sizeof(int));
+    up(C.farlist_dev, far.data(), far.size() * sizeof(int));
     BEM_HIP_TRY(hipStreamSynchronize(st));
 }
 
@@ -139,6 +148,8 @@ ApplyArgs plan_args(const CompressedOp& C, int nrhs)
     A.K = C.K;
     A.L = C.L;
     A.nrhs = nrhs;
+    A.far_list = C.farlist_dev.as<int>();
+    A.nfar = C.nfar;
     return A;
 }
 
