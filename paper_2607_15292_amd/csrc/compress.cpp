@@ -46,7 +46,8 @@ constexpr int KMAX_ACA = 96;       // column capacity of the per-slice ACA scrat
 constexpr double QPTS_REGULAR = 7.0;
 constexpr double FLOPS_RESIDUAL = 216.0;
 double flops_eval(int op) { return op == BEM_OP_V ? 125.0 : (op == BEM_OP_TABLE ? 0.0 : 236.0); }
-constexpr size_t ACA_SLOTS = 512;  // faces per launch of the per-slice ACA pass
+constexpr size_t ACA_SLOTS = 4096;  // faces per launch of the per-slice ACA pass (scratch slots)
+constexpr int POOL_STEPS0 = 32;     // 3D-ACA steps of every block in the initial pool
 
 void build_apply_plan(CompressedOp& C, hipStream_t st)
 {
@@ -294,16 +295,30 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     fda_dev.alloc(sizeof(zd) * 9 * (size_t)nb * L);
     tp_dev.alloc(sizeof(double) * 8 * (size_t)ntiles);
     list_dev.alloc(sizeof(int) * std::max<size_t>(3 * (size_t)ntiles + 2 * (size_t)nb + 64, (size_t)n_aca * L + 64));
-    // pool: caller-sized, or auto-sized with up to three attempts (growing on overflow)
-    size_t pool_bytes = (size_t)o.pool_bytes;
-    const bool auto_pool = pool_bytes == 0;
-    if (auto_pool) {
+    // pool of faces and fibres: sized for POOL_STEPS0 steps of every block (or by the caller)
+    // and grown between steps, by a copy of its used part, when the allocations of the next
+    // step might not fit
+    auto step_bytes = [&](int b) -> size_t {  // one face + fibre of block b as pool_alloc rounds
+        const BlockIn& B = C->blocks[b];
+        const size_t zs = B.f32 ? sizeof(zf) : sizeof(zd);
+        const size_t fb = (zs * 9 * (size_t)B.rs * B.cs + 15) & ~(size_t)15;
+        return (fb + sizeof(zd) * 9 * (size_t)L + 255) & ~(size_t)255;
+    };
+    auto avail = [&]() {
         size_t fr = 0, tot = 0;
         BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
-        double dense = (double)L * 9.0 * (double)K * (double)K * 16.0;  // dense array size
-        double want = std::max(0.3 * dense + (double)(1 << 30), (double)(1 << 30));
-        pool_bytes = (size_t)std::min(0.45 * (double)fr, want);
-    }
+        return fr + ctx->cache.cached;
+    };
+    size_t all_step = 0;
+    for (int b = 0; b < nb; ++b) all_step += step_bytes(b);
+    size_t pool_bytes = (size_t)o.pool_bytes;
+    const bool auto_pool = pool_bytes == 0;
+    if (auto_pool) pool_bytes = std::min((size_t)(0.6 * (double)avail()), all_step * (size_t)std::min(L, POOL_STEPS0));
+    if (pool_bytes < all_step)
+        throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes cannot hold one step (" +
+                                     std::to_string(all_step) + " bytes)");
+    C->pool.cache = &ctx->cache;
+    C->work.cache = &ctx->cache;
     BEM_HIP_TRY(hipStreamSynchronize(st));
     hipEvent_t ev0, ev1, ev2, evf0, evf1;
     BEM_HIP_TRY(hipEventCreate(&ev0));
@@ -318,148 +333,166 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     std::vector<BlockState>& S = C->st;
     S.resize(nb);
     CompressArgs A;
-    for (int attempt = 0;; ++attempt) {
-        C->pool.release();
-        C->pool.alloc(pool_bytes);
-        BEM_HIP_TRY(hipMemsetAsync(aux.p, 0, 256, st));
-        BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
-        A = CompressArgs{};
-        A.c = ctx->devctx(C->geo.geo, C->perm_dev.as<int>());
-        A.op = op;
-        A.mixed = C->mixed;
-        A.L = L;
-        A.nblocks = nb;
-        A.kmax = kmax;
-        A.d = 0;
-        A.blocks = C->blocks_dev.as<BlockIn>();
-        A.faces = C->faces_dev.as<FaceDesc>();
-        A.st = st_dev.as<BlockState>();
-        A.used = used_dev.as<unsigned char>();
-        A.Fda = fda_dev.as<zd>();
-        A.tp = tp_dev.as<double>();
-        A.list = nullptr;
-        A.nlist = 0;
-        A.pool = C->pool.as<char>();
-        A.pool_cap = pool_bytes;
-        A.pool_top = top_dev;
-        A.err = err_dev;
-        A.scratch = nullptr;
-        A.scratch_per_slot = 0;
-        A.pairs = pairs_dev.as<int>();
-        A.eps3d = o.eps3d;
-        A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
-        A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
-        BEM_HIP_TRY(hipEventRecord(ev0, st));
-        launch_init(A, st);
-        // phase A: 3D-ACA of every block on dense residual faces, one step d per pass; the
-        // face kernels of each step are bracketed by events (read after the next sync)
-        std::vector<int> tiles, act;
-        face_ms = 0.0;
-        face_launches = 0;
-        face_pairs = 0;
-        face_flop = 0.0;
-        bool face_pending = false;
-        for (int d = 0; d < L; ++d) {
-            BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
-            BEM_HIP_TRY(hipStreamSynchronize(st));
-            if (face_pending) {
-                float ms = 0.f;
-                BEM_HIP_TRY(hipEventElapsedTime(&ms, evf0, evf1));
-                face_ms += ms;
-                face_pending = false;
-            }
-            tiles.clear();
-            act.clear();
-            // tiles grouped by face-kernel path (one instantiation per group): regular tiles
-            // of complex64 / complex128 blocks -> 1 / 2, the others -> 3 / 0
-            size_t pstart[5] = {0, 0, 0, 0, 0};
-            for (int path = 0; path < 4; ++path) {
-                pstart[path] = tiles.size();
-                for (int b = 0; b < nb; ++b) {
-                    const BlockIn& B = C->blocks[b];
-                    if (!S[b].active) continue;
-                    const int preg = B.f32 ? 1 : 2, pgen = B.f32 ? 3 : 0;
-                    if (path == preg)
-                        for (int t = 0; t < B.ntr; ++t) tiles.push_back((b << 12) | t);
-                    if (path == pgen)
-                        for (int t = B.ntr; t < B.ntile; ++t) tiles.push_back((b << 12) | t);
-                }
-            }
-            pstart[4] = tiles.size();
-            for (int b = 0; b < nb; ++b)
-                if (S[b].active) act.push_back(b);
-            if (act.empty()) break;
-            const int* p_tiles = put_list(list_dev, 0, tiles, st);
-            const int* p_act = put_list(list_dev, tiles.size(), act, st);
-            A.d = d;
-            int64_t pairs = 0;
-            for (int b : act) pairs += (int64_t)C->blocks[b].rs * C->blocks[b].cs;
-            face_pairs += pairs;
-            face_flop += (double)pairs * (QPTS_REGULAR * flops_eval(op) + FLOPS_RESIDUAL * d);
-            BEM_HIP_TRY(hipEventRecord(evf0, st));
-            for (int path = 0; path < 4; ++path) {
-                A.list = p_tiles + pstart[path];
-                A.nlist = (int)(pstart[path + 1] - pstart[path]);
-                if (A.nlist) ++face_launches;
-                launch_face_dense(A, path, st);
-            }
-            BEM_HIP_TRY(hipEventRecord(evf1, st));
-            face_pending = true;
-            A.list = p_act;
-            A.nlist = (int)act.size();
-            launch_pivot(A, st);
-            launch_fibre(A, st);
-            A.list = p_tiles;
-            A.nlist = (int)tiles.size();
-            launch_cross_dense(A, st);
-            A.list = p_act;
-            A.nlist = (int)act.size();
-            launch_final(A, st);
-        }
-        // dense fallback of the blocks without a regular pivot
+    // grows the pool (between steps, stream idle) so that `need` more bytes fit
+    auto ensure_pool = [&](CompressArgs& Ar, size_t need) {
+        unsigned long long top = 0;
+        BEM_HIP_TRY(hipMemcpy(&top, top_dev, sizeof(top), hipMemcpyDeviceToHost));
+        if (top + need <= Ar.pool_cap) return;
+        if (!auto_pool)
+            throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(Ar.pool_cap) +
+                                         " bytes is too small; raise pool_bytes or pass 0");
+        size_t want = std::max<size_t>((size_t)(1.5 * (double)Ar.pool_cap), (size_t)top + 2 * need);
+        want = std::min<size_t>(want, (size_t)top + (size_t)(0.9 * (double)avail()));
+        if (want < top + need) throw Err(BEM_ERR_NOMEM, "device memory exhausted by the compression pool");
+        DevBuf np(&ctx->cache);
+        np.alloc(want);
+        BEM_HIP_TRY(hipMemcpyAsync(np.p, C->pool.p, top, hipMemcpyDeviceToDevice, st));
+        BEM_HIP_TRY(hipStreamSynchronize(st));
+        C->pool.swap(np);
+        np.release();
+        Ar.pool = C->pool.as<char>();
+        Ar.pool_cap = C->pool.bytes;
+    };
+    C->pool.alloc(pool_bytes);
+    BEM_HIP_TRY(hipMemsetAsync(aux.p, 0, 256, st));
+    BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
+    A = CompressArgs{};
+    A.c = ctx->devctx(C->geo.geo, C->perm_dev.as<int>());
+    A.op = op;
+    A.mixed = C->mixed;
+    A.L = L;
+    A.nblocks = nb;
+    A.kmax = kmax;
+    A.d = 0;
+    A.blocks = C->blocks_dev.as<BlockIn>();
+    A.faces = C->faces_dev.as<FaceDesc>();
+    A.st = st_dev.as<BlockState>();
+    A.used = used_dev.as<unsigned char>();
+    A.Fda = fda_dev.as<zd>();
+    A.tp = tp_dev.as<double>();
+    A.list = nullptr;
+    A.nlist = 0;
+    A.pool = C->pool.as<char>();
+    A.pool_cap = C->pool.bytes;
+    A.pool_top = top_dev;
+    A.err = err_dev;
+    A.scratch = nullptr;
+    A.scratch_per_slot = 0;
+    A.pairs = pairs_dev.as<int>();
+    A.eps3d = o.eps3d;
+    A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
+    A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
+    BEM_HIP_TRY(hipEventRecord(ev0, st));
+    launch_init(A, st);
+    // phase A: 3D-ACA of every block on dense residual faces, one step d per pass; the
+    // face kernels of each step are bracketed by events (read after the next sync)
+    std::vector<int> tiles, act;
+    face_ms = 0.0;
+    face_launches = 0;
+    face_pairs = 0;
+    face_flop = 0.0;
+    bool face_pending = false;
+    for (int d = 0; d < L; ++d) {
         BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
         BEM_HIP_TRY(hipStreamSynchronize(st));
         if (face_pending) {
             float ms = 0.f;
             BEM_HIP_TRY(hipEventElapsedTime(&ms, evf0, evf1));
             face_ms += ms;
+            face_pending = false;
         }
-        std::vector<int> fb_blocks, fb_tiles;
+        ensure_pool(A, [&] {
+            size_t need = 0;
+            for (int b = 0; b < nb; ++b)
+                if (S[b].active) need += step_bytes(b);
+            return need;
+        }());
+        tiles.clear();
+        act.clear();
+        // tiles grouped by face-kernel path (one instantiation per group): regular tiles
+        // of complex64 / complex128 blocks -> 1 / 2, the others -> 3 / 0
+        size_t pstart[5] = {0, 0, 0, 0, 0};
+        for (int path = 0; path < 4; ++path) {
+            pstart[path] = tiles.size();
+            for (int b = 0; b < nb; ++b) {
+                const BlockIn& B = C->blocks[b];
+                if (!S[b].active) continue;
+                const int preg = B.f32 ? 1 : 2, pgen = B.f32 ? 3 : 0;
+                if (path == preg)
+                    for (int t = 0; t < B.ntr; ++t) tiles.push_back((b << 12) | t);
+                if (path == pgen)
+                    for (int t = B.ntr; t < B.ntile; ++t) tiles.push_back((b << 12) | t);
+            }
+        }
+        pstart[4] = tiles.size();
         for (int b = 0; b < nb; ++b)
-            if (S[b].fallback) {
-                fb_blocks.push_back(b);
-                for (int t = 0; t < C->blocks[b].ntile; ++t) fb_tiles.push_back((b << 12) | t);
-            }
-        if (!fb_blocks.empty()) {
-            const int* p_fb = put_list(list_dev, 0, fb_blocks, st);
-            const int* p_ft = put_list(list_dev, fb_blocks.size(), fb_tiles, st);
-            for (int kf = 0; kf < L; ++kf) {
-                A.list = p_fb;
-                A.nlist = (int)fb_blocks.size();
-                launch_fallback(A, kf, st);
-                A.list = p_ft;
-                A.nlist = (int)fb_tiles.size();
-                launch_fallback_faces(A, kf, st);
-            }
+            if (S[b].active) act.push_back(b);
+        if (act.empty()) break;
+        const int* p_tiles = put_list(list_dev, 0, tiles, st);
+        const int* p_act = put_list(list_dev, tiles.size(), act, st);
+        A.d = d;
+        int64_t pairs = 0;
+        for (int b : act) pairs += (int64_t)C->blocks[b].rs * C->blocks[b].cs;
+        face_pairs += pairs;
+        face_flop += (double)pairs * (QPTS_REGULAR * flops_eval(op) + FLOPS_RESIDUAL * d);
+        BEM_HIP_TRY(hipEventRecord(evf0, st));
+        for (int path = 0; path < 4; ++path) {
+            A.list = p_tiles + pstart[path];
+            A.nlist = (int)(pstart[path + 1] - pstart[path]);
+            if (A.nlist) ++face_launches;
+            launch_face_dense(A, path, st);
         }
-        BEM_HIP_TRY(hipStreamSynchronize(st));
-        unsigned long long top = 0;
-        BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
-        BEM_HIP_TRY(hipMemcpy(&top, top_dev, sizeof(top), hipMemcpyDeviceToHost));
-        if (!(err & 2)) break;
-        if (!auto_pool || attempt >= 2) {
-            (void)hipEventDestroy(ev0);
-            (void)hipEventDestroy(ev1);
-            (void)hipEventDestroy(ev2);
-            (void)hipEventDestroy(evf0);
-            (void)hipEventDestroy(evf1);
-            throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes overflowed (" +
-                                         std::to_string(top) + " requested); raise pool_bytes");
+        BEM_HIP_TRY(hipEventRecord(evf1, st));
+        face_pending = true;
+        A.list = p_act;
+        A.nlist = (int)act.size();
+        launch_pivot(A, st);
+        launch_fibre(A, st);
+        A.list = p_tiles;
+        A.nlist = (int)tiles.size();
+        launch_cross_dense(A, st);
+        A.list = p_act;
+        A.nlist = (int)act.size();
+        launch_final(A, st);
+    }
+    // dense fallback of the blocks without a regular pivot
+    BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    if (face_pending) {
+        float ms = 0.f;
+        BEM_HIP_TRY(hipEventElapsedTime(&ms, evf0, evf1));
+        face_ms += ms;
+    }
+    std::vector<int> fb_blocks, fb_tiles;
+    for (int b = 0; b < nb; ++b)
+        if (S[b].fallback) {
+            fb_blocks.push_back(b);
+            for (int t = 0; t < C->blocks[b].ntile; ++t) fb_tiles.push_back((b << 12) | t);
         }
-        C->pool.release();
-        size_t fr = 0, tot = 0;
-        BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
-        pool_bytes = (size_t)std::min(0.85 * (double)fr, 2.5 * (double)top + (double)(1 << 28));
+    if (!fb_blocks.empty()) {
+        size_t need = 0;
+        for (int b : fb_blocks) need += (size_t)L * step_bytes(b);
+        ensure_pool(A, need);
+        const int* p_fb = put_list(list_dev, 0, fb_blocks, st);
+        const int* p_ft = put_list(list_dev, fb_blocks.size(), fb_tiles, st);
+        for (int kf = 0; kf < L; ++kf) {
+            A.list = p_fb;
+            A.nlist = (int)fb_blocks.size();
+            launch_fallback(A, kf, st);
+            A.list = p_ft;
+            A.nlist = (int)fb_tiles.size();
+            launch_fallback_faces(A, kf, st);
+        }
+    }
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
+    if (err & 2) {
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        (void)hipEventDestroy(ev2);
+        (void)hipEventDestroy(evf0);
+        (void)hipEventDestroy(evf1);
+        throw Err(BEM_ERR_NOMEM, "compression pool overflowed");
     }
     BEM_HIP_TRY(hipMemcpy(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost));
     // phase B: per-slice ACA + recompression of the far faces of the ACA blocks, in place
@@ -467,11 +500,20 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     for (int b = 0; b < nb; ++b)
         if (C->blocks[b].aca && !S[b].fallback)
             for (int d = 0; d < S[b].rank; ++d) items.push_back((b << 8) | d);
+    // largest faces first: the long workgroups start early instead of forming the tail
+    std::stable_sort(items.begin(), items.end(), [&](int x, int y) {
+        const BlockIn& X = C->blocks[x >> 8];
+        const BlockIn& Y = C->blocks[y >> 8];
+        return (int64_t)X.rs * X.cs > (int64_t)Y.rs * Y.cs;
+    });
     BEM_HIP_TRY(hipEventRecord(ev1, st));
     if (!items.empty()) {
-        const int slots = (int)std::min<size_t>(items.size(), ACA_SLOTS);
         size_t per_slot = (aca_scratch_doubles(mmax, nmax, kmax) + 31) & ~(size_t)31;
-        DevBuf scratch;
+        size_t fr = 0, tot = 0;
+        BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
+        const size_t fit = std::max<size_t>(256, (size_t)(0.5 * (double)fr) / (per_slot * sizeof(double)));
+        const int slots = (int)std::min({items.size(), ACA_SLOTS, fit});
+        DevBuf scratch(&ctx->cache);
         scratch.alloc(per_slot * slots * sizeof(double));
         A.scratch = scratch.as<double>();
         A.scratch_per_slot = per_slot;
@@ -523,7 +565,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
                 top = up256(top + nbf);
             }
         }
-        DevBuf np, segd;
+        DevBuf np(&ctx->cache), segd;
         bool ok = true;
         try {
             np.alloc(std::max<long long>(top, 256));

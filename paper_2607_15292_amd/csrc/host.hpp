@@ -2,6 +2,8 @@
 // partition.cpp and compress.cpp).
 #pragma once
 
+#include <iterator>
+#include <map>
 #include <memory>
 #include <string>
 #include <utility>
@@ -19,11 +21,45 @@ struct ApiError : std::runtime_error {
     ApiError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
-// Owning device allocation.
+// Large device buffers released by the operators of a context are kept here and handed
+// out again to allocations of similar size: repeated compressions do not return tens of
+// GB to the driver and map them again.  Not thread-safe (a context is not).
+struct MemCache {
+    static constexpr size_t MIN_BYTES = (size_t)64 << 20;  // smaller buffers bypass the cache
+    std::multimap<size_t, void*> bufs;
+    size_t cached = 0;
+    // smallest cached buffer of at least n bytes and at most 1.5 n + 64 MiB; null if none
+    void* take(size_t n, size_t* got)
+    {
+        auto it = bufs.lower_bound(n);
+        if (it == bufs.end() || (double)it->first > 1.5 * (double)n + (double)(64 << 20)) return nullptr;
+        void* q = it->second;
+        *got = it->first;
+        cached -= it->first;
+        bufs.erase(it);
+        return q;
+    }
+    void put(void* q, size_t n)
+    {
+        bufs.emplace(n, q);
+        cached += n;
+    }
+    void clear()
+    {
+        for (auto& b : bufs) (void)hipFree(b.second);
+        bufs.clear();
+        cached = 0;
+    }
+    ~MemCache() { clear(); }
+};
+
+// Owning device allocation (through the context's MemCache when `cache` is set).
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    MemCache* cache = nullptr;
     DevBuf() = default;
+    explicit DevBuf(MemCache* c) : cache(c) {}
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
@@ -31,7 +67,23 @@ struct DevBuf {
     {
         release();
         if (n == 0) return;
+        if (cache && n >= MemCache::MIN_BYTES) {
+            size_t got = 0;
+            if (void* q = cache->take(n, &got)) {
+                p = q;
+                bytes = got;
+                return;
+            }
+        }
         hipError_t e = hipMalloc(&p, n);
+        while (e != hipSuccess && cache && !cache->bufs.empty()) {  // evict, largest first
+            (void)hipGetLastError();
+            auto it = std::prev(cache->bufs.end());
+            (void)hipFree(it->second);
+            cache->cached -= it->first;
+            cache->bufs.erase(it);
+            e = hipMalloc(&p, n);
+        }
         if (e != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
@@ -41,7 +93,10 @@ struct DevBuf {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (cache && bytes >= MemCache::MIN_BYTES) cache->put(p, bytes);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -50,6 +105,7 @@ struct DevBuf {
     {
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
+        std::swap(cache, o.cache);
     }
     struct bem_nomem : std::runtime_error {
         explicit bem_nomem(size_t n) : std::runtime_error("device allocation of " + std::to_string(n) + " bytes failed") {}
@@ -116,6 +172,7 @@ struct bem_ctx {
     bem::QuadTab qtab{};
     const zd* table = nullptr;
     int live_ops = 0;
+    bem::MemCache cache;  // large buffers of destroyed operators (freed with the context)
 
     bem::DevCtx devctx(const bem::Geo& g, const int* perm) const;
 };
