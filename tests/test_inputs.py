@@ -5,18 +5,27 @@ Pins: node/element counts of the paper's unit-cube family (Table 1: 50/96, 194/3
 enclosed volume by the divergence theorem), outward orientation, and the BDF2 contour points
 (conjugate pairs, Re s > 0, min/max modulus).
 """
+import os
+
 import numpy as np
 import pytest
 
 from paper_2607_15292_amd import workloads as W
 
 
-@pytest.mark.parametrize("level,nodes,elems", [(1, 50, 96), (2, 194, 384), (3, 770, 1536), (4, 3074, 6144)])
-def test_paper_cube_table1_counts(level, nodes, elems):
-    X, T = W.paper_cube(level)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_cube_meshes.txt")
+TABLE1 = [tuple(float(v) for v in ln.split()) for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
+
+
+@pytest.mark.parametrize("level,nodes,elems,h", TABLE1)
+def test_paper_cube_table1_counts(level, nodes, elems, h):
+    X, T = W.paper_cube(int(level))
     s = W.mesh_summary(X, T)
-    assert (s["nodes"], s["elements"]) == (nodes, elems)
+    assert (s["nodes"], s["elements"]) == (int(nodes), int(elems))
     assert s["nodes"] - s["edges"] + s["elements"] == 2
+    # h of Table 1 is the longest edge of the triangles of the unit cube
+    P = X[T]
+    assert np.allclose(np.linalg.norm(P[:, [1, 2, 0]] - P, axis=-1).max(axis=1), h)
 
 
 def _volume(X, T):
