@@ -163,6 +163,39 @@ __device__ __forceinline__ void sub_residual(blk& E, const CompressArgs& A, cons
     }
 }
 
+// the share of lane u (of a group of lpp) in the residual of E: faces a = u, u + lpp, ...
+__device__ __forceinline__ void sub_residual_share(blk& E, const CompressArgs& A, const FaceDesc* fd, int d, int n,
+                                                   int i, int j, int k, int u, int lpp)
+{
+    for (int a = u; a < d; a += lpp) {
+        const FaceDesc f = fd[a];
+        if (f.kk < 0 || (f.sel && f.k != k)) continue;
+        blk H = face_block(A.pool, f, n, i, j);
+        blk fk = fibre_at(A.pool, f, k);
+        blk_mul_sub(E, H, fk);
+    }
+}
+
+// lanes per pair for the rule of a pair class: regular 1, near level 1 / 2: 4 / 16 (one
+// sub-triangle each), self: a wavefront (angular lines round robin)
+__device__ __forceinline__ int pair_lanes(int cls)
+{
+    return cls == CLS_REGULAR ? 1 : (cls == CLS_NEAR1 ? 4 : (cls == CLS_NEAR2 ? 16 : 64));
+}
+
+// sum of E over the aligned groups of lpp lanes (lpp a power of two dividing 64); every
+// lane of the wavefront must take part
+__device__ __forceinline__ void group_sum(blk& E, int lpp)
+{
+    for (int o = lpp >> 1; o >= 1; o >>= 1) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            E.a[t].re += __shfl_xor(E.a[t].re, o, 64);
+            E.a[t].im += __shfl_xor(E.a[t].im, o, 64);
+        }
+    }
+}
+
 __device__ __forceinline__ blk entry_of(const CompressArgs& A, const BlockIn& B, int i, int j, int k)
 {
     if (A.mixed && B.far) return entry_dispatch<true>(A.c, A.op, B.rb + i, B.cb + j, k);
@@ -226,19 +259,14 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
 
 // ---------------------------------------------------------------- dense faces
 
-// Entry of a pair for the face kernels.  PATH 0: any pair class, FP64; PATH 1 / 2: block
-// whose pairs are all regular (checked on the host), FP32 / FP64 regular rule; PATH 3: any
-// pair class with the FP32 regular rule (admissible blocks of the mixed path that contain
-// near pairs).  KOP: 0 = V, 1 = K or I/2 + K, 2 = entry table.
+// Entry of a regular pair for the face kernels: PATH 1 / 2 = FP32 / FP64 regular rule.
+// KOP: 0 = V, 1 = K or I/2 + K (the free term sits on i == j, never a regular pair),
+// 2 = entry table.
 template <int KOP, int PATH>
 __device__ __forceinline__ blk pair_entry(const CompressArgs& A, int gi, int gj, int k)
 {
     if constexpr (KOP == 2) {
         return entry_dispatch<false>(A.c, OP_TABLE, gi, gj, k);
-    } else if constexpr (PATH == 0) {
-        return entry_dispatch<false>(A.c, A.op, gi, gj, k);
-    } else if constexpr (PATH == 3) {
-        return entry_dispatch<true>(A.c, A.op, gi, gj, k);
     } else {
         blk out;
         if constexpr (PATH == 1)
@@ -281,15 +309,8 @@ __device__ __forceinline__ void sub_residual_t(blk& E, const char* pool, const F
 // pair number p of lane `lane` in tile t of block B, or -1
 __device__ __forceinline__ int tile_pair(const CompressArgs& A, const BlockIn& B, int t, int lane)
 {
-    const int mn = B.rs * B.cs;
-    int q;
-    if (t < B.ntr) {
-        q = t * TILE + lane;
-        if (q >= B.nreg) return -1;
-    } else {
-        q = B.nreg + (t - B.ntr) * TILE + lane;
-        if (q >= mn) return -1;
-    }
+    const int q = t * TILE + lane;
+    if (t >= B.ntr || q >= B.nreg) return -1;
     return B.pair0 < 0 ? q : A.pairs[B.pair0 + q];
 }
 
@@ -298,7 +319,7 @@ __device__ __forceinline__ int tile_pair(const CompressArgs& A, const BlockIn& B
 template <int KOP, int PATH>
 __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
 {
-    constexpr bool F32 = PATH == 1 || PATH == 3;
+    constexpr bool F32 = PATH == 1;
     __shared__ Red S;
     const int item = A.list[blockIdx.x];
     const int b = item >> 12, t = item & 4095;
@@ -348,9 +369,103 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
         tp[1] = (double)pi;
         tp[2] = v[0];
         tp[3] = fm;
-        const int cnt = t < B.ntr ? min(TILE, B.nreg - t * TILE) : min(TILE, m * n - B.nreg - (t - B.ntr) * TILE);
-        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(cnt, 0));
+        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(TILE, B.nreg - t * TILE)));
     }
+}
+
+// Face kernel for the tiles of near and self pairs (tile t >= ntr of a block): tiles of one
+// class, a group of pair_lanes(cls) lanes per pair, each lane one or more units of the rule
+// and a share of the residual, summed over the group.  F32: faces stored in complex64.
+template <int KOP, bool F32>
+__global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
+{
+    __shared__ Red S;
+    const int item = A.list[blockIdx.x];
+    const int b = item >> 12, t = item & 4095;
+    if (!A.st[b].active) return;
+    const BlockIn B = A.blocks[b];
+    const int m = B.rs, n = B.cs, d = A.d;
+    const int k = A.st[b].k;
+    const FaceDesc* fd = A.faces + (size_t)b * A.L;
+    const FaceDesc F = fd[d];
+    int tl = t - B.ntr, cls, base, cnt;
+    const int t1 = (B.n1 + WG / 4 - 1) / (WG / 4), t2 = (B.n2 + WG / 16 - 1) / (WG / 16);
+    if (tl < t1) {
+        cls = CLS_NEAR1;
+        base = B.nreg;
+        cnt = B.n1;
+    } else if (tl < t1 + t2) {
+        cls = CLS_NEAR2;
+        tl -= t1;
+        base = B.nreg + B.n1;
+        cnt = B.n2;
+    } else {
+        cls = CLS_SELF;
+        tl -= t1 + t2;
+        base = B.nreg + B.n1 + B.n2;
+        cnt = B.n3;
+    }
+    const int lpp = pair_lanes(cls), ppt = WG / lpp;
+    const int q = tl * ppt + (int)threadIdx.x / lpp, u = threadIdx.x % lpp;
+    const bool valid = q < cnt;
+    const int p = valid ? A.pairs[B.pair0 + base + q] : 0;
+    const int i = p / n, j = p - (p / n) * n;
+    blk E = blk_zero();
+    if (valid) {
+        const int nu = rule_units(cls, A.c.qt);
+        for (int uu = u; uu < nu; uu += lpp) {
+            blk e;
+            entry_unit<KOP>(A.c.geo, B.rb + i, B.cb + j, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
+#pragma unroll
+            for (int x = 0; x < 9; ++x) E.a[x] += e.a[x];
+        }
+        if (u == 0 && A.op == OP_HK && B.rb + i == B.cb + j) {
+            E.a[0].re += 0.5;
+            E.a[4].re += 0.5;
+            E.a[8].re += 0.5;
+        }
+        sub_residual_share(E, A, fd, d, n, i, j, k, u, lpp);
+    }
+    group_sum(E, lpp);
+    double s3 = -1.0, e2 = 0.0;
+    int pi = 0x7fffffff;
+    if (valid && u == 0) {
+        const size_t ld = 3 * (size_t)n;
+        if constexpr (F32) {
+            zf* H = (zf*)(A.pool + F.face_off);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const zd v = E.a[3 * a + c];
+                    const zf w = {(float)v.re, (float)v.im};
+                    H[(size_t)(3 * i + a) * ld + 3 * j + c] = w;
+                    E.a[3 * a + c] = {(double)w.re, (double)w.im};
+                }
+        } else {
+            zd* H = (zd*)(A.pool + F.face_off);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) H[(size_t)(3 * i + a) * ld + 3 * j + c] = E.a[3 * a + c];
+        }
+        e2 = blk_fro2(E);
+        s3 = blk_sigma3(E);
+        pi = p;
+    }
+    double v[1] = {e2};
+    wg_sum<1>(v, S);
+    double fm = wg_max(e2, S);
+    wg_argmax(s3, pi, S);
+    if (threadIdx.x == 0) {
+        double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
+        tp[0] = s3;
+        tp[1] = (double)pi;
+        tp[2] = v[0];
+        tp[3] = fm;
+        atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(ppt, cnt - tl * ppt)));
+    }
+    (void)m;
 }
 
 __global__ __launch_bounds__(WG) void k_classify(DevCtx c, const BlockIn* blocks, const int* list,
@@ -1487,20 +1602,47 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
     zd* f = (zd*)(A.pool + fd[d].fib_off);
     double fn2 = 0.0, best = -1.0;
     int bk = 0x7fffffff;
-    for (int k = threadIdx.x; k < L; k += WG) {
-        blk E = entry_of(A, B, pi, pj, k);
-        sub_residual(E, A, fd, d, n, pi, pj, k);
-        blk Pi;
+    // a near or self pivot pair spreads each entry's rule over a group of lanes
+    const int gi = B.rb + pi, gj = B.cb + pj;
+    const int cls = A.op == OP_TABLE ? CLS_REGULAR : pair_class(A.c.geo, gi, gj, A.c.qt);
+    const int lpp = pair_lanes(cls), nu = cls == CLS_REGULAR ? 1 : rule_units(cls, A.c.qt);
+    const int u = threadIdx.x % lpp;
+    for (int k0 = 0; k0 < L; k0 += WG / lpp) {
+        const int k = k0 + threadIdx.x / lpp;
+        blk E = blk_zero();
+        if (k < L) {
+            if (cls == CLS_REGULAR) {
+                E = entry_of(A, B, pi, pj, k);
+            } else {
+                for (int uu = u; uu < nu; uu += lpp) {
+                    blk e;
+                    if (A.op == OP_V) entry_unit<0>(A.c.geo, gi, gj, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
+                    else entry_unit<1>(A.c.geo, gi, gj, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
 #pragma unroll
-        for (int t = 0; t < 9; ++t) Pi.a[t] = Pi_s[t];
-        blk fk = blk_mul(Pi, E);
+                    for (int t = 0; t < 9; ++t) E.a[t] += e.a[t];
+                }
+                if (u == 0 && A.op == OP_HK && gi == gj) {
+                    E.a[0].re += 0.5;
+                    E.a[4].re += 0.5;
+                    E.a[8].re += 0.5;
+                }
+            }
+            sub_residual_share(E, A, fd, d, n, pi, pj, k, u, lpp);
+        }
+        group_sum(E, lpp);
+        if (k < L && u == 0) {
+            blk Pi;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) f[(size_t)k * 9 + t] = fk.a[t];
-        fn2 += blk_fro2(fk);
-        double s3 = A.used[(size_t)b * L + k] ? -1.0 : blk_sigma3(fk);
-        if (s3 > best || (s3 == best && k < bk)) {
-            best = s3;
-            bk = k;
+            for (int t = 0; t < 9; ++t) Pi.a[t] = Pi_s[t];
+            blk fk = blk_mul(Pi, E);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) f[(size_t)k * 9 + t] = fk.a[t];
+            fn2 += blk_fro2(fk);
+            double s3 = A.used[(size_t)b * L + k] ? -1.0 : blk_sigma3(fk);
+            if (s3 > best || (s3 == best && k < bk)) {
+                best = s3;
+                bk = k;
+            }
         }
     }
     double v1[1] = {fn2};
@@ -1727,13 +1869,19 @@ void launch_face_dense_path(const CompressArgs& A, hipStream_t st)
     else if (A.op == OP_V) BEM_LAUNCH((k_face_dense<0, PATH>), A.nlist, WG, A);
     else BEM_LAUNCH((k_face_dense<1, PATH>), A.nlist, WG, A);
 }
+template <bool F32>
+void launch_face_general(const CompressArgs& A, hipStream_t st)
+{
+    if (A.op == OP_V) BEM_LAUNCH((k_face_general<0, F32>), A.nlist, WG, A);
+    else BEM_LAUNCH((k_face_general<1, F32>), A.nlist, WG, A);
+}
 void launch_face_dense(const CompressArgs& A, int path, hipStream_t st)
 {
     switch (path) {
-        case 0: launch_face_dense_path<0>(A, st); break;
+        case 0: launch_face_general<false>(A, st); break;
         case 1: launch_face_dense_path<1>(A, st); break;
         case 2: launch_face_dense_path<2>(A, st); break;
-        default: launch_face_dense_path<3>(A, st); break;
+        default: launch_face_general<true>(A, st); break;
     }
 }
 void launch_face_aca(const CompressArgs& A, hipStream_t st)

@@ -9,15 +9,17 @@ namespace bem {
 constexpr int MAX_L = 256;  // largest number of frequencies of one compression
 constexpr int TILE = 256;   // pairs (i, j) per workgroup in the tiled phases
 
-// Pairs (i, j) of a block are numbered p = i * cs + j.  The face kernels take them in
-// tiles of TILE: the first ntr tiles hold the nreg pairs of the regular rule, the others the
-// remaining pairs (near and self rules, sorted by class), so that a wavefront runs one rule.
+// Pairs (i, j) of a block are numbered p = i * cs + j and ordered regular, near level 1,
+// near level 2, self.  The face kernels take them in tiles of one class: ntr tiles of TILE
+// regular pairs (k_face_dense), then tiles of 64 near-1, 16 near-2 and 4 self pairs
+// (k_face_general, a group of 4 / 16 / 64 lanes per pair), so that a wavefront runs one rule.
 struct BlockIn {
     int rb, rs, cb, cs;  // rows [rb, rb + rs), columns [cb, cb + cs) in cluster order
     int far;             // admissible (far field): the mixed path computes it in FP32
     int aca;             // faces compressed by the per-slice ACA + recompression pass
     int tile0, ntile;    // range of this block's pair tiles
     int ntr, nreg;       // tiles of regular pairs, number of regular pairs
+    int n1, n2, n3;      // near level 1, near level 2 and self pairs
     int pair0;           // offset of the block's pair order in the pair list; -1: p = position
                          // (every pair regular)
     int f32;             // faces stored in complex64 (admissible block, mixed path)
@@ -93,8 +95,8 @@ __host__ __device__ inline int face_aca_cap(int m, int n)
 
 size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
 void launch_init(const CompressArgs& A, hipStream_t st);
-// path: 0 general pairs FP64, 1 / 2 regular pairs FP32 / FP64, 3 general pairs with FP32
-// regular rule and complex64 faces; every listed tile must be of that kind
+// path: 1 / 2 regular tiles with complex64 / complex128 faces (k_face_dense, FP32 / FP64
+// rule), 0 / 3 near and self tiles with complex128 / complex64 faces (k_face_general, FP64)
 void launch_face_dense(const CompressArgs& A, int path, hipStream_t st);
 // cls[off[q] + p] = pair class of pair p of block list[q] (one workgroup per listed block)
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,

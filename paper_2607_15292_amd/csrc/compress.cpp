@@ -224,7 +224,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         const BlockDesc& d = C->part.blocks[b];
         const int aca = d.far && std::min(d.rs, d.cs) > o.far_dense_max;
         const int f32 = C->mixed && d.far;
-        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, aca, 0, 0, 0, d.rs * d.cs, -1, f32};
+        C->blocks[b] = BlockIn{d.rb, d.rs, d.cb, d.cs, d.far, aca, 0, 0, 0, d.rs * d.cs, 0, 0, 0, -1, f32};
         const bool reg = op == BEM_OP_TABLE || (d.far && all_pairs_regular(ctx->hgeo, C->part.perm, ctx->quad, d));
         if (!reg) cls_blocks.push_back(b);
         n_far += d.far;
@@ -267,8 +267,12 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             for (int k = 0; k < 4; ++k)
                 for (int p = 0; p < mn; ++p)
                     if (c[p] == k) pair_order.push_back(p);
-            B.nreg = 0;
-            for (int p = 0; p < mn; ++p) B.nreg += c[p] == 0;
+            int cnt[4] = {0, 0, 0, 0};
+            for (int p = 0; p < mn; ++p) ++cnt[c[p]];
+            B.nreg = cnt[0];
+            B.n1 = cnt[1];
+            B.n2 = cnt[2];
+            B.n3 = cnt[3];
         }
         pairs_dev.alloc(sizeof(int) * pair_order.size());
         BEM_HIP_TRY(hipMemcpyAsync(pairs_dev.p, pair_order.data(), sizeof(int) * pair_order.size(),
@@ -277,7 +281,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     for (int b = 0; b < nb; ++b) {
         BlockIn& B = C->blocks[b];
         B.ntr = (B.nreg + TILE - 1) / TILE;
-        B.ntile = B.ntr + (B.rs * B.cs - B.nreg + TILE - 1) / TILE;
+        B.ntile = B.ntr + (B.n1 + TILE / 4 - 1) / (TILE / 4) + (B.n2 + TILE / 16 - 1) / (TILE / 16) +
+                  (B.n3 + TILE / 64 - 1) / (TILE / 64);
         if (B.ntile >= 4096) throw Err(BEM_ERR_ARG, "block too large for the tile lists (raise leaf or lower eta)");
         B.tile0 = ntiles;
         ntiles += B.ntile;

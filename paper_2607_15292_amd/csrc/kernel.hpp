@@ -296,122 +296,164 @@ BEM_HD void entry_regular(const Geo& g, int op, int i, int j, cx<T> s, cx<T> sin
     }
 }
 
-// Near pair: 7-point rule on the 4^m sub-triangles (children ordered (p0,m01,m20),
-// (m01,p1,m12), (m20,m12,p2), (m01,m12,m20)); FP64.
+// Units of a pair's rule: the regular rule is one unit, the near rule of level m has 4^m
+// sub-triangles (7 points each), the self rule 3 nt angular lines (nr points each).  A unit
+// costs about one regular entry, so entries of near and self pairs can be split over lanes.
+BEM_HD int rule_units(int cls, const QuadTab& Q)
+{
+    return cls == CLS_SELF ? 3 * Q.nt : (cls == CLS_REGULAR ? 1 : (1 << (2 * cls)));
+}
+
+// Near pair, sub-triangle u of the 4^m congruent children (children ordered (p0,m01,m20),
+// (m01,p1,m12), (m20,m12,p2), (m01,m12,m20) at every level, u read in base 4 from the top
+// level); 7-point rule on it, FP64.  KOP: 0 = V, 1 = K.
+template <int KOP>
+BEM_HD void near_unit(const Geo& g, int i, int j, int m, int u, zd s, zd sinv, const Mat<double>& M,
+                      const QuadTab& Q, blk& out)
+{
+    const int K = g.K;
+    const double x[3] = {g.cx[i], g.cy[i], g.cz[i]};
+    double P[3][3];
+    for (int a = 0; a < 3; ++a) {
+        P[a][0] = g.vx[a * K + j];
+        P[a][1] = g.vy[a * K + j];
+        P[a][2] = g.vz[a * K + j];
+    }
+    const double wA = g.area[j] / (double)(1 << (2 * m));
+    for (int lev = m - 1; lev >= 0; --lev) {
+        const int c = (u >> (2 * lev)) & 3;
+        double m01[3], m12[3], m20[3];
+        for (int k = 0; k < 3; ++k) {
+            m01[k] = 0.5 * (P[0][k] + P[1][k]);
+            m12[k] = 0.5 * (P[1][k] + P[2][k]);
+            m20[k] = 0.5 * (P[2][k] + P[0][k]);
+        }
+        for (int k = 0; k < 3; ++k) {
+            const double p0 = P[0][k], p1 = P[1][k], p2 = P[2][k];
+            if (c == 0) { P[0][k] = p0;     P[1][k] = m01[k]; P[2][k] = m20[k]; }
+            else if (c == 1) { P[0][k] = m01[k]; P[1][k] = p1;     P[2][k] = m12[k]; }
+            else if (c == 2) { P[0][k] = m20[k]; P[1][k] = m12[k]; P[2][k] = p2; }
+            else { P[0][k] = m01[k]; P[1][k] = m12[k]; P[2][k] = m20[k]; }
+        }
+    }
+    if constexpr (KOP == 0) {
+        AccV<double> acc;
+        acc.zero();
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double b0 = Q.b7[3 * q], b1 = Q.b7[3 * q + 1], b2 = Q.b7[3 * q + 2];
+            double y[3];
+            for (int k = 0; k < 3; ++k) y[k] = b0 * P[0][k] + b1 * P[1][k] + b2 * P[2][k];
+            acc.add(y[0] - x[0], y[1] - x[1], y[2] - x[2], Q.w7[q] * wA, s, sinv, M);
+        }
+        acc.store(out, M.inv4pirho);
+    } else {
+        const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+        AccK<double> acc;
+        acc.zero();
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double b0 = Q.b7[3 * q], b1 = Q.b7[3 * q + 1], b2 = Q.b7[3 * q + 2];
+            double y[3];
+            for (int k = 0; k < 3; ++k) y[k] = b0 * P[0][k] + b1 * P[1][k] + b2 * P[2][k];
+            acc.add(y[0] - x[0], y[1] - x[1], y[2] - x[2], n[0], n[1], n[2], Q.w7[q] * wA, s, sinv, M);
+        }
+        acc.store(out, n[0], n[1], n[2], M.inv4pi);
+    }
+}
+
+// Self pair, angular line u = (sub-triangle a = u / nt, angle index u % nt) of the polar
+// rule about the centroid; FP64.  For T the principal value of the line is
+// w_theta [sum_rho w_rho rho T + g(theta) (ln R(theta) - crho)], crho = sum_k w_k / rho_k
+// being independent of R for the scaled Gauss-Legendre rule.
+template <int KOP>
+BEM_HD void self_unit(const Geo& g, int j, int u, zd s, zd sinv, const Mat<double>& M, const QuadTab& Q, blk& out)
+{
+    const int K = g.K;
+    const double x[3] = {g.cx[j], g.cy[j], g.cz[j]};
+    const int a = u / Q.nt, it = u - (u / Q.nt) * Q.nt;
+    const int b = (a + 1) % 3;
+    const double va[3] = {g.vx[a * K + j], g.vy[a * K + j], g.vz[a * K + j]};
+    const double vb[3] = {g.vx[b * K + j], g.vy[b * K + j], g.vz[b * K + j]};
+    double t[3] = {vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]};
+    const double le = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    for (int k = 0; k < 3; ++k) t[k] /= le;
+    const double proj = (x[0] - va[0]) * t[0] + (x[1] - va[1]) * t[1] + (x[2] - va[2]) * t[2];
+    double foot[3], p[3];
+    for (int k = 0; k < 3; ++k) {
+        foot[k] = va[k] + proj * t[k];
+        p[k] = foot[k] - x[k];
+    }
+    const double d = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    for (int k = 0; k < 3; ++k) p[k] /= d;
+    const double sa = (va[0] - foot[0]) * t[0] + (va[1] - foot[1]) * t[1] + (va[2] - foot[2]) * t[2];
+    const double sb = (vb[0] - foot[0]) * t[0] + (vb[1] - foot[1]) * t[1] + (vb[2] - foot[2]) * t[2];
+    const double ta = atan2(sa, d), tb = atan2(sb, d);
+    const double hth = 0.5 * (tb - ta), mth = 0.5 * (ta + tb);
+    const double th = mth + hth * Q.tx[it];
+    const double wth = hth * Q.tw[it];
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double R = d / cs;
+    const double dir[3] = {cs * p[0] + sn * t[0], cs * p[1] + sn * t[1], cs * p[2] + sn * t[2]};
+    if constexpr (KOP == 0) {
+        AccV<double> acc;
+        acc.zero();
+        for (int ir = 0; ir < Q.nr; ++ir) {
+            const double rho = 0.5 * R * (1.0 + Q.rx[ir]);
+            const double w = wth * (0.5 * R * Q.rw[ir]) * rho;
+            acc.add(rho * dir[0], rho * dir[1], rho * dir[2], w, s, sinv, M);
+        }
+        acc.store(out, M.inv4pirho);
+    } else {
+        const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+        AccK<double> acc;
+        acc.zero();
+        for (int ir = 0; ir < Q.nr; ++ir) {
+            const double rho = 0.5 * R * (1.0 + Q.rx[ir]);
+            const double w = wth * (0.5 * R * Q.rw[ir]) * rho;
+            acc.add(rho * dir[0], rho * dir[1], rho * dir[2], n[0], n[1], n[2], w, s, sinv, M);
+        }
+        acc.store(out, n[0], n[1], n[2], M.inv4pi);
+        const double c = wth * (log(R) - Q.crho);
+        for (int ii = 0; ii < 3; ++ii)
+            for (int jj = 0; jj < 3; ++jj) out.a[3 * ii + jj].re += M.gcoef * c * (dir[ii] * n[jj] - dir[jj] * n[ii]);
+    }
+}
+
+// Unit u of the rule of a near (cls 1, 2) or self (cls 3) pair.
+template <int KOP>
+BEM_HD void entry_unit(const Geo& g, int i, int j, int cls, int u, zd s, zd sinv, const Mat<double>& M,
+                       const QuadTab& Q, blk& out)
+{
+    if (cls == CLS_SELF) self_unit<KOP>(g, j, u, s, sinv, M, Q, out);
+    else near_unit<KOP>(g, i, j, cls, u, s, sinv, M, Q, out);
+}
+
+// Near pair (4^m sub-triangles) and self pair (polar rule): the sums of their units.
 BEM_HD void entry_near(const Geo& g, int op, int i, int j, int m, zd s, zd sinv, const Mat<double>& M,
                        const QuadTab& Q, blk& out)
 {
-    const int K = g.K;
-    double x[3] = {g.cx[i], g.cy[i], g.cz[i]};
-    double V[3][3];
-    for (int a = 0; a < 3; ++a) {
-        V[a][0] = g.vx[a * K + j];
-        V[a][1] = g.vy[a * K + j];
-        V[a][2] = g.vz[a * K + j];
+    out = blk_zero();
+    const int nu = 1 << (2 * m);
+    for (int u = 0; u < nu; ++u) {
+        blk e;
+        if (op == 0) near_unit<0>(g, i, j, m, u, s, sinv, M, Q, e);
+        else near_unit<1>(g, i, j, m, u, s, sinv, M, Q, e);
+        for (int t = 0; t < 9; ++t) out.a[t] += e.a[t];
     }
-    double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
-    int nsub = 1 << (2 * m);
-    double wA = g.area[j] / nsub;
-    AccV<double> av;
-    AccK<double> ak;
-    av.zero();
-    ak.zero();
-    for (int t = 0; t < nsub; ++t) {
-        double P[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int k = 0; k < 3; ++k) P[a][k] = V[a][k];
-        for (int lev = m - 1; lev >= 0; --lev) {
-            int c = (t >> (2 * lev)) & 3;
-            double m01[3], m12[3], m20[3];
-            for (int k = 0; k < 3; ++k) {
-                m01[k] = 0.5 * (P[0][k] + P[1][k]);
-                m12[k] = 0.5 * (P[1][k] + P[2][k]);
-                m20[k] = 0.5 * (P[2][k] + P[0][k]);
-            }
-            for (int k = 0; k < 3; ++k) {
-                double p0 = P[0][k], p1 = P[1][k], p2 = P[2][k];
-                if (c == 0) { P[0][k] = p0;     P[1][k] = m01[k]; P[2][k] = m20[k]; }
-                else if (c == 1) { P[0][k] = m01[k]; P[1][k] = p1;     P[2][k] = m12[k]; }
-                else if (c == 2) { P[0][k] = m20[k]; P[1][k] = m12[k]; P[2][k] = p2; }
-                else { P[0][k] = m01[k]; P[1][k] = m12[k]; P[2][k] = m20[k]; }
-            }
-        }
-        for (int q = 0; q < 7; ++q) {
-            double b0 = Q.b7[3 * q], b1 = Q.b7[3 * q + 1], b2 = Q.b7[3 * q + 2];
-            double y[3];
-            for (int k = 0; k < 3; ++k) y[k] = b0 * P[0][k] + b1 * P[1][k] + b2 * P[2][k];
-            double w = Q.w7[q] * wA;
-            if (op == 0) av.add(y[0] - x[0], y[1] - x[1], y[2] - x[2], w, s, sinv, M);
-            else ak.add(y[0] - x[0], y[1] - x[1], y[2] - x[2], n[0], n[1], n[2], w, s, sinv, M);
-        }
-    }
-    if (op == 0) av.store(out, M.inv4pirho);
-    else ak.store(out, n[0], n[1], n[2], M.inv4pi);
 }
 
-// Self pair: polar coordinates about the centroid; FP64.  For T the principal value is
-// sum_theta w_theta [sum_rho w_rho rho T + g(theta) (ln R(theta) - crho)], where
-// crho = sum_k w_k / rho_k is independent of R for the scaled Gauss-Legendre rule.
 BEM_HD void entry_self(const Geo& g, int op, int j, zd s, zd sinv, const Mat<double>& M, const QuadTab& Q,
                        blk& out)
 {
-    const int K = g.K;
-    double x[3] = {g.cx[j], g.cy[j], g.cz[j]};
-    double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
-    double V[3][3];
-    for (int a = 0; a < 3; ++a) {
-        V[a][0] = g.vx[a * K + j];
-        V[a][1] = g.vy[a * K + j];
-        V[a][2] = g.vz[a * K + j];
-    }
-    AccV<double> av;
-    AccK<double> ak;
-    av.zero();
-    ak.zero();
-    double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // sum w_theta (ln R - crho) (dir_i n_j - dir_j n_i)
-    for (int a = 0; a < 3; ++a) {
-        const double* va = V[a];
-        const double* vb = V[(a + 1) % 3];
-        double t[3] = {vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]};
-        double le = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-        for (int k = 0; k < 3; ++k) t[k] /= le;
-        double proj = (x[0] - va[0]) * t[0] + (x[1] - va[1]) * t[1] + (x[2] - va[2]) * t[2];
-        double foot[3], p[3];
-        for (int k = 0; k < 3; ++k) {
-            foot[k] = va[k] + proj * t[k];
-            p[k] = foot[k] - x[k];
-        }
-        double d = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-        for (int k = 0; k < 3; ++k) p[k] /= d;
-        double sa = (va[0] - foot[0]) * t[0] + (va[1] - foot[1]) * t[1] + (va[2] - foot[2]) * t[2];
-        double sb = (vb[0] - foot[0]) * t[0] + (vb[1] - foot[1]) * t[1] + (vb[2] - foot[2]) * t[2];
-        double ta = atan2(sa, d), tb = atan2(sb, d);
-        double hth = 0.5 * (tb - ta), mth = 0.5 * (ta + tb);
-        for (int it = 0; it < Q.nt; ++it) {
-            double th = mth + hth * Q.tx[it];
-            double wth = hth * Q.tw[it];
-            double sn, cs;
-            sincos(th, &sn, &cs);
-            double R = d / cs;
-            double dir[3] = {cs * p[0] + sn * t[0], cs * p[1] + sn * t[1], cs * p[2] + sn * t[2]};
-            for (int ir = 0; ir < Q.nr; ++ir) {
-                double rho = 0.5 * R * (1.0 + Q.rx[ir]);
-                double w = wth * (0.5 * R * Q.rw[ir]) * rho;
-                if (op == 0) av.add(rho * dir[0], rho * dir[1], rho * dir[2], w, s, sinv, M);
-                else ak.add(rho * dir[0], rho * dir[1], rho * dir[2], n[0], n[1], n[2], w, s, sinv, M);
-            }
-            if (op != 0) {
-                double c = wth * (log(R) - Q.crho);
-                for (int ii = 0; ii < 3; ++ii)
-                    for (int jj = 0; jj < 3; ++jj) G[3 * ii + jj] += c * (dir[ii] * n[jj] - dir[jj] * n[ii]);
-            }
-        }
-    }
-    if (op == 0) {
-        av.store(out, M.inv4pirho);
-    } else {
-        ak.store(out, n[0], n[1], n[2], M.inv4pi);
-        for (int t = 0; t < 9; ++t) out.a[t].re += M.gcoef * G[t];
+    out = blk_zero();
+    const int nu = 3 * Q.nt;
+    for (int u = 0; u < nu; ++u) {
+        blk e;
+        if (op == 0) self_unit<0>(g, j, u, s, sinv, M, Q, e);
+        else self_unit<1>(g, j, u, s, sinv, M, Q, e);
+        for (int t = 0; t < 9; ++t) out.a[t] += e.a[t];
     }
 }
 
