@@ -40,10 +40,12 @@ Readings of the paper taken here (the same readings bind the GPU library):
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 PIVOT_RTOL = 1e-14
 MAX_FAIL = 8
-KMAX_ACA = 192
+KMAX_ACA = 96
+QRCP_FRAC = 0.25
 
 
 def sigma3(B):
@@ -238,20 +240,34 @@ def aca_matrix(A, tol, max_cols=None):
 
 
 def recompress(U, V, tol):
-    """eq. (ACA): U V^H = Q_U (R_U R_V^H) Q_V^H = Q_U (Uc S Vc^H) Q_V^H, truncated to the
-    smallest k with sqrt(sum_{i>=k} s_i^2) <= tol (at least 1 when U V^H != 0).
-    Returns Ubar (3m x k, scaled by the singular values) and Vbar (3n x k)."""
+    """eq. (ACA): U V^H = Q_U M Q_V^H with M = R_U R_V^H, and the SVD approximation of M.
+
+    The SVD of M is taken through a QR with column pivoting, M P = Q_M R, cut at the first
+    step whose remaining rows R[j:, j:] have Frobenius norm rest <= QRCP_FRAC tol; the SVD
+    of the kept rows R[:j] P^T = X S Y^H gives M ~ (Q_M[:, :j] X) S Y^H, truncated to the
+    smallest k with sqrt(rest^2 + sum_{i>=k} s_i^2) <= tol (at least 1 when M != 0).
+    Returns Ubar = Q_U Q_M X_k S_k (3m x k) and Vbar = Q_V Y_k (3n x k)."""
     if U.shape[1] == 0:
         return U, V
     QU, RU = np.linalg.qr(U)
     QV, RV = np.linalg.qr(V)
-    Uc, S, Vch = np.linalg.svd(RU @ RV.conj().T)
-    tot = np.sqrt(np.sum(S**2))
+    M = RU @ RV.conj().T
+    QM, R, perm = scipy.linalg.qr(M, pivoting=True)
+    n = M.shape[1]
+    trail = [float(np.sum(np.abs(R[j:, j:]) ** 2)) for j in range(n)] + [0.0]
+    kq = next(j for j in range(n + 1) if np.sqrt(trail[j]) <= QRCP_FRAC * tol)
+    if kq == 0:
+        return U[:, :0], V[:, :0]
+    B = np.zeros((kq, n), dtype=M.dtype)
+    B[:, perm] = R[:kq]
+    X, S, Yh = np.linalg.svd(B, full_matrices=False)
+    rest2 = trail[kq]
+    tot = np.sqrt(rest2 + np.sum(S**2))
     k = len(S)
-    while k > 0 and np.sqrt(np.sum(S[k - 1:] ** 2)) <= tol:
+    while k > 0 and np.sqrt(rest2 + np.sum(S[k - 1:] ** 2)) <= tol:
         k -= 1
     k = max(k, 1) if tot > 0 else 0
-    return (QU @ Uc[:, :k]) * S[:k], QV @ Vch[:k].conj().T
+    return (QU @ (QM[:, :kq] @ X[:, :k])) * S[:k], QV @ Yh[:k].conj().T
 
 
 def compress_face(H, tol, max_cols=KMAX_ACA):
@@ -266,7 +282,7 @@ def compress_face(H, tol, max_cols=KMAX_ACA):
     if not ok:
         return None, -1
     Ub, Vb = recompress(U, V, tol)
-    if Ub.shape[1] * (m + n) >= 3 * m * n:
+    if Ub.shape[1] == 0 or Ub.shape[1] * (m + n) >= 3 * m * n:
         return None, U.shape[1]
     return (Ub, Vb), U.shape[1]
 

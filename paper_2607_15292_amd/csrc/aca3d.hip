@@ -1028,6 +1028,11 @@ __device__ void lds_trsm(zd* X, int rows, const zd* Lm, int kc)
     __syncthreads();
 }
 
+// The pivoted QR of the core matrix stops once its remaining columns are below
+// QRCP_FRAC tol; the SVD truncation of the kept rows then has sqrt(1 - QRCP_FRAC^2) of the
+// tolerance left.
+constexpr double QRCP_FRAC = 0.25;
+
 // Smallest Cholesky pivot of the column-scaled Gram (unit diagonal) that a single CholeskyQR
 // accepts: below it (cond above ~1e5) the factor is refined by a second pass.
 constexpr double CQ2_PIVOT = 1e-10;
@@ -1314,7 +1319,7 @@ __device__ void out_gemm(cx<T>* out, const zd* X, int rows, int kc, const zd* Y,
 // Recompression (eq. (ACA)) of U (3m x kc), V (3n x kc), kc <= KF, in LDS:
 //   U = Q_U R_U, V = Q_V R_V (CholeskyQR, column-scaled), M = R_U R_V^H,
 //   M P = Q_M R (Householder QR with column pivoting, stopped when the remaining columns
-//   are below 1e-3 tol: M ~ Q_M B with B = R_top P^T, k' rows),
+//   are below QRCP_FRAC tol: M ~ Q_M B with B = R_top P^T, k' rows),
 //   B^H VJ = W (one-sided Jacobi, W with orthogonal columns sigma_s), VJ_s = B W_s / sigma_s^2,
 //   so M ~ sum_s (Q_M VJ_s) sigma_s (W_s / sigma_s)^H, truncated at tol (the dropped QR part
 //   counted in the tail); Ubar_s = Q_U Q_M VJ_s sigma_s, Vbar_s = Q_V W_s / sigma_s.
@@ -1336,7 +1341,7 @@ __device__ int face_recompress_lds(cx<T>* Hout, int m, int n, const AcaWork& w, 
     }
     __syncthreads();
     double rest2 = 0.0;
-    const int kq = lds_qrcp(Lm, kc, 1e-3 * tol, L, S, &rest2);
+    const int kq = lds_qrcp(Lm, kc, QRCP_FRAC * tol, L, S, &rest2);
     if (kq == 0) return 0;
     // keep the pivoted QR, form B^H (kc x kq): B^H[perm[c]][i] = conj(R[i][c]), i <= c
     for (int q = threadIdx.x; q < kc * kc; q += WG) w.M[q] = Lm[q];
