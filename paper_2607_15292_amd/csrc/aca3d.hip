@@ -376,7 +376,7 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
 // Face kernel for the tiles of near and self pairs (tile t >= ntr of a block): tiles of one
 // class, a group of pair_lanes(cls) lanes per pair, each lane one or more units of the rule
 // and a share of the residual, summed over the group.  F32: faces stored in complex64.
-template <int KOP, bool F32>
+template <int KOP, bool F32, bool SELF>
 __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
 {
     __shared__ Red S;
@@ -390,20 +390,20 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
     const FaceDesc F = fd[d];
     int tl = t - B.ntr, cls, base, cnt;
     const int t1 = (B.n1 + WG / 4 - 1) / (WG / 4), t2 = (B.n2 + WG / 16 - 1) / (WG / 16);
-    if (tl < t1) {
-        cls = CLS_NEAR1;
-        base = B.nreg;
-        cnt = B.n1;
-    } else if (tl < t1 + t2) {
-        cls = CLS_NEAR2;
-        tl -= t1;
-        base = B.nreg + B.n1;
-        cnt = B.n2;
-    } else {
+    if (SELF) {
         cls = CLS_SELF;
         tl -= t1 + t2;
         base = B.nreg + B.n1 + B.n2;
         cnt = B.n3;
+    } else if (tl < t1) {
+        cls = CLS_NEAR1;
+        base = B.nreg;
+        cnt = B.n1;
+    } else {
+        cls = CLS_NEAR2;
+        tl -= t1;
+        base = B.nreg + B.n1;
+        cnt = B.n2;
     }
     const int lpp = pair_lanes(cls), ppt = WG / lpp;
     const int q = tl * ppt + (int)threadIdx.x / lpp, u = threadIdx.x % lpp;
@@ -415,7 +415,10 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
         const int nu = rule_units(cls, A.c.qt);
         for (int uu = u; uu < nu; uu += lpp) {
             blk e;
-            entry_unit<KOP>(A.c.geo, B.rb + i, B.cb + j, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
+            if constexpr (SELF)
+                self_unit<KOP>(A.c.geo, B.cb + j, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
+            else
+                near_unit<KOP>(A.c.geo, B.rb + i, B.cb + j, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
 #pragma unroll
             for (int x = 0; x < 9; ++x) E.a[x] += e.a[x];
         }
@@ -1591,6 +1594,8 @@ __global__ __launch_bounds__(64) void k_pivot(CompressArgs A)
 
 // ---------------------------------------------------------------- fibres
 
+// GEN: blocks whose pivot pair takes the near or self rule (else the regular rule)
+template <bool GEN>
 __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
 {
     __shared__ Red S;
@@ -1602,6 +1607,10 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
     const FaceDesc* fd = A.faces + (size_t)b * L;
     const int piv = A.st[b].piv;
     const int pi = piv / n, pj = piv - (piv / n) * n;
+    {
+        const bool gen = A.op != OP_TABLE && pair_class(A.c.geo, B.rb + pi, B.cb + pj, A.c.qt) != CLS_REGULAR;
+        if (gen != GEN) return;
+    }
     if (threadIdx.x < 9) Pi_s[threadIdx.x] = A.st[b].pinv[threadIdx.x];
     __syncthreads();
     zd* f = (zd*)(A.pool + fd[d].fib_off);
@@ -1609,15 +1618,19 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
     int bk = 0x7fffffff;
     // a near or self pivot pair spreads each entry's rule over a group of lanes
     const int gi = B.rb + pi, gj = B.cb + pj;
-    const int cls = A.op == OP_TABLE ? CLS_REGULAR : pair_class(A.c.geo, gi, gj, A.c.qt);
-    const int lpp = pair_lanes(cls), nu = cls == CLS_REGULAR ? 1 : rule_units(cls, A.c.qt);
+    const int cls = GEN ? pair_class(A.c.geo, gi, gj, A.c.qt) : CLS_REGULAR;
+    const int lpp = pair_lanes(cls), nu = GEN ? rule_units(cls, A.c.qt) : 1;
     const int u = threadIdx.x % lpp;
     for (int k0 = 0; k0 < L; k0 += WG / lpp) {
         const int k = k0 + threadIdx.x / lpp;
         blk E = blk_zero();
         if (k < L) {
-            if (cls == CLS_REGULAR) {
-                E = entry_of(A, B, pi, pj, k);
+            if constexpr (!GEN) {
+                if (A.op == OP_TABLE) E = entry_dispatch<false>(A.c, OP_TABLE, gi, gj, k);
+                else if (B.f32)
+                    entry_regular<float>(A.c.geo, A.op == OP_V ? 0 : 1, gi, gj, A.c.fr.sf[k], A.c.fr.sinvf[k], A.c.mf, E);
+                else
+                    entry_regular<double>(A.c.geo, A.op == OP_V ? 0 : 1, gi, gj, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, E);
             } else {
                 for (int uu = u; uu < nu; uu += lpp) {
                     blk e;
@@ -1874,19 +1887,21 @@ void launch_face_dense_path(const CompressArgs& A, hipStream_t st)
     else if (A.op == OP_V) BEM_LAUNCH((k_face_dense<0, PATH>), A.nlist, WG, A);
     else BEM_LAUNCH((k_face_dense<1, PATH>), A.nlist, WG, A);
 }
-template <bool F32>
+template <bool F32, bool SELF>
 void launch_face_general(const CompressArgs& A, hipStream_t st)
 {
-    if (A.op == OP_V) BEM_LAUNCH((k_face_general<0, F32>), A.nlist, WG, A);
-    else BEM_LAUNCH((k_face_general<1, F32>), A.nlist, WG, A);
+    if (A.op == OP_V) BEM_LAUNCH((k_face_general<0, F32, SELF>), A.nlist, WG, A);
+    else BEM_LAUNCH((k_face_general<1, F32, SELF>), A.nlist, WG, A);
 }
 void launch_face_dense(const CompressArgs& A, int path, hipStream_t st)
 {
     switch (path) {
-        case 0: launch_face_general<false>(A, st); break;
+        case 0: launch_face_general<false, false>(A, st); break;
         case 1: launch_face_dense_path<1>(A, st); break;
         case 2: launch_face_dense_path<2>(A, st); break;
-        default: launch_face_general<true>(A, st); break;
+        case 3: launch_face_general<true, false>(A, st); break;
+        case 4: launch_face_general<false, true>(A, st); break;
+        default: launch_face_general<true, true>(A, st); break;
     }
 }
 void launch_face_aca(const CompressArgs& A, hipStream_t st)
@@ -1900,7 +1915,11 @@ void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, co
     BEM_LAUNCH(k_classify, n, WG, c, blocks, list, off, cls);
 }
 void launch_pivot(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_pivot, (A.nlist + 63) / 64, 64, A); }
-void launch_fibre(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_fibre, A.nlist, WG, A); }
+void launch_fibre(const CompressArgs& A, hipStream_t st)
+{
+    BEM_LAUNCH(k_fibre<false>, A.nlist, WG, A);
+    BEM_LAUNCH(k_fibre<true>, A.nlist, WG, A);
+}
 void launch_cross_dense(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_cross_dense, A.nlist, WG, A); }
 void launch_final(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_final, (A.nlist + 63) / 64, 64, A); }
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st)

@@ -96,7 +96,8 @@ __host__ __device__ inline int face_aca_cap(int m, int n)
 size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
 void launch_init(const CompressArgs& A, hipStream_t st);
 // path: 1 / 2 regular tiles with complex64 / complex128 faces (k_face_dense, FP32 / FP64
-// rule), 0 / 3 near and self tiles with complex128 / complex64 faces (k_face_general, FP64)
+// rule); 0 / 3 near tiles and 4 / 5 self tiles with complex128 / complex64 faces
+// (k_face_general, FP64 rules)
 void launch_face_dense(const CompressArgs& A, int path, hipStream_t st);
 // cls[off[q] + p] = pair class of pair p of block list[q] (one workgroup per listed block)
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,

@@ -415,21 +415,25 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         tiles.clear();
         act.clear();
         // tiles grouped by face-kernel path (one instantiation per group): regular tiles
-        // of complex64 / complex128 blocks -> 1 / 2, the others -> 3 / 0
-        size_t pstart[5] = {0, 0, 0, 0, 0};
-        for (int path = 0; path < 4; ++path) {
+        // of complex64 / complex128 blocks -> 1 / 2, near tiles -> 3 / 0, self tiles -> 5 / 4
+        constexpr int NPATH = 6;
+        size_t pstart[NPATH + 1] = {0, 0, 0, 0, 0, 0, 0};
+        for (int path = 0; path < NPATH; ++path) {
             pstart[path] = tiles.size();
             for (int b = 0; b < nb; ++b) {
                 const BlockIn& B = C->blocks[b];
                 if (!S[b].active) continue;
-                const int preg = B.f32 ? 1 : 2, pgen = B.f32 ? 3 : 0;
+                const int tn = B.ntr + (B.n1 + TILE / 4 - 1) / (TILE / 4) + (B.n2 + TILE / 16 - 1) / (TILE / 16);
+                const int preg = B.f32 ? 1 : 2, pnear = B.f32 ? 3 : 0, pself = B.f32 ? 5 : 4;
                 if (path == preg)
                     for (int t = 0; t < B.ntr; ++t) tiles.push_back((b << 12) | t);
-                if (path == pgen)
-                    for (int t = B.ntr; t < B.ntile; ++t) tiles.push_back((b << 12) | t);
+                if (path == pnear)
+                    for (int t = B.ntr; t < tn; ++t) tiles.push_back((b << 12) | t);
+                if (path == pself)
+                    for (int t = tn; t < B.ntile; ++t) tiles.push_back((b << 12) | t);
             }
         }
-        pstart[4] = tiles.size();
+        pstart[NPATH] = tiles.size();
         for (int b = 0; b < nb; ++b)
             if (S[b].active) act.push_back(b);
         if (act.empty()) break;
@@ -441,7 +445,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         face_pairs += pairs;
         face_flop += (double)pairs * (QPTS_REGULAR * flops_eval(op) + FLOPS_RESIDUAL * d);
         BEM_HIP_TRY(hipEventRecord(evf0, st));
-        for (int path = 0; path < 4; ++path) {
+        for (int path = 0; path < NPATH; ++path) {
             A.list = p_tiles + pstart[path];
             A.nlist = (int)(pstart[path + 1] - pstart[path]);
             if (A.nlist) ++face_launches;
