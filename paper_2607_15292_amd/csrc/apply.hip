@@ -32,47 +32,49 @@ __device__ __forceinline__ void mul3(const zd* f, const zd* v, zd* z)
     for (int a = 0; a < 3; ++a) z[a] = f[3 * a] * v[0] + f[3 * a + 1] * v[1] + f[3 * a + 2] * v[2];
 }
 
-// Z[3j + c][col] of a face: (f[l] x_{r,l}[J])_c with col = r L + l, or the contracted
-// vector of the weighted sum (ncols = 1).
+// Fs[cl] = f[l] (3x3) of column c0 + cl (col = r L + l), the selector fibre of a dense
+// fallback face, or nothing for the weighted sum; read by stage_z after a barrier.
 template <bool WEIGHTED>
-__device__ __forceinline__ void z_entry(const ApplyArgs& A, const ApplyFace& F, const BlockIn& B, const zd* zw, int j,
-                                        int col, zd* z)
+__device__ __forceinline__ void stage_fibres(const ApplyArgs& A, const ApplyFace& F, int c0, int ncols, zd (*Fs)[9])
 {
-    if (WEIGHTED) {
-        const zd* v = zw + 3 * (size_t)j;
-        z[0] = v[0];
-        z[1] = v[1];
-        z[2] = v[2];
-        return;
-    }
-    const int L = A.L;
-    const int l = col % L, r = col / L;
-    const zd* xv = A.x + ((size_t)r * L + l) * 3 * A.K + 3 * (size_t)(B.cb + j);
-    if (F.sel) {
-        if (l == F.ksel) {
-            z[0] = xv[0];
-            z[1] = xv[1];
-            z[2] = xv[2];
-        } else {
-            z[0] = z[1] = z[2] = {0.0, 0.0};
+    if (WEIGHTED) return;
+    const zd* fib = (const zd*)(A.pool + F.fib_off);
+    for (int e = threadIdx.x; e < NC * 9; e += WGA) {
+        const int cl = e / 9, t = e - 9 * (e / 9);
+        const int col = c0 + cl, l = col % A.L;
+        zd v = {0.0, 0.0};
+        if (col < ncols) {
+            if (F.sel) v = (l == F.ksel && (t == 0 || t == 4 || t == 8)) ? zd{1.0, 0.0} : zd{0.0, 0.0};
+            else v = fib[(size_t)l * 9 + t];
         }
-        return;
+        Fs[cl][t] = v;
     }
-    const zd* f = (const zd*)(A.pool + F.fib_off) + (size_t)l * 9;
-    const zd v[3] = {xv[0], xv[1], xv[2]};
-    mul3(f, v, z);
 }
 
-// Zs[k][c] for the scalar columns k0 .. k0 + KTL of the face and the columns c0 .. c0 + NC
+// Zs[k][c] for the scalar columns k0 .. k0 + KTL of the face and the columns c0 .. c0 + NC:
+// Z[3j + c][col] = (f[l] x_{r,l}[J])_c with col = r L + l (fibres from Fs), or the contracted
+// vector of the weighted sum (ncols = 1).
 template <bool WEIGHTED, int KTL>
-__device__ __forceinline__ void stage_z(const ApplyArgs& A, const ApplyFace& F, const BlockIn& B, const zd* zw, int k0,
-                                        int c0, int ncols, zd (*Zs)[NC])
+__device__ __forceinline__ void stage_z(const ApplyArgs& A, const BlockIn& B, const zd* zw, int k0, int c0, int ncols,
+                                        const zd (*Fs)[9], zd (*Zs)[NC])
 {
     const int j0 = k0 / 3, nj = min(KTL / 3, B.cs - j0);
     for (int e = threadIdx.x; e < (KTL / 3) * NC; e += WGA) {
         const int jj = e / NC, cl = e - jj * NC;
         zd z[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        if (jj < nj && c0 + cl < ncols) z_entry<WEIGHTED>(A, F, B, zw, j0 + jj, c0 + cl, z);
+        if (jj < nj && c0 + cl < ncols) {
+            if (WEIGHTED) {
+                const zd* v = zw + 3 * (size_t)(j0 + jj);
+                z[0] = v[0];
+                z[1] = v[1];
+                z[2] = v[2];
+            } else {
+                const int col = c0 + cl, l = col % A.L, r = col / A.L;
+                const zd* xv = A.x + ((size_t)r * A.L + l) * 3 * A.K + 3 * (size_t)(B.cb + j0 + jj);
+                const zd v[3] = {xv[0], xv[1], xv[2]};
+                mul3(Fs[cl], v, z);
+            }
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) Zs[3 * jj + c][cl] = z[c];
     }
@@ -82,7 +84,7 @@ __device__ __forceinline__ void stage_z(const ApplyArgs& A, const ApplyFace& F, 
 // tile); thread = 3 ranks (t, t + 32, t + 64) x 8 columns.
 template <typename T, bool WEIGHTED>
 __device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const zd* zw_all, int ncols, int c0,
-                                  zd (*Vs)[KMAXF], zd (*Zs)[NC])
+                                  zd (*Vs)[KMAXF], zd (*Zs)[NC], zd (*Fs)[9])
 {
     const BlockIn B = A.blocks[F.block];
     const int m = B.rs, n = B.cs, kk = F.kk;
@@ -94,6 +96,7 @@ __device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const 
     for (int u = 0; u < 3; ++u)
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[u][v] = {0.0, 0.0};
+    stage_fibres<WEIGHTED>(A, F, c0, ncols, Fs);
     for (int k0 = 0; k0 < 3 * n; k0 += KTF) {
         const int nk = min(KTF, 3 * n - k0);
         __syncthreads();
@@ -101,7 +104,7 @@ __device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const 
             const int kr = e / kk, t = e - kr * kk;
             Vs[kr][t] = kr < nk ? ldz(V + (size_t)(k0 + kr) * kk + t) : zd{0.0, 0.0};
         }
-        stage_z<WEIGHTED, KTF>(A, F, B, zw, k0, c0, ncols, Zs);
+        stage_z<WEIGHTED, KTF>(A, B, zw, k0, c0, ncols, Fs, Zs);
         __syncthreads();
         for (int k = 0; k < nk; ++k) {
             zd vv[3];
@@ -133,10 +136,11 @@ __global__ __launch_bounds__(WGA) void k_far_products(ApplyArgs A, const int* fa
 {
     __shared__ zd Vs[KTF][KMAXF];
     __shared__ zd Zs[KTF][NC];
+    __shared__ zd Fs[NC][9];
     const ApplyFace F = A.faces[far_list[blockIdx.x]];
     const int c0 = blockIdx.y * NC;
-    if (F.fp32) far_products_face<float, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs);
-    else far_products_face<double, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs);
+    if (F.fp32) far_products_face<float, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs, Fs);
+    else far_products_face<double, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs, Fs);
 }
 
 // Y[rows][cols] += Hs[rows][k] Ts[k][cols] over one staged tile; thread = element row er
@@ -160,6 +164,7 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
 {
     __shared__ zd Hs[3 * RCE][KT];
     __shared__ zd Zs[KT][NC];
+    __shared__ zd Fs[NC][9];
     const int g = blockIdx.x;
     const int c0 = blockIdx.y * NC;
     const int er = threadIdx.x >> 5, cp = threadIdx.x & 31;  // element row, column pair
@@ -176,6 +181,8 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
         if (F.kk == 0) {
             const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
             const size_t ld = 3 * (size_t)n;
+            __syncthreads();
+            stage_fibres<WEIGHTED>(A, F, c0, ncols, Fs);
             for (int k0 = 0; k0 < 3 * n; k0 += KT) {
                 const int nk = min(KT, 3 * n - k0);
                 __syncthreads();
@@ -188,7 +195,7 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
                     }
                     Hs[r][kc] = h;
                 }
-                stage_z<WEIGHTED, KT>(A, F, B, zw, k0, c0, ncols, Zs);
+                stage_z<WEIGHTED, KT>(A, B, zw, k0, c0, ncols, Fs, Zs);
                 __syncthreads();
                 tile_mac(Hs, Zs, nk, er, cp, acc);
             }
