@@ -484,42 +484,6 @@ __global__ __launch_bounds__(WG) void k_classify(DevCtx c, const BlockIn* blocks
 
 // ---------------------------------------------------------------- per-slice ACA of far faces
 
-// Scratch of one face: ACA columns and the small matrices of the recompression.
-struct AcaWork {
-    zd *U, *V;        // 3m x kmax, 3n x kmax column-major
-    zd *G, *RU, *RV;  // kmax x kmax
-    zd *M, *VJ;       // kmax x kmax
-    double* dn;       // kmax
-    int* usedrow;     // m
-    int* order;       // kmax
-    int* info;        // [0]: ACA columns of the face in this slot (-1: not resolved)
-};
-
-__device__ AcaWork aca_work(double* base, int m, int n, int kmax)
-{
-    AcaWork w;
-    zd* z = (zd*)base;
-    w.U = z;
-    z += (size_t)3 * m * kmax;
-    w.V = z;
-    z += (size_t)3 * n * kmax;
-    w.G = z;
-    z += (size_t)kmax * kmax;
-    w.RU = z;
-    z += (size_t)kmax * kmax;
-    w.RV = z;
-    z += (size_t)kmax * kmax;
-    w.M = z;
-    z += (size_t)kmax * kmax;
-    w.VJ = z;
-    z += (size_t)kmax * kmax;
-    w.dn = (double*)z;
-    w.usedrow = (int*)(w.dn + kmax);
-    w.order = w.usedrow + m;
-    w.info = w.order + kmax;
-    return w;
-}
-
 struct AcaShared {
     Red r;
     zd pinv[9];
@@ -643,814 +607,6 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
     }
 }
 
-// Cholesky G = R^H R (R upper, column-major ld = kc); dependent columns get a zero row.
-__device__ void wg_cholesky(zd* G, zd* R, int kc, AcaShared& S)
-{
-    for (int q = threadIdx.x; q < kc * kc; q += WG) R[q] = {0.0, 0.0};
-    __syncthreads();
-    for (int k = 0; k < kc; ++k) {
-        if (threadIdx.x == 0) {
-            double piv = G[(size_t)k * kc + k].re;
-            S.s = piv > 1e-24 ? sqrt(piv) : 0.0;
-        }
-        __syncthreads();
-        double rkk = S.s;
-        for (int j = k + threadIdx.x; j < kc; j += WG) {
-            zd g = G[(size_t)j * kc + k];
-            R[(size_t)j * kc + k] = (j == k) ? zd{rkk, 0.0} : (rkk > 0.0 ? g * (1.0 / rkk) : zd{0.0, 0.0});
-        }
-        __syncthreads();
-        int rem = kc - k - 1;
-        for (int q = threadIdx.x; q < rem * rem; q += WG) {
-            int ii = k + 1 + q / rem, jj = k + 1 + q % rem;
-            if (ii > jj) continue;
-            G[(size_t)jj * kc + ii] -= conj_mul(R[(size_t)ii * kc + k], R[(size_t)jj * kc + k]);
-        }
-        __syncthreads();
-    }
-}
-
-// X (rows x kc, column-major) <- X R^{-1}; zero pivots give zero columns.
-__device__ void wg_trsm_right(zd* X, int rows, const zd* R, int kc)
-{
-    for (int r = threadIdx.x; r < rows; r += WG) {
-        for (int j = 0; j < kc; ++j) {
-            zd s = X[(size_t)j * rows + r];
-            for (int i = 0; i < j; ++i) s -= X[(size_t)i * rows + r] * R[(size_t)j * kc + i];
-            double rjj = R[(size_t)j * kc + j].re;
-            X[(size_t)j * rows + r] = rjj > 0.0 ? s * (1.0 / rjj) : zd{0.0, 0.0};
-        }
-    }
-    __syncthreads();
-}
-
-// G = X^H X (kc x kc column-major, full); one wavefront per column pair, lanes over rows.
-__device__ void wg_gram(const zd* X, int rows, int kc, zd* G)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = wv; q < kc * kc; q += WG / 64) {
-        int s = q % kc, t = q / kc;
-        if (s > t) continue;  // uniform per wavefront
-        double re = 0.0, im = 0.0;
-        for (int r = lane; r < rows; r += 64) {
-            zd c = conj_mul(X[(size_t)s * rows + r], X[(size_t)t * rows + r]);
-            re += c.re;
-            im += c.im;
-        }
-        re = wsum(re);
-        im = wsum(im);
-        if (lane == 0) {
-            G[(size_t)t * kc + s] = {re, im};
-            G[(size_t)s * kc + t] = {re, -im};
-        }
-    }
-    __syncthreads();
-}
-
-// X = Q R (R upper in Rout): column scaling, then CholeskyQR applied twice.
-__device__ void wg_qr(zd* X, int rows, int kc, zd* G, zd* Rtmp, zd* Rout, double* dn, AcaShared& S)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = wv; c < kc; c += WG / 64) {
-        double s = 0.0;
-        for (int r = lane; r < rows; r += 64) s += abs2(X[(size_t)c * rows + r]);
-        s = wsum(s);
-        if (lane == 0) dn[c] = sqrt(s);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < rows * kc; q += WG) {
-        int c = q / rows;
-        X[q] = dn[c] > 0.0 ? X[q] * (1.0 / dn[c]) : zd{0.0, 0.0};
-    }
-    __syncthreads();
-    wg_gram(X, rows, kc, G);
-    wg_cholesky(G, Rout, kc, S);
-    wg_trsm_right(X, rows, Rout, kc);
-    wg_gram(X, rows, kc, G);
-    wg_cholesky(G, Rtmp, kc, S);
-    wg_trsm_right(X, rows, Rtmp, kc);
-    for (int q = threadIdx.x; q < kc * kc; q += WG) {
-        int i = q % kc, j = q / kc;
-        zd s = {0.0, 0.0};
-        if (i <= j)
-            for (int t = i; t <= j; ++t) s += Rtmp[(size_t)t * kc + i] * Rout[(size_t)j * kc + t];
-        G[q] = s * dn[j];
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < kc * kc; q += WG) Rout[q] = G[q];
-    __syncthreads();
-}
-
-// One-sided Jacobi SVD of M (kc x kc, column-major): M VJ = W with orthogonal columns.
-// Round-robin ordering; each column pair of a round is handled by JG lanes of one wavefront.
-constexpr int JG = 8;
-__device__ void wg_jacobi(zd* M, zd* VJ, int kc, AcaShared& S)
-{
-    for (int q = threadIdx.x; q < kc * kc; q += WG) VJ[q] = (q % kc == q / kc) ? zd{1.0, 0.0} : zd{0.0, 0.0};
-    __syncthreads();
-    const int np = kc + (kc & 1);
-    const int g = threadIdx.x / JG, gl = threadIdx.x % JG;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (threadIdx.x == 0) S.flag = 0;
-        __syncthreads();
-        for (int rnd = 0; rnd < np - 1; ++rnd) {
-            for (int pr = g; pr < np / 2; pr += WG / JG) {
-                int p, q;
-                if (pr == 0) {
-                    p = rnd;
-                    q = np - 1;
-                } else {
-                    p = (rnd + pr) % (np - 1);
-                    q = (rnd - pr + np - 1) % (np - 1);
-                }
-                if (p > q) {
-                    int t = p;
-                    p = q;
-                    q = t;
-                }
-                if (q >= kc) continue;  // uniform within the lane group
-                zd* mp = M + (size_t)p * kc;
-                zd* mq = M + (size_t)q * kc;
-                double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-                for (int r = gl; r < kc; r += JG) {
-                    al += abs2(mp[r]);
-                    be += abs2(mq[r]);
-                    zd c = conj_mul(mp[r], mq[r]);
-                    gr += c.re;
-                    gi += c.im;
-                }
-#pragma unroll
-                for (int o = 1; o < JG; o <<= 1) {
-                    al += __shfl_xor(al, o, 64);
-                    be += __shfl_xor(be, o, 64);
-                    gr += __shfl_xor(gr, o, 64);
-                    gi += __shfl_xor(gi, o, 64);
-                }
-                double gabs = sqrt(gr * gr + gi * gi);
-                if (!(gabs > 1e-15 * sqrt(al * be)) || gabs == 0.0) continue;
-                if (gl == 0) S.flag = 1;
-                zd e = {gr / gabs, gi / gabs};
-                double zeta = (be - al) / (2.0 * gabs);
-                double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                zd ce = conj(e);
-                zd* vp = VJ + (size_t)p * kc;
-                zd* vq = VJ + (size_t)q * kc;
-                for (int r = gl; r < kc; r += JG) {
-                    zd a = mp[r], b = mq[r] * ce;
-                    mp[r] = c * a - s * b;
-                    mq[r] = (s * a + c * b) * e;
-                    zd va = vp[r], vb = vq[r] * ce;
-                    vp[r] = c * va - s * vb;
-                    vq[r] = (s * va + c * vb) * e;
-                }
-            }
-            __syncthreads();
-        }
-        int f = S.flag;
-        __syncthreads();
-        if (!f) break;
-    }
-}
-
-// Recompression (eq. (ACA)) of U (3m x kc), V (3n x kc): QR of both, SVD of R_U R_V^H,
-// truncation to the smallest kk with sqrt(sum_{t >= kk} s_t^2) <= tol.  When the
-// factors Ubar = Q_U Uc Sigma (3m x kk) and Vbar = Q_V Vc (3n x kk) take less memory than
-// the dense face, they are written row-major over the face storage Hout (precision T)
-// and kk is returned; otherwise 0 (the face stays dense).
-template <typename T>
-__device__ int face_recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, AcaShared& S)
-{
-    wg_qr(w.U, 3 * m, kc, w.G, w.M, w.RU, w.dn, S);
-    wg_qr(w.V, 3 * n, kc, w.G, w.M, w.RV, w.dn, S);
-    for (int q = threadIdx.x; q < kc * kc; q += WG) {
-        int i = q % kc, j = q / kc;
-        zd s = {0.0, 0.0};
-        for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
-        w.M[q] = s;
-    }
-    __syncthreads();
-    wg_jacobi(w.M, w.VJ, kc, S);
-    for (int c = threadIdx.x; c < kc; c += WG) {
-        double s = 0.0;
-        for (int r = 0; r < kc; ++r) s += abs2(w.M[(size_t)c * kc + r]);
-        w.dn[c] = sqrt(s);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int c = 0; c < kc; ++c) w.order[c] = c;
-        for (int a = 0; a < kc; ++a) {
-            int bsel = a;
-            for (int c = a + 1; c < kc; ++c)
-                if (w.dn[w.order[c]] > w.dn[w.order[bsel]]) bsel = c;
-            int t = w.order[a];
-            w.order[a] = w.order[bsel];
-            w.order[bsel] = t;
-        }
-        double tot = 0.0;
-        for (int c = 0; c < kc; ++c) tot += w.dn[c] * w.dn[c];
-        int kk = kc;
-        double tail = 0.0;
-        while (kk > 0) {
-            double s = w.dn[w.order[kk - 1]];
-            if (sqrt(tail + s * s) <= tol) {
-                tail += s * s;
-                --kk;
-            } else {
-                break;
-            }
-        }
-        if (tot > 0.0 && kk == 0) kk = 1;
-        if ((long long)kk * (m + n) >= 3LL * m * n) kk = 0;  // no saving over the dense face
-        S.piv = kk;
-    }
-    __syncthreads();
-    const int kk = S.piv;
-    if (kk <= 0) return 0;
-    cx<T>* Ub = Hout;
-    cx<T>* Vb = Hout + (size_t)3 * m * kk;
-    for (int q = threadIdx.x; q < 3 * m * kk; q += WG) {
-        int r = q / kk, s = q - r * kk;
-        int c = w.order[s];
-        zd acc = {0.0, 0.0};
-        for (int t = 0; t < kc; ++t) acc += w.U[(size_t)t * 3 * m + r] * w.M[(size_t)c * kc + t];
-        stz(Ub + q, acc);
-    }
-    for (int q = threadIdx.x; q < 3 * n * kk; q += WG) {
-        int r = q / kk, s = q - r * kk;
-        int c = w.order[s];
-        zd acc = {0.0, 0.0};
-        for (int t = 0; t < kc; ++t) acc += w.V[(size_t)t * 3 * n + r] * w.VJ[(size_t)c * kc + t];
-        stz(Vb + q, acc);
-    }
-    __syncthreads();
-    return kk;
-}
-
-// ---------------------------------------------------------------- recompression in LDS
-
-// Faces with kc <= KF columns recompress with their kc x kc matrices in LDS (one workgroup
-// per face, kc^2 complex128 = 144 KiB at kc = 96); larger ones take the global-memory path.
-constexpr int KF = 96;
-constexpr int GCH = 4;  // rows of a Gram chunk staged in LDS
-
-struct RecompShared {
-    zd m[KF * KF];       // kc x kc column-major working matrix
-    zd stage[GCH * KF];  // Gram row chunk
-    zd tau[KF];          // reflector coefficients of the pivoted QR
-    double sv[KF];       // column norms / singular values
-    int order[KF];
-    int perm[KF];        // column order of the pivoted QR
-};
-
-// Lm (kc x kc, column-major, full Hermitian) = X^H X for X (rows x kc, column-major, global).
-// 4 x 4 output tiles per thread over the upper tile triangle; X streamed through LDS.
-__device__ void lds_gram(const zd* X, int rows, int kc, zd* Lm, zd* stage)
-{
-    const int nt = (kc + 3) >> 2, ntri = nt * (nt + 1) / 2;
-    for (int base = 0; base < ntri; base += WG) {
-        const int tt = base + threadIdx.x;
-        const bool act = tt < ntri;
-        int tj = 0, ti = 0;
-        if (act) {
-            tj = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
-            while ((tj + 1) * (tj + 2) / 2 <= tt) ++tj;
-            while (tj * (tj + 1) / 2 > tt) --tj;
-            ti = tt - tj * (tj + 1) / 2;
-        }
-        zd acc[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = {0.0, 0.0};
-        for (int r0 = 0; r0 < rows; r0 += GCH) {
-            const int nr = min(GCH, rows - r0);
-            __syncthreads();
-            for (int q = threadIdx.x; q < GCH * kc; q += WG) {
-                const int c = q / GCH, r = q - c * GCH;
-                stage[r * kc + c] = r < nr ? X[(size_t)c * rows + r0 + r] : zd{0.0, 0.0};
-            }
-            __syncthreads();
-            if (act) {
-                for (int r = 0; r < nr; ++r) {
-                    zd a[4], b[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int ca = 4 * ti + u, cb = 4 * tj + u;
-                        a[u] = ca < kc ? stage[r * kc + ca] : zd{0.0, 0.0};
-                        b[u] = cb < kc ? stage[r * kc + cb] : zd{0.0, 0.0};
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[u][v] += conj_mul(a[u], b[v]);
-                }
-            }
-        }
-        if (act) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = 4 * ti + u, j = 4 * tj + v;
-                    if (i < kc && j < kc && i <= j) {
-                        Lm[(size_t)j * kc + i] = acc[u][v];
-                        Lm[(size_t)i * kc + j] = conj(acc[u][v]);
-                    }
-                }
-        }
-    }
-    __syncthreads();
-}
-
-// Cholesky in place: Lm = R^H R with R upper (stored in the upper triangle, lower zeroed);
-// a pivot without positive mass gives a zero row.  Returns the smallest pivot (before the
-// square root) to every thread.
-__device__ double lds_cholesky(zd* Lm, int kc, AcaShared& S)
-{
-    double pmin = 1e300;
-    for (int k = 0; k < kc; ++k) {
-        if (threadIdx.x == 0) {
-            const double p = Lm[(size_t)k * kc + k].re;
-            pmin = fmin(pmin, p);
-            S.s = p > 1e-24 ? sqrt(p) : 0.0;
-        }
-        __syncthreads();
-        const double rkk = S.s;
-        for (int j = k + threadIdx.x; j < kc; j += WG) {
-            const zd g = Lm[(size_t)j * kc + k];
-            Lm[(size_t)j * kc + k] = (j == k) ? zd{rkk, 0.0} : (rkk > 0.0 ? g * (1.0 / rkk) : zd{0.0, 0.0});
-        }
-        __syncthreads();
-        const int rem = kc - k - 1;
-        for (int q = threadIdx.x; q < rem * rem; q += WG) {
-            const int jj = k + 1 + q / rem, ii = k + 1 + q % rem;
-            if (ii <= jj) Lm[(size_t)jj * kc + ii] -= conj_mul(Lm[(size_t)ii * kc + k], Lm[(size_t)jj * kc + k]);
-        }
-        __syncthreads();
-    }
-    for (int q = threadIdx.x; q < kc * kc; q += WG)
-        if (q % kc > q / kc) Lm[q] = {0.0, 0.0};
-    if (threadIdx.x == 0) S.s = pmin;
-    __syncthreads();
-    pmin = S.s;
-    __syncthreads();
-    return pmin;
-}
-
-// X (rows x kc, column-major, global) <- X R^{-1}, R upper in Lm; blocks of 8 columns per
-// pass, one row per thread; zero pivots give zero columns.
-__device__ void lds_trsm(zd* X, int rows, const zd* Lm, int kc)
-{
-    constexpr int NB = 8;
-    for (int r = threadIdx.x; r < rows; r += WG) {
-        for (int j0 = 0; j0 < kc; j0 += NB) {
-            const int nb = min(NB, kc - j0);
-            zd acc[NB];
-#pragma unroll
-            for (int t = 0; t < NB; ++t) acc[t] = t < nb ? X[(size_t)(j0 + t) * rows + r] : zd{0.0, 0.0};
-            for (int i = 0; i < j0; ++i) {
-                const zd x = X[(size_t)i * rows + r];
-#pragma unroll
-                for (int t = 0; t < NB; ++t)
-                    if (t < nb) acc[t] -= x * Lm[(size_t)(j0 + t) * kc + i];
-            }
-#pragma unroll
-            for (int t = 0; t < NB; ++t) {
-                if (t >= nb) break;
-#pragma unroll
-                for (int u = 0; u < t; ++u) acc[t] -= acc[u] * Lm[(size_t)(j0 + t) * kc + j0 + u];
-                const double d = Lm[(size_t)(j0 + t) * kc + j0 + t].re;
-                acc[t] = d > 0.0 ? acc[t] * (1.0 / d) : zd{0.0, 0.0};
-            }
-#pragma unroll
-            for (int t = 0; t < NB; ++t)
-                if (t < nb) X[(size_t)(j0 + t) * rows + r] = acc[t];
-        }
-    }
-    __syncthreads();
-}
-
-// The pivoted QR of the core matrix stops once its remaining columns are below
-// QRCP_FRAC tol; the SVD truncation of the kept rows then has sqrt(1 - QRCP_FRAC^2) of the
-// tolerance left.
-constexpr double QRCP_FRAC = 0.25;
-
-// Smallest Cholesky pivot of the column-scaled Gram (unit diagonal) that a single CholeskyQR
-// accepts: below it (cond above ~1e5) the factor is refined by a second pass.
-constexpr double CQ2_PIVOT = 1e-10;
-
-// Column scaling + CholeskyQR of X (rows x kc), repeated once (CholeskyQR2) when the first
-// pass meets a pivot below CQ2_PIVOT.  On return Q = X T^{-1} with T upper in Tout (X holds
-// X D^{-1}, or Q1 = X D^{-1} R1^{-1} after two passes) and R = R_fact D in Rout, R_fact the
-// triangular factor of X D^{-1}; both kc x kc column-major in global scratch.
-__device__ void lds_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, zd* Lm, RecompShared& L, AcaShared& S)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = wv; c < kc; c += WG / 64) {
-        double s = 0.0;
-        for (int r = lane; r < rows; r += 64) s += abs2(X[(size_t)c * rows + r]);
-        s = wsum(s);
-        if (lane == 0) L.sv[c] = sqrt(s);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < rows * kc; q += WG) {
-        const double dc = L.sv[q / rows];
-        X[q] = dc > 0.0 ? X[q] * (1.0 / dc) : zd{0.0, 0.0};
-    }
-    __syncthreads();
-    lds_gram(X, rows, kc, Lm, L.stage);
-    const double pmin = lds_cholesky(Lm, kc, S);
-    if (pmin >= CQ2_PIVOT) {
-        for (int q = threadIdx.x; q < kc * kc; q += WG) {
-            Tout[q] = Lm[q];
-            Rout[q] = Lm[q] * L.sv[q / kc];
-        }
-        __syncthreads();
-        return;
-    }
-    lds_trsm(X, rows, Lm, kc);
-    for (int q = threadIdx.x; q < kc * kc; q += WG) Tout[q] = Lm[q];  // R1 (temporarily)
-    __syncthreads();
-    lds_gram(X, rows, kc, Lm, L.stage);
-    lds_cholesky(Lm, kc, S);
-    // Rout = R2 R1 D, then Tout = R2
-    for (int q = threadIdx.x; q < kc * kc; q += WG) {
-        const int i = q % kc, j = q / kc;
-        zd s = {0.0, 0.0};
-        for (int t = i; t <= j; ++t) s += Lm[(size_t)t * kc + i] * Tout[(size_t)j * kc + t];
-        Rout[q] = i <= j ? s * L.sv[j] : zd{0.0, 0.0};
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < kc * kc; q += WG) Tout[q] = Lm[q];
-    __syncthreads();
-}
-
-// Householder QR with column pivoting of A = Lm (kc x kc, column-major) in place (complex
-// reflectors H = I - tau v v^H, v[0] = 1, v below the diagonal), stopped at the first step
-// whose remaining columns have Frobenius norm <= delta.  Returns the number of steps k;
-// tau in L.tau, the column order in L.perm, the remaining squared norm in *rest2.
-__device__ int lds_qrcp(zd* Lm, int kc, double delta, RecompShared& L, AcaShared& S, double* rest2)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = wv; c < kc; c += WG / 64) {
-        double s = 0.0;
-        for (int r = lane; r < kc; r += 64) s += abs2(Lm[(size_t)c * kc + r]);
-        s = wsum(s);
-        if (lane == 0) {
-            L.sv[c] = s;
-            L.perm[c] = c;
-        }
-    }
-    __syncthreads();
-    int j = 0;
-    for (; j < kc; ++j) {
-        // remaining norm and pivot column (wavefront 0)
-        if (wv == 0) {
-            double t = 0.0, best = -1.0;
-            int bi = 0x7fffffff;
-            for (int c = j + lane; c < kc; c += 64) {
-                t += L.sv[c];
-                if (L.sv[c] > best || (L.sv[c] == best && c < bi)) {
-                    best = L.sv[c];
-                    bi = c;
-                }
-            }
-            t = wsum(t);
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double ob = __shfl_xor(best, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            if (lane == 0) {
-                S.s = t;
-                S.piv = bi;
-            }
-        }
-        __syncthreads();
-        const double rest = S.s;
-        const int p = S.piv;
-        if (sqrt(fmax(rest, 0.0)) <= delta) break;
-        if (p != j) {
-            for (int r = threadIdx.x; r < kc; r += WG) {
-                const zd a = Lm[(size_t)j * kc + r];
-                Lm[(size_t)j * kc + r] = Lm[(size_t)p * kc + r];
-                Lm[(size_t)p * kc + r] = a;
-            }
-            if (threadIdx.x == 0) {
-                const double sv = L.sv[j];
-                L.sv[j] = L.sv[p];
-                L.sv[p] = sv;
-                const int pm = L.perm[j];
-                L.perm[j] = L.perm[p];
-                L.perm[p] = pm;
-            }
-        }
-        __syncthreads();
-        // reflector of column j (wavefront 0): beta = -sign(Re alpha) ||x||
-        zd* aj = Lm + (size_t)j * kc;
-        if (wv == 0) {
-            double x2 = 0.0;
-            for (int r = j + 1 + lane; r < kc; r += 64) x2 += abs2(aj[r]);
-            x2 = wsum(x2);
-            if (lane == 0) {
-                const zd al = aj[j];
-                zd tau = {0.0, 0.0}, sc = {0.0, 0.0};
-                if (x2 > 0.0 || al.im != 0.0) {
-                    const double nrm = sqrt(abs2(al) + x2);
-                    const double beta = al.re >= 0.0 ? -nrm : nrm;
-                    tau = {(beta - al.re) / beta, -al.im / beta};
-                    sc = zdiv(zd{1.0, 0.0}, al - zd{beta, 0.0});
-                    aj[j] = {beta, 0.0};
-                }
-                L.tau[j] = tau;
-                S.pinv[0] = sc;
-            }
-        }
-        __syncthreads();
-        const zd sc = S.pinv[0];
-        for (int r = j + 1 + threadIdx.x; r < kc; r += WG) aj[r] = aj[r] * sc;
-        __syncthreads();
-        // apply H^H to the columns j + 1 .. kc - 1 (one wavefront per column), refresh norms
-        const zd tc = conj(L.tau[j]);
-        for (int c = j + 1 + wv; c < kc; c += WG / 64) {
-            zd* ac = Lm + (size_t)c * kc;
-            double wr = 0.0, wi = 0.0;
-            for (int r = j + lane; r < kc; r += 64) {
-                const zd v = r == j ? zd{1.0, 0.0} : aj[r];
-                const zd t = conj_mul(v, ac[r]);
-                wr += t.re;
-                wi += t.im;
-            }
-            wr = wsum(wr);
-            wi = wsum(wi);
-            const zd wv2 = tc * zd{wr, wi};
-            double s = 0.0;
-            for (int r = j + lane; r < kc; r += 64) {
-                const zd v = r == j ? zd{1.0, 0.0} : aj[r];
-                const zd a = ac[r] - v * wv2;
-                ac[r] = a;
-                if (r > j) s += abs2(a);
-            }
-            s = wsum(s);
-            if (lane == 0) L.sv[c] = s;
-        }
-        __syncthreads();
-    }
-    double rs = 0.0;
-    for (int c = j; c < kc; ++c) rs += L.sv[c];
-    *rest2 = j < kc ? rs : 0.0;
-    __syncthreads();
-    return j;
-}
-
-// One-sided Jacobi on the ncol columns (length rows, stride ld) at Lm: Lm <- B VJ with
-// orthogonal columns, rotations not accumulated.  JGL lanes of a wavefront per column pair.
-constexpr int JGL = 8;
-__device__ void lds_jacobi(zd* Lm, int rows, int ncol, int ld, AcaShared& S)
-{
-    const int np = ncol + (ncol & 1);
-    const int g = threadIdx.x / JGL, gl = threadIdx.x % JGL;
-    if (ncol < 2) return;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (threadIdx.x == 0) S.flag = 0;
-        __syncthreads();
-        for (int rnd = 0; rnd < np - 1; ++rnd) {
-            for (int pr = g; pr < np / 2; pr += WG / JGL) {
-                int p, q;
-                if (pr == 0) {
-                    p = rnd;
-                    q = np - 1;
-                } else {
-                    p = (rnd + pr) % (np - 1);
-                    q = (rnd - pr + np - 1) % (np - 1);
-                }
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                if (q >= ncol) continue;  // uniform within the lane group
-                zd* mp = Lm + (size_t)p * ld;
-                zd* mq = Lm + (size_t)q * ld;
-                double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-                for (int r = gl; r < rows; r += JGL) {
-                    const zd a = mp[r], b = mq[r];
-                    al += abs2(a);
-                    be += abs2(b);
-                    const zd c = conj_mul(a, b);
-                    gr += c.re;
-                    gi += c.im;
-                }
-#pragma unroll
-                for (int o = 1; o < JGL; o <<= 1) {
-                    al += __shfl_xor(al, o, 64);
-                    be += __shfl_xor(be, o, 64);
-                    gr += __shfl_xor(gr, o, 64);
-                    gi += __shfl_xor(gi, o, 64);
-                }
-                const double gabs = sqrt(gr * gr + gi * gi);
-                if (!(gabs > 1e-12 * sqrt(al * be)) || gabs == 0.0) continue;
-                if (gl == 0) S.flag = 1;
-                const zd e = {gr / gabs, gi / gabs};
-                const double zeta = (be - al) / (2.0 * gabs);
-                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                const zd ce = conj(e);
-                for (int r = gl; r < rows; r += JGL) {
-                    const zd a = mp[r], b = mq[r] * ce;
-                    mp[r] = c * a - s * b;
-                    mq[r] = (s * a + c * b) * e;
-                }
-            }
-            __syncthreads();
-        }
-        const int f = S.flag;
-        __syncthreads();
-        if (!f) break;
-    }
-}
-
-// Y <- R^{-1} Y in place for kk columns (column s at Y + s * ldy, kc rows; LDS or global),
-// R upper (kc x kc, column-major, global): right-looking, all threads per step.
-__device__ void backsub_cols(const zd* R, int kc, zd* Y, int ldy, int kk)
-{
-    for (int i = kc - 1; i >= 0; --i) {
-        const double d = R[(size_t)i * kc + i].re;
-        for (int s = threadIdx.x; s < kk; s += WG) {
-            const zd v = Y[(size_t)s * ldy + i];
-            Y[(size_t)s * ldy + i] = d > 0.0 ? v * (1.0 / d) : zd{0.0, 0.0};
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < i * kk; q += WG) {
-            const int t = q % i, s = q / i;
-            Y[(size_t)s * ldy + t] -= R[(size_t)i * kc + t] * Y[(size_t)s * ldy + i];
-        }
-        __syncthreads();
-    }
-}
-
-// out (rows x kk, row-major, precision T) = X (rows x kc, column-major, global) Y (kc x kk,
-// column-major in LDS); one row per thread, 16 columns per pass.
-template <typename T>
-__device__ void out_gemm(cx<T>* out, const zd* X, int rows, int kc, const zd* Y, int kk)
-{
-    constexpr int CH = 16;
-    for (int r = threadIdx.x; r < rows; r += WG) {
-        for (int s0 = 0; s0 < kk; s0 += CH) {
-            zd acc[CH];
-#pragma unroll
-            for (int u = 0; u < CH; ++u) acc[u] = {0.0, 0.0};
-            for (int t = 0; t < kc; ++t) {
-                const zd x = X[(size_t)t * rows + r];
-#pragma unroll
-                for (int u = 0; u < CH; ++u)
-                    if (s0 + u < kk) acc[u] += x * Y[(size_t)(s0 + u) * kc + t];
-            }
-#pragma unroll
-            for (int u = 0; u < CH; ++u)
-                if (s0 + u < kk) stz(out + (size_t)r * kk + s0 + u, acc[u]);
-        }
-    }
-    __syncthreads();
-}
-
-// Recompression (eq. (ACA)) of U (3m x kc), V (3n x kc), kc <= KF, in LDS:
-//   U = Q_U R_U, V = Q_V R_V (CholeskyQR, column-scaled), M = R_U R_V^H,
-//   M P = Q_M R (Householder QR with column pivoting, stopped when the remaining columns
-//   are below QRCP_FRAC tol: M ~ Q_M B with B = R_top P^T, k' rows),
-//   B^H VJ = W (one-sided Jacobi, W with orthogonal columns sigma_s), VJ_s = B W_s / sigma_s^2,
-//   so M ~ sum_s (Q_M VJ_s) sigma_s (W_s / sigma_s)^H, truncated at tol (the dropped QR part
-//   counted in the tail); Ubar_s = Q_U Q_M VJ_s sigma_s, Vbar_s = Q_V W_s / sigma_s.
-// Factors are written row-major over the face storage Hout when they take less memory than
-// the dense face (returns kk), else 0.  Scratch: G = T_U, VJ = T_V, RU = R_U then B^H then
-// Vbar coefficients, RV = R_V then Ubar coefficients, M = the pivoted QR.
-template <typename T>
-__device__ int face_recompress_lds(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol,
-                                   RecompShared& L, AcaShared& S)
-{
-    zd* Lm = L.m;
-    lds_qr(w.U, 3 * m, kc, w.RU, w.G, Lm, L, S);
-    lds_qr(w.V, 3 * n, kc, w.RV, w.VJ, Lm, L, S);
-    for (int q = threadIdx.x; q < kc * kc; q += WG) {
-        const int i = q % kc, j = q / kc;
-        zd s = {0.0, 0.0};
-        for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
-        Lm[q] = s;
-    }
-    __syncthreads();
-    double rest2 = 0.0;
-    const int kq = lds_qrcp(Lm, kc, QRCP_FRAC * tol, L, S, &rest2);
-    if (kq == 0) return 0;
-    // keep the pivoted QR, form B^H (kc x kq): B^H[perm[c]][i] = conj(R[i][c]), i <= c
-    for (int q = threadIdx.x; q < kc * kc; q += WG) w.M[q] = Lm[q];
-    __syncthreads();
-    for (int q = threadIdx.x; q < kc * kq; q += WG) {
-        const int c = q % kc, i = q / kc;
-        const zd v = i <= c ? conj(w.M[(size_t)c * kc + i]) : zd{0.0, 0.0};
-        Lm[(size_t)i * kc + L.perm[c]] = v;
-        w.RU[(size_t)i * kc + L.perm[c]] = v;
-    }
-    __syncthreads();
-    lds_jacobi(Lm, kc, kq, kc, S);
-    for (int c = threadIdx.x; c < kq; c += WG) {
-        double s = 0.0;
-        for (int r = 0; r < kc; ++r) s += abs2(Lm[(size_t)c * kc + r]);
-        L.sv[c] = sqrt(s);
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < kq; c += WG) {
-        const double sc = L.sv[c];
-        int rank = 0;
-        for (int c2 = 0; c2 < kq; ++c2) {
-            const double s2 = L.sv[c2];
-            rank += (s2 > sc || (s2 == sc && c2 < c)) ? 1 : 0;
-        }
-        L.order[rank] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = rest2;
-        for (int c = 0; c < kq; ++c) tot += L.sv[c] * L.sv[c];
-        int kk = kq;
-        double tail = rest2;
-        while (kk > 0) {
-            const double s = L.sv[L.order[kk - 1]];
-            if (sqrt(tail + s * s) <= tol) {
-                tail += s * s;
-                --kk;
-            } else {
-                break;
-            }
-        }
-        if (tot > 0.0 && kk == 0) kk = 1;
-        if ((long long)kk * (m + n) >= 3LL * m * n) kk = 0;
-        S.piv = kk;
-    }
-    __syncthreads();
-    const int kk = S.piv;
-    if (kk <= 0) return 0;
-    // Ubar coefficients -> RV: sigma_s Q_M [VJ_s; 0], VJ_s = B W_s / sigma_s^2 (kq entries)
-    for (int q = threadIdx.x; q < kc * kk; q += WG) {
-        const int i = q % kc, s = q / kc;
-        zd v = {0.0, 0.0};
-        if (i < kq) {
-            const int c = L.order[s];
-            const double sg = L.sv[c];
-            for (int r = 0; r < kc; ++r) v += conj_mul(w.RU[(size_t)i * kc + r], Lm[(size_t)c * kc + r]);
-            v = sg > 0.0 ? v * (1.0 / sg) : zd{0.0, 0.0};
-        }
-        w.RV[(size_t)s * kc + i] = v;
-    }
-    __syncthreads();
-    // Vbar coefficients -> RU: W_s / sigma_s
-    for (int q = threadIdx.x; q < kc * kk; q += WG) {
-        const int r = q % kc, s = q / kc;
-        const int c = L.order[s];
-        const double sg = L.sv[c];
-        w.RU[(size_t)s * kc + r] = sg > 0.0 ? Lm[(size_t)c * kc + r] * (1.0 / sg) : zd{0.0, 0.0};
-    }
-    __syncthreads();
-    cx<T>* Ub = Hout;
-    cx<T>* Vb = Hout + (size_t)3 * m * kk;
-    for (int q = threadIdx.x; q < kc * kk; q += WG) Lm[q] = w.RV[q];
-    __syncthreads();
-    // apply Q_M = H_0 ... H_{kq-1} (H = I - tau v v^H) to the Ubar coefficients, one
-    // wavefront per column
-    {
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int jq = kq - 1; jq >= 0; --jq) {
-            const zd tj = L.tau[jq];
-            const zd* vj = w.M + (size_t)jq * kc;
-            for (int s = wv; s < kk; s += WG / 64) {
-                zd* y = Lm + (size_t)s * kc;
-                double dr = 0.0, di = 0.0;
-                for (int r = jq + lane; r < kc; r += 64) {
-                    const zd t = r == jq ? y[r] : conj_mul(vj[r], y[r]);
-                    dr += t.re;
-                    di += t.im;
-                }
-                dr = wsum(dr);
-                di = wsum(di);
-                const zd f = tj * zd{dr, di};
-                for (int r = jq + lane; r < kc; r += 64) y[r] -= (r == jq ? zd{1.0, 0.0} : vj[r]) * f;
-            }
-            __syncthreads();
-        }
-    }
-    backsub_cols(w.G, kc, Lm, kc, kk);
-    out_gemm(Ub, w.U, 3 * m, kc, Lm, kk);
-    for (int q = threadIdx.x; q < kc * kk; q += WG) Lm[q] = w.RU[q];
-    __syncthreads();
-    backsub_cols(w.VJ, kc, Lm, kc, kk);
-    out_gemm(Vb, w.V, 3 * n, kc, Lm, kk);
-    return kk;
-}
-
 // ACA stage of one stored dense face: ||H||_F, the pivot scale max |H|, then face_aca;
 // returns the column count (-1: not resolved, or a zero face).
 template <typename T>
@@ -1469,16 +625,6 @@ __device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, in
     return v1[0] > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, S) : -1;
 }
 
-// Recompression stage: kk > 0 (factors written over the face) or 0 (kept dense).
-template <typename T>
-__device__ int face_recompress_stage(cx<T>* H, int m, int n, const AcaWork& w, int kc, double tol, RecompShared& L,
-                                     AcaShared& S)
-{
-    if (kc <= 0) return 0;
-    if (kc <= KF) return face_recompress_lds(H, m, n, w, kc, tol, L, S);
-    return face_recompress(H, m, n, w, kc, tol, S);
-}
-
 // Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
 // face-fibre term errs by at most about eps_aca ||C^(r)||_F.
 __device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f, AcaShared& S)
@@ -1492,8 +638,9 @@ __device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f, AcaS
 }
 
 // Per-slice ACA pass, one workgroup per listed face (items (block << 8) | d, scratch slot =
-// position in the list): k_face_aca leaves the ACA columns in the slot, k_face_recomp
-// recompresses them and rewrites the face descriptor.
+// position in the list): k_face_aca leaves the ACA columns, their count and the face's
+// tolerance in the slot; k_face_recomp (recomp.hip) recompresses them and rewrites the face
+// descriptor.
 __global__ __launch_bounds__(WG) void k_face_aca(CompressArgs A)
 {
     __shared__ AcaShared S;
@@ -1504,41 +651,16 @@ __global__ __launch_bounds__(WG) void k_face_aca(CompressArgs A)
     const int m = B.rs, n = B.cs;
     AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
     int kc = -1;
+    double tol = 0.0;
     if (f.kk == 0 && !f.sel) {
         const int cap = min(A.kmax, face_aca_cap(m, n));
-        const double tol = face_tol(A, b, f, S);
+        tol = face_tol(A, b, f, S);
         kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, S)
                     : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, S);
     }
-    if (threadIdx.x == 0) w.info[0] = kc;
-}
-
-__global__ __launch_bounds__(WG) void k_face_recomp(CompressArgs A)
-{
-    __shared__ AcaShared S;
-    __shared__ RecompShared L;
-    const int item = A.list[blockIdx.x];
-    const int b = item >> 8, d = item & 255;
-    const BlockIn B = A.blocks[b];
-    FaceDesc* fp = A.faces + (size_t)b * A.L + d;
-    const FaceDesc f = *fp;
-    if (f.kk != 0 || f.sel) return;
-    const int m = B.rs, n = B.cs;
-    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
-    const int kc = w.info[0];
-    int kk = 0;
-    if (kc > 0) {
-        const double tol = face_tol(A, b, f, S);
-        kk = f.fp32 ? face_recompress_stage((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L, S)
-                    : face_recompress_stage((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L, S);
-    }
     if (threadIdx.x == 0) {
-        if (kk > 0) {
-            fp->kk = kk;
-            atomicAdd((unsigned long long*)&A.st[b].aca_cols, (unsigned long long)kc);
-        } else {
-            atomicAdd(&A.st[b].aca_dense, 1);
-        }
+        w.info[0] = kc;
+        w.tol[0] = tol;
     }
 }
 
@@ -1595,7 +717,7 @@ __global__ __launch_bounds__(64) void k_pivot(CompressArgs A)
 // ---------------------------------------------------------------- fibres
 
 // GEN: blocks whose pivot pair takes the near or self rule (else the regular rule)
-template <bool GEN>
+template <int KOP, bool GEN>
 __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
 {
     __shared__ Red S;
@@ -1608,7 +730,7 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
     const int piv = A.st[b].piv;
     const int pi = piv / n, pj = piv - (piv / n) * n;
     {
-        const bool gen = A.op != OP_TABLE && pair_class(A.c.geo, B.rb + pi, B.cb + pj, A.c.qt) != CLS_REGULAR;
+        const bool gen = KOP != 2 && pair_class(A.c.geo, B.rb + pi, B.cb + pj, A.c.qt) != CLS_REGULAR;
         if (gen != GEN) return;
     }
     if (threadIdx.x < 9) Pi_s[threadIdx.x] = A.st[b].pinv[threadIdx.x];
@@ -1625,21 +747,19 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
         const int k = k0 + threadIdx.x / lpp;
         blk E = blk_zero();
         if (k < L) {
-            if constexpr (!GEN) {
-                if (A.op == OP_TABLE) E = entry_dispatch<false>(A.c, OP_TABLE, gi, gj, k);
-                else if (B.f32)
-                    entry_regular<float>(A.c.geo, A.op == OP_V ? 0 : 1, gi, gj, A.c.fr.sf[k], A.c.fr.sinvf[k], A.c.mf, E);
-                else
-                    entry_regular<double>(A.c.geo, A.op == OP_V ? 0 : 1, gi, gj, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, E);
+            if constexpr (KOP == 2) {
+                E = entry_dispatch<false>(A.c, OP_TABLE, gi, gj, k);
+            } else if constexpr (!GEN) {
+                if (B.f32) entry_regular<float>(A.c.geo, KOP, gi, gj, A.c.fr.sf[k], A.c.fr.sinvf[k], A.c.mf, E);
+                else entry_regular<double>(A.c.geo, KOP, gi, gj, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, E);
             } else {
                 for (int uu = u; uu < nu; uu += lpp) {
                     blk e;
-                    if (A.op == OP_V) entry_unit<0>(A.c.geo, gi, gj, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
-                    else entry_unit<1>(A.c.geo, gi, gj, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
+                    entry_unit<KOP>(A.c.geo, gi, gj, cls, uu, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, A.c.qt, e);
 #pragma unroll
                     for (int t = 0; t < 9; ++t) E.a[t] += e.a[t];
                 }
-                if (u == 0 && A.op == OP_HK && gi == gj) {
+                if (u == 0 && KOP == 1 && gi == gj) {
                     E.a[0].re += 0.5;
                     E.a[4].re += 0.5;
                     E.a[8].re += 0.5;
@@ -1828,24 +948,20 @@ __global__ __launch_bounds__(WG) void k_fallback_face(CompressArgs A, int kf)
         atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(TILE, m * n - t * TILE)));
 }
 
-// the same pass on one given matrix: out[0] = ACA columns, out[1] = kk
+// the ACA stage on one given matrix: out[0] = ACA columns (the recompression follows in
+// k_aca_matrix_recomp, which sets out[1])
 __global__ __launch_bounds__(WG) void k_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax,
                                                    double* scratch, int* out)
 {
     __shared__ AcaShared S;
-    __shared__ RecompShared L;
     AcaWork w = aca_work(scratch, m, n, kmax);
-    int kc, kk;
-    if (fp32) {
-        kc = face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, S);
-        kk = face_recompress_stage((cx<float>*)H, m, n, w, kc, tol, L, S);
-    } else {
-        kc = face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, S);
-        kk = face_recompress_stage((cx<double>*)H, m, n, w, kc, tol, L, S);
-    }
+    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, S)
+                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, S);
     if (threadIdx.x == 0) {
         out[0] = kc;
-        out[1] = kk;
+        out[1] = 0;
+        w.info[0] = kc;
+        w.tol[0] = tol;
     }
 }
 
@@ -1907,7 +1023,7 @@ void launch_face_dense(const CompressArgs& A, int path, hipStream_t st)
 void launch_face_aca(const CompressArgs& A, hipStream_t st)
 {
     BEM_LAUNCH(k_face_aca, A.nlist, WG, A);
-    BEM_LAUNCH(k_face_recomp, A.nlist, WG, A);
+    launch_face_recomp(A, st);
 }
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
                      unsigned char* cls, hipStream_t st)
@@ -1917,8 +1033,15 @@ void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, co
 void launch_pivot(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_pivot, (A.nlist + 63) / 64, 64, A); }
 void launch_fibre(const CompressArgs& A, hipStream_t st)
 {
-    BEM_LAUNCH(k_fibre<false>, A.nlist, WG, A);
-    BEM_LAUNCH(k_fibre<true>, A.nlist, WG, A);
+    if (A.op == OP_TABLE) {
+        BEM_LAUNCH((k_fibre<2, false>), A.nlist, WG, A);
+    } else if (A.op == OP_V) {
+        BEM_LAUNCH((k_fibre<0, false>), A.nlist, WG, A);
+        BEM_LAUNCH((k_fibre<0, true>), A.nlist, WG, A);
+    } else {
+        BEM_LAUNCH((k_fibre<1, false>), A.nlist, WG, A);
+        BEM_LAUNCH((k_fibre<1, true>), A.nlist, WG, A);
+    }
 }
 void launch_cross_dense(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_cross_dense, A.nlist, WG, A); }
 void launch_final(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_final, (A.nlist + 63) / 64, 64, A); }
@@ -1938,6 +1061,7 @@ void launch_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int
                        hipStream_t st)
 {
     BEM_LAUNCH(k_aca_matrix, 1, WG, H, m, n, fp32, tol, cap, kmax, scratch, out);
+    launch_aca_matrix_recomp(H, m, n, fp32, kmax, scratch, out, st);
 }
 
 }  // namespace bem

@@ -93,6 +93,43 @@ __host__ __device__ inline int face_aca_cap(int m, int n)
     return 3 * (s < m ? (s < n ? s : n) : (m < n ? m : n));
 }
 
+// Scratch slot of one face in the per-slice ACA pass: ACA columns and the small matrices of
+// the recompression.
+struct AcaWork {
+    zd *U, *V;        // 3m x kmax, 3n x kmax column-major
+    zd *G, *RU, *RV;  // kmax x kmax
+    zd *M, *VJ;       // kmax x kmax
+    double* tol;      // [0]: absolute tolerance of the face in this slot
+    int* usedrow;     // m
+    int* order;       // kmax
+    int* info;        // [0]: ACA columns of the face in this slot (-1: not resolved)
+};
+
+__device__ inline AcaWork aca_work(double* base, int m, int n, int kmax)
+{
+    AcaWork w;
+    zd* z = (zd*)base;
+    w.U = z;
+    z += (size_t)3 * m * kmax;
+    w.V = z;
+    z += (size_t)3 * n * kmax;
+    w.G = z;
+    z += (size_t)kmax * kmax;
+    w.RU = z;
+    z += (size_t)kmax * kmax;
+    w.RV = z;
+    z += (size_t)kmax * kmax;
+    w.M = z;
+    z += (size_t)kmax * kmax;
+    w.VJ = z;
+    z += (size_t)kmax * kmax;
+    w.tol = (double*)z;
+    w.usedrow = (int*)(w.tol + kmax);
+    w.order = w.usedrow + m;
+    w.info = w.order + kmax;
+    return w;
+}
+
 size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
 void launch_init(const CompressArgs& A, hipStream_t st);
 // path: 1 / 2 regular tiles with complex64 / complex128 faces (k_face_dense, FP32 / FP64
@@ -108,10 +145,13 @@ void launch_cross_dense(const CompressArgs& A, hipStream_t st);
 void launch_final(const CompressArgs& A, hipStream_t st);
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st);
 void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st);
+// per-slice ACA (k_face_aca) then the recompression of its columns (k_face_recomp)
 void launch_face_aca(const CompressArgs& A, hipStream_t st);
+void launch_face_recomp(const CompressArgs& A, hipStream_t st);
 void launch_copy_segments(const char* src, char* dst, const long long* seg, int nseg, hipStream_t st);
 void launch_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax, double* scratch, int* out,
                        hipStream_t st);
+void launch_aca_matrix_recomp(char* H, int m, int n, int fp32, int kmax, double* scratch, int* out, hipStream_t st);
 
 // ---------------------------------------------------------------- apply (apply.hip)
 
