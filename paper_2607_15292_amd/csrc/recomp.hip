@@ -35,6 +35,9 @@ constexpr int KF = 96;          // largest core (ACA columns)
 // SVD truncation of the kept rows then has sqrt(1 - QRCP_FRAC^2) of the tolerance left.
 constexpr double QRCP_FRAC = 0.25;
 
+// Pairs of the Jacobi SVD whose inner product is below JAC_GMIN tol^2 are left as they are.
+constexpr double JAC_GMIN = 1e-6;
+
 // Smallest Cholesky pivot of the column-scaled Gram (unit diagonal) that a single CholeskyQR
 // accepts: below it (condition above ~1e5) the factor is refined by a second pass.
 constexpr double CQ2_PIVOT = 1e-10;
@@ -49,6 +52,29 @@ __device__ __forceinline__ double wsum(double v)
     return v;
 }
 
+// Lanes per column in the column updates of the pivoted QR and the reflector application:
+// a group's reduction tree and scalar work are replicated over its lanes, so groups are
+// narrower than a wavefront.
+constexpr int CG = 16;
+
+// sum over the aligned group of CG lanes
+__device__ __forceinline__ double gsum(double v)
+{
+#pragma unroll
+    for (int o = CG >> 1; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// 1 / sqrt(x) in FP64 to a few ulp: the hardware reciprocal square root refined by two
+// Newton steps (y <- y (3 - x y^2) / 2), for positive normal x
+__device__ __forceinline__ double rsqrt_d(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
 // orders the LDS accesses of the lanes of one wavefront (no hardware wait is needed: a
 // wavefront's LDS instructions complete in order)
 __device__ __forceinline__ void wave_sync()
@@ -57,22 +83,35 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// LDS matrices use the odd leading dimension kc | 1: with complex128 entries (4 banks each),
+// an odd stride keeps the accesses of a row (stride ld) of 8 consecutive lanes in distinct
+// banks.
+constexpr int LMS = KF * (KF + 1);
+
 struct Rs {
-    zd m[KF * KF];  // kc x kc working matrix, column-major with ld kc; Gram staging area
+    zd m[LMS];      // kc x kc working matrix, column-major with ld = kc | 1; Gram staging area
     zd tau[KF];     // reflector coefficients of the pivoted QR
-    double sv[KF];  // column scales, squared column norms, singular values
+    double sv[KF];  // squared column norms, singular values
     int order[KF];  // singular values by decreasing size
     int perm[KF];   // column order of the pivoted QR
+    double du[KF];  // column norms of U and V (1 once applied to the columns themselves)
+    double dv[KF];
     double s;
     int piv, flag;
 };
 
-// Lm = X^H X (kc x kc, full Hermitian) for X (rows x kc, column-major, global).  A thread
-// owns up to two 2 x 2 tiles of the upper triangle; X is staged through Lm in row chunks.
-__device__ void gram(const zd* X, int rows, int kc, zd* Lm)
+// 32 x 32 thread grid for the element loops over small matrices
+__device__ __forceinline__ int gx() { return threadIdx.x & 31; }
+__device__ __forceinline__ int gy() { return threadIdx.x >> 5; }
+
+// Lm = X^H X (kc x kc, full Hermitian, ld) for X (rows x kc, column-major, global).  A
+// thread owns up to two 2 x 2 tiles of the upper triangle.  Row chunks of X are staged
+// through Lm in two planes (even and odd columns), so that the lanes of a tile row read
+// consecutive entries.
+__device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
 {
-    const int nt = (kc + 1) >> 1, ntri = nt * (nt + 1) / 2, kp = 2 * nt;
-    const int cr = min(rows, (KF * KF) / kp);
+    const int nt = (kc + 1) >> 1, ntri = nt * (nt + 1) / 2;
+    const int cr = min(rows, LMS / (2 * nt)), pl = cr * nt;
     int ti[2], tj[2];
     bool act[2];
 #pragma unroll
@@ -94,20 +133,30 @@ __device__ void gram(const zd* X, int rows, int kc, zd* Lm)
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[h][u] = {0.0, 0.0};
     for (int r0 = 0; r0 < rows; r0 += cr) {
-        const int nr = min(cr, rows - r0);
+        const int nr = min(cr, rows - r0), tot = nr * 2 * nt;
         __syncthreads();
-        for (int q = threadIdx.x; q < nr * kp; q += NT) {
-            const int c = q / nr, r = q - c * nr;
-            Lm[r * kp + c] = c < kc ? X[(size_t)c * rows + r0 + r] : zd{0.0, 0.0};
+        for (int q0 = 0; q0 < tot; q0 += 4 * NT) {
+            zd v[4];
+            int o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + threadIdx.x + u * NT;
+                const int c = q / nr, r = q - c * nr;
+                o[u] = q < tot ? (c & 1) * pl + r * nt + (c >> 1) : -1;
+                v[u] = q < tot && c < kc ? X[(size_t)c * rows + r0 + r] : zd{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (o[u] >= 0) Lm[o[u]] = v[u];
         }
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (!act[h]) continue;
-            const zd* pa = Lm + 2 * ti[h];
-            const zd* pb = Lm + 2 * tj[h];
+            const zd* pa = Lm + ti[h];
+            const zd* pb = Lm + tj[h];
             for (int r = 0; r < nr; ++r) {
-                const zd a0 = pa[r * kp], a1 = pa[r * kp + 1], b0 = pb[r * kp], b1 = pb[r * kp + 1];
+                const zd a0 = pa[r * nt], a1 = pa[pl + r * nt], b0 = pb[r * nt], b1 = pb[pl + r * nt];
                 acc[h][0] += conj_mul(a0, b0);
                 acc[h][1] += conj_mul(a0, b1);
                 acc[h][2] += conj_mul(a1, b0);
@@ -123,8 +172,8 @@ __device__ void gram(const zd* X, int rows, int kc, zd* Lm)
         for (int u = 0; u < 4; ++u) {
             const int i = 2 * ti[h] + (u >> 1), j = 2 * tj[h] + (u & 1);
             if (i < kc && j < kc && i <= j) {
-                Lm[(size_t)j * kc + i] = acc[h][u];
-                Lm[(size_t)i * kc + j] = conj(acc[h][u]);
+                Lm[(size_t)j * ld + i] = acc[h][u];
+                Lm[(size_t)i * ld + j] = conj(acc[h][u]);
             }
         }
     }
@@ -135,44 +184,41 @@ __device__ void gram(const zd* X, int rows, int kc, zd* Lm)
 // zeroed); a pivot without positive mass gives a zero row.  Step k updates the trailing
 // matrix from the unscaled row k (divided by the pivot) and scales row k - 1 with the pivot
 // read one step earlier.  Returns the smallest pivot (before the square root).
-__device__ double cholesky(zd* Lm, int kc)
+__device__ double cholesky(zd* Lm, int kc, int ld)
 {
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int tx = gx(), ty = gy();
     double pmin = 1e300, pprev = 0.0;
     for (int k = 0; k < kc; ++k) {
-        const double p = Lm[(size_t)k * kc + k].re;
+        const double p = Lm[(size_t)k * ld + k].re;
         pmin = fmin(pmin, p);
         if (k > 0) {
             const int kr = k - 1;
             const double rk = pprev > 1e-24 ? sqrt(pprev) : 0.0;
             for (int j = kr + threadIdx.x; j < kc; j += NT) {
-                zd* e = Lm + (size_t)j * kc + kr;
+                zd* e = Lm + (size_t)j * ld + kr;
                 *e = j == kr ? zd{rk, 0.0} : (rk > 0.0 ? *e * (1.0 / rk) : zd{0.0, 0.0});
             }
         }
         if (p > 1e-24) {
             const double ip = 1.0 / p;
             for (int j = k + 1 + ty; j < kc; j += 32) {
-                const zd rj = Lm[(size_t)j * kc + k] * ip;
-                for (int i = k + 1 + tx; i <= j; i += 32) Lm[(size_t)j * kc + i] -= conj_mul(Lm[(size_t)i * kc + k], rj);
+                const zd rj = Lm[(size_t)j * ld + k] * ip;
+                for (int i = k + 1 + tx; i <= j; i += 32) Lm[(size_t)j * ld + i] -= conj_mul(Lm[(size_t)i * ld + k], rj);
             }
         }
         pprev = p;
         __syncthreads();
     }
-    if (threadIdx.x == 0 && kc > 0) {
-        zd* e = Lm + (size_t)(kc - 1) * kc + kc - 1;
-        *e = {pprev > 1e-24 ? sqrt(pprev) : 0.0, 0.0};
-    }
-    for (int q = threadIdx.x; q < kc * kc; q += NT)
-        if (q % kc > q / kc) Lm[q] = {0.0, 0.0};
+    if (threadIdx.x == 0 && kc > 0) Lm[(size_t)(kc - 1) * ld + kc - 1] = {pprev > 1e-24 ? sqrt(pprev) : 0.0, 0.0};
+    for (int j = ty; j < kc; j += 32)
+        for (int i = j + 1 + tx; i < kc; i += 32) Lm[(size_t)j * ld + i] = {0.0, 0.0};
     __syncthreads();
     return pmin;
 }
 
-// X (rows x kc, column-major, global) <- X R^{-1}, R upper in Lm; one row per thread, blocks
-// of 8 columns; zero pivots give zero columns.
-__device__ void trsm(zd* X, int rows, const zd* Lm, int kc)
+// X (rows x kc, column-major, global) <- X R^{-1}, R upper in Lm (ld); one row per thread,
+// blocks of 8 columns; zero pivots give zero columns.
+__device__ void trsm(zd* X, int rows, const zd* Lm, int kc, int ld)
 {
     constexpr int NB = 8;
     for (int r = threadIdx.x; r < rows; r += NT) {
@@ -185,15 +231,16 @@ __device__ void trsm(zd* X, int rows, const zd* Lm, int kc)
                 const zd x = X[(size_t)i * rows + r];
 #pragma unroll
                 for (int t = 0; t < NB; ++t)
-                    if (t < nb) acc[t] -= x * Lm[(size_t)(j0 + t) * kc + i];
+                    if (t < nb) acc[t] -= x * Lm[(size_t)(j0 + t) * ld + i];
             }
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
-                if (t >= nb) break;
+                if (t < nb) {
 #pragma unroll
-                for (int u = 0; u < t; ++u) acc[t] -= acc[u] * Lm[(size_t)(j0 + t) * kc + j0 + u];
-                const double d = Lm[(size_t)(j0 + t) * kc + j0 + t].re;
-                acc[t] = d > 0.0 ? acc[t] * (1.0 / d) : zd{0.0, 0.0};
+                    for (int u = 0; u < t; ++u) acc[t] -= acc[u] * Lm[(size_t)(j0 + t) * ld + j0 + u];
+                    const double d = Lm[(size_t)(j0 + t) * ld + j0 + t].re;
+                    acc[t] = d > 0.0 ? acc[t] * (1.0 / d) : zd{0.0, 0.0};
+                }
             }
 #pragma unroll
             for (int t = 0; t < NB; ++t)
@@ -203,65 +250,77 @@ __device__ void trsm(zd* X, int rows, const zd* Lm, int kc)
     __syncthreads();
 }
 
-// Column scaling + CholeskyQR of X (rows x kc), repeated once when the first pass meets a
-// pivot below CQ2_PIVOT.  On return Q = X T^{-1} with T upper in Tout (X holds X D^{-1}, or
-// X D^{-1} R1^{-1} after two passes) and R = R_fact D in Rout, R_fact the triangular factor
-// of X D^{-1}; both kc x kc column-major in global scratch.
-__device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, Rs& L)
+// CholeskyQR of X (rows x kc) with column scaling, repeated once when the first pass meets a
+// pivot below CQ2_PIVOT.  The first pass scales the Gram (D^-1 X^H X D^-1, D the column
+// norms, kept in dsc) instead of X.  On return Q = X dsc^-1 T^{-1} with T upper in Tout
+// (after two passes X holds X D^{-1} R1^{-1} and dsc is 1) and R = R_fact D in Rout, R_fact
+// the triangular factor of X D^{-1}; both kc x kc column-major (ld kc) in global scratch.
+__device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, double* dsc, Rs& L, int ld)
 {
     zd* Lm = L.m;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = wv; c < kc; c += NW) {
-        double s = 0.0;
-        for (int r = lane; r < rows; r += 64) s += abs2(X[(size_t)c * rows + r]);
-        s = wsum(s);
-        if (lane == 0) L.sv[c] = sqrt(s);
+    const int tx = gx(), ty = gy();
+    gram(X, rows, kc, Lm, ld);
+    for (int c = threadIdx.x; c < kc; c += NT) {
+        const double g = Lm[(size_t)c * ld + c].re;
+        dsc[c] = g > 0.0 ? sqrt(g) : 0.0;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < rows * kc; q += NT) {
-        const double dc = L.sv[q / rows];
-        X[q] = dc > 0.0 ? X[q] * (1.0 / dc) : zd{0.0, 0.0};
-    }
-    __syncthreads();
-    gram(X, rows, kc, Lm);
-    const double pmin = cholesky(Lm, kc);
-    if (pmin >= CQ2_PIVOT) {
-        for (int q = threadIdx.x; q < kc * kc; q += NT) {
-            Tout[q] = Lm[q];
-            Rout[q] = Lm[q] * L.sv[q / kc];
+    for (int j = ty; j < kc; j += 32)
+        for (int i = tx; i < kc; i += 32) {
+            const double di = dsc[i], dj = dsc[j];
+            zd* e = Lm + (size_t)j * ld + i;
+            *e = di > 0.0 && dj > 0.0 ? *e * (1.0 / (di * dj)) : zd{0.0, 0.0};
         }
+    __syncthreads();
+    const double pmin = cholesky(Lm, kc, ld);
+    if (pmin >= CQ2_PIVOT) {
+        for (int j = ty; j < kc; j += 32)
+            for (int i = tx; i < kc; i += 32) {
+                const zd v = Lm[(size_t)j * ld + i];
+                Tout[(size_t)j * kc + i] = v;
+                Rout[(size_t)j * kc + i] = v * dsc[j];
+            }
         __syncthreads();
         return;
     }
-    trsm(X, rows, Lm, kc);
-    for (int q = threadIdx.x; q < kc * kc; q += NT) Tout[q] = Lm[q];  // R1 (for now)
-    __syncthreads();
-    gram(X, rows, kc, Lm);
-    cholesky(Lm, kc);
-    // Rout = R2 R1 D, then Tout = R2
-    for (int q = threadIdx.x; q < kc * kc; q += NT) {
-        const int i = q % kc, j = q / kc;
-        zd s = {0.0, 0.0};
-        for (int t = i; t <= j; ++t) s += Lm[(size_t)t * kc + i] * Tout[(size_t)j * kc + t];
-        Rout[q] = i <= j ? s * L.sv[j] : zd{0.0, 0.0};
+    for (int q = threadIdx.x; q < rows * kc; q += NT) {
+        const double dc = dsc[q / rows];
+        X[q] = dc > 0.0 ? X[q] * (1.0 / dc) : zd{0.0, 0.0};
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kc * kc; q += NT) Tout[q] = Lm[q];
+    trsm(X, rows, Lm, kc, ld);
+    for (int j = ty; j < kc; j += 32)
+        for (int i = tx; i < kc; i += 32) Tout[(size_t)j * kc + i] = Lm[(size_t)j * ld + i];  // R1 (for now)
+    __syncthreads();
+    gram(X, rows, kc, Lm, ld);
+    cholesky(Lm, kc, ld);
+    // Rout = R2 R1 D, then Tout = R2
+    for (int j = ty; j < kc; j += 32)
+        for (int i = tx; i < kc; i += 32) {
+            zd s = {0.0, 0.0};
+            for (int t = i; t <= j; ++t) s += Lm[(size_t)t * ld + i] * Tout[(size_t)j * kc + t];
+            Rout[(size_t)j * kc + i] = i <= j ? s * dsc[j] : zd{0.0, 0.0};
+        }
+    __syncthreads();
+    for (int j = ty; j < kc; j += 32)
+        for (int i = tx; i < kc; i += 32) Tout[(size_t)j * kc + i] = Lm[(size_t)j * ld + i];
+    for (int c = threadIdx.x; c < kc; c += NT) dsc[c] = 1.0;
     __syncthreads();
 }
 
-// Householder QR with column pivoting of Lm (kc x kc, column-major) in place: reflectors
-// H = I - tau v v^H with v[0] = 1 stored below the diagonal, stopped at the first step whose
-// remaining columns have Frobenius norm <= delta.  Returns the number of steps; tau in L.tau,
-// the column order in L.perm, the remaining squared norm in *rest2.
-__device__ int qrcp(zd* Lm, int kc, double delta, Rs& L, double* rest2)
+// Householder QR with column pivoting of Lm (kc x kc, column-major, ld) in place:
+// reflectors H = I - tau v v^H with v[0] = 1 stored below the diagonal, stopped at the first
+// step whose remaining columns have Frobenius norm <= delta.  Returns the number of steps;
+// tau in L.tau, the column order in L.perm, the remaining squared norm in *rest2.
+__device__ int qrcp(zd* Lm, int kc, int ld, double delta, Rs& L, double* rest2)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = wv; c < kc; c += NW) {
+    for (int c = threadIdx.x / CG; c < kc; c += NT / CG) {
+        const int gl = threadIdx.x % CG;
         double s = 0.0;
-        for (int r = lane; r < kc; r += 64) s += abs2(Lm[(size_t)c * kc + r]);
-        s = wsum(s);
-        if (lane == 0) {
+        for (int r = gl; r < kc; r += CG) s += abs2(Lm[(size_t)c * ld + r]);
+        s = gsum(s);
+        if (gl == 0) {
             L.sv[c] = s;
             L.perm[c] = c;
         }
@@ -294,8 +353,8 @@ __device__ int qrcp(zd* Lm, int kc, double delta, Rs& L, double* rest2)
             if (sqrt(fmax(t, 0.0)) <= delta) p = -1;
             if (p >= 0) {
                 // reflector of the pivot column (rows j..): beta = -sign(Re alpha) ||x||
-                zd* aj = Lm + (size_t)j * kc;
-                zd* ap = Lm + (size_t)p * kc;
+                zd* aj = Lm + (size_t)j * ld;
+                zd* ap = Lm + (size_t)p * ld;
                 double x2 = 0.0;
                 for (int r = j + 1 + lane; r < kc; r += 64) x2 += abs2(ap[r]);
                 x2 = wsum(x2);
@@ -329,30 +388,32 @@ __device__ int qrcp(zd* Lm, int kc, double delta, Rs& L, double* rest2)
         }
         __syncthreads();
         if (L.piv < 0) break;
-        // apply H^H to the columns j + 1 .. kc - 1 (one wavefront per column), refresh norms
+        // apply H^H to the columns j + 1 .. kc - 1 (a group of CG lanes per column), refresh
+        // the column norms
         const zd tc = conj(L.tau[j]);
-        const zd* aj = Lm + (size_t)j * kc;
-        for (int c = j + 1 + wv; c < kc; c += NW) {
-            zd* ac = Lm + (size_t)c * kc;
+        const zd* aj = Lm + (size_t)j * ld;
+        for (int c = j + 1 + threadIdx.x / CG; c < kc; c += NT / CG) {
+            const int gl = threadIdx.x % CG;
+            zd* ac = Lm + (size_t)c * ld;
             double wr = 0.0, wi = 0.0;
-            for (int r = j + lane; r < kc; r += 64) {
+            for (int r = j + gl; r < kc; r += CG) {
                 const zd v = r == j ? zd{1.0, 0.0} : aj[r];
                 const zd t = conj_mul(v, ac[r]);
                 wr += t.re;
                 wi += t.im;
             }
-            wr = wsum(wr);
-            wi = wsum(wi);
+            wr = gsum(wr);
+            wi = gsum(wi);
             const zd f = tc * zd{wr, wi};
             double s = 0.0;
-            for (int r = j + lane; r < kc; r += 64) {
+            for (int r = j + gl; r < kc; r += CG) {
                 const zd v = r == j ? zd{1.0, 0.0} : aj[r];
                 const zd a = ac[r] - v * f;
                 ac[r] = a;
                 if (r > j) s += abs2(a);
             }
-            s = wsum(s);
-            if (lane == 0) L.sv[c] = s;
+            s = gsum(s);
+            if (gl == 0) L.sv[c] = s;
         }
         __syncthreads();
     }
@@ -364,14 +425,17 @@ __device__ int qrcp(zd* Lm, int kc, double delta, Rs& L, double* rest2)
 }
 
 // One-sided Jacobi on the ncol columns (length rows <= KF, stride ld) at Lm: Lm <- B VJ with
-// orthogonal columns, rotations not accumulated.  A group of JG lanes per column pair (the
-// pair's rows in registers), round-robin pair order, one barrier per round.
-template <int JG>
-__device__ void jacobi(zd* Lm, int rows, int ncol, int ld, Rs& L)
+// orthogonal columns, rotations not accumulated.  A group of JG lanes per column pair holds
+// the pair in registers; round-robin pair order, one barrier per round.  A pair is rotated
+// while |<a, b>| > 1e-12 |a| |b| and |<a, b>| > gmin: below gmin (a small fraction of tol^2)
+// the pair's non-orthogonality cannot move the truncation at tol.
+constexpr int JG = 16;
+__device__ void jacobi(zd* Lm, int rows, int ncol, int ld, double gmin, Rs& L)
 {
     constexpr int RPL = (KF + JG - 1) / JG;
     const int np = ncol + (ncol & 1);
     const int g = threadIdx.x / JG, gl = threadIdx.x % JG;
+    const double gmin2 = gmin * gmin;
     if (ncol < 2) return;
     for (int sweep = 0; sweep < 40; ++sweep) {
         if (threadIdx.x == 0) L.flag = 0;
@@ -383,8 +447,10 @@ __device__ void jacobi(zd* Lm, int rows, int ncol, int ld, Rs& L)
                     p = rnd;
                     q = np - 1;
                 } else {
-                    p = (rnd + pr) % (np - 1);
-                    q = (rnd - pr + np - 1) % (np - 1);
+                    p = rnd + pr;
+                    p -= p >= np - 1 ? np - 1 : 0;
+                    q = rnd - pr;
+                    q += q < 0 ? np - 1 : 0;
                 }
                 if (p > q) {
                     const int t = p;
@@ -397,13 +463,16 @@ __device__ void jacobi(zd* Lm, int rows, int ncol, int ld, Rs& L)
                 zd a[RPL], b[RPL];
                 double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
 #pragma unroll
-                for (int t = 0; t < RPL; ++t) {
-                    const int r = gl + JG * t;
-                    a[t] = r < rows ? mp[r] : zd{0.0, 0.0};
-                    b[t] = r < rows ? mq[r] : zd{0.0, 0.0};
-                    al += abs2(a[t]);
-                    be += abs2(b[t]);
-                    const zd c = conj_mul(a[t], b[t]);
+                for (int u = 0; u < RPL; ++u) {
+                    const int r = gl + JG * u;
+                    a[u] = r < rows ? mp[r] : zd{0.0, 0.0};
+                    b[u] = r < rows ? mq[r] : zd{0.0, 0.0};
+                }
+#pragma unroll
+                for (int u = 0; u < RPL; ++u) {
+                    al += abs2(a[u]);
+                    be += abs2(b[u]);
+                    const zd c = conj_mul(a[u], b[u]);
                     gr += c.re;
                     gi += c.im;
                 }
@@ -414,21 +483,23 @@ __device__ void jacobi(zd* Lm, int rows, int ncol, int ld, Rs& L)
                     gr += __shfl_xor(gr, o, 64);
                     gi += __shfl_xor(gi, o, 64);
                 }
-                const double gabs = sqrt(gr * gr + gi * gi);
-                if (!(gabs > 1e-12 * sqrt(al * be)) || gabs == 0.0) continue;
+                const double g2 = gr * gr + gi * gi;
+                if (!(g2 > 1e-24 * (al * be)) || !(g2 > gmin2)) continue;
                 if (gl == 0) L.flag = 1;
-                const zd e = {gr / gabs, gi / gabs};
-                const double zeta = (be - al) / (2.0 * gabs);
+                const double ig = rsqrt_d(g2);
+                const zd e = {gr * ig, gi * ig};
+                const double zeta = (be - al) * (0.5 * ig);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                const double c = rsqrt_d(1.0 + t * t), s = c * t;
                 const zd ce = conj(e);
 #pragma unroll
                 for (int u = 0; u < RPL; ++u) {
                     const int r = gl + JG * u;
-                    if (r >= rows) break;
-                    const zd bb = b[u] * ce;
-                    mp[r] = c * a[u] - s * bb;
-                    mq[r] = (s * a[u] + c * bb) * e;
+                    if (r < rows) {
+                        const zd bb = b[u] * ce;
+                        mp[r] = c * a[u] - s * bb;
+                        mq[r] = (s * a[u] + c * bb) * e;
+                    }
                 }
             }
             __syncthreads();
@@ -439,44 +510,72 @@ __device__ void jacobi(zd* Lm, int rows, int ncol, int ld, Rs& L)
     }
 }
 
-// Y_h <- R_h^{-1} Y_h for up to two systems h (kk columns each, column s at Y_h + s kc, kc
-// rows in LDS), R_h upper (kc x kc, column-major, global); right-looking from the last row,
-// one barrier per row: step i subtracts column i of R times y_i / r_ii from the rows above,
-// and the rows are divided by their pivots at the end (zero pivots: zero rows).
-__device__ void backsub2(const zd* R0, zd* Y0, const zd* R1, zd* Y1, int kc, int kk)
+// Y_h <- D_h^{-1} R_h^{-1} Y_h for up to two systems h (kk columns each, column s at
+// Y_h + s ldy, kc rows in LDS), R_h upper (kc x kc, column-major, ld kc, global),
+// D_h = diag(d_h) (zero entries and zero pivots give zero rows).  Blocks of BS rows from the
+// bottom: a thread per column solves the diagonal block, then the rows above are updated as
+// a small GEMM; two barriers per block.
+constexpr int BS = 8;
+__device__ void backsub2(const zd* R0, const double* d0, zd* Y0, const zd* R1, const double* d1, zd* Y1, int kc,
+                         int kk, int ldy)
 {
     const int nsys = Y1 ? 2 : 1;
-    for (int i = kc - 1; i >= 1; --i) {
-        const int per = i * kk;
-        for (int q = threadIdx.x; q < nsys * per; q += NT) {
-            const bool h = q >= per;
-            const int qq = h ? q - per : q;
-            const int s = qq / i, t = qq - s * i;
+    for (int i1 = kc; i1 > 0; i1 -= BS) {
+        const int i0 = max(0, i1 - BS), nb = i1 - i0;
+        for (int q = threadIdx.x; q < nsys * kk; q += NT) {
+            const bool h = q >= kk;
             const zd* R = h ? R1 : R0;
-            const double d = R[(size_t)i * kc + i].re;
-            if (d > 0.0) {
-                zd* y = (h ? Y1 : Y0) + (size_t)s * kc;
-                y[t] -= R[(size_t)i * kc + t] * (y[i] * (1.0 / d));
+            zd* y = (h ? Y1 : Y0) + (size_t)(h ? q - kk : q) * ldy + i0;
+            zd v[BS];
+#pragma unroll
+            for (int a = 0; a < BS; ++a) v[a] = a < nb ? y[a] : zd{0.0, 0.0};
+#pragma unroll
+            for (int a = BS - 1; a >= 0; --a) {
+                if (a < nb) {
+                    const zd* Rc = R + (size_t)(i0 + a) * kc + i0;  // column i0 + a, rows i0 ..
+                    const double dg = Rc[a].re;
+                    const zd ya = dg > 0.0 ? v[a] * (1.0 / dg) : zd{0.0, 0.0};
+                    v[a] = ya;
+#pragma unroll
+                    for (int b = 0; b < a; ++b) v[b] -= Rc[b] * ya;
+                }
             }
+#pragma unroll
+            for (int a = 0; a < BS; ++a)
+                if (a < nb) y[a] = v[a];
+        }
+        __syncthreads();
+        if (i0 == 0) break;
+        for (int q = threadIdx.x; q < nsys * i0 * kk; q += NT) {
+            const bool h = q >= i0 * kk;
+            const int qq = h ? q - i0 * kk : q;
+            const int s = qq / i0, t = qq - s * i0;
+            const zd* R = h ? R1 : R0;
+            zd* y = (h ? Y1 : Y0) + (size_t)s * ldy;
+            zd acc = y[t];
+#pragma unroll
+            for (int a = 0; a < BS; ++a)
+                if (a < nb) acc -= R[(size_t)(i0 + a) * kc + t] * y[i0 + a];
+            y[t] = acc;
         }
         __syncthreads();
     }
-    for (int q = threadIdx.x; q < nsys * kc * kk; q += NT) {
-        const bool h = q >= kc * kk;
-        const int qq = h ? q - kc * kk : q;
-        const int i = qq % kc;
-        const double d = (h ? R1 : R0)[(size_t)i * kc + i].re;
-        zd* y = (h ? Y1 : Y0) + qq;
-        *y = d > 0.0 ? *y * (1.0 / d) : zd{0.0, 0.0};
+    const int tx = gx(), ty = gy();
+    for (int s = ty; s < nsys * kk; s += 32) {
+        const bool h = s >= kk;
+        const double* d = h ? d1 : d0;
+        zd* y = (h ? Y1 : Y0) + (size_t)(h ? s - kk : s) * ldy;
+        for (int i = tx; i < kc; i += 32) y[i] = d[i] > 0.0 ? y[i] * (1.0 / d[i]) : zd{0.0, 0.0};
     }
     __syncthreads();
 }
 
 // out_h (rows_h x kk, row-major, precision T) = X_h (rows_h x kc, column-major, global) Y_h
-// (kc x kk, column-major with ld kc, LDS) for two products; a thread per (row, 8 columns).
+// (kc x kk, column-major with ld ldy, LDS) for up to two products; a thread per (row, 8
+// columns).
 template <typename T>
 __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T>* o1, const zd* X1, int rows1,
-                          const zd* Y1, int kc, int kk)
+                          const zd* Y1, int kc, int kk, int ldy)
 {
     constexpr int CH = 8;
     const int nch = (kk + CH - 1) / CH;
@@ -490,11 +589,12 @@ __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T
         zd acc[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) acc[u] = {0.0, 0.0};
+#pragma unroll 8
         for (int t = 0; t < kc; ++t) {
             const zd x = X[(size_t)t * rows + r];
 #pragma unroll
             for (int u = 0; u < CH; ++u)
-                if (s0 + u < kk) acc[u] += x * Y[(size_t)(s0 + u) * kc + t];
+                if (s0 + u < kk) acc[u] += x * Y[(size_t)(s0 + u) * ldy + t];
         }
         cx<T>* out = h ? o1 : o0;
 #pragma unroll
@@ -507,39 +607,42 @@ __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T
 // Recompression of U (3m x kc), V (3n x kc) of the scratch slot w at absolute tolerance tol;
 // returns kk > 0 with the factors written over Hout, or 0 (face kept dense).  Scratch:
 // G = T_U, VJ = T_V, RU = R_U then B^H then the Vbar coefficients, RV = R_V then the Ubar
-// coefficients, M = the pivoted QR.
+// coefficients, M = the pivoted QR (all kc x kc, ld kc).
 template <typename T>
 __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L)
 {
     zd* Lm = L.m;
+    const int ld = kc | 1;
+    const int tx = gx(), ty = gy();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    chol_qr(w.U, 3 * m, kc, w.RU, w.G, L);
-    chol_qr(w.V, 3 * n, kc, w.RV, w.VJ, L);
-    for (int q = threadIdx.x; q < kc * kc; q += NT) {
-        const int i = q % kc, j = q / kc;
-        zd s = {0.0, 0.0};
-        for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
-        Lm[q] = s;
-    }
+    chol_qr(w.U, 3 * m, kc, w.RU, w.G, L.du, L, ld);
+    chol_qr(w.V, 3 * n, kc, w.RV, w.VJ, L.dv, L, ld);
+    // M = R_U R_V^H
+    for (int j = ty; j < kc; j += 32)
+        for (int i = tx; i < kc; i += 32) {
+            zd s = {0.0, 0.0};
+            for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
+            Lm[(size_t)j * ld + i] = s;
+        }
     __syncthreads();
     double rest2 = 0.0;
-    const int kq = qrcp(Lm, kc, QRCP_FRAC * tol, L, &rest2);
+    const int kq = qrcp(Lm, kc, ld, QRCP_FRAC * tol, L, &rest2);
     if (kq == 0) return 0;
     // keep the pivoted QR, form B^H (kc x kq): B^H[perm[c]][i] = conj(R[i][c]), i <= c
-    for (int q = threadIdx.x; q < kc * kc; q += NT) w.M[q] = Lm[q];
+    for (int j = ty; j < kc; j += 32)
+        for (int i = tx; i < kc; i += 32) w.M[(size_t)j * kc + i] = Lm[(size_t)j * ld + i];
     __syncthreads();
-    for (int q = threadIdx.x; q < kc * kq; q += NT) {
-        const int c = q % kc, i = q / kc;
-        const zd v = i <= c ? conj(w.M[(size_t)c * kc + i]) : zd{0.0, 0.0};
-        Lm[(size_t)i * kc + L.perm[c]] = v;
-        w.RU[(size_t)i * kc + L.perm[c]] = v;
-    }
+    for (int i = ty; i < kq; i += 32)
+        for (int c = tx; c < kc; c += 32) {
+            const zd v = i <= c ? conj(w.M[(size_t)c * kc + i]) : zd{0.0, 0.0};
+            Lm[(size_t)i * ld + L.perm[c]] = v;
+            w.RU[(size_t)i * kc + L.perm[c]] = v;
+        }
     __syncthreads();
-    if (kq / 2 <= NT / 32) jacobi<32>(Lm, kc, kq, kc, L);
-    else jacobi<16>(Lm, kc, kq, kc, L);
+    jacobi(Lm, kc, kq, ld, JAC_GMIN * tol * tol, L);
     for (int c = wv; c < kq; c += NW) {
         double s = 0.0;
-        for (int r = lane; r < kc; r += 64) s += abs2(Lm[(size_t)c * kc + r]);
+        for (int r = lane; r < kc; r += 64) s += abs2(Lm[(size_t)c * ld + r]);
         s = wsum(s);
         if (lane == 0) L.sv[c] = sqrt(s);
     }
@@ -577,66 +680,73 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     if (kk <= 0) return 0;
     // Ubar coefficients -> RV: sigma_s [VJ_s; 0] with VJ_s = B W_s / sigma_s^2 (kq entries);
     // Vbar coefficients -> RU: W_s / sigma_s
-    for (int q = threadIdx.x; q < kc * kk; q += NT) {
-        const int i = q % kc, s = q / kc;
+    for (int s = ty; s < kk; s += 32) {
         const int c = L.order[s];
         const double sg = L.sv[c];
-        zd v = {0.0, 0.0};
-        if (i < kq && sg > 0.0) {
-            for (int r = 0; r < kc; ++r) v += conj_mul(w.RU[(size_t)i * kc + r], Lm[(size_t)c * kc + r]);
-            v = v * (1.0 / sg);
+        const zd* Wc = Lm + (size_t)c * ld;
+        for (int i = tx; i < kc; i += 32) {
+            zd v = {0.0, 0.0};
+            if (i < kq && sg > 0.0) {
+                const zd* Bi = w.RU + (size_t)i * kc;
+                for (int r = 0; r < kc; ++r) v += conj_mul(Bi[r], Wc[r]);
+                v = v * (1.0 / sg);
+            }
+            w.RV[(size_t)s * kc + i] = v;
         }
-        w.RV[(size_t)s * kc + i] = v;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kc * kk; q += NT) {
-        const int r = q % kc, s = q / kc;
+    for (int s = ty; s < kk; s += 32) {
         const int c = L.order[s];
         const double sg = L.sv[c];
-        w.RU[(size_t)s * kc + r] = sg > 0.0 ? Lm[(size_t)c * kc + r] * (1.0 / sg) : zd{0.0, 0.0};
+        for (int r = tx; r < kc; r += 32)
+            w.RU[(size_t)s * kc + r] = sg > 0.0 ? Lm[(size_t)c * ld + r] * (1.0 / sg) : zd{0.0, 0.0};
     }
     __syncthreads();
-    // Lm = [Ubar coefficients | Vbar coefficients] when both fit, else one at a time
-    const bool both = 2 * kc * kk <= KF * KF;
+    // Lm = [Ubar coefficients | Vbar coefficients] (columns of stride ld) when both fit, else
+    // one at a time
+    const bool both = 2 * ld * kk <= LMS;
     zd* Yu = Lm;
-    zd* Yv = both ? Lm + (size_t)kc * kk : nullptr;
-    for (int q = threadIdx.x; q < kc * kk; q += NT) {
-        Yu[q] = w.RV[q];
-        if (both) Yv[q] = w.RU[q];
-    }
+    zd* Yv = both ? Lm + (size_t)ld * kk : nullptr;
+    for (int s = ty; s < kk; s += 32)
+        for (int i = tx; i < kc; i += 32) {
+            Yu[(size_t)s * ld + i] = w.RV[(size_t)s * kc + i];
+            if (both) Yv[(size_t)s * ld + i] = w.RU[(size_t)s * kc + i];
+        }
     __syncthreads();
-    // apply Q_M = H_0 ... H_{kq-1} (H = I - tau v v^H) to the Ubar coefficients, one
-    // wavefront per column
+    // apply Q_M = H_0 ... H_{kq-1} (H = I - tau v v^H) to the Ubar coefficients, a group of
+    // CG lanes per column
     for (int jq = kq - 1; jq >= 0; --jq) {
         const zd tj = L.tau[jq];
         const zd* vj = w.M + (size_t)jq * kc;
-        for (int s = wv; s < kk; s += NW) {
-            zd* y = Yu + (size_t)s * kc;
+        const int gl = threadIdx.x % CG;
+        for (int s = threadIdx.x / CG; s < kk; s += NT / CG) {
+            zd* y = Yu + (size_t)s * ld;
             double dr = 0.0, di = 0.0;
-            for (int r = jq + lane; r < kc; r += 64) {
+            for (int r = jq + gl; r < kc; r += CG) {
                 const zd t = r == jq ? y[r] : conj_mul(vj[r], y[r]);
                 dr += t.re;
                 di += t.im;
             }
-            dr = wsum(dr);
-            di = wsum(di);
+            dr = gsum(dr);
+            di = gsum(di);
             const zd f = tj * zd{dr, di};
-            for (int r = jq + lane; r < kc; r += 64) y[r] -= (r == jq ? zd{1.0, 0.0} : vj[r]) * f;
+            for (int r = jq + gl; r < kc; r += CG) y[r] -= (r == jq ? zd{1.0, 0.0} : vj[r]) * f;
         }
         __syncthreads();
     }
     cx<T>* Ub = Hout;
     cx<T>* Vb = Hout + (size_t)3 * m * kk;
     if (both) {
-        backsub2(w.G, Yu, w.VJ, Yv, kc, kk);
-        out_gemm2(Ub, w.U, 3 * m, Yu, Vb, w.V, 3 * n, Yv, kc, kk);
+        backsub2(w.G, L.du, Yu, w.VJ, L.dv, Yv, kc, kk, ld);
+        out_gemm2(Ub, w.U, 3 * m, Yu, Vb, w.V, 3 * n, Yv, kc, kk, ld);
     } else {
-        backsub2(w.G, Yu, nullptr, nullptr, kc, kk);
-        out_gemm2<T>(Ub, w.U, 3 * m, Yu, nullptr, nullptr, 0, nullptr, kc, kk);
-        for (int q = threadIdx.x; q < kc * kk; q += NT) Lm[q] = w.RU[q];
+        backsub2(w.G, L.du, Yu, nullptr, nullptr, nullptr, kc, kk, ld);
+        out_gemm2<T>(Ub, w.U, 3 * m, Yu, nullptr, nullptr, 0, nullptr, kc, kk, ld);
+        for (int s = ty; s < kk; s += 32)
+            for (int i = tx; i < kc; i += 32) Lm[(size_t)s * ld + i] = w.RU[(size_t)s * kc + i];
         __syncthreads();
-        backsub2(w.VJ, Lm, nullptr, nullptr, kc, kk);
-        out_gemm2<T>(Vb, w.V, 3 * n, Lm, nullptr, nullptr, 0, nullptr, kc, kk);
+        backsub2(w.VJ, L.dv, Lm, nullptr, nullptr, nullptr, kc, kk, ld);
+        out_gemm2<T>(Vb, w.V, 3 * n, Lm, nullptr, nullptr, 0, nullptr, kc, kk, ld);
     }
     return kk;
 }
