@@ -491,6 +491,36 @@ struct AcaShared {
     int piv, flag;
 };
 
+// ---------------------------------------------------------------- per-slice ACA
+//
+// One wavefront per face: a lane per block column (row pass) or block row (column pass),
+// wavefront reductions, no LDS.  The ACA is bound by the latency of reading the stored face
+// and the earlier columns, so many faces per CU (small register footprint) beat many lanes
+// per face.
+constexpr int WA = 64;
+
+__device__ __forceinline__ double wmax(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// argmax over the wavefront with ties to the smallest index; NaN counts as -inf
+__device__ __forceinline__ void wargmax(double& v, int& idx)
+{
+    if (!(v == v)) v = -1.0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(idx, o, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+}
+
 // block (i, j) of the stored face H (3m x 3n row-major) minus the cross approximation U V^H
 template <typename T>
 __device__ __forceinline__ blk aca_residual(const cx<T>* H, int m, int n, const AcaWork& w, int kc, int i, int j)
@@ -501,12 +531,16 @@ __device__ __forceinline__ blk aca_residual(const cx<T>* H, int m, int n, const 
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) E.a[3 * a + c] = ldz(H + (size_t)(3 * i + a) * ld + 3 * j + c);
+    const zd* up = w.U + 3 * i;
+    const zd* vp = w.V + 3 * j;
+    const size_t su = 3 * (size_t)m, sv = 3 * (size_t)n;
+#pragma unroll 2
     for (int c = 0; c < kc; ++c) {
         zd u[3], v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            u[a] = w.U[(size_t)c * 3 * m + 3 * i + a];
-            v[a] = w.V[(size_t)c * 3 * n + 3 * j + a];
+            u[a] = up[c * su + a];
+            v[a] = vp[c * sv + a];
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -520,13 +554,13 @@ __device__ __forceinline__ blk aca_residual(const cx<T>* H, int m, int n, const 
 // (the matrix form of the pivoting of Algorithm 1).  Stops once the newest 3 columns satisfy
 // ||U_k||_F ||V_k||_F <= tol, or when a residual row without a regular block is itself
 // below tol.  Returns the number of columns, or -1 when the face is not resolved within cap
-// columns short of 3 min(m, n) (or MAX_FAIL rows in a row have no regular pivot, or a row skipped that way is
-// left at the end): the caller keeps the face dense.
+// columns short of 3 min(m, n) (or MAX_FAIL rows in a row have no regular pivot, or a row
+// skipped that way is left at the end): the caller keeps the face dense.  One wavefront.
 template <typename T>
-__device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax,
-                        AcaShared& S)
+__device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax, zd* pinv)
 {
-    for (int i = threadIdx.x; i < m; i += WG) w.usedrow[i] = 0;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < m; i += WA) w.usedrow[i] = 0;
     __syncthreads();
     int kc = 0, fails = 0, skipped = 0, irow = 0;
     for (;;) {
@@ -534,116 +568,114 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
         // residual row block irow -> V columns kc..kc+2 (row^H)
         double best = -1.0, rn2 = 0.0;
         int bj = 0x7fffffff;
-        for (int j = threadIdx.x; j < n; j += WG) {
-            blk E = aca_residual(H, m, n, w, kc, irow, j);
+        for (int j = lane; j < n; j += WA) {
+            const blk E = aca_residual(H, m, n, w, kc, irow, j);
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
                 for (int x = 0; x < 3; ++x) w.V[(size_t)(kc + y) * 3 * n + 3 * j + x] = conj(E.a[3 * y + x]);
             rn2 += blk_fro2(E);
-            double s3 = blk_sigma3(E);
+            const double s3 = blk_sigma3(E);
             if (s3 > best || (s3 == best && j < bj)) {
                 best = s3;
                 bj = j;
             }
         }
-        if (threadIdx.x == 0) w.usedrow[irow] = 1;
-        double v1[1] = {rn2};
-        wg_sum<1>(v1, S.r);
-        rn2 = v1[0];
-        wg_argmax(best, bj, S.r);
+        if (lane == 0) w.usedrow[irow] = 1;
+        rn2 = wsum(rn2);
+        wargmax(best, bj);
+        __syncthreads();
         if (!(best > PIVOT_RTOL * amax)) {
             if (sqrt(rn2) <= tol) return kc;  // negligible residual row
             ++skipped;
             if (++fails >= MAX_FAIL) return -1;
             int cand = 0x7fffffff;
-            for (int i = threadIdx.x; i < m; i += WG)
+            for (int i = lane; i < m; i += WA)
                 if (!w.usedrow[i] && i < cand) cand = i;
             double cv = cand == 0x7fffffff ? -1.0 : 1.0;
-            wg_argmax(cv, cand, S.r);
+            wargmax(cv, cand);
             if (cv < 0.0) return -1;  // every row visited, a skipped row remains
             irow = cand;
             continue;
         }
         fails = 0;
-        if (threadIdx.x == 0) {
+        // pivot block P = residual block (irow, bj), its inverse shared through LDS
+        if (lane == 0) {
             blk P;
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
                 for (int x = 0; x < 3; ++x) P.a[3 * y + x] = conj(w.V[(size_t)(kc + y) * 3 * n + 3 * bj + x]);
-            blk Pi = blk_inv(P);
+            const blk Pi = blk_inv(P);
 #pragma unroll
-            for (int t = 0; t < 9; ++t) S.pinv[t] = Pi.a[t];
+            for (int t = 0; t < 9; ++t) pinv[t] = Pi.a[t];
         }
         __syncthreads();
         // residual column block bj -> U columns kc..kc+2 = column * P^{-1}
         double best2 = -1.0, un2 = 0.0;
         int bi2 = 0x7fffffff;
-        for (int i = threadIdx.x; i < m; i += WG) {
-            blk E = aca_residual(H, m, n, w, kc, i, bj);
+        for (int i = lane; i < m; i += WA) {
+            const blk E = aca_residual(H, m, n, w, kc, i, bj);
             blk Pi;
 #pragma unroll
-            for (int t = 0; t < 9; ++t) Pi.a[t] = S.pinv[t];
-            blk Un = blk_mul(E, Pi);
+            for (int t = 0; t < 9; ++t) Pi.a[t] = pinv[t];
+            const blk Un = blk_mul(E, Pi);
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
                 for (int x = 0; x < 3; ++x) w.U[(size_t)(kc + x) * 3 * m + 3 * i + y] = Un.a[3 * y + x];
             un2 += blk_fro2(Un);
-            double s3 = w.usedrow[i] ? -1.0 : blk_sigma3(Un);
+            const double s3 = w.usedrow[i] ? -1.0 : blk_sigma3(Un);
             if (s3 > best2 || (s3 == best2 && i < bi2)) {
                 best2 = s3;
                 bi2 = i;
             }
         }
-        double v2[1] = {un2};
-        wg_sum<1>(v2, S.r);
+        un2 = wsum(un2);
         kc += 3;
-        if (sqrt(v2[0] * rn2) <= tol) return kc;
-        wg_argmax(best2, bi2, S.r);
+        if (sqrt(un2 * rn2) <= tol) return kc;
+        wargmax(best2, bi2);
         if (best2 < 0.0) return skipped ? -1 : kc;  // every row is a pivot row: exact
         irow = bi2;
+        __syncthreads();
     }
 }
 
 // ACA stage of one stored dense face: ||H||_F, the pivot scale max |H|, then face_aca;
-// returns the column count (-1: not resolved, or a zero face).
+// returns the column count (-1: not resolved, or a zero face).  One wavefront.
 template <typename T>
-__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, AcaShared& S)
+__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol)
 {
     double s2 = 0.0, amax = 0.0;
-    const size_t cnt = (size_t)9 * m * n;
-    for (size_t q = threadIdx.x; q < cnt; q += WG) {
+    const int cnt = 9 * m * n;
+    for (int q = threadIdx.x; q < cnt; q += WA) {
         const double a2 = abs2(ldz(H + q));
         s2 += a2;
         amax = fmax(amax, a2);
     }
-    double v1[1] = {s2};
-    wg_sum<1>(v1, S.r);
-    amax = sqrt(wg_max(amax, S.r));
-    return v1[0] > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, S) : -1;
+    s2 = wsum(s2);
+    amax = sqrt(wmax(amax));
+    __shared__ zd pinv[9];
+    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv) : -1;
 }
 
 // Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
-// face-fibre term errs by at most about eps_aca ||C^(r)||_F.
-__device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f, AcaShared& S)
+// face-fibre term errs by at most about eps_aca ||C^(r)||_F.  One wavefront.
+__device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f)
 {
     double fn2 = 0.0;
     const zd* fib = (const zd*)(A.pool + f.fib_off);
-    for (int q = threadIdx.x; q < 9 * A.L; q += WG) fn2 += abs2(fib[q]);
-    double v1[1] = {fn2};
-    wg_sum<1>(v1, S.r);
-    return v1[0] > 0.0 ? A.eps_aca_far * sqrt(fmax(A.st[b].norm2, 0.0) / v1[0]) : 0.0;
+    for (int q = threadIdx.x; q < 9 * A.L; q += WA) fn2 += abs2(fib[q]);
+    fn2 = wsum(fn2);
+    return fn2 > 0.0 ? A.eps_aca_far * sqrt(fmax(A.st[b].norm2, 0.0) / fn2) : 0.0;
 }
 
-// Per-slice ACA pass, one workgroup per listed face (items (block << 8) | d, scratch slot =
+// Per-slice ACA pass, one wavefront per listed face (items (block << 8) | d, scratch slot =
 // position in the list): k_face_aca leaves the ACA columns, their count and the face's
 // tolerance in the slot; k_face_recomp (recomp.hip) recompresses them and rewrites the face
 // descriptor.
-__global__ __launch_bounds__(WG) void k_face_aca(CompressArgs A)
+__global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A)
 {
-    __shared__ AcaShared S;
     const int item = A.list[blockIdx.x];
     const int b = item >> 8, d = item & 255;
     const BlockIn B = A.blocks[b];
@@ -654,9 +686,9 @@ __global__ __launch_bounds__(WG) void k_face_aca(CompressArgs A)
     double tol = 0.0;
     if (f.kk == 0 && !f.sel) {
         const int cap = min(A.kmax, face_aca_cap(m, n));
-        tol = face_tol(A, b, f, S);
-        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, S)
-                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, S);
+        tol = face_tol(A, b, f);
+        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol)
+                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol);
     }
     if (threadIdx.x == 0) {
         w.info[0] = kc;
@@ -950,13 +982,12 @@ __global__ __launch_bounds__(WG) void k_fallback_face(CompressArgs A, int kf)
 
 // the ACA stage on one given matrix: out[0] = ACA columns (the recompression follows in
 // k_aca_matrix_recomp, which sets out[1])
-__global__ __launch_bounds__(WG) void k_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax,
+__global__ __launch_bounds__(WA) void k_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax,
                                                    double* scratch, int* out)
 {
-    __shared__ AcaShared S;
     AcaWork w = aca_work(scratch, m, n, kmax);
-    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, S)
-                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, S);
+    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol)
+                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol);
     if (threadIdx.x == 0) {
         out[0] = kc;
         out[1] = 0;
@@ -1022,7 +1053,7 @@ void launch_face_dense(const CompressArgs& A, int path, hipStream_t st)
 }
 void launch_face_aca(const CompressArgs& A, hipStream_t st)
 {
-    BEM_LAUNCH(k_face_aca, A.nlist, WG, A);
+    BEM_LAUNCH(k_face_aca, A.nlist, WA, A);
     launch_face_recomp(A, st);
 }
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
@@ -1060,7 +1091,7 @@ void launch_copy_segments(const char* src, char* dst, const long long* seg, int 
 void launch_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax, double* scratch, int* out,
                        hipStream_t st)
 {
-    BEM_LAUNCH(k_aca_matrix, 1, WG, H, m, n, fp32, tol, cap, kmax, scratch, out);
+    BEM_LAUNCH(k_aca_matrix, 1, WA, H, m, n, fp32, tol, cap, kmax, scratch, out);
     launch_aca_matrix_recomp(H, m, n, fp32, kmax, scratch, out, st);
 }
 

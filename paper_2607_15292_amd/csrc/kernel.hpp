@@ -106,22 +106,59 @@ template <> struct Series<double> { static constexpr int N = 20; };
 template <> struct Series<float> { static constexpr int N = 11; };
 
 constexpr double fact_inv(int n) { return n <= 1 ? 1.0 : fact_inv(n - 1) / n; }
+constexpr double ser_phi(int n) { return fact_inv(n) / (n + 2); }
+constexpr double ser_chi(int n) { return fact_inv(n) / (n + 3); }
 
-// phi(z) = sum (-z)^n phi_n and chi(z) = sum (-z)^n chi_n by Horner in w = -z.
+#define BEM_SER21(f) {f(0), f(1), f(2), f(3), f(4), f(5), f(6), f(7), f(8), f(9), f(10), f(11), f(12), \
+                      f(13), f(14), f(15), f(16), f(17), f(18), f(19), f(20)}
+#define BEM_SER12(f) {(float)f(0), (float)f(1), (float)f(2), (float)f(3), (float)f(4), (float)f(5), (float)f(6), \
+                      (float)f(7), (float)f(8), (float)f(9), (float)f(10), (float)f(11)}
+
+// The coefficient tables live in constant memory and the Horner loops stay rolled, reading
+// one coefficient per step: unrolled, the 20-odd FP64 literals per series are hoisted into
+// registers and double the register footprint of every kernel evaluation.
+#if defined(__HIP_DEVICE_COMPILE__)
+static __constant__ double SER_PHI_D[21] = BEM_SER21(ser_phi);
+static __constant__ double SER_CHI_D[21] = BEM_SER21(ser_chi);
+static __constant__ float SER_PHI_F[12] = BEM_SER12(ser_phi);
+static __constant__ float SER_CHI_F[12] = BEM_SER12(ser_chi);
+template <typename T> __device__ __forceinline__ T ser_c(int n, bool chi);
+template <> __device__ __forceinline__ double ser_c<double>(int n, bool chi) { return chi ? SER_CHI_D[n] : SER_PHI_D[n]; }
+template <> __device__ __forceinline__ float ser_c<float>(int n, bool chi) { return chi ? SER_CHI_F[n] : SER_PHI_F[n]; }
+#else
+template <typename T> inline T ser_c(int n, bool chi) { return (T)(chi ? ser_chi(n) : ser_phi(n)); }
+#endif
+
+// phi(z_a) = sum (-z_a)^n phi_n and chi(z_a) = sum (-z_a)^n chi_n (a = 1, 2) by Horner in
+// w = -z, both arguments in one loop.
 template <typename T>
-BEM_HD void phi_chi(cx<T> z, cx<T>& phi, cx<T>& chi, bool need_chi)
+BEM_HD void phi_chi2(cx<T> z1, cx<T> z2, cx<T>& phi1, cx<T>& phi2, cx<T>& chi1, cx<T>& chi2, bool need_chi)
 {
     constexpr int N = Series<T>::N;
-    cx<T> w = -z;
-    cx<T> p = {(T)(fact_inv(N) / (N + 2)), (T)0};
-#pragma unroll
-    for (int n = N - 1; n >= 0; --n) p = fma_c(p, w, cx<T>{(T)(fact_inv(n) / (n + 2)), (T)0});
-    phi = p;
+    const cx<T> w1 = -z1, w2 = -z2;
+    {
+        const T c = ser_c<T>(N, false);
+        cx<T> p1 = {c, (T)0}, p2 = {c, (T)0};
+#pragma unroll 1
+        for (int n = N - 1; n >= 0; --n) {
+            const cx<T> cn = {ser_c<T>(n, false), (T)0};
+            p1 = fma_c(p1, w1, cn);
+            p2 = fma_c(p2, w2, cn);
+        }
+        phi1 = p1;
+        phi2 = p2;
+    }
     if (need_chi) {
-        cx<T> q = {(T)(fact_inv(N) / (N + 3)), (T)0};
-#pragma unroll
-        for (int n = N - 1; n >= 0; --n) q = fma_c(q, w, cx<T>{(T)(fact_inv(n) / (n + 3)), (T)0});
-        chi = q;
+        const T c = ser_c<T>(N, true);
+        cx<T> q1 = {c, (T)0}, q2 = {c, (T)0};
+#pragma unroll 1
+        for (int n = N - 1; n >= 0; --n) {
+            const cx<T> cn = {ser_c<T>(n, true), (T)0};
+            q1 = fma_c(q1, w1, cn);
+            q2 = fma_c(q2, w2, cn);
+        }
+        chi1 = q1;
+        chi2 = q2;
     }
 }
 
@@ -135,8 +172,7 @@ BEM_HD void kernel_AB(T r, T rinv, cx<T> s, cx<T> sinv, const Mat<T>& M, cx<T>& 
     cx<T> e1r = e1 * (M.ic1s * rinv), e2r = e2 * (M.ic2s * rinv);
     if (abs2(x2) < one) {
         cx<T> p1, p2, q1, q2;
-        phi_chi<T>(x1, p1, q1, DERIV);
-        phi_chi<T>(x2, p2, q2, DERIV);
+        phi_chi2<T>(x1, x2, p1, p2, q1, q2, DERIV);
         cx<T> Ir = (p2 * M.ic2s - p1 * M.ic1s) * rinv;  // I / r
         A = e2r - Ir;
         B = (T)3 * Ir + e1r - e2r;
@@ -339,7 +375,7 @@ BEM_HD void near_unit(const Geo& g, int i, int j, int m, int u, zd s, zd sinv, c
     if constexpr (KOP == 0) {
         AccV<double> acc;
         acc.zero();
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < 7; ++q) {
             const double b0 = Q.b7[3 * q], b1 = Q.b7[3 * q + 1], b2 = Q.b7[3 * q + 2];
             double y[3];
@@ -351,7 +387,7 @@ BEM_HD void near_unit(const Geo& g, int i, int j, int m, int u, zd s, zd sinv, c
         const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
         AccK<double> acc;
         acc.zero();
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < 7; ++q) {
             const double b0 = Q.b7[3 * q], b1 = Q.b7[3 * q + 1], b2 = Q.b7[3 * q + 2];
             double y[3];
