@@ -506,6 +506,18 @@ __device__ __forceinline__ double wmax(double v)
     return v;
 }
 
+// a wavefront-uniform double moved to scalar registers
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b), hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// sigma_3 of a block as a call: its eigenvalue solve (acos, cos) is the register peak of the
+// ACA loop, and a call keeps it out of the loop's allocation
+__device__ __noinline__ double sigma3_call(const blk E) { return blk_sigma3(E); }
+
 // argmax over the wavefront with ties to the smallest index; NaN counts as -inf
 __device__ __forceinline__ void wargmax(double& v, int& idx)
 {
@@ -534,7 +546,7 @@ __device__ __forceinline__ blk aca_residual(const cx<T>* H, int m, int n, const 
     const zd* up = w.U + 3 * i;
     const zd* vp = w.V + 3 * j;
     const size_t su = 3 * (size_t)m, sv = 3 * (size_t)n;
-#pragma unroll 2
+#pragma unroll 1
     for (int c = 0; c < kc; ++c) {
         zd u[3], v[3];
 #pragma unroll
@@ -575,7 +587,17 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
 #pragma unroll
                 for (int x = 0; x < 3; ++x) w.V[(size_t)(kc + y) * 3 * n + 3 * j + x] = conj(E.a[3 * y + x]);
             rn2 += blk_fro2(E);
-            const double s3 = blk_sigma3(E);
+        }
+        __syncthreads();
+        // pivot search on the stored row (a separate pass keeps the sigma_3 solve out of the
+        // residual loop's registers)
+        for (int j = lane; j < n; j += WA) {
+            blk E;
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+#pragma unroll
+                for (int x = 0; x < 3; ++x) E.a[3 * y + x] = conj(w.V[(size_t)(kc + y) * 3 * n + 3 * j + x]);
+            const double s3 = sigma3_call(E);
             if (s3 > best || (s3 == best && j < bj)) {
                 best = s3;
                 bj = j;
@@ -614,18 +636,33 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
         // residual column block bj -> U columns kc..kc+2 = column * P^{-1}
         double best2 = -1.0, un2 = 0.0;
         int bi2 = 0x7fffffff;
+        zd pv[9];  // P^{-1}, uniform: kept in scalar registers
+#pragma unroll
+        for (int t = 0; t < 9; ++t) pv[t] = {uniform_d(pinv[t].re), uniform_d(pinv[t].im)};
         for (int i = lane; i < m; i += WA) {
             const blk E = aca_residual(H, m, n, w, kc, i, bj);
-            blk Pi;
 #pragma unroll
-            for (int t = 0; t < 9; ++t) Pi.a[t] = pinv[t];
-            const blk Un = blk_mul(E, Pi);
+            for (int y = 0; y < 3; ++y) {
+                // row y of E P^{-1}
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    zd u = E.a[3 * y] * pv[x];
+                    u = fma_c(E.a[3 * y + 1], pv[3 + x], u);
+                    u = fma_c(E.a[3 * y + 2], pv[6 + x], u);
+                    w.U[(size_t)(kc + x) * 3 * m + 3 * i + y] = u;
+                    un2 += abs2(u);
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = lane; i < m; i += WA) {
+            if (w.usedrow[i]) continue;
+            blk Un;
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
-                for (int x = 0; x < 3; ++x) w.U[(size_t)(kc + x) * 3 * m + 3 * i + y] = Un.a[3 * y + x];
-            un2 += blk_fro2(Un);
-            const double s3 = w.usedrow[i] ? -1.0 : blk_sigma3(Un);
+                for (int x = 0; x < 3; ++x) Un.a[3 * y + x] = w.U[(size_t)(kc + x) * 3 * m + 3 * i + y];
+            const double s3 = sigma3_call(Un);
             if (s3 > best2 || (s3 == best2 && i < bi2)) {
                 best2 = s3;
                 bi2 = i;
@@ -674,7 +711,7 @@ __device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f)
 // position in the list): k_face_aca leaves the ACA columns, their count and the face's
 // tolerance in the slot; k_face_recomp (recomp.hip) recompresses them and rewrites the face
 // descriptor.
-__global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A)
+__global__ __launch_bounds__(WA, 4) void k_face_aca(CompressArgs A)
 {
     const int item = A.list[blockIdx.x];
     const int b = item >> 8, d = item & 255;
