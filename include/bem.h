@@ -134,6 +134,12 @@ typedef struct {
     double face_flop;             /* algorithmic flops of the face kernels: per pair of step d,
                                      7 regular-rule kernel evaluations (125 flops for U, 236 for
                                      T) and d residual updates (216 flops) */
+    double recomp_ms;             /* device time of the recompression kernel (k_face_recomp) */
+    int64_t recomp_launches;      /* its launches */
+    double recomp_flop;           /* algorithmic flops of the recompressions (complex
+                                     multiply-add = 8): Grams, Choleskys, core product, pivoted
+                                     QR, Jacobi sweeps, coefficients, reflectors,
+                                     back-substitutions and output products, as executed */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */

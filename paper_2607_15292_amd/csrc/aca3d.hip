@@ -251,6 +251,8 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
     s.norm2 = 0.0;
     s.hn2 = s.fmax2 = s.s3max = s.fn2 = 0.0;
     s.entries = 0;
+    s.recomp_flop = 0.0;
+    s.pad2 = 0.0;
     for (int t = 0; t < 9; ++t) s.pinv[t] = {0.0, 0.0};
     for (int k = 0; k < A.L; ++k) A.used[(size_t)b * A.L + k] = 0;
     if (!alloc_step(A, b, 0, 0)) s.active = 0;
@@ -498,6 +500,7 @@ struct AcaShared {
 // and the earlier columns, so many faces per CU (small register footprint) beat many lanes
 // per face.
 constexpr int WA = 64;
+constexpr int KMAX_SLICE = 96;  // largest ACA column count (the scratch and LDS capacity)
 
 __device__ __forceinline__ double wmax(double v)
 {
@@ -533,80 +536,69 @@ __device__ __forceinline__ void wargmax(double& v, int& idx)
     }
 }
 
-// block (i, j) of the stored face H (3m x 3n row-major) minus the cross approximation U V^H
-template <typename T>
-__device__ __forceinline__ blk aca_residual(const cx<T>* H, int m, int n, const AcaWork& w, int kc, int i, int j)
-{
-    blk E;
-    const size_t ld = 3 * (size_t)n;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) E.a[3 * a + c] = ldz(H + (size_t)(3 * i + a) * ld + 3 * j + c);
-    const zd* up = w.U + 3 * i;
-    const zd* vp = w.V + 3 * j;
-    const size_t su = 3 * (size_t)m, sv = 3 * (size_t)n;
-#pragma unroll 1
-    for (int c = 0; c < kc; ++c) {
-        zd u[3], v[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            u[a] = up[c * su + a];
-            v[a] = vp[c * sv + a];
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb) E.a[3 * a + bb] -= mul_conj(u[a], v[bb]);
-    }
-    return E;
-}
-
 // Matrix-valued partial-pivot ACA of the stored face with rank-3 steps and sigma_3 pivots
 // (the matrix form of the pivoting of Algorithm 1).  Stops once the newest 3 columns satisfy
 // ||U_k||_F ||V_k||_F <= tol, or when a residual row without a regular block is itself
 // below tol.  Returns the number of columns, or -1 when the face is not resolved within cap
 // columns short of 3 min(m, n) (or MAX_FAIL rows in a row have no regular pivot, or a row
-// skipped that way is left at the end): the caller keeps the face dense.  One wavefront.
+// skipped that way is left at the end): the caller keeps the face dense.
+//
+// One wavefront.  The residual passes give a lane one scalar column (row pass) or one scalar
+// row (column pass) of the pivot block row / column, so that the reads of the earlier ACA
+// columns are contiguous across lanes; the pivot's own 3 x kc slice is staged in LDS (sk).
+// The sigma_3 pivot search then reads the stored 3 x 3 blocks back.
 template <typename T>
-__device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax, zd* pinv)
+__device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax, zd* pinv,
+                        zd* sk)
 {
     const int lane = threadIdx.x;
+    const int M3 = 3 * m, N3 = 3 * n;
     for (int i = lane; i < m; i += WA) w.usedrow[i] = 0;
     __syncthreads();
     int kc = 0, fails = 0, skipped = 0, irow = 0;
     for (;;) {
         if (kc + 3 > cap) return kc >= 3 * min(m, n) ? kc : -1;  // all of min(m, n) interpolated: exact
-        // residual row block irow -> V columns kc..kc+2 (row^H)
-        double best = -1.0, rn2 = 0.0;
-        int bj = 0x7fffffff;
-        for (int j = lane; j < n; j += WA) {
-            const blk E = aca_residual(H, m, n, w, kc, irow, j);
-#pragma unroll
-            for (int y = 0; y < 3; ++y)
-#pragma unroll
-                for (int x = 0; x < 3; ++x) w.V[(size_t)(kc + y) * 3 * n + 3 * j + x] = conj(E.a[3 * y + x]);
-            rn2 += blk_fro2(E);
+        // residual row block irow -> V columns kc..kc+2 (row^H); sk = U rows 3 irow .. + 2
+        for (int q = lane; q < 3 * kc; q += WA) {
+            const int c = q / 3, y = q - 3 * c;
+            sk[q] = w.U[(size_t)c * M3 + 3 * irow + y];
         }
         __syncthreads();
-        // pivot search on the stored row (a separate pass keeps the sigma_3 solve out of the
-        // residual loop's registers)
+        double rn2 = 0.0;
+        for (int q = lane; q < N3; q += WA) {
+            zd e[3];
+#pragma unroll
+            for (int y = 0; y < 3; ++y) e[y] = ldz(H + (size_t)(3 * irow + y) * N3 + q);
+            const zd* vq = w.V + q;
+            for (int c = 0; c < kc; ++c) {
+                const zd v = vq[(size_t)c * N3];
+#pragma unroll
+                for (int y = 0; y < 3; ++y) e[y] -= mul_conj(sk[3 * c + y], v);
+            }
+#pragma unroll
+            for (int y = 0; y < 3; ++y) {
+                w.V[(size_t)(kc + y) * N3 + q] = conj(e[y]);
+                rn2 += abs2(e[y]);
+            }
+        }
+        if (lane == 0) w.usedrow[irow] = 1;
+        rn2 = wsum(rn2);
+        __syncthreads();
+        double best = -1.0;
+        int bj = 0x7fffffff;
         for (int j = lane; j < n; j += WA) {
             blk E;
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
-                for (int x = 0; x < 3; ++x) E.a[3 * y + x] = conj(w.V[(size_t)(kc + y) * 3 * n + 3 * j + x]);
+                for (int x = 0; x < 3; ++x) E.a[3 * y + x] = conj(w.V[(size_t)(kc + y) * N3 + 3 * j + x]);
             const double s3 = sigma3_call(E);
             if (s3 > best || (s3 == best && j < bj)) {
                 best = s3;
                 bj = j;
             }
         }
-        if (lane == 0) w.usedrow[irow] = 1;
-        rn2 = wsum(rn2);
         wargmax(best, bj);
-        __syncthreads();
         if (!(best > PIVOT_RTOL * amax)) {
             if (sqrt(rn2) <= tol) return kc;  // negligible residual row
             ++skipped;
@@ -618,59 +610,70 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
             wargmax(cv, cand);
             if (cv < 0.0) return -1;  // every row visited, a skipped row remains
             irow = cand;
+            __syncthreads();
             continue;
         }
         fails = 0;
-        // pivot block P = residual block (irow, bj), its inverse shared through LDS
+        // pivot block P = residual block (irow, bj), its inverse shared through LDS; sk = V
+        // rows 3 bj .. + 2
         if (lane == 0) {
             blk P;
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
-                for (int x = 0; x < 3; ++x) P.a[3 * y + x] = conj(w.V[(size_t)(kc + y) * 3 * n + 3 * bj + x]);
+                for (int x = 0; x < 3; ++x) P.a[3 * y + x] = conj(w.V[(size_t)(kc + y) * N3 + 3 * bj + x]);
             const blk Pi = blk_inv(P);
 #pragma unroll
             for (int t = 0; t < 9; ++t) pinv[t] = Pi.a[t];
         }
+        for (int q = lane; q < 3 * kc; q += WA) {
+            const int c = q / 3, x = q - 3 * c;
+            sk[q] = w.V[(size_t)c * N3 + 3 * bj + x];
+        }
         __syncthreads();
-        // residual column block bj -> U columns kc..kc+2 = column * P^{-1}
-        double best2 = -1.0, un2 = 0.0;
-        int bi2 = 0x7fffffff;
         zd pv[9];  // P^{-1}, uniform: kept in scalar registers
 #pragma unroll
         for (int t = 0; t < 9; ++t) pv[t] = {uniform_d(pinv[t].re), uniform_d(pinv[t].im)};
-        for (int i = lane; i < m; i += WA) {
-            const blk E = aca_residual(H, m, n, w, kc, i, bj);
+        // residual column block bj -> U columns kc..kc+2 = column * P^{-1}
+        double un2 = 0.0;
+        for (int q = lane; q < M3; q += WA) {
+            zd e[3];
 #pragma unroll
-            for (int y = 0; y < 3; ++y) {
-                // row y of E P^{-1}
+            for (int x = 0; x < 3; ++x) e[x] = ldz(H + (size_t)q * N3 + 3 * bj + x);
+            const zd* uq = w.U + q;
+            for (int c = 0; c < kc; ++c) {
+                const zd u = uq[(size_t)c * M3];
 #pragma unroll
-                for (int x = 0; x < 3; ++x) {
-                    zd u = E.a[3 * y] * pv[x];
-                    u = fma_c(E.a[3 * y + 1], pv[3 + x], u);
-                    u = fma_c(E.a[3 * y + 2], pv[6 + x], u);
-                    w.U[(size_t)(kc + x) * 3 * m + 3 * i + y] = u;
-                    un2 += abs2(u);
-                }
+                for (int x = 0; x < 3; ++x) e[x] -= mul_conj(u, sk[3 * c + x]);
+            }
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                zd t = e[0] * pv[x];
+                t = fma_c(e[1], pv[3 + x], t);
+                t = fma_c(e[2], pv[6 + x], t);
+                w.U[(size_t)(kc + x) * M3 + q] = t;
+                un2 += abs2(t);
             }
         }
+        un2 = wsum(un2);
+        kc += 3;
+        if (sqrt(un2 * rn2) <= tol) return kc;
         __syncthreads();
+        double best2 = -1.0;
+        int bi2 = 0x7fffffff;
         for (int i = lane; i < m; i += WA) {
             if (w.usedrow[i]) continue;
             blk Un;
 #pragma unroll
             for (int y = 0; y < 3; ++y)
 #pragma unroll
-                for (int x = 0; x < 3; ++x) Un.a[3 * y + x] = w.U[(size_t)(kc + x) * 3 * m + 3 * i + y];
+                for (int x = 0; x < 3; ++x) Un.a[3 * y + x] = w.U[(size_t)(kc - 3 + x) * M3 + 3 * i + y];
             const double s3 = sigma3_call(Un);
             if (s3 > best2 || (s3 == best2 && i < bi2)) {
                 best2 = s3;
                 bi2 = i;
             }
         }
-        un2 = wsum(un2);
-        kc += 3;
-        if (sqrt(un2 * rn2) <= tol) return kc;
         wargmax(best2, bi2);
         if (best2 < 0.0) return skipped ? -1 : kc;  // every row is a pivot row: exact
         irow = bi2;
@@ -693,7 +696,9 @@ __device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, in
     s2 = wsum(s2);
     amax = sqrt(wmax(amax));
     __shared__ zd pinv[9];
-    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv) : -1;
+    __shared__ zd sk[3 * KMAX_SLICE];
+    if (cap > KMAX_SLICE) return -1;
+    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk) : -1;
 }
 
 // Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
@@ -711,7 +716,7 @@ __device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f)
 // position in the list): k_face_aca leaves the ACA columns, their count and the face's
 // tolerance in the slot; k_face_recomp (recomp.hip) recompresses them and rewrites the face
 // descriptor.
-__global__ __launch_bounds__(WA, 4) void k_face_aca(CompressArgs A)
+__global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A)
 {
     const int item = A.list[blockIdx.x];
     const int b = item >> 8, d = item & 255;
@@ -1091,7 +1096,6 @@ void launch_face_dense(const CompressArgs& A, int path, hipStream_t st)
 void launch_face_aca(const CompressArgs& A, hipStream_t st)
 {
     BEM_LAUNCH(k_face_aca, A.nlist, WA, A);
-    launch_face_recomp(A, st);
 }
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
                      unsigned char* cls, hipStream_t st)

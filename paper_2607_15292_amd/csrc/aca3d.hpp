@@ -54,6 +54,8 @@ struct BlockState {
     double norm2;   // ||C^(d)||_F^2
     double hn2, fmax2, s3max, fn2;
     long long entries;
+    double recomp_flop;  // algorithmic flops of this block's face recompressions
+    double pad2;
     zd pinv[9];
 };
 
@@ -145,7 +147,7 @@ void launch_cross_dense(const CompressArgs& A, hipStream_t st);
 void launch_final(const CompressArgs& A, hipStream_t st);
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st);
 void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st);
-// per-slice ACA (k_face_aca) then the recompression of its columns (k_face_recomp)
+// per-slice ACA (k_face_aca); the recompression of its columns follows (k_face_recomp)
 void launch_face_aca(const CompressArgs& A, hipStream_t st);
 void launch_face_recomp(const CompressArgs& A, hipStream_t st);
 void launch_copy_segments(const char* src, char* dst, const long long* seg, int nseg, hipStream_t st);
@@ -185,9 +187,17 @@ struct ApplyArgs {
     zd* tbuf;                  // far products workspace
     const int* far_list;       // faces with kk > 0 (at most 96)
     int nfar;
+    // segments of the row groups' face lists (one row-kernel workgroup per segment and column
+    // tile): group, first entry of row_faces (seg_begin[nseg] = end), segments of a group
+    int nseg;
+    const int* seg_group;
+    const int* seg_begin;
+    const int* group_seg;
+    zd* pbuf;                  // partial rows of the segments [nseg][3 APPLY_ROW_CHUNK][ncols]
 };
 
-constexpr int APPLY_ROW_CHUNK = 8;  // element rows per workgroup of the product (row chunks)
+constexpr int APPLY_ROW_CHUNK = 16;  // element rows per workgroup of the product (row chunks)
+constexpr int APPLY_SEGMENTS = 2048; // target number of row-kernel workgroups per column tile
 
 void launch_apply(const ApplyArgs& A, hipStream_t st);
 void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nrhs, int64_t in_l_stride, bool to_cluster,

@@ -16,9 +16,9 @@ namespace bem {
 
 namespace {
 
-constexpr int RCE = 8;   // elements per row chunk (24 rows)
+constexpr int RCE = APPLY_ROW_CHUNK;  // elements per row chunk (48 rows)
 constexpr int NC = 64;   // columns (rhs x frequency) per tile
-constexpr int KT = 48;   // scalar columns of a face (16 elements) per staged tile
+constexpr int KR = 24;   // scalar columns of a face (8 elements) per staged tile of the row kernel
 constexpr int KTF = 24;  // rows of Vbar per staged tile in the far products
 constexpr int KMAXF = 96;  // largest rank of a factored face
 constexpr int WGA = 256;
@@ -143,51 +143,58 @@ __global__ __launch_bounds__(WGA) void k_far_products(ApplyArgs A, const int* fa
     else far_products_face<double, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs, Fs);
 }
 
-// Y[rows][cols] += Hs[rows][k] Ts[k][cols] over one staged tile; thread = element row er
-// (3 rows) x 2 columns
-__device__ __forceinline__ void tile_mac(const zd (*Hs)[KT], const zd (*Ts)[NC], int nk, int er, int cp, zd (*acc)[2])
+// Y[rows][cols] += Hs[rows][k] Zs[k][cols] over one staged tile; thread = element row er
+// (3 rows) x 4 consecutive columns: 12 complex accumulators, 7 LDS reads per 12 complex
+// multiply-adds (the FP64 VALU, not LDS, bounds the loop)
+template <int KTL>
+__device__ __forceinline__ void tile_mac(const zd (*Hs)[KTL], const zd (*Zs)[NC], int nk, int er, int cq, zd (*acc)[4])
 {
     for (int k = 0; k < nk; ++k) {
-        const zd z0 = Ts[k][2 * cp], z1 = Ts[k][2 * cp + 1];
+        zd z[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) z[v] = Zs[k][4 * cq + v];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const zd h = Hs[3 * er + a][k];
-            acc[a][0] = fma_c(h, z0, acc[a][0]);
-            acc[a][1] = fma_c(h, z1, acc[a][1]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][v] = fma_c(h, z[v], acc[a][v]);
         }
     }
 }
 
-// rows: one workgroup per (row chunk of RCE elements, column tile)
+// rows: one workgroup per (segment of a row chunk's faces, column tile of NC columns); the
+// segment's partial rows go to pbuf and k_reduce_rows adds them in segment order
 template <bool WEIGHTED>
-__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int ncols, zd* yout)
+__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int ncols)
 {
-    __shared__ zd Hs[3 * RCE][KT];
-    __shared__ zd Zs[KT][NC];
+    __shared__ zd Hs[3 * RCE][KR];
+    __shared__ zd Zs[KR][NC];
     __shared__ zd Fs[NC][9];
-    const int g = blockIdx.x;
+    const int sg = blockIdx.x, g = A.seg_group[sg];
     const int c0 = blockIdx.y * NC;
-    const int er = threadIdx.x >> 5, cp = threadIdx.x & 31;  // element row, column pair
+    const int er = threadIdx.x >> 4, cq = threadIdx.x & 15;  // element row, column quad
     const int rs0 = A.row_start[g], rsz = A.row_size[g];
-    zd acc[3][2];
+    zd acc[3][4];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) acc[a][0] = acc[a][1] = {0.0, 0.0};
-    for (int q = A.row_ptr[g]; q < A.row_ptr[g + 1]; ++q) {
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[a][v] = {0.0, 0.0};
+    for (int q = A.seg_begin[sg]; q < A.seg_begin[sg + 1]; ++q) {
         const ApplyFace F = A.faces[A.row_faces[q]];
         if (F.kk < 0) continue;
         const BlockIn B = A.blocks[F.block];
-        const int m = B.rs, n = B.cs;
+        const int n = B.cs;
         const int ioff = rs0 - B.rb;  // first element row of the chunk inside the block
         if (F.kk == 0) {
             const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
             const size_t ld = 3 * (size_t)n;
             __syncthreads();
             stage_fibres<WEIGHTED>(A, F, c0, ncols, Fs);
-            for (int k0 = 0; k0 < 3 * n; k0 += KT) {
-                const int nk = min(KT, 3 * n - k0);
+            for (int k0 = 0; k0 < 3 * n; k0 += KR) {
+                const int nk = min(KR, 3 * n - k0);
                 __syncthreads();
-                for (int e = threadIdx.x; e < 3 * RCE * KT; e += WGA) {
-                    const int r = e / KT, kc = e - r * KT;
+                for (int e = threadIdx.x; e < 3 * RCE * KR; e += WGA) {
+                    const int r = e / KR, kc = e - r * KR;
                     zd h = {0.0, 0.0};
                     if (r < 3 * rsz && kc < nk) {
                         const size_t o = (size_t)(3 * ioff + r) * ld + k0 + kc;
@@ -195,18 +202,18 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
                     }
                     Hs[r][kc] = h;
                 }
-                stage_z<WEIGHTED, KT>(A, B, zw, k0, c0, ncols, Fs, Zs);
+                stage_z<WEIGHTED, KR>(A, B, zw, k0, c0, ncols, Fs, Zs);
                 __syncthreads();
-                tile_mac(Hs, Zs, nk, er, cp, acc);
+                tile_mac<KR>(Hs, Zs, nk, er, cq, acc);
             }
         } else {
             const int kk = F.kk;
             const zd* Tf = A.tbuf + F.t_off * (size_t)ncols;
-            for (int k0 = 0; k0 < kk; k0 += KT) {
-                const int nk = min(KT, kk - k0);
+            for (int k0 = 0; k0 < kk; k0 += KR) {
+                const int nk = min(KR, kk - k0);
                 __syncthreads();
-                for (int e = threadIdx.x; e < 3 * RCE * KT; e += WGA) {
-                    const int r = e / KT, kc = e - r * KT;
+                for (int e = threadIdx.x; e < 3 * RCE * KR; e += WGA) {
+                    const int r = e / KR, kc = e - r * KR;
                     zd h = {0.0, 0.0};
                     if (r < 3 * rsz && kc < nk) {
                         const size_t o = (size_t)(3 * ioff + r) * kk + k0 + kc;
@@ -214,31 +221,44 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
                     }
                     Hs[r][kc] = h;
                 }
-                for (int e = threadIdx.x; e < KT * NC; e += WGA) {
+                for (int e = threadIdx.x; e < KR * NC; e += WGA) {
                     const int kr = e / NC, cl = e - kr * NC;
                     Zs[kr][cl] = (kr < nk && c0 + cl < ncols) ? Tf[(size_t)(k0 + kr) * ncols + c0 + cl] : zd{0.0, 0.0};
                 }
                 __syncthreads();
-                tile_mac(Hs, Zs, nk, er, cp, acc);
+                tile_mac<KR>(Hs, Zs, nk, er, cq, acc);
             }
         }
-        (void)m;
     }
     if (er < rsz) {
-        const size_t M = 3 * (size_t)A.K;
+        zd* pb = A.pbuf + (size_t)sg * 3 * RCE * ncols;
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int col = c0 + 2 * cp + v;
+        for (int v = 0; v < 4; ++v) {
+            const int col = c0 + 4 * cq + v;
             if (col >= ncols) continue;
-            if (WEIGHTED) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) yout[3 * (size_t)(rs0 + er) + a] = acc[a][v];
-            } else {
-                const int l = col % A.L, r = col / A.L;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) yout[((size_t)r * A.L + l) * M + 3 * (size_t)(rs0 + er) + a] = acc[a][v];
-            }
+            for (int a = 0; a < 3; ++a) pb[(size_t)(3 * er + a) * ncols + col] = acc[a][v];
         }
+    }
+}
+
+// y rows of row chunk g = sum of its segments' partial rows, in segment order
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_reduce_rows(ApplyArgs A, int ncols, zd* yout)
+{
+    const int g = blockIdx.x;
+    const int rsz = A.row_size[g], rs0 = A.row_start[g];
+    const int q = blockIdx.y * 256 + threadIdx.x;  // (row, col) with col fastest
+    if (q >= 3 * rsz * ncols) return;
+    const int row = q / ncols, col = q - row * ncols;
+    zd s = {0.0, 0.0};
+    for (int sg = A.group_seg[g]; sg < A.group_seg[g + 1]; ++sg) s += A.pbuf[((size_t)sg * 3 * RCE + row) * ncols + col];
+    if (WEIGHTED) {
+        yout[3 * (size_t)rs0 + row] = s;
+    } else {
+        const size_t M = 3 * (size_t)A.K;
+        const int l = col % A.L, r = col / A.L;
+        yout[((size_t)r * A.L + l) * M + 3 * (size_t)rs0 + row] = s;
     }
 }
 
@@ -314,7 +334,10 @@ void launch_apply(const ApplyArgs& A, hipStream_t st)
     if (A.nfar > 0) hipLaunchKernelGGL((k_far_products<false>), dim3(A.nfar, ct), dim3(WGA), 0, st, A, A.far_list,
                                        nullptr, ncols);
     BEM_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL((k_rows<false>), dim3(A.nrow_groups, ct), dim3(WGA), 0, st, A, nullptr, ncols, A.y);
+    hipLaunchKernelGGL((k_rows<false>), dim3(A.nseg, ct), dim3(WGA), 0, st, A, nullptr, ncols);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_reduce_rows<false>), dim3(A.nrow_groups, (3 * RCE * ncols + 255) / 256), dim3(256), 0, st, A,
+                       ncols, A.y);
     BEM_HIP_TRY(hipGetLastError());
 }
 
@@ -329,7 +352,9 @@ void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t
         hipLaunchKernelGGL((k_far_products<true>), dim3(A.nfar, 1), dim3(WGA), 0, st, A, A.far_list, zw, 1);
         BEM_HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_rows<true>), dim3(A.nrow_groups, 1), dim3(WGA), 0, st, A, zw, 1, y);
+    hipLaunchKernelGGL((k_rows<true>), dim3(A.nseg, 1), dim3(WGA), 0, st, A, zw, 1);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_reduce_rows<true>), dim3(A.nrow_groups, (3 * RCE + 255) / 256), dim3(256), 0, st, A, 1, y);
     BEM_HIP_TRY(hipGetLastError());
 }
 

@@ -25,7 +25,9 @@ struct CompressedOp {
     // apply plan
     std::vector<ApplyFace> af;
     DevBuf af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev, farlist_dev;
+    DevBuf seg_dev;             // segments: [nseg] group, [nseg + 1] face ranges, [ngroups + 1] group ranges
     int ngroups = 0;
+    int nseg = 0;
     int nfar = 0;               // factored faces
     long long far_rows = 0;     // sum of kk over far faces
     long long zw_total = 0;     // sum of 3 cs over faces
@@ -120,6 +122,36 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
         ptr[g + 1] = ptr[g] + (int)lists[g].size();
         flat.insert(flat.end(), lists[g].begin(), lists[g].end());
     }
+    // segments: each group's face list cut into pieces of about equal work (the staged
+    // inner dimension: 3 cs for a dense face, kk for factors, plus a per-face overhead), so
+    // that the row kernel has about APPLY_SEGMENTS workgroups per column tile; partial sums
+    // are added in segment order
+    auto cost = [&](int fi) { const ApplyFace& a = C.af[fi]; return (double)(a.kk > 0 ? a.kk : 3 * C.blocks[a.block].cs) + 24.0; };
+    double total = 0.0;
+    for (int fi : flat) total += cost(fi);
+    const double per = std::max(1.0, total / APPLY_SEGMENTS);
+    std::vector<int> sgroup, sbeg, gseg(C.ngroups + 1, 0);
+    for (int g = 0; g < C.ngroups; ++g) {
+        double cg = 0.0;
+        for (int q = ptr[g]; q < ptr[g + 1]; ++q) cg += cost(flat[q]);
+        const int ns = std::max(1, (int)std::lround(cg / per));
+        const double target = cg / ns;
+        int q = ptr[g];
+        for (int k = 0; k < ns; ++k) {
+            sgroup.push_back(g);
+            sbeg.push_back(q);
+            double acc = 0.0;
+            while (q < ptr[g + 1] && (k == ns - 1 || acc == 0.0 || acc + 0.5 * cost(flat[q]) < target))
+                acc += cost(flat[q++]);
+        }
+        gseg[g + 1] = (int)sgroup.size();
+    }
+    C.nseg = (int)sgroup.size();
+    std::vector<int> segbuf;
+    segbuf.insert(segbuf.end(), sgroup.begin(), sgroup.end());
+    segbuf.insert(segbuf.end(), sbeg.begin(), sbeg.end());
+    segbuf.push_back(ptr[C.ngroups]);
+    segbuf.insert(segbuf.end(), gseg.begin(), gseg.end());
     auto up = [&](DevBuf& d, const void* src, size_t bytes) {
         d.alloc(std::max<size_t>(bytes, 16));
         if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
@@ -130,6 +162,7 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
     up(C.rowstart_dev, s2.data(), s2.size() * sizeof(int));
     up(C.rowsize_dev, z2.data(), z2.size() * sizeof(int));
     up(C.farlist_dev, far.data(), far.size() * sizeof(int));
+    up(C.seg_dev, segbuf.data(), segbuf.size() * sizeof(int));
     BEM_HIP_TRY(hipStreamSynchronize(st));
 }
 
@@ -151,6 +184,10 @@ ApplyArgs plan_args(const CompressedOp& C, int nrhs)
     A.nrhs = nrhs;
     A.far_list = C.farlist_dev.as<int>();
     A.nfar = C.nfar;
+    A.nseg = C.nseg;
+    A.seg_group = C.seg_dev.as<int>();
+    A.seg_begin = A.seg_group + C.nseg;
+    A.group_seg = A.seg_begin + C.nseg + 1;
     return A;
 }
 
@@ -334,6 +371,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     double face_ms = 0.0, face_flop = 0.0;
     int64_t face_launches = 0, face_pairs = 0;
     float kms = 0.f, aca_ms = 0.f;
+    double recomp_ms = 0.0;
+    int64_t recomp_launches = 0;
     int err = 0;
     std::vector<BlockState>& S = C->st;
     S.resize(nb);
@@ -527,12 +566,28 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         A.scratch = scratch.as<double>();
         A.scratch_per_slot = per_slot;
         const int* p_items = put_list(list_dev, 0, items, st);
+        std::vector<hipEvent_t> evr;
         for (size_t c0 = 0; c0 < items.size(); c0 += (size_t)slots) {
             A.list = p_items + c0;
             A.nlist = (int)std::min<size_t>((size_t)slots, items.size() - c0);
             launch_face_aca(A, st);
+            hipEvent_t e0, e1;
+            BEM_HIP_TRY(hipEventCreate(&e0));
+            BEM_HIP_TRY(hipEventCreate(&e1));
+            evr.push_back(e0);
+            evr.push_back(e1);
+            BEM_HIP_TRY(hipEventRecord(e0, st));
+            launch_face_recomp(A, st);
+            BEM_HIP_TRY(hipEventRecord(e1, st));
+            ++recomp_launches;
         }
         BEM_HIP_TRY(hipStreamSynchronize(st));
+        for (size_t e = 0; e < evr.size(); e += 2) {
+            float ms = 0.f;
+            BEM_HIP_TRY(hipEventElapsedTime(&ms, evr[e], evr[e + 1]));
+            recomp_ms += ms;
+        }
+        for (hipEvent_t e : evr) (void)hipEventDestroy(e);
     }
     BEM_HIP_TRY(hipEventRecord(ev2, st));
     BEM_HIP_TRY(hipStreamSynchronize(st));
@@ -606,7 +661,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.n_far = n_far;
     R.n_near = nb - n_far;
     R.rank_min = L + 1;
-    double rsum = 0, acasum = 0, colsum = 0;
+    double rsum = 0, acasum = 0, colsum = 0, rflop = 0;
     int64_t nfarfaces = 0, bytes = 0, ent = 0;
     for (int b = 0; b < nb; ++b) {
         const BlockState& s = S[b];
@@ -618,6 +673,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         ent += s.entries;
         R.n_aca_dense += s.aca_dense;
         colsum += (double)s.aca_cols;
+        rflop += s.recomp_flop;
         for (int d = 0; d < s.rank; ++d) {
             const FaceDesc& f = C->faces[(size_t)b * L + d];
             bytes += (int64_t)L * 9 * sizeof(zd);
@@ -645,6 +701,9 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.face_launches = face_launches;
     R.face_pairs = face_pairs;
     R.face_flop = face_flop;
+    R.recomp_ms = recomp_ms;
+    R.recomp_launches = recomp_launches;
+    R.recomp_flop = rflop;
     R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BEM_OK;
 }
@@ -682,7 +741,8 @@ void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride,
     CompressedOp& C = *op->comp;
     const size_t M = 3 * (size_t)C.K;
     const size_t ncols = (size_t)C.L * nrhs;
-    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + 16) * sizeof(zd);
+    const size_t prow = (size_t)3 * APPLY_ROW_CHUNK * ncols;  // partial rows of one segment
+    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + (size_t)C.nseg * prow + 16) * sizeof(zd);
     if (C.work.bytes < need) C.work.alloc(need);
     zd* xp = C.work.as<zd>();
     zd* yp = xp + ncols * M;
@@ -692,6 +752,7 @@ void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride,
     A.x = xp;
     A.y = yp;
     A.tbuf = tb;
+    A.pbuf = tb + (size_t)C.far_rows * ncols;
     launch_apply(A, st);
     launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, C.L, nrhs, (int64_t)M, false, st);
 }
@@ -700,7 +761,9 @@ void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream
 {
     CompressedOp& C = *op->comp;
     const size_t M = 3 * (size_t)C.K;
-    size_t need = ((size_t)C.L * M + M + (size_t)C.zw_total + (size_t)C.far_rows + 16) * sizeof(zd);
+    const size_t prow = (size_t)3 * APPLY_ROW_CHUNK;
+    size_t need = ((size_t)C.L * M + M + (size_t)C.zw_total + (size_t)C.far_rows + (size_t)C.nseg * prow + 16) *
+                  sizeof(zd);
     if (C.work.bytes < need) C.work.alloc(need);
     zd* Wp = C.work.as<zd>();
     zd* yp = Wp + (size_t)C.L * M;
@@ -711,6 +774,7 @@ void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream
     A.x = Wp;
     A.y = yp;
     A.tbuf = tb;
+    A.pbuf = tb + C.far_rows;
     launch_weighted(A, Wp, zw, yp, st);
     launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, 1, 1, (int64_t)M, false, st);
 }

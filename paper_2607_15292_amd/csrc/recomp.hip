@@ -430,14 +430,15 @@ __device__ int qrcp(zd* Lm, int kc, int ld, double delta, Rs& L, double* rest2)
 // while |<a, b>| > 1e-12 |a| |b| and |<a, b>| > gmin: below gmin (a small fraction of tol^2)
 // the pair's non-orthogonality cannot move the truncation at tol.
 constexpr int JG = 16;
-__device__ void jacobi(zd* Lm, int rows, int ncol, int ld, double gmin, Rs& L)
+__device__ int jacobi(zd* Lm, int rows, int ncol, int ld, double gmin, Rs& L)
 {
     constexpr int RPL = (KF + JG - 1) / JG;
     const int np = ncol + (ncol & 1);
     const int g = threadIdx.x / JG, gl = threadIdx.x % JG;
     const double gmin2 = gmin * gmin;
-    if (ncol < 2) return;
-    for (int sweep = 0; sweep < 40; ++sweep) {
+    if (ncol < 2) return 0;
+    int sweep = 0;
+    for (; sweep < 40; ++sweep) {
         if (threadIdx.x == 0) L.flag = 0;
         __syncthreads();
         for (int rnd = 0; rnd < np - 1; ++rnd) {
@@ -508,6 +509,7 @@ __device__ void jacobi(zd* Lm, int rows, int ncol, int ld, double gmin, Rs& L)
         __syncthreads();
         if (!f) break;
     }
+    return sweep + 1;
 }
 
 // Y_h <- D_h^{-1} R_h^{-1} Y_h for up to two systems h (kk columns each, column s at
@@ -608,8 +610,24 @@ __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T
 // returns kk > 0 with the factors written over Hout, or 0 (face kept dense).  Scratch:
 // G = T_U, VJ = T_V, RU = R_U then B^H then the Vbar coefficients, RV = R_V then the Ubar
 // coefficients, M = the pivoted QR (all kc x kc, ld kc).
+// Algorithmic flops of the executed parts of one recompression (complex multiply-add = 8):
+// stage 0 = QR factors, core and pivoted QR; 1 = + Jacobi; 2 = + coefficients, reflectors,
+// back-substitutions and output products.
+__device__ double recomp_flops(int stage, int m, int n, int kc, int kq, int sweeps, int kk)
+{
+    const double c = kc, ru = 3.0 * m, rv = 3.0 * n;
+    double f = 8.0 * ((ru + rv) * c * (c + 1.0) / 2.0 + 2.0 * c * c * c / 6.0 + c * c * c / 3.0);
+    for (int j = 0; j < kq; ++j) f += 16.0 * (double)(kc - j) * (double)(kc - j);
+    if (stage >= 1) f += 24.0 * sweeps * (double)kq * (kq - 1) / 2.0 * c;
+    if (stage >= 2) {
+        f += 8.0 * c * c * kk + 8.0 * c * c * kk + 8.0 * (ru + rv) * c * kk;
+        for (int j = 0; j < kq; ++j) f += 16.0 * (double)kk * (double)(kc - j);
+    }
+    return f;
+}
+
 template <typename T>
-__device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L)
+__device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L, double& flop)
 {
     zd* Lm = L.m;
     const int ld = kc | 1;
@@ -627,6 +645,7 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     __syncthreads();
     double rest2 = 0.0;
     const int kq = qrcp(Lm, kc, ld, QRCP_FRAC * tol, L, &rest2);
+    flop = recomp_flops(0, m, n, kc, kq, 0, 0);
     if (kq == 0) return 0;
     // keep the pivoted QR, form B^H (kc x kq): B^H[perm[c]][i] = conj(R[i][c]), i <= c
     for (int j = ty; j < kc; j += 32)
@@ -639,7 +658,8 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
             w.RU[(size_t)i * kc + L.perm[c]] = v;
         }
     __syncthreads();
-    jacobi(Lm, kc, kq, ld, JAC_GMIN * tol * tol, L);
+    const int sweeps = jacobi(Lm, kc, kq, ld, JAC_GMIN * tol * tol, L);
+    flop = recomp_flops(1, m, n, kc, kq, sweeps, 0);
     for (int c = wv; c < kq; c += NW) {
         double s = 0.0;
         for (int r = lane; r < kc; r += 64) s += abs2(Lm[(size_t)c * ld + r]);
@@ -678,6 +698,7 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     __syncthreads();
     const int kk = L.piv;
     if (kk <= 0) return 0;
+    flop = recomp_flops(2, m, n, kc, kq, sweeps, kk);
     // Ubar coefficients -> RV: sigma_s [VJ_s; 0] with VJ_s = B W_s / sigma_s^2 (kq entries);
     // Vbar coefficients -> RU: W_s / sigma_s
     for (int s = ty; s < kk; s += 32) {
@@ -766,12 +787,14 @@ __global__ __launch_bounds__(NT) void k_face_recomp(CompressArgs A)
     AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
     const int kc = w.info[0];
     int kk = 0;
+    double flop = 0.0;
     if (kc > 0 && kc <= KF) {
         const double tol = w.tol[0];
-        kk = f.fp32 ? recompress((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L)
-                    : recompress((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L);
+        kk = f.fp32 ? recompress((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop)
+                    : recompress((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop);
     }
     if (threadIdx.x == 0) {
+        atomicAdd(&A.st[b].recomp_flop, flop);
         if (kk > 0) {
             fp->kk = kk;
             atomicAdd((unsigned long long*)&A.st[b].aca_cols, (unsigned long long)kc);
@@ -789,9 +812,11 @@ __global__ __launch_bounds__(NT) void k_aca_matrix_recomp(char* H, int m, int n,
     AcaWork w = aca_work(scratch, m, n, kmax);
     const int kc = out[0];
     int kk = 0;
+    double flop = 0.0;
     if (kc > 0 && kc <= KF) {
         const double tol = w.tol[0];
-        kk = fp32 ? recompress((cx<float>*)H, m, n, w, kc, tol, L) : recompress((cx<double>*)H, m, n, w, kc, tol, L);
+        kk = fp32 ? recompress((cx<float>*)H, m, n, w, kc, tol, L, flop)
+                  : recompress((cx<double>*)H, m, n, w, kc, tol, L, flop);
     }
     if (threadIdx.x == 0) out[1] = kk;
 }
