@@ -61,6 +61,7 @@ typedef struct bem_op bem_op;
 #define BEM_ERR_NOMEM (-7)     /* device allocation failed or the compression pool overflowed */
 #define BEM_ERR_NODEVICE (-8)  /* GPU call on a host-only context (device = -1) */
 #define BEM_WARN_BULK 1        /* cp^2 < 4/3 cs^2: negative bulk modulus (still computed) */
+#define BEM_WARN_NOCONV 2      /* bem_solve: tolerance not met within max_iter / max_refine */
 
 /* operators */
 #define BEM_OP_V 0     /* single layer V (eq. (SLP)), kernel U */
@@ -239,6 +240,46 @@ int bem_apply(bem_op *op, int32_t nrhs, const void *x, void *y, int32_t flags);
  * sum_k H_k (sum_l f_k[l] W[l]) on a compressed operator (plain sum on a dense one).
  * W: [L][3K] complex128, y: [3K] complex128. */
 int bem_apply_weighted(bem_op *op, const void *W, void *y, int32_t flags);
+
+/* Options of bem_solve (NULL: tol 1e-8, inner_tol 1e-3, restart 30, max_iter 500,
+ * max_refine 10). */
+typedef struct bem_solve_opts {
+    double tol;          /* target: ||b_l - A(s_l) x_l|| <= tol ||b_l|| for every frequency and
+                            right-hand side, residual taken with the fine operator A */
+    double inner_tol;    /* relative residual reached by each inner GMRES run on A_inner */
+    int32_t restart;     /* Krylov vectors per GMRES cycle (>= 1) */
+    int32_t max_iter;    /* inner-operator products in total (>= 1) */
+    int32_t max_refine;  /* refinement sweeps after the first (>= 0) */
+    int32_t pad;
+} bem_solve_opts;
+
+/* Results of bem_solve. */
+typedef struct bem_solve_stats {
+    int32_t iterations;   /* inner-operator products (each covers all frequencies and
+                             right-hand sides) */
+    int32_t refinements;  /* fine-operator products (residuals) */
+    int32_t converged;    /* 1 when tol was met */
+    int32_t pad;
+    double rel_residual;  /* max over frequencies and right-hand sides of ||b - A x|| / ||b|| */
+    double seconds;       /* wall time of the call */
+} bem_solve_stats;
+
+/* Solution of the discrete boundary integral equations at every contour point: the
+ * collocation system of Sec. 2.3 (eq. (discrVK) in the Laplace domain, Sec. 2.4), e.g.
+ * V(s_l) t_l = (I/2 + K(s_l)) g_l for the tractions of a Dirichlet problem, with b_l the
+ * right-hand side computed by bem_apply.  Solves A(s_l) x[r][l] = b[r][l] for every r < nrhs
+ * and l: GMRES per column (all columns batched in each product) with re-orthogonalised
+ * classical Gram-Schmidt in FP64, inside iterative refinement: each sweep runs GMRES on
+ * A_inner d = r (to inner_tol, or, when A_inner is NULL or A, to what tol requires) and adds
+ * d to x, then takes the residual r = b - A x with A.  A cheap inner operator (e.g. the
+ * mixed-precision compression) with an accurate fine one (FP64 at a tighter eps) gives the
+ * fine operator's accuracy at mostly inner-operator cost.
+ *   A, A_inner: operators of the same context, K and L (dense or compressed; A_inner may
+ *   be NULL).  b, x: [nrhs][L][3K] complex128, mesh order, host or device per flags; x is
+ *   overwritten (zero initial guess).  stats may be NULL.  Returns BEM_OK, BEM_WARN_NOCONV
+ *   (x holds the last iterate), or an error (BEM_ERR_ARG for bad sizes or options). */
+int bem_solve(bem_op *A, bem_op *A_inner, int32_t nrhs, const void *b, void *x, int32_t flags,
+              const bem_solve_opts *opts, bem_solve_stats *stats);
 
 /* Per-block description of a compressed operator for tests and reports:
  * rows (int64 x 8 per block): row_begin, row_size, col_begin, col_size (cluster order),

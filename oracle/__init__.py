@@ -123,6 +123,19 @@ class Problem:
         E = self.entries(op, ii.ravel(), jj.ravel(), ll.ravel()).reshape(K, K, L, 3, 3)
         return np.ascontiguousarray(E.transpose(2, 0, 3, 1, 4).reshape(L, 3 * K, 3 * K))
 
+    def solve(self, op, b, rhs_op=None):
+        """x[r, l] = A_l^{-1} c[r, l] with A_l the dense operator op at s_l (the collocation
+        system of Sec. 2.3 at each contour point), c = b, or c = B_l b with B the dense
+        operator rhs_op (V t = (I/2 + K) g: op = OP_V, rhs_op = OP_HK).  LU solve per
+        frequency (numpy).  b: [nrhs, L, 3K] -> [nrhs, L, 3K]."""
+        b = np.asarray(b, dtype=np.complex128)
+        A = self.dense(op)
+        c = b if rhs_op is None else np.einsum("lij,rlj->rli", self.dense(rhs_op), b)
+        x = np.empty_like(c)
+        for l in range(self.L):
+            x[:, l, :] = np.linalg.solve(A[l], c[:, l, :].T).T
+        return x
+
     def point_entries(self, op, pts, p, j, l):
         """int_{gamma_j} kernel(pts[p], y) dy for field points off the boundary -> [n, 3, 3]."""
         pts = np.ascontiguousarray(np.reshape(pts, (-1, 3)), dtype=np.float64)

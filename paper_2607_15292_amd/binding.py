@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BEM_LIBRARY", os.path.join(_HERE, "libbem.so"))
 
 BEM_OK = 0
+WARN_NOCONV = 2
 ERR_NAMES = {-1: "BEM_ERR_ARG", -2: "BEM_ERR_MESH", -3: "BEM_ERR_MATERIAL", -4: "BEM_ERR_FREQ",
              -5: "BEM_ERR_STATE", -6: "BEM_ERR_HIP", -7: "BEM_ERR_NOMEM", -8: "BEM_ERR_NODEVICE"}
 OP_V, OP_K, OP_HK, OP_TABLE = 0, 1, 2, 3
@@ -57,6 +58,19 @@ class bem_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class bem_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class bem_solve_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 # exported symbols and their signatures (also checked by the CPU tests)
 _P = ctypes.c_void_p
 _SIGS = {
@@ -80,6 +94,8 @@ _SIGS = {
     "bem_op_stats": (ctypes.c_int, [_P, ctypes.POINTER(bem_stats)]),
     "bem_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "bem_apply_weighted": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "bem_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(bem_solve_opts),
+                                 ctypes.POINTER(bem_solve_stats)]),
     "bem_op_blocks": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), _P, _P]),
     "bem_partition": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), _P, _P]),
     "bem_op_freq_hist": (ctypes.c_int, [_P, _P]),
@@ -300,6 +316,29 @@ class Operator:
         py, _ = _ptr(y)
         self.ctx._check(lib().bem_apply(self.h, int(nrhs), px, py, fl | (SHARED_X if shared_x else 0)))
         return y
+
+    def solve(self, b, x=None, inner=None, tol=1e-8, inner_tol=1e-3, restart=30, max_iter=500, max_refine=10):
+        """x[r, l] = A(s_l)^{-1} b[r, l] by GMRES with iterative refinement (bem_solve);
+        inner: a cheaper operator of the same context for the inner GMRES runs.
+        Returns (x, stats dict)."""
+        K, L = self.ctx.K, self.ctx.L
+        nrhs = b.shape[0]
+        if _is_torch(b):
+            import torch
+            if x is None:
+                x = torch.empty((nrhs, L, 3 * K), dtype=torch.complex128, device=b.device)
+            self.ctx._sync_torch_stream()
+        elif x is None:
+            x = np.empty((nrhs, L, 3 * K), dtype=np.complex128)
+        pb, fl = _ptr(b)
+        px, _ = _ptr(x)
+        o = bem_solve_opts(float(tol), float(inner_tol), int(restart), int(max_iter), int(max_refine), 0)
+        st = bem_solve_stats()
+        rc = self.ctx._check(lib().bem_solve(self.h, inner.h if inner is not None else None, int(nrhs), pb, px, fl,
+                                             ctypes.byref(o), ctypes.byref(st)))
+        d = st.as_dict()
+        d["rc"] = rc
+        return x, d
 
     def apply_weighted(self, W, y=None):
         K = self.ctx.K

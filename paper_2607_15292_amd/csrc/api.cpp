@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "host.hpp"
+#include "solve.hpp"
 
 using namespace bem;
 
@@ -651,6 +652,67 @@ int bem_apply(bem_op* op, int32_t nrhs, const void* x, void* y, int32_t flags)
             apply_compressed(op, nrhs, (const zd*)sx.dev, xls, (zd*)sy.dev, st);
         finish_out(sy, y, yb, dev, st);
         return BEM_OK;
+    });
+}
+
+namespace {
+
+// y = A x for [nrhs][L][3K] device buffers (mesh order)
+void op_apply(bem_op* op, int nrhs, const zd* x, zd* y, hipStream_t st)
+{
+    const size_t M = 3 * (size_t)op->K;
+    if (op->kind == 0)
+        launch_dense_apply(op->dense.as<zd>(), (int)M, op->L, nrhs, x, (int64_t)M, y, st);
+    else
+        apply_compressed(op, nrhs, x, (int64_t)M, y, st);
+}
+
+}  // namespace
+
+int bem_solve(bem_op* A, bem_op* A_inner, int32_t nrhs, const void* b, void* x, int32_t flags,
+              const bem_solve_opts* opts, bem_solve_stats* stats)
+{
+    if (!A) return BEM_ERR_ARG;
+    bem_ctx* ctx = A->ctx;
+    return guarded(ctx, [&]() -> int {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (nrhs < 1 || !b || !x) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
+        if (A_inner && (A_inner->ctx != ctx || A_inner->K != A->K || A_inner->L != A->L))
+            throw api_error(BEM_ERR_ARG, "inner operator of another context or size");
+        bem::SolveParams p;
+        if (opts) {
+            if (!(opts->tol > 0.0) || !(opts->inner_tol > 0.0 && opts->inner_tol < 1.0) || opts->restart < 1 ||
+                opts->max_iter < 1 || opts->max_refine < 0)
+                throw api_error(BEM_ERR_ARG, "solve options out of range");
+            p.tol = opts->tol;
+            p.inner_tol = opts->inner_tol;
+            p.restart = opts->restart;
+            p.max_iter = opts->max_iter;
+            p.max_refine = opts->max_refine;
+        }
+        need_device(ctx);
+        const bool dev = (flags & BEM_DEVICE_PTR) != 0;
+        const size_t M = 3 * (size_t)A->K;
+        const size_t bytes = (size_t)nrhs * A->L * M * sizeof(zd);
+        hipStream_t st = ctx->stream;
+        Staged sb, sx;
+        stage_in(sb, b, bytes, dev, st);
+        stage_out(sx, x, bytes, dev);
+        bem::DevApply fa = [&](const zd* in, zd* out) { op_apply(A, nrhs, in, out, st); };
+        bem::DevApply fi = [&](const zd* in, zd* out) { op_apply(A_inner, nrhs, in, out, st); };
+        const bool two = A_inner && A_inner != A;
+        const bem::SolveResult R = bem::gmres_refine(fa, two ? fi : fa, (int)M, nrhs * A->L, (const zd*)sb.dev,
+                                                     (zd*)sx.dev, p, st);
+        finish_out(sx, x, bytes, dev, st);
+        if (stats) {
+            stats->iterations = R.iterations;
+            stats->refinements = R.refinements;
+            stats->converged = R.converged ? 1 : 0;
+            stats->pad = 0;
+            stats->rel_residual = R.rel_residual;
+            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return R.converged ? BEM_OK : BEM_WARN_NOCONV;
     });
 }
 

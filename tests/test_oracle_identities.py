@@ -134,3 +134,37 @@ def test_pulsating_sphere_collocation_converges():
         res.append(np.abs(r).max() / np.abs(u).max())
     assert res[1] < 0.03
     assert res[1] < 0.6 * res[0]
+
+
+def test_oracle_solve_pulsating_sphere_converges():
+    """The oracle's dense solve of V t = (I/2 + K) u (Sec. 2.3 collocation system at one
+    contour point) recovers the exact traction of the pulsating sphere, with the error
+    falling under refinement."""
+    s = 1.78 + 0.9j
+    err = []
+    for lvl in (1, 2):
+        X, T = workloads.icosphere(lvl)
+        T = T[:, [0, 2, 1]].copy()
+        C, n = _geom(X, T)
+        u, t = _pulsating_sphere(C, n, s)
+        P = oracle.Problem(X, T, [s], near_on=True)
+        x = P.solve(oracle.OP_V, u.reshape(1, 1, -1), rhs_op=oracle.OP_HK)
+        err.append(np.linalg.norm(x[0, 0] - t.ravel()) / np.linalg.norm(t))
+    assert err[1] < 0.05
+    assert err[1] < 0.6 * err[0]
+
+
+def test_oracle_solve_is_inverse():
+    """solve(op, A x) = x for the dense operator itself (two right-hand sides, two
+    frequencies), and the right-hand-side operator is applied before the solve."""
+    X, T = workloads.icosphere(1)
+    s = [1.5 + 0.5j, 4.0 - 2.0j]
+    P = oracle.Problem(X, T, s, near_on=True)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, 2, 3 * P.K)) + 1j * rng.standard_normal((2, 2, 3 * P.K))
+    V = P.dense(oracle.OP_V)
+    H = P.dense(oracle.OP_HK)
+    b = np.einsum("lij,rlj->rli", V, x)
+    assert np.abs(P.solve(oracle.OP_V, b) - x).max() < 1e-9 * np.abs(x).max()
+    c = np.einsum("lij,rlj->rli", np.linalg.inv(H), b)  # H^-1 V x, so V^-1 H c = x
+    assert np.abs(P.solve(oracle.OP_V, c, rhs_op=oracle.OP_HK) - x).max() < 1e-8 * np.abs(x).max()
