@@ -58,10 +58,12 @@ def main():
     ap.add_argument("--eps-fp64-strict", type=float, default=1e-8,
                     help="3D-ACA tolerance of the FP64 run that meets 1e-6 per-frequency error")
     ap.add_argument("--pool-gb", type=float, default=0.0, help="0 = library default")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve leg (reported apart from value)")
+    ap.add_argument("--solve-tol", type=float, default=1e-6)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the sharded design is described in "
-              "DESIGN.md); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (the sharded path is designed, not built); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -154,6 +156,45 @@ def main():
                           "compression_rate": [v["compression_rate"] for v in st_s]}
         log("fp64 eps %.0e: compress %s ms" % (args.eps_fp64_strict, fp64["strict"]["compress_ms"]))
 
+    # solve leg (reported apart from value): V(s_l) t_l = (I/2 + K(s_l)) g_l at every contour
+    # point for the pulsating sphere; FP64 operators at the strict eps for the residuals and
+    # the right-hand side, the mixed V for the inner GMRES runs
+    solve = None
+    if not args.no_solve:
+        C = X[T].mean(axis=1)
+        nrm = np.cross(X[T[:, 1]] - X[T[:, 0]], X[T[:, 2]] - X[T[:, 0]])
+        nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+        g = np.empty((1, L, M), dtype=np.complex128)
+        t_ex = np.empty_like(g)
+        for l in range(L):
+            u_l, t_l = W.pulsating_sphere(C, nrm, s[l])
+            g[0, l] = u_l.ravel()
+            t_ex[0, l] = t_l.ravel()
+        tc0 = time.perf_counter()
+        Vf = c.compress(B.OP_V, eps3d=args.eps_fp64_strict, leaf=64, eta=1.5, prec=B.PREC_F64, pool_bytes=pool)
+        Vi = c.compress(B.OP_V, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED, pool_bytes=pool)
+        Hf = c.compress(B.OP_HK, eps3d=args.eps_fp64_strict, leaf=64, eta=1.5, prec=B.PREC_F64, pool_bytes=pool)
+        gd = torch.tensor(g, device=dev)
+        b = Hf.apply(gd)
+        torch.cuda.synchronize()
+        tc1 = time.perf_counter()
+        xs, sst = Vf.solve(b, inner=Vi, tol=args.solve_tol, inner_tol=1e-3)
+        torch.cuda.synchronize()
+        tc2 = time.perf_counter()
+        xh = xs.cpu().numpy()
+        err = float(np.max(np.linalg.norm(xh - t_ex, axis=-1) / np.linalg.norm(t_ex, axis=-1)))
+        solve = {"problem": "pulsating unit sphere, V t = (I/2 + K) g at all %d contour points" % L,
+                 "seconds": tc2 - tc1, "setup_seconds": tc1 - tc0, "iterations": sst["iterations"],
+                 "refinements": sst["refinements"], "converged": bool(sst["converged"]),
+                 "rel_residual": sst["rel_residual"], "tol": args.solve_tol,
+                 "max_rel_err_vs_closed_form": err,
+                 "operators": "fine: V FP64 eps %.0e; inner: V mixed eps %.0e; rhs: I/2+K FP64 eps %.0e"
+                              % (args.eps_fp64_strict, args.eps, args.eps_fp64_strict)}
+        log("solve: %.3f s, %d inner products, %d refinements, residual %.2e, error vs closed form %.3e"
+            % (tc2 - tc1, sst["iterations"], sst["refinements"], sst["rel_residual"], err))
+        for o in (Vf, Vi, Hf):
+            o.destroy()
+
     # roofline of the dominant compression kernel: algorithmic flops over event-timed device
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
     # 3D-ACA face kernels (k_face_dense / k_face_general); the one with more device time is
@@ -230,6 +271,7 @@ def main():
         "rel_err": errs,
         "roofline": roofline,
         "roofline_next": roofline_next,
+        "solve": solve,
         "cpu_baseline": cpu,
     }
     if fp64:

@@ -15,6 +15,9 @@ Triangles are oriented so that (v1 - v0) x (v2 - v0) points out of the bounded b
   uniform red refinement (194/384, 770/1536, 3074/6144).
 * ``icosphere(level, radius)`` -- icosahedron with midpoint subdivision projected to the
   sphere: 20 * 4**level triangles (1280, 5120, 20480 for levels 3, 4, 5).
+* ``pulsating_sphere(points, normals, s)`` -- Dirichlet data and exact traction of the
+  radially pulsating unit sphere (exterior domain), the closed-form test problem of the
+  solve.
 * ``bdf2_contour(L, dt)`` -- the L contour points s_l = (3 - 4 z + z^2) / (2 dt),
   z = R exp(2 pi i l / L), R = (1e-10)**(1 / (2 L)); they come in conjugate pairs
   (Sec. 4.1 notes this property of the gCQ points).
@@ -192,6 +195,31 @@ def bdf2_contour(L: int, dt: float = 0.1):
     if L % 2 == 0:
         s[L // 2] = s[L // 2].real
     return s.astype(np.complex128)
+
+
+def pulsating_sphere(points, normals, s, rho=1.0, cp=1.0, cs=0.5, a=2.5):
+    """Exact displacement u and traction t = sigma n at points (normals n) of the radially
+    pulsating unit sphere in the Laplace domain: u = A grad phi, phi = exp(-k r) / r,
+    k = s / cp, scaled so that u(r = 1) = G(s) rh with G the Laplace transform of the pulse
+    (a t)^4 exp(-a t) of Sec. 4.2 (a = 2.5); sigma from the isotropic stress law of
+    Sec. 2.1.  Returns complex128 arrays [n, 3] (u, t)."""
+    points = np.asarray(points, dtype=np.float64)
+    normals = np.asarray(normals, dtype=np.float64)
+    mu = rho * cs**2
+    lam = rho * cp**2 - 2 * mu
+    k = s / cp
+    G = a**4 * 24.0 / (s + a) ** 5
+    A = G / (-(1 + k) * np.exp(-k))
+    r = np.linalg.norm(points, axis=1)
+    rh = points / r[:, None]
+    e = np.exp(-k * r)
+    d1 = -(1 + k * r) * e / r**2
+    d2 = (2 + 2 * k * r + (k * r) ** 2) * e / r**3
+    u = (A * d1)[:, None] * rh
+    rn = np.sum(rh * normals, axis=1)
+    t = ((lam * A * k * k * e / r)[:, None] * normals
+         + 2 * mu * A * ((d2 * rn)[:, None] * rh + (d1 / r)[:, None] * (normals - rn[:, None] * rh)))
+    return u, t
 
 
 def random_rhs(seed: int, shape):
