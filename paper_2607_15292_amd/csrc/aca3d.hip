@@ -501,6 +501,7 @@ struct AcaShared {
 // per face.
 constexpr int WA = 64;
 constexpr int KMAX_SLICE = 96;  // largest ACA column count (the scratch and LDS capacity)
+constexpr int CB = 8;           // earlier ACA columns read per batch in the residual passes
 
 __device__ __forceinline__ double wmax(double v)
 {
@@ -570,7 +571,17 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
 #pragma unroll
             for (int y = 0; y < 3; ++y) e[y] = ldz(H + (size_t)(3 * irow + y) * N3 + q);
             const zd* vq = w.V + q;
-            for (int c = 0; c < kc; ++c) {
+            int c = 0;
+            for (; c + CB <= kc; c += CB) {  // CB loads in flight per lane
+                zd v[CB];
+#pragma unroll
+                for (int t = 0; t < CB; ++t) v[t] = vq[(size_t)(c + t) * N3];
+#pragma unroll
+                for (int t = 0; t < CB; ++t)
+#pragma unroll
+                    for (int y = 0; y < 3; ++y) e[y] -= mul_conj(sk[3 * (c + t) + y], v[t]);
+            }
+            for (; c < kc; ++c) {
                 const zd v = vq[(size_t)c * N3];
 #pragma unroll
                 for (int y = 0; y < 3; ++y) e[y] -= mul_conj(sk[3 * c + y], v);
@@ -641,7 +652,17 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
 #pragma unroll
             for (int x = 0; x < 3; ++x) e[x] = ldz(H + (size_t)q * N3 + 3 * bj + x);
             const zd* uq = w.U + q;
-            for (int c = 0; c < kc; ++c) {
+            int c = 0;
+            for (; c + CB <= kc; c += CB) {
+                zd u[CB];
+#pragma unroll
+                for (int t = 0; t < CB; ++t) u[t] = uq[(size_t)(c + t) * M3];
+#pragma unroll
+                for (int t = 0; t < CB; ++t)
+#pragma unroll
+                    for (int x = 0; x < 3; ++x) e[x] -= mul_conj(u[t], sk[3 * (c + t) + x]);
+            }
+            for (; c < kc; ++c) {
                 const zd u = uq[(size_t)c * M3];
 #pragma unroll
                 for (int x = 0; x < 3; ++x) e[x] -= mul_conj(u, sk[3 * c + x]);
