@@ -176,6 +176,55 @@ __device__ __forceinline__ void sub_residual_share(blk& E, const CompressArgs& A
     }
 }
 
+// Y += H F^H for a 3x3 block H and F = F_{d-1,a} (row-major complex128 in global memory)
+__device__ __forceinline__ void acc_hfh(blk& Y, const blk& H, const zd* F)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            zd s = Y.a[3 * i + j];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) s += mul_conj(H.a[3 * i + t], F[3 * j + t]);
+            Y.a[3 * i + j] = s;
+        }
+}
+
+// Re sum_ij conj(Y_ij) H_ij
+__device__ __forceinline__ double re_inner(const blk& Y, const blk& H)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s += Y.a[q].re * H.a[q].re + Y.a[q].im * H.a[q].im;
+    return s;
+}
+
+// the share of lane u (of a group of lpp) in the residual of E and in the previous step's
+// trace-form terms (sub_residual_cross): faces a = u, u + lpp, ...; every lane adds
+// <Y_u, H_{d-1}> for its share Y_u, lane 0 also the t_dd term
+__device__ __forceinline__ void sub_residual_share_cross(blk& E, const CompressArgs& A, const FaceDesc* fd,
+                                                         const zd* Fb, int d, int n, int i, int j, int k, int u,
+                                                         int lpp, double& cross, double& tdd)
+{
+    blk Y = blk_zero();
+    for (int a = u; a < d; a += lpp) {
+        const FaceDesc f = fd[a];
+        const blk H = face_block(A.pool, f, n, i, j);
+        const blk fk = fibre_at(A.pool, f, k);
+        blk_mul_sub(E, H, fk);
+        if (a < d - 1) acc_hfh(Y, H, Fb + 9 * (size_t)a);
+    }
+    if (d >= 1) {
+        const blk Hp = face_block(A.pool, fd[d - 1], n, i, j);
+        cross += re_inner(Y, Hp);
+        if (u == 0) {
+            blk Z = blk_zero();
+            acc_hfh(Z, Hp, Fb + 9 * (size_t)(d - 1));
+            tdd += re_inner(Z, Hp);
+        }
+    }
+}
+
 // lanes per pair for the rule of a pair class: regular 1, near level 1 / 2: 4 / 16 (one
 // sub-triangle each), self: a wavefront (angular lines round robin)
 __device__ __forceinline__ int pair_lanes(int cls)
@@ -246,7 +295,7 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
     s.piv = 0;
     s.nextk = -1;
     s.aca_dense = 0;
-    s.pad = 0;
+    s.term = 0;
     s.aca_cols = 0;
     s.norm2 = 0.0;
     s.hn2 = s.fmax2 = s.s3max = s.fn2 = 0.0;
@@ -279,14 +328,18 @@ __device__ __forceinline__ blk pair_entry(const CompressArgs& A, int gi, int gj,
     }
 }
 
-// E -= sum_{a<d} H_a[i,j] f_a[k] over the dense faces of an iterating block (precision of
-// the faces known at compile time).
+// The trace-form norm terms of the previous step d - 1 at pair (i, j), taken in the
+// residual loop of step d while the earlier faces pass through registers (eq. (FrobNorm)):
+//   cross += Re sum_{a<d-1} tr(H_a^H H_{d-1} F_{d-1,a}) = Re <sum_a H_a F_{d-1,a}^H, H_{d-1}>
+//   tdd   += Re tr(H_{d-1}^H H_{d-1} F_{d-1,d-1})      = Re <H_{d-1} F_{d-1,d-1}^H, H_{d-1}>
+// F_{d-1,a} = A.Fda[b][a] as left by the fibre kernel of step d - 1.
 template <bool F32>
-__device__ __forceinline__ void sub_residual_t(blk& E, const char* pool, const FaceDesc* fd, int d, int n, int i,
-                                               int j, int k)
+__device__ __forceinline__ void sub_residual_cross(blk& E, const char* pool, const FaceDesc* fd, const zd* Fb, int d,
+                                                   int n, int i, int j, int k, double& cross, double& tdd)
 {
     const size_t ld = 3 * (size_t)n;
-#pragma unroll 2
+    blk Y = blk_zero();
+#pragma unroll 1
     for (int a = 0; a < d; ++a) {
         const FaceDesc f = fd[a];
         blk H;
@@ -305,6 +358,14 @@ __device__ __forceinline__ void sub_residual_t(blk& E, const char* pool, const F
         }
         const blk fk = fibre_at(pool, f, k);
         blk_mul_sub(E, H, fk);
+        if (a < d - 1) {
+            acc_hfh(Y, H, Fb + 9 * (size_t)a);
+        } else {
+            cross += re_inner(Y, H);
+            blk Z = blk_zero();
+            acc_hfh(Z, H, Fb + 9 * (size_t)a);
+            tdd += re_inner(Z, H);
+        }
     }
 }
 
@@ -332,12 +393,12 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
     const FaceDesc* fd = A.faces + (size_t)b * A.L;
     const FaceDesc F = fd[d];
     const int p = tile_pair(A, B, t, threadIdx.x);
-    double s3 = -1.0, e2 = 0.0;
+    double s3 = -1.0, e2 = 0.0, cross = 0.0, tdd = 0.0;
     int pi = 0x7fffffff;
     if (p >= 0) {
         const int i = p / n, j = p - (p / n) * n;
         blk E = pair_entry<KOP, PATH>(A, B.rb + i, B.cb + j, k);
-        sub_residual_t<F32>(E, A.pool, fd, d, n, i, j, k);
+        sub_residual_cross<F32>(E, A.pool, fd, A.Fda + (size_t)b * A.L * 9, d, n, i, j, k, cross, tdd);
         const size_t ld = 3 * (size_t)n;
         if constexpr (F32) {
             zf* H = (zf*)(A.pool + F.face_off);
@@ -361,8 +422,8 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
         s3 = blk_sigma3(E);
         pi = p;
     }
-    double v[1] = {e2};
-    wg_sum<1>(v, S);
+    double v[3] = {e2, cross, tdd};
+    wg_sum<3>(v, S);
     double fm = wg_max(e2, S);
     wg_argmax(s3, pi, S);
     if (threadIdx.x == 0) {
@@ -371,6 +432,8 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
         tp[1] = (double)pi;
         tp[2] = v[0];
         tp[3] = fm;
+        tp[4] = v[1];  // trace-form terms of step d - 1
+        tp[5] = v[2];
         atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(TILE, B.nreg - t * TILE)));
     }
 }
@@ -413,6 +476,7 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
     const int p = valid ? A.pairs[B.pair0 + base + q] : 0;
     const int i = p / n, j = p - (p / n) * n;
     blk E = blk_zero();
+    double cross = 0.0, tdd = 0.0;
     if (valid) {
         const int nu = rule_units(cls, A.c.qt);
         for (int uu = u; uu < nu; uu += lpp) {
@@ -429,7 +493,7 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
             E.a[4].re += 0.5;
             E.a[8].re += 0.5;
         }
-        sub_residual_share(E, A, fd, d, n, i, j, k, u, lpp);
+        sub_residual_share_cross(E, A, fd, A.Fda + (size_t)b * A.L * 9, d, n, i, j, k, u, lpp, cross, tdd);
     }
     group_sum(E, lpp);
     double s3 = -1.0, e2 = 0.0;
@@ -458,8 +522,8 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
         s3 = blk_sigma3(E);
         pi = p;
     }
-    double v[1] = {e2};
-    wg_sum<1>(v, S);
+    double v[3] = {e2, cross, tdd};
+    wg_sum<3>(v, S);
     double fm = wg_max(e2, S);
     wg_argmax(s3, pi, S);
     if (threadIdx.x == 0) {
@@ -468,6 +532,8 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
         tp[1] = (double)pi;
         tp[2] = v[0];
         tp[3] = fm;
+        tp[4] = v[1];  // trace-form terms of step d - 1
+        tp[5] = v[2];
         atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(ppt, cnt - tl * ppt)));
     }
     (void)m;
@@ -920,7 +986,7 @@ __global__ __launch_bounds__(WG) void k_cross_dense(CompressArgs A)
     __shared__ zd Fs[MAX_L * 9];
     const int item = A.list[blockIdx.x];
     const int b = item >> 12, t = item & 4095;
-    if (!A.st[b].active || A.st[b].stop) return;
+    if (!A.st[b].active || A.st[b].stop || !A.st[b].term) return;
     const BlockIn B = A.blocks[b];
     const int m = B.rs, n = B.cs, d = A.d, L = A.L;
     const FaceDesc* fd = A.faces + (size_t)b * L;
@@ -955,13 +1021,62 @@ __global__ __launch_bounds__(WG) void k_cross_dense(CompressArgs A)
 
 // ---------------------------------------------------------------- finalize the step
 
+// Step d of a block that has no next frequency (d + 1 == L or every k used): its trace-form
+// terms come from k_cross_dense; norm update and the test of eq. (precision).
 __global__ __launch_bounds__(64) void k_final(CompressArgs A)
 {
     int q = blockIdx.x * 64 + threadIdx.x;
     if (q >= A.nlist) return;
     const int b = A.list[q];
     BlockState s = A.st[b];
+    if (!s.active || s.stop || !s.term) return;
+    const BlockIn B = A.blocks[b];
+    const int d = A.d;
+    double cross = 0.0, tdd = 0.0;
+    for (int t = 0; t < B.ntile; ++t) {
+        const double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
+        cross += tp[4];
+        tdd += tp[5];
+    }
+    s.norm2 += 2.0 * cross + tdd;
+    const double eps = block_eps(A, B);
+    s.rank = !(sqrt(s.hn2 * s.fn2) > eps * sqrt(fmax(s.norm2, 0.0))) ? d : d + 1;  // sub-tolerance pair dropped
+    s.active = 0;
+    A.st[b] = s;
+}
+
+// After the fibre of step d: a block with a next frequency starts step d + 1 before the test
+// of step d is known (its trace-form terms come with the face kernels of step d + 1);
+// without one it is terminal (k_cross_dense, k_final).
+__global__ __launch_bounds__(64) void k_advance(CompressArgs A)
+{
+    int q = blockIdx.x * 64 + threadIdx.x;
+    if (q >= A.nlist) return;
+    const int b = A.list[q];
+    BlockState s = A.st[b];
     if (!s.active || s.stop) return;
+    const int d = A.d;
+    if (s.nextk < 0 || d + 1 == A.L) {
+        s.term = 1;
+    } else {
+        s.k = s.nextk;
+        if (!alloc_step(A, b, d + 1, s.k)) {
+            s.term = 1;  // pool exhausted: the error flag is set, the block ends here
+        }
+    }
+    A.st[b] = s;
+}
+
+// After the face kernels of step d (d >= 1): trace-form terms of step d - 1 (tile partials
+// 4, 5), norm update and the test of eq. (precision) for step d - 1.  On failure the pair
+// d - 1 is dropped (rank d - 1) and the face of step d is discarded.
+__global__ __launch_bounds__(64) void k_final_prev(CompressArgs A)
+{
+    int q = blockIdx.x * 64 + threadIdx.x;
+    if (q >= A.nlist) return;
+    const int b = A.list[q];
+    BlockState s = A.st[b];
+    if (!s.active) return;
     const BlockIn B = A.blocks[b];
     const int d = A.d;
     double cross = 0.0, tdd = 0.0;
@@ -973,16 +1088,11 @@ __global__ __launch_bounds__(64) void k_final(CompressArgs A)
     s.norm2 += 2.0 * cross + tdd;
     const double eps = block_eps(A, B);
     if (!(sqrt(s.hn2 * s.fn2) > eps * sqrt(fmax(s.norm2, 0.0)))) {
-        s.rank = d;  // the sub-tolerance pair is dropped
+        s.rank = d - 1;
         s.active = 0;
+        s.entries -= (long long)B.rs * B.cs;  // the face of step d is not kept
     } else {
-        s.rank = d + 1;
-        if (s.nextk < 0 || d + 1 == A.L) {
-            s.active = 0;
-        } else {
-            s.k = s.nextk;
-            if (!alloc_step(A, b, d + 1, s.k)) s.active = 0;
-        }
+        s.rank = d;
     }
     A.st[b] = s;
 }
@@ -1138,6 +1248,11 @@ void launch_fibre(const CompressArgs& A, hipStream_t st)
 }
 void launch_cross_dense(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_cross_dense, A.nlist, WG, A); }
 void launch_final(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_final, (A.nlist + 63) / 64, 64, A); }
+void launch_advance(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_advance, (A.nlist + 63) / 64, 64, A); }
+void launch_final_prev(const CompressArgs& A, hipStream_t st)
+{
+    BEM_LAUNCH(k_final_prev, (A.nlist + 63) / 64, 64, A);
+}
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st)
 {
     BEM_LAUNCH(k_fallback_alloc, (A.nlist + 63) / 64, 64, A, kf);

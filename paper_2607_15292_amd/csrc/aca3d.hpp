@@ -49,7 +49,7 @@ struct BlockState {
     int piv;        // pivot pair of the current face
     int nextk;      // next frequency
     int aca_dense;  // faces of this block left dense by the per-slice ACA pass
-    int pad;
+    int term;       // no next frequency: the current step is the last one
     long long aca_cols;  // ACA columns (before recompression) over the faces stored as factors
     double norm2;   // ||C^(d)||_F^2
     double hn2, fmax2, s3max, fn2;
@@ -145,6 +145,8 @@ void launch_pivot(const CompressArgs& A, hipStream_t st);
 void launch_fibre(const CompressArgs& A, hipStream_t st);
 void launch_cross_dense(const CompressArgs& A, hipStream_t st);
 void launch_final(const CompressArgs& A, hipStream_t st);
+void launch_advance(const CompressArgs& A, hipStream_t st);
+void launch_final_prev(const CompressArgs& A, hipStream_t st);
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st);
 void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st);
 // per-slice ACA (k_face_aca); the recompression of its columns follows (k_face_recomp)

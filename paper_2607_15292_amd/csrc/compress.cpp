@@ -494,11 +494,13 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         face_pending = true;
         A.list = p_act;
         A.nlist = (int)act.size();
+        if (d > 0) launch_final_prev(A, st);  // trace-form terms of step d - 1 came with the faces
         launch_pivot(A, st);
         launch_fibre(A, st);
+        launch_advance(A, st);
         A.list = p_tiles;
         A.nlist = (int)tiles.size();
-        launch_cross_dense(A, st);
+        launch_cross_dense(A, st);  // blocks without a next frequency only
         A.list = p_act;
         A.nlist = (int)act.size();
         launch_final(A, st);
