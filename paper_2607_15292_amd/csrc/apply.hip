@@ -144,15 +144,16 @@ __global__ __launch_bounds__(WGA) void k_far_products(ApplyArgs A, const int* fa
 }
 
 // Y[rows][cols] += Hs[rows][k] Zs[k][cols] over one staged tile; thread = element row er
-// (3 rows) x 4 consecutive columns: 12 complex accumulators, 7 LDS reads per 12 complex
-// multiply-adds (the FP64 VALU, not LDS, bounds the loop)
+// (3 rows) x columns cq, cq + 16, cq + 32, cq + 48: 12 complex accumulators, 7 LDS reads
+// per 12 complex multiply-adds.  Lanes of a wavefront read consecutive Zs entries and Hs rows
+// are padded to an odd number of entries, so neither read has bank conflicts.
 template <int KTL>
 __device__ __forceinline__ void tile_mac(const zd (*Hs)[KTL], const zd (*Zs)[NC], int nk, int er, int cq, zd (*acc)[4])
 {
     for (int k = 0; k < nk; ++k) {
         zd z[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) z[v] = Zs[k][4 * cq + v];
+        for (int v = 0; v < 4; ++v) z[v] = Zs[k][cq + 16 * v];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const zd h = Hs[3 * er + a][k];
@@ -167,7 +168,7 @@ __device__ __forceinline__ void tile_mac(const zd (*Hs)[KTL], const zd (*Zs)[NC]
 template <bool WEIGHTED>
 __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int ncols)
 {
-    __shared__ zd Hs[3 * RCE][KR];
+    __shared__ zd Hs[3 * RCE][KR + 1];
     __shared__ zd Zs[KR][NC];
     __shared__ zd Fs[NC][9];
     const int sg = blockIdx.x, g = A.seg_group[sg];
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
                 }
                 stage_z<WEIGHTED, KR>(A, B, zw, k0, c0, ncols, Fs, Zs);
                 __syncthreads();
-                tile_mac<KR>(Hs, Zs, nk, er, cq, acc);
+                tile_mac<KR + 1>(Hs, Zs, nk, er, cq, acc);
             }
         } else {
             const int kk = F.kk;
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
                     Zs[kr][cl] = (kr < nk && c0 + cl < ncols) ? Tf[(size_t)(k0 + kr) * ncols + c0 + cl] : zd{0.0, 0.0};
                 }
                 __syncthreads();
-                tile_mac<KR>(Hs, Zs, nk, er, cq, acc);
+                tile_mac<KR + 1>(Hs, Zs, nk, er, cq, acc);
             }
         }
     }
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
         zd* pb = A.pbuf + (size_t)sg * 3 * RCE * ncols;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int col = c0 + 4 * cq + v;
+            const int col = c0 + cq + 16 * v;
             if (col >= ncols) continue;
 #pragma unroll
             for (int a = 0; a < 3; ++a) pb[(size_t)(3 * er + a) * ncols + col] = acc[a][v];
