@@ -539,14 +539,60 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
     (void)m;
 }
 
+// Pair order of block list[q]: its pairs p = i cs + j sorted by class (regular, near 1, near
+// 2, self), increasing p within a class (a stable partition), written to order[off[q] ..];
+// counts[4 q + c] = pairs of class c.  One workgroup per listed block: a counting pass, then
+// a scatter pass over chunks of WG pairs with wavefront ballots for the ranks.
 __global__ __launch_bounds__(WG) void k_classify(DevCtx c, const BlockIn* blocks, const int* list,
-                                                 const long long* off, unsigned char* cls)
+                                                 const long long* off, int* order, int* counts)
 {
+    __shared__ int cnt[4];
+    __shared__ int wcnt[WG / 64][4];
     const BlockIn B = blocks[list[blockIdx.x]];
-    unsigned char* o = cls + off[blockIdx.x];
-    for (int p = threadIdx.x; p < B.rs * B.cs; p += WG) {
+    const int mn = B.rs * B.cs;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int own[4] = {0, 0, 0, 0};
+    for (int p = threadIdx.x; p < mn; p += WG) {
         const int i = p / B.cs, j = p - i * B.cs;
-        o[p] = (unsigned char)pair_class(c.geo, B.rb + i, B.cb + j, c.qt);
+        ++own[pair_class(c.geo, B.rb + i, B.cb + j, c.qt)];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) atomicAdd(&cnt[k], own[k]);
+    __syncthreads();
+    int base[4];
+    base[0] = 0;
+    base[1] = cnt[0];
+    base[2] = cnt[0] + cnt[1];
+    base[3] = cnt[0] + cnt[1] + cnt[2];
+    if (threadIdx.x < 4) counts[4 * (size_t)blockIdx.x + threadIdx.x] = cnt[threadIdx.x];
+    int* o = order + off[blockIdx.x];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int p0 = 0; p0 < mn; p0 += WG) {
+        const int p = p0 + threadIdx.x;
+        int k = -1;
+        if (p < mn) {
+            const int i = p / B.cs, j = p - i * B.cs;
+            k = pair_class(c.geo, B.rb + i, B.cb + j, c.qt);
+        }
+        int rank = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned long long m = __ballot(k == q);
+            if (k == q) rank = __popcll(m & below);
+            if (lane == 0) wcnt[wv][q] = __popcll(m);
+        }
+        __syncthreads();
+        if (k >= 0) {
+            int pos = base[k] + rank;
+            for (int w = 0; w < wv; ++w) pos += wcnt[w][k];
+            o[pos] = p;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            for (int w = 0; w < WG / 64; ++w) base[q] += wcnt[w][q];
+        __syncthreads();
     }
 }
 
@@ -1229,9 +1275,9 @@ void launch_face_aca(const CompressArgs& A, hipStream_t st)
     BEM_LAUNCH(k_face_aca, A.nlist, WA, A);
 }
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
-                     unsigned char* cls, hipStream_t st)
+                     int* order, int* counts, hipStream_t st)
 {
-    BEM_LAUNCH(k_classify, n, WG, c, blocks, list, off, cls);
+    BEM_LAUNCH(k_classify, n, WG, c, blocks, list, off, order, counts);
 }
 void launch_pivot(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_pivot, (A.nlist + 63) / 64, 64, A); }
 void launch_fibre(const CompressArgs& A, hipStream_t st)

@@ -138,9 +138,10 @@ void launch_init(const CompressArgs& A, hipStream_t st);
 // rule); 0 / 3 near tiles and 4 / 5 self tiles with complex128 / complex64 faces
 // (k_face_general, FP64 rules)
 void launch_face_dense(const CompressArgs& A, int path, hipStream_t st);
-// cls[off[q] + p] = pair class of pair p of block list[q] (one workgroup per listed block)
+// order[off[q] ..] = pairs of block list[q] stably sorted by class (regular, near 1, near 2,
+// self); counts[4 q + c] = pairs of class c (one workgroup per listed block)
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
-                     unsigned char* cls, hipStream_t st);
+                     int* order, int* counts, hipStream_t st);
 void launch_pivot(const CompressArgs& A, hipStream_t st);
 void launch_fibre(const CompressArgs& A, hipStream_t st);
 void launch_cross_dense(const CompressArgs& A, hipStream_t st);

@@ -274,46 +274,35 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     }
     // pair orders: regular pairs first, then the near and self pairs sorted by class
     DevBuf pairs_dev;
-    std::vector<int> pair_order;
     if (!cls_blocks.empty()) {
         std::vector<long long> off(cls_blocks.size() + 1, 0);
         for (size_t q = 0; q < cls_blocks.size(); ++q) {
             const BlockIn& B = C->blocks[cls_blocks[q]];
             off[q + 1] = off[q] + (long long)B.rs * B.cs;
         }
-        DevBuf cls_d, off_d, lst_d;
-        cls_d.alloc(std::max<long long>(off.back(), 16));
+        if (off.back() >= (1LL << 31)) throw Err(BEM_ERR_ARG, "pair list too long");
+        DevBuf off_d, lst_d, cnt_d;
         off_d.alloc(sizeof(long long) * off.size());
         lst_d.alloc(sizeof(int) * cls_blocks.size());
+        cnt_d.alloc(sizeof(int) * 4 * cls_blocks.size());
+        pairs_dev.alloc(sizeof(int) * std::max<long long>(off.back(), 4));
         C->blocks_dev.alloc(sizeof(BlockIn) * nb);
         BEM_HIP_TRY(hipMemcpyAsync(C->blocks_dev.p, C->blocks.data(), sizeof(BlockIn) * nb, hipMemcpyHostToDevice, st));
         BEM_HIP_TRY(hipMemcpyAsync(off_d.p, off.data(), sizeof(long long) * off.size(), hipMemcpyHostToDevice, st));
         BEM_HIP_TRY(hipMemcpyAsync(lst_d.p, cls_blocks.data(), sizeof(int) * cls_blocks.size(), hipMemcpyHostToDevice, st));
         launch_classify(ctx->devctx(C->geo.geo, C->perm_dev.as<int>()), C->blocks_dev.as<BlockIn>(), lst_d.as<int>(),
-                        off_d.as<long long>(), (int)cls_blocks.size(), cls_d.as<unsigned char>(), st);
-        std::vector<unsigned char> cls(off.back());
-        BEM_HIP_TRY(hipMemcpyAsync(cls.data(), cls_d.p, cls.size(), hipMemcpyDeviceToHost, st));
+                        off_d.as<long long>(), (int)cls_blocks.size(), pairs_dev.as<int>(), cnt_d.as<int>(), st);
+        std::vector<int> cnt(4 * cls_blocks.size());
+        BEM_HIP_TRY(hipMemcpyAsync(cnt.data(), cnt_d.p, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost, st));
         BEM_HIP_TRY(hipStreamSynchronize(st));
-        pair_order.reserve(off.back());
         for (size_t q = 0; q < cls_blocks.size(); ++q) {
             BlockIn& B = C->blocks[cls_blocks[q]];
-            const unsigned char* c = cls.data() + off[q];
-            const int mn = B.rs * B.cs;
-            if ((long long)pair_order.size() + mn >= (1LL << 31)) throw Err(BEM_ERR_ARG, "pair list too long");
-            B.pair0 = (int)pair_order.size();
-            for (int k = 0; k < 4; ++k)
-                for (int p = 0; p < mn; ++p)
-                    if (c[p] == k) pair_order.push_back(p);
-            int cnt[4] = {0, 0, 0, 0};
-            for (int p = 0; p < mn; ++p) ++cnt[c[p]];
-            B.nreg = cnt[0];
-            B.n1 = cnt[1];
-            B.n2 = cnt[2];
-            B.n3 = cnt[3];
+            B.pair0 = (int)off[q];
+            B.nreg = cnt[4 * q];
+            B.n1 = cnt[4 * q + 1];
+            B.n2 = cnt[4 * q + 2];
+            B.n3 = cnt[4 * q + 3];
         }
-        pairs_dev.alloc(sizeof(int) * pair_order.size());
-        BEM_HIP_TRY(hipMemcpyAsync(pairs_dev.p, pair_order.data(), sizeof(int) * pair_order.size(),
-                                   hipMemcpyHostToDevice, st));
     }
     for (int b = 0; b < nb; ++b) {
         BlockIn& B = C->blocks[b];
@@ -326,7 +315,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     }
     kmax = std::min(kmax, KMAX_ACA);
     DevBuf aux, st_dev, used_dev, fda_dev, tp_dev, list_dev;
-    C->blocks_dev.alloc(sizeof(BlockIn) * nb);
+    if (!C->blocks_dev.p) C->blocks_dev.alloc(sizeof(BlockIn) * nb);
     BEM_HIP_TRY(hipMemcpyAsync(C->blocks_dev.p, C->blocks.data(), sizeof(BlockIn) * nb, hipMemcpyHostToDevice, st));
     aux.alloc(256);
     int* err_dev = aux.as<int>();
