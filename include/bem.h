@@ -281,6 +281,55 @@ typedef struct bem_solve_stats {
 int bem_solve(bem_op *A, bem_op *A_inner, int32_t nrhs, const void *b, void *x, int32_t flags,
               const bem_solve_opts *opts, bem_solve_stats *stats);
 
+/* ---- Batched products of several compressed operators ------------------------------------
+ * The all-frequency product of bem_apply (the face-fibre form of eq. (3DacaMult) at every
+ * contour point) for up to 16 compressed operators at once, e.g. several meshes sharing one
+ * set of L contour points: one merged plan of all their blocks, faces and row chunks, so that
+ * each kernel of the product runs once over every operator, frequency and right-hand side
+ * (far-face products, row products, row sums, two batched permutations). */
+typedef struct bem_batch bem_batch;
+
+#define BEM_BATCH_GRAPH 1  /* bem_batch_create: record the launches of a call in a HIP graph and
+                              replay it while the same device buffers and stream come back */
+#define BEM_BATCH_TUNE 2   /* bem_batch_create: time the candidate schedules (segment counts,
+                              persistent row grid, far faces by decreasing rank) and keep the
+                              fastest */
+
+/* Schedule and counters of a batch. */
+typedef struct bem_batch_info {
+    int32_t nops, nrhs, L, K_total;   /* operators, right-hand sides, frequencies, elements */
+    int32_t n_groups, n_segments;     /* row chunks of all operators, row-kernel segments */
+    int32_t n_far_faces, seg_target;  /* factored faces, segment target of the schedule */
+    int32_t persistent, persistent_wgs; /* row kernel on a persistent grid of that many groups */
+    int32_t far_sorted, graph;        /* far faces by decreasing rank; HIP graph replay on */
+    int32_t graph_builds, graph_launches;
+    int32_t n_tuned, pad;             /* timed candidates (at most 8) */
+    double tune_ms[8];                /* product time of each timed candidate (events, ms) */
+    int32_t tune_segments[8];         /* its segment count */
+    double workspace_bytes;           /* device workspace held by the batch */
+} bem_batch_info;
+
+/* Creates a batch over ops[0 .. nops) (1 <= nops <= 16): compressed operators with the same
+ * L on the same device, possibly of different contexts and meshes; nrhs right-hand sides per
+ * operator.  The batch holds its plan and a workspace sized for nrhs (no allocation in
+ * bem_batch_apply); the operators must stay alive while it does (bem_op_destroy returns
+ * BEM_ERR_STATE until the batch is destroyed).  Runs on the stream of ops[0]'s context.
+ * Errors: BEM_ERR_ARG (dense operator, different L or device, nops or nrhs out of range),
+ * BEM_ERR_NOMEM. */
+int bem_batch_create(bem_op *const *ops, int32_t nops, int32_t nrhs, int32_t flags, bem_batch **out);
+
+/* y[o][r][l] = A_o(s_l) x[o][r][l] for every operator o of the batch: x[o], y[o] are
+ * [nrhs][L][3 K_o] complex128 in mesh order, host or device per flags (BEM_DEVICE_PTR; a
+ * batch created with BEM_BATCH_GRAPH takes device buffers only).  Results equal those of
+ * bem_apply on each operator up to the order of the floating-point sums. */
+int bem_batch_apply(bem_batch *b, const void *const *x, void *const *y, int32_t flags);
+
+/* Schedule, tuning times and graph counters of a batch. */
+int bem_batch_info_get(const bem_batch *b, bem_batch_info *info);
+
+/* Releases a batch (its plan, workspace and graph). */
+int bem_batch_destroy(bem_batch *b);
+
 /* Per-block description of a compressed operator for tests and reports:
  * rows (int64 x 8 per block): row_begin, row_size, col_begin, col_size (cluster order),
  * is_far, rank, dense_fallback, aca_cols_total.  perm: [K] int32, cluster position ->

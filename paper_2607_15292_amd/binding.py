@@ -71,6 +71,22 @@ class bem_solve_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class bem_batch_info(ctypes.Structure):
+    _fields_ = [("nops", ctypes.c_int32), ("nrhs", ctypes.c_int32), ("L", ctypes.c_int32), ("K_total", ctypes.c_int32),
+                ("n_groups", ctypes.c_int32), ("n_segments", ctypes.c_int32), ("n_far_faces", ctypes.c_int32),
+                ("seg_target", ctypes.c_int32), ("persistent", ctypes.c_int32), ("persistent_wgs", ctypes.c_int32),
+                ("far_sorted", ctypes.c_int32), ("graph", ctypes.c_int32), ("graph_builds", ctypes.c_int32),
+                ("graph_launches", ctypes.c_int32), ("n_tuned", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("tune_ms", ctypes.c_double * 8), ("tune_segments", ctypes.c_int32 * 8),
+                ("workspace_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "tune_ms", "tune_segments")}
+        d["tune_ms"] = list(self.tune_ms)[:self.n_tuned]
+        d["tune_segments"] = list(self.tune_segments)[:self.n_tuned]
+        return d
+
+
 # exported symbols and their signatures (also checked by the CPU tests)
 _P = ctypes.c_void_p
 _SIGS = {
@@ -96,6 +112,11 @@ _SIGS = {
     "bem_apply_weighted": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "bem_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(bem_solve_opts),
                                  ctypes.POINTER(bem_solve_stats)]),
+    "bem_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "bem_batch_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "bem_batch_info_get": (ctypes.c_int, [_P, ctypes.POINTER(bem_batch_info)]),
+    "bem_batch_destroy": (ctypes.c_int, [_P]),
     "bem_op_blocks": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), _P, _P]),
     "bem_partition": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), _P, _P]),
     "bem_op_freq_hist": (ctypes.c_int, [_P, _P]),
@@ -370,3 +391,63 @@ class Operator:
 
 def version():
     return lib().bem_version().decode()
+
+
+BATCH_GRAPH = 1
+BATCH_TUNE = 2
+
+
+class Batch:
+    """Owns a bem_batch: the products of several compressed operators (same L) in one set of
+    launches.  Keeps the operators alive while it lives."""
+
+    def __init__(self, ops, nrhs=1, graph=False, tune=False):
+        self.ops = list(ops)
+        self.ctx = self.ops[0].ctx
+        self.nrhs = int(nrhs)
+        arr = (ctypes.c_void_p * len(self.ops))(*[o.h for o in self.ops])
+        h = ctypes.c_void_p()
+        self.ctx._sync_torch_stream()
+        fl = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0)
+        self.ctx._check(lib().bem_batch_create(arr, len(self.ops), self.nrhs, fl, ctypes.byref(h)))
+        self.h = h
+
+    def apply(self, xs, ys=None):
+        """ys[o][r, l] = A_o(s_l) xs[o][r, l]; xs: list of [nrhs, L, 3 K_o] arrays, all numpy or
+        all torch CUDA tensors."""
+        if len(xs) != len(self.ops):
+            raise ValueError("one input per operator")
+        dev = _is_torch(xs[0])
+        if ys is None:
+            if dev:
+                import torch
+                ys = [torch.empty_like(x) for x in xs]
+            else:
+                ys = [np.empty_like(x) for x in xs]
+        if dev:
+            self.ctx._sync_torch_stream()
+        px, fl = zip(*[_ptr(x) for x in xs])
+        py, fly = zip(*[_ptr(y) for y in ys])
+        if len(set(fl) | set(fly)) != 1:
+            raise ValueError("inputs and outputs must all be host arrays or all device tensors")
+        ax = (ctypes.c_void_p * len(xs))(*[p.value for p in px])
+        ay = (ctypes.c_void_p * len(ys))(*[p.value for p in py])
+        self.ctx._check(lib().bem_batch_apply(self.h, ax, ay, fl[0]))
+        return ys
+
+    def info(self):
+        i = bem_batch_info()
+        self.ctx._check(lib().bem_batch_info_get(self.h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def destroy(self):
+        if self.h:
+            self.ctx._check(lib().bem_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().bem_batch_destroy(self.h)
+        except Exception:
+            pass

@@ -202,7 +202,29 @@ struct ApplyArgs {
 constexpr int APPLY_ROW_CHUNK = 16;  // element rows per workgroup of the product (row chunks)
 constexpr int APPLY_SEGMENTS = 2048; // target number of row-kernel workgroups per column tile
 
-void launch_apply(const ApplyArgs& A, hipStream_t st);
+// persistent_wgs > 0: the row kernel runs on at most that many workgroups, each striding
+// over the (segment, column tile) items
+void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs = 0);
+// workgroups of the row kernel that fit on one CU at once
+int apply_rows_occupancy();
+
+// Operators of a batched product: mesh-order vectors x (input) and y (output) of operator o,
+// [nrhs][L][3 K], and its cluster permutation; the workspace holds all operators side by
+// side, [nrhs][L][3 Ktot] with operator o at element offset koff.
+constexpr int MAX_BATCH_OPS = 16;
+struct BatchPerm {
+    const zd* x;
+    zd* y;
+    const int* perm;
+    int K;
+    int koff;
+};
+struct BatchPermTable {
+    BatchPerm op[MAX_BATCH_OPS];
+    int nops, L, nrhs, Ktot;
+};
+// kmax = largest K of the table
+void launch_permute_batch(const BatchPermTable& T, int kmax, zd* work, bool to_cluster, hipStream_t st);
 void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nrhs, int64_t in_l_stride, bool to_cluster,
                     hipStream_t st);
 void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t st);

@@ -788,9 +788,98 @@ int bem_op_freq_hist(const bem_op* op, int64_t* hist)
     return BEM_OK;
 }
 
+struct bem_batch {
+    bem_ctx* ctx = nullptr;
+    std::vector<bem_op*> ops;
+    bem::BatchPlan* plan = nullptr;
+    ~bem_batch()
+    {
+        if (plan) bem::batch_destroy(plan);
+        for (bem_op* o : ops) o->batches--;
+    }
+};
+
+int bem_batch_create(bem_op* const* ops, int32_t nops, int32_t nrhs, int32_t flags, bem_batch** out)
+{
+    if (!ops || !out || nops < 1 || !ops[0]) return BEM_ERR_ARG;
+    bem_ctx* ctx = ops[0]->ctx;
+    return guarded(ctx, [&]() -> int {
+        *out = nullptr;
+        if (nops > 16) throw api_error(BEM_ERR_ARG, "at most 16 operators per batch");
+        if (nrhs < 1) throw api_error(BEM_ERR_ARG, "need nrhs >= 1");
+        if (flags & ~(BEM_BATCH_GRAPH | BEM_BATCH_TUNE)) throw api_error(BEM_ERR_ARG, "unknown batch flags");
+        need_device(ctx);
+        for (int o = 0; o < nops; ++o) {
+            const bem_op* op = ops[o];
+            if (!op || op->kind != 1) throw api_error(BEM_ERR_ARG, "batch of compressed operators only");
+            if (op->L != ops[0]->L) throw api_error(BEM_ERR_ARG, "operators of a batch need the same L");
+            if (op->ctx->device != ctx->device) throw api_error(BEM_ERR_ARG, "operators on different devices");
+            for (int q = 0; q < o; ++q)
+                if (ops[q] == op) throw api_error(BEM_ERR_ARG, "operator listed twice");
+        }
+        if ((size_t)nrhs * ops[0]->L > (1u << 20)) throw api_error(BEM_ERR_ARG, "nrhs * L above 2^20");
+        auto b = std::make_unique<bem_batch>();
+        b->ctx = ctx;
+        b->plan = bem::batch_create(ops, nops, nrhs, flags, ctx->stream);
+        b->ops.assign(ops, ops + nops);
+        for (bem_op* o : b->ops) o->batches++;
+        *out = b.release();
+        return BEM_OK;
+    });
+}
+
+int bem_batch_apply(bem_batch* b, const void* const* x, void* const* y, int32_t flags)
+{
+    if (!b) return BEM_ERR_ARG;
+    bem_ctx* ctx = b->ctx;
+    return guarded(ctx, [&]() -> int {
+        if (!x || !y) throw api_error(BEM_ERR_ARG, "need buffers");
+        const int n = (int)b->ops.size();
+        for (int o = 0; o < n; ++o)
+            if (!x[o] || !y[o]) throw api_error(BEM_ERR_ARG, "null buffer in the batch");
+        if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_batch_apply");
+        const bool dev = (flags & BEM_DEVICE_PTR) != 0;
+        bem_batch_info info{};
+        bem::batch_info(b->plan, &info);
+        if (info.graph && !dev) throw api_error(BEM_ERR_ARG, "a graph batch takes device buffers");
+        need_device(ctx);
+        hipStream_t st = ctx->stream;
+        std::vector<Staged> sx(n), sy(n);
+        std::vector<const zd*> xd(n);
+        std::vector<zd*> yd(n);
+        std::vector<size_t> bytes(n);
+        for (int o = 0; o < n; ++o) {
+            bytes[o] = (size_t)info.nrhs * info.L * 3 * (size_t)b->ops[o]->K * sizeof(zd);
+            stage_in(sx[o], x[o], bytes[o], dev, st);
+            stage_out(sy[o], y[o], bytes[o], dev);
+            xd[o] = (const zd*)sx[o].dev;
+            yd[o] = (zd*)sy[o].dev;
+        }
+        bem::batch_apply(b->plan, xd.data(), yd.data(), st);
+        for (int o = 0; o < n; ++o) finish_out(sy[o], y[o], bytes[o], dev, st);
+        return BEM_OK;
+    });
+}
+
+int bem_batch_info_get(const bem_batch* b, bem_batch_info* info)
+{
+    if (!b || !info) return BEM_ERR_ARG;
+    bem::batch_info(b->plan, info);
+    return BEM_OK;
+}
+
+int bem_batch_destroy(bem_batch* b)
+{
+    if (!b) return BEM_ERR_ARG;
+    if (b->ctx && b->ctx->device >= 0) (void)hipSetDevice(b->ctx->device);
+    delete b;
+    return BEM_OK;
+}
+
 int bem_op_destroy(bem_op* op)
 {
     if (!op) return BEM_ERR_ARG;
+    if (op->batches > 0) return fail(op->ctx, BEM_ERR_STATE, "a batch still uses this operator");
     if (op->ctx && op->ctx->device >= 0) (void)hipSetDevice(op->ctx->device);
     delete op;
     return BEM_OK;

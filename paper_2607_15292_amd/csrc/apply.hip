@@ -163,16 +163,15 @@ __device__ __forceinline__ void tile_mac(const zd (*Hs)[KTL], const zd (*Zs)[NC]
     }
 }
 
-// rows: one workgroup per (segment of a row chunk's faces, column tile of NC columns); the
-// segment's partial rows go to pbuf and k_reduce_rows adds them in segment order
+// One work item of the row kernel: segment sg of a row chunk's faces times the column tile
+// starting at c0; the segment's partial rows go to pbuf and k_reduce_rows adds them in
+// segment order.  Every LDS write is preceded by a barrier, so items can follow each other
+// in one workgroup.
 template <bool WEIGHTED>
-__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int ncols)
+__device__ __forceinline__ void rows_item(const ApplyArgs& A, const zd* zw_all, int ncols, int sg, int c0,
+                                          zd (*Hs)[KR + 1], zd (*Zs)[NC], zd (*Fs)[9])
 {
-    __shared__ zd Hs[3 * RCE][KR + 1];
-    __shared__ zd Zs[KR][NC];
-    __shared__ zd Fs[NC][9];
-    const int sg = blockIdx.x, g = A.seg_group[sg];
-    const int c0 = blockIdx.y * NC;
+    const int g = A.seg_group[sg];
     const int er = threadIdx.x >> 4, cq = threadIdx.x & 15;  // element row, column quad
     const int rs0 = A.row_start[g], rsz = A.row_size[g];
     zd acc[3][4];
@@ -240,6 +239,20 @@ __global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int
 #pragma unroll
             for (int a = 0; a < 3; ++a) pb[(size_t)(3 * er + a) * ncols + col] = acc[a][v];
         }
+    }
+}
+
+// rows: work items w = sg + nseg * tile (segment fastest), one per workgroup, or strided
+// over a smaller persistent grid
+template <bool WEIGHTED>
+__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int ncols, int nitems)
+{
+    __shared__ zd Hs[3 * RCE][KR + 1];
+    __shared__ zd Zs[KR][NC];
+    __shared__ zd Fs[NC][9];
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        const int tile = w / A.nseg;
+        rows_item<WEIGHTED>(A, zw_all, ncols, w - tile * A.nseg, tile * NC, Hs, Zs, Fs);
     }
 }
 
@@ -317,7 +330,48 @@ __global__ __launch_bounds__(256) void k_permute(const zd* in, zd* out, const in
     }
 }
 
+// Batched permutation between the mesh-order vectors of several operators and one
+// cluster-order workspace [nrhs][L][3 Ktot] (operator o at element offset koff); blockIdx.y
+// = operator.
+__global__ __launch_bounds__(256) void k_permute_batch(BatchPermTable T, zd* work, int to_cluster)
+{
+    const BatchPerm& P = T.op[blockIdx.y];
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)T.nrhs * T.L * P.K) return;
+    const int p = (int)(q % P.K);
+    const int64_t rl = q / P.K;  // r L + l
+    const int e = P.perm[p];
+    zd* w = work + (size_t)rl * 3 * T.Ktot + 3 * (size_t)(P.koff + p);
+    if (to_cluster) {
+        const zd* src = P.x + (size_t)rl * 3 * P.K + 3 * (size_t)e;
+        w[0] = src[0];
+        w[1] = src[1];
+        w[2] = src[2];
+    } else {
+        zd* dst = P.y + (size_t)rl * 3 * P.K + 3 * (size_t)e;
+        dst[0] = w[0];
+        dst[1] = w[1];
+        dst[2] = w[2];
+    }
+}
+
 }  // namespace
+
+void launch_permute_batch(const BatchPermTable& T, int kmax, zd* work, bool to_cluster, hipStream_t st)
+{
+    if (T.nops < 1 || T.nops > MAX_BATCH_OPS) throw std::invalid_argument("batch of 1 to 16 operators");
+    const int64_t total = (int64_t)T.nrhs * T.L * kmax;
+    hipLaunchKernelGGL(k_permute_batch, dim3((unsigned)((total + 255) / 256), T.nops), dim3(256), 0, st, T, work,
+                       (int)to_cluster);
+    BEM_HIP_TRY(hipGetLastError());
+}
+
+int apply_rows_occupancy()
+{
+    int n = 0;
+    BEM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows<false>, WGA, 0));
+    return n;
+}
 
 void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nrhs, int64_t in_l_stride, bool to_cluster,
                     hipStream_t st)
@@ -328,14 +382,17 @@ void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nr
     BEM_HIP_TRY(hipGetLastError());
 }
 
-void launch_apply(const ApplyArgs& A, hipStream_t st)
+void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs)
 {
     const int ncols = A.L * A.nrhs;
     const unsigned ct = (unsigned)((ncols + NC - 1) / NC);
     if (A.nfar > 0) hipLaunchKernelGGL((k_far_products<false>), dim3(A.nfar, ct), dim3(WGA), 0, st, A, A.far_list,
                                        nullptr, ncols);
     BEM_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL((k_rows<false>), dim3(A.nseg, ct), dim3(WGA), 0, st, A, nullptr, ncols);
+    const long long items = (long long)A.nseg * ct;
+    if (items >= (1LL << 31)) throw std::invalid_argument("too many row work items");
+    const unsigned grid = persistent_wgs > 0 ? (unsigned)std::min<long long>(items, persistent_wgs) : (unsigned)items;
+    hipLaunchKernelGGL((k_rows<false>), dim3(grid), dim3(WGA), 0, st, A, nullptr, ncols, (int)items);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_reduce_rows<false>), dim3(A.nrow_groups, (3 * RCE * ncols + 255) / 256), dim3(256), 0, st, A,
                        ncols, A.y);
@@ -353,7 +410,7 @@ void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t
         hipLaunchKernelGGL((k_far_products<true>), dim3(A.nfar, 1), dim3(WGA), 0, st, A, A.far_list, zw, 1);
         BEM_HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_rows<true>), dim3(A.nseg, 1), dim3(WGA), 0, st, A, zw, 1);
+    hipLaunchKernelGGL((k_rows<true>), dim3(A.nseg), dim3(WGA), 0, st, A, zw, 1, A.nseg);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_reduce_rows<true>), dim3(A.nrow_groups, (3 * RCE + 255) / 256), dim3(256), 0, st, A, 1, y);
     BEM_HIP_TRY(hipGetLastError());

@@ -24,6 +24,7 @@ struct CompressedOp {
     std::vector<BlockState> st;
     // apply plan
     std::vector<ApplyFace> af;
+    std::vector<int> h_flat, h_ptr, h_start, h_size, h_far;  // row groups and far faces (host copy)
     DevBuf af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev, farlist_dev;
     DevBuf seg_dev;             // segments: [nseg] group, [nseg + 1] face ranges, [ngroups + 1] group ranges
     int ngroups = 0;
@@ -50,6 +51,42 @@ constexpr double FLOPS_RESIDUAL = 216.0;
 double flops_eval(int op) { return op == BEM_OP_V ? 125.0 : (op == BEM_OP_TABLE ? 0.0 : 236.0); }
 constexpr size_t ACA_SLOTS = 4096;  // faces per launch of the per-slice ACA pass (scratch slots)
 constexpr int POOL_STEPS0 = 32;     // 3D-ACA steps of every block in the initial pool
+
+// Segments: each row group's face list cut into pieces of about equal work (the staged inner
+// dimension: 3 cs for a dense face, kk for factors, plus a per-face overhead), about target
+// pieces in all; partial sums are added in segment order.  segbuf = [nseg] group, [nseg + 1]
+// first face entry, [ngroups + 1] first segment of each group.
+std::vector<int> make_segments(const std::vector<ApplyFace>& af, const std::vector<BlockIn>& blocks,
+                               const std::vector<int>& ptr, const std::vector<int>& flat, int target, int* nseg_out)
+{
+    const int ngroups = (int)ptr.size() - 1;
+    auto cost = [&](int fi) { const ApplyFace& a = af[fi]; return (double)(a.kk > 0 ? a.kk : 3 * blocks[a.block].cs) + 24.0; };
+    double total = 0.0;
+    for (int fi : flat) total += cost(fi);
+    const double per = std::max(1.0, total / std::max(target, 1));
+    std::vector<int> sgroup, sbeg, gseg(ngroups + 1, 0);
+    for (int g = 0; g < ngroups; ++g) {
+        double cg = 0.0;
+        for (int q = ptr[g]; q < ptr[g + 1]; ++q) cg += cost(flat[q]);
+        const int ns = std::max(1, (int)std::lround(cg / per));
+        const double tgt = cg / ns;
+        int q = ptr[g];
+        for (int k = 0; k < ns; ++k) {
+            sgroup.push_back(g);
+            sbeg.push_back(q);
+            double acc = 0.0;
+            while (q < ptr[g + 1] && (k == ns - 1 || acc == 0.0 || acc + 0.5 * cost(flat[q]) < tgt)) acc += cost(flat[q++]);
+        }
+        gseg[g + 1] = (int)sgroup.size();
+    }
+    *nseg_out = (int)sgroup.size();
+    std::vector<int> segbuf;
+    segbuf.insert(segbuf.end(), sgroup.begin(), sgroup.end());
+    segbuf.insert(segbuf.end(), sbeg.begin(), sbeg.end());
+    segbuf.push_back(ptr[ngroups]);
+    segbuf.insert(segbuf.end(), gseg.begin(), gseg.end());
+    return segbuf;
+}
 
 void build_apply_plan(CompressedOp& C, hipStream_t st)
 {
@@ -122,36 +159,7 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
         ptr[g + 1] = ptr[g] + (int)lists[g].size();
         flat.insert(flat.end(), lists[g].begin(), lists[g].end());
     }
-    // segments: each group's face list cut into pieces of about equal work (the staged
-    // inner dimension: 3 cs for a dense face, kk for factors, plus a per-face overhead), so
-    // that the row kernel has about APPLY_SEGMENTS workgroups per column tile; partial sums
-    // are added in segment order
-    auto cost = [&](int fi) { const ApplyFace& a = C.af[fi]; return (double)(a.kk > 0 ? a.kk : 3 * C.blocks[a.block].cs) + 24.0; };
-    double total = 0.0;
-    for (int fi : flat) total += cost(fi);
-    const double per = std::max(1.0, total / APPLY_SEGMENTS);
-    std::vector<int> sgroup, sbeg, gseg(C.ngroups + 1, 0);
-    for (int g = 0; g < C.ngroups; ++g) {
-        double cg = 0.0;
-        for (int q = ptr[g]; q < ptr[g + 1]; ++q) cg += cost(flat[q]);
-        const int ns = std::max(1, (int)std::lround(cg / per));
-        const double target = cg / ns;
-        int q = ptr[g];
-        for (int k = 0; k < ns; ++k) {
-            sgroup.push_back(g);
-            sbeg.push_back(q);
-            double acc = 0.0;
-            while (q < ptr[g + 1] && (k == ns - 1 || acc == 0.0 || acc + 0.5 * cost(flat[q]) < target))
-                acc += cost(flat[q++]);
-        }
-        gseg[g + 1] = (int)sgroup.size();
-    }
-    C.nseg = (int)sgroup.size();
-    std::vector<int> segbuf;
-    segbuf.insert(segbuf.end(), sgroup.begin(), sgroup.end());
-    segbuf.insert(segbuf.end(), sbeg.begin(), sbeg.end());
-    segbuf.push_back(ptr[C.ngroups]);
-    segbuf.insert(segbuf.end(), gseg.begin(), gseg.end());
+    std::vector<int> segbuf = make_segments(C.af, C.blocks, ptr, flat, APPLY_SEGMENTS, &C.nseg);
     auto up = [&](DevBuf& d, const void* src, size_t bytes) {
         d.alloc(std::max<size_t>(bytes, 16));
         if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
@@ -164,6 +172,11 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
     up(C.farlist_dev, far.data(), far.size() * sizeof(int));
     up(C.seg_dev, segbuf.data(), segbuf.size() * sizeof(int));
     BEM_HIP_TRY(hipStreamSynchronize(st));
+    C.h_flat = std::move(flat);
+    C.h_ptr = std::move(ptr);
+    C.h_start = std::move(s2);
+    C.h_size = std::move(z2);
+    C.h_far = std::move(far);
 }
 
 ApplyArgs plan_args(const CompressedOp& C, int nrhs)
@@ -795,5 +808,316 @@ void compressed_freq_hist(const bem_op* op, int64_t* hist)
         for (int d = 0; d < C.st[b].rank; ++d) hist[C.faces[b * C.L + d].k]++;
     }
 }
+
+
+// ---------------------------------------------------------------- batched products
+
+struct BatchPlan {
+    std::vector<bem_op*> ops;
+    int nrhs = 0, L = 0, Ktot = 0, Kmax = 0;
+    std::vector<int> koff;
+    // merged plan (host)
+    std::vector<BlockIn> blocks;
+    std::vector<ApplyFace> af;
+    std::vector<int> flat, ptr, start, size, far;
+    long long far_rows = 0;
+    const char* base = nullptr;
+    DevBuf blocks_dev, af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev, far_dev, far_sorted_dev, seg_dev;
+    int ngroups = 0, nfar = 0;
+    // schedule
+    int seg_target = 0, nseg = 0, persistent = 0, far_sorted = 0, persist_wgs = 0;
+    std::vector<double> tune_ms;
+    std::vector<int> tune_seg;
+    DevBuf work;
+    size_t work_bytes = 0;
+    // graph of the last device-pointer call
+    bool use_graph = false;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> gx;
+    std::vector<void*> gy;
+    hipStream_t gstream = nullptr;
+    int graph_builds = 0, graph_launches = 0;
+    ~BatchPlan()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace {
+
+size_t batch_work_bytes(const BatchPlan& P, int nseg)
+{
+    const size_t ncols = (size_t)P.L * P.nrhs, M = 3 * (size_t)P.Ktot;
+    return (2 * ncols * M + (size_t)P.far_rows * ncols + (size_t)nseg * 3 * APPLY_ROW_CHUNK * ncols + 16) * sizeof(zd);
+}
+
+void batch_set_segments(BatchPlan& P, int target, hipStream_t st)
+{
+    int nseg = 0;
+    std::vector<int> segbuf = make_segments(P.af, P.blocks, P.ptr, P.flat, target, &nseg);
+    P.seg_dev.alloc(segbuf.size() * sizeof(int));
+    BEM_HIP_TRY(hipMemcpyAsync(P.seg_dev.p, segbuf.data(), segbuf.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    P.seg_target = target;
+    P.nseg = nseg;
+}
+
+ApplyArgs batch_args(const BatchPlan& P)
+{
+    ApplyArgs A{};
+    A.blocks = P.blocks_dev.as<BlockIn>();
+    A.faces = P.af_dev.as<ApplyFace>();
+    A.nfaces = (int)P.af.size();
+    A.row_faces = P.rowfaces_dev.as<int>();
+    A.row_ptr = P.rowptr_dev.as<int>();
+    A.row_start = P.rowstart_dev.as<int>();
+    A.row_size = P.rowsize_dev.as<int>();
+    A.nrow_groups = P.ngroups;
+    A.pool = P.base;
+    A.K = P.Ktot;
+    A.L = P.L;
+    A.nrhs = P.nrhs;
+    A.far_list = (P.far_sorted ? P.far_sorted_dev : P.far_dev).as<int>();
+    A.nfar = P.nfar;
+    A.nseg = P.nseg;
+    A.seg_group = P.seg_dev.as<int>();
+    A.seg_begin = A.seg_group + P.nseg;
+    A.group_seg = A.seg_begin + P.nseg + 1;
+    const size_t ncols = (size_t)P.L * P.nrhs, M = 3 * (size_t)P.Ktot;
+    zd* xp = P.work.as<zd>();
+    A.x = xp;
+    A.y = xp + ncols * M;
+    A.tbuf = xp + 2 * ncols * M;
+    A.pbuf = A.tbuf + (size_t)P.far_rows * ncols;
+    return A;
+}
+
+// the products of the batch: permutation in, far products, rows, row sums, permutation out
+void batch_enqueue(const BatchPlan& P, const zd* const* x, zd* const* y, hipStream_t st)
+{
+    BatchPermTable T{};
+    T.nops = (int)P.ops.size();
+    T.L = P.L;
+    T.nrhs = P.nrhs;
+    T.Ktot = P.Ktot;
+    for (int o = 0; o < T.nops; ++o) {
+        const CompressedOp& C = *P.ops[o]->comp;
+        T.op[o] = BatchPerm{x ? x[o] : nullptr, y ? y[o] : nullptr, C.perm_dev.as<int>(), C.K, P.koff[o]};
+    }
+    ApplyArgs A = batch_args(P);
+    launch_permute_batch(T, P.Kmax, P.work.as<zd>(), true, st);
+    launch_apply(A, st, P.persistent ? P.persist_wgs : 0);
+    launch_permute_batch(T, P.Kmax, const_cast<zd*>(A.y), false, st);
+}
+
+double batch_time_ms(const BatchPlan& P, hipStream_t st, int reps)
+{
+    hipEvent_t e0, e1;
+    BEM_HIP_TRY(hipEventCreate(&e0));
+    BEM_HIP_TRY(hipEventCreate(&e1));
+    ApplyArgs A = batch_args(P);
+    launch_apply(A, st, P.persistent ? P.persist_wgs : 0);  // warm-up
+    BEM_HIP_TRY(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) launch_apply(A, st, P.persistent ? P.persist_wgs : 0);
+    BEM_HIP_TRY(hipEventRecord(e1, st));
+    BEM_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BEM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+
+}  // namespace
+
+BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipStream_t st)
+{
+    auto P = std::make_unique<BatchPlan>();
+    P->ops.assign(ops, ops + nops);
+    P->nrhs = nrhs;
+    P->L = ops[0]->L;
+    P->use_graph = (flags & BEM_BATCH_GRAPH) != 0;
+    // merged plan: blocks, faces, row groups and far faces of every operator, element
+    // indices shifted by the operator's offset, face offsets taken from the lowest pool
+    uintptr_t lo = UINTPTR_MAX;
+    for (bem_op* op : P->ops) lo = std::min(lo, (uintptr_t)op->comp->pool.p);
+    P->base = (const char*)lo;
+    long long trow = 0;
+    for (int o = 0; o < nops; ++o) {
+        const CompressedOp& C = *ops[o]->comp;
+        const int boff = (int)P->blocks.size(), foff = (int)P->af.size(), koff = P->Ktot;
+        const long long delta = (long long)((uintptr_t)C.pool.p - lo);
+        P->koff.push_back(koff);
+        for (BlockIn B : C.blocks) {
+            B.rb += koff;
+            B.cb += koff;
+            P->blocks.push_back(B);
+        }
+        for (ApplyFace a : C.af) {
+            a.face_off += delta;
+            a.fib_off += delta;
+            a.block += boff;
+            a.t_off += trow;
+            a.zw_off = 0;
+            P->af.push_back(a);
+        }
+        const int e0 = (int)P->flat.size();
+        for (int fi : C.h_flat) P->flat.push_back(fi + foff);
+        if (P->ptr.empty()) P->ptr.push_back(0);
+        for (size_t g = 1; g < C.h_ptr.size(); ++g) P->ptr.push_back(C.h_ptr[g] + e0);
+        for (int s0 : C.h_start) P->start.push_back(s0 + koff);
+        P->size.insert(P->size.end(), C.h_size.begin(), C.h_size.end());
+        for (int f : C.h_far) P->far.push_back(f + foff);
+        trow += C.far_rows;
+        P->Ktot += C.K;
+        P->Kmax = std::max(P->Kmax, C.K);
+    }
+    P->far_rows = trow;
+    P->ngroups = (int)P->start.size();
+    P->nfar = (int)P->far.size();
+    std::vector<int> far_sorted = P->far;
+    std::stable_sort(far_sorted.begin(), far_sorted.end(), [&](int a, int b) { return P->af[a].kk > P->af[b].kk; });
+    auto up = [&](DevBuf& d, const void* src, size_t bytes) {
+        d.alloc(std::max<size_t>(bytes, 16));
+        if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    up(P->blocks_dev, P->blocks.data(), P->blocks.size() * sizeof(BlockIn));
+    up(P->af_dev, P->af.data(), P->af.size() * sizeof(ApplyFace));
+    up(P->rowfaces_dev, P->flat.data(), P->flat.size() * sizeof(int));
+    up(P->rowptr_dev, P->ptr.data(), P->ptr.size() * sizeof(int));
+    up(P->rowstart_dev, P->start.data(), P->start.size() * sizeof(int));
+    up(P->rowsize_dev, P->size.data(), P->size.size() * sizeof(int));
+    up(P->far_dev, P->far.data(), P->far.size() * sizeof(int));
+    up(P->far_sorted_dev, far_sorted.data(), far_sorted.size() * sizeof(int));
+    int dev = 0, ncu = 0;
+    BEM_HIP_TRY(hipGetDevice(&dev));
+    BEM_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    P->persist_wgs = std::max(1, ncu * std::max(1, apply_rows_occupancy()));
+    // schedule: segment count, persistent or one workgroup per item, far faces in plan order
+    // or by decreasing rank; the default is the single-operator schedule, the tuner times
+    // the candidates that fit in half of the free memory and keeps the fastest
+    // (default: about APPLY_SEGMENTS row workgroups per launch, at least one segment per group)
+    const int ctiles = (P->L * nrhs + 63) / 64;
+    const int tdef = std::max(P->ngroups, APPLY_SEGMENTS / ctiles);
+    std::vector<int> targets = {std::max(1, P->ngroups / 2), P->ngroups, 2 * P->ngroups, 4 * P->ngroups, tdef};
+    std::sort(targets.begin(), targets.end());
+    targets.erase(std::unique(targets.begin(), targets.end()), targets.end());
+    size_t free_b = 0, total_b = 0;
+    BEM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    std::vector<int> fit;
+    for (int t : targets) {
+        int ns = 0;
+        (void)make_segments(P->af, P->blocks, P->ptr, P->flat, t, &ns);
+        if (batch_work_bytes(*P, ns) <= free_b / 2 || t == targets.front()) fit.push_back(t);
+    }
+    int best_t = std::find(fit.begin(), fit.end(), tdef) != fit.end() ? tdef : fit.front();
+    size_t need = 0;
+    for (int t : fit) {
+        int ns = 0;
+        (void)make_segments(P->af, P->blocks, P->ptr, P->flat, t, &ns);
+        need = std::max(need, batch_work_bytes(*P, ns));
+    }
+    if (!(flags & BEM_BATCH_TUNE)) {
+        int ns = 0;
+        (void)make_segments(P->af, P->blocks, P->ptr, P->flat, best_t, &ns);
+        need = batch_work_bytes(*P, ns);
+    }
+    P->work.alloc(need);
+    P->work_bytes = need;
+    BEM_HIP_TRY(hipMemsetAsync(P->work.p, 0, need, st));
+    if (flags & BEM_BATCH_TUNE) {
+        double best = 1e300;
+        for (int t : fit) {
+            batch_set_segments(*P, t, st);
+            const double ms = batch_time_ms(*P, st, 2);
+            P->tune_seg.push_back(P->nseg);
+            P->tune_ms.push_back(ms);
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+        batch_set_segments(*P, best_t, st);
+        for (int knob = 0; knob < 2; ++knob) {
+            int& v = knob == 0 ? P->persistent : P->far_sorted;
+            v = 1;
+            const double ms = batch_time_ms(*P, st, 2);
+            P->tune_seg.push_back(P->nseg);
+            P->tune_ms.push_back(ms);
+            if (ms < best) best = ms;
+            else v = 0;
+        }
+    } else {
+        batch_set_segments(*P, best_t, st);
+    }
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    return P.release();
+}
+
+void batch_apply(BatchPlan* P, const zd* const* x, zd* const* y, hipStream_t st)
+{
+    if (!P->use_graph) {
+        batch_enqueue(*P, x, y, st);
+        return;
+    }
+    const int n = (int)P->ops.size();
+    bool same = P->exec && P->gstream == st;
+    for (int o = 0; same && o < n; ++o) same = P->gx[o] == x[o] && P->gy[o] == y[o];
+    if (!same) {
+        if (P->exec) {
+            BEM_HIP_TRY(hipGraphExecDestroy(P->exec));
+            P->exec = nullptr;
+        }
+        if (!P->cap) BEM_HIP_TRY(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        BEM_HIP_TRY(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+        try {
+            batch_enqueue(*P, x, y, P->cap);
+        } catch (...) {
+            (void)hipStreamEndCapture(P->cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        BEM_HIP_TRY(hipStreamEndCapture(P->cap, &g));
+        const hipError_t e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        BEM_HIP_TRY(e);
+        P->gx.assign(x, x + n);
+        P->gy.assign(y, y + n);
+        P->gstream = st;
+        ++P->graph_builds;
+    }
+    BEM_HIP_TRY(hipGraphLaunch(P->exec, st));
+    ++P->graph_launches;
+}
+
+void batch_info(const BatchPlan* P, bem_batch_info* I)
+{
+    *I = bem_batch_info{};
+    I->nops = (int32_t)P->ops.size();
+    I->nrhs = P->nrhs;
+    I->L = P->L;
+    I->K_total = P->Ktot;
+    I->n_groups = P->ngroups;
+    I->n_segments = P->nseg;
+    I->n_far_faces = P->nfar;
+    I->seg_target = P->seg_target;
+    I->persistent = P->persistent;
+    I->persistent_wgs = P->persist_wgs;
+    I->far_sorted = P->far_sorted;
+    I->graph = P->use_graph;
+    I->graph_builds = P->graph_builds;
+    I->graph_launches = P->graph_launches;
+    I->n_tuned = (int32_t)std::min<size_t>(P->tune_ms.size(), 8);
+    for (int i = 0; i < I->n_tuned; ++i) {
+        I->tune_ms[i] = P->tune_ms[i];
+        I->tune_segments[i] = P->tune_seg[i];
+    }
+    I->workspace_bytes = (double)P->work_bytes;
+}
+
+void batch_destroy(BatchPlan* P) { delete P; }
 
 }  // namespace bem

@@ -185,6 +185,7 @@ struct bem_op {
     bem::DevBuf dense;                               // kind 0: [L][3K][3K]
     bem::CompressedOp* comp = nullptr;               // kind 1 (owned)
     bem_stats stats{};
+    int batches = 0;  // live batches that reference this operator
     ~bem_op();
 };
 
@@ -197,4 +198,10 @@ void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream
 void compressed_blocks(const bem_op* op, int64_t* n, int64_t* rows, int32_t* perm);
 void compressed_freq_hist(const bem_op* op, int64_t* hist);
 void destroy_compressed(CompressedOp* c);
+// batched products of several compressed operators with one L (compress.cpp)
+struct BatchPlan;
+BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipStream_t st);
+void batch_apply(BatchPlan* P, const zd* const* x, zd* const* y, hipStream_t st);
+void batch_info(const BatchPlan* P, bem_batch_info* info);
+void batch_destroy(BatchPlan* P);
 }  // namespace bem
