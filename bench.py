@@ -13,7 +13,10 @@ y_l = V(s_l) x_l and (I/2 + K)(s_l) x_l for one right-hand side.
 value = kernel entries (3x3 ENTRY(i, j, l) blocks) generated per second over the step.
 Extra fields: all-frequency H-matvecs/s (apply only), the FP64 path's step time and the
 mixed vs FP64 speedup, the relative error against the FP64 oracle on sampled rows, the
-roofline of the compression kernel and the oracle's CPU throughput.
+roofline of the compression kernel and the oracle's CPU throughput; apart from value, a
+solve leg (GMRES with refinement at every contour point) and a batched-product leg (the
+single layers of four cube and sphere meshes, 128 contour points, 32 right-hand sides, one
+set of launches).
 """
 from __future__ import annotations
 
@@ -44,6 +47,80 @@ def workload(level=4, L=64):
     return X, T, s
 
 
+def batched_leg(args, dev, torch):
+    """Batched products (reported apart from value): the single layers of the mixed cube and
+    sphere meshes, one L-point contour, nrhs right-hand sides each, all in one set of launches
+    (schedule tuned at creation, replayed as a HIP graph); the oracle checks sampled rows."""
+    from paper_2607_15292_amd import binding as B
+    from paper_2607_15292_amd import workloads as W
+    Lb, nrhs = args.batch_freqs, args.batch_nrhs
+    s = W.bdf2_contour(Lb, 0.1)
+    ctxs, ops, xs, names = [], [], [], []
+    for i, (name, X, T) in enumerate(W.batch_meshes()):
+        c = B.Context(0)
+        c.set_mesh(X, T)
+        c.set_material(1.0, 1.0, 0.5)
+        c.set_frequencies(s)
+        c.set_quadrature(near_on=True)
+        ctxs.append(c)
+        ops.append(c.compress(B.OP_V, eps3d=args.batch_eps, leaf=64, eta=1.5, prec=B.PREC_MIXED,
+                              mixed_eps_floor=args.batch_eps_floor))
+        xs.append(torch.tensor(W.random_rhs(2 + i, (nrhs, Lb, 3 * len(T))), device=dev))
+        names.append(name)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = B.Batch(ops, nrhs=nrhs, graph=True, tune=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ys = [torch.empty_like(x) for x in xs]
+    b.apply(xs, ys)  # records the graph
+    torch.cuda.synchronize()
+    reps = 2
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.apply(xs, ys)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    info = b.info()
+    log("batched: %d operators, L %d, nrhs %d: %.1f ms per product, tuning %.1f s, %s"
+        % (len(ops), Lb, nrhs, ms, t1 - t0, info))
+    err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        rng = np.random.default_rng(12)
+        err = {}
+        for (name, X, T), x, y in zip(W.batch_meshes(), xs, ys):
+            K = len(T)
+            rows = np.sort(rng.choice(K, size=16, replace=False))
+            ref = oracle.Problem(X, T, s, 1.0, 1.0, 0.5, near_on=True).matvec_rows(B.OP_V, rows, x.cpu().numpy())
+            yg = y.cpu().numpy().reshape(nrhs, Lb, K, 3)[:, :, rows, :].reshape(nrhs, Lb, -1)
+            err[name] = float(np.max(np.linalg.norm(yg - ref, axis=-1) / np.linalg.norm(ref, axis=-1)))
+        log("batched rel err on sampled rows:", err)
+    achieved = info["flop"] / (ms * 1e-3)
+    out = {"workload": "single layers of %s, mixed precision eps %.0e (far-field floor %.0e), %d BDF2 gCQ points, "
+                       "%d right-hand sides each" % (", ".join(names), args.batch_eps, args.batch_eps_floor, Lb, nrhs),
+           "ms_per_product": ms, "products_per_s": len(ops) * nrhs * 1e3 / ms,
+           "single_freq_matvecs_per_s": len(ops) * nrhs * Lb * 1e3 / ms,
+           "compressed_gb": sum(o.stats()["bytes"] for o in ops) / 1e9,
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_VALU, "traffic": None,
+                        "kernel": "batched product (k_far_products + k_rows + k_reduce_rows + permutations)",
+                        "flop_per_product": info["flop"]},
+           "schedule": {k: info[k] for k in ("n_groups", "n_segments", "seg_target", "persistent", "persistent_wgs",
+                                             "far_sorted", "tune_ms", "tune_segments", "graph_builds",
+                                             "graph_launches", "workspace_bytes")},
+           "tune_seconds": t1 - t0, "rel_err_sampled_rows": err}
+    b.destroy()
+    for o in ops:
+        o.destroy()
+    for c in ctxs:
+        c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +137,12 @@ def main():
     ap.add_argument("--pool-gb", type=float, default=0.0, help="0 = library default")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve leg (reported apart from value)")
     ap.add_argument("--solve-tol", type=float, default=1e-6)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-product leg (reported apart from value)")
+    ap.add_argument("--batch-nrhs", type=int, default=32)
+    ap.add_argument("--batch-freqs", type=int, default=128)
+    ap.add_argument("--batch-eps", type=float, default=1e-7,
+                    help="3D-ACA tolerance of the batched leg (1e-6 leaves 2.5e-4 at the largest |s_l| of L = 128)")
+    ap.add_argument("--batch-eps-floor", type=float, default=1e-6, help="far-field tolerance floor of the batched leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the sharded path is designed, not built); "
@@ -195,6 +278,11 @@ def main():
         for o in (Vf, Vi, Hf):
             o.destroy()
 
+    # the batched leg builds its own contexts: release this one's cached pools first
+    c.close()
+    torch.cuda.empty_cache()
+    batched = None if args.no_batch else batched_leg(args, dev, torch)
+
     # roofline of the dominant compression kernel: algorithmic flops over event-timed device
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
     # 3D-ACA face kernels (k_face_dense / k_face_general); the one with more device time is
@@ -272,6 +360,7 @@ def main():
         "roofline": roofline,
         "roofline_next": roofline_next,
         "solve": solve,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     if fp64:

@@ -304,9 +304,13 @@ typedef struct bem_batch_info {
     int32_t far_sorted, graph;        /* far faces by decreasing rank; HIP graph replay on */
     int32_t graph_builds, graph_launches;
     int32_t n_tuned, pad;             /* timed candidates (at most 8) */
-    double tune_ms[8];                /* product time of each timed candidate (events, ms) */
+    double tune_ms[8];                /* product time of each timed candidate (events, ms, on
+                                         at most 512 columns) */
     int32_t tune_segments[8];         /* its segment count */
     double workspace_bytes;           /* device workspace held by the batch */
+    double flop;                      /* algorithmic flops of one batched product: 8 per complex
+                                         multiply-add of the stored faces and factors with the
+                                         columns, and of the fibres with the inputs */
 } bem_batch_info;
 
 /* Creates a batch over ops[0 .. nops) (1 <= nops <= 16): compressed operators with the same

@@ -78,7 +78,7 @@ class bem_batch_info(ctypes.Structure):
                 ("far_sorted", ctypes.c_int32), ("graph", ctypes.c_int32), ("graph_builds", ctypes.c_int32),
                 ("graph_launches", ctypes.c_int32), ("n_tuned", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("tune_ms", ctypes.c_double * 8), ("tune_segments", ctypes.c_int32 * 8),
-                ("workspace_bytes", ctypes.c_double)]
+                ("workspace_bytes", ctypes.c_double), ("flop", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "tune_ms", "tune_segments")}

@@ -838,6 +838,7 @@ struct BatchPlan {
     std::vector<void*> gy;
     hipStream_t gstream = nullptr;
     int graph_builds = 0, graph_launches = 0;
+    double flop = 0.0;  // algorithmic flops of one product
     ~BatchPlan()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -912,12 +913,20 @@ void batch_enqueue(const BatchPlan& P, const zd* const* x, zd* const* y, hipStre
     launch_permute_batch(T, P.Kmax, const_cast<zd*>(A.y), false, st);
 }
 
+// Time of the products of one schedule candidate, taken on at most 512 columns (the same
+// right-hand-side count in every candidate): each column tile costs the same, so the
+// ranking holds for more columns while the tuner stays cheap.
 double batch_time_ms(const BatchPlan& P, hipStream_t st, int reps)
 {
     hipEvent_t e0, e1;
     BEM_HIP_TRY(hipEventCreate(&e0));
     BEM_HIP_TRY(hipEventCreate(&e1));
     ApplyArgs A = batch_args(P);
+    A.nrhs = std::max(1, std::min(P.nrhs, 512 / P.L));
+    const size_t ncols = (size_t)P.L * A.nrhs, M = 3 * (size_t)P.Ktot;
+    A.y = const_cast<zd*>(A.x) + ncols * M;
+    A.tbuf = const_cast<zd*>(A.x) + 2 * ncols * M;
+    A.pbuf = A.tbuf + (size_t)P.far_rows * ncols;
     launch_apply(A, st, P.persistent ? P.persist_wgs : 0);  // warm-up
     BEM_HIP_TRY(hipEventRecord(e0, st));
     for (int r = 0; r < reps; ++r) launch_apply(A, st, P.persistent ? P.persist_wgs : 0);
@@ -975,6 +984,17 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
         P->Kmax = std::max(P->Kmax, C.K);
     }
     P->far_rows = trow;
+    // algorithmic flops of one product: per column, 9 m n complex multiply-adds for a dense
+    // face, 3 (m + n) kk for factors, 9 n for the fibre (a selector face: one frequency, no
+    // fibre); 8 flops each
+    double macs_col = 0.0, macs_sel = 0.0;
+    for (const ApplyFace& a : P->af) {
+        const BlockIn& B = P->blocks[a.block];
+        const double core = a.kk > 0 ? 3.0 * (B.rs + B.cs) * a.kk : 9.0 * B.rs * B.cs;
+        if (a.sel) macs_sel += core;
+        else macs_col += core + 9.0 * B.cs;
+    }
+    P->flop = 8.0 * ((double)P->L * nrhs * macs_col + (double)nrhs * macs_sel);
     P->ngroups = (int)P->start.size();
     P->nfar = (int)P->far.size();
     std::vector<int> far_sorted = P->far;
@@ -1029,9 +1049,14 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
     BEM_HIP_TRY(hipMemsetAsync(P->work.p, 0, need, st));
     if (flags & BEM_BATCH_TUNE) {
         double best = 1e300;
+        std::vector<int> seen;
         for (int t : fit) {
+            int ns = 0;
+            (void)make_segments(P->af, P->blocks, P->ptr, P->flat, t, &ns);
+            if (std::find(seen.begin(), seen.end(), ns) != seen.end()) continue;  // same schedule
+            seen.push_back(ns);
             batch_set_segments(*P, t, st);
-            const double ms = batch_time_ms(*P, st, 2);
+            const double ms = batch_time_ms(*P, st, 1);
             P->tune_seg.push_back(P->nseg);
             P->tune_ms.push_back(ms);
             if (ms < best) {
@@ -1043,7 +1068,7 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
         for (int knob = 0; knob < 2; ++knob) {
             int& v = knob == 0 ? P->persistent : P->far_sorted;
             v = 1;
-            const double ms = batch_time_ms(*P, st, 2);
+            const double ms = batch_time_ms(*P, st, 1);
             P->tune_seg.push_back(P->nseg);
             P->tune_ms.push_back(ms);
             if (ms < best) best = ms;
@@ -1116,6 +1141,7 @@ void batch_info(const BatchPlan* P, bem_batch_info* I)
         I->tune_segments[i] = P->tune_seg[i];
     }
     I->workspace_bytes = (double)P->work_bytes;
+    I->flop = P->flop;
 }
 
 void batch_destroy(BatchPlan* P) { delete P; }

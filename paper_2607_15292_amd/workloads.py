@@ -222,6 +222,14 @@ def pulsating_sphere(points, normals, s, rho=1.0, cp=1.0, cs=0.5, a=2.5):
     return u, t
 
 
+def batch_meshes():
+    """Meshes of the batched-product workload, smallest first: cubes [-1, 1]^3 with 8 and 16
+    squares per face edge (768 and 3072 triangles) and icospheres of radius 1 with 1280 and
+    5120 triangles.  Returns [(name, nodes, tris)]."""
+    return [("cube768",) + cube_grid(8), ("sphere1280",) + icosphere(3),
+            ("cube3072",) + cube_grid(16), ("sphere5120",) + icosphere(4)]
+
+
 def random_rhs(seed: int, shape):
     """complex128 a + i b with a, b ~ N(0, 1) from numpy's default_rng(seed)."""
     rng = np.random.default_rng(seed)

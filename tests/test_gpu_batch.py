@@ -142,3 +142,45 @@ def test_batch_argument_errors(torch, problems):
     dense.destroy()
     c.close()
     assert c0.h is not None
+
+
+def test_batch_bench_workload_sampled_rows(torch):
+    """The benchmark's batched workload at full size (four cube and sphere meshes, single
+    layer, mixed precision at eps3d 1e-7 with far-field tolerances floored at 1e-6, L = 128,
+    32 right-hand sides, tuned schedule, graph replay): 16 sampled rows of every operator
+    against the oracle, the smallest operator's product against its own bem_apply.  (At
+    eps3d 1e-6 the slices of the largest |s_l| err by up to 2.5e-4 relative in FP64 and in
+    mixed precision alike: the truncation of the 3D-ACA, whose criterion is relative to the
+    norm of the whole tensor, not the precision.)"""
+    Lb, nrhs = 128, 32
+    s = W.bdf2_contour(Lb, 0.1)
+    meshes = W.batch_meshes()
+    ctxs, ops, xs = [], [], []
+    for i, (name, X, T) in enumerate(meshes):
+        c = _ctx(X, T, s)
+        ctxs.append(c)
+        ops.append(c.compress(B.OP_V, eps3d=1e-7, leaf=64, eta=1.5, prec=B.PREC_MIXED, mixed_eps_floor=1e-6))
+        xs.append(torch.tensor(W.random_rhs(2 + i, (nrhs, Lb, 3 * len(T))), device="cuda"))
+    b = B.Batch(ops, nrhs=nrhs, graph=True, tune=True)
+    ys = b.apply(xs)
+    torch.cuda.synchronize()
+    info = b.info()
+    assert info["K_total"] == sum(len(T) for _, _, T in meshes) and info["graph_builds"] == 1
+    rng = np.random.default_rng(3)
+    errs = {}
+    for (name, X, T), x, y in zip(meshes, xs, ys):
+        K = len(T)
+        rows = np.sort(rng.choice(K, size=16, replace=False))
+        ref = oracle.Problem(X, T, s, 1.0, 1.0, 0.5, near_on=True).matvec_rows(B.OP_V, rows, x.cpu().numpy())
+        yg = y.cpu().numpy().reshape(nrhs, Lb, K, 3)[:, :, rows, :].reshape(nrhs, Lb, -1)
+        errs[name] = _relerr(yg, ref)
+    print("sampled-row errors", errs)
+    assert max(errs.values()) < 1e-4, errs
+    y0 = ops[0].apply(xs[0])
+    torch.cuda.synchronize()
+    assert _relerr(ys[0].cpu().numpy(), y0.cpu().numpy()) < 1e-12
+    b.destroy()
+    for o in ops:
+        o.destroy()
+    for c in ctxs:
+        c.close()
