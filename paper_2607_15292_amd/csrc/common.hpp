@@ -46,9 +46,12 @@ template <typename T> BEM_HD cx<T> conj_mul(cx<T> a, cx<T> b)
 {
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
-template <typename T> BEM_HD cx<T> fma_c(cx<T> a, cx<T> b, cx<T> c)  // a * b + c
+BEM_HD float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+BEM_HD double fma_r(double a, double b, double c) { return fma(a, b, c); }
+// a * b + c as two fused multiply-adds per part (the accumulator enters the inner one)
+template <typename T> BEM_HD cx<T> fma_c(cx<T> a, cx<T> b, cx<T> c)
 {
-    return {a.re * b.re - a.im * b.im + c.re, a.re * b.im + a.im * b.re + c.im};
+    return {fma_r(a.re, b.re, fma_r(-a.im, b.im, c.re)), fma_r(a.re, b.im, fma_r(a.im, b.re, c.im))};
 }
 
 template <typename To, typename Ti> BEM_HD cx<To> cvt(cx<Ti> a) { return {(To)a.re, (To)a.im}; }
