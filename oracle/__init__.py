@@ -5,7 +5,9 @@ baseline may import this package; the product library neither imports nor links 
 shares no code with it.
 
 * ``bem_oracle.c`` (plain C99, FP64, optional OpenMP): kernel U and T of the paper's
-  Appendix A / Sec. 2.1, collocation entries with the quadrature rules, dense products.
+  Appendix A / Sec. 2.1, collocation entries with the quadrature rules, dense products, and
+  the gradient of a single-layer bilinear form with respect to the node coordinates and the
+  material (regular pairs by the chain rule, self pairs by central differences).
 * ``aca3d.py`` (numpy): the matrix-valued 3D-ACA of Algorithm 1 (Sec. 3) and the
   matrix-valued ACA with QR/SVD recompression of eq. (ACA) (Sec. 3.1), for small tensors.
 * ``partition.py`` (numpy): the PCA cluster tree and admissibility of Sec. 3.1.
@@ -67,6 +69,11 @@ def lib():
         L.oracle_tri7.argtypes = [dp, dp]
         L.oracle_gauss_legendre.restype = None
         L.oracle_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
+        L.oracle_adjoint_v.restype = ctypes.c_int
+        L.oracle_adjoint_v.argtypes = [dp, ctypes.c_int64, ip, ctypes.c_int64,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int32,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int32, dp, dp, ctypes.c_double,
+                                       dp, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -147,6 +154,27 @@ class Problem:
         if rc != 0:
             raise RuntimeError("oracle_point_entries failed with code %d" % rc)
         return (out[..., 0] + 1j * out[..., 1]).reshape(n, 3, 3)
+
+    def adjoint_v(self, w, x, fd_h=1e-5):
+        """Value S = sum_{r, l} w[r, l]^T V(s_l) x[r, l] of the single layer (near rule off)
+        and the gradient of Re S: (S, grad_nodes [n_nodes, 3], grad_mat [rho, c_p, c_s]).
+        Regular pairs by the chain rule, self pairs by central differences of the polar rule
+        (step fd_h relative).  w, x: [nrhs, L, 3K] complex."""
+        if self.near_on:
+            raise ValueError("the adjoint covers the regular and self rules (near rule off)")
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
+        assert w.shape == x.shape
+        wr = np.ascontiguousarray(np.stack([w.real, w.imag], axis=-1))
+        xr = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
+        val = np.zeros(2)
+        gn = np.zeros((self.nodes.shape[0], 3))
+        gm = np.zeros(3)
+        rc = lib().oracle_adjoint_v(*self._common(), self.self_nt, self.self_nr, w.shape[0], _d(wr), _d(xr),
+                                    float(fd_h), _d(val), _d(gn), _d(gm))
+        if rc != 0:
+            raise RuntimeError("oracle_adjoint_v failed with code %d" % rc)
+        return complex(val[0], val[1]), gn, gm
 
     def matvec_rows(self, op, rows, x):
         """y[r, l, 3q + a] = (A_l x[r, l])[3 rows[q] + a] without storing A; x: [nrhs, L, 3K]."""

@@ -525,6 +525,187 @@ int oracle_point_entries(const double *nodes, int64_t n_nodes, const int32_t *tr
     return bad ? -4 : 0;
 }
 
+/* ------------------------------------------------------------ adjoint of V */
+
+/* dU_ab/dc1 and dU_ab/dc2 (c1 = c_p, c2 = c_s) by differentiating the form of kernel_U:
+ * dI1/dc1 = e1 / c1^3 and dI1/dc2 = -e2 / c2^3 (the limits of the lambda-integral move),
+ * d(1/c^2)/dc = -2/c^3, d exp(-s r / c)/dc = exp(-s r / c) s r / c^2. */
+static void kernel_dU_dc(const double *rv, cplx s, const material *m, cplx *D1, cplx *D2)
+{
+    double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+    double rh[3] = {rv[0] / r, rv[1] / r, rv[2] / r};
+    double c1 = m->c1, c2 = m->c2;
+    cplx e1 = cexp(-s * r / c1), e2 = cexp(-s * r / c2);
+    double pref = 1.0 / (4.0 * M_PI * m->rho);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double dij = (i == j) ? 1.0 : 0.0;
+            double P = rh[i] * rh[j];
+            double f0 = (3.0 * P - dij) / r;
+            double f1 = P / (r * c1 * c1);
+            double f2 = (dij - P) / (r * c2 * c2);
+            D1[3 * i + j] = pref * (f0 * e1 / (c1 * c1 * c1) - 2.0 * f1 / c1 * e1 + f1 * e1 * s * r / (c1 * c1));
+            D2[3 * i + j] = pref * (-f0 * e2 / (c2 * c2 * c2) - 2.0 * f2 / c2 * e2 + f2 * e2 * s * r / (c2 * c2));
+        }
+}
+
+/* sum over r, l of w[r][l][3 i .. 3 i + 3]^T E x[r][l][3 j .. 3 j + 3] for one 3x3 block E(l) */
+static cplx contract(const cplx *E, const double *w, const double *x, int64_t K, int32_t L, int32_t nrhs,
+                     int32_t l, int64_t i, int64_t j)
+{
+    cplx sum = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        const double *wv = w + 2 * (((int64_t)r * L + l) * 3 * K + 3 * i);
+        const double *xv = x + 2 * (((int64_t)r * L + l) * 3 * K + 3 * j);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                sum += (wv[2 * a] + I * wv[2 * a + 1]) * E[3 * a + b] * (xv[2 * b] + I * xv[2 * b + 1]);
+    }
+    return sum;
+}
+
+/* Value S = sum_{r, l, i, j} w[r][l][i]^T V_ij(s_l) x[r][l][j] of the single layer (near rule
+ * off) and the gradient of Re S with respect to the node coordinates and to rho, c_p, c_s:
+ * the derivative of the discrete operator.  Regular pairs: chain rule through the Gauss
+ * points y_q = sum_k b_qk v_k of element j, the collocation point (centroid of element i) and
+ * the area of element j, with dU/dy from kernel_gradU and dU/dc from kernel_dU_dc.  Self
+ * pairs: central differences of the polar rule in each vertex coordinate of the element
+ * (step fd_h times its longest edge) and in c_p, c_s (step fd_h times the speed).
+ * value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho, c_p, c_s). */
+int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
+                     double rho, double cp, double cs, const double *s, int32_t L, int self_nt, int self_nr,
+                     int32_t nrhs, const double *w, const double *x, double fd_h,
+                     double *value, double *grad_nodes, double *grad_mat)
+{
+    ctx C;
+    int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, 0, 0.0, 0.0, self_nt, self_nr);
+    if (rc) return rc;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    double *gbuf = (double *)calloc((size_t)nth * (3 * (size_t)n_nodes + 5), sizeof(double));
+    if (!gbuf) { free((void *)C.el); return -3; }
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *g = gbuf + (size_t)tid * (3 * (size_t)n_nodes + 5);
+        double *gm = g + 3 * (size_t)n_nodes;  /* c1, c2, Re S, Im S, (unused) */
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < K; ++i) {
+            const element *ei = &C.el[i];
+            for (int64_t j = 0; j < K; ++j) {
+                const element *ej = &C.el[j];
+                const int32_t *tj = tris + 3 * j, *ti = tris + 3 * i;
+                if (i == j) {
+                    /* value and material derivatives of the self entry, then the vertices */
+                    const double hl = fd_h * sqrt(ej->lmax2);
+                    for (int32_t l = 0; l < L; ++l) {
+                        cplx sl = s[2 * l] + I * s[2 * l + 1];
+                        cplx E[9] = {0};
+                        self_rule(&C, 0, ej, sl, E);
+                        cplx v = contract(E, w, x, K, L, nrhs, l, i, j);
+                        gm[2] += creal(v);
+                        gm[3] += cimag(v);
+                        for (int which = 0; which < 2; ++which) {
+                            ctx Cp = C, Cm = C;
+                            double h = fd_h * (which == 0 ? cp : cs);
+                            if (which == 0) { Cp.mat.c1 += h; Cm.mat.c1 -= h; }
+                            else { Cp.mat.c2 += h; Cm.mat.c2 -= h; }
+                            cplx Ep[9] = {0}, Em[9] = {0};
+                            self_rule(&Cp, 0, ej, sl, Ep);
+                            self_rule(&Cm, 0, ej, sl, Em);
+                            cplx D[9];
+                            for (int t = 0; t < 9; ++t) D[t] = (Ep[t] - Em[t]) / (2.0 * h);
+                            gm[which] += creal(contract(D, w, x, K, L, nrhs, l, i, j));
+                        }
+                        for (int a = 0; a < 3; ++a)
+                            for (int k = 0; k < 3; ++k) {
+                                double vp[9], vm[9];
+                                for (int b = 0; b < 3; ++b)
+                                    for (int q = 0; q < 3; ++q) vp[3 * b + q] = vm[3 * b + q] = ej->v[b][q];
+                                vp[3 * a + k] += hl;
+                                vm[3 * a + k] -= hl;
+                                int32_t loc[3] = {0, 1, 2};
+                                element ep, em;
+                                make_element(vp, loc, &ep);
+                                make_element(vm, loc, &em);
+                                cplx Ep[9] = {0}, Em[9] = {0};
+                                self_rule(&C, 0, &ep, sl, Ep);
+                                self_rule(&C, 0, &em, sl, Em);
+                                cplx D[9];
+                                for (int t = 0; t < 9; ++t) D[t] = (Ep[t] - Em[t]) / (2.0 * hl);
+                                g[3 * (int64_t)tj[a] + k] += creal(contract(D, w, x, K, L, nrhs, l, i, j));
+                            }
+                    }
+                    continue;
+                }
+                /* area derivative of element j: dA/dv1 = (e2 x n)/2, dA/dv2 = (n x e1)/2 */
+                double e1v[3], e2v[3], dA[3][3];
+                for (int k = 0; k < 3; ++k) { e1v[k] = ej->v[1][k] - ej->v[0][k]; e2v[k] = ej->v[2][k] - ej->v[0][k]; }
+                const double *n = ej->n;
+                dA[1][0] = 0.5 * (e2v[1] * n[2] - e2v[2] * n[1]);
+                dA[1][1] = 0.5 * (e2v[2] * n[0] - e2v[0] * n[2]);
+                dA[1][2] = 0.5 * (e2v[0] * n[1] - e2v[1] * n[0]);
+                dA[2][0] = 0.5 * (n[1] * e1v[2] - n[2] * e1v[1]);
+                dA[2][1] = 0.5 * (n[2] * e1v[0] - n[0] * e1v[2]);
+                dA[2][2] = 0.5 * (n[0] * e1v[1] - n[1] * e1v[0]);
+                for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+                for (int q = 0; q < 7; ++q) {
+                    const double *Bq = &C.tri_bary[3 * q];
+                    double y[3], rv[3];
+                    for (int k = 0; k < 3; ++k) {
+                        y[k] = Bq[0] * ej->v[0][k] + Bq[1] * ej->v[1][k] + Bq[2] * ej->v[2][k];
+                        rv[k] = y[k] - ei->c[k];
+                    }
+                    const double wq = C.tri_w[q], wA = wq * ej->area;
+                    for (int32_t l = 0; l < L; ++l) {
+                        cplx sl = s[2 * l] + I * s[2 * l + 1];
+                        cplx U[9], G[27], D1[9], D2[9];
+                        kernel_U(rv, sl, &C.mat, U);
+                        kernel_gradU(rv, sl, &C.mat, G);
+                        kernel_dU_dc(rv, sl, &C.mat, D1, D2);
+                        cplx v = contract(U, w, x, K, L, nrhs, l, i, j);
+                        gm[2] += wA * creal(v);
+                        gm[3] += wA * cimag(v);
+                        gm[0] += wA * creal(contract(D1, w, x, K, L, nrhs, l, i, j));
+                        gm[1] += wA * creal(contract(D2, w, x, K, L, nrhs, l, i, j));
+                        for (int k = 0; k < 3; ++k) {
+                            cplx Gk[9];
+                            for (int t = 0; t < 9; ++t) Gk[t] = G[3 * t + k];
+                            double gk = wA * creal(contract(Gk, w, x, K, L, nrhs, l, i, j));
+                            for (int a = 0; a < 3; ++a) {
+                                g[3 * (int64_t)tj[a] + k] += Bq[a] * gk;  /* Gauss point of element j */
+                                g[3 * (int64_t)ti[a] + k] -= gk / 3.0;     /* centroid of element i */
+                            }
+                        }
+                        for (int a = 0; a < 3; ++a)
+                            for (int k = 0; k < 3; ++k) g[3 * (int64_t)tj[a] + k] += wq * creal(v) * dA[a][k];
+                    }
+                }
+            }
+        }
+    }
+    for (size_t e = 0; e < 3 * (size_t)n_nodes; ++e) grad_nodes[e] = 0.0;
+    double gm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < nth; ++t) {
+        const double *g = gbuf + (size_t)t * (3 * (size_t)n_nodes + 5);
+        for (size_t e = 0; e < 3 * (size_t)n_nodes; ++e) grad_nodes[e] += g[e];
+        for (int k = 0; k < 4; ++k) gm[k] += g[3 * (size_t)n_nodes + k];
+    }
+    value[0] = gm[2];
+    value[1] = gm[3];
+    grad_mat[0] = -gm[2] / rho;  /* U is proportional to 1 / rho */
+    grad_mat[1] = gm[0];
+    grad_mat[2] = gm[1];
+    free(gbuf);
+    free((void *)C.el);
+    return 0;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

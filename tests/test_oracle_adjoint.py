@@ -1,0 +1,68 @@
+"""Pins of the oracle's adjoint of the single layer (oracle.Problem.adjoint_v): the gradient
+of Re S, S = sum_{r, l} w[r, l]^T V(s_l) x[r, l], with respect to the node coordinates and
+rho, c_p, c_s against central differences of the oracle's own dense operator (the plain
+definition of the derivative of the discrete operator), translation invariance, and the value
+against the dense product."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_15292_amd import workloads as W
+
+
+def _setup(level=1, L=3, nrhs=2):
+    X, T = W.icosphere(level)
+    s = W.bdf2_contour(8, 0.1)[[0, 2, 5]][:L]
+    w = W.random_rhs(40, (nrhs, L, 3 * len(T)))
+    x = W.random_rhs(41, (nrhs, L, 3 * len(T)))
+    return X, T, s, w, x
+
+
+def _S(X, T, s, w, x, rho=1.0, cp=1.0, cs=0.5):
+    D = oracle.Problem(X, T, s, rho, cp, cs, near_on=False).dense(oracle.OP_V)
+    return complex(np.einsum("rli,lij,rlj->", w, D, x))
+
+
+def test_value_is_the_dense_bilinear_form():
+    X, T, s, w, x = _setup()
+    val, _, _ = oracle.Problem(X, T, s, near_on=False).adjoint_v(w, x)
+    ref = _S(X, T, s, w, x)
+    assert abs(val - ref) <= 1e-12 * abs(ref)
+
+
+def test_node_gradient_matches_central_differences():
+    X, T, s, w, x = _setup()
+    _, g, _ = oracle.Problem(X, T, s, near_on=False).adjoint_v(w, x)
+    rng = np.random.default_rng(5)
+    h = 1e-5
+    for _ in range(10):
+        D = rng.standard_normal(X.shape)
+        fd = (_S(X + h * D, T, s, w, x).real - _S(X - h * D, T, s, w, x).real) / (2 * h)
+        an = float(np.sum(g * D))
+        assert abs(an - fd) <= 1e-6 * np.linalg.norm(g) * np.linalg.norm(D), (an, fd)
+
+
+def test_material_gradient_matches_central_differences():
+    X, T, s, w, x = _setup()
+    _, _, gm = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=False).adjoint_v(w, x)
+    base = dict(rho=1.3, cp=1.1, cs=0.6)
+    for k, name in enumerate(("rho", "cp", "cs")):
+        h = 1e-6 * base[name]
+        p, m = dict(base), dict(base)
+        p[name] += h
+        m[name] -= h
+        fd = (_S(X, T, s, w, x, **p).real - _S(X, T, s, w, x, **m).real) / (2 * h)
+        assert abs(gm[k] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(gm).max()), (name, gm[k], fd)
+
+
+def test_translation_invariance():
+    # S does not change when every node moves by the same vector
+    X, T, s, w, x = _setup()
+    _, g, _ = oracle.Problem(X, T, s, near_on=False).adjoint_v(w, x)
+    assert np.abs(g.sum(axis=0)).max() <= 1e-8 * np.abs(g).max()
+
+
+def test_rejects_near_rule():
+    X, T, s, w, x = _setup()
+    with pytest.raises(ValueError):
+        oracle.Problem(X, T, s, near_on=True).adjoint_v(w, x)
