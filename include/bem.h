@@ -281,6 +281,30 @@ typedef struct bem_solve_stats {
 int bem_solve(bem_op *A, bem_op *A_inner, int32_t nrhs, const void *b, void *x, int32_t flags,
               const bem_solve_opts *opts, bem_solve_stats *stats);
 
+/* ---- Matrix-free products and the adjoint of the single layer ------------------------------
+ * The dense discrete operators of eq. (discrVK) at the contour points (Sec. 2.3, 2.4) applied
+ * without storing them: every entry is recomputed (regular, near and self rules as in
+ * bem_entries, FP64).  For meshes whose dense array does not fit, and as the forward and
+ * transposed products of a differentiable single layer. */
+
+/* y[r][l] = A(s_l) x[r][l], or A(s_l)^T x[r][l] (plain transpose, no conjugation) when
+ * transpose != 0, for op V, K or HK; x, y: [nrhs][L][3K] complex128 in mesh order, host or
+ * device per flags (BEM_DEVICE_PTR).  Cost: K^2 L entries per pass of 4 right-hand sides. */
+int bem_apply_mf(bem_ctx *ctx, int32_t op, int32_t transpose, int32_t nrhs, const void *x, void *y, int32_t flags);
+
+/* Adjoint of the single layer (an extension; the paper has no adjoint): the value
+ * S = sum_{r, l} w[r][l]^T V(s_l) x[r][l] (no conjugation) and the gradient of Re S with
+ * respect to the node coordinates and the material, for the discrete operator of eq.
+ * (discrVK) with the regular and self rules (the context's near rule must be off:
+ * BEM_ERR_STATE otherwise).  Regular pairs are differentiated exactly (chain rule through
+ * the Gauss points, the collocation points and the element areas; speeds through the kernel);
+ * self pairs by central differences of the polar rule (relative step 1e-5).  Entries are
+ * recomputed, never stored.  w, x: [nrhs][L][3K] complex128, mesh order, host or device per
+ * flags.  value: [2] (Re, Im S); grad_nodes: [n_nodes][3]; grad_mat: [3] = d/d rho, d/d c_p,
+ * d/d c_s; each output may be NULL.  Cost: K^2 L nrhs kernel evaluations with derivatives. */
+int bem_adjoint_v(bem_ctx *ctx, int32_t nrhs, const void *w, const void *x, int32_t flags, double *value,
+                  double *grad_nodes, double *grad_mat);
+
 /* ---- Batched products of several compressed operators ------------------------------------
  * The all-frequency product of bem_apply (the face-fibre form of eq. (3DacaMult) at every
  * contour point) for up to 16 compressed operators at once, e.g. several meshes sharing one

@@ -1,0 +1,59 @@
+"""Differentiable single-layer products: torch.autograd.Function over the library's matrix-free
+product and adjoint (bem_apply_mf, bem_adjoint_v).  Entries are recomputed in the forward
+and in the backward pass; nothing of the operator is stored.
+
+    y = single_layer(bem_ctx, nodes, material, x)
+
+y[r, l] = V(s_l) x[r, l] for the mesh with node coordinates `nodes` (float64 [n_nodes, 3],
+any device; the triangles and contour points are those set on `bem_ctx`), material
+(rho, c_p, c_s) as a float64 tensor [3], and x complex128 [nrhs, L, 3K] on the GPU.  The
+gradients are those of the discrete operator: the node coordinates and the speeds by the
+adjoint kernel, x by the transposed product.  The context's near rule must be off.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _load(ctx, tris, nodes, material):
+    nodes_np = nodes.detach().to("cpu", torch.float64).numpy()
+    mat = material.detach().to("cpu", torch.float64).numpy()
+    ctx.set_mesh(nodes_np, tris)
+    ctx.set_material(float(mat[0]), float(mat[1]), float(mat[2]))
+
+
+class SingleLayer(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, bem_ctx, tris, nodes, material, x):
+        _load(bem_ctx, tris, nodes, material)
+        y = bem_ctx.apply_mf(B.OP_V, x.contiguous())
+        fctx.bem = bem_ctx
+        fctx.tris = tris
+        fctx.save_for_backward(nodes, material, x)
+        return y
+
+    @staticmethod
+    def backward(fctx, gy):
+        nodes, material, x = fctx.saved_tensors
+        bem = fctx.bem
+        _load(bem, fctx.tris, nodes, material)
+        # real loss: dL = Re sum conj(gy) dy, so the node and material gradients are those of
+        # Re S with S = sum conj(gy)^T V x, and the input gradient is V^H gy
+        w = gy.conj().resolve_conj().contiguous()
+        g_nodes = g_mat = g_x = None
+        if fctx.needs_input_grad[2] or fctx.needs_input_grad[3]:
+            _, gn, gm = bem.adjoint_v(w, x.contiguous())
+            g_nodes = torch.as_tensor(gn, dtype=nodes.dtype, device=nodes.device)
+            g_mat = torch.as_tensor(gm, dtype=material.dtype, device=material.device)
+        if fctx.needs_input_grad[4]:
+            g_x = bem.apply_mf(B.OP_V, w, transpose=True).conj()
+        return None, None, g_nodes, g_mat, g_x
+
+
+def single_layer(bem_ctx, nodes, material, x, tris):
+    """y[r, l] = V(s_l) x[r, l], differentiable in nodes, material and x."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    return SingleLayer.apply(bem_ctx, tris, nodes, material, x)

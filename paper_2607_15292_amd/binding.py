@@ -112,6 +112,8 @@ _SIGS = {
     "bem_apply_weighted": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "bem_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(bem_solve_opts),
                                  ctypes.POINTER(bem_solve_stats)]),
+    "bem_apply_mf": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32]),
+    "bem_adjoint_v": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]),
     "bem_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "bem_batch_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
@@ -152,6 +154,8 @@ def _ptr(a):
             raise ValueError("torch tensors must live on the GPU; use numpy for host buffers")
         if not a.is_contiguous():
             raise ValueError("tensor must be contiguous")
+        if a.is_conj() or a.is_neg():
+            raise ValueError("tensor is a lazy conjugate or negative view; call resolve_conj() / resolve_neg()")
         return ctypes.c_void_p(a.data_ptr()), DEVICE_PTR
     if not a.flags["C_CONTIGUOUS"]:
         raise ValueError("array must be C-contiguous")
@@ -200,6 +204,7 @@ class Context:
         nodes = np.ascontiguousarray(nodes, dtype=np.float64)
         tris = np.ascontiguousarray(tris, dtype=np.int32)
         self.K = int(tris.shape[0])
+        self.n_nodes = int(nodes.shape[0])
         return self._check(lib().bem_set_mesh(self.h, nodes.ctypes.data, nodes.shape[0], tris.ctypes.data, tris.shape[0]))
 
     def set_material(self, rho, cp, cs):
@@ -277,6 +282,39 @@ class Context:
         if k <= 0:
             return kc.value, k, None, None
         return kc.value, k, U[:3 * m * k].reshape(3 * m, k), V[:3 * n * k].reshape(3 * n, k)
+
+    def apply_mf(self, op, x, y=None, transpose=False):
+        """y[r, l] = A(s_l) x[r, l] (or A(s_l)^T x[r, l]) with entries recomputed (no storage);
+        x: [nrhs, L, 3K] numpy or torch CUDA complex128."""
+        nrhs = x.shape[0]
+        if _is_torch(x):
+            import torch
+            if y is None:
+                y = torch.empty_like(x)
+            self._sync_torch_stream()
+        elif y is None:
+            y = np.empty_like(x)
+        px, fl = _ptr(x)
+        py, _ = _ptr(y)
+        self._check(lib().bem_apply_mf(self.h, int(op), int(bool(transpose)), int(nrhs), px, py, fl))
+        return y
+
+    def adjoint_v(self, w, x):
+        """(S, grad_nodes [n_nodes, 3], grad_mat [rho, c_p, c_s]) of S = sum w^T V(s_l) x
+        (gradient of Re S); w, x: [nrhs, L, 3K] numpy or torch CUDA complex128."""
+        nrhs = x.shape[0]
+        if _is_torch(x):
+            self._sync_torch_stream()
+        pw, fl = _ptr(w)
+        px, fl2 = _ptr(x)
+        if fl != fl2:
+            raise ValueError("w and x must both be host arrays or both device tensors")
+        val = np.zeros(2)
+        gn = np.zeros((self.n_nodes, 3))
+        gm = np.zeros(3)
+        self._check(lib().bem_adjoint_v(self.h, int(nrhs), pw, px, fl, val.ctypes.data, gn.ctypes.data,
+                                        gm.ctypes.data))
+        return complex(val[0], val[1]), gn, gm
 
     def partition(self, eta=1.5, leaf=64):
         n = ctypes.c_int64()

@@ -1,0 +1,337 @@
+// adjoint.hip -- matrix-free products with the dense discrete operator (entries recomputed,
+// never stored) and the adjoint of the single layer: the gradient of the bilinear form
+// Re S, S = sum_{r, l} w[r][l]^T V(s_l) x[r][l], with respect to the node coordinates and
+// the material (the discrete operator of eq. (discrVK) at the contour points of Sec. 2.4,
+// differentiated; the paper itself has no adjoint).
+//
+// Regular pairs: chain rule.  With r = y - x, R = |r|, rh = r / R and 4 pi rho U = A I +
+// B rh rh^T, f = w^T U v has the gradient
+//   grad_r f = (A' (w.v) + B' (w.rh)(v.rh)) rh + (B / R) ((v.rh) w + (w.rh) v - 2 (w.rh)(v.rh) rh),
+// taken at the Gauss points y_q = sum_a b_qa P_a of element j (rows of node a), minus at the
+// centroid of element i, and the area of element j enters through dA/dP.  The speeds enter
+// through A and B only: dA/dc1 = -e1r / c1, dA/dc2 = e2r (x2 - 1) / c2, dB/dc1 =
+// e1r (x1 + 1) / c1, dB/dc2 = -e2r (x2 + 1) / c2 with x_a = s R / c_a, e_ar = exp(-x_a) /
+// (c_a^2 R) (both branches of the kernel: in the series branch the lambda-integral
+// contributes -+ e_a / c_a^3).  Self pairs: central differences of the polar rule.
+#include "lib.hpp"
+
+namespace bem {
+
+namespace {
+
+constexpr int WG = 256;
+constexpr int JB = 32;     // column elements per workgroup of the adjoint kernel
+constexpr int NR = 4;      // right-hand sides per pass of the matrix-free product
+
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// y[r][l][3 e + a] = sum_o ENTRY(e, o, l)[a][b] x[r][l][3 o + b]  (TRANS: ENTRY(o, e, l)[b][a]);
+// thread per (e, l), e fastest; right-hand sides in passes of NR.
+template <bool TRANS>
+__global__ __launch_bounds__(WG) void k_mf_apply(DevCtx c, int op, int nrhs, const zd* __restrict__ x,
+                                                 zd* __restrict__ y)
+{
+    const int K = c.geo.K, L = c.fr.L;
+    const int e = blockIdx.x * WG + threadIdx.x, l = blockIdx.y;
+    if (e >= K) return;
+    const size_t M = 3 * (size_t)K;
+    for (int r0 = 0; r0 < nrhs; r0 += NR) {
+        const int nr = min(NR, nrhs - r0);
+        zd acc[NR][3];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[rr][a] = {0.0, 0.0};
+        for (int o = 0; o < K; ++o) {
+            const blk E = TRANS ? entry_dispatch<false>(c, op, o, e, l) : entry_dispatch<false>(c, op, e, o, l);
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+                if (rr >= nr) break;
+                const zd* xv = x + ((size_t)(r0 + rr) * L + l) * M + 3 * (size_t)o;
+                const zd v[3] = {xv[0], xv[1], xv[2]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        acc[rr][a] = TRANS ? fma_c(E.a[3 * b + a], v[b], acc[rr][a]) : fma_c(E.a[3 * a + b], v[b], acc[rr][a]);
+            }
+        }
+        for (int rr = 0; rr < nr; ++rr) {
+            zd* yv = y + ((size_t)(r0 + rr) * L + l) * M + 3 * (size_t)e;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) yv[a] = acc[rr][a];
+        }
+    }
+}
+
+// A, B, dA/dR, dB/dR and the speed derivatives of A and B at distance R.
+__device__ __forceinline__ void kernel_adj(double R, double Rinv, zd s, zd sinv, const Mat<double>& M, zd& A, zd& B,
+                                           zd& Ad, zd& Bd, zd& A1, zd& A2, zd& B1, zd& B2)
+{
+    kernel_AB<double, true>(R, Rinv, s, sinv, M, A, B, Ad, Bd);
+    const zd x1 = s * (R * M.ic1), x2 = s * (R * M.ic2);
+    const zd e1r = M_<double>::cexpm(x1) * (M.ic1s * Rinv), e2r = M_<double>::cexpm(x2) * (M.ic2s * Rinv);
+    const zd one = {1.0, 0.0};
+    A1 = e1r * (-M.ic1);
+    A2 = (e2r * (x2 - one)) * M.ic2;
+    B1 = (e1r * (x1 + one)) * M.ic1;
+    B2 = (e2r * (x2 + one)) * (-M.ic2);
+}
+
+// Regular pairs (i != j, near rule off): one thread per row element i, JB column elements per
+// workgroup.  gJ[bx][j][3 a + k]: d Re S / dP_{j,a,k} summed over the workgroup's rows;
+// gI[by][i][k]: d Re S / d(centroid of i)_k over the workgroup's columns; gM[tile]: dc1, dc2,
+// Re S, Im S.
+__global__ __launch_bounds__(WG) void k_adjoint_v(DevCtx c, int nrhs, const zd* __restrict__ w,
+                                                  const zd* __restrict__ x, double* __restrict__ gJ,
+                                                  double* __restrict__ gI, double* __restrict__ gM)
+{
+    __shared__ double red[WG / 64][9];
+    const Geo& g = c.geo;
+    const int K = g.K, L = c.fr.L;
+    const size_t M = 3 * (size_t)K;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const bool act = i < K;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j0 = blockIdx.y * JB, j1 = min(K, j0 + JB);
+    const double pref = c.md.inv4pirho;
+    double ci[3] = {0.0, 0.0, 0.0}, mat[4] = {0.0, 0.0, 0.0, 0.0};
+    const double xi[3] = {act ? g.cx[i] : 0.0, act ? g.cy[i] : 0.0, act ? g.cz[i] : 0.0};
+    for (int j = j0; j < j1; ++j) {
+        double gj[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) gj[t] = 0.0;
+        if (act && i != j) {
+            // dA/dP_a of element j: dA/dP1 = (e2 x n) / 2, dA/dP2 = (n x e1) / 2, dA/dP0 = -(sum)
+            double P[3][3];
+            for (int a = 0; a < 3; ++a) {
+                P[a][0] = g.vx[a * K + j];
+                P[a][1] = g.vy[a * K + j];
+                P[a][2] = g.vz[a * K + j];
+            }
+            const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+            const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+            const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+            double dA[3][3];
+            dA[1][0] = 0.5 * (e2[1] * n[2] - e2[2] * n[1]);
+            dA[1][1] = 0.5 * (e2[2] * n[0] - e2[0] * n[2]);
+            dA[1][2] = 0.5 * (e2[0] * n[1] - e2[1] * n[0]);
+            dA[2][0] = 0.5 * (n[1] * e1[2] - n[2] * e1[1]);
+            dA[2][1] = 0.5 * (n[2] * e1[0] - n[0] * e1[2]);
+            dA[2][2] = 0.5 * (n[0] * e1[1] - n[1] * e1[0]);
+            for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+#pragma unroll 1
+            for (int q = 0; q < 7; ++q) {
+                const int o = q * K + j;
+                const double r[3] = {g.gx[o] - xi[0], g.gy[o] - xi[1], g.gz[o] - xi[2]};
+                const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                const double Rinv = 1.0 / sqrt(R2), R = R2 * Rinv;
+                const double rh[3] = {r[0] * Rinv, r[1] * Rinv, r[2] * Rinv};
+                double G[3] = {0.0, 0.0, 0.0}, V = 0.0, Vi = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll 1
+                for (int l = 0; l < L; ++l) {
+                    zd A, B, Ad, Bd, A1, A2, B1, B2;
+                    kernel_adj(R, Rinv, c.fr.s[l], c.fr.sinv[l], c.md, A, B, Ad, Bd, A1, A2, B1, B2);
+                    const zd BR = B * Rinv;
+#pragma unroll 1
+                    for (int rr = 0; rr < nrhs; ++rr) {
+                        const zd* up = w + ((size_t)rr * L + l) * M + 3 * (size_t)i;
+                        const zd* vp = x + ((size_t)rr * L + l) * M + 3 * (size_t)j;
+                        const zd u[3] = {up[0], up[1], up[2]}, v[3] = {vp[0], vp[1], vp[2]};
+                        const zd uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+                        const zd ur = u[0] * rh[0] + u[1] * rh[1] + u[2] * rh[2];
+                        const zd vr = v[0] * rh[0] + v[1] * rh[1] + v[2] * rh[2];
+                        const zd t2 = ur * vr;
+                        const zd val = A * uv + B * t2;
+                        const double gs = (Ad * uv + Bd * t2).re;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) G[k] += gs * rh[k] + (BR * (vr * u[k] + ur * v[k] - t2 * (2.0 * rh[k]))).re;
+                        V += val.re;
+                        Vi += val.im;
+                        m1 += (A1 * uv + B1 * t2).re;
+                        m2 += (A2 * uv + B2 * t2).re;
+                    }
+                }
+                const double wA = g.gw[o] * pref, w7 = c.qt.w7[q] * pref;
+                const double* b = c.qt.b7 + 3 * q;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double gk = wA * G[k];
+                    ci[k] -= gk;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) gj[3 * a + k] += b[a] * gk + w7 * V * dA[a][k];
+                }
+                mat[0] += wA * m1;
+                mat[1] += wA * m2;
+                mat[2] += wA * V;
+                mat[3] += wA * Vi;
+            }
+        }
+        // sum over the workgroup's rows, in a fixed order
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const double sv = wsum(gj[t]);
+            if (lane == 0) red[wv][t] = sv;
+        }
+        __syncthreads();
+        if (threadIdx.x < 9) {
+            double sv = 0.0;
+            for (int q = 0; q < WG / 64; ++q) sv += red[q][threadIdx.x];
+            gJ[((size_t)blockIdx.x * K + j) * 9 + threadIdx.x] = sv;
+        }
+        __syncthreads();
+    }
+    if (act)
+        for (int k = 0; k < 3; ++k) gI[((size_t)blockIdx.y * K + i) * 3 + k] = ci[k];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double sv = wsum(mat[t]);
+        if (lane == 0) red[wv][t] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double sv = 0.0;
+        for (int q = 0; q < WG / 64; ++q) sv += red[q][threadIdx.x];
+        gM[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = sv;
+    }
+}
+
+// Re and Im of sum_{r, l} w[r][l][j]^T E_l x[r][l][j] with E_l the single-layer self entry of
+// an element with vertices P (polar rule about its centroid) and material Mm.
+__device__ zd self_form(const double (*P)[3], const DevCtx& c, const Mat<double>& Mm, int nrhs, const zd* w,
+                        const zd* x, int j)
+{
+    const int K = c.geo.K, L = c.fr.L;
+    const size_t M = 3 * (size_t)K;
+    double cx = (P[0][0] + P[1][0] + P[2][0]) / 3.0, cy = (P[0][1] + P[1][1] + P[2][1]) / 3.0,
+           cz = (P[0][2] + P[1][2] + P[2][2]) / 3.0;
+    double vx[3] = {P[0][0], P[1][0], P[2][0]}, vy[3] = {P[0][1], P[1][1], P[2][1]}, vz[3] = {P[0][2], P[1][2], P[2][2]};
+    Geo e{};
+    e.K = 1;
+    e.cx = &cx;
+    e.cy = &cy;
+    e.cz = &cz;
+    e.vx = vx;
+    e.vy = vy;
+    e.vz = vz;
+    zd sum = {0.0, 0.0};
+    for (int l = 0; l < L; ++l) {
+        blk E;
+        entry_self(e, 0, 0, c.fr.s[l], c.fr.sinv[l], Mm, c.qt, E);
+        for (int rr = 0; rr < nrhs; ++rr) {
+            const zd* up = w + ((size_t)rr * L + l) * M + 3 * (size_t)j;
+            const zd* vp = x + ((size_t)rr * L + l) * M + 3 * (size_t)j;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) sum = fma_c(up[a] * E.a[3 * a + b], vp[b], sum);
+        }
+    }
+    return sum;
+}
+
+// Self pairs: thread per (element j, quantity d): d < 9 vertex a = d / 3, coordinate d % 3
+// (central difference, step h_rel times the longest edge); d = 9, 10: c1, c2 (the materials
+// at c -+ h are passed in); d = 11: the value.  out[j][13]: 9 vertex derivatives, dc1, dc2,
+// Re, Im.
+__global__ __launch_bounds__(64) void k_adjoint_self(DevCtx c, int nrhs, const zd* __restrict__ w,
+                                                     const zd* __restrict__ x, double h_rel, Mat<double> Mp1,
+                                                     Mat<double> Mm1, double h1, Mat<double> Mp2, Mat<double> Mm2,
+                                                     double h2, double* __restrict__ out)
+{
+    const Geo& g = c.geo;
+    const int K = g.K;
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t >= 12 * K) return;
+    const int j = t / 12, d = t - 12 * j;
+    double P[3][3];
+    for (int a = 0; a < 3; ++a) {
+        P[a][0] = g.vx[a * K + j];
+        P[a][1] = g.vy[a * K + j];
+        P[a][2] = g.vz[a * K + j];
+    }
+    double* o = out + (size_t)j * 13;
+    if (d < 9) {
+        const double h = h_rel * sqrt(g.lmax2[j]);
+        const int a = d / 3, k = d - 3 * (d / 3);
+        const double p0 = P[a][k];
+        P[a][k] = p0 + h;
+        const zd fp = self_form(P, c, c.md, nrhs, w, x, j);
+        P[a][k] = p0 - h;
+        const zd fm = self_form(P, c, c.md, nrhs, w, x, j);
+        o[d] = (fp.re - fm.re) / (2.0 * h);
+    } else if (d < 11) {
+        const zd fp = self_form(P, c, d == 9 ? Mp1 : Mp2, nrhs, w, x, j);
+        const zd fm = self_form(P, c, d == 9 ? Mm1 : Mm2, nrhs, w, x, j);
+        o[d] = (fp.re - fm.re) / (2.0 * (d == 9 ? h1 : h2));
+    } else {
+        const zd f = self_form(P, c, c.md, nrhs, w, x, j);
+        o[11] = f.re;
+        o[12] = f.im;
+    }
+}
+
+// out[e][t] = sum over tiles of part[tile][e][t] (fixed order)
+__global__ __launch_bounds__(WG) void k_sum_tiles(const double* __restrict__ part, int ntile, size_t n,
+                                                  double* __restrict__ out)
+{
+    const size_t q = (size_t)blockIdx.x * WG + threadIdx.x;
+    if (q >= n) return;
+    double s = 0.0;
+    for (int t = 0; t < ntile; ++t) s += part[(size_t)t * n + q];
+    out[q] = s;
+}
+
+}  // namespace
+
+void launch_mf_apply(const DevCtx& c, int op, bool transpose, int nrhs, const zd* x, zd* y, hipStream_t st)
+{
+    const dim3 grid((unsigned)((c.geo.K + WG - 1) / WG), (unsigned)c.fr.L);
+    if (transpose) hipLaunchKernelGGL(k_mf_apply<true>, grid, dim3(WG), 0, st, c, op, nrhs, x, y);
+    else hipLaunchKernelGGL(k_mf_apply<false>, grid, dim3(WG), 0, st, c, op, nrhs, x, y);
+    BEM_HIP_TRY(hipGetLastError());
+}
+
+size_t adjoint_work_doubles(int K)
+{
+    const size_t ti = (K + WG - 1) / WG, tj = (K + JB - 1) / JB;
+    return ti * K * 9 + tj * K * 3 + ti * tj * 4 + (size_t)K * 13 + (size_t)K * 12;
+}
+
+// work: adjoint_work_doubles(K); on return (on the stream) sums[0 .. 12 K): per element 9
+// vertex derivatives of the regular pairs as column element, then 3 centroid derivatives as
+// row element; tiles[..]: the per-workgroup dc1, dc2, Re S, Im S (ntiles_out of them); self
+// results [K][13].
+void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double h_rel, const Mat<double>& Mp1,
+                      const Mat<double>& Mm1, double h1, const Mat<double>& Mp2, const Mat<double>& Mm2, double h2,
+                      double* work, double** sums, double** tiles, int* ntiles_out, double** self_out,
+                      hipStream_t st)
+{
+    const int K = c.geo.K;
+    const unsigned ti = (unsigned)((K + WG - 1) / WG), tj = (unsigned)((K + JB - 1) / JB);
+    double* gJ = work;
+    double* gI = gJ + (size_t)ti * K * 9;
+    double* gM = gI + (size_t)tj * K * 3;
+    double* so = gM + (size_t)ti * tj * 4;
+    double* sum = so + (size_t)K * 13;
+    hipLaunchKernelGGL(k_adjoint_v, dim3(ti, tj), dim3(WG), 0, st, c, nrhs, w, x, gJ, gI, gM);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_adjoint_self, dim3((unsigned)((12 * (size_t)K + 63) / 64)), dim3(64), 0, st, c, nrhs, w, x,
+                       h_rel, Mp1, Mm1, h1, Mp2, Mm2, h2, so);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)((9 * (size_t)K + WG - 1) / WG)), dim3(WG), 0, st, gJ, (int)ti,
+                       9 * (size_t)K, sum);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)((3 * (size_t)K + WG - 1) / WG)), dim3(WG), 0, st, gI, (int)tj,
+                       3 * (size_t)K, sum + 9 * (size_t)K);
+    BEM_HIP_TRY(hipGetLastError());
+    *sums = sum;
+    *tiles = gM;
+    *ntiles_out = (int)(ti * tj);
+    *self_out = so;
+}
+
+}  // namespace bem

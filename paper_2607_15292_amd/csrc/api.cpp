@@ -788,6 +788,95 @@ int bem_op_freq_hist(const bem_op* op, int64_t* hist)
     return BEM_OK;
 }
 
+int bem_apply_mf(bem_ctx* ctx, int32_t op, int32_t transpose, int32_t nrhs, const void* x, void* y, int32_t flags)
+{
+    if (!ctx) return BEM_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        need_state(ctx);
+        if (op != BEM_OP_V && op != BEM_OP_K && op != BEM_OP_HK) throw api_error(BEM_ERR_ARG, "op must be V, K or HK");
+        if (nrhs < 1 || !x || !y) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
+        if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_apply_mf");
+        need_device(ctx);
+        const bool dev = (flags & BEM_DEVICE_PTR) != 0;
+        const size_t bytes = (size_t)nrhs * ctx->freq.L * 3 * (size_t)ctx->hgeo.K * sizeof(zd);
+        hipStream_t st = ctx->stream;
+        Staged sx, sy;
+        stage_in(sx, x, bytes, dev, st);
+        stage_out(sy, y, bytes, dev);
+        launch_mf_apply(ctx->devctx(ctx->dgeo.geo, nullptr), op, transpose != 0, nrhs, (const zd*)sx.dev, (zd*)sy.dev,
+                        st);
+        finish_out(sy, y, bytes, dev, st);
+        return BEM_OK;
+    });
+}
+
+int bem_adjoint_v(bem_ctx* ctx, int32_t nrhs, const void* w, const void* x, int32_t flags, double* value,
+                  double* grad_nodes, double* grad_mat)
+{
+    if (!ctx) return BEM_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        need_state(ctx);
+        if (ctx->quad.near_on) throw api_error(BEM_ERR_STATE, "the adjoint covers the regular and self rules: near rule must be off");
+        if (nrhs < 1 || !w || !x) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
+        if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_adjoint_v");
+        need_device(ctx);
+        const bool dev = (flags & BEM_DEVICE_PTR) != 0;
+        const int K = ctx->hgeo.K;
+        const size_t bytes = (size_t)nrhs * ctx->freq.L * 3 * (size_t)K * sizeof(zd);
+        hipStream_t st = ctx->stream;
+        Staged sw, sx;
+        stage_in(sw, w, bytes, dev, st);
+        stage_in(sx, x, bytes, dev, st);
+        // material tables at c -+ h for the central differences of the self entries
+        const double hrel = 1e-5;
+        const double h1 = hrel * ctx->cp, h2 = hrel * ctx->cs;
+        const Mat<double> Mp1 = make_mat<double>(ctx->rho, ctx->cp + h1, ctx->cs),
+                          Mm1 = make_mat<double>(ctx->rho, ctx->cp - h1, ctx->cs),
+                          Mp2 = make_mat<double>(ctx->rho, ctx->cp, ctx->cs + h2),
+                          Mm2 = make_mat<double>(ctx->rho, ctx->cp, ctx->cs - h2);
+        DevBuf work;
+        work.alloc(adjoint_work_doubles(K) * sizeof(double));
+        double *sums = nullptr, *tiles = nullptr, *self_out = nullptr;
+        int ntiles = 0;
+        launch_adjoint_v(ctx->devctx(ctx->dgeo.geo, nullptr), nrhs, (const zd*)sw.dev, (const zd*)sx.dev, hrel, Mp1, Mm1,
+                         h1, Mp2, Mm2, h2, work.as<double>(), &sums, &tiles, &ntiles, &self_out, st);
+        std::vector<double> hs(12 * (size_t)K), ht(4 * (size_t)ntiles), hself(13 * (size_t)K);
+        BEM_HIP_TRY(hipMemcpyAsync(hs.data(), sums, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        BEM_HIP_TRY(hipMemcpyAsync(ht.data(), tiles, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        BEM_HIP_TRY(hipMemcpyAsync(hself.data(), self_out, hself.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        BEM_HIP_TRY(hipStreamSynchronize(st));
+        // element results to nodes (fixed order: elements ascending)
+        const int64_t nn = (int64_t)ctx->nodes.size() / 3;
+        std::vector<double> gn(3 * (size_t)nn, 0.0);
+        double m[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < ntiles; ++t)
+            for (int k = 0; k < 4; ++k) m[k] += ht[4 * (size_t)t + k];
+        for (int e = 0; e < K; ++e) {
+            const int32_t* tri = &ctx->tris[3 * (size_t)e];
+            const double* gJ = &hs[9 * (size_t)e];
+            const double* gI = &hs[9 * (size_t)K + 3 * (size_t)e];
+            const double* so = &hself[13 * (size_t)e];
+            for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < 3; ++k) gn[3 * (size_t)tri[a] + k] += gJ[3 * a + k] + so[3 * a + k] + gI[k] / 3.0;
+            m[0] += so[9];
+            m[1] += so[10];
+            m[2] += so[11];
+            m[3] += so[12];
+        }
+        if (value) {
+            value[0] = m[2];
+            value[1] = m[3];
+        }
+        if (grad_nodes) std::copy(gn.begin(), gn.end(), grad_nodes);
+        if (grad_mat) {
+            grad_mat[0] = -m[2] / ctx->rho;
+            grad_mat[1] = m[0];
+            grad_mat[2] = m[1];
+        }
+        return BEM_OK;
+    });
+}
+
 struct bem_batch {
     bem_ctx* ctx = nullptr;
     std::vector<bem_op*> ops;

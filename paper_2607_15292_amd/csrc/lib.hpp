@@ -59,4 +59,13 @@ void launch_dense_apply(const zd* A, int M, int L, int nrhs, const zd* x, int64_
                         hipStream_t st);
 void launch_dense_weighted(const zd* A, int M, int L, const zd* W, zd* y, hipStream_t st);
 
+// ---------------------------------------------------------------- matrix-free (adjoint.hip)
+// y = A(s_l) x (transpose: A(s_l)^T x) for every l with entries recomputed; mesh order
+// [nrhs][L][3K]
+void launch_mf_apply(const DevCtx& c, int op, bool transpose, int nrhs, const zd* x, zd* y, hipStream_t st);
+size_t adjoint_work_doubles(int K);
+void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double h_rel, const Mat<double>& Mp1,
+                      const Mat<double>& Mm1, double h1, const Mat<double>& Mp2, const Mat<double>& Mm2, double h2,
+                      double* work, double** sums, double** tiles, int* ntiles, double** self_out, hipStream_t st);
+
 }  // namespace bem
