@@ -16,7 +16,8 @@ mixed vs FP64 speedup, the relative error against the FP64 oracle on sampled row
 roofline of the compression kernel and the oracle's CPU throughput; apart from value, a
 solve leg (GMRES with refinement at every contour point) and a batched-product leg (the
 single layers of four cube and sphere meshes, 128 contour points, 32 right-hand sides, one
-set of launches).
+set of launches) and an adjoint leg (gradient of a single-layer form on the sphere of 20480
+triangles with respect to all node coordinates and the material).
 """
 from __future__ import annotations
 
@@ -121,6 +122,42 @@ def batched_leg(args, dev, torch):
     return out
 
 
+def adjoint_leg(args, dev, torch):
+    """Adjoint of the single layer (reported apart from value): the gradient of
+    Re sum_l w_l^T V(s_l) x_l with respect to all node coordinates and rho, c_p, c_s, entries
+    recomputed (near rule off), and the matrix-free product, on the sphere of 20480 triangles
+    with 64 contour points."""
+    from paper_2607_15292_amd import binding as B
+    from paper_2607_15292_amd import workloads as W
+    X, T = W.icosphere(args.adjoint_level)
+    K, L = len(T), 64
+    s = W.bdf2_contour(L, 0.1)
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(1.0, 1.0, 0.5)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=False)
+    w = torch.tensor(W.random_rhs(70, (1, L, 3 * K)), device=dev)
+    x = torch.tensor(W.random_rhs(71, (1, L, 3 * K)), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    val, gn, gm = c.adjoint_v(w, x)
+    t1 = time.perf_counter()
+    y = c.apply_mf(B.OP_V, x)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log("adjoint: K %d L %d: gradient %.2f s, matrix-free product %.2f s" % (K, L, t1 - t0, t2 - t1))
+    out = {"workload": "single layer on an icosphere of %d triangles, %d BDF2 gCQ points, near rule off, one "
+                       "right-hand side; gradient of Re sum_l w_l^T V(s_l) x_l w.r.t. %d node coordinates and "
+                       "rho, c_p, c_s" % (K, L, 3 * len(X)),
+           "gradient_seconds": t1 - t0, "pair_freqs_per_s": K * K * L / (t1 - t0),
+           "matrix_free_product_seconds": t2 - t1, "matrix_free_entries_per_s": K * K * L / (t2 - t1),
+           "grad_norm_nodes": float(np.linalg.norm(gn)), "grad_mat": [float(v) for v in gm]}
+    del w, x, y
+    c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +176,8 @@ def main():
     ap.add_argument("--solve-tol", type=float, default=1e-6)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-product leg (reported apart from value)")
     ap.add_argument("--batch-nrhs", type=int, default=32)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg (reported apart from value)")
+    ap.add_argument("--adjoint-level", type=int, default=5, help="icosphere level of the adjoint leg (5: 20480 triangles)")
     ap.add_argument("--batch-freqs", type=int, default=128)
     ap.add_argument("--batch-eps", type=float, default=1e-7,
                     help="3D-ACA tolerance of the batched leg (1e-6 leaves 2.5e-4 at the largest |s_l| of L = 128)")
@@ -282,6 +321,7 @@ def main():
     c.close()
     torch.cuda.empty_cache()
     batched = None if args.no_batch else batched_leg(args, dev, torch)
+    adjoint = None if args.no_adjoint else adjoint_leg(args, dev, torch)
 
     # roofline of the dominant compression kernel: algorithmic flops over event-timed device
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
@@ -361,6 +401,7 @@ def main():
         "roofline_next": roofline_next,
         "solve": solve,
         "batched": batched,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     if fp64:
