@@ -358,6 +358,23 @@ int bem_batch_info_get(const bem_batch *b, bem_batch_info *info);
 /* Releases a batch (its plan, workspace and graph). */
 int bem_batch_destroy(bem_batch *b);
 
+/* Time stepping of the Dirichlet problem (Sec. 2.4) by convolution quadrature on uniform
+ * steps with the BDF2 generating function delta(z) = 3/2 - 2 z + z^2/2: the contour points of
+ * the context must be s_l = delta(z_l)/dt, z_l = R exp(2 pi i l / L) (BEM_ERR_FREQ
+ * otherwise).  The CQ weights omega_k(A) = R^-k / L sum_l A(s_l) exp(-2 pi i k l / L) are never
+ * formed: at step n the history sum_{j<n} omega_{n-j}(V) t_j equals sum_l V(s_l) W_l with
+ * W_l = 1/L sum_{j<n} z_l^{-(n-j)} t_j, one weighted sum of eq. (3DacaMult) (the structure of
+ * eq. (gCQ)), and W_l follows the recurrence W_l <- z_l^-1 (W_l + t_n / L) (the role of the
+ * state update eq. (ODEsol)).  Each step solves omega_0(V) t_n = b_n - history by GMRES, the
+ * product of omega_0(V) = 1/L sum_l V(s_l) being a weighted sum with equal weights; the
+ * right-hand side is b_n = sum_{j<=n} omega_{n-j}(H) g_j (H = I/2 + K), or g_n when H is NULL.
+ *   V, H: dense or compressed operators of one context.  g: [N][3K] samples g(t_n),
+ *   t_n = n dt, n < N <= L, mesh order; t: [N][3K] tractions out; host or device per flags.
+ *   opts: tol, restart, max_iter, max_refine per step (inner_tol unused); stats: totals over
+ *   the steps (rel_residual: the worst step).  Returns BEM_OK or BEM_WARN_NOCONV. */
+int bem_cq_dirichlet(bem_op *V, bem_op *H, int32_t N, double dt, double R, const void *g, void *t, int32_t flags,
+                     const bem_solve_opts *opts, bem_solve_stats *stats);
+
 /* Per-block description of a compressed operator for tests and reports:
  * rows (int64 x 8 per block): row_begin, row_size, col_begin, col_size (cluster order),
  * is_far, rank, dense_fallback, aca_cols_total.  perm: [K] int32, cluster position ->

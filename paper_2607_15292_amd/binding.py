@@ -112,6 +112,9 @@ _SIGS = {
     "bem_apply_weighted": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "bem_solve": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(bem_solve_opts),
                                  ctypes.POINTER(bem_solve_stats)]),
+    "bem_cq_dirichlet": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P,
+                                        ctypes.c_int32, ctypes.POINTER(bem_solve_opts),
+                                        ctypes.POINTER(bem_solve_stats)]),
     "bem_apply_mf": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "bem_adjoint_v": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]),
     "bem_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -398,6 +401,28 @@ class Operator:
         d = st.as_dict()
         d["rc"] = rc
         return x, d
+
+    def cq_dirichlet(self, g, dt, R, H=None, t=None, tol=1e-8, restart=30, max_iter=500, max_refine=10):
+        """Tractions t[n] of the Dirichlet problem in time by BDF2 convolution quadrature
+        (marching on in time with weighted-sum histories); g: [N, 3K] samples at t_n = n dt.
+        Returns (t, stats dict)."""
+        N = g.shape[0]
+        if _is_torch(g):
+            import torch
+            if t is None:
+                t = torch.empty_like(g)
+            self.ctx._sync_torch_stream()
+        elif t is None:
+            t = np.empty_like(g)
+        pg, fl = _ptr(g)
+        pt, _ = _ptr(t)
+        o = bem_solve_opts(float(tol), 1e-3, int(restart), int(max_iter), int(max_refine), 0)
+        st = bem_solve_stats()
+        rc = self.ctx._check(lib().bem_cq_dirichlet(self.h, H.h if H is not None else None, int(N), float(dt),
+                                                    float(R), pg, pt, fl, ctypes.byref(o), ctypes.byref(st)))
+        d = st.as_dict()
+        d["rc"] = rc
+        return t, d
 
     def apply_weighted(self, W, y=None):
         K = self.ctx.K

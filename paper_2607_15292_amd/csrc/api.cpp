@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 #include "host.hpp"
@@ -786,6 +787,109 @@ int bem_op_freq_hist(const bem_op* op, int64_t* hist)
     }
     compressed_freq_hist(op, hist);
     return BEM_OK;
+}
+
+namespace {
+
+// y = sum_l A(s_l) W[l] on device buffers (W: [L][3K], y: [3K])
+void op_apply_weighted(bem_op* op, const zd* W, zd* y, hipStream_t st)
+{
+    if (op->kind == 0) launch_dense_weighted(op->dense.as<zd>(), 3 * op->K, op->L, W, y, st);
+    else apply_weighted_compressed(op, W, y, st);
+}
+
+}  // namespace
+
+int bem_cq_dirichlet(bem_op* V, bem_op* H, int32_t N, double dt, double R, const void* g, void* t, int32_t flags,
+                     const bem_solve_opts* opts, bem_solve_stats* stats)
+{
+    if (!V) return BEM_ERR_ARG;
+    bem_ctx* ctx = V->ctx;
+    return guarded(ctx, [&]() -> int {
+        const auto t0 = std::chrono::steady_clock::now();
+        const int L = V->L, K = V->K;
+        if (!g || !t || N < 1 || N > L) throw api_error(BEM_ERR_ARG, "need buffers and 1 <= N <= L");
+        if (H && (H->ctx != ctx || H->K != K || H->L != L)) throw api_error(BEM_ERR_ARG, "H of another context or size");
+        if (!(dt > 0.0) || !(R > 0.0 && R < 1.0)) throw api_error(BEM_ERR_ARG, "need dt > 0 and 0 < R < 1");
+        if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_cq_dirichlet");
+        // the contour points must be the BDF2 ones: s_l = delta(z_l) / dt, z_l = R exp(2 pi i l / L)
+        std::vector<zd> zinv(L);
+        for (int l = 0; l < L; ++l) {
+            const std::complex<double> z = std::polar(R, 2.0 * M_PI * l / L);
+            const std::complex<double> sl = (1.5 - 2.0 * z + 0.5 * z * z) / dt, sc(ctx->s[l].re, ctx->s[l].im);
+            if (std::abs(sl - sc) > 1e-9 * std::abs(sl))
+                throw api_error(BEM_ERR_FREQ, "contour point " + std::to_string(l) + " is not delta(z_l)/dt of BDF2");
+            const std::complex<double> zi = 1.0 / z;
+            zinv[l] = {zi.real(), zi.imag()};
+        }
+        bem::SolveParams p;
+        if (opts) {
+            if (!(opts->tol > 0.0) || opts->restart < 1 || opts->max_iter < 1)
+                throw api_error(BEM_ERR_ARG, "solve options out of range");
+            p.tol = opts->tol;
+            p.restart = opts->restart;
+            p.max_iter = opts->max_iter;
+            p.max_refine = opts->max_refine;
+        }
+        p.inner_tol = 0.0;  // the inner operator is the fine one
+        need_device(ctx);
+        const bool dev = (flags & BEM_DEVICE_PTR) != 0;
+        const size_t M = 3 * (size_t)K;
+        const size_t bytes = (size_t)N * M * sizeof(zd);
+        hipStream_t st = ctx->stream;
+        Staged sg, stt;
+        stage_in(sg, g, bytes, dev, st);
+        stage_out(stt, t, bytes, dev);
+        DevBuf wt, wg, tmp, tmp2, vb, zb;
+        wt.alloc((size_t)L * M * sizeof(zd));
+        wg.alloc((size_t)L * M * sizeof(zd));
+        tmp.alloc((size_t)L * M * sizeof(zd));
+        tmp2.alloc((size_t)L * M * sizeof(zd));
+        vb.alloc(3 * M * sizeof(zd));
+        zb.alloc((size_t)L * sizeof(zd));
+        BEM_HIP_TRY(hipMemsetAsync(wt.p, 0, (size_t)L * M * sizeof(zd), st));
+        BEM_HIP_TRY(hipMemsetAsync(wg.p, 0, (size_t)L * M * sizeof(zd), st));
+        BEM_HIP_TRY(hipMemcpyAsync(zb.p, zinv.data(), (size_t)L * sizeof(zd), hipMemcpyHostToDevice, st));
+        zd* b = vb.as<zd>();
+        zd* h = b + M;
+        zd* rhs = h + M;
+        const zd* gd = (const zd*)sg.dev;
+        zd* td = (zd*)stt.dev;
+        const double invL = 1.0 / L;
+        // omega_0(V) x = sum_l V(s_l) x / L
+        bem::DevApply A0 = [&](const zd* in, zd* out) {
+            launch_cq_fill(tmp2.as<zd>(), nullptr, in, invL, L, (int)M, st);
+            op_apply_weighted(V, tmp2.as<zd>(), out, st);
+        };
+        bem_solve_stats S{};
+        S.converged = 1;
+        for (int n = 0; n < N; ++n) {
+            const zd* gn = gd + (size_t)n * M;
+            zd* tn = td + (size_t)n * M;
+            // b_n = sum_{j <= n} omega_{n-j}(H) g_j = sum_l H(s_l) (Wg[l] + g_n / L)
+            if (H) {
+                launch_cq_fill(tmp.as<zd>(), wg.as<zd>(), gn, invL, L, (int)M, st);
+                op_apply_weighted(H, tmp.as<zd>(), b, st);
+            } else {
+                BEM_HIP_TRY(hipMemcpyAsync(b, gn, M * sizeof(zd), hipMemcpyDeviceToDevice, st));
+            }
+            // history sum_{j < n} omega_{n-j}(V) t_j = sum_l V(s_l) Wt[l] (eq. (3DacaMult))
+            op_apply_weighted(V, wt.as<zd>(), h, st);
+            launch_axpby(rhs, 1.0, b, -1.0, h, M, st);
+            const bem::SolveResult r = bem::gmres_refine(A0, A0, (int)M, 1, rhs, tn, p, st);
+            S.iterations += r.iterations;
+            S.refinements += r.refinements;
+            S.rel_residual = std::max(S.rel_residual, r.rel_residual);
+            if (!r.converged) S.converged = 0;
+            launch_cq_update(wt.as<zd>(), tn, zb.as<zd>(), invL, L, (int)M, st);
+            if (H) launch_cq_update(wg.as<zd>(), gn, zb.as<zd>(), invL, L, (int)M, st);
+        }
+        finish_out(stt, t, bytes, dev, st);
+        BEM_HIP_TRY(hipStreamSynchronize(st));
+        S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats) *stats = S;
+        return S.converged ? BEM_OK : BEM_WARN_NOCONV;
+    });
 }
 
 int bem_apply_mf(bem_ctx* ctx, int32_t op, int32_t transpose, int32_t nrhs, const void* x, void* y, int32_t flags)

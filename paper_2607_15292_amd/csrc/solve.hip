@@ -76,9 +76,38 @@ __global__ __launch_bounds__(WS) void k_axpby(zd* z, double a, const zd* x, doub
     z[q] = x[q] * a + y[q] * b;
 }
 
+// out[l][m] = (W ? W[l][m] : 0) + a v[m] for l < L
+__global__ __launch_bounds__(WS) void k_cq_fill(zd* out, const zd* W, const zd* v, double a, int L, int M)
+{
+    const size_t q = (size_t)blockIdx.x * WS + threadIdx.x;
+    if (q >= (size_t)L * M) return;
+    const zd t = v[q % M] * a;
+    out[q] = W ? W[q] + t : t;
+}
+
+// W[l][m] = zinv[l] (W[l][m] + a v[m]): one step of the history recurrence
+__global__ __launch_bounds__(WS) void k_cq_update(zd* W, const zd* v, const zd* zinv, double a, int L, int M)
+{
+    const size_t q = (size_t)blockIdx.x * WS + threadIdx.x;
+    if (q >= (size_t)L * M) return;
+    W[q] = zinv[q / M] * (W[q] + v[q % M] * a);
+}
+
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + WS - 1) / WS); }
 
 }  // namespace
+
+void launch_cq_fill(zd* out, const zd* W, const zd* v, double a, int L, int M, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cq_fill, dim3(blocks_for((size_t)L * M)), dim3(WS), 0, st, out, W, v, a, L, M);
+    BEM_HIP_TRY(hipGetLastError());
+}
+
+void launch_cq_update(zd* W, const zd* v, const zd* zinv, double a, int L, int M, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cq_update, dim3(blocks_for((size_t)L * M)), dim3(WS), 0, st, W, v, zinv, a, L, M);
+    BEM_HIP_TRY(hipGetLastError());
+}
 
 void launch_dots(const zd* V, size_t vstride, int nvec, const zd* w, int N, int ncols, zd* out, hipStream_t st)
 {

@@ -18,6 +18,11 @@ void launch_scale_cols(zd* dst, const zd* src, const double* scale, int N, int n
 // z = a x + b y over n entries
 void launch_axpby(zd* z, double a, const zd* x, double b, const zd* y, size_t n, hipStream_t st);
 
+// convolution quadrature in time: out[l] = W[l] + a v (W may be null), and the history
+// recurrence W[l] = zinv[l] (W[l] + a v), over L rows of M entries
+void launch_cq_fill(zd* out, const zd* W, const zd* v, double a, int L, int M, hipStream_t st);
+void launch_cq_update(zd* W, const zd* v, const zd* zinv, double a, int L, int M, hipStream_t st);
+
 // y = A x on device buffers [ncols][N]
 using DevApply = std::function<void(const zd* x, zd* y)>;
 
