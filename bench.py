@@ -16,8 +16,9 @@ mixed vs FP64 speedup, the relative error against the FP64 oracle on sampled row
 roofline of the compression kernel and the oracle's CPU throughput; apart from value, a
 solve leg (GMRES with refinement at every contour point) and a batched-product leg (the
 single layers of four cube and sphere meshes, 128 contour points, 32 right-hand sides, one
-set of launches) and an adjoint leg (gradient of a single-layer form on the sphere of 20480
-triangles with respect to all node coordinates and the material).
+set of launches), an adjoint leg (gradient of a single-layer form on the sphere of 20480
+triangles with respect to all node coordinates and the material) and a time-stepping leg
+(the pulsating sphere over 64 BDF2 convolution-quadrature steps).
 """
 from __future__ import annotations
 
@@ -158,6 +159,56 @@ def adjoint_leg(args, dev, torch):
     return out
 
 
+def timestep_leg(args, dev, torch):
+    """Time stepping (reported apart from value): the pulsating sphere of the metric's
+    workload in the time domain, N = 64 steps of BDF2 convolution quadrature with the mixed
+    V and I/2 + K; error against the convolution quadrature of the closed-form traction."""
+    from oracle import cq
+    from paper_2607_15292_amd import binding as B
+    from paper_2607_15292_amd import workloads as W
+    X, T, s = workload(args.level, args.freqs)
+    L, dt = len(s), 0.1
+    R = 1e-10 ** (1.0 / (2 * L))
+    K = len(T)
+    C = X[T].mean(axis=1)
+    nrm = np.cross(X[T[:, 1]] - X[T[:, 0]], X[T[:, 2]] - X[T[:, 0]])
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    a = 2.5
+    Gs = a ** 4 * 24.0 / (s + a) ** 5
+    U = np.empty((L, 3 * K), dtype=np.complex128)
+    Tr = np.empty_like(U)
+    for l in range(L):
+        u, tr = W.pulsating_sphere(C, nrm, s[l], a=a)
+        U[l], Tr[l] = u.ravel() / Gs[l], tr.ravel() / Gs[l]
+    tn = dt * np.arange(L)
+    phi = ((a * tn) ** 4 * np.exp(-a * tn))[:, None] * np.ones((1, 3 * K))
+    g = cq.convolve(cq.weights(U, R), phi)
+    t_ref = cq.convolve(cq.weights(Tr, R), phi)
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(1.0, 1.0, 0.5)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=True)
+    V = c.compress(B.OP_V, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED)
+    H = c.compress(B.OP_HK, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED)
+    gd = torch.tensor(g, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    td, st = V.cq_dirichlet(gd, dt, R, H=H, tol=1e-6)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    err = float(np.abs(td.cpu().numpy() - t_ref).max() / np.abs(t_ref).max())
+    log("time stepping: %d steps in %.2f s, %d GMRES products, error %.3e" % (L, t1 - t0, st["iterations"], err))
+    out = {"workload": "pulsating sphere, icosphere %d triangles, %d BDF2 convolution-quadrature steps (dt %.2f), "
+                       "mixed V and I/2+K at eps %.0e, GMRES to 1e-6 per step" % (K, L, dt, args.eps),
+           "seconds": t1 - t0, "steps_per_s": L / (t1 - t0), "gmres_products": st["iterations"],
+           "max_rel_err_vs_cq_of_closed_form": err, "converged": bool(st["converged"])}
+    V.destroy()
+    H.destroy()
+    c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +228,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-product leg (reported apart from value)")
     ap.add_argument("--batch-nrhs", type=int, default=32)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg (reported apart from value)")
+    ap.add_argument("--no-timestep", action="store_true", help="skip the time-stepping leg (reported apart from value)")
     ap.add_argument("--adjoint-level", type=int, default=5, help="icosphere level of the adjoint leg (5: 20480 triangles)")
     ap.add_argument("--batch-freqs", type=int, default=128)
     ap.add_argument("--batch-eps", type=float, default=1e-7,
@@ -322,6 +374,7 @@ def main():
     torch.cuda.empty_cache()
     batched = None if args.no_batch else batched_leg(args, dev, torch)
     adjoint = None if args.no_adjoint else adjoint_leg(args, dev, torch)
+    timestep = None if args.no_timestep else timestep_leg(args, dev, torch)
 
     # roofline of the dominant compression kernel: algorithmic flops over event-timed device
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
@@ -402,6 +455,7 @@ def main():
         "solve": solve,
         "batched": batched,
         "adjoint": adjoint,
+        "timestep": timestep,
         "cpu_baseline": cpu,
     }
     if fp64:

@@ -227,6 +227,8 @@ struct BatchPermTable {
 void launch_permute_batch(const BatchPermTable& T, int kmax, zd* work, bool to_cluster, hipStream_t st);
 void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nrhs, int64_t in_l_stride, bool to_cluster,
                     hipStream_t st);
-void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t st);
+// uniform: W is one vector x [3K] standing for W_l = scale x at every l
+void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t st, bool uniform = false,
+                     double scale = 1.0);
 
 }  // namespace bem

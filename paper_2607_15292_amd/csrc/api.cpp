@@ -858,8 +858,12 @@ int bem_cq_dirichlet(bem_op* V, bem_op* H, int32_t N, double dt, double R, const
         const double invL = 1.0 / L;
         // omega_0(V) x = sum_l V(s_l) x / L
         bem::DevApply A0 = [&](const zd* in, zd* out) {
-            launch_cq_fill(tmp2.as<zd>(), nullptr, in, invL, L, (int)M, st);
-            op_apply_weighted(V, tmp2.as<zd>(), out, st);
+            if (V->kind == 1) {
+                apply_sum_compressed(V, in, invL, out, st);
+            } else {
+                launch_cq_fill(tmp2.as<zd>(), nullptr, in, invL, L, (int)M, st);
+                op_apply_weighted(V, tmp2.as<zd>(), out, st);
+            }
         };
         bem_solve_stats S{};
         S.converged = 1;

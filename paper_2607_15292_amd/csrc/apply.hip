@@ -276,14 +276,105 @@ __global__ __launch_bounds__(256) void k_reduce_rows(ApplyArgs A, int ncols, zd*
     }
 }
 
-// zw[face][3j + c] = sum_l (f[l] W_l[J])_c  (the fibre contraction of eq. (3DacaMult))
+// One column (the weighted sum): the products are matrix-vector products bound by the HBM
+// reads of the stored faces, so they run without the column tiles of the general kernels.
+
+__device__ __forceinline__ zd wsum_z(zd v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        v.re += __shfl_xor(v.re, o, 64);
+        v.im += __shfl_xor(v.im, o, 64);
+    }
+    return v;
+}
+
+// far faces: T[t] = sum_k conj(Vbar[k][t]) z[k] with z the face's contracted vector; one
+// workgroup per face, waves over k, lanes over t (t and t + 64)
+__global__ __launch_bounds__(256) void k_far_vec(ApplyArgs A, const int* far_list, const zd* zw_all)
+{
+    __shared__ zd part[4][KMAXF];
+    const ApplyFace F = A.faces[far_list[blockIdx.x]];
+    const BlockIn B = A.blocks[F.block];
+    const int kk = F.kk, nk = 3 * B.cs, m = B.rs;
+    const zd* z = zw_all + F.zw_off;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    zd a0 = {0.0, 0.0}, a1 = {0.0, 0.0};
+    for (int k = wv; k < nk; k += 4) {
+        const zd zk = z[k];
+        const size_t o = (size_t)3 * m * kk + (size_t)k * kk;
+        if (F.fp32) {
+            const zf* V = (const zf*)(A.pool + F.face_off) + o;
+            if (lane < kk) a0 = fma_c(conj(ldz(V + lane)), zk, a0);
+            if (lane + 64 < kk) a1 = fma_c(conj(ldz(V + lane + 64)), zk, a1);
+        } else {
+            const zd* V = (const zd*)(A.pool + F.face_off) + o;
+            if (lane < kk) a0 = fma_c(conj(V[lane]), zk, a0);
+            if (lane + 64 < kk) a1 = fma_c(conj(V[lane + 64]), zk, a1);
+        }
+    }
+    part[wv][lane] = a0;
+    if (lane + 64 < KMAXF) part[wv][lane + 64] = a1;
+    __syncthreads();
+    if (threadIdx.x < kk) {
+        zd sum = {0.0, 0.0};
+        for (int w = 0; w < 4; ++w) sum += part[w][threadIdx.x];
+        A.tbuf[F.t_off + threadIdx.x] = sum;
+    }
+}
+
+// rows: segment sg of a row chunk; wave wv owns the rows wv, wv + 4, ... of the chunk's
+// 3 rsz rows, lanes run along the face's columns (dense face: the contracted vector,
+// factors: T); partial rows to pbuf, summed by k_reduce_rows
+__global__ __launch_bounds__(256) void k_rows_vec(ApplyArgs A, const zd* zw_all)
+{
+    constexpr int RPW = 3 * RCE / 4;
+    const int sg = blockIdx.x, g = A.seg_group[sg];
+    const int rs0 = A.row_start[g], nrow = 3 * A.row_size[g];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    zd acc[RPW];
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) acc[u] = {0.0, 0.0};
+    for (int q = A.seg_begin[sg]; q < A.seg_begin[sg + 1]; ++q) {
+        const ApplyFace F = A.faces[A.row_faces[q]];
+        if (F.kk < 0) continue;
+        const BlockIn B = A.blocks[F.block];
+        const int ioff = rs0 - B.rb;
+        const zd* z = F.kk == 0 ? zw_all + F.zw_off : A.tbuf + F.t_off;
+        const int ncol = F.kk == 0 ? 3 * B.cs : F.kk;
+        for (int c0 = 0; c0 < ncol; c0 += 64) {
+            const int c = c0 + lane;
+            if (c >= ncol) continue;
+            const zd zc = z[c];
+#pragma unroll
+            for (int u = 0; u < RPW; ++u) {
+                const int r = wv + 4 * u;
+                if (r < nrow) {
+                    const size_t o = (size_t)(3 * ioff + r) * ncol + c;
+                    const zd h = F.fp32 ? ldz((const zf*)(A.pool + F.face_off) + o) : ((const zd*)(A.pool + F.face_off))[o];
+                    acc[u] = fma_c(h, zc, acc[u]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+        const zd sv = wsum_z(acc[u]);
+        const int r = wv + 4 * u;
+        if (lane == 0 && r < nrow) A.pbuf[(size_t)sg * 3 * RCE + r] = sv;
+    }
+}
+
+// zw[face][3j + c] = sum_l (f[l] W_l[J])_c  (the fibre contraction of eq. (3DacaMult)); one
+// wavefront per face, four faces per workgroup, lanes over the block's column elements
 __global__ __launch_bounds__(256) void k_contract(ApplyArgs A, const zd* W, zd* zw_all)
 {
-    int fi = blockIdx.x;
+    const int fi = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (fi >= A.nfaces) return;
     const ApplyFace F = A.faces[fi];
     const BlockIn B = A.blocks[F.block];
     zd* zw = zw_all + F.zw_off;
-    for (int j = threadIdx.x; j < B.cs; j += 256) {
+    for (int j = lane; j < B.cs; j += 64) {
         zd s[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
         for (int l = 0; l < A.L; ++l) {
             if (F.sel && l != F.ksel) continue;
@@ -301,6 +392,41 @@ __global__ __launch_bounds__(256) void k_contract(ApplyArgs A, const zd* W, zd* 
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) zw[3 * (size_t)j + c] = s[c];
+    }
+}
+
+// The same with one vector for every frequency (W_l = a x): zw = a (sum_l f[l]) x[J], the
+// fibre sum taken once per face; one wavefront per face.
+__global__ __launch_bounds__(256) void k_contract_sum(ApplyArgs A, const zd* x, double a, zd* zw_all)
+{
+    __shared__ zd Fb[4][9];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int fi = blockIdx.x * 4 + wv;
+    const bool act = fi < A.nfaces;
+    const ApplyFace F = A.faces[act ? fi : 0];
+    if (lane < 9) {
+        zd sum = {0.0, 0.0};
+        if (act) {
+            if (F.sel) {
+                sum = (lane == 0 || lane == 4 || lane == 8) ? zd{1.0, 0.0} : zd{0.0, 0.0};
+            } else {
+                const zd* fib = (const zd*)(A.pool + F.fib_off);
+                for (int l = 0; l < A.L; ++l) sum += fib[(size_t)l * 9 + lane];
+            }
+        }
+        Fb[wv][lane] = sum * a;
+    }
+    __syncthreads();
+    if (!act) return;
+    const BlockIn B = A.blocks[F.block];
+    zd* zw = zw_all + F.zw_off;
+    for (int j = lane; j < B.cs; j += 64) {
+        const zd* w = x + 3 * (size_t)(B.cb + j);
+        const zd v[3] = {w[0], w[1], w[2]};
+        zd z[3];
+        mul3(Fb[wv], v, z);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) zw[3 * (size_t)j + c] = z[c];
     }
 }
 
@@ -399,18 +525,20 @@ void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs)
     BEM_HIP_TRY(hipGetLastError());
 }
 
-// W in cluster order [L][3K]; zw: [nfaces][3K] workspace; y in cluster order [3K].
-void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t st)
+// W in cluster order [L][3K] (uniform: one vector [3K] used as a W for every l); zw:
+// [nfaces][3K] workspace; y in cluster order [3K].
+void launch_weighted(const ApplyArgs& A, const zd* W, zd* zw, zd* y, hipStream_t st, bool uniform, double scale)
 {
     if (A.nfaces > 0) {
-        hipLaunchKernelGGL(k_contract, dim3(A.nfaces), dim3(256), 0, st, A, W, zw);
+        if (uniform) hipLaunchKernelGGL(k_contract_sum, dim3((A.nfaces + 3) / 4), dim3(256), 0, st, A, W, scale, zw);
+        else hipLaunchKernelGGL(k_contract, dim3((A.nfaces + 3) / 4), dim3(256), 0, st, A, W, zw);
         BEM_HIP_TRY(hipGetLastError());
     }
     if (A.nfar > 0) {
-        hipLaunchKernelGGL((k_far_products<true>), dim3(A.nfar, 1), dim3(WGA), 0, st, A, A.far_list, zw, 1);
+        hipLaunchKernelGGL(k_far_vec, dim3(A.nfar), dim3(256), 0, st, A, A.far_list, zw);
         BEM_HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_rows<true>), dim3(A.nseg), dim3(WGA), 0, st, A, zw, 1, A.nseg);
+    hipLaunchKernelGGL(k_rows_vec, dim3(A.nseg), dim3(256), 0, st, A, zw);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_reduce_rows<true>), dim3(A.nrow_groups, (3 * RCE + 255) / 256), dim3(256), 0, st, A, 1, y);
     BEM_HIP_TRY(hipGetLastError());

@@ -783,6 +783,27 @@ void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream
     launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, 1, 1, (int64_t)M, false, st);
 }
 
+void apply_sum_compressed(bem_op* op, const zd* x_dev, double scale, zd* y_dev, hipStream_t st)
+{
+    CompressedOp& C = *op->comp;
+    const size_t M = 3 * (size_t)C.K;
+    const size_t prow = (size_t)3 * APPLY_ROW_CHUNK;
+    size_t need = (2 * M + (size_t)C.zw_total + (size_t)C.far_rows + (size_t)C.nseg * prow + 16) * sizeof(zd);
+    if (C.work.bytes < need) C.work.alloc(need);
+    zd* xp = C.work.as<zd>();
+    zd* yp = xp + M;
+    zd* zw = yp + M;
+    zd* tb = zw + C.zw_total;
+    launch_permute(x_dev, xp, C.perm_dev.as<int>(), C.K, 1, 1, (int64_t)M, true, st);
+    ApplyArgs A = plan_args(C, 1);
+    A.x = xp;
+    A.y = yp;
+    A.tbuf = tb;
+    A.pbuf = tb + C.far_rows;
+    launch_weighted(A, xp, zw, yp, st, true, scale);
+    launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, 1, 1, (int64_t)M, false, st);
+}
+
 void compressed_blocks(const bem_op* op, int64_t* n, int64_t* rows, int32_t* perm)
 {
     const CompressedOp& C = *op->comp;
