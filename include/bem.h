@@ -77,6 +77,8 @@ typedef struct bem_op bem_op;
 /* flags */
 #define BEM_DEVICE_PTR 1   /* buffers are device pointers */
 #define BEM_SHARED_X 2     /* bem_apply: x has shape [nrhs][3K], the same for every frequency */
+#define BEM_TRANSPOSE 4    /* bem_apply, bem_solve: the plain transpose A(s_l)^T (no conjugation);
+                              the adjoint of a solution needs A^T solves */
 
 /* Quadrature options (Sec. 2.3: Duffy for the singular collocation integrals; the rest is
  * this library's documented reading).  regular pairs: 7-point degree-5 rule; near pairs
@@ -233,7 +235,9 @@ int bem_op_stats(const bem_op *op, bem_stats *st);
  * y[r][l] = A(s_l) x[r][l] for r < nrhs and every l, where A is the dense or compressed
  * operator.  x, y: [nrhs][L][3K] complex128 (complex64 is not accepted: the product
  * accumulates near field in complex128 and converts far-field partial sums).  With
- * BEM_SHARED_X, x is [nrhs][3K] and used for every l.  x and y must not overlap. */
+ * BEM_SHARED_X, x is [nrhs][3K] and used for every l.  With BEM_TRANSPOSE, y = A(s_l)^T x
+ * (the fibre of each face applied on the output side; not with BEM_SHARED_X).  x and y must
+ * not overlap. */
 int bem_apply(bem_op *op, int32_t nrhs, const void *x, void *y, int32_t flags);
 
 /* gCQ weighted sum (eq. (gCQ) / eq. (3DacaMult)): y = sum_l A(s_l) W[l], computed as
@@ -274,6 +278,8 @@ typedef struct bem_solve_stats {
  * d to x, then takes the residual r = b - A x with A.  A cheap inner operator (e.g. the
  * mixed-precision compression) with an accurate fine one (FP64 at a tighter eps) gives the
  * fine operator's accuracy at mostly inner-operator cost.
+ *   With BEM_TRANSPOSE in flags the systems are A(s_l)^T x = b (the adjoint solves of a
+ *   gradient).
  *   A, A_inner: operators of the same context, K and L (dense or compressed; A_inner may
  *   be NULL).  b, x: [nrhs][L][3K] complex128, mesh order, host or device per flags; x is
  *   overwritten (zero initial guess).  stats may be NULL.  Returns BEM_OK, BEM_WARN_NOCONV

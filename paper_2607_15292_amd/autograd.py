@@ -1,6 +1,7 @@
-"""Differentiable single-layer products: torch.autograd.Function over the library's matrix-free
-product and adjoint (bem_apply_mf, bem_adjoint_v).  Entries are recomputed in the forward
-and in the backward pass; nothing of the operator is stored.
+"""Differentiable single-layer products and solutions: torch.autograd.Function over the
+library's matrix-free product, transposed solves and adjoint (bem_apply_mf, bem_solve with
+BEM_TRANSPOSE, bem_adjoint_v).  The gradients recompute the entries; nothing of the
+operator is stored for them.
 
     y = single_layer(bem_ctx, nodes, material, x)
 
@@ -57,3 +58,42 @@ def single_layer(bem_ctx, nodes, material, x, tris):
     """y[r, l] = V(s_l) x[r, l], differentiable in nodes, material and x."""
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     return SingleLayer.apply(bem_ctx, tris, nodes, material, x)
+
+
+class SingleLayerSolve(torch.autograd.Function):
+    """t[r, l] = V(s_l)^{-1} b[r, l] by GMRES (bem_solve) with V assembled dense or compressed
+    in FP64 at eps; backward: one transposed solve V^T nu = conj(g_t) per call, then
+    g_b = conj(nu) and the node and material gradients are minus those of
+    Re sum nu^T V t (the adjoint kernel)."""
+
+    @staticmethod
+    def forward(fctx, bem_ctx, tris, nodes, material, b, tol, eps):
+        _load(bem_ctx, tris, nodes, material)
+        V = bem_ctx.assemble_dense(B.OP_V) if eps is None else bem_ctx.compress(B.OP_V, eps3d=eps, prec=B.PREC_F64)
+        t, _ = V.solve(b.contiguous(), tol=tol)
+        fctx.bem, fctx.tris, fctx.V, fctx.tol = bem_ctx, tris, V, tol
+        fctx.save_for_backward(nodes, material, t)
+        return t
+
+    @staticmethod
+    def backward(fctx, gt):
+        nodes, material, t = fctx.saved_tensors
+        bem, V = fctx.bem, fctx.V
+        nu, _ = V.solve(gt.conj().resolve_conj().contiguous(), tol=fctx.tol, transpose=True)
+        V.destroy()
+        fctx.V = None
+        _load(bem, fctx.tris, nodes, material)
+        g_nodes = g_mat = None
+        if fctx.needs_input_grad[2] or fctx.needs_input_grad[3]:
+            _, gn, gm = bem.adjoint_v(nu, t.contiguous())
+            g_nodes = -torch.as_tensor(gn, dtype=nodes.dtype, device=nodes.device)
+            g_mat = -torch.as_tensor(gm, dtype=material.dtype, device=material.device)
+        g_b = nu.conj() if fctx.needs_input_grad[4] else None
+        return None, None, g_nodes, g_mat, g_b, None, None
+
+
+def single_layer_solve(bem_ctx, nodes, material, b, tris, tol=1e-10, eps=None):
+    """t[r, l] = V(s_l)^{-1} b[r, l], differentiable in nodes, material and b; V dense
+    (eps None) or compressed in FP64 at eps.  The context's near rule must be off."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    return SingleLayerSolve.apply(bem_ctx, tris, nodes, material, b, tol, eps)

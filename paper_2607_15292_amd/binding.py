@@ -20,7 +20,7 @@ ERR_NAMES = {-1: "BEM_ERR_ARG", -2: "BEM_ERR_MESH", -3: "BEM_ERR_MATERIAL", -4: 
              -5: "BEM_ERR_STATE", -6: "BEM_ERR_HIP", -7: "BEM_ERR_NOMEM", -8: "BEM_ERR_NODEVICE"}
 OP_V, OP_K, OP_HK, OP_TABLE = 0, 1, 2, 3
 PREC_F64, PREC_MIXED = 0, 1
-DEVICE_PTR, SHARED_X = 1, 2
+DEVICE_PTR, SHARED_X, TRANSPOSE = 1, 2, 4
 
 _lib = None
 
@@ -363,8 +363,9 @@ class Operator:
         self.ctx._check(lib().bem_op_dense_copy(self.h, p, fl))
         return out
 
-    def apply(self, x, y=None, shared_x=False):
-        """y[r, l] = A(s_l) x[r, l]; x: [nrhs, L, 3K] (or [nrhs, 3K] with shared_x)."""
+    def apply(self, x, y=None, shared_x=False, transpose=False):
+        """y[r, l] = A(s_l) x[r, l] (A(s_l)^T with transpose); x: [nrhs, L, 3K] (or [nrhs, 3K]
+        with shared_x)."""
         K, L = self.ctx.K, self.ctx.L
         nrhs = x.shape[0]
         if _is_torch(x):
@@ -376,10 +377,12 @@ class Operator:
             y = np.empty((nrhs, L, 3 * K), dtype=np.complex128)
         px, fl = _ptr(x)
         py, _ = _ptr(y)
-        self.ctx._check(lib().bem_apply(self.h, int(nrhs), px, py, fl | (SHARED_X if shared_x else 0)))
+        self.ctx._check(lib().bem_apply(self.h, int(nrhs), px, py,
+                                        fl | (SHARED_X if shared_x else 0) | (TRANSPOSE if transpose else 0)))
         return y
 
-    def solve(self, b, x=None, inner=None, tol=1e-8, inner_tol=1e-3, restart=30, max_iter=500, max_refine=10):
+    def solve(self, b, x=None, inner=None, tol=1e-8, inner_tol=1e-3, restart=30, max_iter=500, max_refine=10,
+              transpose=False):
         """x[r, l] = A(s_l)^{-1} b[r, l] by GMRES with iterative refinement (bem_solve);
         inner: a cheaper operator of the same context for the inner GMRES runs.
         Returns (x, stats dict)."""
@@ -396,6 +399,7 @@ class Operator:
         px, _ = _ptr(x)
         o = bem_solve_opts(float(tol), float(inner_tol), int(restart), int(max_iter), int(max_refine), 0)
         st = bem_solve_stats()
+        fl |= TRANSPOSE if transpose else 0
         rc = self.ctx._check(lib().bem_solve(self.h, inner.h if inner is not None else None, int(nrhs), pb, px, fl,
                                              ctypes.byref(o), ctypes.byref(st)))
         d = st.as_dict()

@@ -205,6 +205,8 @@ constexpr int APPLY_SEGMENTS = 2048; // target number of row-kernel workgroups p
 // persistent_wgs > 0: the row kernel runs on at most that many workgroups, each striding
 // over the (segment, column tile) items
 void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs = 0);
+// y = A(s_l)^T x with a plan grouped by column chunks (row_start / row_size: column chunks)
+void launch_apply_t(const ApplyArgs& A, hipStream_t st);
 // workgroups of the row kernel that fit on one CU at once
 int apply_rows_occupancy();
 

@@ -639,6 +639,8 @@ int bem_apply(bem_op* op, int32_t nrhs, const void* x, void* y, int32_t flags)
         need_device(ctx);
         bool dev = (flags & BEM_DEVICE_PTR) != 0;
         bool shared = (flags & BEM_SHARED_X) != 0;
+        const bool trans = (flags & BEM_TRANSPOSE) != 0;
+        if (trans && shared) throw api_error(BEM_ERR_ARG, "BEM_TRANSPOSE with BEM_SHARED_X");
         size_t M = 3 * (size_t)op->K;
         size_t xb = (size_t)nrhs * (shared ? 1 : op->L) * M * sizeof(zd);
         size_t yb = (size_t)nrhs * op->L * M * sizeof(zd);
@@ -647,7 +649,11 @@ int bem_apply(bem_op* op, int32_t nrhs, const void* x, void* y, int32_t flags)
         stage_in(sx, x, xb, dev, st);
         stage_out(sy, y, yb, dev);
         int64_t xls = shared ? 0 : (int64_t)M;
-        if (op->kind == 0)
+        if (trans && op->kind == 0)
+            launch_dense_apply_t(op->dense.as<zd>(), (int)M, op->L, nrhs, (const zd*)sx.dev, (zd*)sy.dev, st);
+        else if (trans)
+            apply_compressed_t(op, nrhs, (const zd*)sx.dev, (zd*)sy.dev, st);
+        else if (op->kind == 0)
             launch_dense_apply(op->dense.as<zd>(), (int)M, op->L, nrhs, (const zd*)sx.dev, xls, (zd*)sy.dev, st);
         else
             apply_compressed(op, nrhs, (const zd*)sx.dev, xls, (zd*)sy.dev, st);
@@ -659,10 +665,14 @@ int bem_apply(bem_op* op, int32_t nrhs, const void* x, void* y, int32_t flags)
 namespace {
 
 // y = A x for [nrhs][L][3K] device buffers (mesh order)
-void op_apply(bem_op* op, int nrhs, const zd* x, zd* y, hipStream_t st)
+void op_apply(bem_op* op, int nrhs, const zd* x, zd* y, hipStream_t st, bool trans = false)
 {
     const size_t M = 3 * (size_t)op->K;
-    if (op->kind == 0)
+    if (trans && op->kind == 0)
+        launch_dense_apply_t(op->dense.as<zd>(), (int)M, op->L, nrhs, x, y, st);
+    else if (trans)
+        apply_compressed_t(op, nrhs, x, y, st);
+    else if (op->kind == 0)
         launch_dense_apply(op->dense.as<zd>(), (int)M, op->L, nrhs, x, (int64_t)M, y, st);
     else
         apply_compressed(op, nrhs, x, (int64_t)M, y, st);
@@ -699,8 +709,9 @@ int bem_solve(bem_op* A, bem_op* A_inner, int32_t nrhs, const void* b, void* x, 
         Staged sb, sx;
         stage_in(sb, b, bytes, dev, st);
         stage_out(sx, x, bytes, dev);
-        bem::DevApply fa = [&](const zd* in, zd* out) { op_apply(A, nrhs, in, out, st); };
-        bem::DevApply fi = [&](const zd* in, zd* out) { op_apply(A_inner, nrhs, in, out, st); };
+        const bool trans = (flags & BEM_TRANSPOSE) != 0;
+        bem::DevApply fa = [&](const zd* in, zd* out) { op_apply(A, nrhs, in, out, st, trans); };
+        bem::DevApply fi = [&](const zd* in, zd* out) { op_apply(A_inner, nrhs, in, out, st, trans); };
         const bool two = A_inner && A_inner != A;
         const bem::SolveResult R = bem::gmres_refine(fa, two ? fi : fa, (int)M, nrhs * A->L, (const zd*)sb.dev,
                                                      (zd*)sx.dev, p, st);

@@ -276,6 +276,157 @@ __global__ __launch_bounds__(256) void k_reduce_rows(ApplyArgs A, int ncols, zd*
     }
 }
 
+// ---------------------------------------------------------------- transposed products
+// y_l = A(s_l)^T x_l: block (J, I) of the transpose is sum_d (I (x) f_d[l]^T) H_d^T, the fibre
+// acting on the output side.  Factored faces: H^T = conj(Vbar) Ubar^T, so the far products
+// form T' = Ubar^T X (plain rows of x, no fibre) and the row kernel multiplies conj(Vbar).
+
+// T'[t][col] = sum_r Ubar[r][t] x[col][3 rb + r], r < 3m; thread = 3 ranks x 8 columns
+template <typename T>
+__device__ void far_products_face_t(const ApplyArgs& A, const ApplyFace& F, int ncols, int c0, zd (*Us)[KMAXF],
+                                    zd (*Zs)[NC])
+{
+    const BlockIn B = A.blocks[F.block];
+    const int m = B.rs, kk = F.kk;
+    const cx<T>* U = (const cx<T>*)(A.pool + F.face_off);
+    const int tr = threadIdx.x & 31, cg = threadIdx.x >> 5;
+    const size_t M = 3 * (size_t)A.K;
+    zd acc[3][8];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = {0.0, 0.0};
+    for (int k0 = 0; k0 < 3 * m; k0 += KTF) {
+        const int nk = min(KTF, 3 * m - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < KTF * kk; e += WGA) {
+            const int kr = e / kk, t = e - kr * kk;
+            Us[kr][t] = kr < nk ? ldz(U + (size_t)(k0 + kr) * kk + t) : zd{0.0, 0.0};
+        }
+        for (int e = threadIdx.x; e < KTF * NC; e += WGA) {
+            const int kr = e / NC, cl = e - kr * NC, col = c0 + cl;
+            Zs[kr][cl] = (kr < nk && col < ncols) ? A.x[(size_t)col * M + 3 * (size_t)B.rb + k0 + kr] : zd{0.0, 0.0};
+        }
+        __syncthreads();
+        for (int k = 0; k < nk; ++k) {
+            zd uu[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) uu[u] = tr + 32 * u < kk ? Us[k][tr + 32 * u] : zd{0.0, 0.0};
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const zd z = Zs[k][8 * cg + v];
+#pragma unroll
+                for (int u = 0; u < 3; ++u) acc[u][v] = fma_c(uu[u], z, acc[u][v]);
+            }
+        }
+    }
+    zd* Tout = A.tbuf + F.t_off * (size_t)ncols;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int t = tr + 32 * u;
+        if (t >= kk) continue;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int col = c0 + 8 * cg + v;
+            if (col < ncols) Tout[(size_t)t * ncols + col] = acc[u][v];
+        }
+    }
+}
+
+__global__ __launch_bounds__(WGA) void k_far_products_t(ApplyArgs A, const int* far_list, int ncols)
+{
+    __shared__ zd Us[KTF][KMAXF];
+    __shared__ zd Zs[KTF][NC];
+    const ApplyFace F = A.faces[far_list[blockIdx.x]];
+    const int c0 = blockIdx.y * NC;
+    if (F.fp32) far_products_face_t<float>(A, F, ncols, c0, Us, Zs);
+    else far_products_face_t<double>(A, F, ncols, c0, Us, Zs);
+}
+
+// Rows of the transpose: work item = (segment sg of a column chunk's faces, column tile).
+// Per face the product H^T x (or conj(Vbar) T') is accumulated apart and the face's fibre,
+// transposed, is applied per column before it joins the chunk's rows.
+__global__ __launch_bounds__(WGA) void k_rows_t(ApplyArgs A, int ncols, int nitems)
+{
+    __shared__ zd Hs[3 * RCE][KR + 1];
+    __shared__ zd Zs[KR][NC];
+    __shared__ zd Fs[NC][9];
+    const size_t M = 3 * (size_t)A.K;
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        const int tile = w / A.nseg, sg = w - tile * A.nseg, c0 = tile * NC;
+        const int g = A.seg_group[sg];
+        const int er = threadIdx.x >> 4, cq = threadIdx.x & 15;
+        const int cs0 = A.row_start[g], csz = A.row_size[g];
+        zd acc[3][4];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][v] = {0.0, 0.0};
+        for (int q = A.seg_begin[sg]; q < A.seg_begin[sg + 1]; ++q) {
+            const ApplyFace F = A.faces[A.row_faces[q]];
+            if (F.kk < 0) continue;
+            const BlockIn B = A.blocks[F.block];
+            const int m = B.rs, n = B.cs;
+            const int joff = cs0 - B.cb;  // first column element of the chunk inside the block
+            zd tmp[3][4];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) tmp[a][v] = {0.0, 0.0};
+            __syncthreads();
+            stage_fibres<false>(A, F, c0, ncols, Fs);
+            const int kin = F.kk == 0 ? 3 * m : F.kk;
+            for (int k0 = 0; k0 < kin; k0 += KR) {
+                const int nk = min(KR, kin - k0);
+                __syncthreads();
+                for (int e = threadIdx.x; e < 3 * RCE * KR; e += WGA) {
+                    const int kc = e / (3 * RCE), r = e - kc * (3 * RCE);
+                    zd h = {0.0, 0.0};
+                    if (r < 3 * csz && kc < nk) {
+                        if (F.kk == 0) {
+                            const size_t o = (size_t)(k0 + kc) * (3 * (size_t)n) + 3 * joff + r;
+                            h = F.fp32 ? ldz((const zf*)(A.pool + F.face_off) + o) : ((const zd*)(A.pool + F.face_off))[o];
+                        } else {
+                            const size_t o = (size_t)3 * m * F.kk + (size_t)(3 * joff + r) * F.kk + k0 + kc;
+                            h = conj(F.fp32 ? ldz((const zf*)(A.pool + F.face_off) + o) : ((const zd*)(A.pool + F.face_off))[o]);
+                        }
+                    }
+                    Hs[r][kc] = h;
+                }
+                for (int e = threadIdx.x; e < KR * NC; e += WGA) {
+                    const int kr = e / NC, cl = e - kr * NC, col = c0 + cl;
+                    zd z = {0.0, 0.0};
+                    if (kr < nk && col < ncols)
+                        z = F.kk == 0 ? A.x[(size_t)col * M + 3 * (size_t)B.rb + k0 + kr]
+                                      : A.tbuf[(F.t_off + k0 + kr) * (size_t)ncols + col];
+                    Zs[kr][cl] = z;
+                }
+                __syncthreads();
+                tile_mac<KR + 1>(Hs, Zs, nk, er, cq, tmp);
+            }
+            // acc[a][v] += sum_b f[l_v][b][a] tmp[b][v]
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const zd* f = Fs[cq + 16 * v];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) acc[a][v] = fma_c(f[3 * b + a], tmp[b][v], acc[a][v]);
+            }
+        }
+        if (er < csz) {
+            zd* pb = A.pbuf + (size_t)sg * 3 * RCE * ncols;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = c0 + cq + 16 * v;
+                if (col >= ncols) continue;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pb[(size_t)(3 * er + a) * ncols + col] = acc[a][v];
+            }
+        }
+    }
+}
+
 // One column (the weighted sum): the products are matrix-vector products bound by the HBM
 // reads of the stored faces, so they run without the column tiles of the general kernels.
 
@@ -519,6 +670,21 @@ void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs)
     if (items >= (1LL << 31)) throw std::invalid_argument("too many row work items");
     const unsigned grid = persistent_wgs > 0 ? (unsigned)std::min<long long>(items, persistent_wgs) : (unsigned)items;
     hipLaunchKernelGGL((k_rows<false>), dim3(grid), dim3(WGA), 0, st, A, nullptr, ncols, (int)items);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_reduce_rows<false>), dim3(A.nrow_groups, (3 * RCE * ncols + 255) / 256), dim3(256), 0, st, A,
+                       ncols, A.y);
+    BEM_HIP_TRY(hipGetLastError());
+}
+
+void launch_apply_t(const ApplyArgs& A, hipStream_t st)
+{
+    const int ncols = A.L * A.nrhs;
+    const unsigned ct = (unsigned)((ncols + NC - 1) / NC);
+    if (A.nfar > 0) hipLaunchKernelGGL(k_far_products_t, dim3(A.nfar, ct), dim3(WGA), 0, st, A, A.far_list, ncols);
+    BEM_HIP_TRY(hipGetLastError());
+    const long long items = (long long)A.nseg * ct;
+    if (items >= (1LL << 31)) throw std::invalid_argument("too many row work items");
+    hipLaunchKernelGGL(k_rows_t, dim3((unsigned)items), dim3(WGA), 0, st, A, ncols, (int)items);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_reduce_rows<false>), dim3(A.nrow_groups, (3 * RCE * ncols + 255) / 256), dim3(256), 0, st, A,
                        ncols, A.y);

@@ -33,6 +33,10 @@ struct CompressedOp {
     long long far_rows = 0;     // sum of kk over far faces
     long long zw_total = 0;     // sum of 3 cs over faces
     DevBuf work;                // apply workspace (grown on demand)
+    // plan of the transposed product (column chunks), built on first use
+    bool t_built = false;
+    int nseg_t = 0;
+    DevBuf rowfaces_t_dev, rowptr_t_dev, seg_t_dev;
     int mixed = 0, L = 0, K = 0;
 };
 
@@ -57,10 +61,15 @@ constexpr int POOL_STEPS0 = 32;     // 3D-ACA steps of every block in the initia
 // pieces in all; partial sums are added in segment order.  segbuf = [nseg] group, [nseg + 1]
 // first face entry, [ngroups + 1] first segment of each group.
 std::vector<int> make_segments(const std::vector<ApplyFace>& af, const std::vector<BlockIn>& blocks,
-                               const std::vector<int>& ptr, const std::vector<int>& flat, int target, int* nseg_out)
+                               const std::vector<int>& ptr, const std::vector<int>& flat, int target, int* nseg_out,
+                               bool transpose = false)
 {
     const int ngroups = (int)ptr.size() - 1;
-    auto cost = [&](int fi) { const ApplyFace& a = af[fi]; return (double)(a.kk > 0 ? a.kk : 3 * blocks[a.block].cs) + 24.0; };
+    auto cost = [&](int fi) {
+        const ApplyFace& a = af[fi];
+        const BlockIn& B = blocks[a.block];
+        return (double)(a.kk > 0 ? a.kk : 3 * (transpose ? B.rs : B.cs)) + 24.0;
+    };
     double total = 0.0;
     for (int fi : flat) total += cost(fi);
     const double per = std::max(1.0, total / std::max(target, 1));
@@ -758,6 +767,66 @@ void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride,
     A.tbuf = tb;
     A.pbuf = tb + (size_t)C.far_rows * ncols;
     launch_apply(A, st);
+    launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, C.L, nrhs, (int64_t)M, false, st);
+}
+
+// Plan of the transposed product: the same chunks (the partition is square), each with the
+// faces of the blocks whose columns cover it.
+void build_apply_plan_t(CompressedOp& C, hipStream_t st)
+{
+    const int nb = (int)C.blocks.size();
+    std::vector<std::vector<int>> faces_of_block(nb);
+    for (size_t f = 0; f < C.af.size(); ++f) faces_of_block[C.af[f].block].push_back((int)f);
+    const std::vector<int>& s2 = C.h_start;
+    std::vector<std::vector<int>> lists(C.ngroups);
+    for (int b = 0; b < nb; ++b) {
+        const BlockIn& B = C.blocks[b];
+        auto it = std::lower_bound(s2.begin(), s2.end(), B.cb);
+        for (; it != s2.end() && *it < B.cb + B.cs; ++it)
+            for (int fi : faces_of_block[b]) lists[it - s2.begin()].push_back(fi);
+    }
+    std::vector<int> ptr(C.ngroups + 1, 0), flat;
+    for (int g = 0; g < C.ngroups; ++g) {
+        ptr[g + 1] = ptr[g] + (int)lists[g].size();
+        flat.insert(flat.end(), lists[g].begin(), lists[g].end());
+    }
+    std::vector<int> segbuf = make_segments(C.af, C.blocks, ptr, flat, APPLY_SEGMENTS, &C.nseg_t, true);
+    auto up = [&](DevBuf& d, const void* src, size_t bytes) {
+        d.alloc(std::max<size_t>(bytes, 16));
+        if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    up(C.rowfaces_t_dev, flat.data(), flat.size() * sizeof(int));
+    up(C.rowptr_t_dev, ptr.data(), ptr.size() * sizeof(int));
+    up(C.seg_t_dev, segbuf.data(), segbuf.size() * sizeof(int));
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    C.t_built = true;
+}
+
+void apply_compressed_t(bem_op* op, int nrhs, const zd* x_dev, zd* y_dev, hipStream_t st)
+{
+    CompressedOp& C = *op->comp;
+    if (!C.t_built) build_apply_plan_t(C, st);
+    const size_t M = 3 * (size_t)C.K;
+    const size_t ncols = (size_t)C.L * nrhs;
+    const size_t prow = (size_t)3 * APPLY_ROW_CHUNK * ncols;
+    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + (size_t)C.nseg_t * prow + 16) * sizeof(zd);
+    if (C.work.bytes < need) C.work.alloc(need);
+    zd* xp = C.work.as<zd>();
+    zd* yp = xp + ncols * M;
+    zd* tb = yp + ncols * M;
+    launch_permute(x_dev, xp, C.perm_dev.as<int>(), C.K, C.L, nrhs, (int64_t)M, true, st);
+    ApplyArgs A = plan_args(C, nrhs);
+    A.row_faces = C.rowfaces_t_dev.as<int>();
+    A.row_ptr = C.rowptr_t_dev.as<int>();
+    A.nseg = C.nseg_t;
+    A.seg_group = C.seg_t_dev.as<int>();
+    A.seg_begin = A.seg_group + C.nseg_t;
+    A.group_seg = A.seg_begin + C.nseg_t + 1;
+    A.x = xp;
+    A.y = yp;
+    A.tbuf = tb;
+    A.pbuf = tb + (size_t)C.far_rows * ncols;
+    launch_apply_t(A, st);
     launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, C.L, nrhs, (int64_t)M, false, st);
 }
 

@@ -93,6 +93,30 @@ __global__ __launch_bounds__(256) void k_dense_apply(const zd* __restrict__ A, i
     if (lane == 0) y[((size_t)r * L + l) * M + row] = acc;
 }
 
+// y[r][l][c] = sum_row A[l][row][c] x[r][l][row] (the transpose): thread per (c, l, r), c
+// fastest (coalesced along the rows of A)
+__global__ __launch_bounds__(256) void k_dense_apply_t(const zd* __restrict__ A, int M, int L, int nrhs,
+                                                       const zd* __restrict__ x, zd* __restrict__ y)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)M * L * nrhs) return;
+    const int c = (int)(q % M);
+    const int l = (int)((q / M) % L);
+    const int r = (int)(q / ((int64_t)M * L));
+    const zd* a = A + (size_t)l * M * M + c;
+    const zd* xv = x + ((size_t)r * L + l) * M;
+    zd acc = {0.0, 0.0};
+    for (int row = 0; row < M; ++row) acc = fma_c(a[(size_t)row * M], xv[row], acc);
+    y[((size_t)r * L + l) * M + c] = acc;
+}
+
+void launch_dense_apply_t(const zd* A, int M, int L, int nrhs, const zd* x, zd* y, hipStream_t st)
+{
+    const int64_t n = (int64_t)M * L * nrhs;
+    hipLaunchKernelGGL(k_dense_apply_t, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, M, L, nrhs, x, y);
+    BEM_HIP_TRY(hipGetLastError());
+}
+
 void launch_dense_apply(const zd* A, int M, int L, int nrhs, const zd* x, int64_t x_l_stride, zd* y,
                         hipStream_t st)
 {

@@ -195,6 +195,8 @@ void aca_matrix_impl(bem_ctx* ctx, bool fp32, int m, int n, const void* A, doubl
                      void* U, void* V);
 void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride, zd* y_dev, hipStream_t st);
 void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream_t st);
+// y_l = A(s_l)^T x_l (plain transpose), x, y [nrhs][L][3K] mesh order
+void apply_compressed_t(bem_op* op, int nrhs, const zd* x_dev, zd* y_dev, hipStream_t st);
 // y = scale sum_l A(s_l) x (the weighted sum with one vector for every frequency)
 void apply_sum_compressed(bem_op* op, const zd* x_dev, double scale, zd* y_dev, hipStream_t st);
 void compressed_blocks(const bem_op* op, int64_t* n, int64_t* rows, int32_t* perm);

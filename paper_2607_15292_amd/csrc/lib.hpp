@@ -58,6 +58,8 @@ void launch_dense_assemble(const DevCtx& c, int op, int mixed, zd* out, hipStrea
 void launch_dense_apply(const zd* A, int M, int L, int nrhs, const zd* x, int64_t x_l_stride, zd* y,
                         hipStream_t st);
 void launch_dense_weighted(const zd* A, int M, int L, const zd* W, zd* y, hipStream_t st);
+// y = A(s_l)^T x for the stored dense slices, x, y [nrhs][L][M]
+void launch_dense_apply_t(const zd* A, int M, int L, int nrhs, const zd* x, zd* y, hipStream_t st);
 
 // ---------------------------------------------------------------- matrix-free (adjoint.hip)
 // y = A(s_l) x (transpose: A(s_l)^T x) for every l with entries recomputed; mesh order

@@ -142,3 +142,63 @@ def test_adjoint_errors(torch):
     c.set_quadrature(near_on=False)
     with pytest.raises(B.BemError):
         c.apply_mf(7, w)
+
+
+@pytest.mark.parametrize("prec,tol", [(B.PREC_F64, 1e-6), (B.PREC_MIXED, 1e-4)])
+def test_transposed_compressed_product(torch, prec, tol):
+    X, T = W.icosphere(2)  # 320 triangles: far and near blocks, factored faces
+    L = 16
+    s = W.bdf2_contour(L, 0.1)
+    c = _ctx(X, T, s, near_on=True)
+    D = oracle.Problem(X, T, s, near_on=True).dense(oracle.OP_V)
+    op = c.compress(B.OP_V, eps3d=1e-7 if prec == B.PREC_F64 else 1e-6, leaf=16, prec=prec, far_dense_max=8)
+    x = W.random_rhs(90, (3, L, 3 * len(T)))  # 48 columns
+    y = op.apply(torch.tensor(x, device="cuda"), transpose=True).cpu().numpy()
+    yo = np.einsum("lji,rlj->rli", D, x)
+    err = float((np.linalg.norm(y - yo, axis=-1) / np.linalg.norm(yo, axis=-1)).max())
+    assert err < tol, err
+    # 72 columns: a full and a ragged column tile
+    x2 = W.random_rhs(91, (5, L, 3 * len(T)))[:, :, :]
+    y2 = op.apply(x2, transpose=True)
+    yo2 = np.einsum("lji,rlj->rli", D, x2)
+    assert float((np.linalg.norm(y2 - yo2, axis=-1) / np.linalg.norm(yo2, axis=-1)).max()) < tol
+    dense = c.assemble_dense(B.OP_V)
+    yd = dense.apply(x, transpose=True)
+    assert np.abs(yd - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+def test_autograd_single_layer_solve(torch):
+    from paper_2607_15292_amd.autograd import single_layer_solve
+    X, T = W.icosphere(1)
+    s = W.bdf2_contour(8, 0.1)[[0, 3]]
+    c = _ctx(X, T, s)
+    b0 = W.random_rhs(70, (1, 2, 3 * len(T)))
+    cw = torch.tensor(W.random_rhs(71, (1, 2, 3 * len(T))), device="cuda")
+
+    def loss_of(t):
+        return (cw.conj() * t).real.sum() + (t.abs() ** 2).sum() * 0.05
+
+    for eps, rtol in ((None, 1e-5), (1e-10, 1e-4)):
+        nodes = torch.tensor(X, dtype=torch.float64, requires_grad=True)
+        mat = torch.tensor([1.0, 1.0, 0.5], dtype=torch.float64, requires_grad=True)
+        b = torch.tensor(b0, device="cuda", requires_grad=True)
+        loss = loss_of(single_layer_solve(c, nodes, mat, b, T, tol=1e-12, eps=eps))
+        loss.backward()
+
+        def f(Xp, m, bv):
+            with torch.no_grad():
+                t = single_layer_solve(c, torch.tensor(Xp, dtype=torch.float64), torch.tensor(m, dtype=torch.float64),
+                                       torch.tensor(bv, device="cuda"), T, tol=1e-12)
+                return float(loss_of(t).item())
+
+        rng = np.random.default_rng(4)
+        h = 1e-6
+        D = rng.standard_normal(X.shape)
+        m0 = [1.0, 1.0, 0.5]
+        fd = (f(X + h * D, m0, b0) - f(X - h * D, m0, b0)) / (2 * h)
+        assert abs(float((nodes.grad.numpy() * D).sum()) - fd) <= rtol * abs(fd), (eps, fd)
+        fd = (f(X, [1.0, 1.0 + 0.3 * h, 0.5 - 0.2 * h], b0) - f(X, [1.0, 1.0 - 0.3 * h, 0.5 + 0.2 * h], b0)) / (2 * h)
+        assert abs(float((mat.grad.numpy() * np.array([0.0, 0.3, -0.2])).sum()) - fd) <= rtol * abs(fd), (eps, fd)
+        db = W.random_rhs(72, b0.shape)
+        fd = (f(X, m0, b0 + h * db) - f(X, m0, b0 - h * db)) / (2 * h)
+        assert abs(float((b.grad.conj().cpu().numpy() * db).real.sum()) - fd) <= rtol * abs(fd), (eps, fd)
