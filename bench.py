@@ -148,14 +148,49 @@ def adjoint_leg(args, dev, torch):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     log("adjoint: K %d L %d: gradient %.2f s, matrix-free product %.2f s" % (K, L, t1 - t0, t2 - t1))
+    del w, x, y
+    c.close()
+    # gradient of a GMRES solution on the metric's sphere: V t = g at all contour points
+    # (fine V FP64 at the strict eps, inner V mixed), loss sum_l |t_l|^2 / 2: one transposed
+    # solve V^T nu = conj(t) and the adjoint kernel with w = nu, x = t
+    X2, T2, s2 = workload(args.level, args.freqs)
+    K2 = len(T2)
+    c2 = B.Context(0)
+    c2.set_mesh(X2, T2)
+    c2.set_material(1.0, 1.0, 0.5)
+    c2.set_frequencies(s2)
+    c2.set_quadrature(near_on=False)
+    Vf = c2.compress(B.OP_V, eps3d=args.eps_fp64_strict, leaf=64, eta=1.5, prec=B.PREC_F64)
+    Vi = c2.compress(B.OP_V, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED)
+    g = torch.tensor(W.random_rhs(72, (1, L, 3 * K2)), device=dev)
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    tsol, st1 = Vf.solve(g, inner=Vi, tol=1e-8, inner_tol=1e-3)
+    torch.cuda.synchronize()
+    ts1 = time.perf_counter()
+    nu, st2 = Vf.solve(tsol.conj().resolve_conj().contiguous(), inner=Vi, tol=1e-8, inner_tol=1e-3, transpose=True)
+    torch.cuda.synchronize()
+    ts2 = time.perf_counter()
+    _, gn2, gm2 = c2.adjoint_v(nu, tsol)
+    ts3 = time.perf_counter()
+    log("solution gradient: K %d: solve %.2f s, transposed solve %.2f s, adjoint %.2f s"
+        % (K2, ts1 - ts0, ts2 - ts1, ts3 - ts2))
+    sol = {"workload": "V t = g on an icosphere of %d triangles at %d contour points (near rule off), fine V FP64 "
+                       "eps %.0e, inner V mixed eps %.0e; loss sum |t|^2 / 2; gradient w.r.t. %d node coordinates "
+                       "and rho, c_p, c_s" % (K2, L, args.eps_fp64_strict, args.eps, 3 * len(X2)),
+           "solve_seconds": ts1 - ts0, "transposed_solve_seconds": ts2 - ts1, "adjoint_seconds": ts3 - ts2,
+           "gmres_iterations": [st1["iterations"], st2["iterations"]],
+           "grad_mat": [-float(v) for v in gm2]}
+    for o in (Vf, Vi):
+        o.destroy()
+    c2.close()
     out = {"workload": "single layer on an icosphere of %d triangles, %d BDF2 gCQ points, near rule off, one "
                        "right-hand side; gradient of Re sum_l w_l^T V(s_l) x_l w.r.t. %d node coordinates and "
                        "rho, c_p, c_s" % (K, L, 3 * len(X)),
            "gradient_seconds": t1 - t0, "pair_freqs_per_s": K * K * L / (t1 - t0),
            "matrix_free_product_seconds": t2 - t1, "matrix_free_entries_per_s": K * K * L / (t2 - t1),
-           "grad_norm_nodes": float(np.linalg.norm(gn)), "grad_mat": [float(v) for v in gm]}
-    del w, x, y
-    c.close()
+           "grad_norm_nodes": float(np.linalg.norm(gn)), "grad_mat": [float(v) for v in gm],
+           "solution_gradient": sol}
     return out
 
 
