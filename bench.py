@@ -476,13 +476,16 @@ def main():
                                "3D-ACA eps %.0e + H-matrix leaf 64 eta 1.5, complex64 far / complex128 near"
                                % (K, M, L, args.eps),
                    "elements": K, "frequencies": L, "rhs": 1},
+        "entries_per_s_by_rule": {k: sum(v["entries_" + k] for v in stats_steps[-1]) / sec_step
+                                  for k in ("regular", "near", "self", "other")},
         "hmatvecs_per_s": hmv,
         "matvecs_per_s_single_freq": {k: v * L for k, v in hmv.items()},
         "compress_stats": [{k: v[k] for k in ("n_blocks", "n_near", "n_far", "n_dense_fallback", "rank_mean",
                                                "rank_max", "aca_rank_mean", "aca_rank_max", "aca_cols_mean",
                                                "n_far_faces", "n_aca_dense", "compression_rate",
                                                "entries_generated", "kernel_ms", "face_ms", "aca_ms",
-                                               "recomp_ms")}
+                                               "recomp_ms", "entries_regular", "entries_near", "entries_self",
+                                               "entries_other")}
                            for v in st_m],
         "rel_err": errs,
         "roofline": roofline,

@@ -143,6 +143,10 @@ typedef struct {
                                      multiply-add = 8): Grams, Choleskys, core product, pivoted
                                      QR, Jacobi sweeps, coefficients, reflectors,
                                      back-substitutions and output products, as executed */
+    int64_t entries_regular;      /* entries_generated split by rule: the pairs of the kept */
+    int64_t entries_near;         /* faces by class (regular 7-point, near subdivision, self */
+    int64_t entries_self;         /* polar rule), and the rest (fibres and pivot entries) in */
+    int64_t entries_other;        /* entries_other */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */

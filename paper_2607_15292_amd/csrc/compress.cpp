@@ -684,6 +684,9 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         R.rank_max = std::max(R.rank_max, s.rank);
         rsum += s.rank;
         ent += s.entries;
+        R.entries_regular += (int64_t)s.rank * B.nreg;
+        R.entries_near += (int64_t)s.rank * (B.n1 + B.n2);
+        R.entries_self += (int64_t)s.rank * B.n3;
         R.n_aca_dense += s.aca_dense;
         colsum += (double)s.aca_cols;
         rflop += s.recomp_flop;
@@ -707,6 +710,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.bytes = bytes;
     R.compression_rate = (double)bytes / ((double)L * 9.0 * (double)K * (double)K * 16.0);
     R.entries_generated = ent;
+    R.entries_other = ent - R.entries_regular - R.entries_near - R.entries_self;
     R.n_far_faces = nfarfaces;
     R.kernel_ms = kms;
     R.aca_ms = aca_ms;
