@@ -37,6 +37,26 @@ METRIC = "kernel entries/s and all-frequency H-matvecs/s at 1e-6 rel err; mixed 
 PEAK_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: FP64 and non-packed FP32
 
 
+# HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counters (two rocprofv3 --pmc runs of
+# this script, scaled by the counts of a 1 GiB copy; profiles/traffic_c2_sphere5120_L64_mixed.md),
+# valid while the kernels' sources hash to the recorded value
+TRAFFIC = {
+    "face": {"bytes": 5.193e9, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp'], "sha256_16": '469ac24f3c233c1d'},
+    "recomp": {"bytes": 6.031e9, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp'], "sha256_16": '5e8f7dd4c0482e69'},
+}
+
+
+def traffic(key):
+    """Counter-measured bytes per dispatch of a kernel group, or None once its sources changed."""
+    import hashlib
+    t = TRAFFIC[key]
+    m = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2607_15292_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return t["bytes"] if m.hexdigest()[:16] == t["sha256_16"] else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -264,12 +284,24 @@ def main():
     ap.add_argument("--batch-nrhs", type=int, default=32)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg (reported apart from value)")
     ap.add_argument("--no-timestep", action="store_true", help="skip the time-stepping leg (reported apart from value)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB on the GPU three times (the reference kernel of the HBM traffic counters)")
     ap.add_argument("--adjoint-level", type=int, default=5, help="icosphere level of the adjoint leg (5: 20480 triangles)")
     ap.add_argument("--batch-freqs", type=int, default=128)
     ap.add_argument("--batch-eps", type=float, default=1e-7,
                     help="3D-ACA tolerance of the batched leg (1e-6 leaves 2.5e-4 at the largest |s_l| of L = 128)")
     ap.add_argument("--batch-eps-floor", type=float, default=1e-6, help="far-field tolerance floor of the batched leg")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 1 << 26  # 64 Mi complex128 = 1 GiB
+        xs = torch.ones(n, dtype=torch.complex128, device="cuda")
+        ys = torch.empty_like(xs)
+        for _ in range(3):
+            ys.copy_(xs)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 16, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the sharded path is designed, not built); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -415,18 +447,19 @@ def main():
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
     # 3D-ACA face kernels (k_face_dense / k_face_general); the one with more device time is
     # reported as "roofline", the other as "roofline_next"
-    def rl(ms_key, flop_key, launch_key, name):
+    def rl(ms_key, flop_key, launch_key, name, tkey):
         ms = sum(v[ms_key] for stp in stats_steps for v in stp)
         flop = sum(v[flop_key] for stp in stats_steps for v in stp)
         launches = sum(v[launch_key] for stp in stats_steps for v in stp)
         achieved = flop / max(ms * 1e-3, 1e-12)
         return ms, {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_VALU, "traffic": None, "kernel": name, "launches": launches,
+                    "frac": achieved / PEAK_VALU, "traffic": traffic(tkey), "kernel": name, "launches": launches,
                     "avg_launch_ms": ms / max(launches, 1), "flop_per_launch": flop / max(launches, 1)}
 
     rl_rec = rl("recomp_ms", "recomp_flop", "recomp_launches",
-                "k_face_recomp (per-slice recompression: QR, pivoted QR, Jacobi SVD, factor products)")
-    rl_face = rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general (3D-ACA face kernels)")
+                "k_face_recomp (per-slice recompression: QR, pivoted QR, Jacobi SVD, factor products)", "recomp")
+    rl_face = rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general (3D-ACA face kernels)",
+                 "face")
     roofline, roofline_next = (rl_rec[1], rl_face[1]) if rl_rec[0] >= rl_face[0] else (rl_face[1], rl_rec[1])
 
     # CPU baseline (oracle) on sampled rows; its results are also the accuracy reference
