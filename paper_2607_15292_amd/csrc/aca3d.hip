@@ -660,10 +660,20 @@ __device__ __forceinline__ void wargmax(double& v, int& idx)
 // row (column pass) of the pivot block row / column, so that the reads of the earlier ACA
 // columns are contiguous across lanes; the pivot's own 3 x kc slice is staged in LDS (sk).
 // The sigma_3 pivot search then reads the stored 3 x 3 blocks back.
+//
+// abort > 0 (the compression pass): once ABORT_STEPS rank-3 steps are done, the decay of the
+// step norms ||U_k|| ||V_k|| so far is extrapolated geometrically; a face whose predicted
+// column count to reach tol exceeds abort * cap is given up (-1, kept dense) without running
+// to the cap.  Such faces would mostly end dense anyway, and every further step re-reads all
+// earlier columns.  abort = 0 keeps the plain stopping rules (bem_aca_matrix).
+constexpr int ABORT_STEPS = 8;
+constexpr double ACA_ABORT = 1.5;
+
 template <typename T>
 __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax, zd* pinv,
-                        zd* sk)
+                        zd* sk, double abort)
 {
+    double est0 = 0.0;
     const int lane = threadIdx.x;
     const int M3 = 3 * m, N3 = 3 * n;
     for (int i = lane; i < m; i += WA) w.usedrow[i] = 0;
@@ -790,7 +800,14 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
         }
         un2 = wsum(un2);
         kc += 3;
-        if (sqrt(un2 * rn2) <= tol) return kc;
+        const double est = sqrt(un2 * rn2);
+        if (est <= tol) return kc;
+        if (kc == 3) est0 = est;
+        if (abort > 0.0 && kc >= 3 * ABORT_STEPS && est0 > 0.0) {
+            const double rate = pow(est / est0, 3.0 / (kc - 3));  // per step
+            const double steps = rate < 1.0 ? log(tol / est) / log(rate) : 1e30;
+            if (kc + 3.0 * steps > abort * cap) return -1;
+        }
         __syncthreads();
         double best2 = -1.0;
         int bi2 = 0x7fffffff;
@@ -817,7 +834,7 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
 // ACA stage of one stored dense face: ||H||_F, the pivot scale max |H|, then face_aca;
 // returns the column count (-1: not resolved, or a zero face).  One wavefront.
 template <typename T>
-__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol)
+__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double abort)
 {
     double s2 = 0.0, amax = 0.0;
     const int cnt = 9 * m * n;
@@ -831,7 +848,7 @@ __device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, in
     __shared__ zd pinv[9];
     __shared__ zd sk[3 * KMAX_SLICE];
     if (cap > KMAX_SLICE) return -1;
-    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk) : -1;
+    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk, abort) : -1;
 }
 
 // Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
@@ -862,8 +879,8 @@ __global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A)
     if (f.kk == 0 && !f.sel) {
         const int cap = min(A.kmax, face_aca_cap(m, n));
         tol = face_tol(A, b, f);
-        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol)
-                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol);
+        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT)
+                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT);
     }
     if (threadIdx.x == 0) {
         w.info[0] = kc;
@@ -1205,8 +1222,8 @@ __global__ __launch_bounds__(WA) void k_aca_matrix(char* H, int m, int n, int fp
                                                    double* scratch, int* out)
 {
     AcaWork w = aca_work(scratch, m, n, kmax);
-    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol)
-                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol);
+    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, 0.0)
+                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, 0.0);
     if (threadIdx.x == 0) {
         out[0] = kc;
         out[1] = 0;
