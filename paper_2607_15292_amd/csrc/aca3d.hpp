@@ -200,7 +200,9 @@ struct ApplyArgs {
 };
 
 constexpr int APPLY_ROW_CHUNK = 16;  // element rows per workgroup of the product (row chunks)
-constexpr int APPLY_SEGMENTS = 2048; // target number of row-kernel workgroups per column tile
+constexpr int APPLY_SEGMENTS = 2048;       // target number of row-kernel workgroups per column tile
+constexpr int APPLY_SEGMENTS_FINE = 8192;  // the same for products of at most APPLY_FINE_COLS columns
+constexpr int APPLY_FINE_COLS = 128;
 
 // persistent_wgs > 0: the row kernel runs on at most that many workgroups, each striding
 // over the (segment, column tile) items

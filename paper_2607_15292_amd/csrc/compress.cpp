@@ -27,6 +27,8 @@ struct CompressedOp {
     std::vector<int> h_flat, h_ptr, h_start, h_size, h_far;  // row groups and far faces (host copy)
     DevBuf af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev, farlist_dev;
     DevBuf seg_dev;             // segments: [nseg] group, [nseg + 1] face ranges, [ngroups + 1] group ranges
+    DevBuf segf_dev;            // finer segments for products of few columns (nsegf of them)
+    int nsegf = 0;
     int ngroups = 0;
     int nseg = 0;
     int nfar = 0;               // factored faces
@@ -180,6 +182,8 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
     up(C.rowsize_dev, z2.data(), z2.size() * sizeof(int));
     up(C.farlist_dev, far.data(), far.size() * sizeof(int));
     up(C.seg_dev, segbuf.data(), segbuf.size() * sizeof(int));
+    std::vector<int> segf = make_segments(C.af, C.blocks, ptr, flat, APPLY_SEGMENTS_FINE, &C.nsegf);
+    up(C.segf_dev, segf.data(), segf.size() * sizeof(int));
     BEM_HIP_TRY(hipStreamSynchronize(st));
     C.h_flat = std::move(flat);
     C.h_ptr = std::move(ptr);
@@ -206,10 +210,12 @@ ApplyArgs plan_args(const CompressedOp& C, int nrhs)
     A.nrhs = nrhs;
     A.far_list = C.farlist_dev.as<int>();
     A.nfar = C.nfar;
-    A.nseg = C.nseg;
-    A.seg_group = C.seg_dev.as<int>();
-    A.seg_begin = A.seg_group + C.nseg;
-    A.group_seg = A.seg_begin + C.nseg + 1;
+    // few columns: the finer segments keep enough row workgroups in flight
+    const bool fine = (size_t)C.L * nrhs <= (size_t)APPLY_FINE_COLS;
+    A.nseg = fine ? C.nsegf : C.nseg;
+    A.seg_group = (fine ? C.segf_dev : C.seg_dev).as<int>();
+    A.seg_begin = A.seg_group + A.nseg;
+    A.group_seg = A.seg_begin + A.nseg + 1;
     return A;
 }
 
@@ -759,7 +765,8 @@ void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride,
     const size_t M = 3 * (size_t)C.K;
     const size_t ncols = (size_t)C.L * nrhs;
     const size_t prow = (size_t)3 * APPLY_ROW_CHUNK * ncols;  // partial rows of one segment
-    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + (size_t)C.nseg * prow + 16) * sizeof(zd);
+    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + (size_t)std::max(C.nseg, C.nsegf) * prow + 16) *
+                  sizeof(zd);
     if (C.work.bytes < need) C.work.alloc(need);
     zd* xp = C.work.as<zd>();
     zd* yp = xp + ncols * M;
@@ -839,7 +846,7 @@ void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream
     CompressedOp& C = *op->comp;
     const size_t M = 3 * (size_t)C.K;
     const size_t prow = (size_t)3 * APPLY_ROW_CHUNK;
-    size_t need = ((size_t)C.L * M + M + (size_t)C.zw_total + (size_t)C.far_rows + (size_t)C.nseg * prow + 16) *
+    size_t need = ((size_t)C.L * M + M + (size_t)C.zw_total + (size_t)C.far_rows + (size_t)std::max(C.nseg, C.nsegf) * prow + 16) *
                   sizeof(zd);
     if (C.work.bytes < need) C.work.alloc(need);
     zd* Wp = C.work.as<zd>();
@@ -861,7 +868,8 @@ void apply_sum_compressed(bem_op* op, const zd* x_dev, double scale, zd* y_dev, 
     CompressedOp& C = *op->comp;
     const size_t M = 3 * (size_t)C.K;
     const size_t prow = (size_t)3 * APPLY_ROW_CHUNK;
-    size_t need = (2 * M + (size_t)C.zw_total + (size_t)C.far_rows + (size_t)C.nseg * prow + 16) * sizeof(zd);
+    size_t need = (2 * M + (size_t)C.zw_total + (size_t)C.far_rows + (size_t)std::max(C.nseg, C.nsegf) * prow + 16) *
+                  sizeof(zd);
     if (C.work.bytes < need) C.work.alloc(need);
     zd* xp = C.work.as<zd>();
     zd* yp = xp + M;
@@ -1114,7 +1122,7 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
     // the candidates that fit in half of the free memory and keeps the fastest
     // (default: about APPLY_SEGMENTS row workgroups per launch, at least one segment per group)
     const int ctiles = (P->L * nrhs + 63) / 64;
-    const int tdef = std::max(P->ngroups, APPLY_SEGMENTS / ctiles);
+    const int tdef = std::max(P->ngroups, (ctiles <= 2 ? APPLY_SEGMENTS_FINE : APPLY_SEGMENTS) / ctiles);
     std::vector<int> targets = {std::max(1, P->ngroups / 2), P->ngroups, 2 * P->ngroups, 4 * P->ngroups, tdef};
     std::sort(targets.begin(), targets.end());
     targets.erase(std::unique(targets.begin(), targets.end()), targets.end());
