@@ -1311,6 +1311,21 @@ void launch_fibre(const CompressArgs& A, hipStream_t st)
 }
 void launch_cross_dense(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_cross_dense, A.nlist, WG, A); }
 void launch_final(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_final, (A.nlist + 63) / 64, 64, A); }
+
+namespace {
+// flags[b] = block b still iterating (the host's view of the next step)
+__global__ __launch_bounds__(256) void k_active_flags(const BlockState* st, int nb, unsigned char* flags)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b < nb) flags[b] = (unsigned char)(st[b].active != 0);
+}
+}  // namespace
+
+void launch_active_flags(const CompressArgs& A, unsigned char* flags, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_active_flags, dim3((A.nblocks + 255) / 256), dim3(256), 0, st, A.st, A.nblocks, flags);
+    BEM_HIP_TRY(hipGetLastError());
+}
 void launch_advance(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_advance, (A.nlist + 63) / 64, 64, A); }
 void launch_final_prev(const CompressArgs& A, hipStream_t st)
 {

@@ -146,6 +146,8 @@ void launch_pivot(const CompressArgs& A, hipStream_t st);
 void launch_fibre(const CompressArgs& A, hipStream_t st);
 void launch_cross_dense(const CompressArgs& A, hipStream_t st);
 void launch_final(const CompressArgs& A, hipStream_t st);
+// flags[b] = st[b].active for every block (device bytes, copied to the host between steps)
+void launch_active_flags(const CompressArgs& A, unsigned char* flags, hipStream_t st);
 void launch_advance(const CompressArgs& A, hipStream_t st);
 void launch_final_prev(const CompressArgs& A, hipStream_t st);
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st);

@@ -453,9 +453,20 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     face_pairs = 0;
     face_flop = 0.0;
     bool face_pending = false;
+    // between steps only the blocks' activity comes back: one byte per block, pinned
+    DevBuf flags_dev;
+    flags_dev.alloc((size_t)nb + 64);
+    unsigned char* flags = nullptr;
+    BEM_HIP_TRY(hipHostMalloc((void**)&flags, (size_t)nb + 64, hipHostMallocDefault));
+    struct PinnedFree {
+        unsigned char* p;
+        ~PinnedFree() { if (p) (void)hipHostFree(p); }
+    } flags_guard{flags};
     for (int d = 0; d < L; ++d) {
-        BEM_HIP_TRY(hipMemcpyAsync(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost, st));
+        launch_active_flags(A, flags_dev.as<unsigned char>(), st);
+        BEM_HIP_TRY(hipMemcpyAsync(flags, flags_dev.p, (size_t)nb, hipMemcpyDeviceToHost, st));
         BEM_HIP_TRY(hipStreamSynchronize(st));
+        for (int b = 0; b < nb; ++b) S[b].active = flags[b];
         if (face_pending) {
             float ms = 0.f;
             BEM_HIP_TRY(hipEventElapsedTime(&ms, evf0, evf1));
