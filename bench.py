@@ -8,7 +8,8 @@ field complex64, near field complex128.
 
 One step = the whole hot path on resident inputs: partition, compression of V and I/2 + K
 (entries, pivots, fibres, per-slice ACA + recompression), and the all-frequency products
-y_l = V(s_l) x_l and (I/2 + K)(s_l) x_l for one right-hand side.
+y_l = V(s_l) x_l and (I/2 + K)(s_l) x_l for one right-hand side.  The two operators run
+concurrently, each on its own context and stream.
 
 value = kernel entries (3x3 ENTRY(i, j, l) blocks) generated per second over the step.
 Extra fields: all-frequency H-matvecs/s (apply only), the FP64 path's step time and the
@@ -41,8 +42,8 @@ PEAK_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: FP64
 # this script, scaled by the counts of a 1 GiB copy; profiles/traffic_c2_sphere5120_L64_mixed.md),
 # valid while the kernels' sources hash to the recorded value
 TRAFFIC = {
-    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp'], "sha256_16": 'eba2278f6c6d3dae'},
-    "recomp": {"bytes": 4.65e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp'], "sha256_16": '5e8f7dd4c0482e69'},
+    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp'], "sha256_16": '587a7a0858b0e6a0'},
+    "recomp": {"bytes": 4.65e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp'], "sha256_16": '34813205765f0853'},
 }
 
 
@@ -284,6 +285,10 @@ def main():
     ap.add_argument("--batch-nrhs", type=int, default=32)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg (reported apart from value)")
     ap.add_argument("--no-timestep", action="store_true", help="skip the time-stepping leg (reported apart from value)")
+    ap.add_argument("--sequential", action="store_true",
+                    help="timed steps with the operators one at a time (no second stream)")
+    ap.add_argument("--no-measure", action="store_true",
+                    help="skip the product-timing pass (for kernel traces of the timed steps alone)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the GPU three times (the reference kernel of the HBM traffic counters)")
     ap.add_argument("--adjoint-level", type=int, default=5, help="icosphere level of the adjoint leg (5: 20480 triangles)")
@@ -316,42 +321,84 @@ def main():
     X, T, s = workload(args.level, args.freqs)
     K, L = len(T), len(s)
     M = 3 * K
-    c = B.Context(0)
-    c.set_mesh(X, T)
-    c.set_material(1.0, 1.0, 0.5)
-    c.set_frequencies(s)
-    c.set_quadrature(near_on=True)
-    stream = torch.cuda.current_stream()
-    c.set_stream(stream)
+    def make_ctx():
+        cc = B.Context(0)
+        cc.set_mesh(X, T)
+        cc.set_material(1.0, 1.0, 0.5)
+        cc.set_frequencies(s)
+        cc.set_quadrature(near_on=True)
+        return cc
+
+    # V and I/2+K are compressed and applied concurrently, each with its own context on its
+    # own stream (default priority) from its own host thread: the latency-bound phases of
+    # one operator overlap the kernels of the other
+    ctxs = [make_ctx(), make_ctx()]
+    c = ctxs[0]
+
+    def fresh_ctxs():
+        """New contexts: the cached pools of the previous precision go back to the device."""
+        nonlocal c
+        for cc in ctxs:
+            cc.close()
+        torch.cuda.empty_cache()
+        ctxs[0], ctxs[1] = make_ctx(), make_ctx()
+        c = ctxs[0]
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
     x_h = W.random_rhs(1, (1, L, M))
     x = torch.tensor(x_h, device=dev)
+    torch.cuda.synchronize()
     ops_list = (B.OP_V, B.OP_HK)
     pool = int(args.pool_gb * (1 << 30))
+    import threading
 
-    def step(prec, measure=False, eps=None):
-        """One pass of the hot path; with measure, also times repeated applies and returns
-        the products on the host."""
-        st, ys, ams = [], [], []
-        for opk in ops_list:
-            op = c.compress(opk, eps3d=eps or args.eps, leaf=64, eta=1.5, prec=prec, pool_bytes=pool)
-            y = op.apply(x)
-            st.append(op.stats())
-            log("  op %d prec %d: compress %.0f ms (faces %.0f ms, per-slice ACA %.0f ms), rate %.4f"
-                % (opk, prec, st[-1]["kernel_ms"], st[-1]["face_ms"], st[-1]["aca_ms"], st[-1]["compression_rate"]))
-            if measure:
-                torch.cuda.synchronize()
-                ys.append(y.cpu().numpy())
-                y_buf = torch.empty_like(x)
-                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                ev0.record(stream)
-                for _ in range(10):
-                    op.apply(x, y=y_buf)
-                ev1.record(stream)
-                torch.cuda.synchronize()
-                ams.append(ev0.elapsed_time(ev1) / 10)
-            op.destroy()
+    def one(i, opk, prec, eps, measure, res, ci=None):
+        ci = i if ci is None else ci  # context and stream (one context when sequential: its cache serves both)
+        try:
+            with torch.cuda.stream(streams[ci]):
+                op = ctxs[ci].compress(opk, eps3d=eps or args.eps, leaf=64, eta=1.5, prec=prec, pool_bytes=pool)
+                y = op.apply(x)
+                stt = op.stats()
+                yh = am = None
+                if measure:
+                    streams[ci].synchronize()
+                    yh = y.cpu().numpy()
+                    y_buf = torch.empty_like(x)
+                    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    ev0.record(streams[ci])
+                    for _ in range(10):
+                        op.apply(x, y=y_buf)
+                    ev1.record(streams[ci])
+                    streams[ci].synchronize()
+                    am = ev0.elapsed_time(ev1) / 10
+                streams[ci].synchronize()
+                op.destroy()
+                res[i] = (stt, yh, am)
+        except BaseException as e:  # reported by the caller
+            res[i] = e
+
+    def step(prec, measure=False, eps=None, concurrent=True):
+        """One pass of the hot path (both operators concurrently, or one after the other);
+        with measure, the operators run one after the other and the repeated applies are
+        timed alone."""
+        res = [None, None]
+        if measure or not concurrent:
+            for i, opk in enumerate(ops_list):
+                one(i, opk, prec, eps, measure, res, ci=0)
+        else:
+            th = [threading.Thread(target=one, args=(i, opk, prec, eps, False, res)) for i, opk in enumerate(ops_list)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+        for r in res:
+            if isinstance(r, BaseException):
+                raise r
         torch.cuda.synchronize()
-        return st, ys, ams
+        st = [r[0] for r in res]
+        for opk, v in zip(ops_list, st):
+            log("  op %d prec %d: compress %.0f ms (faces %.0f ms, per-slice ACA %.0f ms), rate %.4f"
+                % (opk, prec, v["kernel_ms"], v["face_ms"], v["aca_ms"], v["compression_rate"]))
+        return st, [r[1] for r in res] if measure else [], [r[2] for r in res] if measure else []
 
     log("workload: K=%d L=%d; warmup %d" % (K, L, args.warmup))
     for w in range(args.warmup):
@@ -361,32 +408,51 @@ def main():
     t0 = time.perf_counter()
     stats_steps = []
     for k in range(args.steps):
-        st, _, _ = step(B.PREC_MIXED)
+        st, _, _ = step(B.PREC_MIXED, concurrent=not args.sequential)
         stats_steps.append(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec_step = (t1 - t0) / args.steps
     ents = sum(v["entries_generated"] for v in stats_steps[-1])
     log("timed: %.3f s/step, entries/step %d" % (sec_step, ents))
+    # the kernels' rooflines and the precision comparison take the operators one at a time:
+    # with two streams, events around a kernel also count the co-running kernels
+    if args.sequential:
+        seq_steps, sec_step_seq = stats_steps, sec_step
+    else:
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        st_seq, _, _ = step(B.PREC_MIXED, concurrent=False)
+        torch.cuda.synchronize()
+        sec_step_seq = time.perf_counter() - tq0
+        seq_steps = [st_seq]
+        log("one operator at a time: %.3f s/step" % sec_step_seq)
 
     # one more mixed pass keeping the products and timing the applies alone
-    st_m, ymix, ams = step(B.PREC_MIXED, measure=True)
+    if args.no_measure:
+        st_m, ymix, ams = stats_steps[-1], None, []
+    else:
+        st_m, ymix, ams = step(B.PREC_MIXED, measure=True)
     apply_ms = dict(zip(ops_list, ams))
     log("apply ms:", apply_ms)
 
     fp64 = None
     if not args.no_fp64:
-        step(B.PREC_F64)  # warm-up: the FP64 pools have other sizes than the mixed ones
+        # the FP64 operators do not fit twice at once (compaction holds the growth pool and
+        # the exact one), so the speedup compares the two precisions one operator at a time
+        fresh_ctxs()
+        step(B.PREC_F64, concurrent=False)  # warm-up: the FP64 pools have other sizes than the mixed ones
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        st_d, _, _ = step(B.PREC_F64)
+        st_d, _, _ = step(B.PREC_F64, concurrent=False)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         st_d2, ys_d, ams_d = step(B.PREC_F64, measure=True)
         fp64 = {"sec_per_step": t3 - t2, "stats": st_d, "apply_ms": dict(zip(ops_list, ams_d)), "ys": ys_d}
         log("fp64 step %.3f s" % (t3 - t2))
         # FP64 at the tolerance that meets 1e-6 per-frequency error (one untimed warm-up)
-        step(B.PREC_F64, eps=args.eps_fp64_strict)
+        fresh_ctxs()
+        step(B.PREC_F64, eps=args.eps_fp64_strict, concurrent=False)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
         st_s, ys_s, ams_s = step(B.PREC_F64, measure=True, eps=args.eps_fp64_strict)
@@ -411,6 +477,7 @@ def main():
             u_l, t_l = W.pulsating_sphere(C, nrm, s[l])
             g[0, l] = u_l.ravel()
             t_ex[0, l] = t_l.ravel()
+        fresh_ctxs()
         tc0 = time.perf_counter()
         Vf = c.compress(B.OP_V, eps3d=args.eps_fp64_strict, leaf=64, eta=1.5, prec=B.PREC_F64, pool_bytes=pool)
         Vi = c.compress(B.OP_V, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED, pool_bytes=pool)
@@ -436,8 +503,9 @@ def main():
         for o in (Vf, Vi, Hf):
             o.destroy()
 
-    # the batched leg builds its own contexts: release this one's cached pools first
-    c.close()
+    # the batched leg builds its own contexts: release these ones' cached pools first
+    for cc in ctxs:
+        cc.close()
     torch.cuda.empty_cache()
     batched = None if args.no_batch else batched_leg(args, dev, torch)
     adjoint = None if args.no_adjoint else adjoint_leg(args, dev, torch)
@@ -447,20 +515,29 @@ def main():
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
     # 3D-ACA face kernels (k_face_dense / k_face_general); the one with more device time is
     # reported as "roofline", the other as "roofline_next"
-    def rl(ms_key, flop_key, launch_key, name, tkey):
-        ms = sum(v[ms_key] for stp in stats_steps for v in stp)
-        flop = sum(v[flop_key] for stp in stats_steps for v in stp)
-        launches = sum(v[launch_key] for stp in stats_steps for v in stp)
+    def rl(ms_key, flop_key, launch_key, name, tkey, steps=None):
+        steps = stats_steps if steps is None else steps
+        ms = sum(v[ms_key] for stp in steps for v in stp)
+        flop = sum(v[flop_key] for stp in steps for v in stp)
+        launches = sum(v[launch_key] for stp in steps for v in stp)
         achieved = flop / max(ms * 1e-3, 1e-12)
         return ms, {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
                     "frac": achieved / PEAK_VALU, "traffic": traffic(tkey), "kernel": name, "launches": launches,
                     "avg_launch_ms": ms / max(launches, 1), "flop_per_launch": flop / max(launches, 1)}
 
     rl_rec = rl("recomp_ms", "recomp_flop", "recomp_launches",
-                "k_face_recomp (per-slice recompression: QR, pivoted QR, Jacobi SVD, factor products)", "recomp")
+                "k_face_recomp (per-slice recompression: QR, pivoted QR, Jacobi SVD, factor products)", "recomp",
+                seq_steps)
     rl_face = rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general (3D-ACA face kernels)",
-                 "face")
+                 "face", seq_steps)
     roofline, roofline_next = (rl_rec[1], rl_face[1]) if rl_rec[0] >= rl_face[0] else (rl_face[1], rl_rec[1])
+    for r_ in (roofline, roofline_next):
+        r_["timing"] = "operators one at a time (HIP events around the launches on the context stream)"
+    # the same kernels in the timed steps, the two operators sharing the GPU
+    roofline_conc = None
+    if not args.sequential:
+        roofline_conc = {"face": rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general", "face")[1],
+                         "recomp": rl("recomp_ms", "recomp_flop", "recomp_launches", "k_face_recomp", "recomp")[1]}
 
     # CPU baseline (oracle) on sampled rows; its results are also the accuracy reference
     cpu = None
@@ -486,7 +563,8 @@ def main():
             yg = y.reshape(1, L, K, 3)[:, :, rows, :].reshape(1, L, -1)
             return float(np.max(np.linalg.norm(yg - ref, axis=-1) / np.linalg.norm(ref, axis=-1)))
 
-        errs["mixed"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, ymix)}
+        if ymix is not None:
+            errs["mixed"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, ymix)}
         if fp64:
             errs["fp64"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, fp64["ys"])}
             errs["fp64_eps%.0e" % args.eps_fp64_strict] = {str(opk): rel(y, refs[opk])
@@ -500,6 +578,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": sec_step * 1e3,
+        "ms_per_step_one_operator_at_a_time": sec_step_seq * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -523,6 +602,7 @@ def main():
         "rel_err": errs,
         "roofline": roofline,
         "roofline_next": roofline_next,
+        "roofline_two_streams": roofline_conc,
         "solve": solve,
         "batched": batched,
         "adjoint": adjoint,
@@ -537,7 +617,7 @@ def main():
                        "compression_rate": [v["compression_rate"] for v in fp64["stats"]]}
         out["fp64"]["strict"] = {k: v for k, v in fp64["strict"].items() if k != "ys"}
         out["fp64"]["strict"]["hmatvecs_per_s"] = {str(k): 1e3 / v for k, v in fp64["strict"]["apply_ms"].items()}
-        out["mixed_vs_fp64_speedup"] = fp64["sec_per_step"] / sec_step
+        out["mixed_vs_fp64_speedup"] = fp64["sec_per_step"] / sec_step_seq
     print(json.dumps(out))
 
 
