@@ -32,12 +32,10 @@ __device__ __forceinline__ void mul3(const zd* f, const zd* v, zd* z)
     for (int a = 0; a < 3; ++a) z[a] = f[3 * a] * v[0] + f[3 * a + 1] * v[1] + f[3 * a + 2] * v[2];
 }
 
-// Fs[cl] = f[l] (3x3) of column c0 + cl (col = r L + l), the selector fibre of a dense
-// fallback face, or nothing for the weighted sum; read by stage_z after a barrier.
-template <bool WEIGHTED>
+// Fs[cl] = f[l] (3x3) of column c0 + cl (col = r L + l), or the selector fibre of a dense
+// fallback face; read after a barrier.
 __device__ __forceinline__ void stage_fibres(const ApplyArgs& A, const ApplyFace& F, int c0, int ncols, zd (*Fs)[9])
 {
-    if (WEIGHTED) return;
     const zd* fib = (const zd*)(A.pool + F.fib_off);
     for (int e = threadIdx.x; e < NC * 9; e += WGA) {
         const int cl = e / 9, t = e - 9 * (e / 9);
@@ -52,10 +50,9 @@ __device__ __forceinline__ void stage_fibres(const ApplyArgs& A, const ApplyFace
 }
 
 // Zs[k][c] for the scalar columns k0 .. k0 + KTL of the face and the columns c0 .. c0 + NC:
-// Z[3j + c][col] = (f[l] x_{r,l}[J])_c with col = r L + l (fibres from Fs), or the contracted
-// vector of the weighted sum (ncols = 1).
-template <bool WEIGHTED, int KTL>
-__device__ __forceinline__ void stage_z(const ApplyArgs& A, const BlockIn& B, const zd* zw, int k0, int c0, int ncols,
+// Z[3j + c][col] = (f[l] x_{r,l}[J])_c with col = r L + l (fibres from Fs).
+template <int KTL>
+__device__ __forceinline__ void stage_z(const ApplyArgs& A, const BlockIn& B, int k0, int c0, int ncols,
                                         const zd (*Fs)[9], zd (*Zs)[NC])
 {
     const int j0 = k0 / 3, nj = min(KTL / 3, B.cs - j0);
@@ -63,17 +60,10 @@ __device__ __forceinline__ void stage_z(const ApplyArgs& A, const BlockIn& B, co
         const int jj = e / NC, cl = e - jj * NC;
         zd z[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
         if (jj < nj && c0 + cl < ncols) {
-            if (WEIGHTED) {
-                const zd* v = zw + 3 * (size_t)(j0 + jj);
-                z[0] = v[0];
-                z[1] = v[1];
-                z[2] = v[2];
-            } else {
-                const int col = c0 + cl, l = col % A.L, r = col / A.L;
-                const zd* xv = A.x + ((size_t)r * A.L + l) * 3 * A.K + 3 * (size_t)(B.cb + j0 + jj);
-                const zd v[3] = {xv[0], xv[1], xv[2]};
-                mul3(Fs[cl], v, z);
-            }
+            const int col = c0 + cl, l = col % A.L, r = col / A.L;
+            const zd* xv = A.x + ((size_t)r * A.L + l) * 3 * A.K + 3 * (size_t)(B.cb + j0 + jj);
+            const zd v[3] = {xv[0], xv[1], xv[2]};
+            mul3(Fs[cl], v, z);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) Zs[3 * jj + c][cl] = z[c];
@@ -82,21 +72,20 @@ __device__ __forceinline__ void stage_z(const ApplyArgs& A, const BlockIn& B, co
 
 // far faces: T[t][col] = sum_k conj(Vbar[k][t]) Z[k][col]; one workgroup per (face, column
 // tile); thread = 3 ranks (t, t + 32, t + 64) x 8 columns.
-template <typename T, bool WEIGHTED>
-__device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const zd* zw_all, int ncols, int c0,
-                                  zd (*Vs)[KMAXF], zd (*Zs)[NC], zd (*Fs)[9])
+template <typename T>
+__device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, int ncols, int c0, zd (*Vs)[KMAXF],
+                                  zd (*Zs)[NC], zd (*Fs)[9])
 {
     const BlockIn B = A.blocks[F.block];
     const int m = B.rs, n = B.cs, kk = F.kk;
     const cx<T>* V = (const cx<T>*)(A.pool + F.face_off) + (size_t)3 * m * kk;
-    const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
     const int tr = threadIdx.x & 31, cg = threadIdx.x >> 5;
     zd acc[3][8];
 #pragma unroll
     for (int u = 0; u < 3; ++u)
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[u][v] = {0.0, 0.0};
-    stage_fibres<WEIGHTED>(A, F, c0, ncols, Fs);
+    stage_fibres(A, F, c0, ncols, Fs);
     for (int k0 = 0; k0 < 3 * n; k0 += KTF) {
         const int nk = min(KTF, 3 * n - k0);
         __syncthreads();
@@ -104,7 +93,7 @@ __device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const 
             const int kr = e / kk, t = e - kr * kk;
             Vs[kr][t] = kr < nk ? ldz(V + (size_t)(k0 + kr) * kk + t) : zd{0.0, 0.0};
         }
-        stage_z<WEIGHTED, KTF>(A, B, zw, k0, c0, ncols, Fs, Zs);
+        stage_z<KTF>(A, B, k0, c0, ncols, Fs, Zs);
         __syncthreads();
         for (int k = 0; k < nk; ++k) {
             zd vv[3];
@@ -131,16 +120,15 @@ __device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, const 
     }
 }
 
-template <bool WEIGHTED>
-__global__ __launch_bounds__(WGA) void k_far_products(ApplyArgs A, const int* far_list, const zd* zw_all, int ncols)
+__global__ __launch_bounds__(WGA) void k_far_products(ApplyArgs A, const int* far_list, int ncols)
 {
     __shared__ zd Vs[KTF][KMAXF];
     __shared__ zd Zs[KTF][NC];
     __shared__ zd Fs[NC][9];
     const ApplyFace F = A.faces[far_list[blockIdx.x]];
     const int c0 = blockIdx.y * NC;
-    if (F.fp32) far_products_face<float, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs, Fs);
-    else far_products_face<double, WEIGHTED>(A, F, zw_all, ncols, c0, Vs, Zs, Fs);
+    if (F.fp32) far_products_face<float>(A, F, ncols, c0, Vs, Zs, Fs);
+    else far_products_face<double>(A, F, ncols, c0, Vs, Zs, Fs);
 }
 
 // Y[rows][cols] += Hs[rows][k] Zs[k][cols] over one staged tile; thread = element row er
@@ -167,9 +155,8 @@ __device__ __forceinline__ void tile_mac(const zd (*Hs)[KTL], const zd (*Zs)[NC]
 // starting at c0; the segment's partial rows go to pbuf and k_reduce_rows adds them in
 // segment order.  Every LDS write is preceded by a barrier, so items can follow each other
 // in one workgroup.
-template <bool WEIGHTED>
-__device__ __forceinline__ void rows_item(const ApplyArgs& A, const zd* zw_all, int ncols, int sg, int c0,
-                                          zd (*Hs)[KR + 1], zd (*Zs)[NC], zd (*Fs)[9])
+__device__ __forceinline__ void rows_item(const ApplyArgs& A, int ncols, int sg, int c0, zd (*Hs)[KR + 1],
+                                          zd (*Zs)[NC], zd (*Fs)[9])
 {
     const int g = A.seg_group[sg];
     const int er = threadIdx.x >> 4, cq = threadIdx.x & 15;  // element row, column quad
@@ -186,10 +173,9 @@ __device__ __forceinline__ void rows_item(const ApplyArgs& A, const zd* zw_all, 
         const int n = B.cs;
         const int ioff = rs0 - B.rb;  // first element row of the chunk inside the block
         if (F.kk == 0) {
-            const zd* zw = WEIGHTED ? zw_all + F.zw_off : nullptr;
             const size_t ld = 3 * (size_t)n;
             __syncthreads();
-            stage_fibres<WEIGHTED>(A, F, c0, ncols, Fs);
+            stage_fibres(A, F, c0, ncols, Fs);
             for (int k0 = 0; k0 < 3 * n; k0 += KR) {
                 const int nk = min(KR, 3 * n - k0);
                 __syncthreads();
@@ -202,7 +188,7 @@ __device__ __forceinline__ void rows_item(const ApplyArgs& A, const zd* zw_all, 
                     }
                     Hs[r][kc] = h;
                 }
-                stage_z<WEIGHTED, KR>(A, B, zw, k0, c0, ncols, Fs, Zs);
+                stage_z<KR>(A, B, k0, c0, ncols, Fs, Zs);
                 __syncthreads();
                 tile_mac<KR + 1>(Hs, Zs, nk, er, cq, acc);
             }
@@ -244,15 +230,14 @@ __device__ __forceinline__ void rows_item(const ApplyArgs& A, const zd* zw_all, 
 
 // rows: work items w = sg + nseg * tile (segment fastest), one per workgroup, or strided
 // over a smaller persistent grid
-template <bool WEIGHTED>
-__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, const zd* zw_all, int ncols, int nitems)
+__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, int ncols, int nitems)
 {
     __shared__ zd Hs[3 * RCE][KR + 1];
     __shared__ zd Zs[KR][NC];
     __shared__ zd Fs[NC][9];
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
         const int tile = w / A.nseg;
-        rows_item<WEIGHTED>(A, zw_all, ncols, w - tile * A.nseg, tile * NC, Hs, Zs, Fs);
+        rows_item(A, ncols, w - tile * A.nseg, tile * NC, Hs, Zs, Fs);
     }
 }
 
@@ -374,7 +359,7 @@ __global__ __launch_bounds__(WGA) void k_rows_t(ApplyArgs A, int ncols, int nite
 #pragma unroll
                 for (int v = 0; v < 4; ++v) tmp[a][v] = {0.0, 0.0};
             __syncthreads();
-            stage_fibres<false>(A, F, c0, ncols, Fs);
+            stage_fibres(A, F, c0, ncols, Fs);
             const int kin = F.kk == 0 ? 3 * m : F.kk;
             for (int k0 = 0; k0 < kin; k0 += KR) {
                 const int nk = min(KR, kin - k0);
@@ -646,7 +631,7 @@ void launch_permute_batch(const BatchPermTable& T, int kmax, zd* work, bool to_c
 int apply_rows_occupancy()
 {
     int n = 0;
-    BEM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows<false>, WGA, 0));
+    BEM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows, WGA, 0));
     return n;
 }
 
@@ -663,13 +648,12 @@ void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs)
 {
     const int ncols = A.L * A.nrhs;
     const unsigned ct = (unsigned)((ncols + NC - 1) / NC);
-    if (A.nfar > 0) hipLaunchKernelGGL((k_far_products<false>), dim3(A.nfar, ct), dim3(WGA), 0, st, A, A.far_list,
-                                       nullptr, ncols);
+    if (A.nfar > 0) hipLaunchKernelGGL(k_far_products, dim3(A.nfar, ct), dim3(WGA), 0, st, A, A.far_list, ncols);
     BEM_HIP_TRY(hipGetLastError());
     const long long items = (long long)A.nseg * ct;
     if (items >= (1LL << 31)) throw std::invalid_argument("too many row work items");
     const unsigned grid = persistent_wgs > 0 ? (unsigned)std::min<long long>(items, persistent_wgs) : (unsigned)items;
-    hipLaunchKernelGGL((k_rows<false>), dim3(grid), dim3(WGA), 0, st, A, nullptr, ncols, (int)items);
+    hipLaunchKernelGGL(k_rows, dim3(grid), dim3(WGA), 0, st, A, ncols, (int)items);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_reduce_rows<false>), dim3(A.nrow_groups, (3 * RCE * ncols + 255) / 256), dim3(256), 0, st, A,
                        ncols, A.y);
