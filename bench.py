@@ -147,8 +147,8 @@ def batched_leg(args, dev, torch):
 def adjoint_leg(args, dev, torch):
     """Adjoint of the single layer (reported apart from value): the gradient of
     Re sum_l w_l^T V(s_l) x_l with respect to all node coordinates and rho, c_p, c_s, entries
-    recomputed (near rule off), and the matrix-free product, on the sphere of 20480 triangles
-    with 64 contour points."""
+    recomputed (near rule on, pair classes held fixed), and the matrix-free product, on the
+    sphere of 20480 triangles with 64 contour points."""
     from paper_2607_15292_amd import binding as B
     from paper_2607_15292_amd import workloads as W
     X, T = W.icosphere(args.adjoint_level)
@@ -158,7 +158,7 @@ def adjoint_leg(args, dev, torch):
     c.set_mesh(X, T)
     c.set_material(1.0, 1.0, 0.5)
     c.set_frequencies(s)
-    c.set_quadrature(near_on=False)
+    c.set_quadrature(near_on=True)
     w = torch.tensor(W.random_rhs(70, (1, L, 3 * K)), device=dev)
     x = torch.tensor(W.random_rhs(71, (1, L, 3 * K)), device=dev)
     torch.cuda.synchronize()
@@ -180,7 +180,7 @@ def adjoint_leg(args, dev, torch):
     c2.set_mesh(X2, T2)
     c2.set_material(1.0, 1.0, 0.5)
     c2.set_frequencies(s2)
-    c2.set_quadrature(near_on=False)
+    c2.set_quadrature(near_on=True)
     Vf = c2.compress(B.OP_V, eps3d=args.eps_fp64_strict, leaf=64, eta=1.5, prec=B.PREC_F64)
     Vi = c2.compress(B.OP_V, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED)
     g = torch.tensor(W.random_rhs(72, (1, L, 3 * K2)), device=dev)
@@ -196,7 +196,7 @@ def adjoint_leg(args, dev, torch):
     ts3 = time.perf_counter()
     log("solution gradient: K %d: solve %.2f s, transposed solve %.2f s, adjoint %.2f s"
         % (K2, ts1 - ts0, ts2 - ts1, ts3 - ts2))
-    sol = {"workload": "V t = g on an icosphere of %d triangles at %d contour points (near rule off), fine V FP64 "
+    sol = {"workload": "V t = g on an icosphere of %d triangles at %d contour points (near rule on), fine V FP64 "
                        "eps %.0e, inner V mixed eps %.0e; loss sum |t|^2 / 2; gradient w.r.t. %d node coordinates "
                        "and rho, c_p, c_s" % (K2, L, args.eps_fp64_strict, args.eps, 3 * len(X2)),
            "solve_seconds": ts1 - ts0, "transposed_solve_seconds": ts2 - ts1, "adjoint_seconds": ts3 - ts2,
@@ -205,7 +205,7 @@ def adjoint_leg(args, dev, torch):
     for o in (Vf, Vi):
         o.destroy()
     c2.close()
-    out = {"workload": "single layer on an icosphere of %d triangles, %d BDF2 gCQ points, near rule off, one "
+    out = {"workload": "single layer on an icosphere of %d triangles, %d BDF2 gCQ points, near rule on, one "
                        "right-hand side; gradient of Re sum_l w_l^T V(s_l) x_l w.r.t. %d node coordinates and "
                        "rho, c_p, c_s" % (K, L, 3 * len(X)),
            "gradient_seconds": t1 - t0, "pair_freqs_per_s": K * K * L / (t1 - t0),

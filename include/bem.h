@@ -305,10 +305,11 @@ int bem_apply_mf(bem_ctx *ctx, int32_t op, int32_t transpose, int32_t nrhs, cons
 /* Adjoint of the single layer (an extension; the paper has no adjoint): the value
  * S = sum_{r, l} w[r][l]^T V(s_l) x[r][l] (no conjugation) and the gradient of Re S with
  * respect to the node coordinates and the material, for the discrete operator of eq.
- * (discrVK) with the regular and self rules (the context's near rule must be off:
- * BEM_ERR_STATE otherwise).  Regular pairs are differentiated exactly (chain rule through
- * the Gauss points, the collocation points and the element areas; speeds through the kernel);
- * self pairs by central differences of the polar rule (relative step 1e-5).  Entries are
+ * (discrVK) with the context's quadrature (regular, near and self rules), the class of every
+ * pair held fixed.  Regular and near pairs are differentiated exactly (chain rule through the
+ * Gauss points, also those of the near rule's sub-triangles, the collocation points and the
+ * element areas; speeds through the kernel); self pairs by central differences of the polar
+ * rule (relative step 1e-5).  Entries are
  * recomputed, never stored.  w, x: [nrhs][L][3K] complex128, mesh order, host or device per
  * flags.  value: [2] (Re, Im S); grad_nodes: [n_nodes][3]; grad_mat: [3] = d/d rho, d/d c_p,
  * d/d c_s; each output may be NULL.  Cost: K^2 L nrhs kernel evaluations with derivatives. */

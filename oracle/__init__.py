@@ -7,7 +7,7 @@ shares no code with it.
 * ``bem_oracle.c`` (plain C99, FP64, optional OpenMP): kernel U and T of the paper's
   Appendix A / Sec. 2.1, collocation entries with the quadrature rules, dense products, and
   the gradient of a single-layer bilinear form with respect to the node coordinates and the
-  material (regular pairs by the chain rule, self pairs by central differences).
+  material (regular and near pairs by the chain rule, self pairs by central differences).
 * ``aca3d.py`` (numpy): the matrix-valued 3D-ACA of Algorithm 1 (Sec. 3) and the
   matrix-valued ACA with QR/SVD recompression of eq. (ACA) (Sec. 3.1), for small tensors.
 * ``partition.py`` (numpy): the PCA cluster tree and admissibility of Sec. 3.1.
@@ -72,6 +72,7 @@ def lib():
         L.oracle_adjoint_v.restype = ctypes.c_int
         L.oracle_adjoint_v.argtypes = [dp, ctypes.c_int64, ip, ctypes.c_int64,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int32,
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int32, dp, dp, ctypes.c_double,
                                        dp, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
@@ -156,12 +157,10 @@ class Problem:
         return (out[..., 0] + 1j * out[..., 1]).reshape(n, 3, 3)
 
     def adjoint_v(self, w, x, fd_h=1e-5):
-        """Value S = sum_{r, l} w[r, l]^T V(s_l) x[r, l] of the single layer (near rule off)
-        and the gradient of Re S: (S, grad_nodes [n_nodes, 3], grad_mat [rho, c_p, c_s]).
-        Regular pairs by the chain rule, self pairs by central differences of the polar rule
-        (step fd_h relative).  w, x: [nrhs, L, 3K] complex."""
-        if self.near_on:
-            raise ValueError("the adjoint covers the regular and self rules (near rule off)")
+        """Value S = sum_{r, l} w[r, l]^T V(s_l) x[r, l] of the single layer and the gradient
+        of Re S: (S, grad_nodes [n_nodes, 3], grad_mat [rho, c_p, c_s]), pair classes held
+        fixed.  Regular and near pairs by the chain rule, self pairs by central differences of
+        the polar rule (step fd_h relative).  w, x: [nrhs, L, 3K] complex."""
         w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
         x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
         assert w.shape == x.shape
@@ -170,7 +169,7 @@ class Problem:
         val = np.zeros(2)
         gn = np.zeros((self.nodes.shape[0], 3))
         gm = np.zeros(3)
-        rc = lib().oracle_adjoint_v(*self._common(), self.self_nt, self.self_nr, w.shape[0], _d(wr), _d(xr),
+        rc = lib().oracle_adjoint_v(*self._common(), *self._quad(0)[1:], w.shape[0], _d(wr), _d(xr),
                                     float(fd_h), _d(val), _d(gn), _d(gm))
         if rc != 0:
             raise RuntimeError("oracle_adjoint_v failed with code %d" % rc)

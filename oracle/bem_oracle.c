@@ -564,21 +564,48 @@ static cplx contract(const cplx *E, const double *w, const double *x, int64_t K,
     return sum;
 }
 
-/* Value S = sum_{r, l, i, j} w[r][l][i]^T V_ij(s_l) x[r][l][j] of the single layer (near rule
- * off) and the gradient of Re S with respect to the node coordinates and to rho, c_p, c_s:
- * the derivative of the discrete operator.  Regular pairs: chain rule through the Gauss
- * points y_q = sum_k b_qk v_k of element j, the collocation point (centroid of element i) and
- * the area of element j, with dU/dy from kernel_gradU and dU/dc from kernel_dU_dc.  Self
- * pairs: central differences of the polar rule in each vertex coordinate of the element
- * (step fd_h times its longest edge) and in c_p, c_s (step fd_h times the speed).
- * value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho, c_p, c_s). */
+/* Barycentric coordinates, with respect to the parent's vertices, of the vertices of the 4^m
+ * sub-triangles of the edge-midpoint splitting, in the order subdivided_rule visits them:
+ * out[t][b][a] is coordinate a of vertex b of sub-triangle t.  Returns the count 4^m. */
+static int sub_triangles(const double *b0, const double *b1, const double *b2, int m, double (*out)[3][3], int n)
+{
+    if (m == 0) {
+        for (int a = 0; a < 3; ++a) {
+            out[n][0][a] = b0[a];
+            out[n][1][a] = b1[a];
+            out[n][2][a] = b2[a];
+        }
+        return n + 1;
+    }
+    double m01[3], m12[3], m20[3];
+    for (int a = 0; a < 3; ++a) {
+        m01[a] = 0.5 * (b0[a] + b1[a]);
+        m12[a] = 0.5 * (b1[a] + b2[a]);
+        m20[a] = 0.5 * (b2[a] + b0[a]);
+    }
+    n = sub_triangles(b0, m01, m20, m - 1, out, n);
+    n = sub_triangles(m01, b1, m12, m - 1, out, n);
+    n = sub_triangles(m20, m12, b2, m - 1, out, n);
+    return sub_triangles(m01, m12, m20, m - 1, out, n);
+}
+
+/* Value S = sum_{r, l, i, j} w[r][l][i]^T V_ij(s_l) x[r][l][j] of the single layer and the
+ * gradient of Re S with respect to the node coordinates and to rho, c_p, c_s: the derivative
+ * of the discrete operator, with the pair classes (regular, near level m, self) held fixed.
+ * Regular and near pairs: chain rule through the Gauss points y = sum_a beta_a v_a of element
+ * j (beta: the 7-point rule's barycentric point mapped into each of the 4^m sub-triangles, so
+ * the points move with the vertices), the collocation point (centroid of element i) and the
+ * area of element j (each sub-triangle has a 4^-m share of it), with dU/dy from kernel_gradU
+ * and dU/dc from kernel_dU_dc.  Self pairs: central differences of the polar rule in each
+ * vertex coordinate of the element (step fd_h times its longest edge) and in c_p, c_s (step
+ * fd_h times the speed).  value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho, c_p, c_s). */
 int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
-                     double rho, double cp, double cs, const double *s, int32_t L, int self_nt, int self_nr,
-                     int32_t nrhs, const double *w, const double *x, double fd_h,
-                     double *value, double *grad_nodes, double *grad_mat)
+                     double rho, double cp, double cs, const double *s, int32_t L, int near_on, double r1,
+                     double r2, int self_nt, int self_nr, int32_t nrhs, const double *w, const double *x,
+                     double fd_h, double *value, double *grad_nodes, double *grad_mat)
 {
     ctx C;
-    int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, 0, 0.0, 0.0, self_nt, self_nr);
+    int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, near_on, r1, r2, self_nt, self_nr);
     if (rc) return rc;
     int nth = 1;
 #ifdef _OPENMP
@@ -654,14 +681,26 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
                 dA[2][1] = 0.5 * (n[2] * e1v[0] - n[0] * e1v[2]);
                 dA[2][2] = 0.5 * (n[0] * e1v[1] - n[1] * e1v[0]);
                 for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
-                for (int q = 0; q < 7; ++q) {
-                    const double *Bq = &C.tri_bary[3 * q];
-                    double y[3], rv[3];
+                int m = 0;
+                if (C.qo.near_on) {
+                    double d2 = 0.0;
+                    for (int k = 0; k < 3; ++k) d2 += (ei->c[k] - ej->c[k]) * (ei->c[k] - ej->c[k]);
+                    if (d2 < C.qo.r1 * C.qo.r1 * ej->lmax2) m = 2;
+                    else if (d2 < C.qo.r2 * C.qo.r2 * ej->lmax2) m = 1;
+                }
+                static const double id[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+                double sub[16][3][3];
+                const int nsub = sub_triangles(id[0], id[1], id[2], m, sub, 0);
+                for (int qq = 0; qq < 7 * nsub; ++qq) {
+                    const int t = qq / 7, q = qq % 7;
+                    const double *bq = &C.tri_bary[3 * q];
+                    double Bq[3], y[3], rv[3];
+                    for (int a = 0; a < 3; ++a) Bq[a] = bq[0] * sub[t][0][a] + bq[1] * sub[t][1][a] + bq[2] * sub[t][2][a];
                     for (int k = 0; k < 3; ++k) {
                         y[k] = Bq[0] * ej->v[0][k] + Bq[1] * ej->v[1][k] + Bq[2] * ej->v[2][k];
                         rv[k] = y[k] - ei->c[k];
                     }
-                    const double wq = C.tri_w[q], wA = wq * ej->area;
+                    const double wq = C.tri_w[q] / nsub, wA = wq * ej->area;
                     for (int32_t l = 0; l < L; ++l) {
                         cplx sl = s[2 * l] + I * s[2 * l + 1];
                         cplx U[9], G[27], D1[9], D2[9];

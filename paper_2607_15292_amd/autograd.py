@@ -8,8 +8,9 @@ operator is stored for them.
 y[r, l] = V(s_l) x[r, l] for the mesh with node coordinates `nodes` (float64 [n_nodes, 3],
 any device; the triangles and contour points are those set on `bem_ctx`), material
 (rho, c_p, c_s) as a float64 tensor [3], and x complex128 [nrhs, L, 3K] on the GPU.  The
-gradients are those of the discrete operator: the node coordinates and the speeds by the
-adjoint kernel, x by the transposed product.  The context's near rule must be off.
+gradients are those of the discrete operator with the context's quadrature (pair classes of
+the near rule held fixed): the node coordinates and the speeds by the adjoint kernel, x by the
+transposed product.
 """
 from __future__ import annotations
 
@@ -94,6 +95,6 @@ class SingleLayerSolve(torch.autograd.Function):
 
 def single_layer_solve(bem_ctx, nodes, material, b, tris, tol=1e-10, eps=None):
     """t[r, l] = V(s_l)^{-1} b[r, l], differentiable in nodes, material and b; V dense
-    (eps None) or compressed in FP64 at eps.  The context's near rule must be off."""
+    (eps None) or compressed in FP64 at eps."""
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     return SingleLayerSolve.apply(bem_ctx, tris, nodes, material, b, tol, eps)

@@ -151,8 +151,16 @@ def _is_torch(a):
     return type(a).__module__.startswith("torch")
 
 
-def _ptr(a):
-    """(pointer, flags) of a numpy array (host) or torch CUDA tensor (device)."""
+def _ptr(a, shape=None):
+    """(pointer, flags) of a numpy array (host) or torch CUDA tensor (device).  With shape, the
+    buffer must be complex128 of exactly that shape: the library reads and writes that many
+    elements through the pointer."""
+    if shape is not None:
+        dt = str(a.dtype)
+        if dt not in ("complex128", "torch.complex128"):
+            raise ValueError("expected a complex128 buffer, got %s" % dt)
+        if tuple(a.shape) != tuple(shape):
+            raise ValueError("expected shape %s, got %s" % (tuple(shape), tuple(a.shape)))
     if _is_torch(a):
         if not a.is_cuda:
             raise ValueError("torch tensors must live on the GPU; use numpy for host buffers")
@@ -298,8 +306,9 @@ class Context:
             self._sync_torch_stream()
         elif y is None:
             y = np.empty_like(x)
-        px, fl = _ptr(x)
-        py, _ = _ptr(y)
+        shp = (nrhs, self.L, 3 * self.K)
+        px, fl = _ptr(x, shp)
+        py, _ = _ptr(y, shp)
         self._check(lib().bem_apply_mf(self.h, int(op), int(bool(transpose)), int(nrhs), px, py, fl))
         return y
 
@@ -309,8 +318,9 @@ class Context:
         nrhs = x.shape[0]
         if _is_torch(x):
             self._sync_torch_stream()
-        pw, fl = _ptr(w)
-        px, fl2 = _ptr(x)
+        shp = (nrhs, self.L, 3 * self.K)
+        pw, fl = _ptr(w, shp)
+        px, fl2 = _ptr(x, shp)
         if fl != fl2:
             raise ValueError("w and x must both be host arrays or both device tensors")
         val = np.zeros(2)
@@ -376,8 +386,8 @@ class Operator:
             self.ctx._sync_torch_stream()
         elif y is None:
             y = np.empty((nrhs, L, 3 * K), dtype=np.complex128)
-        px, fl = _ptr(x)
-        py, _ = _ptr(y)
+        px, fl = _ptr(x, (nrhs, 3 * K) if shared_x else (nrhs, L, 3 * K))
+        py, _ = _ptr(y, (nrhs, L, 3 * K))
         self.ctx._check(lib().bem_apply(self.h, int(nrhs), px, py,
                                         fl | (SHARED_X if shared_x else 0) | (TRANSPOSE if transpose else 0)))
         return y
@@ -396,8 +406,8 @@ class Operator:
             self.ctx._sync_torch_stream()
         elif x is None:
             x = np.empty((nrhs, L, 3 * K), dtype=np.complex128)
-        pb, fl = _ptr(b)
-        px, _ = _ptr(x)
+        pb, fl = _ptr(b, (nrhs, L, 3 * K))
+        px, _ = _ptr(x, (nrhs, L, 3 * K))
         o = bem_solve_opts(float(tol), float(inner_tol), int(restart), int(max_iter), int(max_refine), 0)
         st = bem_solve_stats()
         fl |= TRANSPOSE if transpose else 0
@@ -419,8 +429,8 @@ class Operator:
             self.ctx._sync_torch_stream()
         elif t is None:
             t = np.empty_like(g)
-        pg, fl = _ptr(g)
-        pt, _ = _ptr(t)
+        pg, fl = _ptr(g, (N, 3 * self.ctx.K))
+        pt, _ = _ptr(t, (N, 3 * self.ctx.K))
         o = bem_solve_opts(float(tol), 1e-3, int(restart), int(max_iter), int(max_refine), 0)
         st = bem_solve_stats()
         rc = self.ctx._check(lib().bem_cq_dirichlet(self.h, H.h if H is not None else None, int(N), float(dt),
@@ -438,8 +448,8 @@ class Operator:
             self.ctx._sync_torch_stream()
         elif y is None:
             y = np.empty((3 * K,), dtype=np.complex128)
-        pw, fl = _ptr(W)
-        py, _ = _ptr(y)
+        pw, fl = _ptr(W, (self.ctx.L, 3 * K))
+        py, _ = _ptr(y, (3 * K,))
         self.ctx._check(lib().bem_apply_weighted(self.h, pw, py, fl))
         return y
 
@@ -494,8 +504,9 @@ class Batch:
                 ys = [np.empty_like(x) for x in xs]
         if dev:
             self.ctx._sync_torch_stream()
-        px, fl = zip(*[_ptr(x) for x in xs])
-        py, fly = zip(*[_ptr(y) for y in ys])
+        shp = [(self.nrhs, op.ctx.L, 3 * op.ctx.K) for op in self.ops]
+        px, fl = zip(*[_ptr(x, sh) for x, sh in zip(xs, shp)])
+        py, fly = zip(*[_ptr(y, sh) for y, sh in zip(ys, shp)])
         if len(set(fl) | set(fly)) != 1:
             raise ValueError("inputs and outputs must all be host arrays or all device tensors")
         ax = (ctypes.c_void_p * len(xs))(*[p.value for p in px])

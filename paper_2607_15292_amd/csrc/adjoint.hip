@@ -7,8 +7,9 @@
 // Regular pairs: chain rule.  With r = y - x, R = |r|, rh = r / R and 4 pi rho U = A I +
 // B rh rh^T, f = w^T U v has the gradient
 //   grad_r f = (A' (w.v) + B' (w.rh)(v.rh)) rh + (B / R) ((v.rh) w + (w.rh) v - 2 (w.rh)(v.rh) rh),
-// taken at the Gauss points y_q = sum_a b_qa P_a of element j (rows of node a), minus at the
-// centroid of element i, and the area of element j enters through dA/dP.  The speeds enter
+// taken at the Gauss points y_q = sum_a b_qa P_a of element j (rows of node a; for a near
+// pair, the points of the 4^m sub-triangles in barycentric coordinates of element j), minus
+// at the centroid of element i, and the area of element j enters through dA/dP.  The speeds enter
 // through A and B only: dA/dc1 = -e1r / c1, dA/dc2 = e2r (x2 - 1) / c2, dB/dc1 =
 // e1r (x1 + 1) / c1, dB/dc2 = -e2r (x2 + 1) / c2 with x_a = s R / c_a, e_ar = exp(-x_a) /
 // (c_a^2 R) (both branches of the kernel: in the series branch the lambda-integral
@@ -83,8 +84,9 @@ __device__ __forceinline__ void kernel_adj(double R, double Rinv, zd s, zd sinv,
     B2 = (e2r * (x2 + one)) * (-M.ic2);
 }
 
-// Regular pairs (i != j, near rule off): one thread per row element i, JB column elements per
-// workgroup.  gJ[bx][j][3 a + k]: d Re S / dP_{j,a,k} summed over the workgroup's rows;
+// Regular and near pairs (i != j; pair classes held fixed, the Gauss points of the near
+// rule's sub-triangles move with the vertices): one thread per row element i, JB column
+// elements per workgroup.  gJ[bx][j][3 a + k]: d Re S / dP_{j,a,k} summed over the workgroup's rows;
 // gI[by][i][k]: d Re S / d(centroid of i)_k over the workgroup's columns; gM[tile]: dc1, dc2,
 // Re S, Im S.
 __global__ __launch_bounds__(WG) void k_adjoint_v(DevCtx c, int nrhs, const zd* __restrict__ w,
@@ -125,10 +127,36 @@ __global__ __launch_bounds__(WG) void k_adjoint_v(DevCtx c, int nrhs, const zd* 
             dA[2][1] = 0.5 * (n[2] * e1[0] - n[0] * e1[2]);
             dA[2][2] = 0.5 * (n[0] * e1[1] - n[1] * e1[0]);
             for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+            // regular pair: one unit; near pair of level m: the 4^m sub-triangles, ordered as
+            // in the forward near rule; Sb[b][a] is coordinate a of sub-vertex b in P
+            const int m = pair_class(g, i, j, c.qt);
+            const int nsub = 1 << (2 * m);
+            const double wsub = g.area[j] * pref / (double)nsub;
+#pragma unroll 1
+            for (int u = 0; u < nsub; ++u) {
+            double Sb[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+#pragma unroll 1
+            for (int lev = m - 1; lev >= 0; --lev) {
+                const int ch = (u >> (2 * lev)) & 3;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double p0 = Sb[0][a], p1 = Sb[1][a], p2 = Sb[2][a];
+                    const double m01 = 0.5 * (p0 + p1), m12 = 0.5 * (p1 + p2), m20 = 0.5 * (p2 + p0);
+                    if (ch == 0) { Sb[1][a] = m01; Sb[2][a] = m20; }
+                    else if (ch == 1) { Sb[0][a] = m01; Sb[2][a] = m12; }
+                    else if (ch == 2) { Sb[0][a] = m20; Sb[1][a] = m12; }
+                    else { Sb[0][a] = m01; Sb[1][a] = m12; Sb[2][a] = m20; }
+                }
+            }
 #pragma unroll 1
             for (int q = 0; q < 7; ++q) {
-                const int o = q * K + j;
-                const double r[3] = {g.gx[o] - xi[0], g.gy[o] - xi[1], g.gz[o] - xi[2]};
+                const double* bq = c.qt.b7 + 3 * q;
+                double b[3], y[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) b[a] = bq[0] * Sb[0][a] + bq[1] * Sb[1][a] + bq[2] * Sb[2][a];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) y[k] = b[0] * P[0][k] + b[1] * P[1][k] + b[2] * P[2][k];
+                const double r[3] = {y[0] - xi[0], y[1] - xi[1], y[2] - xi[2]};
                 const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
                 const double Rinv = 1.0 / sqrt(R2), R = R2 * Rinv;
                 const double rh[3] = {r[0] * Rinv, r[1] * Rinv, r[2] * Rinv};
@@ -157,8 +185,7 @@ __global__ __launch_bounds__(WG) void k_adjoint_v(DevCtx c, int nrhs, const zd* 
                         m2 += (A2 * uv + B2 * t2).re;
                     }
                 }
-                const double wA = g.gw[o] * pref, w7 = c.qt.w7[q] * pref;
-                const double* b = c.qt.b7 + 3 * q;
+                const double w7 = c.qt.w7[q] * pref / (double)nsub, wA = c.qt.w7[q] * wsub;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const double gk = wA * G[k];
@@ -170,6 +197,7 @@ __global__ __launch_bounds__(WG) void k_adjoint_v(DevCtx c, int nrhs, const zd* 
                 mat[1] += wA * m2;
                 mat[2] += wA * V;
                 mat[3] += wA * Vi;
+            }
             }
         }
         // sum over the workgroup's rows, in a fixed order

@@ -935,7 +935,6 @@ int bem_adjoint_v(bem_ctx* ctx, int32_t nrhs, const void* w, const void* x, int3
     if (!ctx) return BEM_ERR_ARG;
     return guarded(ctx, [&]() -> int {
         need_state(ctx);
-        if (ctx->quad.near_on) throw api_error(BEM_ERR_STATE, "the adjoint covers the regular and self rules: near rule must be off");
         if (nrhs < 1 || !w || !x) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
         if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_adjoint_v");
         need_device(ctx);

@@ -88,3 +88,15 @@ def test_quadrature_option_validation():
         c.set_quadrature(True, 1.5, 3.0, 0, 8)
     with pytest.raises(B.BemError):
         c.set_quadrature(True, 3.0, 1.5, 8, 8)
+
+
+def test_binding_checks_buffer_shapes():
+    # the binding refuses buffers whose shape or dtype differ from what the library will read
+    a = np.zeros((2, 3, 12), dtype=np.complex128)
+    assert B._ptr(a, (2, 3, 12))[1] == 0
+    with pytest.raises(ValueError):
+        B._ptr(a, (2, 4, 12))
+    with pytest.raises(ValueError):
+        B._ptr(a.astype(np.complex64), (2, 3, 12))
+    with pytest.raises(ValueError):
+        B._ptr(a[:, :, ::2], (2, 3, 6))

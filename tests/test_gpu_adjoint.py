@@ -50,26 +50,46 @@ def test_mf_apply_matches_oracle(torch, mesh, near_on):
         assert np.abs(yt - yto).max() <= 1e-12 * np.abs(yto).max()
 
 
+def _class_margin(X, T, r1=1.5, r2=3.0):
+    # smallest |d^2 / lmax_j^2 - r^2| over the pairs: how far the mesh is from a switch of the
+    # near rule's pair classes
+    P = X[T]
+    c = P.mean(axis=1)
+    e = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 1], P[:, 0] - P[:, 2]], axis=1)
+    l2 = (e ** 2).sum(-1).max(-1)
+    d2 = ((c[:, None, :] - c[None, :, :]) ** 2).sum(-1) / l2[None, :]
+    return min(np.abs(d2 - r1 * r1).min(), np.abs(d2 - r2 * r2).min())
+
+
+@pytest.mark.parametrize("near_on", [False, True])
 @pytest.mark.parametrize("mesh", list(MESHES))
-def test_adjoint_matches_oracle(torch, mesh):
+def test_adjoint_matches_oracle(torch, mesh, near_on):
     X, T = MESHES[mesh]()
     s = W.bdf2_contour(8, 0.1)[[0, 2, 5]]
     mat = (1.3, 1.1, 0.6)
-    c = _ctx(X, T, s, mat=mat)
+    c = _ctx(X, T, s, mat=mat, near_on=near_on)
     w = W.random_rhs(40, (2, 3, 3 * len(T)))
     x = W.random_rhs(41, (2, 3, 3 * len(T)))
     val, gn, gm = c.adjoint_v(torch.tensor(w, device="cuda"), torch.tensor(x, device="cuda"))
-    val_o, gn_o, gm_o = oracle.Problem(X, T, s, *mat, near_on=False).adjoint_v(w, x)
+    val_o, gn_o, gm_o = oracle.Problem(X, T, s, *mat, near_on=near_on).adjoint_v(w, x)
     assert abs(val - val_o) <= 1e-12 * abs(val_o)
-    # regular pairs exact on both sides; self pairs by central differences (relative step 1e-5)
+    # regular and near pairs exact on both sides; self pairs by central differences (relative
+    # step 1e-5)
     assert np.abs(gn - gn_o).max() <= 1e-7 * np.abs(gn_o).max()
     assert np.abs(gm - gm_o).max() <= 1e-7 * np.abs(gm_o).max()
 
 
-def test_adjoint_matches_central_differences(torch):
+@pytest.mark.parametrize("near_on", [False, True])
+def test_adjoint_matches_central_differences(torch, near_on):
     X, T = W.icosphere(2)  # 320 triangles
+    h = 1e-5
+    if near_on:
+        # jittered so that the difference steps switch no pair class of the near rule
+        X = X + 0.005 * np.random.default_rng(12).standard_normal(X.shape)
+        h = 1e-6
+        assert _class_margin(X, T) > 1e2 * h
     s = W.bdf2_contour(8, 0.1)[[1, 4]]
-    c = _ctx(X, T, s)
+    c = _ctx(X, T, s, near_on=near_on)
     w = W.random_rhs(50, (1, 2, 3 * len(T)))
     x = W.random_rhs(51, (1, 2, 3 * len(T)))
     _, gn, gm = c.adjoint_v(w, x)
@@ -80,7 +100,6 @@ def test_adjoint_matches_central_differences(torch):
         return np.sum(w * c.apply_mf(B.OP_V, x)).real
 
     rng = np.random.default_rng(9)
-    h = 1e-5
     for _ in range(10):
         D = rng.standard_normal(X.shape)
         fd = (S(X + h * D) - S(X - h * D)) / (2 * h)
@@ -134,14 +153,12 @@ def test_autograd_single_layer(torch):
 def test_adjoint_errors(torch):
     X, T = W.icosphere(1)
     s = W.bdf2_contour(4, 0.1)
-    c = _ctx(X, T, s, near_on=True)
+    c = _ctx(X, T, s)
     w = W.random_rhs(1, (1, 4, 3 * len(T)))
-    with pytest.raises(B.BemError) as e:
-        c.adjoint_v(w, w)
-    assert e.value.code == -5  # BEM_ERR_STATE: near rule on
-    c.set_quadrature(near_on=False)
     with pytest.raises(B.BemError):
         c.apply_mf(7, w)
+    with pytest.raises(ValueError):  # the binding checks shapes before the library reads them
+        c.adjoint_v(w, w[:, :2].copy())
 
 
 @pytest.mark.parametrize("prec,tol", [(B.PREC_F64, 1e-6), (B.PREC_MIXED, 1e-4)])

@@ -2,7 +2,8 @@
 of Re S, S = sum_{r, l} w[r, l]^T V(s_l) x[r, l], with respect to the node coordinates and
 rho, c_p, c_s against central differences of the oracle's own dense operator (the plain
 definition of the derivative of the discrete operator), translation invariance, and the value
-against the dense product."""
+against the dense product; with the near rule on, on a jittered mesh whose pairs keep their
+classes under the difference steps."""
 import numpy as np
 import pytest
 
@@ -62,7 +63,66 @@ def test_translation_invariance():
     assert np.abs(g.sum(axis=0)).max() <= 1e-8 * np.abs(g).max()
 
 
-def test_rejects_near_rule():
+def _near_setup():
+    # jittered mesh so that no pair sits on a class boundary of the near rule
     X, T, s, w, x = _setup()
-    with pytest.raises(ValueError):
-        oracle.Problem(X, T, s, near_on=True).adjoint_v(w, x)
+    X = X + 0.02 * np.random.default_rng(9).standard_normal(X.shape)
+    return X, T, s, w, x
+
+
+def _class_margin(X, T, r1=1.5, r2=3.0):
+    # smallest |d^2 / lmax_j^2 - r^2| over the pairs: how far the mesh is from a class switch
+    P = X[T]
+    c = P.mean(axis=1)
+    e = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 1], P[:, 0] - P[:, 2]], axis=1)
+    l2 = (e ** 2).sum(-1).max(-1)
+    d2 = ((c[:, None, :] - c[None, :, :]) ** 2).sum(-1) / l2[None, :]
+    return min(np.abs(d2 - r1 * r1).min(), np.abs(d2 - r2 * r2).min())
+
+
+def _S_near(X, T, s, w, x, rho=1.0, cp=1.0, cs=0.5):
+    D = oracle.Problem(X, T, s, rho, cp, cs, near_on=True).dense(oracle.OP_V)
+    return complex(np.einsum("rli,lij,rlj->", w, D, x))
+
+
+def test_near_rule_value_is_the_dense_bilinear_form():
+    X, T, s, w, x = _near_setup()
+    val, _, _ = oracle.Problem(X, T, s, near_on=True).adjoint_v(w, x)
+    ref = _S_near(X, T, s, w, x)
+    assert abs(val - ref) <= 1e-12 * abs(ref)
+    # the near rule changes the form: the level-1 sphere has pairs of both near levels
+    assert abs(val - _S(X, T, s, w, x)) > 1e-6 * abs(ref)
+
+
+def test_near_rule_node_gradient_matches_central_differences():
+    X, T, s, w, x = _near_setup()
+    h = 1e-6
+    assert _class_margin(X, T) > 1e2 * h
+    _, g, _ = oracle.Problem(X, T, s, near_on=True).adjoint_v(w, x)
+    _, g0, _ = oracle.Problem(X, T, s, near_on=False).adjoint_v(w, x)
+    assert np.abs(g - g0).max() > 1e-6 * np.abs(g).max()
+    rng = np.random.default_rng(6)
+    for _ in range(8):
+        D = rng.standard_normal(X.shape)
+        fd = (_S_near(X + h * D, T, s, w, x).real - _S_near(X - h * D, T, s, w, x).real) / (2 * h)
+        an = float(np.sum(g * D))
+        assert abs(an - fd) <= 1e-6 * np.linalg.norm(g) * np.linalg.norm(D), (an, fd)
+
+
+def test_near_rule_material_gradient_matches_central_differences():
+    X, T, s, w, x = _near_setup()
+    _, _, gm = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=True).adjoint_v(w, x)
+    base = dict(rho=1.3, cp=1.1, cs=0.6)
+    for k, name in enumerate(("rho", "cp", "cs")):
+        h = 1e-6 * base[name]
+        p, m = dict(base), dict(base)
+        p[name] += h
+        m[name] -= h
+        fd = (_S_near(X, T, s, w, x, **p).real - _S_near(X, T, s, w, x, **m).real) / (2 * h)
+        assert abs(gm[k] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(gm).max()), (name, gm[k], fd)
+
+
+def test_near_rule_translation_invariance():
+    X, T, s, w, x = _near_setup()
+    _, g, _ = oracle.Problem(X, T, s, near_on=True).adjoint_v(w, x)
+    assert np.abs(g.sum(axis=0)).max() <= 1e-8 * np.abs(g).max()
