@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "kernel entries/s and all-frequency H-matvecs/s at 1e-6 rel err; mixed vs FP64 speedup"
 PEAK_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: FP64 and non-packed FP32
+PEAK_HBM = 8.0e12    # HBM3E bytes/s
 
 
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counters (two rocprofv3 --pmc runs of
@@ -515,28 +516,43 @@ def main():
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
     # 3D-ACA face kernels (k_face_dense / k_face_general); the one with more device time is
     # reported as "roofline", the other as "roofline_next"
-    def rl(ms_key, flop_key, launch_key, name, tkey, steps=None):
+    # With algorithmic bytes (bytes_key), the roof is the one the kernel's arithmetic intensity
+    # falls under: HBM below the ridge PEAK_VALU / PEAK_HBM (9.8 flop/B), the vector ALU above;
+    # the other roof's figures are kept beside it.
+    def rl(ms_key, flop_key, launch_key, name, tkey, steps=None, bytes_key=None):
         steps = stats_steps if steps is None else steps
         ms = sum(v[ms_key] for stp in steps for v in stp)
         flop = sum(v[flop_key] for stp in steps for v in stp)
         launches = sum(v[launch_key] for stp in steps for v in stp)
         achieved = flop / max(ms * 1e-3, 1e-12)
-        return ms, {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_VALU, "traffic": traffic(tkey), "kernel": name, "launches": launches,
-                    "avg_launch_ms": ms / max(launches, 1), "flop_per_launch": flop / max(launches, 1)}
+        alu = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
+               "frac": achieved / PEAK_VALU}
+        out = dict(alu)
+        if bytes_key is not None:
+            nbytes = sum(v[bytes_key] for stp in steps for v in stp)
+            bw = nbytes / max(ms * 1e-3, 1e-12)
+            hbm = {"bound": "hbm", "achieved": bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": bw / PEAK_HBM}
+            ai = flop / max(nbytes, 1.0)
+            out = dict(hbm, alu=alu) if ai < PEAK_VALU / PEAK_HBM else dict(alu, hbm=hbm)
+            out["intensity_flop_per_byte"] = ai
+            out["bytes_per_launch"] = nbytes / max(launches, 1)
+        out.update({"traffic": traffic(tkey), "kernel": name, "launches": launches,
+                    "avg_launch_ms": ms / max(launches, 1), "flop_per_launch": flop / max(launches, 1)})
+        return ms, out
 
     rl_rec = rl("recomp_ms", "recomp_flop", "recomp_launches",
                 "k_face_recomp (per-slice recompression: QR, pivoted QR, Jacobi SVD, factor products)", "recomp",
                 seq_steps)
     rl_face = rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general (3D-ACA face kernels)",
-                 "face", seq_steps)
+                 "face", seq_steps, bytes_key="face_bytes")
     roofline, roofline_next = (rl_rec[1], rl_face[1]) if rl_rec[0] >= rl_face[0] else (rl_face[1], rl_rec[1])
     for r_ in (roofline, roofline_next):
         r_["timing"] = "operators one at a time (HIP events around the launches on the context stream)"
     # the same kernels in the timed steps, the two operators sharing the GPU
     roofline_conc = None
     if not args.sequential:
-        roofline_conc = {"face": rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general", "face")[1],
+        roofline_conc = {"face": rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general", "face",
+                                    bytes_key="face_bytes")[1],
                          "recomp": rl("recomp_ms", "recomp_flop", "recomp_launches", "k_face_recomp", "recomp")[1]}
 
     # CPU baseline (oracle) on sampled rows; its results are also the accuracy reference

@@ -147,6 +147,9 @@ typedef struct {
     int64_t entries_near;         /* faces by class (regular 7-point, near subdivision, self */
     int64_t entries_self;         /* polar rule), and the rest (fibres and pivot entries) in */
     int64_t entries_other;        /* entries_other */
+    double face_bytes;            /* algorithmic HBM bytes of the face kernels: per pair of step
+                                     d, the new face block written and the d earlier face
+                                     blocks read (72 B each in complex64, 144 B in complex128) */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */

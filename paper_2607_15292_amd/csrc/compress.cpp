@@ -385,7 +385,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     BEM_HIP_TRY(hipEventCreate(&ev2));
     BEM_HIP_TRY(hipEventCreate(&evf0));
     BEM_HIP_TRY(hipEventCreate(&evf1));
-    double face_ms = 0.0, face_flop = 0.0;
+    double face_ms = 0.0, face_flop = 0.0, face_bytes = 0.0;
     int64_t face_launches = 0, face_pairs = 0;
     float kms = 0.f, aca_ms = 0.f;
     double recomp_ms = 0.0;
@@ -403,7 +403,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(Ar.pool_cap) +
                                          " bytes is too small; raise pool_bytes or pass 0");
         size_t want = std::max<size_t>((size_t)(1.5 * (double)Ar.pool_cap), (size_t)top + 2 * need);
-        want = std::min<size_t>(want, (size_t)top + (size_t)(0.9 * (double)avail()));
+        want = std::min<size_t>(want, (size_t)(0.9 * (double)avail()));  // the old pool stays alive during the copy
         if (want < top + need) throw Err(BEM_ERR_NOMEM, "device memory exhausted by the compression pool");
         DevBuf np(&ctx->cache);
         np.alloc(want);
@@ -452,6 +452,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     face_launches = 0;
     face_pairs = 0;
     face_flop = 0.0;
+    face_bytes = 0.0;
     bool face_pending = false;
     // between steps only the blocks' activity comes back: one byte per block, pinned
     DevBuf flags_dev;
@@ -508,7 +509,11 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         const int* p_act = put_list(list_dev, tiles.size(), act, st);
         A.d = d;
         int64_t pairs = 0;
-        for (int b : act) pairs += (int64_t)C->blocks[b].rs * C->blocks[b].cs;
+        for (int b : act) {
+            const BlockIn& B = C->blocks[b];
+            pairs += (int64_t)B.rs * B.cs;
+            face_bytes += (double)B.rs * B.cs * 9.0 * (B.f32 ? sizeof(zf) : sizeof(zd)) * (d + 1);
+        }
         face_pairs += pairs;
         face_flop += (double)pairs * (QPTS_REGULAR * flops_eval(op) + FLOPS_RESIDUAL * d);
         BEM_HIP_TRY(hipEventRecord(evf0, st));
@@ -735,6 +740,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.face_launches = face_launches;
     R.face_pairs = face_pairs;
     R.face_flop = face_flop;
+    R.face_bytes = face_bytes;
     R.recomp_ms = recomp_ms;
     R.recomp_launches = recomp_launches;
     R.recomp_flop = rflop;
