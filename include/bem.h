@@ -103,7 +103,11 @@ typedef struct {
     int32_t prec;        /* BEM_PREC_F64 or BEM_PREC_MIXED */
     double mixed_eps_floor; /* MIXED only: far-field tolerances are raised to at least this
                                value (complex64 entries cannot resolve less); default 1e-5 */
-    int64_t pool_bytes;  /* device bytes reserved for faces, fibres and factors; 0 = auto */
+    int64_t pool_bytes;  /* working pool of the faces, fibres and factors of one block group
+                            (bytes; 0 = auto: 60 % of the free memory, grown on demand).
+                            The blocks are compressed in consecutive groups whose faces of
+                            min(L, 32) steps fit the pool; each group is compacted into a
+                            pool of exact size before the next starts */
     int32_t far_dense_max; /* admissible blocks whose smaller side has at most this many
                               elements keep dense faces (their per-slice ACA rank is close to
                               full); 0 = per-slice ACA on every admissible block; default 48 */
@@ -150,6 +154,9 @@ typedef struct {
     double face_bytes;            /* algorithmic HBM bytes of the face kernels: per pair of step
                                      d, the new face block written and the d earlier face
                                      blocks read (72 B each in complex64, 144 B in complex128) */
+    int64_t block_groups;         /* groups the blocks were compressed in, one after the other
+                                     (1 unless the faces of all blocks would not fit the memory
+                                     or bem_aca_opts.pool_bytes) */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -286,6 +286,7 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
 {
     int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= A.nblocks) return;
+    if (A.sel && !A.sel[b]) return;  // a block of another group of the compression
     BlockState s;
     s.k = 0;
     s.rank = 0;

@@ -83,6 +83,7 @@ struct CompressArgs {
     double* scratch;
     size_t scratch_per_slot;  // doubles
     const int* pairs;       // pair orders of the blocks with pair0 >= 0
+    const unsigned char* sel;  // blocks that k_init starts (nullptr: all); the others keep their state
     double eps3d, eps3d_far, eps_aca_far;
 };
 

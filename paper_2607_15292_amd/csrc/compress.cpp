@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <cstdio>
 
@@ -18,7 +19,8 @@ struct CompressedOp {
     DevBuf perm_dev;            // [K] cluster position -> mesh element
     DevBuf blocks_dev;          // BlockIn[nb]
     DevBuf faces_dev;           // FaceDesc[nb][L]
-    DevBuf pool;                // faces, factors, fibres
+    DevBuf pool;                // faces, factors, fibres (offsets of FaceDesc are from its base)
+    std::vector<std::unique_ptr<DevBuf>> extra_pools;  // pools of further block groups, above it
     std::vector<BlockIn> blocks;
     std::vector<FaceDesc> faces;
     std::vector<BlockState> st;
@@ -40,6 +42,7 @@ struct CompressedOp {
     int nseg_t = 0;
     DevBuf rowfaces_t_dev, rowptr_t_dev, seg_t_dev;
     int mixed = 0, L = 0, K = 0;
+    int ngroups_c = 1;          // block groups of the compression
 };
 
 void destroy_compressed(CompressedOp* c) { delete c; }
@@ -368,14 +371,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
         return fr + ctx->cache.cached;
     };
-    size_t all_step = 0;
-    for (int b = 0; b < nb; ++b) all_step += step_bytes(b);
-    size_t pool_bytes = (size_t)o.pool_bytes;
-    const bool auto_pool = pool_bytes == 0;
-    if (auto_pool) pool_bytes = std::min((size_t)(0.6 * (double)avail()), all_step * (size_t)std::min(L, POOL_STEPS0));
-    if (pool_bytes < all_step)
-        throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes cannot hold one step (" +
-                                     std::to_string(all_step) + " bytes)");
+    const bool auto_pool = o.pool_bytes == 0;
+    const size_t steps0 = (size_t)std::min(L, POOL_STEPS0);
     C->pool.cache = &ctx->cache;
     C->work.cache = &ctx->cache;
     BEM_HIP_TRY(hipStreamSynchronize(st));
@@ -414,7 +411,6 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         Ar.pool = C->pool.as<char>();
         Ar.pool_cap = C->pool.bytes;
     };
-    C->pool.alloc(pool_bytes);
     BEM_HIP_TRY(hipMemsetAsync(aux.p, 0, 256, st));
     BEM_HIP_TRY(hipMemsetAsync(C->faces_dev.p, 0, sizeof(FaceDesc) * (size_t)nb * L, st));
     A = CompressArgs{};
@@ -444,15 +440,68 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
     A.eps_aca_far = C->mixed ? std::max(o.eps_aca, o.mixed_eps_floor) : o.eps_aca;
     BEM_HIP_TRY(hipEventRecord(ev0, st));
-    launch_init(A, st);
-    // phase A: 3D-ACA of every block on dense residual faces, one step d per pass; the
-    // face kernels of each step are bracketed by events (read after the next sync)
+    // Block groups: when the faces of every block (POOL_STEPS0 steps each) would not fit the
+    // memory, the blocks are compressed group after group.  Each group runs phases A to C in
+    // the working pool (reused by the next group) and keeps its compacted pool; blocks of
+    // other groups are inactive meanwhile (their states start at zero and k_init skips them).
+    std::vector<std::unique_ptr<DevBuf>> gpools;
+    std::vector<std::vector<int>> gblk;
+    std::vector<unsigned char> selh((size_t)nb, 0);
+    DevBuf sel_dev;
+    sel_dev.alloc((size_t)nb + 64);
+    BEM_HIP_TRY(hipMemsetAsync(st_dev.p, 0, sizeof(BlockState) * nb, st));
+    C->faces.resize((size_t)nb * L);
+    std::vector<FaceDesc> fh((size_t)nb * L);
     std::vector<int> tiles, act;
     face_ms = 0.0;
     face_launches = 0;
     face_pairs = 0;
     face_flop = 0.0;
     face_bytes = 0.0;
+    // auto pool: one group if the faces of all blocks fit 60 % of the free memory; otherwise
+    // groups in a working pool of 30 %, the rest left to the compacted pools of the groups
+    size_t est_all = 0;
+    for (int b = 0; b < nb; ++b) est_all += step_bytes(b) * steps0;
+    const double pool_frac = est_all <= (size_t)(0.6 * (double)avail()) ? 0.6 : 0.3;
+    for (int gpos = 0; gpos < nb;) {
+    std::vector<int> grp;
+    size_t pool_bytes = 0;
+    {
+        // the working pool of the previous group is reused: it counts as available
+        const size_t budget = auto_pool ? std::max((size_t)C->pool.bytes, (size_t)(pool_frac * (double)avail()))
+                                        : (size_t)o.pool_bytes;
+        size_t est = 0, gstep = 0;
+        while (gpos < nb) {
+            const size_t e = step_bytes(gpos) * steps0;
+            if (!grp.empty() && est + e > budget) break;
+            est += e;
+            gstep += step_bytes(gpos);
+            grp.push_back(gpos++);
+        }
+        pool_bytes = auto_pool ? std::min(budget, est) : (size_t)o.pool_bytes;
+        if (pool_bytes < gstep)
+            throw Err(BEM_ERR_NOMEM, "compression pool of " + std::to_string(pool_bytes) + " bytes cannot hold one step (" +
+                                         std::to_string(gstep) + " bytes)");
+    }
+    const bool grouped = !gblk.empty() || gpos < nb;
+    if (C->pool.bytes < pool_bytes) {
+        C->pool.release();
+        C->pool.alloc(pool_bytes);
+    }
+    BEM_HIP_TRY(hipMemsetAsync(top_dev, 0, sizeof(unsigned long long), st));
+    A.pool = C->pool.as<char>();
+    A.pool_cap = C->pool.bytes;
+    A.sel = nullptr;
+    if (grouped) {
+        std::fill(selh.begin(), selh.end(), (unsigned char)0);
+        for (int b : grp) selh[b] = 1;
+        BEM_HIP_TRY(hipMemcpyAsync(sel_dev.p, selh.data(), (size_t)nb, hipMemcpyHostToDevice, st));
+        A.sel = sel_dev.as<unsigned char>();
+    }
+    launch_init(A, st);
+    A.sel = nullptr;
+    // phase A: 3D-ACA of every block on dense residual faces, one step d per pass; the
+    // face kernels of each step are bracketed by events (read after the next sync)
     bool face_pending = false;
     // between steps only the blocks' activity comes back: one byte per block, pinned
     DevBuf flags_dev;
@@ -547,7 +596,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         face_ms += ms;
     }
     std::vector<int> fb_blocks, fb_tiles;
-    for (int b = 0; b < nb; ++b)
+    for (int b : grp)
         if (S[b].fallback) {
             fb_blocks.push_back(b);
             for (int t = 0; t < C->blocks[b].ntile; ++t) fb_tiles.push_back((b << 12) | t);
@@ -580,7 +629,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     BEM_HIP_TRY(hipMemcpy(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost));
     // phase B: per-slice ACA + recompression of the far faces of the ACA blocks, in place
     std::vector<int> items;
-    for (int b = 0; b < nb; ++b)
+    for (int b : grp)
         if (C->blocks[b].aca && !S[b].fallback)
             for (int d = 0; d < S[b].rank; ++d) items.push_back((b << 8) | d);
     // largest faces first: the long workgroups start early instead of forming the tail
@@ -626,20 +675,19 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     }
     BEM_HIP_TRY(hipEventRecord(ev2, st));
     BEM_HIP_TRY(hipStreamSynchronize(st));
-    BEM_HIP_TRY(hipEventElapsedTime(&kms, ev0, ev2));
-    BEM_HIP_TRY(hipEventElapsedTime(&aca_ms, ev1, ev2));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    (void)hipEventDestroy(ev2);
-    (void)hipEventDestroy(evf0);
-    (void)hipEventDestroy(evf1);
+    {
+        float ms = 0.f;
+        BEM_HIP_TRY(hipEventElapsedTime(&kms, ev0, ev2));
+        BEM_HIP_TRY(hipEventElapsedTime(&ms, ev1, ev2));
+        aca_ms += ms;
+    }
     BEM_HIP_TRY(hipMemcpy(S.data(), st_dev.p, sizeof(BlockState) * nb, hipMemcpyDeviceToHost));
-    C->faces.resize((size_t)nb * L);
-    BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L, hipMemcpyDeviceToHost));
+    BEM_HIP_TRY(hipMemcpy(fh.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L, hipMemcpyDeviceToHost));
+    for (int b : grp) std::copy(fh.begin() + (size_t)b * L, fh.begin() + (size_t)(b + 1) * L, C->faces.begin() + (size_t)b * L);
 
     // phase C: compaction of the kept faces, factors and fibres into a pool of exact size
     {
-        auto face_bytes = [&](const FaceDesc& f, const BlockIn& B) -> long long {
+        auto kept_bytes = [&](const FaceDesc& f, const BlockIn& B) -> long long {
             const long long zs = f.fp32 ? (long long)sizeof(zf) : (long long)sizeof(zd);
             if (f.kk == 0) return zs * 9 * B.rs * B.cs;
             if (f.kk > 0) return zs * 3 * (B.rs + B.cs) * f.kk;
@@ -648,11 +696,11 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         auto up256 = [](long long v) { return (v + 255) & ~255LL; };
         std::vector<long long> seg;
         long long top = 0;
-        for (int b = 0; b < nb; ++b) {
+        for (int b : grp) {
             const BlockIn& B = C->blocks[b];
             for (int d = 0; d < S[b].rank; ++d) {
                 FaceDesc& f = C->faces[(size_t)b * L + d];
-                const long long fb = face_bytes(f, B);
+                const long long fb = kept_bytes(f, B);
                 if (fb > 0) {
                     seg.insert(seg.end(), {f.face_off, top, fb});
                     f.face_off = top;
@@ -679,12 +727,55 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
                 launch_copy_segments(C->pool.as<char>(), np.as<char>(), segd.as<long long>(), nseg, st);
             }
             BEM_HIP_TRY(hipStreamSynchronize(st));
-            C->pool.swap(np);
+            if (grouped) {
+                gpools.push_back(std::make_unique<DevBuf>(&ctx->cache));
+                gpools.back()->swap(np);
+                gblk.push_back(grp);
+            } else {
+                C->pool.swap(np);
+            }
             np.release();
         } else {
-            BEM_HIP_TRY(hipMemcpy(C->faces.data(), C->faces_dev.p, sizeof(FaceDesc) * (size_t)nb * L,
-                                  hipMemcpyDeviceToHost));
+            // not enough memory for the copy: a single group keeps its working pool
+            if (grouped) {
+                size_t kept = 0;
+                for (const auto& g : gpools) kept += g->bytes;
+                throw Err(BEM_ERR_NOMEM, "device memory exhausted by the compaction of block group " +
+                                             std::to_string(gpools.size()) + " (" + std::to_string(top) +
+                                             " bytes; earlier groups hold " + std::to_string(kept) +
+                                             " bytes, the working pool " + std::to_string(C->pool.bytes) + ")");
+            }
+            for (int b : grp)
+                std::copy(fh.begin() + (size_t)b * L, fh.begin() + (size_t)(b + 1) * L, C->faces.begin() + (size_t)b * L);
         }
+    }
+    }  // block groups
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    (void)hipEventDestroy(ev2);
+    (void)hipEventDestroy(evf0);
+    (void)hipEventDestroy(evf1);
+    if (!gpools.empty()) {
+        // the operator's pool is the group pool at the lowest address; the faces of every
+        // group are addressed from its base
+        C->pool.release();
+        size_t lo = 0;
+        for (size_t g = 1; g < gpools.size(); ++g)
+            if ((uintptr_t)gpools[g]->p < (uintptr_t)gpools[lo]->p) lo = g;
+        const uintptr_t base = (uintptr_t)gpools[lo]->p;
+        for (size_t g = 0; g < gpools.size(); ++g) {
+            const long long delta = (long long)((uintptr_t)gpools[g]->p - base);
+            for (int b : gblk[g])
+                for (int d = 0; d < S[b].rank; ++d) {
+                    FaceDesc& f = C->faces[(size_t)b * L + d];
+                    f.face_off += delta;
+                    f.fib_off += delta;
+                }
+        }
+        C->pool.swap(*gpools[lo]);
+        for (size_t g = 0; g < gpools.size(); ++g)
+            if (g != lo) C->extra_pools.push_back(std::move(gpools[g]));
+        C->ngroups_c = (int)gpools.size();
     }
     C->faces_dev.release();
     build_apply_plan(*C, st);
@@ -741,6 +832,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.face_pairs = face_pairs;
     R.face_flop = face_flop;
     R.face_bytes = face_bytes;
+    R.block_groups = C->ngroups_c;
     R.recomp_ms = recomp_ms;
     R.recomp_launches = recomp_launches;
     R.recomp_flop = rflop;
