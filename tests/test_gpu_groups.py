@@ -55,3 +55,36 @@ def test_grouped_compression_matches_single_group(prec):
     for o in (V1, Vg):
         o.destroy()
     c.close()
+
+
+def test_grouped_operator_in_transposed_and_batched_products():
+    # the faces of a grouped operator live in several pools addressed from the lowest base:
+    # the transposed product and a batch with another operator address them the same way
+    X, T = W.icosphere(3)
+    L = 16
+    s = W.bdf2_contour(L, 0.1)
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(1.0, 1.0, 0.5)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=True)
+    rows, _ = c.partition(eta=1.5, leaf=64)
+    est = _step_bytes(rows, L, True) * min(L, 32)
+    pool = int(max(est.max(), 0.3 * est.sum()))
+    V1 = c.compress(B.OP_V, eps3d=1e-6, leaf=64, eta=1.5, prec=B.PREC_MIXED)
+    Vg = c.compress(B.OP_V, eps3d=1e-6, leaf=64, eta=1.5, prec=B.PREC_MIXED, pool_bytes=pool)
+    H1 = c.compress(B.OP_HK, eps3d=1e-6, leaf=64, eta=1.5, prec=B.PREC_MIXED, pool_bytes=pool)
+    assert Vg.stats()["block_groups"] >= 3 and H1.stats()["block_groups"] >= 3
+    x = W.random_rhs(6, (2, L, 3 * len(T)))
+    yt1 = V1.apply(x, transpose=True)
+    ytg = Vg.apply(x, transpose=True)
+    assert np.abs(ytg - yt1).max() <= 1e-13 * np.abs(yt1).max()
+    xh = W.random_rhs(7, (2, L, 3 * len(T)))
+    bt = B.Batch([Vg, H1], nrhs=2)
+    yv, yh = bt.apply([x, xh])
+    assert np.abs(yv - V1.apply(x)).max() <= 1e-12 * np.abs(yv).max()
+    assert np.abs(yh - H1.apply(xh)).max() <= 1e-12 * np.abs(yh).max()
+    bt.destroy()
+    for o in (V1, Vg, H1):
+        o.destroy()
+    c.close()
