@@ -1011,28 +1011,33 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
     double v1[1] = {fn2};
     wg_sum<1>(v1, S);
     wg_argmax(best, bk, S);
-    // F_da = sum_k f_d[k] f_a[k]^H for a <= d
-    for (int a = 0; a <= d; ++a) {
-        double Fv[18];
+    // F_da = sum_k f_d[k] f_a[k]^H for a <= d: one wavefront per face a, its lanes over k,
+    // a wavefront reduction each (no workgroup barrier per face)
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int a = w; a <= d; a += WG / 64) {
+            double Fv[18];
 #pragma unroll
-        for (int t = 0; t < 18; ++t) Fv[t] = 0.0;
-        const zd* fa = (const zd*)(A.pool + fd[a].fib_off);
-        for (int k = threadIdx.x; k < L; k += WG) {
-            blk x = ld_blk9(f + (size_t)k * 9), y = ld_blk9(fa + (size_t)k * 9);
+            for (int t = 0; t < 18; ++t) Fv[t] = 0.0;
+            const zd* fa = (const zd*)(A.pool + fd[a].fib_off);
+            for (int k = lane; k < L; k += 64) {
+                blk x = ld_blk9(f + (size_t)k * 9), y = ld_blk9(fa + (size_t)k * 9);
 #pragma unroll
-            for (int r = 0; r < 3; ++r)
+                for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    zd s = {0.0, 0.0};
+                    for (int c = 0; c < 3; ++c) {
+                        zd s = {0.0, 0.0};
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) s += mul_conj(x.a[3 * r + q], y.a[3 * c + q]);
-                    Fv[2 * (3 * r + c)] += s.re;
-                    Fv[2 * (3 * r + c) + 1] += s.im;
-                }
+                        for (int q = 0; q < 3; ++q) s += mul_conj(x.a[3 * r + q], y.a[3 * c + q]);
+                        Fv[2 * (3 * r + c)] += s.re;
+                        Fv[2 * (3 * r + c) + 1] += s.im;
+                    }
+            }
+#pragma unroll
+            for (int t = 0; t < 18; ++t) Fv[t] = wsum(Fv[t]);
+            if (lane == 0)
+                for (int t = 0; t < 9; ++t) A.Fda[((size_t)b * L + a) * 9 + t] = {Fv[2 * t], Fv[2 * t + 1]};
         }
-        wg_sum<18>(Fv, S);
-        if (threadIdx.x == 0)
-            for (int t = 0; t < 9; ++t) A.Fda[((size_t)b * L + a) * 9 + t] = {Fv[2 * t], Fv[2 * t + 1]};
     }
     if (threadIdx.x == 0) {
         A.st[b].fn2 = v1[0];
