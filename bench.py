@@ -43,8 +43,8 @@ PEAK_HBM = 8.0e12    # HBM3E bytes/s
 # this script, scaled by the counts of a 1 GiB copy; profiles/traffic_c2_sphere5120_L64_mixed.md),
 # valid while the kernels' sources hash to the recorded value
 TRAFFIC = {
-    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp'], "sha256_16": '2b65300dd1e51f96'},
-    "recomp": {"bytes": 4.649e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp'], "sha256_16": 'a2213f77c36a1155'},
+    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp'], "sha256_16": '39a39f257fdd305a'},
+    "recomp": {"bytes": 4.65e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp'], "sha256_16": 'a2213f77c36a1155'},
 }
 
 

@@ -966,17 +966,24 @@ __global__ __launch_bounds__(WG) void k_fibre(CompressArgs A)
     // a near or self pivot pair spreads each entry's rule over a group of lanes
     const int gi = B.rb + pi, gj = B.cb + pj;
     const int cls = GEN ? pair_class(A.c.geo, gi, gj, A.c.qt) : CLS_REGULAR;
-    const int lpp = pair_lanes(cls), nu = GEN ? rule_units(cls, A.c.qt) : 1;
+    // regular rule: the entry on the first lane of a group, the residual over the earlier
+    // faces shared by the group's lanes (as many as the L frequencies leave in the workgroup)
+    int lpp = pair_lanes(cls);
+    if (!GEN)
+        while (lpp < 64 && 2 * lpp * L <= WG) lpp *= 2;
+    const int nu = GEN ? rule_units(cls, A.c.qt) : 1;
     const int u = threadIdx.x % lpp;
     for (int k0 = 0; k0 < L; k0 += WG / lpp) {
         const int k = k0 + threadIdx.x / lpp;
         blk E = blk_zero();
         if (k < L) {
             if constexpr (KOP == 2) {
-                E = entry_dispatch<false>(A.c, OP_TABLE, gi, gj, k);
+                if (u == 0) E = entry_dispatch<false>(A.c, OP_TABLE, gi, gj, k);
             } else if constexpr (!GEN) {
-                if (B.f32) entry_regular<float>(A.c.geo, KOP, gi, gj, A.c.fr.sf[k], A.c.fr.sinvf[k], A.c.mf, E);
-                else entry_regular<double>(A.c.geo, KOP, gi, gj, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, E);
+                if (u == 0) {
+                    if (B.f32) entry_regular<float>(A.c.geo, KOP, gi, gj, A.c.fr.sf[k], A.c.fr.sinvf[k], A.c.mf, E);
+                    else entry_regular<double>(A.c.geo, KOP, gi, gj, A.c.fr.s[k], A.c.fr.sinv[k], A.c.md, E);
+                }
             } else {
                 for (int uu = u; uu < nu; uu += lpp) {
                     blk e;
