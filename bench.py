@@ -307,8 +307,8 @@ def main():
         print(json.dumps({"copy_bytes": n * 16, "copies": 3}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the sharded path is designed, not built); "
-              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU; sharding the blocks over several GPUs is not "
+              "implemented, so --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

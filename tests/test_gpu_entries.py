@@ -1,10 +1,10 @@
 """GPU parity of the raw entry generator and the dense all-frequency products against the
 FP64 oracle, through the C-ABI.
 
-Tolerances (derived in the design doc): FP64 entries agree elementwise to
-1e-13 * max|entry| + 1e-10 * |entry| (same rules, different but equivalent formulas and
-summation order; the principal-value self term of K loses ~1e-11 of itself to cancellation).
-Mixed entries (regular pairs in FP32) agree to 3e-6 of the largest entry of their block row.
+Tolerances: FP64 entries agree elementwise to 1e-13 * max|entry| + 1e-10 * |entry| (same
+rules, different but equivalent formulas and summation order; the principal-value self term
+of K loses ~1e-11 of itself to cancellation).  Mixed entries (regular pairs in FP32, 7-point
+sums of unit-roundoff 6e-8 terms) agree to 3e-6 of the largest entry of their block row.
 """
 import numpy as np
 import pytest
