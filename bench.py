@@ -41,10 +41,11 @@ PEAK_HBM = 8.0e12    # HBM3E bytes/s
 
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counters (two rocprofv3 --pmc runs of
 # this script, scaled by the counts of a 1 GiB copy; profiles/traffic_c2_sphere5120_L64_mixed.md),
-# valid while the kernels' sources hash to the recorded value
+# valid while the kernels' sources and the launch composition (compress.cpp) hash to the
+# recorded value
 TRAFFIC = {
-    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp'], "sha256_16": '39a39f257fdd305a'},
-    "recomp": {"bytes": 4.65e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp'], "sha256_16": 'a2213f77c36a1155'},
+    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp', 'compress.cpp'], "sha256_16": '0aaad72f98dea4e3'},
+    "recomp": {"bytes": 8.82e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": 'a712f7b478606821'},
 }
 
 

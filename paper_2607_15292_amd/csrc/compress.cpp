@@ -58,7 +58,7 @@ constexpr int KMAX_ACA = 96;       // column capacity of the per-slice ACA scrat
 constexpr double QPTS_REGULAR = 7.0;
 constexpr double FLOPS_RESIDUAL = 216.0;
 double flops_eval(int op) { return op == BEM_OP_V ? 125.0 : (op == BEM_OP_TABLE ? 0.0 : 236.0); }
-constexpr size_t ACA_SLOTS = 4096;  // faces per launch of the per-slice ACA pass (scratch slots)
+constexpr size_t ACA_SLOTS = 8192;  // faces per launch of the per-slice ACA pass (scratch slots)
 constexpr int POOL_STEPS0 = 32;     // 3D-ACA steps of every block in the initial pool
 
 // Segments: each row group's face list cut into pieces of about equal work (the staged inner
