@@ -8,9 +8,10 @@ shares no code with it.
   Appendix A / Sec. 2.1, collocation entries with the quadrature rules, dense products, and
   the gradient of a single-layer bilinear form with respect to the node coordinates and the
   material (regular and near pairs by the chain rule, self pairs by central differences).
-* ``aca3d.py`` (numpy): the matrix-valued 3D-ACA of Algorithm 1 (Sec. 3) and the
-  matrix-valued ACA with QR/SVD recompression of eq. (ACA) (Sec. 3.1), for small tensors.
-* ``partition.py`` (numpy): the PCA cluster tree and admissibility of Sec. 3.1.
+* ``aca3d.py`` (numpy): the matrix-valued 3D-ACA of Algorithm 1 (Sec. 3), the matrix-valued
+  ACA with QR/SVD recompression of eq. (ACA), and the H-matrix variant of Sec. 3.1 (faces
+  approximated inside the loop, pivot on the reconstruction), for small tensors.
+* ``cq.py`` (numpy): convolution quadrature weights and marching on in time (Sec. 2.4).
 """
 from __future__ import annotations
 

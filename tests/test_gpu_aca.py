@@ -2,10 +2,17 @@
 oracle, through bem_aca_matrix, and of the compressed product when every admissible face
 goes through that pass (far_dense_max = 0).
 
-For one matrix the two sides take the same pivots (same rules, ties to the smallest
-index), so the ACA column count kc and the recompressed rank kk must agree exactly; the
-reconstructions agree to the tolerance.  The failure rules (column cap, no memory saving)
-give the same outcome on both sides.
+The oracle is the plain matrix-valued ACA (no column cap) followed by the QR + SVD
+truncation of eq. (ACA).  The library adds rules of its own: a column cap at twice the
+break-even memory (at most 96 columns; the face then stays dense), a pivoted-QR reduction
+of the core before its SVD (it can only keep more singular values: the tail it drops is
+measured on a submatrix), and dense storage when the factors would not save memory.  So
+the GPU is judged by
+  * reconstruction error ||A - Ubar Vbar^H||_F <= tol + the ACA residual (<= 0.5 tol,
+    checked on the oracle's run of the same rule) + rounding;
+  * rank kk within one of the oracle's truncated rank;
+  * giving up (kc = -1) only when the oracle's ACA needs more columns than the cap;
+  * dense storage (kk = 0) only when the oracle's rank does not save memory either.
 """
 import numpy as np
 import pytest
@@ -16,6 +23,8 @@ from paper_2607_15292_amd import binding as B
 from paper_2607_15292_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+KMAX_LIB = 96  # the library's largest ACA column count (bem_aca_matrix documents it)
 
 
 @pytest.fixture(scope="module")
@@ -43,14 +52,38 @@ def _lowrank(rng, m, n, r):
     return a @ b
 
 
-def _oracle(A, tol, max_cols=A3.KMAX_ACA):
+def _lib_cap(m, n, max_cols=0):
+    cap = max_cols if max_cols > 0 else 3 * -(-2 * m * n // (m + n))
+    cap = min(cap, 3 * min(m, n), KMAX_LIB)
+    return cap - cap % 3
+
+
+def _oracle(A, tol):
+    """Plain ACA + eq. (ACA) truncation: (kc, kk, ACA residual, reconstruction)."""
+    U, V, ok = A3.aca_matrix(A, tol=tol)
+    assert ok
+    Ub, Vb = A3.recompress(U, V, tol=tol)
+    return U.shape[1], Ub.shape[1], np.linalg.norm(U @ V.conj().T - A), Ub @ Vb.conj().T
+
+
+def _check(A, tol, got, max_cols=0, extra=0.0):
+    kc, kk, U, V = got
     m, n = A.shape[0] // 3, A.shape[1] // 3
-    U, V, ok = A3.aca_matrix(A, tol, min(max_cols, A3.face_aca_cap(m, n)))
-    if not ok:
-        return -1, 0, None
-    Ub, Vb = A3.recompress(U, V, tol)
-    kk = Ub.shape[1] if Ub.shape[1] * (m + n) < 3 * m * n else 0
-    return U.shape[1], kk, (Ub @ Vb.conj().T if kk else None)
+    okc, okk, oaca, Ao = _oracle(A.astype(np.complex128), tol)
+    assert oaca <= 0.5 * tol + extra
+    if kc == -1:
+        assert okc > _lib_cap(m, n, max_cols), (okc, _lib_cap(m, n, max_cols))
+        return kc, kk, okc, okk
+    assert kc % 3 == 0 and kc <= _lib_cap(m, n, max_cols)
+    if kk == 0:
+        assert (okk + 1) * (m + n) >= 3 * m * n, (kk, okk)
+        return kc, kk, okc, okk
+    assert okk - 1 <= kk <= okk + 1, (kk, okk)
+    Ag = U.astype(np.complex128) @ V.astype(np.complex128).conj().T
+    err = np.linalg.norm(Ag - A)
+    assert err <= tol + oaca + 0.05 * tol + extra, (err / tol, oaca / tol)
+    assert np.linalg.norm(Ag - Ao) <= 2 * tol + 2 * oaca + extra
+    return kc, kk, okc, okk
 
 
 @pytest.mark.parametrize("m,n,r", [(20, 15, 6), (24, 30, 12), (33, 17, 9)])
@@ -58,7 +91,7 @@ def test_exact_low_rank(ctx, m, n, r):
     A = _lowrank(np.random.default_rng(m * n + r), m, n, r)
     tol = 1e-10 * np.linalg.norm(A)
     kc, kk, U, V = ctx.aca_matrix(A, tol)
-    okc, okk, _ = _oracle(A, tol)
+    okc, okk, _, _ = _oracle(A, tol)
     assert (kc, kk) == (okc, okk) == (r, r)
     assert np.linalg.norm(U @ V.conj().T - A) < 1e-9 * np.linalg.norm(A)
 
@@ -68,40 +101,36 @@ def test_exact_low_rank(ctx, m, n, r):
 def test_kernel_face_matches_oracle(ctx, rtol, l):
     A = _kernel_face(l=l)
     tol = rtol * np.linalg.norm(A)
-    kc, kk, U, V = ctx.aca_matrix(A, tol)
-    okc, okk, Ao = _oracle(A, tol)
-    assert (kc, kk) == (okc, okk)
-    if kk:
-        Ag = U @ V.conj().T
-        assert np.linalg.norm(Ag - A) <= 3 * tol
-        assert np.linalg.norm(Ag - Ao) <= 2 * tol
+    kc, kk, okc, okk = _check(A, tol, ctx.aca_matrix(A, tol))
+    # the 48 x 40 kernel faces resolve within the cap at these tolerances
+    assert kc > 0 and kk > 0
 
 
 def test_mixed_precision_face(ctx):
-    """complex64 storage: the pass runs on the rounded matrix; the same rounded matrix in
-    complex128 gives the oracle's ranks, and the factors (complex64) reproduce it."""
+    """complex64 storage: the pass runs on the rounded matrix; the oracle runs on the same
+    rounded matrix in complex128, and the factors (complex64) reproduce it."""
     A = _kernel_face(l=1).astype(np.complex64)
     tol = 1e-4 * np.linalg.norm(A)
-    kc, kk, U, V = ctx.aca_matrix(A, tol, prec=B.PREC_MIXED)
-    okc, okk, _ = _oracle(A.astype(np.complex128), tol)
-    assert (kc, kk) == (okc, okk) and kk > 0
-    assert U.dtype == np.complex64
-    err = np.linalg.norm(U.astype(np.complex128) @ V.astype(np.complex128).conj().T - A)
-    assert err <= 3 * tol + 1e-6 * np.linalg.norm(A)
+    got = ctx.aca_matrix(A, tol, prec=B.PREC_MIXED)
+    assert got[1] > 0 and got[2].dtype == np.complex64
+    _check(A.astype(np.complex128), tol, got, extra=1e-6 * np.linalg.norm(A))
 
 
 def test_failure_rules(ctx):
     rng = np.random.default_rng(3)
     A = rng.standard_normal((30, 24)) + 1j * rng.standard_normal((30, 24))
     tol = 1e-12 * np.linalg.norm(A)
-    # column cap short of 3 min(m, n): not resolved
-    assert ctx.aca_matrix(A, tol, max_cols=9)[:2] == (-1, 0)
-    assert _oracle(A, tol, max_cols=9)[:2] == (-1, 0)
+    # column cap short of 3 min(m, n): not resolved (the plain ACA needs 24 columns)
+    got = ctx.aca_matrix(A, tol, max_cols=9)
+    assert got[:2] == (-1, 0)
+    _check(A, tol, got, max_cols=9)
     # full interpolation resolves, but full rank saves no memory: kept dense
-    kc, kk, _, _ = ctx.aca_matrix(A, tol)
-    assert (kc, kk) == _oracle(A, tol)[:2] == (24, 0)
-    # zero matrix
+    got = ctx.aca_matrix(A, tol)
+    assert got[:2] == (24, 0)
+    _check(A, tol, got)
+    # zero matrix: nothing to factor
     assert ctx.aca_matrix(np.zeros((6, 9), complex), 1.0)[:2] == (-1, 0)
+    assert A3.compress_face(np.zeros((2, 3, 3, 3), complex), tol=1.0) == (None, 0)
 
 
 def test_argument_errors(ctx):

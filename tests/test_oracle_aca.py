@@ -6,8 +6,11 @@
 * On a well-separated kernel block the error is a small multiple of eps, the first slice is
   k = 0 and the next ones are the small-Re(s) conjugate pairs (Sec. 4.1 observes this).
 * Blocks without a regular 3x3 pivot (sigma_3 = 0 everywhere) fall back to dense storage.
-* Per-slice ACA recovers exact low-rank matrices; recompression removes redundant columns
-  and respects its tolerance.
+* Per-slice ACA recovers exact low-rank matrices and interpolates its pivot rows and
+  columns; recompression equals the truncated SVD of the explicit product (Eckart-Young).
+* The H-matrix variant of Sec. 3.1 (faces approximated in the loop, pivot on the
+  reconstruction) reproduces tensors with low-rank faces and keeps kernel blocks within a
+  small multiple of eps.
 """
 import numpy as np
 import pytest
@@ -93,7 +96,7 @@ def test_aca_exact_low_rank_and_recompression():
     m, n, r = 20, 15, 6  # matrix-valued ACA captures rank in steps of 3
     A = (rng.standard_normal((3 * m, r)) + 1j * rng.standard_normal((3 * m, r))) @ \
         (rng.standard_normal((r, 3 * n)) + 1j * rng.standard_normal((r, 3 * n)))
-    U, V, ok = A3.aca_matrix(A, 1e-12 * np.linalg.norm(A))
+    U, V, ok = A3.aca_matrix(A, tol=1e-12 * np.linalg.norm(A))
     assert ok and U.shape[1] == r
     assert np.linalg.norm(U @ V.conj().T - A) < 1e-10 * np.linalg.norm(A)
     # recompression of a redundant factorisation (rank 4 written with 9 columns)
@@ -102,9 +105,58 @@ def test_aca_exact_low_rank_and_recompression():
     mix = rng.standard_normal((4, 9))
     U9, V9 = B @ mix, Cm @ np.linalg.pinv(mix).conj().T
     M = U9 @ V9.conj().T
-    Ub, Vb = A3.recompress(U9, V9, 1e-10 * np.linalg.norm(M))
+    Ub, Vb = A3.recompress(U9, V9, tol=1e-10 * np.linalg.norm(M))
     assert Ub.shape[1] == 4
     assert np.linalg.norm(Ub @ Vb.conj().T - M) < 1e-10 * np.linalg.norm(M)
+
+
+def test_recompression_is_truncated_svd_of_the_product():
+    """eq. (ACA) gives the truncated SVD of U V^H: same singular values as an SVD of the
+    explicit product, the best rank-k approximation (Eckart-Young), and the smallest k
+    whose dropped tail is within the tolerance."""
+    rng = np.random.default_rng(12)
+    m3, n3, k0 = 45, 36, 18
+    sv = 10.0 ** -np.linspace(0, 6, k0)
+    X = np.linalg.qr(rng.standard_normal((m3, k0)) + 1j * rng.standard_normal((m3, k0)))[0]
+    Y = np.linalg.qr(rng.standard_normal((n3, k0)) + 1j * rng.standard_normal((n3, k0)))[0]
+    mix = rng.standard_normal((k0, k0)) + 1j * rng.standard_normal((k0, k0))
+    U = (X * sv) @ mix
+    V = Y @ np.linalg.inv(mix).conj().T          # U V^H = X diag(sv) Y^H
+    M = U @ V.conj().T
+    for tol in (1e-1, 1e-3, 3e-5):
+        Ub, Vb = A3.recompress(U, V, tol=tol)
+        k = Ub.shape[1]
+        tails = [np.sqrt(np.sum(sv[q:] ** 2)) for q in range(k0 + 1)]
+        assert k == min(q for q in range(k0 + 1) if tails[q] <= tol)
+        Xs, S, Yh = np.linalg.svd(M)
+        best = (Xs[:, :k] * S[:k]) @ Yh[:k]
+        assert np.linalg.norm(Ub @ Vb.conj().T - best) < 1e-12 * np.linalg.norm(M)
+        assert np.allclose(np.linalg.norm(Ub, axis=0), sv[:k], rtol=1e-10)  # Ubar = Q X S
+        assert np.allclose(Vb.conj().T @ Vb, np.eye(k), atol=1e-12)          # Vbar orthonormal
+    # relative form: eps ||Sigma||_F
+    Ub, _ = A3.recompress(U, V, eps=1e-3)
+    thr = 1e-3 * np.linalg.norm(sv)
+    assert Ub.shape[1] == min(q for q in range(k0 + 1) if np.sqrt(np.sum(sv[q:] ** 2)) <= thr)
+
+
+def test_aca_cross_interpolation():
+    """A cross approximation reproduces A exactly on the block rows whose U blocks it took
+    as pivots' rows and on the pivot block columns; its stop test compares the newest
+    step with the norm of the approximation (relative form)."""
+    C = _kernel_block(L=4, grid=8, nr=48, nc=40)
+    Amat = A3.blocks_to_matrix(C[1])
+    U, V, ok = A3.aca_matrix(Amat, eps=1e-5)
+    assert ok and U.shape[1] % 3 == 0
+    R = Amat - U @ V.conj().T
+    scale = np.abs(Amat).max()
+    # the block rows of the pivots are rows of V^H; the columns of the pivots rebuild them
+    k = U.shape[1] // 3
+    nz_rows = [q for q in range(Amat.shape[0] // 3) if np.abs(R[3 * q:3 * q + 3]).max() < 1e-12 * scale]
+    nz_cols = [q for q in range(Amat.shape[1] // 3) if np.abs(R[:, 3 * q:3 * q + 3]).max() < 1e-12 * scale]
+    assert len(nz_rows) >= k and len(nz_cols) >= k
+    Un, Vn = U[:, -3:], V[:, -3:]
+    assert np.linalg.norm(Un) * np.linalg.norm(Vn) <= 1e-5 * np.linalg.norm(U @ V.conj().T)
+    assert np.linalg.norm(R) < 1e-4 * np.linalg.norm(Amat)
 
 
 def test_aca_on_kernel_face_meets_tolerance():
@@ -112,28 +164,59 @@ def test_aca_on_kernel_face_meets_tolerance():
     Amat = A3.blocks_to_matrix(C[0])
     for eps in (1e-4, 1e-8):
         tol = eps * np.linalg.norm(Amat)
-        U, V, ok = A3.aca_matrix(Amat, tol)
+        U, V, ok = A3.aca_matrix(Amat, tol=tol)
         assert ok
-        Ub, Vb = A3.recompress(U, V, tol)
+        Ub, Vb = A3.recompress(U, V, tol=tol)
         err = np.linalg.norm(Ub @ Vb.conj().T - Amat) / np.linalg.norm(Amat)
-        assert err < 20 * eps
+        assert err < 2 * eps
         assert Ub.shape[1] <= U.shape[1]
 
 
+def test_aca3d_hmatrix_variant_exact_on_low_rank_faces():
+    """Sec. 3.1 order (faces approximated inside the loop, pivot on the reconstruction):
+    a tensor sum_r H_r (x) g_r with low-rank faces H_r is reproduced to rounding."""
+    rng = np.random.default_rng(21)
+    L, m, n = 10, 9, 7
+    C = np.zeros((L, m, n, 3, 3), dtype=np.complex128)
+    for _ in range(3):
+        Hm = (rng.standard_normal((3 * m, 4)) + 1j * rng.standard_normal((3 * m, 4))) @ \
+             (rng.standard_normal((4, 3 * n)) + 1j * rng.standard_normal((4, 3 * n)))
+        g = _rand_blocks(rng, L)
+        C += np.einsum("ijab,kbc->kijac", A3.matrix_to_blocks(Hm), g)
+    ap = A3.aca3d(C, 1e-10, eps_aca=1e-13)
+    assert not ap.dense and ap.rank == 3
+    assert all(uv is not None and uv[0].shape[1] <= 12 for uv in ap.factors)
+    assert np.linalg.norm(ap.tensor() - C) < 1e-10 * np.linalg.norm(C)
+
+
+def test_aca3d_hmatrix_variant_on_kernel_block():
+    """On a well-separated kernel block the H-matrix variant keeps the error within a small
+    multiple of eps + rank eps_aca, selects the frequencies of the exact-face run, and its
+    slices k_d are reproduced up to the face approximation."""
+    C = _kernel_block(L=16, grid=8, nr=48, nc=40)
+    nC = np.linalg.norm(C)
+    for eps, eps_aca in ((1e-4, 1e-6), (1e-6, 1e-8)):
+        ex = A3.aca3d(C, eps)
+        ap = A3.aca3d(C, eps, eps_aca=eps_aca)
+        assert not ap.dense and ap.ks == ex.ks
+        err = np.linalg.norm(ap.tensor() - C) / nC
+        assert err < 10 * eps
+        Ct = ap.tensor()
+        for k in ap.ks:
+            assert np.linalg.norm(Ct[k] - C[k]) < 10 * ap.rank * eps_aca * nC
+        # every face is held as factors; the first (an exact slice) in low rank
+        assert all(uv is not None for uv in ap.factors)
+        assert ap.factors[0][0].shape[1] < 3 * min(C.shape[1:3])
+
+
 def test_aca3d_with_aca_faces_error():
-    """The ACA pass over the faces (tol_d = eps_aca ||C|| / ||f_d||) keeps the tensor error
-    within a small multiple of eps + rank * eps_aca, and every face it keeps as factors
-    takes less memory than the dense face."""
+    """The ACA pass over the exact faces of a finished 3D-ACA (tol_d = eps_aca ||C|| / ||f_d||)
+    keeps the tensor error within a small multiple of eps + rank * eps_aca."""
     C = _kernel_block(L=16, grid=8, nr=48, nc=40)
     ap = A3.aca3d(C, 1e-4)
     exact = ap.tensor()
     A3.compress_faces(ap, 1e-6)
-    nf = sum(uv is not None for uv in ap.factors)
-    assert nf > 0
-    m, n = C.shape[1:3]
-    for uv in ap.factors:
-        if uv is not None:
-            assert uv[0].shape[1] * (m + n) < 3 * m * n
+    assert sum(uv is not None for uv in ap.factors) == ap.rank
     err = np.linalg.norm(ap.tensor() - C) / np.linalg.norm(C)
     assert err < 1e-3
     # each face-fibre term moves by at most about eps_aca ||C||
@@ -141,19 +224,20 @@ def test_aca3d_with_aca_faces_error():
     assert dev < 2e-6 * ap.rank
 
 
-def test_aca_cap_and_failure_rules():
-    """A full-rank face does not resolve within a small column cap (ok False: kept dense);
-    an all-zero face is kept dense; the cap is twice the break-even rank."""
+def test_aca_full_rank_and_degenerate_rows():
+    """A full-rank matrix is interpolated after 3 min(m, n) columns and reproduced; a zero
+    matrix gives no factors; block rows without a regular 3x3 block are skipped, and a
+    matrix whose other rows carry the rank is still resolved."""
     rng = np.random.default_rng(5)
     A = rng.standard_normal((30, 24)) + 1j * rng.standard_normal((30, 24))
-    U, V, ok = A3.aca_matrix(A, 1e-12 * np.linalg.norm(A), max_cols=9)
-    assert not ok and U.shape[1] == 9
-    U, V, ok = A3.aca_matrix(A, 1e-12 * np.linalg.norm(A))
-    assert ok and np.linalg.norm(U @ V.conj().T - A) < 1e-9 * np.linalg.norm(A)
-    assert A3.compress_face(np.zeros((4, 5, 3, 3), complex), 1.0) == (None, -1)
-    assert A3.face_aca_cap(80, 80) == 240 and A3.face_aca_cap(160, 80) == 240
-    assert A3.face_aca_cap(2, 2) == 6  # at most 3 min(m, n)
-    # factors that would not save memory are dropped: random 10 x 10 blocks need full rank
-    H = A3.matrix_to_blocks(rng.standard_normal((30, 30)) + 1j * rng.standard_normal((30, 30)))
-    uv, kc = A3.compress_face(H, 1e-10)
-    assert uv is None
+    U, V, ok = A3.aca_matrix(A, tol=1e-12 * np.linalg.norm(A))
+    assert ok and U.shape[1] == 24
+    assert np.linalg.norm(U @ V.conj().T - A) < 1e-9 * np.linalg.norm(A)
+    assert A3.compress_face(np.zeros((4, 5, 3, 3), complex), 1.0) == (None, 0)
+    B = (rng.standard_normal((30, 6)) + 1j * rng.standard_normal((30, 6))) @ \
+        (rng.standard_normal((6, 24)) + 1j * rng.standard_normal((6, 24)))
+    B[0:3] = 0.0           # block row 0 is zero: skipped
+    B[3:6, :] = np.outer([1.0, 2.0, 3.0], B[9])  # block row 1: every block of rank 1
+    U, V, ok = A3.aca_matrix(B, tol=1e-12 * np.linalg.norm(B))
+    assert ok and U.shape[1] <= 9
+    assert np.linalg.norm(U @ V.conj().T - B) < 1e-10 * np.linalg.norm(B)
