@@ -242,6 +242,28 @@ int bem_compress(bem_ctx *ctx, int32_t op, const bem_aca_opts *opts, bem_op **ou
 int bem_aca_matrix(bem_ctx *ctx, int32_t prec, int32_t m, int32_t n, const void *A, double tol, int32_t max_cols,
                    int32_t *kc, int32_t *kk, void *U, void *V);
 
+/* The computation of bem_aca_matrix on device buffers with no allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no hipMalloc, hipFree or allocating library call is made.  The working copy of
+ * A, the ACA columns and the recompression matrices live in one library-held device array of
+ * BEM_ACA_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends; its address is looked
+ * up in bem_create, or on the first call on a device).  Every call on one GPU shares that
+ * array and leaves the last call's contents in it: calls that overlap on one GPU (several
+ * streams or threads) race.
+ *   A: device [3m][3n] row-major, complex128 (BEM_PREC_F64) or complex64 (BEM_PREC_MIXED),
+ *   read only.  tol, max_cols: as bem_aca_matrix.  kc_kk: device int32[2] receives (kc, kk)
+ *   as bem_aca_matrix defines them.  U, V: device buffers of A's precision with room for
+ *   9 m min(m, n) and 9 n min(m, n) entries; when kk > 0 they receive Ubar ([3m][kk]) and
+ *   Vbar ([3n][kk]) row-major, A ~= Ubar Vbar^H; otherwise they are not written.  All
+ *   pointers must be device memory of the context's device, aligned to their element size.
+ *   Work is enqueued on the context's stream; the call returns without waiting.
+ * Errors: BEM_ERR_ARG for m or n outside [1, BEM_ACA_NOALLOC_MAX_ELEMENTS], bad prec, tol < 0,
+ * NULL, host or misaligned pointers; BEM_ERR_HIP when the scratch address cannot be found. */
+#define BEM_ACA_NOALLOC_MAX_ELEMENTS 128     /* largest m and n */
+#define BEM_ACA_NOALLOC_SCRATCH_BYTES 4718592 /* 4.5 MiB of device memory per GPU */
+int bem_aca_matrix_noalloc(bem_ctx *ctx, int32_t prec, int32_t m, int32_t n, const void *A, double tol,
+                           int32_t max_cols, int32_t *kc_kk, void *U, void *V);
+
 /* Statistics of a compressed or dense operator. */
 int bem_op_stats(const bem_op *op, bem_stats *st);
 

@@ -109,6 +109,8 @@ _SIGS = {
     "bem_aca_matrix": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_double,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       _P, _P]),
+    "bem_aca_matrix_noalloc": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_double,
+                                              ctypes.c_int32, _P, _P, _P]),
     "bem_op_stats": (ctypes.c_int, [_P, ctypes.POINTER(bem_stats)]),
     "bem_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "bem_apply_weighted": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
@@ -295,6 +297,32 @@ class Context:
         if k <= 0:
             return kc.value, k, None, None
         return kc.value, k, U[:3 * m * k].reshape(3 * m, k), V[:3 * n * k].reshape(3 * n, k)
+
+    def aca_matrix_noalloc(self, A, tol, max_cols=0, U=None, V=None, kc_kk=None):
+        """bem_aca_matrix_noalloc on torch CUDA tensors: A [3m, 3n] complex128 or complex64
+        (the precision follows A).  U, V, kc_kk (int32 [2]) are allocated here by torch unless
+        given (the library itself allocates nothing).  Returns (kc, kk, U[:, :kk], V[:, :kk])
+        after synchronising the stream; U, V are None unless kk > 0."""
+        import torch
+        assert _is_torch(A) and A.is_cuda and A.dim() == 2
+        A = A.contiguous()
+        prec = PREC_MIXED if A.dtype == torch.complex64 else PREC_F64
+        m, n = A.shape[0] // 3, A.shape[1] // 3
+        cap = 3 * min(m, n)
+        if U is None:
+            U = torch.zeros(3 * m * cap, dtype=A.dtype, device=A.device)
+        if V is None:
+            V = torch.zeros(3 * n * cap, dtype=A.dtype, device=A.device)
+        if kc_kk is None:
+            kc_kk = torch.zeros(2, dtype=torch.int32, device=A.device)
+        self._sync_torch_stream()
+        self._check(lib().bem_aca_matrix_noalloc(self.h, int(prec), m, n, A.data_ptr(), float(tol), int(max_cols),
+                                                 kc_kk.data_ptr(), U.data_ptr(), V.data_ptr()))
+        torch.cuda.current_stream().synchronize()
+        kc, kk = (int(v) for v in kc_kk.cpu())
+        if kk <= 0:
+            return kc, kk, None, None
+        return kc, kk, U[:3 * m * kk].reshape(3 * m, kk), V[:3 * n * kk].reshape(3 * n, kk)
 
     def apply_mf(self, op, x, y=None, transpose=False):
         """y[r, l] = A(s_l) x[r, l] (or A(s_l)^T x[r, l]) with entries recomputed (no storage);

@@ -297,6 +297,13 @@ int bem_create(bem_ctx** out, int32_t device)
             delete ctx;
             return BEM_ERR_HIP;
         }
+        // device address of the no-allocation scratch, once per device; a failure here is
+        // reported by bem_aca_matrix_noalloc, which looks it up again
+        try {
+            (void)bem::noalloc_scratch(device);
+        } catch (...) {
+            (void)hipGetLastError();
+        }
     }
     *out = ctx;
     return BEM_OK;
@@ -619,6 +626,21 @@ int bem_aca_matrix(bem_ctx* ctx, int32_t prec, int32_t m, int32_t n, const void*
         aca_matrix_impl(ctx, prec == BEM_PREC_MIXED, m, n, A, tol, max_cols, &c, &k, U, V);
         if (kc) *kc = c;
         if (kk) *kk = k;
+        return BEM_OK;
+    });
+}
+
+int bem_aca_matrix_noalloc(bem_ctx* ctx, int32_t prec, int32_t m, int32_t n, const void* A, double tol,
+                           int32_t max_cols, int32_t* kc_kk, void* U, void* V)
+{
+    if (!ctx) return BEM_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        if (m < 1 || n < 1 || m > BEM_ACA_NOALLOC_MAX_ELEMENTS || n > BEM_ACA_NOALLOC_MAX_ELEMENTS ||
+            (prec != BEM_PREC_F64 && prec != BEM_PREC_MIXED) || !(tol >= 0) || !A || !kc_kk || !U || !V)
+            throw api_error(BEM_ERR_ARG, "bad bem_aca_matrix_noalloc arguments");
+        need_device(ctx);
+        aca_matrix_noalloc_impl(ctx->device, prec == BEM_PREC_MIXED, m, n, A, tol, max_cols, kc_kk, U, V,
+                                ctx->stream);
         return BEM_OK;
     });
 }

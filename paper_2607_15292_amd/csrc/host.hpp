@@ -193,6 +193,10 @@ namespace bem {
 int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out);
 void aca_matrix_impl(bem_ctx* ctx, bool fp32, int m, int n, const void* A, double tol, int max_cols, int* kc, int* kk,
                      void* U, void* V);
+// bem_aca_matrix on device buffers with the library's static device scratch (noalloc.hip)
+char* noalloc_scratch(int device);
+void aca_matrix_noalloc_impl(int device, bool fp32, int m, int n, const void* A, double tol, int max_cols,
+                             int32_t* kckk, void* U, void* V, hipStream_t st);
 void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride, zd* y_dev, hipStream_t st);
 void apply_weighted_compressed(bem_op* op, const zd* W_dev, zd* y_dev, hipStream_t st);
 // y_l = A(s_l)^T x_l (plain transpose), x, y [nrhs][L][3K] mesh order
