@@ -157,6 +157,14 @@ typedef struct {
     int64_t block_groups;         /* groups the blocks were compressed in, one after the other
                                      (1 unless the faces of all blocks would not fit the memory
                                      or bem_aca_opts.pool_bytes) */
+    double apply_macs_c64;        /* algorithmic work of bem_apply: complex multiply-adds per
+                                     column (right-hand side and frequency) of the faces and
+                                     factors stored in complex64 (9 m n per dense face,
+                                     3 (m + n) kk per factored one) */
+    double apply_macs_c128;       /* the same for the faces and factors stored in complex128 */
+    double apply_macs_sel;        /* the same per right-hand side for the dense-fallback faces
+                                     (each acts at one frequency) */
+    double apply_macs_fibre;      /* complex multiply-adds per column of the fibres (9 n per face) */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -359,15 +367,15 @@ typedef struct bem_batch bem_batch;
 #define BEM_BATCH_GRAPH 1  /* bem_batch_create: record the launches of a call in a HIP graph and
                               replay it while the same device buffers and stream come back */
 #define BEM_BATCH_TUNE 2   /* bem_batch_create: time the candidate schedules (segment counts,
-                              persistent row grid, far faces by decreasing rank) and keep the
-                              fastest */
+                              far faces by decreasing rank) and keep the fastest */
 
 /* Schedule and counters of a batch. */
 typedef struct bem_batch_info {
     int32_t nops, nrhs, L, K_total;   /* operators, right-hand sides, frequencies, elements */
     int32_t n_groups, n_segments;     /* row chunks of all operators, row-kernel segments */
     int32_t n_far_faces, seg_target;  /* factored faces, segment target of the schedule */
-    int32_t persistent, persistent_wgs; /* row kernel on a persistent grid of that many groups */
+    int32_t persistent, persistent_wgs; /* always 0: every product kernel takes one work item
+                                           (segment or face, column tile) per workgroup */
     int32_t far_sorted, graph;        /* far faces by decreasing rank; HIP graph replay on */
     int32_t graph_builds, graph_launches;
     int32_t n_tuned, pad;             /* timed candidates (at most 8) */

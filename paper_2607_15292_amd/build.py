@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbem.so")
-SOURCES = ["api.cpp", "partition.cpp", "compress.cpp", "entries.hip", "aca3d.hip", "recomp.hip", "apply.hip", "solve.hip", "solve.cpp", "adjoint.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "partition.cpp", "compress.cpp", "entries.hip", "aca3d.hip", "recomp.hip", "apply.hip", "solve.hip", "solve.cpp", "adjoint.hip", "noalloc.hip", "mfma.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

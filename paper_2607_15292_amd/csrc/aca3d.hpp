@@ -207,13 +207,45 @@ constexpr int APPLY_SEGMENTS = 2048;       // target number of row-kernel workgr
 constexpr int APPLY_SEGMENTS_FINE = 8192;  // the same for products of at most APPLY_FINE_COLS columns
 constexpr int APPLY_FINE_COLS = 128;
 
-// persistent_wgs > 0: the row kernel runs on at most that many workgroups, each striding
-// over the (segment, column tile) items
-void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs = 0);
 // y = A(s_l)^T x with a plan grouped by column chunks (row_start / row_size: column chunks)
 void launch_apply_t(const ApplyArgs& A, hipStream_t st);
-// workgroups of the row kernel that fit on one CU at once
-int apply_rows_occupancy();
+
+// ---------------------------------------------------------------- MFMA product (mfma.hip)
+// Row chunks of the product on the matrix cores: leaf clusters cut into nearly equal pieces of
+// at most MFMA_ROW_CHUNK elements (126 rows: 8 MFMA row tiles); each chunk lists its
+// complex128 faces, then its complex64 faces, and its segments hold faces of one precision.
+// Column tiles of MFMA_COLS (rhs, l) columns.
+constexpr int MFMA_ROW_CHUNK = 42;
+constexpr int MFMA_COLS = 64;
+constexpr int MFMA_SEGMENTS = 2048;  // target segment count for products of at most 2 column tiles
+
+struct MApplyArgs {
+    const BlockIn* blocks;
+    const ApplyFace* faces;
+    const char* pool;
+    int K, L, nrhs;
+    const zd* x;               // permuted input [nrhs][L][3K] (cluster order)
+    zd* y;                     // permuted output
+    zd* tbuf;                  // T = Vbar^H Z of the far faces [far_rows][ncols]
+    zd* pbuf;                  // partial rows of the segments [nseg][3 MFMA_ROW_CHUNK][ncols]
+    const int* row_faces;      // faces of the chunks (per chunk: complex128, then complex64)
+    const int* row_start;      // chunk start (cluster order) and size (elements)
+    const int* row_size;
+    int ngroups;
+    const int* seg_group;      // per segment: chunk, first entry of row_faces (seg_begin[nseg] = end)
+    const int* seg_begin;
+    const int* group_seg;      // per chunk: first segment (group_seg[ngroups] = nseg)
+    int nseg;
+    const int* seg64;          // segments of complex128 faces
+    int nseg64;
+    const int* seg32;          // segments of complex64 faces
+    int nseg32;
+    const int* far64;          // factored faces in complex128
+    int nfar64;
+    const int* far32;          // factored faces in complex64
+    int nfar32;
+};
+void launch_apply_mfma(const MApplyArgs& A, hipStream_t st);
 
 // Operators of a batched product: mesh-order vectors x (input) and y (output) of operator o,
 // [nrhs][L][3 K], and its cluster permutation; the workspace holds all operators side by

@@ -1,15 +1,15 @@
-// apply.hip -- all-frequency product of the compressed array and the gCQ weighted sum.
+// apply.hip -- transposed products and the gCQ weighted sum of the compressed array, and the
+// permutations between mesh and cluster order.  (The plain all-frequency product runs on the
+// matrix cores: mfma.hip.)
 //
-// y_l = sum_b sum_d H_{b,d} (I (x) f_{b,d}[l]) x_l      (per frequency l and right-hand side)
+// y_l = A(s_l)^T x_l                                     (transposed product, per frequency)
 // y   = sum_b sum_d H_{b,d} sum_l (I (x) f_{b,d}[l]) W_l  (eq. (3DacaMult))
 //
-// Per face the product is a small GEMM: Y[I, :] += H[I, J] Z, with Z[3j + c, col] the
-// fibre-weighted input of column col = (rhs, l).  Factored faces H = Ubar Vbar^H go through
-// T = Vbar^H Z (k_far_products, once per face and column tile) and Y += Ubar T.  The row
-// kernel owns a chunk of RCE element rows and a tile of NC columns, walks the faces of its
-// block row in a fixed order (sums in a fixed order, no atomics) and reads each stored face
-// tile once per column tile.  Operands are staged in LDS; arithmetic is FP64 (faces stored
-// in complex64 are widened on load).
+// The transposed product walks column chunks of RCE elements: factored faces H = Ubar Vbar^H
+// go through T' = Ubar^T X (k_far_products_t) and conj(Vbar) T'; the fibre acts on the output
+// side.  The weighted sum contracts the fibres with W once per face and runs matrix-vector
+// products bound by the HBM reads of the stored faces.  Arithmetic is FP64 (faces stored in
+// complex64 are widened on load).
 #include "aca3d.hpp"
 
 namespace bem {
@@ -49,88 +49,6 @@ __device__ __forceinline__ void stage_fibres(const ApplyArgs& A, const ApplyFace
     }
 }
 
-// Zs[k][c] for the scalar columns k0 .. k0 + KTL of the face and the columns c0 .. c0 + NC:
-// Z[3j + c][col] = (f[l] x_{r,l}[J])_c with col = r L + l (fibres from Fs).
-template <int KTL>
-__device__ __forceinline__ void stage_z(const ApplyArgs& A, const BlockIn& B, int k0, int c0, int ncols,
-                                        const zd (*Fs)[9], zd (*Zs)[NC])
-{
-    const int j0 = k0 / 3, nj = min(KTL / 3, B.cs - j0);
-    for (int e = threadIdx.x; e < (KTL / 3) * NC; e += WGA) {
-        const int jj = e / NC, cl = e - jj * NC;
-        zd z[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-        if (jj < nj && c0 + cl < ncols) {
-            const int col = c0 + cl, l = col % A.L, r = col / A.L;
-            const zd* xv = A.x + ((size_t)r * A.L + l) * 3 * A.K + 3 * (size_t)(B.cb + j0 + jj);
-            const zd v[3] = {xv[0], xv[1], xv[2]};
-            mul3(Fs[cl], v, z);
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Zs[3 * jj + c][cl] = z[c];
-    }
-}
-
-// far faces: T[t][col] = sum_k conj(Vbar[k][t]) Z[k][col]; one workgroup per (face, column
-// tile); thread = 3 ranks (t, t + 32, t + 64) x 8 columns.
-template <typename T>
-__device__ void far_products_face(const ApplyArgs& A, const ApplyFace& F, int ncols, int c0, zd (*Vs)[KMAXF],
-                                  zd (*Zs)[NC], zd (*Fs)[9])
-{
-    const BlockIn B = A.blocks[F.block];
-    const int m = B.rs, n = B.cs, kk = F.kk;
-    const cx<T>* V = (const cx<T>*)(A.pool + F.face_off) + (size_t)3 * m * kk;
-    const int tr = threadIdx.x & 31, cg = threadIdx.x >> 5;
-    zd acc[3][8];
-#pragma unroll
-    for (int u = 0; u < 3; ++u)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) acc[u][v] = {0.0, 0.0};
-    stage_fibres(A, F, c0, ncols, Fs);
-    for (int k0 = 0; k0 < 3 * n; k0 += KTF) {
-        const int nk = min(KTF, 3 * n - k0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < KTF * kk; e += WGA) {
-            const int kr = e / kk, t = e - kr * kk;
-            Vs[kr][t] = kr < nk ? ldz(V + (size_t)(k0 + kr) * kk + t) : zd{0.0, 0.0};
-        }
-        stage_z<KTF>(A, B, k0, c0, ncols, Fs, Zs);
-        __syncthreads();
-        for (int k = 0; k < nk; ++k) {
-            zd vv[3];
-#pragma unroll
-            for (int u = 0; u < 3; ++u) vv[u] = tr + 32 * u < kk ? conj(Vs[k][tr + 32 * u]) : zd{0.0, 0.0};
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const zd z = Zs[k][8 * cg + v];
-#pragma unroll
-                for (int u = 0; u < 3; ++u) acc[u][v] = fma_c(vv[u], z, acc[u][v]);
-            }
-        }
-    }
-    zd* Tout = A.tbuf + F.t_off * (size_t)ncols;
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        const int t = tr + 32 * u;
-        if (t >= kk) continue;
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int col = c0 + 8 * cg + v;
-            if (col < ncols) Tout[(size_t)t * ncols + col] = acc[u][v];
-        }
-    }
-}
-
-__global__ __launch_bounds__(WGA) void k_far_products(ApplyArgs A, const int* far_list, int ncols)
-{
-    __shared__ zd Vs[KTF][KMAXF];
-    __shared__ zd Zs[KTF][NC];
-    __shared__ zd Fs[NC][9];
-    const ApplyFace F = A.faces[far_list[blockIdx.x]];
-    const int c0 = blockIdx.y * NC;
-    if (F.fp32) far_products_face<float>(A, F, ncols, c0, Vs, Zs, Fs);
-    else far_products_face<double>(A, F, ncols, c0, Vs, Zs, Fs);
-}
-
 // Y[rows][cols] += Hs[rows][k] Zs[k][cols] over one staged tile; thread = element row er
 // (3 rows) x columns cq, cq + 16, cq + 32, cq + 48: 12 complex accumulators, 7 LDS reads
 // per 12 complex multiply-adds.  Lanes of a wavefront read consecutive Zs entries and Hs rows
@@ -148,96 +66,6 @@ __device__ __forceinline__ void tile_mac(const zd (*Hs)[KTL], const zd (*Zs)[NC]
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[a][v] = fma_c(h, z[v], acc[a][v]);
         }
-    }
-}
-
-// One work item of the row kernel: segment sg of a row chunk's faces times the column tile
-// starting at c0; the segment's partial rows go to pbuf and k_reduce_rows adds them in
-// segment order.  Every LDS write is preceded by a barrier, so items can follow each other
-// in one workgroup.
-__device__ __forceinline__ void rows_item(const ApplyArgs& A, int ncols, int sg, int c0, zd (*Hs)[KR + 1],
-                                          zd (*Zs)[NC], zd (*Fs)[9])
-{
-    const int g = A.seg_group[sg];
-    const int er = threadIdx.x >> 4, cq = threadIdx.x & 15;  // element row, column quad
-    const int rs0 = A.row_start[g], rsz = A.row_size[g];
-    zd acc[3][4];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[a][v] = {0.0, 0.0};
-    for (int q = A.seg_begin[sg]; q < A.seg_begin[sg + 1]; ++q) {
-        const ApplyFace F = A.faces[A.row_faces[q]];
-        if (F.kk < 0) continue;
-        const BlockIn B = A.blocks[F.block];
-        const int n = B.cs;
-        const int ioff = rs0 - B.rb;  // first element row of the chunk inside the block
-        if (F.kk == 0) {
-            const size_t ld = 3 * (size_t)n;
-            __syncthreads();
-            stage_fibres(A, F, c0, ncols, Fs);
-            for (int k0 = 0; k0 < 3 * n; k0 += KR) {
-                const int nk = min(KR, 3 * n - k0);
-                __syncthreads();
-                for (int e = threadIdx.x; e < 3 * RCE * KR; e += WGA) {
-                    const int r = e / KR, kc = e - r * KR;
-                    zd h = {0.0, 0.0};
-                    if (r < 3 * rsz && kc < nk) {
-                        const size_t o = (size_t)(3 * ioff + r) * ld + k0 + kc;
-                        h = F.fp32 ? ldz((const zf*)(A.pool + F.face_off) + o) : ((const zd*)(A.pool + F.face_off))[o];
-                    }
-                    Hs[r][kc] = h;
-                }
-                stage_z<KR>(A, B, k0, c0, ncols, Fs, Zs);
-                __syncthreads();
-                tile_mac<KR + 1>(Hs, Zs, nk, er, cq, acc);
-            }
-        } else {
-            const int kk = F.kk;
-            const zd* Tf = A.tbuf + F.t_off * (size_t)ncols;
-            for (int k0 = 0; k0 < kk; k0 += KR) {
-                const int nk = min(KR, kk - k0);
-                __syncthreads();
-                for (int e = threadIdx.x; e < 3 * RCE * KR; e += WGA) {
-                    const int r = e / KR, kc = e - r * KR;
-                    zd h = {0.0, 0.0};
-                    if (r < 3 * rsz && kc < nk) {
-                        const size_t o = (size_t)(3 * ioff + r) * kk + k0 + kc;
-                        h = F.fp32 ? ldz((const zf*)(A.pool + F.face_off) + o) : ((const zd*)(A.pool + F.face_off))[o];
-                    }
-                    Hs[r][kc] = h;
-                }
-                for (int e = threadIdx.x; e < KR * NC; e += WGA) {
-                    const int kr = e / NC, cl = e - kr * NC;
-                    Zs[kr][cl] = (kr < nk && c0 + cl < ncols) ? Tf[(size_t)(k0 + kr) * ncols + c0 + cl] : zd{0.0, 0.0};
-                }
-                __syncthreads();
-                tile_mac<KR + 1>(Hs, Zs, nk, er, cq, acc);
-            }
-        }
-    }
-    if (er < rsz) {
-        zd* pb = A.pbuf + (size_t)sg * 3 * RCE * ncols;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int col = c0 + cq + 16 * v;
-            if (col >= ncols) continue;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) pb[(size_t)(3 * er + a) * ncols + col] = acc[a][v];
-        }
-    }
-}
-
-// rows: work items w = sg + nseg * tile (segment fastest), one per workgroup, or strided
-// over a smaller persistent grid
-__global__ __launch_bounds__(WGA) void k_rows(ApplyArgs A, int ncols, int nitems)
-{
-    __shared__ zd Hs[3 * RCE][KR + 1];
-    __shared__ zd Zs[KR][NC];
-    __shared__ zd Fs[NC][9];
-    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-        const int tile = w / A.nseg;
-        rows_item(A, ncols, w - tile * A.nseg, tile * NC, Hs, Zs, Fs);
     }
 }
 
@@ -628,35 +456,12 @@ void launch_permute_batch(const BatchPermTable& T, int kmax, zd* work, bool to_c
     BEM_HIP_TRY(hipGetLastError());
 }
 
-int apply_rows_occupancy()
-{
-    int n = 0;
-    BEM_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rows, WGA, 0));
-    return n;
-}
-
 void launch_permute(const zd* in, zd* out, const int* perm, int K, int L, int nrhs, int64_t in_l_stride, bool to_cluster,
                     hipStream_t st)
 {
     int64_t total = (int64_t)nrhs * L * K;
     hipLaunchKernelGGL(k_permute, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, in, out, perm, K, L, nrhs,
                        in_l_stride, (int)to_cluster);
-    BEM_HIP_TRY(hipGetLastError());
-}
-
-void launch_apply(const ApplyArgs& A, hipStream_t st, int persistent_wgs)
-{
-    const int ncols = A.L * A.nrhs;
-    const unsigned ct = (unsigned)((ncols + NC - 1) / NC);
-    if (A.nfar > 0) hipLaunchKernelGGL(k_far_products, dim3(A.nfar, ct), dim3(WGA), 0, st, A, A.far_list, ncols);
-    BEM_HIP_TRY(hipGetLastError());
-    const long long items = (long long)A.nseg * ct;
-    if (items >= (1LL << 31)) throw std::invalid_argument("too many row work items");
-    const unsigned grid = persistent_wgs > 0 ? (unsigned)std::min<long long>(items, persistent_wgs) : (unsigned)items;
-    hipLaunchKernelGGL(k_rows, dim3(grid), dim3(WGA), 0, st, A, ncols, (int)items);
-    BEM_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL((k_reduce_rows<false>), dim3(A.nrow_groups, (3 * RCE * ncols + 255) / 256), dim3(256), 0, st, A,
-                       ncols, A.y);
     BEM_HIP_TRY(hipGetLastError());
 }
 

@@ -13,6 +13,19 @@
 
 namespace bem {
 
+// Plan of the product on the matrix cores (mfma.hip): row chunks of at most MFMA_ROW_CHUNK
+// elements, each with its complex128 faces, then its complex64 faces.
+struct MPlan {
+    std::vector<int> flat, ptr, nf64, start, size, far64, far32;
+    DevBuf flat_dev, start_dev, size_dev, far_dev;
+    struct Segs {
+        DevBuf dev;  // [nseg] chunk, [nseg + 1] first face, [ngroups + 1] first segment, [n64], [n32]
+        int nseg = 0, n64 = 0, n32 = 0;
+    };
+    Segs fine, coarse;  // fine: products of at most 2 column tiles
+    int ngroups = 0;
+};
+
 struct CompressedOp {
     Partition part;
     DevGeo geo;                 // element tables in cluster order
@@ -36,6 +49,7 @@ struct CompressedOp {
     int nfar = 0;               // factored faces
     long long far_rows = 0;     // sum of kk over far faces
     long long zw_total = 0;     // sum of 3 cs over faces
+    MPlan mp;                   // plan of the product (matrix cores)
     DevBuf work;                // apply workspace (grown on demand)
     // plan of the transposed product (column chunks), built on first use
     bool t_built = false;
@@ -193,6 +207,162 @@ void build_apply_plan(CompressedOp& C, hipStream_t st)
     C.h_start = std::move(s2);
     C.h_size = std::move(z2);
     C.h_far = std::move(far);
+}
+
+// Segments of the product on the matrix cores: the complex128 faces and the complex64 faces
+// of every chunk cut into pieces of about equal work (staged k per face: 3 cs for a dense face,
+// kk for factors, plus a per-face overhead; complex128 work counts twice, the FP64 MFMA rate
+// being half the FP32 one), about target pieces in all.  Partial sums are added in segment
+// order.  Returns [nseg] chunk, [nseg + 1] first face entry, [ngroups + 1] first segment of
+// each chunk, [n64] complex128 segments, [n32] complex64 segments.
+std::vector<int> make_msegments(const std::vector<ApplyFace>& af, const std::vector<BlockIn>& blocks,
+                                const std::vector<int>& ptr, const std::vector<int>& nf64, const std::vector<int>& flat,
+                                int target, int* nseg, int* n64, int* n32)
+{
+    const int ngroups = (int)ptr.size() - 1;
+    auto cost = [&](int fi) {
+        const ApplyFace& a = af[fi];
+        return (a.kk > 0 ? (double)a.kk : 3.0 * blocks[a.block].cs) + 16.0;
+    };
+    double total = 0.0;
+    for (int g = 0; g < ngroups; ++g)
+        for (int q = ptr[g]; q < ptr[g + 1]; ++q) total += cost(flat[q]) * (q < ptr[g] + nf64[g] ? 2.0 : 1.0);
+    const double per = std::max(1.0, total / std::max(target, 1));
+    std::vector<int> sgroup, sbeg, s64, s32, gseg(ngroups + 1, 0);
+    for (int g = 0; g < ngroups; ++g) {
+        for (int p = 0; p < 2; ++p) {
+            const int b = ptr[g] + (p ? nf64[g] : 0), e = p ? ptr[g + 1] : ptr[g] + nf64[g];
+            if (b >= e) continue;
+            const double w = p ? 1.0 : 2.0;
+            double cg = 0.0;
+            for (int q = b; q < e; ++q) cg += w * cost(flat[q]);
+            const int ns = std::max(1, (int)std::lround(cg / per));
+            const double tgt = cg / ns;
+            int q = b;
+            for (int k = 0; k < ns && q < e; ++k) {
+                (p ? s32 : s64).push_back((int)sgroup.size());
+                sgroup.push_back(g);
+                sbeg.push_back(q);
+                double acc = 0.0;
+                while (q < e && (k == ns - 1 || acc == 0.0 || acc + 0.5 * w * cost(flat[q]) < tgt)) acc += w * cost(flat[q++]);
+            }
+        }
+        gseg[g + 1] = (int)sgroup.size();
+    }
+    *nseg = (int)sgroup.size();
+    *n64 = (int)s64.size();
+    *n32 = (int)s32.size();
+    std::vector<int> segbuf;
+    segbuf.insert(segbuf.end(), sgroup.begin(), sgroup.end());
+    segbuf.insert(segbuf.end(), sbeg.begin(), sbeg.end());
+    segbuf.push_back(ptr[ngroups]);
+    segbuf.insert(segbuf.end(), gseg.begin(), gseg.end());
+    segbuf.insert(segbuf.end(), s64.begin(), s64.end());
+    segbuf.insert(segbuf.end(), s32.begin(), s32.end());
+    return segbuf;
+}
+
+void upload_ints(DevBuf& d, const std::vector<int>& v, hipStream_t st)
+{
+    d.alloc(std::max<size_t>(v.size() * sizeof(int), 16));
+    if (!v.empty()) BEM_HIP_TRY(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+}
+
+void set_msegments(MPlan::Segs& S, const std::vector<ApplyFace>& af, const std::vector<BlockIn>& blocks,
+                   const MPlan& P, int target, hipStream_t st)
+{
+    upload_ints(S.dev, make_msegments(af, blocks, P.ptr, P.nf64, P.flat, target, &S.nseg, &S.n64, &S.n32), st);
+}
+
+// Chunks: leaves of the cluster tree cut into nearly equal pieces of at most MFMA_ROW_CHUNK
+// elements, in cluster order; each gets the faces of the blocks whose rows cover it,
+// complex128 first.
+void build_mplan(CompressedOp& C, hipStream_t st)
+{
+    MPlan& P = C.mp;
+    std::vector<std::pair<int, int>> ch;
+    for (const Cluster& n : C.part.nodes)
+        if (n.child[0] < 0) {
+            const int pieces = (n.size + MFMA_ROW_CHUNK - 1) / MFMA_ROW_CHUNK;
+            for (int q = 0, s0 = 0; q < pieces; ++q) {
+                const int sz = (n.size - s0) / (pieces - q);
+                ch.push_back({n.begin + s0, sz});
+                s0 += sz;
+            }
+        }
+    std::sort(ch.begin(), ch.end());
+    P.ngroups = (int)ch.size();
+    P.start.resize(P.ngroups);
+    P.size.resize(P.ngroups);
+    for (int g = 0; g < P.ngroups; ++g) {
+        P.start[g] = ch[g].first;
+        P.size[g] = ch[g].second;
+    }
+    const int nb = (int)C.blocks.size();
+    std::vector<std::vector<int>> of_block(nb);
+    for (size_t f = 0; f < C.af.size(); ++f) of_block[C.af[f].block].push_back((int)f);
+    std::vector<std::vector<int>> l64(P.ngroups), l32(P.ngroups);
+    for (int b = 0; b < nb; ++b) {
+        const BlockIn& B = C.blocks[b];
+        auto it = std::lower_bound(P.start.begin(), P.start.end(), B.rb);
+        for (; it != P.start.end() && *it < B.rb + B.rs; ++it) {
+            const int g = (int)(it - P.start.begin());
+            for (int fi : of_block[b]) (C.af[fi].fp32 ? l32 : l64)[g].push_back(fi);
+        }
+    }
+    P.flat.clear();
+    P.ptr.assign(1, 0);
+    P.nf64.assign(P.ngroups, 0);
+    for (int g = 0; g < P.ngroups; ++g) {
+        P.nf64[g] = (int)l64[g].size();
+        P.flat.insert(P.flat.end(), l64[g].begin(), l64[g].end());
+        P.flat.insert(P.flat.end(), l32[g].begin(), l32[g].end());
+        P.ptr.push_back((int)P.flat.size());
+    }
+    P.far64.clear();
+    P.far32.clear();
+    for (size_t f = 0; f < C.af.size(); ++f)
+        if (C.af[f].kk > 0) (C.af[f].fp32 ? P.far32 : P.far64).push_back((int)f);
+    std::vector<int> far = P.far64;
+    far.insert(far.end(), P.far32.begin(), P.far32.end());
+    upload_ints(P.flat_dev, P.flat, st);
+    upload_ints(P.start_dev, P.start, st);
+    upload_ints(P.size_dev, P.size, st);
+    upload_ints(P.far_dev, far, st);
+    set_msegments(P.fine, C.af, C.blocks, P, MFMA_SEGMENTS, st);
+    set_msegments(P.coarse, C.af, C.blocks, P, std::max(P.ngroups, 256), st);
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+}
+
+// Arguments of the product on the matrix cores for segments S; the workspace pointers are
+// set by the caller.
+MApplyArgs margs(const MPlan& P, const MPlan::Segs& S, const DevBuf& blocks_dev, const DevBuf& af_dev,
+                 const char* pool, int K, int L, int nrhs)
+{
+    MApplyArgs A{};
+    A.blocks = blocks_dev.as<BlockIn>();
+    A.faces = af_dev.as<ApplyFace>();
+    A.pool = pool;
+    A.K = K;
+    A.L = L;
+    A.nrhs = nrhs;
+    A.row_faces = P.flat_dev.as<int>();
+    A.row_start = P.start_dev.as<int>();
+    A.row_size = P.size_dev.as<int>();
+    A.ngroups = P.ngroups;
+    A.nseg = S.nseg;
+    A.seg_group = S.dev.as<int>();
+    A.seg_begin = A.seg_group + S.nseg;
+    A.group_seg = A.seg_begin + S.nseg + 1;
+    A.seg64 = A.group_seg + P.ngroups + 1;
+    A.nseg64 = S.n64;
+    A.seg32 = A.seg64 + S.n64;
+    A.nseg32 = S.n32;
+    A.far64 = P.far_dev.as<int>();
+    A.nfar64 = (int)P.far64.size();
+    A.far32 = A.far64 + P.far64.size();
+    A.nfar32 = (int)P.far32.size();
+    return A;
 }
 
 ApplyArgs plan_args(const CompressedOp& C, int nrhs)
@@ -779,6 +949,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     }
     C->faces_dev.release();
     build_apply_plan(*C, st);
+    build_mplan(*C, st);
 
     // statistics
     bem_stats& R = out->stats;
@@ -807,6 +978,12 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             const FaceDesc& f = C->faces[(size_t)b * L + d];
             bytes += (int64_t)L * 9 * sizeof(zd);
             size_t zs = f.fp32 ? sizeof(zf) : sizeof(zd);
+            if (f.kk >= 0) {
+                const double core = f.kk > 0 ? 3.0 * (B.rs + B.cs) * f.kk : 9.0 * B.rs * B.cs;
+                if (f.sel) R.apply_macs_sel += core;
+                else (f.fp32 ? R.apply_macs_c64 : R.apply_macs_c128) += core;
+                if (!f.sel) R.apply_macs_fibre += 9.0 * B.cs;
+            }
             if (f.kk == 0) {
                 bytes += (int64_t)9 * B.rs * B.cs * (int64_t)zs;
             } else if (f.kk > 0) {
@@ -873,20 +1050,20 @@ void apply_compressed(bem_op* op, int nrhs, const zd* x_dev, int64_t x_l_stride,
     CompressedOp& C = *op->comp;
     const size_t M = 3 * (size_t)C.K;
     const size_t ncols = (size_t)C.L * nrhs;
-    const size_t prow = (size_t)3 * APPLY_ROW_CHUNK * ncols;  // partial rows of one segment
-    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + (size_t)std::max(C.nseg, C.nsegf) * prow + 16) *
-                  sizeof(zd);
+    const MPlan::Segs& S = (ncols + MFMA_COLS - 1) / MFMA_COLS <= 2 ? C.mp.fine : C.mp.coarse;
+    const size_t prow = (size_t)3 * MFMA_ROW_CHUNK * ncols;  // partial rows of one segment
+    size_t need = (2 * ncols * M + (size_t)C.far_rows * ncols + (size_t)S.nseg * prow + 16) * sizeof(zd);
     if (C.work.bytes < need) C.work.alloc(need);
     zd* xp = C.work.as<zd>();
     zd* yp = xp + ncols * M;
     zd* tb = yp + ncols * M;
     launch_permute(x_dev, xp, C.perm_dev.as<int>(), C.K, C.L, nrhs, x_l_stride, true, st);
-    ApplyArgs A = plan_args(C, nrhs);
+    MApplyArgs A = margs(C.mp, S, C.blocks_dev, C.af_dev, C.pool.as<char>(), C.K, C.L, nrhs);
     A.x = xp;
     A.y = yp;
     A.tbuf = tb;
     A.pbuf = tb + (size_t)C.far_rows * ncols;
-    launch_apply(A, st);
+    launch_apply_mfma(A, st);
     launch_permute(yp, y_dev, C.perm_dev.as<int>(), C.K, C.L, nrhs, (int64_t)M, false, st);
 }
 
@@ -1027,16 +1204,15 @@ struct BatchPlan {
     std::vector<bem_op*> ops;
     int nrhs = 0, L = 0, Ktot = 0, Kmax = 0;
     std::vector<int> koff;
-    // merged plan (host)
+    // merged plan (host): blocks, faces and the chunks of the product on the matrix cores
     std::vector<BlockIn> blocks;
     std::vector<ApplyFace> af;
-    std::vector<int> flat, ptr, start, size, far;
+    MPlan mp;
     long long far_rows = 0;
     const char* base = nullptr;
-    DevBuf blocks_dev, af_dev, rowfaces_dev, rowptr_dev, rowstart_dev, rowsize_dev, far_dev, far_sorted_dev, seg_dev;
-    int ngroups = 0, nfar = 0;
+    DevBuf blocks_dev, af_dev, far_sorted_dev;
     // schedule
-    int seg_target = 0, nseg = 0, persistent = 0, far_sorted = 0, persist_wgs = 0;
+    int seg_target = 0, far_sorted = 0;
     std::vector<double> tune_ms;
     std::vector<int> tune_seg;
     DevBuf work;
@@ -1062,41 +1238,23 @@ namespace {
 size_t batch_work_bytes(const BatchPlan& P, int nseg)
 {
     const size_t ncols = (size_t)P.L * P.nrhs, M = 3 * (size_t)P.Ktot;
-    return (2 * ncols * M + (size_t)P.far_rows * ncols + (size_t)nseg * 3 * APPLY_ROW_CHUNK * ncols + 16) * sizeof(zd);
+    return (2 * ncols * M + (size_t)P.far_rows * ncols + (size_t)nseg * 3 * MFMA_ROW_CHUNK * ncols + 16) * sizeof(zd);
 }
 
 void batch_set_segments(BatchPlan& P, int target, hipStream_t st)
 {
-    int nseg = 0;
-    std::vector<int> segbuf = make_segments(P.af, P.blocks, P.ptr, P.flat, target, &nseg);
-    P.seg_dev.alloc(segbuf.size() * sizeof(int));
-    BEM_HIP_TRY(hipMemcpyAsync(P.seg_dev.p, segbuf.data(), segbuf.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    set_msegments(P.mp.fine, P.af, P.blocks, P.mp, target, st);
     BEM_HIP_TRY(hipStreamSynchronize(st));
     P.seg_target = target;
-    P.nseg = nseg;
 }
 
-ApplyArgs batch_args(const BatchPlan& P)
+MApplyArgs batch_args(const BatchPlan& P)
 {
-    ApplyArgs A{};
-    A.blocks = P.blocks_dev.as<BlockIn>();
-    A.faces = P.af_dev.as<ApplyFace>();
-    A.nfaces = (int)P.af.size();
-    A.row_faces = P.rowfaces_dev.as<int>();
-    A.row_ptr = P.rowptr_dev.as<int>();
-    A.row_start = P.rowstart_dev.as<int>();
-    A.row_size = P.rowsize_dev.as<int>();
-    A.nrow_groups = P.ngroups;
-    A.pool = P.base;
-    A.K = P.Ktot;
-    A.L = P.L;
-    A.nrhs = P.nrhs;
-    A.far_list = (P.far_sorted ? P.far_sorted_dev : P.far_dev).as<int>();
-    A.nfar = P.nfar;
-    A.nseg = P.nseg;
-    A.seg_group = P.seg_dev.as<int>();
-    A.seg_begin = A.seg_group + P.nseg;
-    A.group_seg = A.seg_begin + P.nseg + 1;
+    MApplyArgs A = margs(P.mp, P.mp.fine, P.blocks_dev, P.af_dev, P.base, P.Ktot, P.L, P.nrhs);
+    if (P.far_sorted) {
+        A.far64 = P.far_sorted_dev.as<int>();
+        A.far32 = A.far64 + P.mp.far64.size();
+    }
     const size_t ncols = (size_t)P.L * P.nrhs, M = 3 * (size_t)P.Ktot;
     zd* xp = P.work.as<zd>();
     A.x = xp;
@@ -1118,9 +1276,9 @@ void batch_enqueue(const BatchPlan& P, const zd* const* x, zd* const* y, hipStre
         const CompressedOp& C = *P.ops[o]->comp;
         T.op[o] = BatchPerm{x ? x[o] : nullptr, y ? y[o] : nullptr, C.perm_dev.as<int>(), C.K, P.koff[o]};
     }
-    ApplyArgs A = batch_args(P);
+    MApplyArgs A = batch_args(P);
     launch_permute_batch(T, P.Kmax, P.work.as<zd>(), true, st);
-    launch_apply(A, st, P.persistent ? P.persist_wgs : 0);
+    launch_apply_mfma(A, st);
     launch_permute_batch(T, P.Kmax, const_cast<zd*>(A.y), false, st);
 }
 
@@ -1132,15 +1290,15 @@ double batch_time_ms(const BatchPlan& P, hipStream_t st, int reps)
     hipEvent_t e0, e1;
     BEM_HIP_TRY(hipEventCreate(&e0));
     BEM_HIP_TRY(hipEventCreate(&e1));
-    ApplyArgs A = batch_args(P);
+    MApplyArgs A = batch_args(P);
     A.nrhs = std::max(1, std::min(P.nrhs, 512 / P.L));
     const size_t ncols = (size_t)P.L * A.nrhs, M = 3 * (size_t)P.Ktot;
     A.y = const_cast<zd*>(A.x) + ncols * M;
     A.tbuf = const_cast<zd*>(A.x) + 2 * ncols * M;
     A.pbuf = A.tbuf + (size_t)P.far_rows * ncols;
-    launch_apply(A, st, P.persistent ? P.persist_wgs : 0);  // warm-up
+    launch_apply_mfma(A, st);  // warm-up
     BEM_HIP_TRY(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r) launch_apply(A, st, P.persistent ? P.persist_wgs : 0);
+    for (int r = 0; r < reps; ++r) launch_apply_mfma(A, st);
     BEM_HIP_TRY(hipEventRecord(e1, st));
     BEM_HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1148,6 +1306,13 @@ double batch_time_ms(const BatchPlan& P, hipStream_t st, int reps)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return ms / reps;
+}
+
+int count_msegments(const BatchPlan& P, int target)
+{
+    int ns = 0, n64 = 0, n32 = 0;
+    (void)make_msegments(P.af, P.blocks, P.mp.ptr, P.mp.nf64, P.mp.flat, target, &ns, &n64, &n32);
+    return ns;
 }
 
 }  // namespace
@@ -1159,12 +1324,14 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
     P->nrhs = nrhs;
     P->L = ops[0]->L;
     P->use_graph = (flags & BEM_BATCH_GRAPH) != 0;
-    // merged plan: blocks, faces, row groups and far faces of every operator, element
-    // indices shifted by the operator's offset, face offsets taken from the lowest pool
+    // merged plan: blocks, faces, chunks and far faces of every operator, element indices
+    // shifted by the operator's offset, face offsets taken from the lowest pool
     uintptr_t lo = UINTPTR_MAX;
     for (bem_op* op : P->ops) lo = std::min(lo, (uintptr_t)op->comp->pool.p);
     P->base = (const char*)lo;
     long long trow = 0;
+    MPlan& mp = P->mp;
+    mp.ptr.assign(1, 0);
     for (int o = 0; o < nops; ++o) {
         const CompressedOp& C = *ops[o]->comp;
         const int boff = (int)P->blocks.size(), foff = (int)P->af.size(), koff = P->Ktot;
@@ -1183,17 +1350,19 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
             a.zw_off = 0;
             P->af.push_back(a);
         }
-        const int e0 = (int)P->flat.size();
-        for (int fi : C.h_flat) P->flat.push_back(fi + foff);
-        if (P->ptr.empty()) P->ptr.push_back(0);
-        for (size_t g = 1; g < C.h_ptr.size(); ++g) P->ptr.push_back(C.h_ptr[g] + e0);
-        for (int s0 : C.h_start) P->start.push_back(s0 + koff);
-        P->size.insert(P->size.end(), C.h_size.begin(), C.h_size.end());
-        for (int f : C.h_far) P->far.push_back(f + foff);
+        const int e0 = (int)mp.flat.size();
+        for (int fi : C.mp.flat) mp.flat.push_back(fi + foff);
+        for (size_t g = 1; g < C.mp.ptr.size(); ++g) mp.ptr.push_back(C.mp.ptr[g] + e0);
+        mp.nf64.insert(mp.nf64.end(), C.mp.nf64.begin(), C.mp.nf64.end());
+        for (int s0 : C.mp.start) mp.start.push_back(s0 + koff);
+        mp.size.insert(mp.size.end(), C.mp.size.begin(), C.mp.size.end());
+        for (int f : C.mp.far64) mp.far64.push_back(f + foff);
+        for (int f : C.mp.far32) mp.far32.push_back(f + foff);
         trow += C.far_rows;
         P->Ktot += C.K;
         P->Kmax = std::max(P->Kmax, C.K);
     }
+    mp.ngroups = (int)mp.start.size();
     P->far_rows = trow;
     // algorithmic flops of one product: per column, 9 m n complex multiply-adds for a dense
     // face, 3 (m + n) kk for factors, 9 n for the fibre (a selector face: one frequency, no
@@ -1206,54 +1375,44 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
         else macs_col += core + 9.0 * B.cs;
     }
     P->flop = 8.0 * ((double)P->L * nrhs * macs_col + (double)nrhs * macs_sel);
-    P->ngroups = (int)P->start.size();
-    P->nfar = (int)P->far.size();
-    std::vector<int> far_sorted = P->far;
-    std::stable_sort(far_sorted.begin(), far_sorted.end(), [&](int a, int b) { return P->af[a].kk > P->af[b].kk; });
+    std::vector<int> far = mp.far64, far_sorted;
+    far.insert(far.end(), mp.far32.begin(), mp.far32.end());
+    for (const std::vector<int>* lst : {&mp.far64, &mp.far32}) {
+        std::vector<int> v = *lst;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return P->af[a].kk > P->af[b].kk; });
+        far_sorted.insert(far_sorted.end(), v.begin(), v.end());
+    }
     auto up = [&](DevBuf& d, const void* src, size_t bytes) {
         d.alloc(std::max<size_t>(bytes, 16));
         if (bytes) BEM_HIP_TRY(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
     };
     up(P->blocks_dev, P->blocks.data(), P->blocks.size() * sizeof(BlockIn));
     up(P->af_dev, P->af.data(), P->af.size() * sizeof(ApplyFace));
-    up(P->rowfaces_dev, P->flat.data(), P->flat.size() * sizeof(int));
-    up(P->rowptr_dev, P->ptr.data(), P->ptr.size() * sizeof(int));
-    up(P->rowstart_dev, P->start.data(), P->start.size() * sizeof(int));
-    up(P->rowsize_dev, P->size.data(), P->size.size() * sizeof(int));
-    up(P->far_dev, P->far.data(), P->far.size() * sizeof(int));
-    up(P->far_sorted_dev, far_sorted.data(), far_sorted.size() * sizeof(int));
-    int dev = 0, ncu = 0;
-    BEM_HIP_TRY(hipGetDevice(&dev));
-    BEM_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    P->persist_wgs = std::max(1, ncu * std::max(1, apply_rows_occupancy()));
-    // schedule: segment count, persistent or one workgroup per item, far faces in plan order
-    // or by decreasing rank; the default is the single-operator schedule, the tuner times
-    // the candidates that fit in half of the free memory and keeps the fastest
-    // (default: about APPLY_SEGMENTS row workgroups per launch, at least one segment per group)
-    const int ctiles = (P->L * nrhs + 63) / 64;
-    const int tdef = std::max(P->ngroups, (ctiles <= 2 ? APPLY_SEGMENTS_FINE : APPLY_SEGMENTS) / ctiles);
-    std::vector<int> targets = {std::max(1, P->ngroups / 2), P->ngroups, 2 * P->ngroups, 4 * P->ngroups, tdef};
+    upload_ints(mp.flat_dev, mp.flat, st);
+    upload_ints(mp.start_dev, mp.start, st);
+    upload_ints(mp.size_dev, mp.size, st);
+    upload_ints(mp.far_dev, far, st);
+    upload_ints(P->far_sorted_dev, far_sorted, st);
+    // schedule: segment count and far faces in plan order or by decreasing rank; the default
+    // is the single-operator schedule, the tuner times the candidates that fit in half of the
+    // free memory and keeps the fastest
+    const int ctiles = (P->L * nrhs + MFMA_COLS - 1) / MFMA_COLS;
+    const int ng = mp.ngroups;
+    const int tdef = ctiles <= 2 ? MFMA_SEGMENTS : std::max(ng, 256);
+    std::vector<int> targets = {std::max(1, ng / 2), ng, 2 * ng, 4 * ng, tdef};
     std::sort(targets.begin(), targets.end());
     targets.erase(std::unique(targets.begin(), targets.end()), targets.end());
     size_t free_b = 0, total_b = 0;
     BEM_HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     std::vector<int> fit;
-    for (int t : targets) {
-        int ns = 0;
-        (void)make_segments(P->af, P->blocks, P->ptr, P->flat, t, &ns);
-        if (batch_work_bytes(*P, ns) <= free_b / 2 || t == targets.front()) fit.push_back(t);
-    }
+    for (int t : targets)
+        if (batch_work_bytes(*P, count_msegments(*P, t)) <= free_b / 2 || t == targets.front()) fit.push_back(t);
     int best_t = std::find(fit.begin(), fit.end(), tdef) != fit.end() ? tdef : fit.front();
     size_t need = 0;
-    for (int t : fit) {
-        int ns = 0;
-        (void)make_segments(P->af, P->blocks, P->ptr, P->flat, t, &ns);
-        need = std::max(need, batch_work_bytes(*P, ns));
-    }
-    if (!(flags & BEM_BATCH_TUNE)) {
-        int ns = 0;
-        (void)make_segments(P->af, P->blocks, P->ptr, P->flat, best_t, &ns);
-        need = batch_work_bytes(*P, ns);
+    if (flags & BEM_BATCH_TUNE) {
+        for (int t : fit) need = std::max(need, batch_work_bytes(*P, count_msegments(*P, t)));
+    } else {
+        need = batch_work_bytes(*P, count_msegments(*P, best_t));
     }
     P->work.alloc(need);
     P->work_bytes = need;
@@ -1262,13 +1421,12 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
         double best = 1e300;
         std::vector<int> seen;
         for (int t : fit) {
-            int ns = 0;
-            (void)make_segments(P->af, P->blocks, P->ptr, P->flat, t, &ns);
+            const int ns = count_msegments(*P, t);
             if (std::find(seen.begin(), seen.end(), ns) != seen.end()) continue;  // same schedule
             seen.push_back(ns);
             batch_set_segments(*P, t, st);
             const double ms = batch_time_ms(*P, st, 1);
-            P->tune_seg.push_back(P->nseg);
+            P->tune_seg.push_back(P->mp.fine.nseg);
             P->tune_ms.push_back(ms);
             if (ms < best) {
                 best = ms;
@@ -1276,15 +1434,11 @@ BatchPlan* batch_create(bem_op* const* ops, int nops, int nrhs, int flags, hipSt
             }
         }
         batch_set_segments(*P, best_t, st);
-        for (int knob = 0; knob < 2; ++knob) {
-            int& v = knob == 0 ? P->persistent : P->far_sorted;
-            v = 1;
-            const double ms = batch_time_ms(*P, st, 1);
-            P->tune_seg.push_back(P->nseg);
-            P->tune_ms.push_back(ms);
-            if (ms < best) best = ms;
-            else v = 0;
-        }
+        P->far_sorted = 1;
+        const double ms = batch_time_ms(*P, st, 1);
+        P->tune_seg.push_back(P->mp.fine.nseg);
+        P->tune_ms.push_back(ms);
+        if (!(ms < best)) P->far_sorted = 0;
     } else {
         batch_set_segments(*P, best_t, st);
     }
@@ -1336,12 +1490,12 @@ void batch_info(const BatchPlan* P, bem_batch_info* I)
     I->nrhs = P->nrhs;
     I->L = P->L;
     I->K_total = P->Ktot;
-    I->n_groups = P->ngroups;
-    I->n_segments = P->nseg;
-    I->n_far_faces = P->nfar;
+    I->n_groups = P->mp.ngroups;
+    I->n_segments = P->mp.fine.nseg;
+    I->n_far_faces = (int32_t)(P->mp.far64.size() + P->mp.far32.size());
     I->seg_target = P->seg_target;
-    I->persistent = P->persistent;
-    I->persistent_wgs = P->persist_wgs;
+    I->persistent = 0;
+    I->persistent_wgs = 0;
     I->far_sorted = P->far_sorted;
     I->graph = P->use_graph;
     I->graph_builds = P->graph_builds;

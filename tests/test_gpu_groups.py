@@ -82,8 +82,11 @@ def test_grouped_operator_in_transposed_and_batched_products():
     xh = W.random_rhs(7, (2, L, 3 * len(T)))
     bt = B.Batch([Vg, H1], nrhs=2)
     yv, yh = bt.apply([x, xh])
-    assert np.abs(yv - V1.apply(x)).max() <= 1e-12 * np.abs(yv).max()
-    assert np.abs(yh - H1.apply(xh)).max() <= 1e-12 * np.abs(yh).max()
+    # complex64 faces accumulate in FP32 per segment of a row chunk, and the batch cuts its
+    # segments differently from each operator's own plan: the sums differ by FP32 rounding of
+    # the far-field part (a wrong face address would differ at order one)
+    assert np.abs(yv - V1.apply(x)).max() <= 1e-9 * np.abs(yv).max()
+    assert np.abs(yh - H1.apply(xh)).max() <= 1e-9 * np.abs(yh).max()
     bt.destroy()
     for o in (V1, Vg, H1):
         o.destroy()
