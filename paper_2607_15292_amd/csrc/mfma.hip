@@ -201,15 +201,116 @@ __global__ __launch_bounds__(WGM, 4) void k_far_mfma(MApplyArgs A, int ncols, co
 }
 
 // Rows: one workgroup per (segment of one precision, column tile); the segment's partial rows
-// go to pbuf[sg] and k_reduce_mrows adds them.
+// go to pbuf[sg] and k_reduce_mrows adds them.  The segment is a sequence of jobs (face, tile of
+// KC real k): the face rows of the chunk (A) and the input side (B') of a job are staged in
+// one of two LDS buffers.  While the MFMAs of job j read one buffer, the global loads of job
+// j + 1 are in flight in registers; after the MFMAs they are written to the other buffer (the
+// fibre contraction Z = f x happens then), and one barrier ends the step.
+struct RowJob {
+    int q, k0;         // entry of row_faces, first real k of the tile
+    int dense, kreal;  // dense face (else factors), real entries per face row
+    long long face_off, fib_off, t_off;
+    int kk, sel, ksel, rb, cb;
+};
+
+__device__ __forceinline__ void job_face(const MApplyArgs& A, int q, RowJob& J)
+{
+    const ApplyFace& F = A.faces[A.row_faces[q]];
+    const BlockIn& B = A.blocks[F.block];
+    J.q = q;
+    J.k0 = 0;
+    J.face_off = F.face_off;
+    J.fib_off = F.fib_off;
+    J.t_off = F.t_off;
+    J.kk = F.kk;
+    J.sel = F.sel;
+    J.ksel = F.ksel;
+    J.rb = B.rb;
+    J.cb = B.cb;
+    J.dense = F.kk == 0;
+    J.kreal = J.dense ? 6 * B.cs : 2 * F.kk;
+}
+
 template <typename R>
-__global__ __launch_bounds__(WGM, 4) void k_rows_mfma(MApplyArgs A, int ncols, const int* seglist, int nsegs)
+__device__ __forceinline__ void put_b(R* bs, int zcc, int kc, zd z)
+{
+    constexpr int LD = ldk<R>();
+    R* b0 = bs + (2 * zcc) * LD + 2 * kc;
+    b0[0] = (R)z.re;
+    b0[1] = (R)-z.im;
+    b0[LD] = (R)z.im;
+    b0[LD + 1] = (R)z.re;
+}
+
+// Staging of one job, written out in the kernel body (the loaded values must stay in
+// registers across the MFMAs of the previous job; helper functions taking them by reference
+// left them in memory).
+// ROW_FETCH(J): global loads of job J into av[] (face entries) and x0..x2 (the three inputs
+// of this thread's (column, element) pair: x of the element, or rows of T for factors).
+#define ROW_FETCH(J)                                                                                    \
+    do {                                                                                                \
+        const int nk_ = min(KC, (J).kreal - (J).k0);                                                    \
+        const R* H_ = (const R*)(A.pool + (J).face_off) + (size_t)3 * (rs0 - (J).rb) * (J).kreal + (J).k0; \
+        _Pragma("unroll") for (int i = 0; i < APT; ++i)                                                 \
+        {                                                                                               \
+            const int e = tid + WGM * i, r = e / KC, kr = e - r * KC;                                   \
+            av[i] = (r < nrows && kr < nk_) ? H_[(size_t)r * (J).kreal + kr] : (R)0;                    \
+        }                                                                                               \
+        const int kg0_ = ((J).k0 >> 1) + 3 * zjj;                                                       \
+        x0 = x1 = x2 = zd{0.0, 0.0};                                                                    \
+        if (zact && 6 * zjj < nk_) {                                                                    \
+            if ((J).dense) {                                                                            \
+                const zd* xv_ = A.x + ((size_t)zr * A.L + zl) * 3 * A.K + 3 * (size_t)((J).cb + kg0_ / 3); \
+                x0 = xv_[0];                                                                            \
+                x1 = xv_[1];                                                                            \
+                x2 = xv_[2];                                                                            \
+            } else {                                                                                    \
+                const zd* tv_ = A.tbuf + ((J).t_off + kg0_) * (size_t)ncols + zcol;                   \
+                x0 = tv_[0];                                                                            \
+                if (kg0_ + 1 < (J).kk) x1 = tv_[ncols];                                               \
+                if (kg0_ + 2 < (J).kk) x2 = tv_[2 * (size_t)ncols];                                   \
+            }                                                                                           \
+        }                                                                                               \
+    } while (0)
+
+// ROW_STORE(J, t): the registers of job J into LDS buffer t, with the fibre contraction
+// Z = f[l] x for a dense face
+#define ROW_STORE(J, t)                                                                                 \
+    do {                                                                                                \
+        R* as_ = As[t];                                                                                 \
+        _Pragma("unroll") for (int i = 0; i < APT; ++i)                                                 \
+        {                                                                                               \
+            const int e = tid + WGM * i, r = e / KC, kr = e - r * KC;                                   \
+            as_[r * LD + kr] = av[i];                                                                   \
+        }                                                                                               \
+        if (zcc < MCOL) {                                                                               \
+            zd z0 = x0, z1 = x1, z2 = x2;                                                               \
+            if ((J).dense && zact) {                                                                    \
+                if ((J).sel) {                                                                        \
+                    if (zl != (J).ksel) z0 = z1 = z2 = zd{0.0, 0.0};                                  \
+                } else {                                                                                \
+                    const zd* f = (const zd*)(A.pool + (J).fib_off) + (size_t)zl * 9;                 \
+                    z0 = fma_c(f[2], x2, fma_c(f[1], x1, f[0] * x0));                                   \
+                    z1 = fma_c(f[5], x2, fma_c(f[4], x1, f[3] * x0));                                   \
+                    z2 = fma_c(f[8], x2, fma_c(f[7], x1, f[6] * x0));                                   \
+                }                                                                                       \
+            }                                                                                           \
+            put_b<R>(Bs[t], zcc, 3 * zjj, z0);                                                          \
+            put_b<R>(Bs[t], zcc, 3 * zjj + 1, z1);                                                      \
+            put_b<R>(Bs[t], zcc, 3 * zjj + 2, z2);                                                      \
+        }                                                                                               \
+    } while (0)
+
+template <typename R>
+__global__ __launch_bounds__(WGM, 2) void k_rows_mfma(MApplyArgs A, int ncols, const int* seglist, int nsegs)
 {
     using C = MM<R>;
     constexpr int KC = C::KC, LD = ldk<R>();
-    __shared__ __align__(16) R As[MTR * LD];
-    __shared__ __align__(16) R Bs[NTR * LD];
-    __shared__ zd Fs[MCOL][9];
+    constexpr int APT = MTR * KC / WGM;   // face entries staged per thread and job
+    constexpr int EPT = KC / 6;           // column elements per job (KC real k = KC / 6 elements)
+    static_assert(KC % 6 == 0 && (MTR * KC) % WGM == 0, "tile shape");
+    __shared__ __align__(16) R As[2][MTR * LD];
+    __shared__ __align__(16) R Bs[2][NTR * LD];
     const int sg = seglist[blockIdx.x % nsegs];
     const int c0 = (blockIdx.x / nsegs) * MCOL;
     const int g = A.seg_group[sg];
@@ -217,32 +318,40 @@ __global__ __launch_bounds__(WGM, 4) void k_rows_mfma(MApplyArgs A, int ncols, c
     const int nrt = (nrows + 15) >> 4;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int rt0 = wv & 3, ct0 = 4 * (wv >> 2);
+    // this thread's (column, element) pair of the input side of a job
+    const int zcc = tid / EPT, zjj = tid - zcc * EPT;
+    const int zcol = c0 + zcc;
+    const bool zact = zcc < MCOL && zcol < ncols;
+    const int zl = zcol % A.L, zr = zcol / A.L;
     typename C::acc_t acc[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = typename C::acc_t{};
-    for (int q = A.seg_begin[sg]; q < A.seg_begin[sg + 1]; ++q) {
-        const ApplyFace F = A.faces[A.row_faces[q]];
-        if (F.kk < 0) continue;
-        const BlockIn B = A.blocks[F.block];
-        const bool dense = F.kk == 0;
-        const int kreal = dense ? 6 * B.cs : 2 * F.kk;  // real entries of a face row
-        const R* H = (const R*)(A.pool + F.face_off) + (size_t)3 * (rs0 - B.rb) * kreal;
-        // Fs is read only by the B staging, which every thread finished before the barrier
-        // that followed it, so it can be overwritten here
-        if (dense) stage_fibres_m(A, F, c0, ncols, Fs);
-        for (int k0 = 0; k0 < kreal; k0 += KC) {
-            const int nk = min(KC, kreal - k0);
-            __syncthreads();
-            for (int e = tid; e < 16 * nrt * KC; e += WGM) {
-                const int r = e / KC, kr = e - r * KC;
-                As[r * LD + kr] = (r < nrows && kr < nk) ? H[(size_t)r * kreal + k0 + kr] : (R)0;
-            }
-            stage_b<R>(A, B, F, dense, k0, nk, c0, ncols, Fs, Bs);
-            __syncthreads();
-            mfma_tile<R, 2>(As, Bs, rt0, ct0, nrt, lane, acc);
+    R av[APT];
+    zd x0, x1, x2;
+    const int qend = A.seg_begin[sg + 1];
+    RowJob cur;
+    job_face(A, A.seg_begin[sg], cur);
+    ROW_FETCH(cur);
+    ROW_STORE(cur, 0);
+    __syncthreads();
+    int buf = 0;
+    for (;;) {
+        RowJob nxt = cur;
+        bool more = true;
+        nxt.k0 += KC;
+        if (nxt.k0 >= nxt.kreal) {
+            if (cur.q + 1 < qend) job_face(A, cur.q + 1, nxt);
+            else more = false;
         }
+        if (more) ROW_FETCH(nxt);
+        mfma_tile<R, 2>(As[buf], Bs[buf], rt0, ct0, nrt, lane, acc);
+        if (!more) break;
+        ROW_STORE(nxt, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+        cur = nxt;
     }
     zd* pb = A.pbuf + (size_t)sg * MTM * ncols;
     const int li = lane & 15;
@@ -262,6 +371,9 @@ __global__ __launch_bounds__(WGM, 4) void k_rows_mfma(MApplyArgs A, int ncols, c
         }
     }
 }
+
+#undef ROW_FETCH
+#undef ROW_STORE
 
 // y rows of row chunk g = sum of its segments' partial rows, in segment order
 __global__ __launch_bounds__(256) void k_reduce_mrows(MApplyArgs A, int ncols)
