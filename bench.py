@@ -14,7 +14,9 @@ concurrently, each on its own context and stream.
 value = kernel entries (3x3 ENTRY(i, j, l) blocks) generated per second over the step.
 Extra fields: all-frequency H-matvecs/s (apply only), the FP64 path's step time and the
 mixed vs FP64 speedup, the relative error against the FP64 oracle on sampled rows, the
-roofline of the compression kernel and the oracle's CPU throughput; apart from value, a
+rooflines of the kernel groups of a step (3D-ACA face kernels, per-slice ACA, recompression,
+products on the matrix cores; `roofline` is the one with the most device time) and the
+oracle's CPU throughput; apart from value, a
 solve leg (GMRES with refinement at every contour point) and a batched-product leg (the
 single layers of four cube and sphere meshes, 128 contour points, 32 right-hand sides, one
 set of launches), an adjoint leg (gradient of a single-layer form on the sphere of 20480
@@ -37,6 +39,8 @@ sys.path.insert(0, ROOT)
 METRIC = "kernel entries/s and all-frequency H-matvecs/s at 1e-6 rel err; mixed vs FP64 speedup"
 PEAK_VALU = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: FP64 and non-packed FP32
 PEAK_HBM = 8.0e12    # HBM3E bytes/s
+PEAK_MFMA64 = 78.6e12   # dense FP64 MFMA
+PEAK_MFMA32 = 157.3e12  # dense FP32 MFMA
 
 
 # HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counters (two rocprofv3 --pmc runs of
@@ -46,6 +50,8 @@ PEAK_HBM = 8.0e12    # HBM3E bytes/s
 TRAFFIC = {
     "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp', 'compress.cpp'], "sha256_16": '0aaad72f98dea4e3'},
     "recomp": {"bytes": 8.82e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": 'a712f7b478606821'},
+    "aca": {"bytes": None, "sources": ['aca3d.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": None},
+    "product": {"bytes": None, "sources": ['mfma.hip', 'apply.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": None},
 }
 
 
@@ -53,6 +59,8 @@ def traffic(key):
     """Counter-measured bytes per dispatch of a kernel group, or None once its sources changed."""
     import hashlib
     t = TRAFFIC[key]
+    if t["bytes"] is None:
+        return None
     m = hashlib.sha256()
     for f in t["sources"]:
         with open(os.path.join(ROOT, "paper_2607_15292_amd", "csrc", f), "rb") as fh:
@@ -120,18 +128,26 @@ def batched_leg(args, dev, torch):
         yg = y.cpu().numpy().reshape(nrhs, Lb, K, 3)[:, :, rows, :].reshape(nrhs, Lb, -1)
         samples.append((name, X, T, rows, x.cpu().numpy(), yg))
     achieved = info["flop"] / (ms * 1e-3)
+    # roof of the arithmetic mix: complex64 work at the FP32 MFMA rate, complex128 work and the
+    # FP64 fibre contraction at the FP64 rate (the info flops split the same way)
+    f32 = f64 = 0.0
+    for o in ops:
+        v = o.stats()
+        f32 += 8.0 * v["apply_macs_c64"] * Lb * nrhs
+        f64 += 8.0 * ((v["apply_macs_c128"] + v["apply_macs_fibre"]) * Lb * nrhs + v["apply_macs_sel"] * nrhs)
+    peak = (f32 + f64) / (f32 / PEAK_MFMA32 + f64 / PEAK_MFMA64)
     out = {"workload": "single layers of %s, mixed precision eps %.0e (far-field floor %.0e), %d BDF2 gCQ points, "
                        "%d right-hand sides each" % (", ".join(names), args.batch_eps, args.batch_eps_floor, Lb, nrhs),
            "ms_per_product": ms, "products_per_s": len(ops) * nrhs * 1e3 / ms,
            "single_freq_matvecs_per_s": len(ops) * nrhs * Lb * 1e3 / ms,
            "compressed_gb": sum(o.stats()["bytes"] for o in ops) / 1e9,
-           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TFLOP/s",
-                        "frac": achieved / PEAK_VALU, "traffic": None,
-                        "kernel": "batched product (k_far_products + k_rows + k_reduce_rows + permutations)",
-                        "flop_per_product": info["flop"]},
-           "schedule": {k: info[k] for k in ("n_groups", "n_segments", "seg_target", "persistent", "persistent_wgs",
-                                             "far_sorted", "tune_ms", "tune_segments", "graph_builds",
-                                             "graph_launches", "workspace_bytes")},
+           "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / peak, "traffic": None,
+                        "kernel": "batched product (k_far_mfma + k_rows_mfma<float/double> + k_reduce_mrows + "
+                                  "permutations)",
+                        "flop_per_product": info["flop"], "flop_complex64_share": f32 / max(f32 + f64, 1.0)},
+           "schedule": {k: info[k] for k in ("n_groups", "n_segments", "seg_target", "far_sorted", "tune_ms",
+                                             "tune_segments", "graph_builds", "graph_launches", "workspace_bytes")},
            "tune_seconds": t1 - t0, "rel_err_sampled_rows": None,
            "_check": {"s": s, "samples": samples}}
     b.destroy()
@@ -544,9 +560,44 @@ def main():
                 seq_steps)
     rl_face = rl("face_ms", "face_flop", "face_launches", "k_face_dense / k_face_general (3D-ACA face kernels)",
                  "face", seq_steps, bytes_key="face_bytes")
-    roofline, roofline_next = (rl_rec[1], rl_face[1]) if rl_rec[0] >= rl_face[0] else (rl_face[1], rl_rec[1])
-    for r_ in (roofline, roofline_next):
-        r_["timing"] = "operators one at a time (HIP events around the launches on the context stream)"
+    rl_aca = rl("aca_kernel_ms", "aca_flop", "aca_launches", "k_face_aca (per-slice matrix-valued ACA of the far faces)",
+                "aca", seq_steps, bytes_key="aca_bytes")
+    groups = [rl_face, rl_aca, rl_rec]
+    # the all-frequency products (one operator at a time, HIP events around 10 products on the
+    # context stream): algorithmic flops 8 per complex multiply-add of the stored faces and
+    # factors with every column, plus the fibres; bytes = stored bytes + x + y; the roof is the
+    # MFMA peak of the arithmetic mix (complex64 work at the FP32 MFMA rate, complex128 work and
+    # the FP64 fibre contraction at the FP64 rate)
+    rl_prod = None
+    if apply_ms:
+        pflop = pt = pbytes = 0.0
+        for opk, v in zip(ops_list, st_m):
+            f32 = 8.0 * v["apply_macs_c64"] * L
+            f64 = 8.0 * ((v["apply_macs_c128"] + v["apply_macs_fibre"]) * L + v["apply_macs_sel"])
+            pflop += f32 + f64
+            pt += f32 / PEAK_MFMA32 + f64 / PEAK_MFMA64
+            pbytes += v["bytes"] + 2.0 * L * M * 16.0
+        ms = sum(apply_ms.values())
+        achieved = pflop / (ms * 1e-3)
+        peak = pflop / pt
+        rl_prod = (ms, {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / peak, "traffic": traffic("product"),
+                        "kernel": "bem_apply: k_far_mfma, k_rows_mfma<float/double>, k_reduce_mrows, permutations "
+                                  "(all-frequency products of V and I/2+K)",
+                        "launches": len(apply_ms), "avg_launch_ms": ms / len(apply_ms),
+                        "flop_per_launch": pflop / len(apply_ms), "bytes_per_launch": pbytes / len(apply_ms),
+                        "intensity_flop_per_byte": pflop / pbytes,
+                        "peak_note": "MFMA peak of the mix: FP32 %.1f and FP64 %.1f TFLOP/s weighted by the "
+                                     "algorithmic flops of each precision" % (PEAK_MFMA32 / 1e12, PEAK_MFMA64 / 1e12),
+                        "hbm": {"achieved": pbytes / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                "frac": pbytes / (ms * 1e-3) / PEAK_HBM}})
+        groups.append(rl_prod)
+    groups.sort(key=lambda g_: -g_[0])
+    roofline, roofline_next = groups[0][1], groups[1][1]
+    for g_ in groups:
+        g_[1]["timing"] = "operators one at a time (HIP events around the launches on the context stream)"
+        g_[1]["device_ms_per_step"] = g_[0] / (1 if g_ is rl_prod else len(seq_steps))
+    rooflines = {"face": rl_face[1], "aca": rl_aca[1], "recomp": rl_rec[1], "product": rl_prod[1] if rl_prod else None}
     # the same kernels in the timed steps, the two operators sharing the GPU
     roofline_conc = None
     if not args.sequential:
@@ -619,8 +670,9 @@ def main():
         "dtype": "mixed-f32-f64",
         "data": "synthetic",
         "config": {"workload": "pulsating sphere, icosphere %d triangles (%d DOF), V and I/2+K, %d BDF2 gCQ points, "
-                               "3D-ACA eps %.0e + H-matrix leaf 64 eta 1.5, complex64 far / complex128 near"
-                               % (K, M, L, args.eps),
+                               "3D-ACA eps %.0e (admissible blocks: eps and per-slice eps_ACA raised to the "
+                               "complex64 floor 1e-05; near blocks eps_ACA = eps/100) + H-matrix leaf 64 eta 1.5, "
+                               "complex64 far / complex128 near" % (K, M, L, args.eps),
                    "elements": K, "frequencies": L, "rhs": 1},
         "entries_per_s_by_rule": {k: sum(v["entries_" + k] for v in stats_steps[-1]) / sec_step
                                   for k in ("regular", "near", "self", "other")},
@@ -628,14 +680,15 @@ def main():
         "matvecs_per_s_single_freq": {k: v * L for k, v in hmv.items()},
         "compress_stats": [{k: v[k] for k in ("n_blocks", "n_near", "n_far", "n_dense_fallback", "rank_mean",
                                                "rank_max", "aca_rank_mean", "aca_rank_max", "aca_cols_mean",
-                                               "n_far_faces", "n_aca_dense", "compression_rate",
+                                               "n_far_faces", "n_aca_dense", "compression_rate", "bytes",
                                                "entries_generated", "kernel_ms", "face_ms", "aca_ms",
-                                               "recomp_ms", "entries_regular", "entries_near", "entries_self",
-                                               "entries_other")}
+                                               "aca_kernel_ms", "recomp_ms", "entries_regular", "entries_near",
+                                               "entries_self", "entries_other")}
                            for v in st_m],
         "rel_err": errs,
         "roofline": roofline,
         "roofline_next": roofline_next,
+        "rooflines": rooflines,
         "roofline_two_streams": roofline_conc,
         "solve": solve,
         "batched": batched,
@@ -652,6 +705,12 @@ def main():
         out["fp64"]["strict"] = {k: v for k, v in fp64["strict"].items() if k != "ys"}
         out["fp64"]["strict"]["hmatvecs_per_s"] = {str(k): 1e3 / v for k, v in fp64["strict"]["apply_ms"].items()}
         out["mixed_vs_fp64_speedup"] = fp64["sec_per_step"] / sec_step_seq
+        out["mixed_vs_fp64_speedup_basis"] = (
+            "step time, one operator at a time, FP64 at eps %.0e over mixed at eps %.0e: equal accuracy when "
+            "rel_err.fp64 and rel_err.mixed agree (the far-field floor of the mixed run does not show in the "
+            "per-frequency error); fp64.strict is the FP64 run that meets 1e-6" % (args.eps, args.eps))
+        out["mixed_vs_fp64_product_speedup"] = {
+            str(k): fp64["apply_ms"][k] / apply_ms[k] for k in ops_list if k in apply_ms and k in fp64["apply_ms"]}
     print(json.dumps(out))
 
 

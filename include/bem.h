@@ -165,6 +165,16 @@ typedef struct {
     double apply_macs_sel;        /* the same per right-hand side for the dense-fallback faces
                                      (each acts at one frequency) */
     double apply_macs_fibre;      /* complex multiply-adds per column of the fibres (9 n per face) */
+    double aca_kernel_ms;         /* device time of the per-slice ACA kernel (k_face_aca), HIP
+                                     events around each launch */
+    int64_t aca_launches;         /* its launches */
+    double aca_flop;              /* its algorithmic flops: per rank-3 step t of a face, the
+                                     residual 3-row and 3-column blocks updated by the 3t earlier
+                                     columns (9 (m + n) 3t complex multiply-adds) and the pivot
+                                     inverse applied (27 m) */
+    double aca_bytes;             /* its algorithmic bytes: per step the 3 (m + n) 3t earlier
+                                     column entries read (FP64), 9 (m + n) face entries read and
+                                     9 (m + n) column entries written */
 } bem_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -56,7 +56,9 @@ class bem_stats(ctypes.Structure):
                 ("entries_near", ctypes.c_int64), ("entries_self", ctypes.c_int64), ("entries_other", ctypes.c_int64),
                 ("face_bytes", ctypes.c_double), ("block_groups", ctypes.c_int64),
                 ("apply_macs_c64", ctypes.c_double), ("apply_macs_c128", ctypes.c_double),
-                ("apply_macs_sel", ctypes.c_double), ("apply_macs_fibre", ctypes.c_double)]
+                ("apply_macs_sel", ctypes.c_double), ("apply_macs_fibre", ctypes.c_double),
+                ("aca_kernel_ms", ctypes.c_double), ("aca_launches", ctypes.c_int64),
+                ("aca_flop", ctypes.c_double), ("aca_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

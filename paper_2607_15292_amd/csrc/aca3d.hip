@@ -302,6 +302,8 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
     s.hn2 = s.fmax2 = s.s3max = s.fn2 = 0.0;
     s.entries = 0;
     s.recomp_flop = 0.0;
+    s.aca_flop = 0.0;
+    s.aca_bytes = 0.0;
     s.pad2 = 0.0;
     for (int t = 0; t < 9; ++t) s.pinv[t] = {0.0, 0.0};
     for (int k = 0; k < A.L; ++k) A.used[(size_t)b * A.L + k] = 0;
@@ -672,7 +674,7 @@ constexpr double ACA_ABORT = 1.5;
 
 template <typename T>
 __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax, zd* pinv,
-                        zd* sk, double abort)
+                        zd* sk, double abort, int& built)
 {
     double est0 = 0.0;
     const int lane = threadIdx.x;
@@ -801,6 +803,7 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
         }
         un2 = wsum(un2);
         kc += 3;
+        built = kc;
         const double est = sqrt(un2 * rn2);
         if (est <= tol) return kc;
         if (kc == 3) est0 = est;
@@ -835,7 +838,8 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
 // ACA stage of one stored dense face: ||H||_F, the pivot scale max |H|, then face_aca;
 // returns the column count (-1: not resolved, or a zero face).  One wavefront.
 template <typename T>
-__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double abort)
+__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double abort,
+                              int& built)
 {
     double s2 = 0.0, amax = 0.0;
     const int cnt = 9 * m * n;
@@ -849,7 +853,7 @@ __device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, in
     __shared__ zd pinv[9];
     __shared__ zd sk[3 * KMAX_SLICE];
     if (cap > KMAX_SLICE) return -1;
-    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk, abort) : -1;
+    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk, abort, built) : -1;
 }
 
 // Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
@@ -875,17 +879,26 @@ __global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A)
     const FaceDesc f = A.faces[(size_t)b * A.L + d];
     const int m = B.rs, n = B.cs;
     AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
-    int kc = -1;
+    int kc = -1, built = 0;
     double tol = 0.0;
     if (f.kk == 0 && !f.sel) {
         const int cap = min(A.kmax, face_aca_cap(m, n));
         tol = face_tol(A, b, f);
-        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT)
-                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT);
+        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT, built)
+                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT, built);
     }
     if (threadIdx.x == 0) {
         w.info[0] = kc;
         w.tol[0] = tol;
+        // algorithmic work of the s = built / 3 rank-3 steps: step t updates a 3-row and a
+        // 3-column block by the 3t earlier columns (9 (m + n) 3t complex multiply-adds, reading
+        // 3 (m + n) 3t earlier column entries in FP64) and scales the new columns by the pivot
+        // inverse (27 m); it reads 9 (m + n) face entries and writes 9 (m + n) column entries
+        const double sd = built / 3, mn = (double)(m + n);
+        const double macs = 13.5 * mn * sd * (sd - 1.0) + 27.0 * m * sd;
+        const double bytes = 72.0 * mn * sd * (sd - 1.0) + sd * (9.0 * mn * (f.fp32 ? 8.0 : 16.0) + 144.0 * mn);
+        atomicAdd(&A.st[b].aca_flop, 8.0 * macs);
+        atomicAdd(&A.st[b].aca_bytes, bytes);
     }
 }
 
@@ -1235,8 +1248,9 @@ __global__ __launch_bounds__(WA) void k_aca_matrix(char* H, int m, int n, int fp
                                                    double* scratch, int* out)
 {
     AcaWork w = aca_work(scratch, m, n, kmax);
-    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, 0.0)
-                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, 0.0);
+    int built = 0;
+    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, 0.0, built)
+                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, 0.0, built);
     if (threadIdx.x == 0) {
         out[0] = kc;
         out[1] = 0;

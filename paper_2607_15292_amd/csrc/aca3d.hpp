@@ -55,6 +55,8 @@ struct BlockState {
     double hn2, fmax2, s3max, fn2;
     long long entries;
     double recomp_flop;  // algorithmic flops of this block's face recompressions
+    double aca_flop;     // algorithmic flops and HBM bytes of this block's per-slice ACA runs
+    double aca_bytes;
     double pad2;
     zd pinv[9];
 };

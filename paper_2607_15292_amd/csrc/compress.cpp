@@ -555,8 +555,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     double face_ms = 0.0, face_flop = 0.0, face_bytes = 0.0;
     int64_t face_launches = 0, face_pairs = 0;
     float kms = 0.f, aca_ms = 0.f;
-    double recomp_ms = 0.0;
-    int64_t recomp_launches = 0;
+    double recomp_ms = 0.0, aca_kernel_ms = 0.0;
+    int64_t recomp_launches = 0, aca_launches = 0;
     int err = 0;
     std::vector<BlockState>& S = C->st;
     S.resize(nb);
@@ -824,21 +824,25 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         for (size_t c0 = 0; c0 < items.size(); c0 += (size_t)slots) {
             A.list = p_items + c0;
             A.nlist = (int)std::min<size_t>((size_t)slots, items.size() - c0);
+            hipEvent_t e[3];
+            for (hipEvent_t& ev : e) {
+                BEM_HIP_TRY(hipEventCreate(&ev));
+                evr.push_back(ev);
+            }
+            BEM_HIP_TRY(hipEventRecord(e[0], st));
             launch_face_aca(A, st);
-            hipEvent_t e0, e1;
-            BEM_HIP_TRY(hipEventCreate(&e0));
-            BEM_HIP_TRY(hipEventCreate(&e1));
-            evr.push_back(e0);
-            evr.push_back(e1);
-            BEM_HIP_TRY(hipEventRecord(e0, st));
+            BEM_HIP_TRY(hipEventRecord(e[1], st));
             launch_face_recomp(A, st);
-            BEM_HIP_TRY(hipEventRecord(e1, st));
+            BEM_HIP_TRY(hipEventRecord(e[2], st));
+            ++aca_launches;
             ++recomp_launches;
         }
         BEM_HIP_TRY(hipStreamSynchronize(st));
-        for (size_t e = 0; e < evr.size(); e += 2) {
+        for (size_t e = 0; e < evr.size(); e += 3) {
             float ms = 0.f;
             BEM_HIP_TRY(hipEventElapsedTime(&ms, evr[e], evr[e + 1]));
+            aca_kernel_ms += ms;
+            BEM_HIP_TRY(hipEventElapsedTime(&ms, evr[e + 1], evr[e + 2]));
             recomp_ms += ms;
         }
         for (hipEvent_t e : evr) (void)hipEventDestroy(e);
@@ -974,6 +978,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         R.n_aca_dense += s.aca_dense;
         colsum += (double)s.aca_cols;
         rflop += s.recomp_flop;
+        R.aca_flop += s.aca_flop;
+        R.aca_bytes += s.aca_bytes;
         for (int d = 0; d < s.rank; ++d) {
             const FaceDesc& f = C->faces[(size_t)b * L + d];
             bytes += (int64_t)L * 9 * sizeof(zd);
@@ -1012,6 +1018,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.block_groups = C->ngroups_c;
     R.recomp_ms = recomp_ms;
     R.recomp_launches = recomp_launches;
+    R.aca_kernel_ms = aca_kernel_ms;
+    R.aca_launches = aca_launches;
     R.recomp_flop = rflop;
     R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BEM_OK;
