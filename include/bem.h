@@ -111,6 +111,12 @@ typedef struct {
     int32_t far_dense_max; /* admissible blocks whose smaller side has at most this many
                               elements keep dense faces (their per-slice ACA rank is close to
                               full); 0 = per-slice ACA on every admissible block; default 48 */
+    int32_t aca_rounds;   /* per-slice ACA runs that reach the column capacity of the pass (96
+                             columns) on a face whose factors could still save memory: 0 = the
+                             face stays dense (default); > 0 = the columns are recompressed
+                             (eq. (ACA), at a quarter of the face tolerance) and the ACA resumes
+                             from them, up to this many times per pass.  For memory-bound
+                             compressions: it trades recompression time for storage */
 } bem_aca_opts;
 
 /* Statistics of an operator (compression rate as defined in Sec. 4.1: memory of the

@@ -39,7 +39,7 @@ class bem_quad(ctypes.Structure):
 class bem_aca_opts(ctypes.Structure):
     _fields_ = [("eps3d", ctypes.c_double), ("eps_aca", ctypes.c_double), ("eta", ctypes.c_double),
                 ("leaf", ctypes.c_int32), ("prec", ctypes.c_int32), ("mixed_eps_floor", ctypes.c_double),
-                ("pool_bytes", ctypes.c_int64), ("far_dense_max", ctypes.c_int32)]
+                ("pool_bytes", ctypes.c_int64), ("far_dense_max", ctypes.c_int32), ("aca_rounds", ctypes.c_int32)]
 
 
 class bem_stats(ctypes.Structure):
@@ -278,9 +278,9 @@ class Context:
         return Operator(self, h)
 
     def compress(self, op, eps3d=1e-6, eps_aca=0.0, eta=1.5, leaf=64, prec=PREC_F64, mixed_eps_floor=1e-5,
-                 pool_bytes=0, far_dense_max=48):
+                 pool_bytes=0, far_dense_max=48, aca_rounds=0):
         o = bem_aca_opts(float(eps3d), float(eps_aca), float(eta), int(leaf), int(prec), float(mixed_eps_floor),
-                         int(pool_bytes), int(far_dense_max))
+                         int(pool_bytes), int(far_dense_max), int(aca_rounds))
         h = ctypes.c_void_p()
         self._check(lib().bem_compress(self.h, int(op), ctypes.byref(o), ctypes.byref(h)))
         return Operator(self, h)

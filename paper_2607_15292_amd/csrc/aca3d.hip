@@ -664,26 +664,38 @@ __device__ __forceinline__ void wargmax(double& v, int& idx)
 // columns are contiguous across lanes; the pivot's own 3 x kc slice is staged in LDS (sk).
 // The sigma_3 pivot search then reads the stored 3 x 3 blocks back.
 //
-// abort > 0 (the compression pass): once ABORT_STEPS rank-3 steps are done, the decay of the
-// step norms ||U_k|| ||V_k|| so far is extrapolated geometrically; a face whose predicted
-// column count to reach tol exceeds abort * cap is given up (-1, kept dense) without running
-// to the cap.  Such faces would mostly end dense anyway, and every further step re-reads all
-// earlier columns.  abort = 0 keeps the plain stopping rules (bem_aca_matrix).
+// kc0 > 0 resumes a run with kc0 columns already in U, V (recompressed from an earlier run that
+// reached the column capacity) at row irow0, with the used rows of that run.  resumable: on
+// reaching cap short of 3 min(m, n) columns the run returns -2 (and the next row in
+// info[2]) instead of -1, for the caller to recompress and resume.
+//
+// abort > 0 (the compression pass without resume): once ABORT_STEPS rank-3 steps are done, the
+// decay of the step norms ||U_k|| ||V_k|| so far is extrapolated geometrically; a face whose
+// predicted column count to reach tol exceeds abort * cap is given up (-1, kept dense) without
+// running to the cap.  Such faces would mostly end dense anyway, and every further step re-reads
+// all earlier columns.  abort = 0 keeps the plain stopping rules.
 constexpr int ABORT_STEPS = 8;
 constexpr double ACA_ABORT = 1.5;
 
 template <typename T>
 __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax, zd* pinv,
-                        zd* sk, double abort, int& built)
+                        zd* sk, int kc0, int irow0, bool resumable, double abort, int& built)
 {
     double est0 = 0.0;
     const int lane = threadIdx.x;
     const int M3 = 3 * m, N3 = 3 * n;
-    for (int i = lane; i < m; i += WA) w.usedrow[i] = 0;
+    if (kc0 == 0)
+        for (int i = lane; i < m; i += WA) w.usedrow[i] = 0;
     __syncthreads();
-    int kc = 0, fails = 0, skipped = 0, irow = 0;
+    int kc = kc0, fails = 0, skipped = 0, irow = irow0;
+    built = kc0;
     for (;;) {
-        if (kc + 3 > cap) return kc >= 3 * min(m, n) ? kc : -1;  // all of min(m, n) interpolated: exact
+        if (kc + 3 > cap) {
+            if (kc >= 3 * min(m, n)) return kc;  // all of min(m, n) interpolated: exact
+            if (!resumable) return -1;
+            if (lane == 0) w.info[2] = irow;
+            return -2;
+        }
         // residual row block irow -> V columns kc..kc+2 (row^H); sk = U rows 3 irow .. + 2
         for (int q = lane; q < 3 * kc; q += WA) {
             const int c = q / 3, y = q - 3 * c;
@@ -838,8 +850,8 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
 // ACA stage of one stored dense face: ||H||_F, the pivot scale max |H|, then face_aca;
 // returns the column count (-1: not resolved, or a zero face).  One wavefront.
 template <typename T>
-__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double abort,
-                              int& built)
+__device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, int kc0, int irow0,
+                              bool resumable, double abort, int& built)
 {
     double s2 = 0.0, amax = 0.0;
     const int cnt = 9 * m * n;
@@ -853,7 +865,7 @@ __device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, in
     __shared__ zd pinv[9];
     __shared__ zd sk[3 * KMAX_SLICE];
     if (cap > KMAX_SLICE) return -1;
-    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk, abort, built) : -1;
+    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk, kc0, irow0, resumable, abort, built) : -1;
 }
 
 // Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
@@ -870,35 +882,56 @@ __device__ double face_tol(const CompressArgs& A, int b, const FaceDesc& f)
 // Per-slice ACA pass, one wavefront per listed face (items (block << 8) | d, scratch slot =
 // position in the list): k_face_aca leaves the ACA columns, their count and the face's
 // tolerance in the slot; k_face_recomp (recomp.hip) recompresses them and rewrites the face
-// descriptor.
-__global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A)
+// descriptor.  A run that reaches the column capacity of the slot (KMAX_SLICE) on a face whose
+// factors could still save memory returns -2: k_face_recomp recompresses its columns into the
+// slot's other half at a tighter tolerance and leaves state -3, and a resume launch
+// (resume = 1) continues the run from those columns.
+__global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A, int resume)
 {
     const int item = A.list[blockIdx.x];
     const int b = item >> 8, d = item & 255;
     const BlockIn B = A.blocks[b];
     const FaceDesc f = A.faces[(size_t)b * A.L + d];
     const int m = B.rs, n = B.cs;
-    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
-    int kc = -1, built = 0;
+    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax, ACA_HALVES);
+    if (resume && w.info[0] != -3) return;
+    int kc = -1, built = 0, kc0 = 0, irow0 = 0;
     double tol = 0.0;
+    if (resume) {
+        kc0 = w.info[1];
+        irow0 = w.info[2];
+        tol = w.tol[0];
+        aca_select_half(w);
+    } else if (threadIdx.x == 0) {
+        w.info[3] = 0;
+    }
     if (f.kk == 0 && !f.sel) {
         const int cap = min(A.kmax, face_aca_cap(m, n));
-        tol = face_tol(A, b, f);
-        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT, built)
-                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, ACA_ABORT, built);
+        const bool resumable = A.aca_rounds > 0 && cap == KMAX_SLICE && face_aca_cap(m, n) > KMAX_SLICE;
+        const double abort = A.aca_rounds > 0 ? 0.0 : ACA_ABORT;
+        if (!resume) tol = face_tol(A, b, f);
+        kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, tol, kc0, irow0, resumable,
+                                     abort, built)
+                    : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, tol, kc0, irow0, resumable,
+                                     abort, built);
     }
     if (threadIdx.x == 0) {
         w.info[0] = kc;
         w.tol[0] = tol;
-        // algorithmic work of the s = built / 3 rank-3 steps: step t updates a 3-row and a
-        // 3-column block by the 3t earlier columns (9 (m + n) 3t complex multiply-adds, reading
-        // 3 (m + n) 3t earlier column entries in FP64) and scales the new columns by the pivot
-        // inverse (27 m); it reads 9 (m + n) face entries and writes 9 (m + n) column entries
-        const double sd = built / 3, mn = (double)(m + n);
-        const double macs = 13.5 * mn * sd * (sd - 1.0) + 27.0 * m * sd;
-        const double bytes = 72.0 * mn * sd * (sd - 1.0) + sd * (9.0 * mn * (f.fp32 ? 8.0 : 16.0) + 144.0 * mn);
-        atomicAdd(&A.st[b].aca_flop, 8.0 * macs);
-        atomicAdd(&A.st[b].aca_bytes, bytes);
+        if (kc == -2) w.info[1] = built;  // the columns to recompress
+        // algorithmic work of the rank-3 steps t = t0 .. t1 - 1 of this run (t0 = kc0 / 3,
+        // t1 = built / 3): step t updates a 3-row and a 3-column block by the 3t earlier columns
+        // (9 (m + n) 3t complex multiply-adds, reading 3 (m + n) 3t earlier column entries in
+        // FP64) and scales the new columns by the pivot inverse (27 m); it reads 9 (m + n) face
+        // entries and writes 9 (m + n) column entries
+        const double t0 = kc0 / 3, t1 = built / 3, mn = (double)(m + n);
+        const double tri = t1 * (t1 - 1.0) - t0 * (t0 - 1.0);
+        const double macs = 13.5 * mn * tri + 27.0 * m * (t1 - t0);
+        const double bytes = 72.0 * mn * tri + (t1 - t0) * (9.0 * mn * (f.fp32 ? 8.0 : 16.0) + 144.0 * mn);
+        if (t1 > t0) {
+            atomicAdd(&A.st[b].aca_flop, 8.0 * macs);
+            atomicAdd(&A.st[b].aca_bytes, bytes);
+        }
     }
 }
 
@@ -1249,8 +1282,8 @@ __global__ __launch_bounds__(WA) void k_aca_matrix(char* H, int m, int n, int fp
 {
     AcaWork w = aca_work(scratch, m, n, kmax);
     int built = 0;
-    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, 0.0, built)
-                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, 0.0, built);
+    const int kc = fp32 ? face_aca_stage((const cx<float>*)H, m, n, w, cap, tol, 0, 0, false, 0.0, built)
+                        : face_aca_stage((const cx<double>*)H, m, n, w, cap, tol, 0, 0, false, 0.0, built);
     if (threadIdx.x == 0) {
         out[0] = kc;
         out[1] = 0;
@@ -1277,10 +1310,10 @@ __global__ __launch_bounds__(WG) void k_copy_segments(const char* src, char* dst
 
 }  // namespace
 
-size_t aca_scratch_doubles(int m, int n, int kmax)
+size_t aca_scratch_doubles(int m, int n, int kmax, int halves)
 {
-    return (size_t)2 * (3 * (size_t)m * kmax + 3 * (size_t)n * kmax + 5 * (size_t)kmax * kmax) + kmax +
-           (m + kmax + 4 + 1) / 2 + 8;
+    return (size_t)2 * (3 * (size_t)halves * m * kmax + 3 * (size_t)halves * n * kmax + 5 * (size_t)kmax * kmax) +
+           kmax + (m + kmax + 4 + 1) / 2 + 8;
 }
 
 #define BEM_LAUNCH(kern, grid, block, ...)                                                     \
@@ -1314,9 +1347,9 @@ void launch_face_dense(const CompressArgs& A, int path, hipStream_t st)
         default: launch_face_general<true, true>(A, st); break;
     }
 }
-void launch_face_aca(const CompressArgs& A, hipStream_t st)
+void launch_face_aca(const CompressArgs& A, hipStream_t st, int resume)
 {
-    BEM_LAUNCH(k_face_aca, A.nlist, WA, A);
+    BEM_LAUNCH(k_face_aca, A.nlist, WA, A, resume);
 }
 void launch_classify(const DevCtx& c, const BlockIn* blocks, const int* list, const long long* off, int n,
                      int* order, int* counts, hipStream_t st)

@@ -84,6 +84,8 @@ struct CompressArgs {
     int* err;
     double* scratch;
     size_t scratch_per_slot;  // doubles
+    int* pending;           // faces left at slot state -3 by a recompression launch (counter)
+    int aca_rounds;         // resume launches allowed after intermediate recompressions (0: none)
     const int* pairs;       // pair orders of the blocks with pair0 >= 0
     const unsigned char* sel;  // blocks that k_init starts (nullptr: all); the others keep their state
     double eps3d, eps3d_far, eps_aca_far;
@@ -100,24 +102,34 @@ __host__ __device__ inline int face_aca_cap(int m, int n)
 
 // Scratch slot of one face in the per-slice ACA pass: ACA columns and the small matrices of
 // the recompression.
+// The compression pass keeps two column halves (U2, V2): an ACA that reaches the column
+// capacity is recompressed into the other half and resumes from there.
 struct AcaWork {
-    zd *U, *V;        // 3m x kmax, 3n x kmax column-major
+    zd *U, *V;        // 3m x kmax, 3n x kmax column-major: the current ACA columns
+    zd *U2, *V2;      // the other halves (null in a one-half slot)
     zd *G, *RU, *RV;  // kmax x kmax
     zd *M, *VJ;       // kmax x kmax
     double* tol;      // [0]: absolute tolerance of the face in this slot
     int* usedrow;     // m
     int* order;       // kmax
-    int* info;        // [0]: ACA columns of the face in this slot (-1: not resolved)
+    int* info;        // [0]: state of the face in this slot: ACA columns (> 0), -1 not resolved,
+                      // -2 column capacity reached (recompress and resume), -3 resume pending,
+                      // -4 done; [1]: columns to resume with; [2]: next pivot row; [3]: current
+                      // half (0 or 1)
 };
 
-__device__ inline AcaWork aca_work(double* base, int m, int n, int kmax)
+__device__ inline AcaWork aca_work(double* base, int m, int n, int kmax, int halves = 1)
 {
     AcaWork w;
     zd* z = (zd*)base;
     w.U = z;
     z += (size_t)3 * m * kmax;
+    w.U2 = halves > 1 ? z : nullptr;
+    z += (size_t)(halves - 1) * 3 * m * kmax;
     w.V = z;
     z += (size_t)3 * n * kmax;
+    w.V2 = halves > 1 ? z : nullptr;
+    z += (size_t)(halves - 1) * 3 * n * kmax;
     w.G = z;
     z += (size_t)kmax * kmax;
     w.RU = z;
@@ -135,7 +147,21 @@ __device__ inline AcaWork aca_work(double* base, int m, int n, int kmax)
     return w;
 }
 
-size_t aca_scratch_doubles(int mmax, int nmax, int kmax);
+size_t aca_scratch_doubles(int mmax, int nmax, int kmax, int halves = 1);
+// the slot of the compression pass: two column halves
+constexpr int ACA_HALVES = 2;
+// the current column half of a slot (info[3]) as U, V
+__device__ inline void aca_select_half(AcaWork& w)
+{
+    if (w.U2 && w.info[3]) {
+        zd* t = w.U;
+        w.U = w.U2;
+        w.U2 = t;
+        t = w.V;
+        w.V = w.V2;
+        w.V2 = t;
+    }
+}
 void launch_init(const CompressArgs& A, hipStream_t st);
 // path: 1 / 2 regular tiles with complex64 / complex128 faces (k_face_dense, FP32 / FP64
 // rule); 0 / 3 near tiles and 4 / 5 self tiles with complex128 / complex64 faces
@@ -156,7 +182,9 @@ void launch_final_prev(const CompressArgs& A, hipStream_t st);
 void launch_fallback(const CompressArgs& A, int kf, hipStream_t st);
 void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st);
 // per-slice ACA (k_face_aca); the recompression of its columns follows (k_face_recomp)
-void launch_face_aca(const CompressArgs& A, hipStream_t st);
+// resume = 0: first run over the listed faces; 1: the faces whose run is pending after an
+// intermediate recompression (slot state -3)
+void launch_face_aca(const CompressArgs& A, hipStream_t st, int resume = 0);
 void launch_face_recomp(const CompressArgs& A, hipStream_t st);
 void launch_copy_segments(const char* src, char* dst, const long long* seg, int nseg, hipStream_t st);
 void launch_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax, double* scratch, int* out,

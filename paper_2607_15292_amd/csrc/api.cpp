@@ -591,10 +591,11 @@ int bem_compress(bem_ctx* ctx, int32_t op, const bem_aca_opts* opts, bem_op** ou
         need_state(ctx);
         need_device(ctx);
         if (op == BEM_OP_TABLE && !ctx->table) throw api_error(BEM_ERR_STATE, "no entry table set");
-        bem_aca_opts o{1e-6, 0.0, 1.5, 64, BEM_PREC_F64, 1e-5, 0, 48};
+        bem_aca_opts o{1e-6, 0.0, 1.5, 64, BEM_PREC_F64, 1e-5, 0, 48, 0};
         if (opts) o = *opts;
         if (!(o.eps3d > 0 && o.eps3d < 1) || !(o.eta > 0) || o.leaf < 1 ||
-            (o.prec != BEM_PREC_F64 && o.prec != BEM_PREC_MIXED) || o.pool_bytes < 0 || o.far_dense_max < 0)
+            (o.prec != BEM_PREC_F64 && o.prec != BEM_PREC_MIXED) || o.pool_bytes < 0 || o.far_dense_max < 0 ||
+            o.aca_rounds < 0 || o.aca_rounds > 64)
             throw api_error(BEM_ERR_ARG, "bad compression options");
         if (!(o.eps_aca > 0)) o.eps_aca = o.eps3d / 100.0;
         if (!(o.mixed_eps_floor > 0)) o.mixed_eps_floor = 1e-5;

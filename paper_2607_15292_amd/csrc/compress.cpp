@@ -603,6 +603,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     A.pool_cap = C->pool.bytes;
     A.pool_top = top_dev;
     A.err = err_dev;
+    A.pending = (int*)(aux.as<char>() + 128);
+    A.aca_rounds = o.aca_rounds;
     A.scratch = nullptr;
     A.scratch_per_slot = 0;
     A.pairs = pairs_dev.as<int>();
@@ -682,6 +684,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         unsigned char* p;
         ~PinnedFree() { if (p) (void)hipHostFree(p); }
     } flags_guard{flags};
+    int* pending_h = (int*)(flags + (((size_t)nb + 3) & ~(size_t)3));  // in the pinned tail
     for (int d = 0; d < L; ++d) {
         launch_active_flags(A, flags_dev.as<unsigned char>(), st);
         BEM_HIP_TRY(hipMemcpyAsync(flags, flags_dev.p, (size_t)nb, hipMemcpyDeviceToHost, st));
@@ -810,7 +813,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     });
     BEM_HIP_TRY(hipEventRecord(ev1, st));
     if (!items.empty()) {
-        size_t per_slot = (aca_scratch_doubles(mmax, nmax, kmax) + 31) & ~(size_t)31;
+        size_t per_slot = (aca_scratch_doubles(mmax, nmax, kmax, ACA_HALVES) + 31) & ~(size_t)31;
         size_t fr = 0, tot = 0;
         BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
         const size_t fit = std::max<size_t>(256, (size_t)(0.5 * (double)fr) / (per_slot * sizeof(double)));
@@ -824,18 +827,28 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         for (size_t c0 = 0; c0 < items.size(); c0 += (size_t)slots) {
             A.list = p_items + c0;
             A.nlist = (int)std::min<size_t>((size_t)slots, items.size() - c0);
-            hipEvent_t e[3];
-            for (hipEvent_t& ev : e) {
-                BEM_HIP_TRY(hipEventCreate(&ev));
-                evr.push_back(ev);
+            // first run over the chunk, then resume launches while intermediate recompressions
+            // leave faces pending (the count comes back through pinned memory)
+            for (int round = 0; round <= o.aca_rounds; ++round) {
+                if (round > 0) {
+                    BEM_HIP_TRY(hipMemcpyAsync(pending_h, A.pending, sizeof(int), hipMemcpyDeviceToHost, st));
+                    BEM_HIP_TRY(hipStreamSynchronize(st));
+                    if (*pending_h == 0) break;
+                }
+                BEM_HIP_TRY(hipMemsetAsync(A.pending, 0, sizeof(int), st));
+                hipEvent_t e[3];
+                for (hipEvent_t& ev : e) {
+                    BEM_HIP_TRY(hipEventCreate(&ev));
+                    evr.push_back(ev);
+                }
+                BEM_HIP_TRY(hipEventRecord(e[0], st));
+                launch_face_aca(A, st, round > 0 ? 1 : 0);
+                BEM_HIP_TRY(hipEventRecord(e[1], st));
+                launch_face_recomp(A, st);
+                BEM_HIP_TRY(hipEventRecord(e[2], st));
+                ++aca_launches;
+                ++recomp_launches;
             }
-            BEM_HIP_TRY(hipEventRecord(e[0], st));
-            launch_face_aca(A, st);
-            BEM_HIP_TRY(hipEventRecord(e[1], st));
-            launch_face_recomp(A, st);
-            BEM_HIP_TRY(hipEventRecord(e[2], st));
-            ++aca_launches;
-            ++recomp_launches;
         }
         BEM_HIP_TRY(hipStreamSynchronize(st));
         for (size_t e = 0; e < evr.size(); e += 3) {

@@ -100,7 +100,8 @@ struct Rs {
     int piv, flag;
 };
 
-// 32 x 32 thread grid for the element loops over small matrices
+// 32 x GY thread grid for the element loops over small matrices
+constexpr int GY = NT / 32;
 __device__ __forceinline__ int gx() { return threadIdx.x & 31; }
 __device__ __forceinline__ int gy() { return threadIdx.x >> 5; }
 
@@ -108,14 +109,15 @@ __device__ __forceinline__ int gy() { return threadIdx.x >> 5; }
 // thread owns up to two 2 x 2 tiles of the upper triangle.  Row chunks of X are staged
 // through Lm in two planes (even and odd columns), so that the lanes of a tile row read
 // consecutive entries.
+constexpr int GT = ((KF / 2) * (KF / 2 + 1) / 2 + NT - 1) / NT;  // 2 x 2 tiles per thread
 __device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
 {
     const int nt = (kc + 1) >> 1, ntri = nt * (nt + 1) / 2;
     const int cr = min(rows, LMS / (2 * nt)), pl = cr * nt;
-    int ti[2], tj[2];
-    bool act[2];
+    int ti[GT], tj[GT];
+    bool act[GT];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < GT; ++h) {
         const int tt = threadIdx.x + h * NT;
         act[h] = tt < ntri;
         int j = 0;
@@ -127,9 +129,9 @@ __device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
         tj[h] = j;
         ti[h] = act[h] ? tt - j * (j + 1) / 2 : 0;
     }
-    zd acc[2][4];
+    zd acc[GT][4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < GT; ++h)
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[h][u] = {0.0, 0.0};
     for (int r0 = 0; r0 < rows; r0 += cr) {
@@ -151,7 +153,7 @@ __device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
         }
         __syncthreads();
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < GT; ++h) {
             if (!act[h]) continue;
             const zd* pa = Lm + ti[h];
             const zd* pb = Lm + tj[h];
@@ -166,7 +168,7 @@ __device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
     }
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < GT; ++h) {
         if (!act[h]) continue;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -201,7 +203,7 @@ __device__ double cholesky(zd* Lm, int kc, int ld)
         }
         if (p > 1e-24) {
             const double ip = 1.0 / p;
-            for (int j = k + 1 + ty; j < kc; j += 32) {
+            for (int j = k + 1 + ty; j < kc; j += GY) {
                 const zd rj = Lm[(size_t)j * ld + k] * ip;
                 for (int i = k + 1 + tx; i <= j; i += 32) Lm[(size_t)j * ld + i] -= conj_mul(Lm[(size_t)i * ld + k], rj);
             }
@@ -210,7 +212,7 @@ __device__ double cholesky(zd* Lm, int kc, int ld)
         __syncthreads();
     }
     if (threadIdx.x == 0 && kc > 0) Lm[(size_t)(kc - 1) * ld + kc - 1] = {pprev > 1e-24 ? sqrt(pprev) : 0.0, 0.0};
-    for (int j = ty; j < kc; j += 32)
+    for (int j = ty; j < kc; j += GY)
         for (int i = j + 1 + tx; i < kc; i += 32) Lm[(size_t)j * ld + i] = {0.0, 0.0};
     __syncthreads();
     return pmin;
@@ -265,7 +267,7 @@ __device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, double* dsc
         dsc[c] = g > 0.0 ? sqrt(g) : 0.0;
     }
     __syncthreads();
-    for (int j = ty; j < kc; j += 32)
+    for (int j = ty; j < kc; j += GY)
         for (int i = tx; i < kc; i += 32) {
             const double di = dsc[i], dj = dsc[j];
             zd* e = Lm + (size_t)j * ld + i;
@@ -274,7 +276,7 @@ __device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, double* dsc
     __syncthreads();
     const double pmin = cholesky(Lm, kc, ld);
     if (pmin >= CQ2_PIVOT) {
-        for (int j = ty; j < kc; j += 32)
+        for (int j = ty; j < kc; j += GY)
             for (int i = tx; i < kc; i += 32) {
                 const zd v = Lm[(size_t)j * ld + i];
                 Tout[(size_t)j * kc + i] = v;
@@ -289,20 +291,20 @@ __device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, double* dsc
     }
     __syncthreads();
     trsm(X, rows, Lm, kc, ld);
-    for (int j = ty; j < kc; j += 32)
+    for (int j = ty; j < kc; j += GY)
         for (int i = tx; i < kc; i += 32) Tout[(size_t)j * kc + i] = Lm[(size_t)j * ld + i];  // R1 (for now)
     __syncthreads();
     gram(X, rows, kc, Lm, ld);
     cholesky(Lm, kc, ld);
     // Rout = R2 R1 D, then Tout = R2
-    for (int j = ty; j < kc; j += 32)
+    for (int j = ty; j < kc; j += GY)
         for (int i = tx; i < kc; i += 32) {
             zd s = {0.0, 0.0};
             for (int t = i; t <= j; ++t) s += Lm[(size_t)t * ld + i] * Tout[(size_t)j * kc + t];
             Rout[(size_t)j * kc + i] = i <= j ? s * dsc[j] : zd{0.0, 0.0};
         }
     __syncthreads();
-    for (int j = ty; j < kc; j += 32)
+    for (int j = ty; j < kc; j += GY)
         for (int i = tx; i < kc; i += 32) Tout[(size_t)j * kc + i] = Lm[(size_t)j * ld + i];
     for (int c = threadIdx.x; c < kc; c += NT) dsc[c] = 1.0;
     __syncthreads();
@@ -563,7 +565,7 @@ __device__ void backsub2(const zd* R0, const double* d0, zd* Y0, const zd* R1, c
         __syncthreads();
     }
     const int tx = gx(), ty = gy();
-    for (int s = ty; s < nsys * kk; s += 32) {
+    for (int s = ty; s < nsys * kk; s += GY) {
         const bool h = s >= kk;
         const double* d = h ? d1 : d0;
         zd* y = (h ? Y1 : Y0) + (size_t)(h ? s - kk : s) * ldy;
@@ -572,10 +574,10 @@ __device__ void backsub2(const zd* R0, const double* d0, zd* Y0, const zd* R1, c
     __syncthreads();
 }
 
-// out_h (rows_h x kk, row-major, precision T) = X_h (rows_h x kc, column-major, global) Y_h
-// (kc x kk, column-major with ld ldy, LDS) for up to two products; a thread per (row, 8
-// columns).
-template <typename T>
+// out_h (rows_h x kk, row-major, precision T; CM: column-major complex128) = X_h (rows_h x kc,
+// column-major, global) Y_h (kc x kk, column-major with ld ldy, LDS) for up to two products; a
+// thread per (row, 8 columns).
+template <typename T, bool CM = false>
 __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T>* o1, const zd* X1, int rows1,
                           const zd* Y1, int kc, int kk, int ldy)
 {
@@ -601,7 +603,10 @@ __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T
         cx<T>* out = h ? o1 : o0;
 #pragma unroll
         for (int u = 0; u < CH; ++u)
-            if (s0 + u < kk) stz(out + (size_t)r * kk + s0 + u, acc[u]);
+            if (s0 + u < kk) {
+                if (CM) ((zd*)out)[(size_t)(s0 + u) * rows + r] = acc[u];
+                else stz(out + (size_t)r * kk + s0 + u, acc[u]);
+            }
     }
     __syncthreads();
 }
@@ -626,7 +631,11 @@ __device__ double recomp_flops(int stage, int m, int n, int kc, int kq, int swee
     return f;
 }
 
-template <typename T>
+// CM (the intermediate recompression of a run that reached the column capacity): the factors
+// go to the slot's other column half (w.U2, w.V2) in complex128 column-major, at most KF_RESUME
+// of them, with no memory rule.
+constexpr int KF_RESUME = KF - 12;
+template <typename T, bool CM = false>
 __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L, double& flop)
 {
     zd* Lm = L.m;
@@ -636,7 +645,7 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     chol_qr(w.U, 3 * m, kc, w.RU, w.G, L.du, L, ld);
     chol_qr(w.V, 3 * n, kc, w.RV, w.VJ, L.dv, L, ld);
     // M = R_U R_V^H
-    for (int j = ty; j < kc; j += 32)
+    for (int j = ty; j < kc; j += GY)
         for (int i = tx; i < kc; i += 32) {
             zd s = {0.0, 0.0};
             for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
@@ -648,10 +657,10 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     flop = recomp_flops(0, m, n, kc, kq, 0, 0);
     if (kq == 0) return 0;
     // keep the pivoted QR, form B^H (kc x kq): B^H[perm[c]][i] = conj(R[i][c]), i <= c
-    for (int j = ty; j < kc; j += 32)
+    for (int j = ty; j < kc; j += GY)
         for (int i = tx; i < kc; i += 32) w.M[(size_t)j * kc + i] = Lm[(size_t)j * ld + i];
     __syncthreads();
-    for (int i = ty; i < kq; i += 32)
+    for (int i = ty; i < kq; i += GY)
         for (int c = tx; c < kc; c += 32) {
             const zd v = i <= c ? conj(w.M[(size_t)c * kc + i]) : zd{0.0, 0.0};
             Lm[(size_t)i * ld + L.perm[c]] = v;
@@ -692,7 +701,7 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
             }
         }
         if (tot > 0.0 && kk == 0) kk = 1;
-        if ((long long)kk * (m + n) >= 3LL * m * n) kk = 0;
+        if (CM ? kk > KF_RESUME : (long long)kk * (m + n) >= 3LL * m * n) kk = 0;
         L.piv = kk;
     }
     __syncthreads();
@@ -701,7 +710,7 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     flop = recomp_flops(2, m, n, kc, kq, sweeps, kk);
     // Ubar coefficients -> RV: sigma_s [VJ_s; 0] with VJ_s = B W_s / sigma_s^2 (kq entries);
     // Vbar coefficients -> RU: W_s / sigma_s
-    for (int s = ty; s < kk; s += 32) {
+    for (int s = ty; s < kk; s += GY) {
         const int c = L.order[s];
         const double sg = L.sv[c];
         const zd* Wc = Lm + (size_t)c * ld;
@@ -716,7 +725,7 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
         }
     }
     __syncthreads();
-    for (int s = ty; s < kk; s += 32) {
+    for (int s = ty; s < kk; s += GY) {
         const int c = L.order[s];
         const double sg = L.sv[c];
         for (int r = tx; r < kc; r += 32)
@@ -728,7 +737,7 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     const bool both = 2 * ld * kk <= LMS;
     zd* Yu = Lm;
     zd* Yv = both ? Lm + (size_t)ld * kk : nullptr;
-    for (int s = ty; s < kk; s += 32)
+    for (int s = ty; s < kk; s += GY)
         for (int i = tx; i < kc; i += 32) {
             Yu[(size_t)s * ld + i] = w.RV[(size_t)s * kc + i];
             if (both) Yv[(size_t)s * ld + i] = w.RU[(size_t)s * kc + i];
@@ -755,25 +764,27 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
         }
         __syncthreads();
     }
-    cx<T>* Ub = Hout;
-    cx<T>* Vb = Hout + (size_t)3 * m * kk;
+    cx<T>* Ub = CM ? (cx<T>*)w.U2 : Hout;
+    cx<T>* Vb = CM ? (cx<T>*)w.V2 : Hout + (size_t)3 * m * kk;
     if (both) {
         backsub2(w.G, L.du, Yu, w.VJ, L.dv, Yv, kc, kk, ld);
-        out_gemm2(Ub, w.U, 3 * m, Yu, Vb, w.V, 3 * n, Yv, kc, kk, ld);
+        out_gemm2<T, CM>(Ub, w.U, 3 * m, Yu, Vb, w.V, 3 * n, Yv, kc, kk, ld);
     } else {
         backsub2(w.G, L.du, Yu, nullptr, nullptr, nullptr, kc, kk, ld);
-        out_gemm2<T>(Ub, w.U, 3 * m, Yu, nullptr, nullptr, 0, nullptr, kc, kk, ld);
-        for (int s = ty; s < kk; s += 32)
+        out_gemm2<T, CM>(Ub, w.U, 3 * m, Yu, nullptr, nullptr, 0, nullptr, kc, kk, ld);
+        for (int s = ty; s < kk; s += GY)
             for (int i = tx; i < kc; i += 32) Lm[(size_t)s * ld + i] = w.RU[(size_t)s * kc + i];
         __syncthreads();
         backsub2(w.VJ, L.dv, Lm, nullptr, nullptr, nullptr, kc, kk, ld);
-        out_gemm2<T>(Vb, w.V, 3 * n, Lm, nullptr, nullptr, 0, nullptr, kc, kk, ld);
+        out_gemm2<T, CM>(Vb, w.V, 3 * n, Lm, nullptr, nullptr, 0, nullptr, kc, kk, ld);
     }
     return kk;
 }
 
 // one workgroup per listed face (item (block << 8) | d, scratch slot = position in the list)
-// after k_face_aca: recompresses the slot's ACA columns and rewrites the face descriptor
+// after k_face_aca: recompresses the slot's ACA columns and rewrites the face descriptor.  A
+// run that reached the column capacity (state -2) is recompressed at tol / 4 into the slot's
+// other half and left for a resume launch (state -3); every other face ends at state -4.
 __global__ __launch_bounds__(NT) void k_face_recomp(CompressArgs A)
 {
     __shared__ Rs L;
@@ -784,22 +795,34 @@ __global__ __launch_bounds__(NT) void k_face_recomp(CompressArgs A)
     const FaceDesc f = *fp;
     if (f.kk != 0 || f.sel) return;
     const int m = B.rs, n = B.cs;
-    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax);
+    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax, ACA_HALVES);
     const int kc = w.info[0];
+    if (kc == -3 || kc == -4) return;
+    aca_select_half(w);
     int kk = 0;
     double flop = 0.0;
     if (kc > 0 && kc <= KF) {
         const double tol = w.tol[0];
         kk = f.fp32 ? recompress((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop)
                     : recompress((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop);
+    } else if (kc == -2) {
+        kk = recompress<double, true>(nullptr, m, n, w, w.info[1], 0.25 * w.tol[0], L, flop);
     }
     if (threadIdx.x == 0) {
         atomicAdd(&A.st[b].recomp_flop, flop);
-        if (kk > 0) {
-            fp->kk = kk;
-            atomicAdd((unsigned long long*)&A.st[b].aca_cols, (unsigned long long)kc);
+        if (kc == -2 && kk > 0) {
+            w.info[1] = kk;
+            w.info[3] ^= 1;
+            w.info[0] = -3;
+            atomicAdd(A.pending, 1);
         } else {
-            atomicAdd(&A.st[b].aca_dense, 1);
+            w.info[0] = -4;
+            if (kc > 0 && kk > 0) {
+                fp->kk = kk;
+                atomicAdd((unsigned long long*)&A.st[b].aca_cols, (unsigned long long)kc);
+            } else {
+                atomicAdd(&A.st[b].aca_dense, 1);
+            }
         }
     }
 }

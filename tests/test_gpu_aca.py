@@ -162,3 +162,36 @@ def test_compressed_apply_with_aca_faces(ctx, prec, eps, bound):
     yg = y.reshape(1, L, K, 3)[:, :, rows, :].reshape(1, L, -1)
     err = float((np.linalg.norm(yg - yo, axis=-1) / np.linalg.norm(yo, axis=-1)).max())
     assert err < bound, (err, st)
+
+
+@pytest.mark.parametrize("prec,eps,bound", [(B.PREC_F64, 1e-7, 1e-6), (B.PREC_MIXED, 1e-6, 1e-4)])
+def test_resumed_aca_faces(ctx, prec, eps, bound):
+    """Per-slice ACA runs that reach the 96-column capacity are recompressed and resumed
+    (aca_rounds; the early abort is off then): fewer faces stay dense than without resume, and
+    the product still meets the bound against the oracle on sampled rows."""
+    X, T = W.icosphere(3)  # 1280 triangles, leaves of 40 elements
+    K, L = len(T), 16
+    s = W.bdf2_contour(L, 0.1)
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(1.0, 1.0, 0.5)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=True)
+    base = c.compress(B.OP_V, eps3d=eps, leaf=64, prec=prec, far_dense_max=0)
+    st0 = base.stats()
+    base.destroy()
+    op = c.compress(B.OP_V, eps3d=eps, leaf=64, prec=prec, far_dense_max=0, aca_rounds=6)
+    st = op.stats()
+    assert st0["n_aca_dense"] > 0, st0
+    assert st["n_aca_dense"] < st0["n_aca_dense"], (st["n_aca_dense"], st0["n_aca_dense"])
+    if prec == B.PREC_F64:  # at 1e-7 some runs reach the column capacity and resume
+        assert st["aca_launches"] > st0["aca_launches"]
+    assert st["bytes"] < st0["bytes"]
+    x = W.random_rhs(8, (1, L, 3 * K))
+    y = op.apply(x)
+    rows = np.sort(np.random.default_rng(5).choice(K, size=24, replace=False))
+    yo = oracle.Problem(X, T, s, near_on=True).matvec_rows(B.OP_V, rows, x)
+    yg = y.reshape(1, L, K, 3)[:, :, rows, :].reshape(1, L, -1)
+    err = float((np.linalg.norm(yg - yo, axis=-1) / np.linalg.norm(yo, axis=-1)).max())
+    assert err < bound, (err, st)
+    op.destroy()
