@@ -128,7 +128,8 @@ typedef struct {
     int32_t aca_rank_max;         /* largest rank kk of a far face stored as factors */
     double aca_rank_mean;         /* mean kk over the far faces stored as factors */
     int64_t bytes;                /* device bytes of faces, factors and fibres */
-    double compression_rate;      /* bytes / (L * (3K)^2 * 16) */
+    double compression_rate;      /* bytes / (L * (3K)^2 * 16), with several components the
+                                     sum of L (3K_c)^2 16 over the components */
     int64_t entries_generated;    /* ENTRY(i, j, l) 3x3 blocks evaluated during compression */
     int64_t n_far_faces;          /* far faces stored as factors */
     double seconds;               /* wall time of the compression call */
@@ -200,6 +201,18 @@ int bem_set_stream(bem_ctx *ctx, void *hip_stream);
  * nodes: [n_nodes][3] double (host), tris: [K][3] int32 (host).
  * Errors: BEM_ERR_MESH for K < 1, an index outside [0, n_nodes) or a zero-area triangle. */
 int bem_set_mesh(bem_ctx *ctx, const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K);
+
+/* Several meshes in one context (the meshes of a batch sharing material and contour points):
+ * comp[e] in [0, ncomp) names the mesh of element e (every component non-empty); the
+ * elements of different components do not interact.  bem_compress then partitions each
+ * component apart (no block couples two components) and compresses all of them in one set of
+ * launches, and the products of the operator are those of every mesh at once (block
+ * diagonal).  bem_entries ignores components; bem_assemble_dense, bem_apply_mf and
+ * bem_adjoint_v return BEM_ERR_STATE on a context of several components.  comp = NULL or
+ * ncomp <= 1 restores one component; bem_set_mesh resets to one component.  Host array,
+ * copied.  Errors: BEM_ERR_STATE before bem_set_mesh, BEM_ERR_ARG for an index out of range or
+ * an empty component. */
+int bem_set_components(bem_ctx *ctx, const int32_t *comp, int32_t ncomp);
 
 /* Material (Sec. 2.1, eq. (lame)): density rho, compression and shear wave speeds
  * cp = c1 > cs = c2 > 0.  Returns BEM_WARN_BULK if cp^2 < 4/3 cs^2. */

@@ -101,6 +101,7 @@ _SIGS = {
     "bem_last_error": (ctypes.c_char_p, [_P]),
     "bem_set_stream": (ctypes.c_int, [_P, _P]),
     "bem_set_mesh": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int64]),
+    "bem_set_components": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "bem_set_material": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "bem_set_frequencies": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "bem_freq_pairs": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -225,6 +226,22 @@ class Context:
         self.K = int(tris.shape[0])
         self.n_nodes = int(nodes.shape[0])
         return self._check(lib().bem_set_mesh(self.h, nodes.ctypes.data, nodes.shape[0], tris.ctypes.data, tris.shape[0]))
+
+    def set_meshes(self, meshes):
+        """Several meshes [(nodes, tris), ...] in one context as components (a batch sharing
+        material and contour): nodes and triangles concatenated in order, element offsets
+        returned; the compressed operator is block diagonal over the meshes."""
+        nodes, tris, comp, offs, noff = [], [], [], [0], 0
+        for c, (X, T) in enumerate(meshes):
+            nodes.append(np.asarray(X, dtype=np.float64))
+            tris.append(np.asarray(T, dtype=np.int32) + noff)
+            comp.append(np.full(len(T), c, dtype=np.int32))
+            noff += len(X)
+            offs.append(offs[-1] + len(T))
+        self.set_mesh(np.concatenate(nodes), np.concatenate(tris))
+        comp = np.ascontiguousarray(np.concatenate(comp))
+        self._check(lib().bem_set_components(self.h, comp.ctypes.data, len(meshes)))
+        return offs
 
     def set_material(self, rho, cp, cs):
         return self._check(lib().bem_set_material(self.h, float(rho), float(cp), float(cs)))

@@ -56,6 +56,13 @@ void need_device(const bem_ctx* ctx)
     BEM_HIP_TRY(hipSetDevice(ctx->device));
 }
 
+// the dense and matrix-free operators couple every pair of elements: not for a context of
+// several components (their operators are block diagonal; bem_compress forms them)
+void need_one_component(const bem_ctx* ctx)
+{
+    if (ctx->hgeo.ncomp > 1) throw api_error(BEM_ERR_STATE, "several mesh components: use bem_compress");
+}
+
 void need_state(const bem_ctx* ctx, bool freq = true)
 {
     if (!ctx->mesh_set) throw api_error(BEM_ERR_STATE, "mesh not set");
@@ -389,7 +396,7 @@ int bem_set_mesh(bem_ctx* ctx, const double* nodes, int64_t n_nodes, const int32
         }
         ctx->nodes.assign(nodes, nodes + 3 * n_nodes);
         ctx->tris.assign(tris, tris + 3 * K);
-        ctx->hgeo = std::move(g);
+        ctx->hgeo = std::move(g);  // one component until bem_set_components
         if (ctx->device >= 0) {
             need_device(ctx);
             ctx->dgeo.upload(ctx->hgeo, nullptr, ctx->stream);
@@ -494,6 +501,30 @@ int bem_set_entry_table(bem_ctx* ctx, const void* table_dev)
     return BEM_OK;
 }
 
+int bem_set_components(bem_ctx* ctx, const int32_t* comp, int32_t ncomp)
+{
+    if (!ctx) return BEM_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        if (!ctx->mesh_set) throw api_error(BEM_ERR_STATE, "mesh not set");
+        HostGeo& g = ctx->hgeo;
+        if (!comp || ncomp <= 1) {
+            g.comp.clear();
+            g.ncomp = 1;
+            return BEM_OK;
+        }
+        std::vector<int> c(comp, comp + g.K), seen(ncomp, 0);
+        for (int e = 0; e < g.K; ++e) {
+            if (c[e] < 0 || c[e] >= ncomp) throw api_error(BEM_ERR_ARG, "component index out of range");
+            seen[c[e]] = 1;
+        }
+        for (int q = 0; q < ncomp; ++q)
+            if (!seen[q]) throw api_error(BEM_ERR_ARG, "component " + std::to_string(q) + " has no element");
+        g.comp = std::move(c);
+        g.ncomp = ncomp;
+        return BEM_OK;
+    });
+}
+
 int bem_entries(bem_ctx* ctx, int32_t op, int32_t prec, int64_t n, const int32_t* i, const int32_t* j,
                 const int32_t* l, void* out, int32_t flags)
 {
@@ -537,6 +568,7 @@ int bem_assemble_dense(bem_ctx* ctx, int32_t op, int32_t prec, bem_op** out)
             throw api_error(BEM_ERR_ARG, "bad op or prec");
         need_state(ctx);
         need_device(ctx);
+        need_one_component(ctx);
         if (op == BEM_OP_TABLE && !ctx->table) throw api_error(BEM_ERR_STATE, "no entry table set");
         int K = ctx->hgeo.K, L = ctx->freq.L;
         if (K > 65535) throw api_error(BEM_ERR_ARG, "dense assembly is limited to K <= 65535");
@@ -939,6 +971,7 @@ int bem_apply_mf(bem_ctx* ctx, int32_t op, int32_t transpose, int32_t nrhs, cons
         if (nrhs < 1 || !x || !y) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
         if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_apply_mf");
         need_device(ctx);
+        need_one_component(ctx);
         const bool dev = (flags & BEM_DEVICE_PTR) != 0;
         const size_t bytes = (size_t)nrhs * ctx->freq.L * 3 * (size_t)ctx->hgeo.K * sizeof(zd);
         hipStream_t st = ctx->stream;
@@ -961,6 +994,7 @@ int bem_adjoint_v(bem_ctx* ctx, int32_t nrhs, const void* w, const void* x, int3
         if (nrhs < 1 || !w || !x) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
         if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_adjoint_v");
         need_device(ctx);
+        need_one_component(ctx);
         const bool dev = (flags & BEM_DEVICE_PTR) != 0;
         const int K = ctx->hgeo.K;
         const size_t bytes = (size_t)nrhs * ctx->freq.L * 3 * (size_t)K * sizeof(zd);

@@ -1017,7 +1017,18 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     R.aca_rank_mean = nfarfaces ? acasum / nfarfaces : 0.0;
     R.aca_cols_mean = nfarfaces ? colsum / nfarfaces : 0.0;
     R.bytes = bytes;
-    R.compression_rate = (double)bytes / ((double)L * 9.0 * (double)K * (double)K * 16.0);
+    {
+        // dense size: the M x M x L array of each component (one for a single mesh)
+        double dense = 0.0;
+        if (ctx->hgeo.ncomp > 1) {
+            std::vector<double> kc(ctx->hgeo.ncomp, 0.0);
+            for (int c : ctx->hgeo.comp) kc[c] += 1.0;
+            for (double k : kc) dense += (double)L * 9.0 * k * k * 16.0;
+        } else {
+            dense = (double)L * 9.0 * (double)K * (double)K * 16.0;
+        }
+        R.compression_rate = (double)bytes / dense;
+    }
     R.entries_generated = ent;
     R.entries_other = ent - R.entries_regular - R.entries_near - R.entries_self;
     R.n_far_faces = nfarfaces;

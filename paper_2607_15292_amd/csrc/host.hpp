@@ -116,6 +116,9 @@ struct DevBuf {
 struct HostGeo {
     int K = 0;
     std::vector<double> cx, cy, cz, nx, ny, nz, area, lmax2, vx, vy, vz, gx, gy, gz, gw;
+    std::vector<int> comp;  // component of each element (empty: one component); blocks never
+                            // couple two components
+    int ncomp = 1;
 };
 
 // Geometry tables uploaded to the device in one allocation.
@@ -130,6 +133,7 @@ struct Cluster {
     int begin, size;
     int child[2];
     double bmin[3], bmax[3];  // box of the element vertices
+    int comp;                 // the component of all its elements, -1 when it spans several
 };
 
 struct BlockDesc {

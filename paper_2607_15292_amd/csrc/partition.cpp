@@ -6,6 +6,9 @@
 // Readings: split at the median of the projections on the principal axis (ties broken by
 // element index), first child = lower half; the axis sign is normalised (largest
 // component positive) so that the tree is deterministic.
+// Several meshes in one context (components, e.g. the meshes of a batch): the tree first
+// splits the list of components in halves down to one component, then bisects each
+// component as above; no block couples two components.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -84,10 +87,28 @@ struct Builder {
         }
     }
 
-    int split(int begin, int size)
+    // element ranges of the components in P.perm (components sorted, contiguous)
+    std::vector<int> cbeg;
+
+    // node over the components c0 .. c1 - 1 (more than one)
+    int split_comps(int c0, int c1)
+    {
+        if (c1 - c0 == 1) return split(cbeg[c0], cbeg[c0 + 1] - cbeg[c0], c0);
+        int id = (int)P.nodes.size();
+        P.nodes.push_back(Cluster{cbeg[c0], cbeg[c1] - cbeg[c0], {-1, -1}, {0, 0, 0}, {0, 0, 0}, -1});
+        box(id);
+        const int h = (c0 + c1) / 2;
+        const int a = split_comps(c0, h);
+        const int b = split_comps(h, c1);
+        P.nodes[id].child[0] = a;
+        P.nodes[id].child[1] = b;
+        return id;
+    }
+
+    int split(int begin, int size, int comp)
     {
         int id = (int)P.nodes.size();
-        P.nodes.push_back(Cluster{begin, size, {-1, -1}, {0, 0, 0}, {0, 0, 0}});
+        P.nodes.push_back(Cluster{begin, size, {-1, -1}, {0, 0, 0}, {0, 0, 0}, comp});
         box(id);
         if (size <= leaf) return id;
         double mu[3] = {0, 0, 0};
@@ -115,8 +136,8 @@ struct Builder {
         std::sort(key.begin(), key.end());
         for (int t = 0; t < size; ++t) P.perm[begin + t] = key[t].second;
         int h = size / 2;
-        int c0 = split(begin, h);
-        int c1 = split(begin + h, size - h);
+        int c0 = split(begin, h, comp);
+        int c1 = split(begin + h, size - h, comp);
         P.nodes[id].child[0] = c0;
         P.nodes[id].child[1] = c1;
         return id;
@@ -142,6 +163,17 @@ struct Builder {
     {
         const Cluster& A = P.nodes[a];
         const Cluster& B = P.nodes[b];
+        if (A.comp >= 0 && B.comp >= 0 && A.comp != B.comp) return;  // two components: no block
+        if (A.comp < 0 || B.comp < 0) {  // a node over several components: split it
+            if (A.comp < 0) {
+                blocks(A.child[0], b, eta);
+                blocks(A.child[1], b, eta);
+            } else {
+                blocks(a, B.child[0], eta);
+                blocks(a, B.child[1], eta);
+            }
+            return;
+        }
         if (std::min(diam(A), diam(B)) <= eta * dist(A, B)) {
             P.blocks.push_back(BlockDesc{A.begin, A.size, B.begin, B.size, 1});
             return;
@@ -175,8 +207,16 @@ void build_partition(const HostGeo& g, double eta, int leaf, Partition& out)
     std::iota(out.perm.begin(), out.perm.end(), 0);
     out.nodes.clear();
     out.blocks.clear();
-    Builder B{g, leaf, out};
-    B.split(0, g.K);
+    Builder B{g, leaf, out, {}};
+    if (g.ncomp <= 1 || g.comp.empty()) {
+        B.split(0, g.K, 0);
+    } else {
+        std::stable_sort(out.perm.begin(), out.perm.end(), [&](int x, int y) { return g.comp[x] < g.comp[y]; });
+        B.cbeg.assign(g.ncomp + 1, 0);
+        for (int e = 0; e < g.K; ++e) ++B.cbeg[g.comp[e] + 1];
+        for (int c = 0; c < g.ncomp; ++c) B.cbeg[c + 1] += B.cbeg[c];
+        B.split_comps(0, g.ncomp);
+    }
     B.blocks(0, 0, eta);
 }
 
