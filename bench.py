@@ -89,6 +89,7 @@ def batched_leg(args, dev, torch):
     Lb, nrhs = args.batch_freqs, args.batch_nrhs
     s = W.bdf2_contour(Lb, 0.1)
     ctxs, ops, xs, names = [], [], [], []
+    sep_s = 0.0
     for i, (name, X, T) in enumerate(W.batch_meshes()):
         c = B.Context(0)
         c.set_mesh(X, T)
@@ -96,15 +97,19 @@ def batched_leg(args, dev, torch):
         c.set_frequencies(s)
         c.set_quadrature(near_on=True)
         ctxs.append(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         ops.append(c.compress(B.OP_V, eps3d=args.batch_eps, leaf=64, eta=1.5, prec=B.PREC_MIXED,
                               mixed_eps_floor=args.batch_eps_floor))
+        torch.cuda.synchronize()
+        sep_s += time.perf_counter() - t0
         xs.append(torch.tensor(W.random_rhs(2 + i, (nrhs, Lb, 3 * len(T))), device=dev))
         names.append(name)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b = B.Batch(ops, nrhs=nrhs, graph=True, tune=True)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    tune_s = time.perf_counter() - t0
     ys = [torch.empty_like(x) for x in xs]
     b.apply(xs, ys)  # records the graph
     torch.cuda.synchronize()
@@ -118,7 +123,7 @@ def batched_leg(args, dev, torch):
     ms = e0.elapsed_time(e1) / reps
     info = b.info()
     log("batched: %d operators, L %d, nrhs %d: %.1f ms per product, tuning %.1f s, %s"
-        % (len(ops), Lb, nrhs, ms, t1 - t0, info))
+        % (len(ops), Lb, nrhs, ms, tune_s, info))
     # sampled rows of every output, checked against the oracle in the CPU-baseline leg
     rng = np.random.default_rng(12)
     samples = []
@@ -127,7 +132,7 @@ def batched_leg(args, dev, torch):
         rows = np.sort(rng.choice(K, size=16, replace=False))
         yg = y.cpu().numpy().reshape(nrhs, Lb, K, 3)[:, :, rows, :].reshape(nrhs, Lb, -1)
         samples.append((name, X, T, rows, x.cpu().numpy(), yg))
-    achieved = info["flop"] / (ms * 1e-3)
+    b.destroy()
     # roof of the arithmetic mix: complex64 work at the FP32 MFMA rate, complex128 work and the
     # FP64 fibre contraction at the FP64 rate (the info flops split the same way)
     f32 = f64 = 0.0
@@ -135,12 +140,52 @@ def batched_leg(args, dev, torch):
         v = o.stats()
         f32 += 8.0 * v["apply_macs_c64"] * Lb * nrhs
         f64 += 8.0 * ((v["apply_macs_c128"] + v["apply_macs_fibre"]) * Lb * nrhs + v["apply_macs_sel"] * nrhs)
+    sep_bytes = sum(o.stats()["bytes"] for o in ops)
+    sep_kernel_ms = sum(o.stats()["kernel_ms"] for o in ops)
+    sep_groups = sum(o.stats()["block_groups"] for o in ops)
+    for o in ops:
+        o.destroy()
+    for c in ctxs:
+        c.close()
+    # the same batch as the components of one context: one compression, one product
+    cu = B.Context(0)
+    offs = cu.set_meshes([(X, T) for _, X, T in W.batch_meshes()])
+    cu.set_material(1.0, 1.0, 0.5)
+    cu.set_frequencies(s)
+    cu.set_quadrature(near_on=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    opu = cu.compress(B.OP_V, eps3d=args.batch_eps, leaf=64, eta=1.5, prec=B.PREC_MIXED,
+                      mixed_eps_floor=args.batch_eps_floor)
+    torch.cuda.synchronize()
+    union_s = time.perf_counter() - t0
+    xu = torch.cat(xs, dim=2)
+    yu = torch.empty_like(xu)
+    opu.apply(xu, yu)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        opu.apply(xu, yu)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_union = e0.elapsed_time(e1) / reps
+    union_diff = max(float(((yu[:, :, 3 * offs[q]:3 * offs[q + 1]] - y).abs().max() / y.abs().max()).item())
+                     for q, y in enumerate(ys))
+    stu = opu.stats()
+    union_bytes = stu["bytes"]
+    del xu, yu
+    opu.destroy()
+    cu.close()
+    log("batched as components of one context: compression %.2f s, device %.0f ms in %d groups (meshes apart "
+        "%.2f s, device %.0f ms in %d groups), product %.1f ms, max rel diff to the batch %.2e"
+        % (union_s, stu["kernel_ms"], stu["block_groups"], sep_s, sep_kernel_ms, sep_groups, ms_union, union_diff))
+    achieved = info["flop"] / (ms * 1e-3)
     peak = (f32 + f64) / (f32 / PEAK_MFMA32 + f64 / PEAK_MFMA64)
     out = {"workload": "single layers of %s, mixed precision eps %.0e (far-field floor %.0e), %d BDF2 gCQ points, "
                        "%d right-hand sides each" % (", ".join(names), args.batch_eps, args.batch_eps_floor, Lb, nrhs),
            "ms_per_product": ms, "products_per_s": len(ops) * nrhs * 1e3 / ms,
            "single_freq_matvecs_per_s": len(ops) * nrhs * Lb * 1e3 / ms,
-           "compressed_gb": sum(o.stats()["bytes"] for o in ops) / 1e9,
+           "compressed_gb": sep_bytes / 1e9,
            "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                         "frac": achieved / peak, "traffic": None,
                         "kernel": "batched product (k_far_mfma + k_rows_mfma<float/double> + k_reduce_mrows + "
@@ -148,13 +193,12 @@ def batched_leg(args, dev, torch):
                         "flop_per_product": info["flop"], "flop_complex64_share": f32 / max(f32 + f64, 1.0)},
            "schedule": {k: info[k] for k in ("n_groups", "n_segments", "seg_target", "far_sorted", "tune_ms",
                                              "tune_segments", "graph_builds", "graph_launches", "workspace_bytes")},
-           "tune_seconds": t1 - t0, "rel_err_sampled_rows": None,
+           "tune_seconds": tune_s, "rel_err_sampled_rows": None,
+           "compress_seconds_meshes_apart": sep_s, "compress_device_ms_meshes_apart": sep_kernel_ms,
+           "components": {"compress_seconds": union_s, "compress_device_ms": stu["kernel_ms"],
+                          "block_groups": stu["block_groups"], "ms_per_product": ms_union,
+                          "compressed_gb": union_bytes / 1e9, "max_rel_diff_to_batch": union_diff},
            "_check": {"s": s, "samples": samples}}
-    b.destroy()
-    for o in ops:
-        o.destroy()
-    for c in ctxs:
-        c.close()
     return out
 
 
