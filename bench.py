@@ -229,40 +229,7 @@ def adjoint_leg(args, dev, torch):
     log("adjoint: K %d L %d: gradient %.2f s, matrix-free product %.2f s" % (K, L, t1 - t0, t2 - t1))
     del w, x, y
     c.close()
-    # gradient of a GMRES solution on the metric's sphere: V t = g at all contour points
-    # (fine V FP64 at the strict eps, inner V mixed), loss sum_l |t_l|^2 / 2: one transposed
-    # solve V^T nu = conj(t) and the adjoint kernel with w = nu, x = t
-    X2, T2, s2 = workload(args.level, args.freqs)
-    K2 = len(T2)
-    c2 = B.Context(0)
-    c2.set_mesh(X2, T2)
-    c2.set_material(1.0, 1.0, 0.5)
-    c2.set_frequencies(s2)
-    c2.set_quadrature(near_on=True)
-    Vf = c2.compress(B.OP_V, eps3d=args.eps_fp64_strict, leaf=64, eta=1.5, prec=B.PREC_F64)
-    Vi = c2.compress(B.OP_V, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED)
-    g = torch.tensor(W.random_rhs(72, (1, L, 3 * K2)), device=dev)
-    torch.cuda.synchronize()
-    ts0 = time.perf_counter()
-    tsol, st1 = Vf.solve(g, inner=Vi, tol=1e-8, inner_tol=1e-3)
-    torch.cuda.synchronize()
-    ts1 = time.perf_counter()
-    nu, st2 = Vf.solve(tsol.conj().resolve_conj().contiguous(), inner=Vi, tol=1e-8, inner_tol=1e-3, transpose=True)
-    torch.cuda.synchronize()
-    ts2 = time.perf_counter()
-    _, gn2, gm2 = c2.adjoint_v(nu, tsol)
-    ts3 = time.perf_counter()
-    log("solution gradient: K %d: solve %.2f s, transposed solve %.2f s, adjoint %.2f s"
-        % (K2, ts1 - ts0, ts2 - ts1, ts3 - ts2))
-    sol = {"workload": "V t = g on an icosphere of %d triangles at %d contour points (near rule on), fine V FP64 "
-                       "eps %.0e, inner V mixed eps %.0e; loss sum |t|^2 / 2; gradient w.r.t. %d node coordinates "
-                       "and rho, c_p, c_s" % (K2, L, args.eps_fp64_strict, args.eps, 3 * len(X2)),
-           "solve_seconds": ts1 - ts0, "transposed_solve_seconds": ts2 - ts1, "adjoint_seconds": ts3 - ts2,
-           "gmres_iterations": [st1["iterations"], st2["iterations"]],
-           "grad_mat": [-float(v) for v in gm2]}
-    for o in (Vf, Vi):
-        o.destroy()
-    c2.close()
+    sol = solution_gradient(args, dev, torch, X, T, s)
     out = {"workload": "single layer on an icosphere of %d triangles, %d BDF2 gCQ points, near rule on, one "
                        "right-hand side; gradient of Re sum_l w_l^T V(s_l) x_l w.r.t. %d node coordinates and "
                        "rho, c_p, c_s" % (K, L, 3 * len(X)),
@@ -270,6 +237,159 @@ def adjoint_leg(args, dev, torch):
            "matrix_free_product_seconds": t2 - t1, "matrix_free_entries_per_s": K * K * L / (t2 - t1),
            "grad_norm_nodes": float(np.linalg.norm(gn)), "grad_mat": [float(v) for v in gm],
            "solution_gradient": sol}
+    return out
+
+
+def _pair_class(X, T, I, J, r1sq=2.25, r2sq=9.0):
+    """Class of the near rule for the pairs (I, J) as the library decides it: 2 if
+    |c_i - c_j|^2 < r1^2 lmax_j^2, 1 if < r2^2 lmax_j^2, else 0 (same arithmetic order)."""
+    V = X[T]
+    c = (V[:, 0] + V[:, 1] + V[:, 2]) / 3.0
+    l2 = np.zeros(len(T))
+    for a in range(3):
+        e = V[:, (a + 1) % 3] - V[:, a]
+        l2 = np.maximum(l2, e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1] + e[:, 2] * e[:, 2])
+    d = c[I] - c[J]
+    d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+    return np.where(d2 < r1sq * l2[J], 2, np.where(d2 < r2sq * l2[J], 1, 0)), np.sqrt(l2.min())
+
+
+def _class_boundary_pairs(X, T, tau, chunk=512):
+    """Pairs i != j with |d^2 / lmax_j^2 - r^2| < tau for r^2 = 2.25 or 9 (host, in row chunks)."""
+    V = X[T]
+    c = (V[:, 0] + V[:, 1] + V[:, 2]) / 3.0
+    l2 = np.zeros(len(T))
+    for a in range(3):
+        e = V[:, (a + 1) % 3] - V[:, a]
+        l2 = np.maximum(l2, (e * e).sum(-1))
+    I, J = [], []
+    for i0 in range(0, len(T), chunk):
+        q = ((c[i0:i0 + chunk, None, :] - c[None, :, :]) ** 2).sum(-1) / l2[None, :]
+        m = (np.abs(q - 2.25) < tau) | (np.abs(q - 9.0) < tau)
+        ii, jj = np.nonzero(m)
+        keep = ii + i0 != jj
+        I.append(ii[keep] + i0)
+        J.append(jj[keep])
+    return np.concatenate(I), np.concatenate(J)
+
+
+def _fd_direction(rng, X, T, h, I, J, tau):
+    """Random direction over the node coordinates (standard normal) for a central difference
+    with step h: the nodes of pairs whose near-rule class would differ between X + h D and
+    X - h D are held fixed (D = 0 there; a class switch is a jump of the discrete operator,
+    not its derivative).  Pairs outside the candidate list (I, J) cannot switch: their
+    normalised distance moves by less than tau."""
+    D = rng.standard_normal(X.shape)
+    base, lmin = _pair_class(X, T, I, J)
+    dc = h * np.abs(D).max() * np.sqrt(3.0)
+    # |d q| <= 48 dc / l + 40 (dc / l)^2 for a node displacement dc (q <= 9 + tau)
+    assert 48.0 * dc / lmin + 40.0 * (dc / lmin) ** 2 < tau, "step too large for the candidate band"
+    held = 0
+    for _ in range(100):
+        cp, _ = _pair_class(X + h * D, T, I, J)
+        cm, _ = _pair_class(X - h * D, T, I, J)
+        sw = (cp != base) | (cm != base)
+        if not sw.any():
+            return D, held
+        nodes = np.unique(T[np.concatenate([I[sw], J[sw]])])
+        held += int((np.abs(D[nodes]).sum(-1) > 0).sum())
+        D[nodes] = 0.0
+    raise RuntimeError("no class-switch-free direction")
+
+
+def solution_gradient(args, dev, torch, X, T, s):
+    """Gradient of a GMRES solution on the sphere of the adjoint leg: V(s_l) t_l = g_l at all
+    contour points, loss sum_l |t_l - t*_l|^2, gradient w.r.t. every node coordinate and
+    rho, c_p, c_s through the torch Function (forward solve, transposed solve, adjoint kernel,
+    entries recomputed).  The fine operator is matrix-free (FP64 entries recomputed at every
+    product: the residuals are exact to quadrature and nothing is stored); the GMRES
+    iterations of the refinement run on a compressed inner operator.  With --adjoint-fd N the
+    gradient is checked against central differences of the loss on N random directions (node
+    coordinates and speeds together), each evaluation a solve with the fine operator of the
+    perturbed mesh and the inner operator of the unperturbed one."""
+    from paper_2607_15292_amd import binding as B
+    from paper_2607_15292_amd import workloads as W
+    from paper_2607_15292_amd.autograd import single_layer_solve
+    K, L = len(T), len(s)
+    tol = min(args.sg_tol, 1e-11) if args.adjoint_fd > 0 else args.sg_tol
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(1.0, 1.0, 0.5)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=True)
+    inner_opts = dict(eps3d=args.sg_inner_eps, eps_aca=args.sg_inner_eps / 10, leaf=64, eta=1.5, prec=B.PREC_MIXED,
+                      mixed_eps_floor=args.sg_inner_eps / 10, far_dense_max=0, aca_rounds=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Vi = c.compress(B.OP_V, **inner_opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sti = Vi.stats()
+    log("solution gradient: K %d: inner V compressed in %.1f s (%.1f GB, rate %.4f)"
+        % (K, t1 - t0, sti["bytes"] / 1e9, sti["compression_rate"]))
+    g = torch.tensor(W.random_rhs(72, (1, L, 3 * K)), device=dev)
+    tstar = torch.tensor(W.random_rhs(73, (1, L, 3 * K)), device=dev)
+    mat0 = [1.0, 1.0, 0.5]
+    nodes = torch.tensor(X, dtype=torch.float64, requires_grad=True)
+    mat = torch.tensor(mat0, dtype=torch.float64, requires_grad=True)
+    t2 = time.perf_counter()
+    tsol = single_layer_solve(c, nodes, mat, g, T, tol=tol, matrix_free=True, inner=Vi)
+    loss = ((tsol - tstar).abs() ** 2).sum()
+    lv = float(loss.item())
+    t3 = time.perf_counter()
+    node = tsol.grad_fn
+    loss.backward()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    st1, st2 = node.stats
+    gn, gm = nodes.grad.numpy().copy(), mat.grad.numpy().copy()
+    log("solution gradient: solve %.1f s (%d refinements, %d inner products), transposed solve + adjoint %.1f s "
+        "(%d refinements, %d inner products), loss %.6e"
+        % (t3 - t2, st1["refinements"], st1["iterations"], t4 - t3, st2["refinements"], st2["iterations"], lv))
+    out = {"workload": "V(s_l) t_l = g_l on an icosphere of %d triangles at %d BDF2 contour points (near rule on), "
+                       "loss sum_l |t_l - t*_l|^2 (g, t* complex Gaussian, seeds 72, 73); gradient w.r.t. %d node "
+                       "coordinates and rho, c_p, c_s; fine V matrix-free FP64, inner V mixed eps3d %.0e / "
+                       "eps_aca %.0e" % (K, L, 3 * len(X), args.sg_inner_eps, args.sg_inner_eps / 10),
+           "inner_compress_seconds": t1 - t0, "inner_gb": sti["bytes"] / 1e9,
+           "inner_compression_rate": sti["compression_rate"], "solve_seconds": t3 - t2,
+           "transposed_solve_and_adjoint_seconds": t4 - t3, "tol": tol,
+           "refinements": [st1["refinements"], st2["refinements"]],
+           "inner_products": [st1["iterations"], st2["iterations"]],
+           "rel_residual": [st1["rel_residual"], st2["rel_residual"]],
+           "loss": lv, "grad_norm_nodes": float(np.linalg.norm(gn)), "grad_mat": [float(v) for v in gm]}
+    if args.adjoint_fd > 0:
+        h = args.adjoint_fd_step
+        tau = 0.05
+        I, J = _class_boundary_pairs(X, T, tau)
+        F = c.matrix_free(B.OP_V)
+
+        def f(Xp, m):
+            c.set_mesh(Xp, T)
+            c.set_material(*m)
+            tp, stp = F.solve(g, inner=Vi, tol=tol)
+            return float(((tp - tstar).abs() ** 2).sum().item())
+
+        rng = np.random.default_rng(74)
+        checks = []
+        for k in range(args.adjoint_fd_skip + args.adjoint_fd):
+            D, held = _fd_direction(rng, X, T, h, I, J, tau)
+            dm = np.array([0.0] + list(rng.standard_normal(2)))  # (rho, c_p, c_s): the speeds
+            if k < args.adjoint_fd_skip:
+                continue
+            fp = f(X + h * D, [m + h * d for m, d in zip(mat0, dm)])
+            fm = f(X - h * D, [m - h * d for m, d in zip(mat0, dm)])
+            fd = (fp - fm) / (2 * h)
+            an = float((gn * D).sum() + (gm * dm).sum())
+            checks.append({"fd": fd, "adjoint": an, "rel_diff": abs(an - fd) / abs(fd), "nodes_held": held})
+            log("solution gradient FD direction %d: adjoint %.9e, central difference %.9e, rel diff %.2e "
+                "(%d nodes held)" % (k, an, fd, abs(an - fd) / abs(fd), held))
+        c.set_mesh(X, T)
+        c.set_material(*mat0)
+        F.destroy()
+        out["fd_check"] = {"directions": checks, "step": h, "max_rel_diff": max(x["rel_diff"] for x in checks),
+                           "candidate_pairs": int(len(I))}
+    Vi.destroy()
+    c.close()
     return out
 
 
@@ -352,6 +472,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the GPU three times (the reference kernel of the HBM traffic counters)")
     ap.add_argument("--adjoint-level", type=int, default=5, help="icosphere level of the adjoint leg (5: 20480 triangles)")
+    ap.add_argument("--adjoint-fd", type=int, default=0,
+                    help="check the solution gradient against central differences on this many random directions "
+                         "(each costs two solves)")
+    ap.add_argument("--adjoint-fd-step", type=float, default=1e-6)
+    ap.add_argument("--sg-inner-eps", type=float, default=1e-3,
+                    help="3D-ACA tolerance of the inner operator of the solution gradient (eps_aca a tenth of it)")
+    ap.add_argument("--sg-tol", type=float, default=1e-8,
+                    help="relative residual of the solution-gradient solves (at most 1e-11 with --adjoint-fd)")
+    ap.add_argument("--adjoint-fd-skip", type=int, default=0,
+                    help="draw and skip this many directions first (to split a long check over several runs)")
     ap.add_argument("--batch-freqs", type=int, default=128)
     ap.add_argument("--batch-eps", type=float, default=1e-7,
                     help="3D-ACA tolerance of the batched leg (1e-6 leaves 2.5e-4 at the largest |s_l| of L = 128)")

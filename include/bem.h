@@ -353,8 +353,9 @@ typedef struct bem_solve_stats {
  * fine operator's accuracy at mostly inner-operator cost.
  *   With BEM_TRANSPOSE in flags the systems are A(s_l)^T x = b (the adjoint solves of a
  *   gradient).
- *   A, A_inner: operators of the same context, K and L (dense or compressed; A_inner may
- *   be NULL).  b, x: [nrhs][L][3K] complex128, mesh order, host or device per flags; x is
+ *   A, A_inner: operators of one device with the same K and L (dense, compressed or
+ *   matrix-free; A_inner may be NULL or belong to another context); the work runs on A's
+ *   context stream.  b, x: [nrhs][L][3K] complex128, mesh order, host or device per flags; x is
  *   overwritten (zero initial guess).  stats may be NULL.  Returns BEM_OK, BEM_WARN_NOCONV
  *   (x holds the last iterate), or an error (BEM_ERR_ARG for bad sizes or options). */
 int bem_solve(bem_op *A, bem_op *A_inner, int32_t nrhs, const void *b, void *x, int32_t flags,
@@ -370,6 +371,17 @@ int bem_solve(bem_op *A, bem_op *A_inner, int32_t nrhs, const void *b, void *x, 
  * transpose != 0, for op V, K or HK; x, y: [nrhs][L][3K] complex128 in mesh order, host or
  * device per flags (BEM_DEVICE_PTR).  Cost: K^2 L entries per pass of 4 right-hand sides. */
 int bem_apply_mf(bem_ctx *ctx, int32_t op, int32_t transpose, int32_t nrhs, const void *x, void *y, int32_t flags);
+
+/* Matrix-free operator (op V, K or HK of eq. (discrVK) in FP64, nothing stored): bem_apply
+ * (plain or BEM_TRANSPOSE, not BEM_SHARED_X) recomputes every entry as bem_apply_mf does, with
+ * the mesh, material, contour points and quadrature the context holds at the call.  It can be
+ * the fine operator of bem_solve, whose residuals are then exact to quadrature while a
+ * compressed inner operator (possibly of another context on the same device, e.g. the
+ * unperturbed mesh of a finite-difference study) carries the GMRES iterations.
+ * bem_apply_weighted, bem_cq_dirichlet, bem_op_dense_copy and batches refuse it (BEM_ERR_ARG);
+ * its statistics report 0 bytes.  Errors: BEM_ERR_ARG for another op, BEM_ERR_STATE without
+ * mesh, material and contour points or with several components. */
+int bem_matrix_free(bem_ctx *ctx, int32_t op, bem_op **out);
 
 /* Adjoint of the single layer (an extension; the paper has no adjoint): the value
  * S = sum_{r, l} w[r][l]^T V(s_l) x[r][l] (no conjugation) and the gradient of Re S with

@@ -62,39 +62,56 @@ def single_layer(bem_ctx, nodes, material, x, tris):
 
 
 class SingleLayerSolve(torch.autograd.Function):
-    """t[r, l] = V(s_l)^{-1} b[r, l] by GMRES (bem_solve) with V assembled dense or compressed
-    in FP64 at eps; backward: one transposed solve V^T nu = conj(g_t) per call, then
+    """t[r, l] = V(s_l)^{-1} b[r, l] by GMRES (bem_solve) with V assembled dense, compressed
+    in FP64 at eps, or matrix-free (entries recomputed at every product), optionally with a
+    compressed inner operator carrying the GMRES iterations of the iterative refinement;
+    backward: one transposed solve V^T nu = conj(g_t) per call with the same operators, then
     g_b = conj(nu) and the node and material gradients are minus those of
     Re sum nu^T V t (the adjoint kernel)."""
 
     @staticmethod
-    def forward(fctx, bem_ctx, tris, nodes, material, b, tol, eps):
+    def forward(fctx, bem_ctx, tris, nodes, material, b, tol, eps, matrix_free, inner):
         _load(bem_ctx, tris, nodes, material)
-        V = bem_ctx.assemble_dense(B.OP_V) if eps is None else bem_ctx.compress(B.OP_V, eps3d=eps, prec=B.PREC_F64)
-        t, _ = V.solve(b.contiguous(), tol=tol)
+        if matrix_free:
+            V = bem_ctx.matrix_free(B.OP_V)
+        elif eps is None:
+            V = bem_ctx.assemble_dense(B.OP_V)
+        else:
+            V = bem_ctx.compress(B.OP_V, eps3d=eps, prec=B.PREC_F64)
+        own_inner = isinstance(inner, dict)
+        Vi = bem_ctx.compress(B.OP_V, **inner) if own_inner else inner
+        t, st = V.solve(b.contiguous(), inner=Vi, tol=tol)
         fctx.bem, fctx.tris, fctx.V, fctx.tol = bem_ctx, tris, V, tol
+        fctx.Vi, fctx.own_inner = Vi, own_inner
+        fctx.stats = [st]
         fctx.save_for_backward(nodes, material, t)
         return t
 
     @staticmethod
     def backward(fctx, gt):
         nodes, material, t = fctx.saved_tensors
-        bem, V = fctx.bem, fctx.V
-        nu, _ = V.solve(gt.conj().resolve_conj().contiguous(), tol=fctx.tol, transpose=True)
-        V.destroy()
-        fctx.V = None
+        bem, V, Vi = fctx.bem, fctx.V, fctx.Vi
         _load(bem, fctx.tris, nodes, material)
+        nu, st = V.solve(gt.conj().resolve_conj().contiguous(), inner=Vi, tol=fctx.tol, transpose=True)
+        fctx.stats.append(st)
+        V.destroy()
+        if fctx.own_inner:
+            Vi.destroy()
+        fctx.V = fctx.Vi = None
         g_nodes = g_mat = None
         if fctx.needs_input_grad[2] or fctx.needs_input_grad[3]:
             _, gn, gm = bem.adjoint_v(nu, t.contiguous())
             g_nodes = -torch.as_tensor(gn, dtype=nodes.dtype, device=nodes.device)
             g_mat = -torch.as_tensor(gm, dtype=material.dtype, device=material.device)
         g_b = nu.conj() if fctx.needs_input_grad[4] else None
-        return None, None, g_nodes, g_mat, g_b, None, None
+        return None, None, g_nodes, g_mat, g_b, None, None, None, None
 
 
-def single_layer_solve(bem_ctx, nodes, material, b, tris, tol=1e-10, eps=None):
-    """t[r, l] = V(s_l)^{-1} b[r, l], differentiable in nodes, material and b; V dense
-    (eps None) or compressed in FP64 at eps."""
+def single_layer_solve(bem_ctx, nodes, material, b, tris, tol=1e-10, eps=None, matrix_free=False, inner=None):
+    """t[r, l] = V(s_l)^{-1} b[r, l], differentiable in nodes, material and b.  V is dense
+    (eps None), compressed in FP64 at eps, or matrix-free (matrix_free=True: FP64 entries
+    recomputed at every product, nothing stored); inner: an operator for the inner GMRES runs
+    of the iterative refinement (same device, K and L; kept by the caller), or a dict of
+    Context.compress keywords for one compressed here and released after the backward pass."""
     tris = np.ascontiguousarray(tris, dtype=np.int32)
-    return SingleLayerSolve.apply(bem_ctx, tris, nodes, material, b, tol, eps)
+    return SingleLayerSolve.apply(bem_ctx, tris, nodes, material, b, tol, eps, bool(matrix_free), inner)

@@ -125,6 +125,7 @@ _SIGS = {
                                         ctypes.c_int32, ctypes.POINTER(bem_solve_opts),
                                         ctypes.POINTER(bem_solve_stats)]),
     "bem_apply_mf": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32]),
+    "bem_matrix_free": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bem_adjoint_v": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]),
     "bem_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_void_p)]),
@@ -302,6 +303,13 @@ class Context:
         self._check(lib().bem_compress(self.h, int(op), ctypes.byref(o), ctypes.byref(h)))
         return Operator(self, h)
 
+    def matrix_free(self, op):
+        """Matrix-free FP64 operator (V, K or HK): every product recomputes the entries with
+        the context's current mesh, material, contour points and quadrature."""
+        h = ctypes.c_void_p()
+        self._check(lib().bem_matrix_free(self.h, int(op), ctypes.byref(h)))
+        return Operator(self, h)
+
     def aca_matrix(self, A, tol, max_cols=0, prec=PREC_F64):
         """Per-slice ACA + recompression of one [3m][3n] host matrix; returns
         (kc, kk, Ubar, Vbar) with Ubar/Vbar None unless kk > 0."""
@@ -445,7 +453,8 @@ class Operator:
     def solve(self, b, x=None, inner=None, tol=1e-8, inner_tol=1e-3, restart=30, max_iter=500, max_refine=10,
               transpose=False):
         """x[r, l] = A(s_l)^{-1} b[r, l] by GMRES with iterative refinement (bem_solve);
-        inner: a cheaper operator of the same context for the inner GMRES runs.
+        inner: a cheaper operator (same device, K and L; possibly of another context) for the
+        inner GMRES runs.
         Returns (x, stats dict)."""
         K, L = self.ctx.K, self.ctx.L
         nrhs = b.shape[0]

@@ -600,6 +600,30 @@ int bem_assemble_dense(bem_ctx* ctx, int32_t op, int32_t prec, bem_op** out)
     });
 }
 
+int bem_matrix_free(bem_ctx* ctx, int32_t op, bem_op** out)
+{
+    if (!ctx || !out) return BEM_ERR_ARG;
+    *out = nullptr;
+    return guarded(ctx, [&]() -> int {
+        if (op != BEM_OP_V && op != BEM_OP_K && op != BEM_OP_HK) throw api_error(BEM_ERR_ARG, "op must be V, K or HK");
+        need_state(ctx);
+        need_device(ctx);
+        need_one_component(ctx);
+        std::unique_ptr<bem_op> o(new bem_op());
+        o->ctx = ctx;
+        ctx->live_ops++;
+        o->op = op;
+        o->prec = BEM_PREC_F64;
+        o->kind = 2;
+        o->K = ctx->hgeo.K;
+        o->L = ctx->freq.L;
+        o->stats.n_blocks = 1;
+        o->stats.n_near = 1;
+        *out = o.release();
+        return BEM_OK;
+    });
+}
+
 int bem_op_dense_copy(const bem_op* op, void* dst, int32_t flags)
 {
     if (!op || !dst) return BEM_ERR_ARG;
@@ -696,6 +720,13 @@ int bem_apply(bem_op* op, int32_t nrhs, const void* x, void* y, int32_t flags)
         bool shared = (flags & BEM_SHARED_X) != 0;
         const bool trans = (flags & BEM_TRANSPOSE) != 0;
         if (trans && shared) throw api_error(BEM_ERR_ARG, "BEM_TRANSPOSE with BEM_SHARED_X");
+        if (op->kind == 2) {
+            if (shared) throw api_error(BEM_ERR_ARG, "BEM_SHARED_X with a matrix-free operator");
+            need_state(ctx);
+            need_one_component(ctx);
+            if (ctx->hgeo.K != op->K || ctx->freq.L != op->L)
+                throw api_error(BEM_ERR_STATE, "the context's mesh or contour changed size since bem_matrix_free");
+        }
         size_t M = 3 * (size_t)op->K;
         size_t xb = (size_t)nrhs * (shared ? 1 : op->L) * M * sizeof(zd);
         size_t yb = (size_t)nrhs * op->L * M * sizeof(zd);
@@ -704,7 +735,10 @@ int bem_apply(bem_op* op, int32_t nrhs, const void* x, void* y, int32_t flags)
         stage_in(sx, x, xb, dev, st);
         stage_out(sy, y, yb, dev);
         int64_t xls = shared ? 0 : (int64_t)M;
-        if (trans && op->kind == 0)
+        if (op->kind == 2) {
+            launch_mf_apply(ctx->devctx(ctx->dgeo.geo, nullptr), op->op, trans, nrhs, (const zd*)sx.dev, (zd*)sy.dev,
+                            st);
+        } else if (trans && op->kind == 0)
             launch_dense_apply_t(op->dense.as<zd>(), (int)M, op->L, nrhs, (const zd*)sx.dev, (zd*)sy.dev, st);
         else if (trans)
             apply_compressed_t(op, nrhs, (const zd*)sx.dev, (zd*)sy.dev, st);
@@ -723,7 +757,12 @@ namespace {
 void op_apply(bem_op* op, int nrhs, const zd* x, zd* y, hipStream_t st, bool trans = false)
 {
     const size_t M = 3 * (size_t)op->K;
-    if (trans && op->kind == 0)
+    if (op->kind == 2) {
+        const bem_ctx* c = op->ctx;
+        if (c->hgeo.K != op->K || c->freq.L != op->L || c->hgeo.ncomp > 1)
+            throw api_error(BEM_ERR_STATE, "the context of a matrix-free operator changed its mesh or contour size");
+        launch_mf_apply(c->devctx(c->dgeo.geo, nullptr), op->op, trans, nrhs, x, y, st);
+    } else if (trans && op->kind == 0)
         launch_dense_apply_t(op->dense.as<zd>(), (int)M, op->L, nrhs, x, y, st);
     else if (trans)
         apply_compressed_t(op, nrhs, x, y, st);
@@ -743,8 +782,12 @@ int bem_solve(bem_op* A, bem_op* A_inner, int32_t nrhs, const void* b, void* x, 
     return guarded(ctx, [&]() -> int {
         const auto t0 = std::chrono::steady_clock::now();
         if (nrhs < 1 || !b || !x) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
-        if (A_inner && (A_inner->ctx != ctx || A_inner->K != A->K || A_inner->L != A->L))
-            throw api_error(BEM_ERR_ARG, "inner operator of another context or size");
+        if (A_inner && (A_inner->ctx->device != ctx->device || A_inner->K != A->K || A_inner->L != A->L))
+            throw api_error(BEM_ERR_ARG, "inner operator of another device or size");
+        for (const bem_op* o : {A, A_inner})
+            if (o && o->kind == 2 &&
+                (o->ctx->hgeo.K != o->K || o->ctx->freq.L != o->L || o->ctx->hgeo.ncomp > 1))
+                throw api_error(BEM_ERR_STATE, "the context of a matrix-free operator changed its mesh or contour size");
         bem::SolveParams p;
         if (opts) {
             if (!(opts->tol > 0.0) || !(opts->inner_tol > 0.0 && opts->inner_tol < 1.0) || opts->restart < 1 ||
@@ -789,6 +832,7 @@ int bem_apply_weighted(bem_op* op, const void* W, void* y, int32_t flags)
     bem_ctx* ctx = op->ctx;
     return guarded(ctx, [&]() -> int {
         if (!W || !y) throw api_error(BEM_ERR_ARG, "null buffer");
+        if (op->kind == 2) throw api_error(BEM_ERR_ARG, "weighted sum of a matrix-free operator");
         need_device(ctx);
         bool dev = (flags & BEM_DEVICE_PTR) != 0;
         size_t M = 3 * (size_t)op->K;
@@ -876,6 +920,7 @@ int bem_cq_dirichlet(bem_op* V, bem_op* H, int32_t N, double dt, double R, const
         const int L = V->L, K = V->K;
         if (!g || !t || N < 1 || N > L) throw api_error(BEM_ERR_ARG, "need buffers and 1 <= N <= L");
         if (H && (H->ctx != ctx || H->K != K || H->L != L)) throw api_error(BEM_ERR_ARG, "H of another context or size");
+        if (V->kind == 2 || (H && H->kind == 2)) throw api_error(BEM_ERR_ARG, "time stepping with a matrix-free operator");
         if (!(dt > 0.0) || !(R > 0.0 && R < 1.0)) throw api_error(BEM_ERR_ARG, "need dt > 0 and 0 < R < 1");
         if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_cq_dirichlet");
         // the contour points must be the BDF2 ones: s_l = delta(z_l) / dt, z_l = R exp(2 pi i l / L)

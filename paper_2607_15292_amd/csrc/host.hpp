@@ -55,6 +55,7 @@ struct MemCache {
 
 // Owning device allocation (through the context's MemCache when `cache` is set).
 struct DevBuf {
+    static constexpr size_t RESERVE = (size_t)2 << 30;  // device memory never taken (bytes)
     void* p = nullptr;
     size_t bytes = 0;
     MemCache* cache = nullptr;
@@ -73,6 +74,19 @@ struct DevBuf {
                 p = q;
                 bytes = got;
                 return;
+            }
+        }
+        if (n >= MemCache::MIN_BYTES) {
+            // leave RESERVE bytes free for the runtime (the scratch memory it allocates when
+            // a kernel with a private segment starts, queues): evict cached buffers, largest
+            // first, else refuse
+            size_t fr = 0, tot = 0;
+            while (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < n + RESERVE) {
+                if (!cache || cache->bufs.empty()) throw bem_nomem(n);
+                auto it = std::prev(cache->bufs.end());
+                (void)hipFree(it->second);
+                cache->cached -= it->first;
+                cache->bufs.erase(it);
             }
         }
         hipError_t e = hipMalloc(&p, n);
@@ -184,7 +198,7 @@ struct bem_ctx {
 struct bem_op {
     bem_ctx* ctx = nullptr;
     int op = 0, prec = 0;
-    int kind = 0;  // 0 dense, 1 compressed
+    int kind = 0;  // 0 dense, 1 compressed, 2 matrix-free (entries recomputed at each product)
     int K = 0, L = 0;
     bem::DevBuf dense;                               // kind 0: [L][3K][3K]
     bem::CompressedOp* comp = nullptr;               // kind 1 (owned)

@@ -219,3 +219,76 @@ def test_autograd_single_layer_solve(torch):
         db = W.random_rhs(72, b0.shape)
         fd = (f(X, m0, b0 + h * db) - f(X, m0, b0 - h * db)) / (2 * h)
         assert abs(float((b.grad.conj().cpu().numpy() * db).real.sum()) - fd) <= rtol * abs(fd), (eps, fd)
+
+
+def test_matrix_free_operator(torch):
+    """bem_matrix_free: products equal the dense operator's (plain and transposed); as the fine
+    operator of bem_solve with a compressed inner operator, of the same or of another context
+    (an unperturbed mesh), the solutions are those of the dense solve; refused uses."""
+    X, T = W.icosphere(2)
+    K, L = len(T), 8
+    s = W.bdf2_contour(L, 0.1)
+    c = _ctx(X, T, s, near_on=True)
+    D = c.assemble_dense(B.OP_V)
+    F = c.matrix_free(B.OP_V)
+    x = torch.tensor(W.random_rhs(80, (2, L, 3 * K)), device="cuda")
+    for tr in (False, True):
+        yd = D.apply(x, transpose=tr)
+        yf = F.apply(x, transpose=tr)
+        assert float((yf - yd).abs().max() / yd.abs().max()) < 1e-13
+    assert F.stats()["bytes"] == 0
+    Vi = c.compress(B.OP_V, eps3d=1e-3, eps_aca=1e-4, leaf=32, prec=B.PREC_MIXED, mixed_eps_floor=1e-4)
+    xd, _ = D.solve(x, tol=1e-11)
+    for tr in (False, True):
+        xd_t, _ = D.solve(x, tol=1e-11, transpose=tr)
+        xf, st = F.solve(x, inner=Vi, tol=1e-11, transpose=tr)
+        assert st["converged"] == 1 and st["refinements"] >= 2
+        assert float((xf - xd_t).abs().max() / xd_t.abs().max()) < 1e-9, tr
+    # fine operator on a perturbed mesh, inner operator of the unperturbed context
+    rng = np.random.default_rng(81)
+    Xp = X + 1e-4 * rng.standard_normal(X.shape)
+    cp = _ctx(Xp, T, s, near_on=True)
+    Dp = cp.assemble_dense(B.OP_V)
+    Fp = cp.matrix_free(B.OP_V)
+    xdp, _ = Dp.solve(x, tol=1e-11)
+    xfp, st = Fp.solve(x, inner=Vi, tol=1e-11)
+    assert st["converged"] == 1
+    assert float((xfp - xdp).abs().max() / xdp.abs().max()) < 1e-9
+    with pytest.raises(B.BemError):
+        F.apply(x[:1, 0].contiguous(), shared_x=True)
+    with pytest.raises(B.BemError):
+        F.apply_weighted(x[0])
+    with pytest.raises(B.BemError):
+        c.matrix_free(B.OP_TABLE)
+    X2, T2 = W.icosphere(1)
+    c.set_mesh(X2, T2)  # another size: the operator refuses to run
+    with pytest.raises(B.BemError):
+        F.apply(torch.tensor(W.random_rhs(84, (1, L, 3 * len(T2))), device="cuda"))
+    for o in (D, F, Vi, Dp, Fp):
+        o.destroy()
+
+
+def test_autograd_solve_matrix_free(torch):
+    """single_layer_solve with the matrix-free fine operator and a compressed inner operator:
+    value and gradients equal those of the dense solve."""
+    from paper_2607_15292_amd.autograd import single_layer_solve
+    X, T = W.icosphere(2)
+    s = W.bdf2_contour(8, 0.1)[[0, 5]]
+    c = _ctx(X, T, s, near_on=True)
+    b0 = W.random_rhs(82, (1, 2, 3 * len(T)))
+    cw = torch.tensor(W.random_rhs(83, (1, 2, 3 * len(T))), device="cuda")
+    res = []
+    for kw in ({}, {"matrix_free": True, "inner": {"eps3d": 1e-3, "eps_aca": 1e-4, "leaf": 32,
+                                                    "prec": B.PREC_MIXED, "mixed_eps_floor": 1e-4}}):
+        nodes = torch.tensor(X, dtype=torch.float64, requires_grad=True)
+        mat = torch.tensor([1.0, 1.0, 0.5], dtype=torch.float64, requires_grad=True)
+        b = torch.tensor(b0, device="cuda", requires_grad=True)
+        t = single_layer_solve(c, nodes, mat, b, T, tol=1e-12, **kw)
+        loss = (cw.conj() * t).real.sum() + (t.abs() ** 2).sum() * 0.05
+        loss.backward()
+        res.append((float(loss.item()), nodes.grad.numpy().copy(), mat.grad.numpy().copy(), b.grad.cpu().numpy()))
+    (l0, gn0, gm0, gb0), (l1, gn1, gm1, gb1) = res
+    assert abs(l1 - l0) <= 1e-10 * abs(l0)
+    assert np.abs(gn1 - gn0).max() <= 1e-8 * np.abs(gn0).max()
+    assert np.abs(gm1 - gm0).max() <= 1e-8 * np.abs(gm0).max()
+    assert np.abs(gb1 - gb0).max() <= 1e-8 * np.abs(gb0).max()
