@@ -3,11 +3,9 @@
 // (d = 0, 1, ...) and every phase of a step runs over all blocks still iterating.
 //
 // Per block, step d:
-//   face    H_d[i,j] = ENTRY(i,j,k_d) - sum_{a<d} H_a[i,j] f_a[k_d]
-//           dense blocks: every pair generated (k_face_dense, one workgroup per 256 pairs);
-//           low-rank blocks: matrix-valued ACA on the residual rows/columns and QR/SVD
-//           recompression (eq. (ACA)) (k_aca, one workgroup per block), pivot searched on
-//           the reconstruction (k_scan_lr), as Sec. 3.1 describes;
+//   face    H_d[i,j] = ENTRY(i,j,k_d) - sum_{a<d} H_a[i,j] f_a[k_d], every pair generated
+//           and stored dense (k_face_dense: regular pairs, one workgroup per 256 pairs;
+//           k_face_general: near and self pairs), sigma_3 of each pair reduced per tile;
 //   pivot   (i_d, j_d) = argmax sigma_3(H_d[i,j]) (criterion of eq. (SVD))      (k_pivot)
 //   fibre   f_d[k] = H_d[i_d,j_d]^{-1} (ENTRY(i_d,j_d,k) - sum_{a<d} H_a[i_d,j_d] f_a[k])
 //           and F_da = sum_k f_d[k] f_a[k]^H                                   (k_fibre)
@@ -18,6 +16,17 @@
 // A residual face below eps ||C^(d-1)||_F ends the block (converged); a face without a
 // regular pivot switches the block to dense storage (one face per frequency with a
 // selector fibre), as Sec. 3 prescribes.  Pivots, inverses and norms are FP64.
+//
+// After the last step, the faces of the admissible blocks go through the per-slice ACA as a
+// post-pass on the exact stored faces (k_face_aca, one wavefront per face: partial-pivot
+// matrix-valued ACA with rank-3 steps and sigma_3 pivots), then the QR + SVD recompression
+// of eq. (ACA) (k_face_recomp in recomp.hip).  A face stays dense when its ACA reaches the
+// column capacity (unless resumed from a recompression of its columns), when the decay of
+// its step norms predicts more columns than 1.5 times the capacity, when it runs out of
+// regular pivot rows, or when its factors would not take less memory than the dense face.
+// The pivots of the 3D-ACA therefore come from the exact faces: the search of the pivot on
+// a reconstruction of the ACA factors, which the paper needs because its faces exist only
+// as factors, is not done here.
 #include "aca3d.hpp"
 
 namespace bem {
@@ -893,7 +902,7 @@ __global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A, int resume)
     const BlockIn B = A.blocks[b];
     const FaceDesc f = A.faces[(size_t)b * A.L + d];
     const int m = B.rs, n = B.cs;
-    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax, ACA_HALVES);
+    AcaWork w = aca_work(A.scratch + A.slot_off[blockIdx.x], m, n, A.kmax, ACA_HALVES);
     if (resume && w.info[0] != -3) return;
     int kc = -1, built = 0, kc0 = 0, irow0 = 0;
     double tol = 0.0;

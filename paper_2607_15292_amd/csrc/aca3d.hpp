@@ -83,7 +83,7 @@ struct CompressArgs {
     unsigned long long* pool_top;
     int* err;
     double* scratch;
-    size_t scratch_per_slot;  // doubles
+    const long long* slot_off;  // scratch slot of each list position (offset in doubles)
     int* pending;           // faces left at slot state -3 by a recompression launch (counter)
     int aca_rounds;         // resume launches allowed after intermediate recompressions (0: none)
     const int* pairs;       // pair orders of the blocks with pair0 >= 0

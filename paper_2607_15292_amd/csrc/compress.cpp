@@ -73,6 +73,7 @@ constexpr double QPTS_REGULAR = 7.0;
 constexpr double FLOPS_RESIDUAL = 216.0;
 double flops_eval(int op) { return op == BEM_OP_V ? 125.0 : (op == BEM_OP_TABLE ? 0.0 : 236.0); }
 constexpr size_t ACA_SLOTS = 8192;  // faces per launch of the per-slice ACA pass (scratch slots)
+constexpr size_t ACA_SCRATCH_BYTES = (size_t)16 << 30;  // scratch of one such launch, at most
 constexpr int POOL_STEPS0 = 32;     // 3D-ACA steps of every block in the initial pool
 
 // Segments: each row group's face list cut into pieces of about equal work (the staged inner
@@ -606,7 +607,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     A.pending = (int*)(aux.as<char>() + 128);
     A.aca_rounds = o.aca_rounds;
     A.scratch = nullptr;
-    A.scratch_per_slot = 0;
+    A.slot_off = nullptr;
     A.pairs = pairs_dev.as<int>();
     A.eps3d = o.eps3d;
     A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
@@ -813,20 +814,41 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     });
     BEM_HIP_TRY(hipEventRecord(ev1, st));
     if (!items.empty()) {
-        size_t per_slot = (aca_scratch_doubles(mmax, nmax, kmax, ACA_HALVES) + 31) & ~(size_t)31;
+        // scratch slots sized by each face's own dimensions, in chunks of at most ACA_SLOTS
+        // faces and ACA_SCRATCH_BYTES (or a quarter of the memory when that is less): the
+        // scratch buffer then has the same size in every compression of the operator and is
+        // served again from the context's cache
+        std::vector<long long> soff(items.size());
+        std::vector<size_t> chunk0;
         size_t fr = 0, tot = 0;
         BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
-        const size_t fit = std::max<size_t>(256, (size_t)(0.5 * (double)fr) / (per_slot * sizeof(double)));
-        const int slots = (int)std::min({items.size(), ACA_SLOTS, fit});
+        const size_t budget = std::min<size_t>(ACA_SCRATCH_BYTES, (size_t)(0.25 * (double)(fr + ctx->cache.cached)));
+        size_t chunk_bytes = 0, max_bytes = 0;
+        for (size_t i = 0; i < items.size(); ++i) {
+            const BlockIn& Bi = C->blocks[items[i] >> 8];
+            const size_t sz = (aca_scratch_doubles(Bi.rs, Bi.cs, kmax, ACA_HALVES) + 31) & ~(size_t)31;
+            if (chunk0.empty() || i - chunk0.back() >= ACA_SLOTS || (chunk_bytes + sz) * sizeof(double) > budget) {
+                chunk0.push_back(i);
+                chunk_bytes = 0;
+            }
+            soff[i] = (long long)chunk_bytes;
+            chunk_bytes += sz;
+            max_bytes = std::max(max_bytes, chunk_bytes * sizeof(double));
+        }
+        chunk0.push_back(items.size());
         DevBuf scratch(&ctx->cache);
-        scratch.alloc(per_slot * slots * sizeof(double));
+        scratch.alloc(max_bytes);
         A.scratch = scratch.as<double>();
-        A.scratch_per_slot = per_slot;
         const int* p_items = put_list(list_dev, 0, items, st);
+        DevBuf soff_dev;
+        soff_dev.alloc(soff.size() * sizeof(long long));
+        BEM_HIP_TRY(hipMemcpyAsync(soff_dev.p, soff.data(), soff.size() * sizeof(long long), hipMemcpyHostToDevice, st));
         std::vector<hipEvent_t> evr;
-        for (size_t c0 = 0; c0 < items.size(); c0 += (size_t)slots) {
+        for (size_t ci = 0; ci + 1 < chunk0.size(); ++ci) {
+            const size_t c0 = chunk0[ci];
             A.list = p_items + c0;
-            A.nlist = (int)std::min<size_t>((size_t)slots, items.size() - c0);
+            A.slot_off = soff_dev.as<long long>() + c0;
+            A.nlist = (int)(chunk0[ci + 1] - c0);
             // first run over the chunk, then resume launches while intermediate recompressions
             // leave faces pending (the count comes back through pinned memory)
             for (int round = 0; round <= o.aca_rounds; ++round) {

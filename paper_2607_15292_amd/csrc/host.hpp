@@ -28,11 +28,12 @@ struct MemCache {
     static constexpr size_t MIN_BYTES = (size_t)64 << 20;  // smaller buffers bypass the cache
     std::multimap<size_t, void*> bufs;
     size_t cached = 0;
-    // smallest cached buffer of at least n bytes and at most 1.5 n + 64 MiB; null if none
-    void* take(size_t n, size_t* got)
+    // smallest cached buffer of at least n bytes and (unless any) at most 1.5 n + 64 MiB; null
+    // if none
+    void* take(size_t n, size_t* got, bool any = false)
     {
         auto it = bufs.lower_bound(n);
-        if (it == bufs.end() || (double)it->first > 1.5 * (double)n + (double)(64 << 20)) return nullptr;
+        if (it == bufs.end() || (!any && (double)it->first > 1.5 * (double)n + (double)(64 << 20))) return nullptr;
         void* q = it->second;
         *got = it->first;
         cached -= it->first;
@@ -81,6 +82,16 @@ struct DevBuf {
             // a kernel with a private segment starts, queues): evict cached buffers, largest
             // first, else refuse
             size_t fr = 0, tot = 0;
+            if (cache && hipMemGetInfo(&fr, &tot) == hipSuccess && fr < n + RESERVE) {
+                // short of memory: a larger cached buffer serves before any is returned to
+                // the driver (freeing and mapping tens of GB takes longer than the kernels)
+                size_t got = 0;
+                if (void* q = cache->take(n, &got, true)) {
+                    p = q;
+                    bytes = got;
+                    return;
+                }
+            }
             while (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < n + RESERVE) {
                 if (!cache || cache->bufs.empty()) throw bem_nomem(n);
                 auto it = std::prev(cache->bufs.end());

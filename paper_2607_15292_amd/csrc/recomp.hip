@@ -27,9 +27,7 @@ namespace bem {
 
 namespace {
 
-constexpr int NT = 1024;        // threads of a recompression workgroup
-constexpr int NW = NT / 64;     // its wavefronts
-constexpr int KF = 96;          // largest core (ACA columns)
+constexpr int KF_MAX = 96;      // largest core (ACA columns) of the pass
 
 // The pivoted QR of the core stops once its remaining columns are below QRCP_FRAC tol; the
 // SVD truncation of the kept rows then has sqrt(1 - QRCP_FRAC^2) of the tolerance left.
@@ -83,10 +81,22 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+__device__ __forceinline__ int gx() { return threadIdx.x & 31; }
+__device__ __forceinline__ int gy() { return threadIdx.x >> 5; }
+
+// The recompression for one workgroup size NT and largest core KF (ACA columns): the LDS
+// working set grows as KF^2, so small cores take a smaller configuration of which several
+// workgroups share a compute unit.
+template <int NT_, int KF_>
+struct Rc {
+static constexpr int NT = NT_;     // threads of a recompression workgroup
+static constexpr int NW = NT / 64; // its wavefronts
+static constexpr int KF = KF_;     // largest core (ACA columns)
+static_assert(KF <= KF_MAX && NT % 64 == 0, "");
 // LDS matrices use the odd leading dimension kc | 1: with complex128 entries (4 banks each),
 // an odd stride keeps the accesses of a row (stride ld) of 8 consecutive lanes in distinct
 // banks.
-constexpr int LMS = KF * (KF + 1);
+static constexpr int LMS = KF * (KF + 1);
 
 struct Rs {
     zd m[LMS];      // kc x kc working matrix, column-major with ld = kc | 1; Gram staging area
@@ -101,16 +111,14 @@ struct Rs {
 };
 
 // 32 x GY thread grid for the element loops over small matrices
-constexpr int GY = NT / 32;
-__device__ __forceinline__ int gx() { return threadIdx.x & 31; }
-__device__ __forceinline__ int gy() { return threadIdx.x >> 5; }
+static constexpr int GY = NT / 32;
 
 // Lm = X^H X (kc x kc, full Hermitian, ld) for X (rows x kc, column-major, global).  A
 // thread owns up to two 2 x 2 tiles of the upper triangle.  Row chunks of X are staged
 // through Lm in two planes (even and odd columns), so that the lanes of a tile row read
 // consecutive entries.
-constexpr int GT = ((KF / 2) * (KF / 2 + 1) / 2 + NT - 1) / NT;  // 2 x 2 tiles per thread
-__device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
+static constexpr int GT = ((KF / 2) * (KF / 2 + 1) / 2 + NT - 1) / NT;  // 2 x 2 tiles per thread
+static __device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
 {
     const int nt = (kc + 1) >> 1, ntri = nt * (nt + 1) / 2;
     const int cr = min(rows, LMS / (2 * nt)), pl = cr * nt;
@@ -186,7 +194,7 @@ __device__ void gram(const zd* X, int rows, int kc, zd* Lm, int ld)
 // zeroed); a pivot without positive mass gives a zero row.  Step k updates the trailing
 // matrix from the unscaled row k (divided by the pivot) and scales row k - 1 with the pivot
 // read one step earlier.  Returns the smallest pivot (before the square root).
-__device__ double cholesky(zd* Lm, int kc, int ld)
+static __device__ double cholesky(zd* Lm, int kc, int ld)
 {
     const int tx = gx(), ty = gy();
     double pmin = 1e300, pprev = 0.0;
@@ -220,7 +228,7 @@ __device__ double cholesky(zd* Lm, int kc, int ld)
 
 // X (rows x kc, column-major, global) <- X R^{-1}, R upper in Lm (ld); one row per thread,
 // blocks of 8 columns; zero pivots give zero columns.
-__device__ void trsm(zd* X, int rows, const zd* Lm, int kc, int ld)
+static __device__ void trsm(zd* X, int rows, const zd* Lm, int kc, int ld)
 {
     constexpr int NB = 8;
     for (int r = threadIdx.x; r < rows; r += NT) {
@@ -257,7 +265,7 @@ __device__ void trsm(zd* X, int rows, const zd* Lm, int kc, int ld)
 // norms, kept in dsc) instead of X.  On return Q = X dsc^-1 T^{-1} with T upper in Tout
 // (after two passes X holds X D^{-1} R1^{-1} and dsc is 1) and R = R_fact D in Rout, R_fact
 // the triangular factor of X D^{-1}; both kc x kc column-major (ld kc) in global scratch.
-__device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, double* dsc, Rs& L, int ld)
+static __device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, double* dsc, Rs& L, int ld)
 {
     zd* Lm = L.m;
     const int tx = gx(), ty = gy();
@@ -314,7 +322,7 @@ __device__ void chol_qr(zd* X, int rows, int kc, zd* Rout, zd* Tout, double* dsc
 // reflectors H = I - tau v v^H with v[0] = 1 stored below the diagonal, stopped at the first
 // step whose remaining columns have Frobenius norm <= delta.  Returns the number of steps;
 // tau in L.tau, the column order in L.perm, the remaining squared norm in *rest2.
-__device__ int qrcp(zd* Lm, int kc, int ld, double delta, Rs& L, double* rest2)
+static __device__ int qrcp(zd* Lm, int kc, int ld, double delta, Rs& L, double* rest2)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int c = threadIdx.x / CG; c < kc; c += NT / CG) {
@@ -431,8 +439,8 @@ __device__ int qrcp(zd* Lm, int kc, int ld, double delta, Rs& L, double* rest2)
 // the pair in registers; round-robin pair order, one barrier per round.  A pair is rotated
 // while |<a, b>| > 1e-12 |a| |b| and |<a, b>| > gmin: below gmin (a small fraction of tol^2)
 // the pair's non-orthogonality cannot move the truncation at tol.
-constexpr int JG = 16;
-__device__ int jacobi(zd* Lm, int rows, int ncol, int ld, double gmin, Rs& L)
+static constexpr int JG = 16;
+static __device__ int jacobi(zd* Lm, int rows, int ncol, int ld, double gmin, Rs& L)
 {
     constexpr int RPL = (KF + JG - 1) / JG;
     const int np = ncol + (ncol & 1);
@@ -519,8 +527,8 @@ __device__ int jacobi(zd* Lm, int rows, int ncol, int ld, double gmin, Rs& L)
 // D_h = diag(d_h) (zero entries and zero pivots give zero rows).  Blocks of BS rows from the
 // bottom: a thread per column solves the diagonal block, then the rows above are updated as
 // a small GEMM; two barriers per block.
-constexpr int BS = 8;
-__device__ void backsub2(const zd* R0, const double* d0, zd* Y0, const zd* R1, const double* d1, zd* Y1, int kc,
+static constexpr int BS = 8;
+static __device__ void backsub2(const zd* R0, const double* d0, zd* Y0, const zd* R1, const double* d1, zd* Y1, int kc,
                          int kk, int ldy)
 {
     const int nsys = Y1 ? 2 : 1;
@@ -578,7 +586,7 @@ __device__ void backsub2(const zd* R0, const double* d0, zd* Y0, const zd* R1, c
 // column-major, global) Y_h (kc x kk, column-major with ld ldy, LDS) for up to two products; a
 // thread per (row, 8 columns).
 template <typename T, bool CM = false>
-__device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T>* o1, const zd* X1, int rows1,
+static __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T>* o1, const zd* X1, int rows1,
                           const zd* Y1, int kc, int kk, int ldy)
 {
     constexpr int CH = 8;
@@ -618,7 +626,7 @@ __device__ void out_gemm2(cx<T>* o0, const zd* X0, int rows0, const zd* Y0, cx<T
 // Algorithmic flops of the executed parts of one recompression (complex multiply-add = 8):
 // stage 0 = QR factors, core and pivoted QR; 1 = + Jacobi; 2 = + coefficients, reflectors,
 // back-substitutions and output products.
-__device__ double recomp_flops(int stage, int m, int n, int kc, int kq, int sweeps, int kk)
+static __device__ double recomp_flops(int stage, int m, int n, int kc, int kq, int sweeps, int kk)
 {
     const double c = kc, ru = 3.0 * m, rv = 3.0 * n;
     double f = 8.0 * ((ru + rv) * c * (c + 1.0) / 2.0 + 2.0 * c * c * c / 6.0 + c * c * c / 3.0);
@@ -634,9 +642,9 @@ __device__ double recomp_flops(int stage, int m, int n, int kc, int kq, int swee
 // CM (the intermediate recompression of a run that reached the column capacity): the factors
 // go to the slot's other column half (w.U2, w.V2) in complex128 column-major, at most KF_RESUME
 // of them, with no memory rule.
-constexpr int KF_RESUME = KF - 12;
+static constexpr int KF_RESUME = KF_MAX - 12;
 template <typename T, bool CM = false>
-__device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L, double& flop)
+static __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L, double& flop)
 {
     zd* Lm = L.m;
     const int ld = kc | 1;
@@ -780,14 +788,23 @@ __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, d
     }
     return kk;
 }
+};  // struct Rc
+
+using RcBig = Rc<1024, KF_MAX>;  // one workgroup per compute unit (149 KB of LDS)
+using RcSmall = Rc<256, 48>;     // 40 KB of LDS: four workgroups per compute unit
+constexpr int KC_SMALL = 48;     // cores of at most this many columns take RcSmall
 
 // one workgroup per listed face (item (block << 8) | d, scratch slot = position in the list)
 // after k_face_aca: recompresses the slot's ACA columns and rewrites the face descriptor.  A
 // run that reached the column capacity (state -2) is recompressed at tol / 4 into the slot's
 // other half and left for a resume launch (state -3); every other face ends at state -4.
-__global__ __launch_bounds__(NT) void k_face_recomp(CompressArgs A)
+// Two launches share the list: R = RcSmall takes the faces of 1..KC_SMALL columns, R = RcBig
+// (KLO = KC_SMALL) all others, so every face is finished by exactly one of them.
+template <class R, int KLO>
+__global__ __launch_bounds__(R::NT) void k_face_recomp(CompressArgs A)
 {
-    __shared__ Rs L;
+    constexpr bool BIG = R::KF == KF_MAX;
+    __shared__ typename R::Rs L;
     const int item = A.list[blockIdx.x];
     const int b = item >> 8, d = item & 255;
     const BlockIn B = A.blocks[b];
@@ -795,18 +812,19 @@ __global__ __launch_bounds__(NT) void k_face_recomp(CompressArgs A)
     const FaceDesc f = *fp;
     if (f.kk != 0 || f.sel) return;
     const int m = B.rs, n = B.cs;
-    AcaWork w = aca_work(A.scratch + (size_t)blockIdx.x * A.scratch_per_slot, m, n, A.kmax, ACA_HALVES);
+    AcaWork w = aca_work(A.scratch + A.slot_off[blockIdx.x], m, n, A.kmax, ACA_HALVES);
     const int kc = w.info[0];
     if (kc == -3 || kc == -4) return;
+    if (BIG ? (kc > 0 && kc <= KLO) : !(kc > KLO && kc <= R::KF)) return;
     aca_select_half(w);
     int kk = 0;
     double flop = 0.0;
-    if (kc > 0 && kc <= KF) {
+    if (kc > 0 && kc <= R::KF) {
         const double tol = w.tol[0];
-        kk = f.fp32 ? recompress((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop)
-                    : recompress((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop);
-    } else if (kc == -2) {
-        kk = recompress<double, true>(nullptr, m, n, w, w.info[1], 0.25 * w.tol[0], L, flop);
+        kk = f.fp32 ? R::recompress((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop)
+                    : R::recompress((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop);
+    } else if (BIG && kc == -2) {
+        kk = R::template recompress<double, true>(nullptr, m, n, w, w.info[1], 0.25 * w.tol[0], L, flop);
     }
     if (threadIdx.x == 0) {
         atomicAdd(&A.st[b].recomp_flop, flop);
@@ -828,18 +846,19 @@ __global__ __launch_bounds__(NT) void k_face_recomp(CompressArgs A)
 }
 
 // the same pass on one given matrix H (after k_aca_matrix): out[0] = ACA columns, out[1] = kk
-__global__ __launch_bounds__(NT) void k_aca_matrix_recomp(char* H, int m, int n, int fp32, int kmax,
-                                                          double* scratch, int* out)
+__global__ __launch_bounds__(RcBig::NT) void k_aca_matrix_recomp(char* H, int m, int n, int fp32, int kmax,
+                                                                double* scratch, int* out)
 {
-    __shared__ Rs L;
+    using R = RcBig;
+    __shared__ R::Rs L;
     AcaWork w = aca_work(scratch, m, n, kmax);
     const int kc = out[0];
     int kk = 0;
     double flop = 0.0;
-    if (kc > 0 && kc <= KF) {
+    if (kc > 0 && kc <= R::KF) {
         const double tol = w.tol[0];
-        kk = fp32 ? recompress((cx<float>*)H, m, n, w, kc, tol, L, flop)
-                  : recompress((cx<double>*)H, m, n, w, kc, tol, L, flop);
+        kk = fp32 ? R::recompress((cx<float>*)H, m, n, w, kc, tol, L, flop)
+                  : R::recompress((cx<double>*)H, m, n, w, kc, tol, L, flop);
     }
     if (threadIdx.x == 0) out[1] = kk;
 }
@@ -848,13 +867,16 @@ __global__ __launch_bounds__(NT) void k_aca_matrix_recomp(char* H, int m, int n,
 
 void launch_face_recomp(const CompressArgs& A, hipStream_t st)
 {
-    if (A.nlist > 0) hipLaunchKernelGGL(k_face_recomp, dim3(A.nlist), dim3(NT), 0, st, A);
+    if (A.nlist > 0) {
+        hipLaunchKernelGGL((k_face_recomp<RcBig, KC_SMALL>), dim3(A.nlist), dim3(RcBig::NT), 0, st, A);
+        hipLaunchKernelGGL((k_face_recomp<RcSmall, 0>), dim3(A.nlist), dim3(RcSmall::NT), 0, st, A);
+    }
     BEM_HIP_TRY(hipGetLastError());
 }
 
 void launch_aca_matrix_recomp(char* H, int m, int n, int fp32, int kmax, double* scratch, int* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_aca_matrix_recomp, dim3(1), dim3(NT), 0, st, H, m, n, fp32, kmax, scratch, out);
+    hipLaunchKernelGGL(k_aca_matrix_recomp, dim3(1), dim3(RcBig::NT), 0, st, H, m, n, fp32, kmax, scratch, out);
     BEM_HIP_TRY(hipGetLastError());
 }
 
