@@ -68,6 +68,9 @@ typedef struct bem_op bem_op;
 #define BEM_OP_K 1     /* double layer K (eq. (DLP)), kernel T, Cauchy principal value */
 #define BEM_OP_HK 2    /* C + K with the free term C = I/2 at smooth points (eq. (SBIE)) */
 #define BEM_OP_TABLE 3 /* ENTRY read from a user table (bem_set_entry_table); for tests */
+#define BEM_OP_KL0 4   /* bem_entries only: the double layer against the hat function of vertex 0 */
+#define BEM_OP_KL1 5   /* (1, 2) of element j: int_{gamma_j} T(x_i, y) lambda_v(y) dy, the element */
+#define BEM_OP_KL2 6   /* share of the continuous piecewise-linear basis of eqs. (subspace), (basis) */
 
 /* precision of entry generation and storage */
 #define BEM_PREC_F64 0   /* complex128 everywhere */
@@ -79,6 +82,7 @@ typedef struct bem_op bem_op;
 #define BEM_SHARED_X 2     /* bem_apply: x has shape [nrhs][3K], the same for every frequency */
 #define BEM_TRANSPOSE 4    /* bem_apply, bem_solve: the plain transpose A(s_l)^T (no conjugation);
                               the adjoint of a solution needs A^T solves */
+#define BEM_FREE_TERM 8    /* bem_apply_linear_dl: add the free term C = I/2 (C + K) */
 
 /* Quadrature options (Sec. 2.3: Duffy for the singular collocation integrals; the rest is
  * this library's documented reading).  regular pairs: 7-point degree-5 rule; near pairs
@@ -117,7 +121,23 @@ typedef struct {
                              (eq. (ACA), at a quarter of the face tolerance) and the ACA resumes
                              from them, up to this many times per pass.  For memory-bound
                              compressions: it trades recompression time for storage */
+    int32_t face_order;   /* where the per-slice ACA of the admissible blocks' faces runs:
+                             BEM_FACES_AFTER (default): a pass over the exact faces once the
+                             3D-ACA of every block has ended (faces compressed to an absolute
+                             tolerance eps_aca ||C|| / ||f_d||);
+                             BEM_FACES_IN_LOOP: the paper's order (Sec. 3.1, the H-matrix
+                             ACA): in every step the residual face is approximated by the ACA
+                             and recompressed (eq. (ACA)) relative to its own norm (stop when
+                             ||U_k|| ||V_k|| <= eps_aca ||U V^H||, truncation at eps_aca of the
+                             singular values), the pivot of Algorithm 1 is searched on the
+                             reconstruction of the factors, and the reconstruction is the face
+                             that the later residuals, the fibre and the norm of eq. (FrobNorm)
+                             use.  A face whose ACA does not resolve within 96 columns, or whose
+                             factors would not take less memory, stays exact.  aca_rounds does
+                             not apply */
 } bem_aca_opts;
+#define BEM_FACES_AFTER 0
+#define BEM_FACES_IN_LOOP 1
 
 /* Statistics of an operator (compression rate as defined in Sec. 4.1: memory of the
  * compressed representation over the memory of the dense M x M x L array). */
@@ -371,6 +391,18 @@ int bem_solve(bem_op *A, bem_op *A_inner, int32_t nrhs, const void *b, void *x, 
  * transpose != 0, for op V, K or HK; x, y: [nrhs][L][3K] complex128 in mesh order, host or
  * device per flags (BEM_DEVICE_PTR).  Cost: K^2 L entries per pass of 4 right-hand sides. */
 int bem_apply_mf(bem_ctx *ctx, int32_t op, int32_t transpose, int32_t nrhs, const void *x, void *y, int32_t flags);
+
+/* The double layer against continuous piecewise-linear shape functions (Sec. 2.3, eqs.
+ * (subspace), (basis): the Dirichlet data of eq. (discreteCollo) are nodal values, and K of
+ * eq. (discrVK) integrates T against the hat function phi_n of each node) collocated at the
+ * element centroids, entries recomputed (matrix-free, FP64 rules of bem_entries):
+ *   y[r][l][3 i + a] = sum_n (K(s_l)[i, n] g[r][l][3 n ..])_a,
+ *   K(s_l)[i, n] = sum over the elements j of node n of int_{gamma_j} T(x_i, y) lambda_v(y) dy
+ *   (v = position of n in element j, lambda_v its barycentric coordinate).
+ * With BEM_FREE_TERM, y also gets C g with C phi_n(x_i) = I/2 * 1/3 for the three nodes of
+ * element i.  g: [nrhs][L][3 n_nodes] complex128 (mesh node order), y: [nrhs][L][3K],
+ * host or device per flags (BEM_DEVICE_PTR).  Cost: K^2 L (three weights per evaluation). */
+int bem_apply_linear_dl(bem_ctx *ctx, int32_t nrhs, const void *g, void *y, int32_t flags);
 
 /* Matrix-free operator (op V, K or HK of eq. (discrVK) in FP64, nothing stored): bem_apply
  * (plain or BEM_TRANSPOSE, not BEM_SHARED_X) recomputes every entry as bem_apply_mf does, with

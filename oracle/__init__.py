@@ -90,6 +90,7 @@ def _i(a):
 
 
 OP_V, OP_K, OP_HK = 0, 1, 2
+OP_KL0, OP_KL1, OP_KL2 = 4, 5, 6  # double layer weighted by the barycentric coordinate of vertex 0, 1, 2
 
 
 class Problem:
@@ -131,6 +132,24 @@ class Problem:
         ii, jj, ll = np.meshgrid(np.arange(K), np.arange(K), np.arange(L), indexing="ij")
         E = self.entries(op, ii.ravel(), jj.ravel(), ll.ravel()).reshape(K, K, L, 3, 3)
         return np.ascontiguousarray(E.transpose(2, 0, 3, 1, 4).reshape(L, 3 * K, 3 * K))
+
+    def dense_linear_dl(self, free_term=True):
+        """Double layer against the continuous piecewise-linear shape functions of the nodes
+        (Sec. 2.3, eqs. (subspace), (basis); K of eq. (discrVK) with phi_l), collocated at the
+        centroids: complex128 [L, 3K, 3N], column block n = node n.  Entry (i, n) is the sum
+        over the elements j sharing node n of int_{gamma_j} T(x_i, y) lambda_v(y) dy with v the
+        position of n in element j.  free_term adds C phi_n(x_i) = I/2 * 1/3 for the three
+        nodes of element i (eq. (discreteCollo) with C = I/2 at the centroids)."""
+        K, L, N = self.K, self.L, self.nodes.shape[0]
+        out = np.zeros((L, 3 * K, N, 3), dtype=np.complex128)
+        for v in range(3):
+            D = self.dense(OP_KL0 + v).reshape(L, 3 * K, K, 3)
+            np.add.at(out, (slice(None), slice(None), self.tris[:, v]), D)
+        if free_term:
+            for v in range(3):
+                for a in range(3):
+                    out[:, 3 * np.arange(K) + a, self.tris[:, v], a] += 0.5 / 3.0
+        return out.reshape(L, 3 * K, 3 * N)
 
     def solve(self, op, b, rhs_op=None):
         """x[r, l] = A_l^{-1} c[r, l] with A_l the dense operator op at s_l (the collocation

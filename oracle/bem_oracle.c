@@ -29,6 +29,13 @@
  *                      leading 1/rho^2 part g(theta) = c2^2/(4 pi c1^2) (rh_i n_j - rh_j n_i)
  *                      integrated analytically in rho (its log terms cancel over 2 pi).
  *   - op 2 adds the free term C = I/2 of eq. (SBIE) at smooth points to K.
+ *   - ops 4, 5, 6: the double layer against the continuous piecewise-linear shape functions
+ *     of the Dirichlet data (eqs. (subspace), (basis), K of eq. (discrVK) with phi_l): the
+ *     integrand T of element j weighted by the barycentric coordinate lambda_v(y) of its
+ *     vertex v = op - 4, with the same rules; in the self pair the principal value is taken
+ *     with the leading part weighted by lambda_v at the centroid (1/3), the remainder
+ *     T (lambda_v(y) - 1/3) being weakly singular.  The linear-basis operator sums these over
+ *     the elements sharing a node.
  *
  * Everything is written per entry, per quadrature point, per frequency; no blocking,
  * no reuse across frequencies, no shared tables with the GPU library.
@@ -274,6 +281,18 @@ typedef struct {
     double gl_t[64], gl_tw[64], gl_r[64], gl_rw[64];
 } ctx;
 
+/* Barycentric coordinate of vertex v of element e at a point y of its plane:
+ * lambda_v(y) = n . ((P_{v+1} - y) x (P_{v+2} - y)) / (2 A).  vw < 0: weight 1. */
+static double bary_weight(const element *e, int vw, const double *y)
+{
+    if (vw < 0) return 1.0;
+    const double *p1 = e->v[(vw + 1) % 3], *p2 = e->v[(vw + 2) % 3];
+    double a[3], b[3];
+    for (int k = 0; k < 3; ++k) { a[k] = p1[k] - y[k]; b[k] = p2[k] - y[k]; }
+    double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    return (e->n[0] * cr[0] + e->n[1] * cr[1] + e->n[2] * cr[2]) / (2.0 * e->area);
+}
+
 /* integrand value at y for collocation point x and element normal n (op 0: U, else T) */
 static void integrand(int op, const double *x, const double *y, const double *n, cplx s, const material *m, cplx *R)
 {
@@ -287,7 +306,7 @@ static void integrand(int op, const double *x, const double *y, const double *n,
 
 /* 7-point rule over the triangle (p0, p1, p2) of area A, accumulated into acc. */
 static void tri_rule(const ctx *C, int op, const double *x, const double *p0, const double *p1, const double *p2,
-                     double A, const double *n, cplx s, cplx *acc)
+                     double A, const double *n, cplx s, const element *par, int vw, cplx *acc)
 {
     for (int q = 0; q < 7; ++q) {
         const double *B = &C->tri_bary[3 * q];
@@ -295,16 +314,18 @@ static void tri_rule(const ctx *C, int op, const double *x, const double *p0, co
         for (int k = 0; k < 3; ++k) y[k] = B[0] * p0[k] + B[1] * p1[k] + B[2] * p2[k];
         cplx R[9];
         integrand(op, x, y, n, s, &C->mat, R);
-        for (int t = 0; t < 9; ++t) acc[t] += C->tri_w[q] * A * R[t];
+        const double lw = bary_weight(par, vw, y);
+        for (int t = 0; t < 9; ++t) acc[t] += C->tri_w[q] * A * lw * R[t];
     }
 }
 
 /* 7-point rule on the 4^m sub-triangles obtained by repeated edge-midpoint splitting. */
 static void subdivided_rule(const ctx *C, int op, const double *x, const double *p0, const double *p1,
-                            const double *p2, double A, const double *n, cplx s, int m, cplx *acc)
+                            const double *p2, double A, const double *n, cplx s, int m, const element *par, int vw,
+                            cplx *acc)
 {
     if (m == 0) {
-        tri_rule(C, op, x, p0, p1, p2, A, n, s, acc);
+        tri_rule(C, op, x, p0, p1, p2, A, n, s, par, vw, acc);
         return;
     }
     double m01[3], m12[3], m20[3];
@@ -313,19 +334,20 @@ static void subdivided_rule(const ctx *C, int op, const double *x, const double 
         m12[k] = 0.5 * (p1[k] + p2[k]);
         m20[k] = 0.5 * (p2[k] + p0[k]);
     }
-    subdivided_rule(C, op, x, p0, m01, m20, 0.25 * A, n, s, m - 1, acc);
-    subdivided_rule(C, op, x, m01, p1, m12, 0.25 * A, n, s, m - 1, acc);
-    subdivided_rule(C, op, x, m20, m12, p2, 0.25 * A, n, s, m - 1, acc);
-    subdivided_rule(C, op, x, m01, m12, m20, 0.25 * A, n, s, m - 1, acc);
+    subdivided_rule(C, op, x, p0, m01, m20, 0.25 * A, n, s, m - 1, par, vw, acc);
+    subdivided_rule(C, op, x, m01, p1, m12, 0.25 * A, n, s, m - 1, par, vw, acc);
+    subdivided_rule(C, op, x, m20, m12, p2, 0.25 * A, n, s, m - 1, par, vw, acc);
+    subdivided_rule(C, op, x, m01, m12, m20, 0.25 * A, n, s, m - 1, par, vw, acc);
 }
 
 /* Self element: polar coordinates about the centroid x on the three sub-triangles
  * (x, v_a, v_b); theta is measured from the foot of the perpendicular onto edge v_a v_b. */
-static void self_rule(const ctx *C, int op, const element *e, cplx s, cplx *acc)
+static void self_rule(const ctx *C, int op, const element *e, cplx s, int vw, cplx *acc)
 {
     const double *x = e->c;
     const double *n = e->n;
     const material *m = &C->mat;
+    const double lx = bary_weight(e, vw, x);  /* weight of the leading part (1/3, or 1) */
     const double gpref = (m->c2 * m->c2) / (4.0 * M_PI * m->c1 * m->c1);
     for (int a = 0; a < 3; ++a) {
         const double *va = e->v[a], *vb = e->v[(a + 1) % 3];
@@ -352,7 +374,7 @@ static void self_rule(const ctx *C, int op, const element *e, cplx s, cplx *acc)
             if (op != 0) {
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) g[3 * i + j] = gpref * (dir[i] * n[j] - dir[j] * n[i]);
-                for (int q = 0; q < 9; ++q) acc[q] += wth * g[q] * log(R);
+                for (int q = 0; q < 9; ++q) acc[q] += wth * lx * g[q] * log(R);
             }
             for (int ir = 0; ir < C->qo.self_nr; ++ir) {
                 double rho = 0.5 * R * (1.0 + C->gl_r[ir]);
@@ -361,9 +383,10 @@ static void self_rule(const ctx *C, int op, const element *e, cplx s, cplx *acc)
                 for (int k = 0; k < 3; ++k) y[k] = x[k] + rho * dir[k];
                 cplx Rv[9];
                 integrand(op, x, y, n, s, m, Rv);
+                const double ly = bary_weight(e, vw, y);
                 for (int q = 0; q < 9; ++q) {
-                    cplx f = rho * Rv[q];
-                    if (op != 0) f -= g[q] / rho;
+                    cplx f = rho * ly * Rv[q];
+                    if (op != 0) f -= lx * g[q] / rho;
                     acc[q] += wth * wr * f;
                 }
             }
@@ -377,8 +400,9 @@ static void entry(const ctx *C, int op, int64_t i, int64_t j, cplx s, cplx *out)
     for (int t = 0; t < 9; ++t) out[t] = 0.0;
     const element *ei = &C->el[i], *ej = &C->el[j];
     int kop = (op == 0) ? 0 : 1;
+    int vw = (op >= 4 && op <= 6) ? op - 4 : -1;  /* linear shape function of vertex vw */
     if (i == j) {
-        self_rule(C, kop, ej, s, out);
+        self_rule(C, kop, ej, s, vw, out);
     } else {
         int m = 0;
         if (C->qo.near_on) {
@@ -387,7 +411,7 @@ static void entry(const ctx *C, int op, int64_t i, int64_t j, cplx s, cplx *out)
             if (d2 < C->qo.r1 * C->qo.r1 * ej->lmax2) m = 2;
             else if (d2 < C->qo.r2 * C->qo.r2 * ej->lmax2) m = 1;
         }
-        subdivided_rule(C, kop, ei->c, ej->v[0], ej->v[1], ej->v[2], ej->area, ej->n, s, m, out);
+        subdivided_rule(C, kop, ei->c, ej->v[0], ej->v[1], ej->v[2], ej->area, ej->n, s, m, ej, vw, out);
     }
     if (op == 2 && i == j) {
         out[0] += 0.5;
@@ -515,7 +539,7 @@ int oracle_point_entries(const double *nodes, int64_t n_nodes, const int32_t *tr
         }
         cplx R[9];
         for (int t = 0; t < 9; ++t) R[t] = 0.0;
-        subdivided_rule(&C, op == 0 ? 0 : 1, x, ej->v[0], ej->v[1], ej->v[2], ej->area, ej->n, s_l, m, R);
+        subdivided_rule(&C, op == 0 ? 0 : 1, x, ej->v[0], ej->v[1], ej->v[2], ej->area, ej->n, s_l, m, ej, -1, R);
         for (int t = 0; t < 9; ++t) {
             out[18 * e + 2 * t] = creal(R[t]);
             out[18 * e + 2 * t + 1] = cimag(R[t]);
@@ -633,7 +657,7 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
                     for (int32_t l = 0; l < L; ++l) {
                         cplx sl = s[2 * l] + I * s[2 * l + 1];
                         cplx E[9] = {0};
-                        self_rule(&C, 0, ej, sl, E);
+                        self_rule(&C, 0, ej, sl, -1, E);
                         cplx v = contract(E, w, x, K, L, nrhs, l, i, j);
                         gm[2] += creal(v);
                         gm[3] += cimag(v);
@@ -643,8 +667,8 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
                             if (which == 0) { Cp.mat.c1 += h; Cm.mat.c1 -= h; }
                             else { Cp.mat.c2 += h; Cm.mat.c2 -= h; }
                             cplx Ep[9] = {0}, Em[9] = {0};
-                            self_rule(&Cp, 0, ej, sl, Ep);
-                            self_rule(&Cm, 0, ej, sl, Em);
+                            self_rule(&Cp, 0, ej, sl, -1, Ep);
+                            self_rule(&Cm, 0, ej, sl, -1, Em);
                             cplx D[9];
                             for (int t = 0; t < 9; ++t) D[t] = (Ep[t] - Em[t]) / (2.0 * h);
                             gm[which] += creal(contract(D, w, x, K, L, nrhs, l, i, j));
@@ -661,8 +685,8 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
                                 make_element(vp, loc, &ep);
                                 make_element(vm, loc, &em);
                                 cplx Ep[9] = {0}, Em[9] = {0};
-                                self_rule(&C, 0, &ep, sl, Ep);
-                                self_rule(&C, 0, &em, sl, Em);
+                                self_rule(&C, 0, &ep, sl, -1, Ep);
+                                self_rule(&C, 0, &em, sl, -1, Em);
                                 cplx D[9];
                                 for (int t = 0; t < 9; ++t) D[t] = (Ep[t] - Em[t]) / (2.0 * hl);
                                 g[3 * (int64_t)tj[a] + k] += creal(contract(D, w, x, K, L, nrhs, l, i, j));

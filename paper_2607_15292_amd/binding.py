@@ -20,7 +20,9 @@ ERR_NAMES = {-1: "BEM_ERR_ARG", -2: "BEM_ERR_MESH", -3: "BEM_ERR_MATERIAL", -4: 
              -5: "BEM_ERR_STATE", -6: "BEM_ERR_HIP", -7: "BEM_ERR_NOMEM", -8: "BEM_ERR_NODEVICE"}
 OP_V, OP_K, OP_HK, OP_TABLE = 0, 1, 2, 3
 PREC_F64, PREC_MIXED = 0, 1
-DEVICE_PTR, SHARED_X, TRANSPOSE = 1, 2, 4
+FACES_AFTER, FACES_IN_LOOP = 0, 1
+DEVICE_PTR, SHARED_X, TRANSPOSE, FREE_TERM = 1, 2, 4, 8
+OP_KL0, OP_KL1, OP_KL2 = 4, 5, 6
 
 _lib = None
 
@@ -39,7 +41,8 @@ class bem_quad(ctypes.Structure):
 class bem_aca_opts(ctypes.Structure):
     _fields_ = [("eps3d", ctypes.c_double), ("eps_aca", ctypes.c_double), ("eta", ctypes.c_double),
                 ("leaf", ctypes.c_int32), ("prec", ctypes.c_int32), ("mixed_eps_floor", ctypes.c_double),
-                ("pool_bytes", ctypes.c_int64), ("far_dense_max", ctypes.c_int32), ("aca_rounds", ctypes.c_int32)]
+                ("pool_bytes", ctypes.c_int64), ("far_dense_max", ctypes.c_int32), ("aca_rounds", ctypes.c_int32),
+                ("face_order", ctypes.c_int32)]
 
 
 class bem_stats(ctypes.Structure):
@@ -125,6 +128,7 @@ _SIGS = {
                                         ctypes.c_int32, ctypes.POINTER(bem_solve_opts),
                                         ctypes.POINTER(bem_solve_stats)]),
     "bem_apply_mf": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32]),
+    "bem_apply_linear_dl": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "bem_matrix_free": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bem_adjoint_v": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]),
     "bem_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -296,9 +300,9 @@ class Context:
         return Operator(self, h)
 
     def compress(self, op, eps3d=1e-6, eps_aca=0.0, eta=1.5, leaf=64, prec=PREC_F64, mixed_eps_floor=1e-5,
-                 pool_bytes=0, far_dense_max=48, aca_rounds=0):
+                 pool_bytes=0, far_dense_max=48, aca_rounds=0, face_order=0):
         o = bem_aca_opts(float(eps3d), float(eps_aca), float(eta), int(leaf), int(prec), float(mixed_eps_floor),
-                         int(pool_bytes), int(far_dense_max), int(aca_rounds))
+                         int(pool_bytes), int(far_dense_max), int(aca_rounds), int(face_order))
         h = ctypes.c_void_p()
         self._check(lib().bem_compress(self.h, int(op), ctypes.byref(o), ctypes.byref(h)))
         return Operator(self, h)
@@ -368,6 +372,24 @@ class Context:
         px, fl = _ptr(x, shp)
         py, _ = _ptr(y, shp)
         self._check(lib().bem_apply_mf(self.h, int(op), int(bool(transpose)), int(nrhs), px, py, fl))
+        return y
+
+    def apply_linear_dl(self, g, y=None, free_term=True):
+        """y[r, l] = (C +) K_lin(s_l) g[r, l]: the double layer against the nodal hat functions
+        (entries recomputed); g: [nrhs, L, 3 n_nodes] numpy or torch CUDA complex128, y:
+        [nrhs, L, 3K]."""
+        nrhs = g.shape[0]
+        shp_y = (nrhs, self.L, 3 * self.K)
+        if _is_torch(g):
+            import torch
+            if y is None:
+                y = torch.empty(shp_y, dtype=g.dtype, device=g.device)
+            self._sync_torch_stream()
+        elif y is None:
+            y = np.empty(shp_y, dtype=np.complex128)
+        pg, fl = _ptr(g, (nrhs, self.L, 3 * self.n_nodes))
+        py, _ = _ptr(y, shp_y)
+        self._check(lib().bem_apply_linear_dl(self.h, int(nrhs), pg, py, fl | (FREE_TERM if free_term else 0)))
         return y
 
     def adjoint_v(self, w, x):

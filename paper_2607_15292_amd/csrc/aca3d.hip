@@ -686,10 +686,52 @@ __device__ __forceinline__ void wargmax(double& v, int& idx)
 constexpr int ABORT_STEPS = 8;
 constexpr double ACA_ABORT = 1.5;
 
+// Growth of ||S||_F^2, S = U V^H, when the columns kc .. kc + 2 join the kc earlier ones:
+// 2 Re sum_{c < kc} sum_x (u_c^H u_x)(v_x^H v_c) + sum_{y, x} (u_y^H u_x)(v_x^H v_y) over the
+// new columns x, y (one wavefront).
+__device__ double aca_norm_growth(const AcaWork& w, int M3, int N3, int kc)
+{
+    double g = 0.0;
+    for (int c = 0; c < kc + 3; ++c) {
+        double a[12];
+#pragma unroll
+        for (int t = 0; t < 12; ++t) a[t] = 0.0;
+        const zd* uc = w.U + (size_t)c * M3;
+        for (int q = threadIdx.x; q < M3; q += WA) {
+            const zd u = uc[q];
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                const zd t = conj_mul(u, w.U[(size_t)(kc + x) * M3 + q]);
+                a[2 * x] += t.re;
+                a[2 * x + 1] += t.im;
+            }
+        }
+        const zd* vc = w.V + (size_t)c * N3;
+        for (int q = threadIdx.x; q < N3; q += WA) {
+            const zd v = vc[q];
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                const zd t = conj_mul(w.V[(size_t)(kc + x) * N3 + q], v);
+                a[6 + 2 * x] += t.re;
+                a[7 + 2 * x] += t.im;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 12; ++t) a[t] = wsum(a[t]);
+        double r = 0.0;
+#pragma unroll
+        for (int x = 0; x < 3; ++x) r += a[2 * x] * a[6 + 2 * x] - a[2 * x + 1] * a[7 + 2 * x];
+        g += (c < kc ? 2.0 : 1.0) * r;
+    }
+    return g;
+}
+
 template <typename T>
 __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, double amax, zd* pinv,
-                        zd* sk, int kc0, int irow0, bool resumable, double abort, int& built)
+                        zd* sk, int kc0, int irow0, bool resumable, double abort, int& built,
+                        double rel = 0.0)
 {
+    double s2n = 0.0;  // ||U V^H||_F^2 of the columns so far (rel > 0)
     double est0 = 0.0;
     const int lane = threadIdx.x;
     const int M3 = 3 * m, N3 = 3 * n;
@@ -757,7 +799,7 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
         }
         wargmax(best, bj);
         if (!(best > PIVOT_RTOL * amax)) {
-            if (sqrt(rn2) <= tol) return kc;  // negligible residual row
+            if (sqrt(rn2) <= fmax(tol, rel * sqrt(fmax(s2n, 0.0)))) return kc;  // negligible residual row
             ++skipped;
             if (++fails >= MAX_FAIL) return -1;
             int cand = 0x7fffffff;
@@ -823,10 +865,17 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
             }
         }
         un2 = wsum(un2);
+        double thr = tol;
+        if (rel > 0.0) {
+            // the stop of the ACA relative to the approximation so far (rel ||U V^H||_F)
+            __syncthreads();
+            s2n += aca_norm_growth(w, M3, N3, kc);
+            thr = fmax(tol, rel * sqrt(fmax(s2n, 0.0)));
+        }
         kc += 3;
         built = kc;
         const double est = sqrt(un2 * rn2);
-        if (est <= tol) return kc;
+        if (est <= thr) return kc;
         if (kc == 3) est0 = est;
         if (abort > 0.0 && kc >= 3 * ABORT_STEPS && est0 > 0.0) {
             const double rate = pow(est / est0, 3.0 / (kc - 3));  // per step
@@ -860,7 +909,7 @@ __device__ int face_aca(const cx<T>* H, int m, int n, const AcaWork& w, int cap,
 // returns the column count (-1: not resolved, or a zero face).  One wavefront.
 template <typename T>
 __device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, int cap, double tol, int kc0, int irow0,
-                              bool resumable, double abort, int& built)
+                              bool resumable, double abort, int& built, double rel = 0.0)
 {
     double s2 = 0.0, amax = 0.0;
     const int cnt = 9 * m * n;
@@ -874,7 +923,7 @@ __device__ int face_aca_stage(const cx<T>* H, int m, int n, const AcaWork& w, in
     __shared__ zd pinv[9];
     __shared__ zd sk[3 * KMAX_SLICE];
     if (cap > KMAX_SLICE) return -1;
-    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk, kc0, irow0, resumable, abort, built) : -1;
+    return s2 > 0.0 ? face_aca(H, m, n, w, cap, tol, amax, pinv, sk, kc0, irow0, resumable, abort, built, rel) : -1;
 }
 
 // Absolute tolerance of face d of block b: eps_aca ||C^(r)||_F / ||f_d||_F, so that each
@@ -904,6 +953,32 @@ __global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A, int resume)
     const int m = B.rs, n = B.cs;
     AcaWork w = aca_work(A.scratch + A.slot_off[blockIdx.x], m, n, A.kmax, ACA_HALVES);
     if (resume && w.info[0] != -3) return;
+    if (A.iloop) {
+        // a face of the current 3D-ACA step (Sec. 3.1 order): relative tolerance, no resume,
+        // no early end; blocks that ended at this step are left alone (state 0)
+        int kc = 0, built = 0;
+        if (A.st[b].active && f.kk == 0 && !f.sel) {
+            const int cap = min(A.kmax, face_aca_cap(m, n));
+            kc = f.fp32 ? face_aca_stage((const cx<float>*)(A.pool + f.face_off), m, n, w, cap, 0.0, 0, 0, false, 0.0,
+                                         built, A.eps_aca_far)
+                        : face_aca_stage((const cx<double>*)(A.pool + f.face_off), m, n, w, cap, 0.0, 0, 0, false, 0.0,
+                                         built, A.eps_aca_far);
+        }
+        if (threadIdx.x == 0) {
+            w.info[0] = kc;
+            w.info[3] = 0;
+            w.tol[0] = 0.0;
+            const double t1 = built / 3, mn = (double)(m + n);
+            if (t1 > 0) {
+                // as below, plus the norm growth: 3 (m + n) (3t + 3) complex multiply-adds per step
+                atomicAdd(&A.st[b].aca_flop, 8.0 * (13.5 * mn * t1 * (t1 - 1.0) + 27.0 * m * t1 +
+                                                    4.5 * mn * t1 * (t1 + 1.0) + 9.0 * mn * t1));
+                atomicAdd(&A.st[b].aca_bytes, 72.0 * mn * t1 * (t1 - 1.0) * 2.0 +
+                                                  t1 * (9.0 * mn * (f.fp32 ? 8.0 : 16.0) + 144.0 * mn));
+            }
+        }
+        return;
+    }
     int kc = -1, built = 0, kc0 = 0, irow0 = 0;
     double tol = 0.0;
     if (resume) {
@@ -942,6 +1017,165 @@ __global__ __launch_bounds__(WA) void k_face_aca(CompressArgs A, int resume)
             atomicAdd(&A.st[b].aca_bytes, bytes);
         }
     }
+}
+
+// ---------------------------------------------------------------- faces inside the loop
+
+// After k_face_recomp in the in-loop order: the factors of each listed face (slot state -5,
+// complex128 column-major in the slot's second half) move to the pool in the face's
+// precision, Ubar (3m x kk) then Vbar (3n x kk), row-major; fac_kk = 0 for a face that stays
+// exact.  One workgroup per listed face.
+__global__ __launch_bounds__(WG) void k_iloop_store(CompressArgs A)
+{
+    __shared__ long long off_s;
+    const int item = A.list[blockIdx.x];
+    const int b = item >> 8, d = item & 255;
+    const BlockIn B = A.blocks[b];
+    const int m = B.rs, n = B.cs;
+    const size_t fi = (size_t)b * A.L + d;
+    AcaWork w = aca_work(A.scratch + A.slot_off[blockIdx.x], m, n, A.kmax, ACA_HALVES);
+    const int state = w.info[0];
+    const int kk = w.info[1];
+    if (state != -5 || kk <= 0) {
+        if (threadIdx.x == 0) A.fac_kk[fi] = 0;
+        return;
+    }
+    const FaceDesc f = A.faces[fi];
+    if (threadIdx.x == 0) off_s = pool_alloc(A, (long long)(f.fp32 ? sizeof(zf) : sizeof(zd)) * 3 * (m + n) * kk);
+    __syncthreads();
+    const long long off = off_s;
+    if (off < 0) {  // pool exhausted (the error flag is set): the face stays exact
+        if (threadIdx.x == 0) A.fac_kk[fi] = 0;
+        return;
+    }
+    const zd* U2 = w.U2;
+    const zd* V2 = w.V2;
+    const int M3 = 3 * m, N3 = 3 * n;
+    for (int q = threadIdx.x; q < (M3 + N3) * kk; q += WG) {
+        const int r = q / kk, c = q - r * kk;
+        const zd v = r < M3 ? U2[(size_t)c * M3 + r] : V2[(size_t)c * N3 + (r - M3)];
+        if (f.fp32) stz((zf*)(A.pool + off) + q, v);
+        else ((zd*)(A.pool + off))[q] = v;
+    }
+    if (threadIdx.x == 0) {
+        A.fac_off[fi] = off;
+        A.fac_kk[fi] = kk;
+        atomicAdd((unsigned long long*)&A.st[b].aca_cols, (unsigned long long)w.info[2]);
+    }
+}
+
+// The pivot search of Sec. 3.1 on the reconstruction: for every pair (i, j) of an in-loop
+// face with factors, H[i,j] = Ubar[3i..3i+2] Vbar[3j..3j+2]^H from the stored factors is
+// written over the exact face (the later residuals, the fibre and the norm use it), and the
+// tile partials of k_pivot (sigma_3 argmax, ||H||_F^2, max block norm) are those of the
+// reconstruction.  Items (block << 12) | t for every face tile t of the block: tiles of
+// TILE consecutive pairs p = i n + j up to m n, the others neutral.
+__global__ __launch_bounds__(WG) void k_iloop_recon(CompressArgs A)
+{
+    __shared__ Red S;
+    const int item = A.list[blockIdx.x];
+    const int b = item >> 12, t = item & 4095;
+    if (!A.st[b].active) return;
+    const BlockIn B = A.blocks[b];
+    const int m = B.rs, n = B.cs, d = A.d;
+    const size_t fi = (size_t)b * A.L + d;
+    const int kk = A.fac_kk[fi];
+    if (kk <= 0) return;  // the exact face and its partials stand
+    const FaceDesc F = A.faces[fi];
+    const int p = t * TILE + threadIdx.x;
+    double s3 = -1.0, e2 = 0.0;
+    int pi = 0x7fffffff;
+    if (p < m * n) {
+        const int i = p / n, j = p - (p / n) * n;
+        blk H;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) H.a[q] = {0.0, 0.0};
+        const size_t ld = 3 * (size_t)n;
+        if (F.fp32) {
+            const zf* Ub = (const zf*)(A.pool + A.fac_off[fi]);
+            const zf* Vb = Ub + (size_t)3 * m * kk;
+            for (int r = 0; r < kk; ++r) {
+                zd u[3], v[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u[a] = ldz(Ub + (size_t)(3 * i + a) * kk + r);
+                    v[a] = ldz(Vb + (size_t)(3 * j + a) * kk + r);
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) H.a[3 * a + c] += mul_conj(u[a], v[c]);
+            }
+            zf* Hd = (zf*)(A.pool + F.face_off);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const zf wv = {(float)H.a[3 * a + c].re, (float)H.a[3 * a + c].im};
+                    Hd[(size_t)(3 * i + a) * ld + 3 * j + c] = wv;
+                    H.a[3 * a + c] = {(double)wv.re, (double)wv.im};  // search on the stored face
+                }
+        } else {
+            const zd* Ub = (const zd*)(A.pool + A.fac_off[fi]);
+            const zd* Vb = Ub + (size_t)3 * m * kk;
+            for (int r = 0; r < kk; ++r) {
+                zd u[3], v[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u[a] = Ub[(size_t)(3 * i + a) * kk + r];
+                    v[a] = Vb[(size_t)(3 * j + a) * kk + r];
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) H.a[3 * a + c] += mul_conj(u[a], v[c]);
+            }
+            zd* Hd = (zd*)(A.pool + F.face_off);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Hd[(size_t)(3 * i + a) * ld + 3 * j + c] = H.a[3 * a + c];
+        }
+        e2 = blk_fro2(H);
+        s3 = blk_sigma3(H);
+        pi = p;
+    }
+    double v[1] = {e2};
+    wg_sum<1>(v, S);
+    double fm = wg_max(e2, S);
+    wg_argmax(s3, pi, S);
+    if (threadIdx.x == 0) {
+        double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
+        tp[0] = s3;
+        tp[1] = (double)pi;
+        tp[2] = v[0];
+        tp[3] = fm;
+    }
+}
+
+// After the last step: the in-loop faces of a block (not a dense fallback) that kept factors
+// are stored as factors; their reconstructions are dropped by the compaction.
+__global__ __launch_bounds__(64) void k_iloop_finish(CompressArgs A)
+{
+    const int q = blockIdx.x * 64 + threadIdx.x;
+    if (q >= A.nlist) return;
+    const int b = A.list[q];
+    const BlockState s = A.st[b];
+    if (s.fallback) return;
+    int dense = 0;
+    for (int d = 0; d < s.rank; ++d) {
+        const size_t fi = (size_t)b * A.L + d;
+        FaceDesc f = A.faces[fi];
+        if (f.kk != 0 || f.sel) continue;
+        if (A.fac_kk[fi] > 0) {
+            f.face_off = A.fac_off[fi];
+            f.kk = A.fac_kk[fi];
+            A.faces[fi] = f;
+        } else {
+            ++dense;
+        }
+    }
+    A.st[b].aca_dense += dense;
 }
 
 // ---------------------------------------------------------------- pivot
@@ -1332,6 +1566,9 @@ size_t aca_scratch_doubles(int m, int n, int kmax, int halves)
     } while (0)
 
 void launch_init(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_init, (A.nblocks + 255) / 256, 256, A); }
+void launch_iloop_store(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_iloop_store, A.nlist, WG, A); }
+void launch_iloop_recon(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_iloop_recon, A.nlist, WG, A); }
+void launch_iloop_finish(const CompressArgs& A, hipStream_t st) { BEM_LAUNCH(k_iloop_finish, (A.nlist + 63) / 64, 64, A); }
 template <int PATH>
 void launch_face_dense_path(const CompressArgs& A, hipStream_t st)
 {

@@ -84,6 +84,10 @@ struct CompressArgs {
     int* err;
     double* scratch;
     const long long* slot_off;  // scratch slot of each list position (offset in doubles)
+    int iloop;              // faces of the ACA blocks approximated inside the 3D-ACA loop (Sec. 3.1)
+    long long* fac_off;     // [nblocks][L] in-loop faces: pool offset of their factors
+    int* fac_kk;            // [nblocks][L] their rank (0: the face stays exact and dense)
+    const long long* blk_slot;  // in-loop pass: scratch slot of each block (offset in doubles), -1 none
     int* pending;           // faces left at slot state -3 by a recompression launch (counter)
     int aca_rounds;         // resume launches allowed after intermediate recompressions (0: none)
     const int* pairs;       // pair orders of the blocks with pair0 >= 0
@@ -186,6 +190,13 @@ void launch_fallback_faces(const CompressArgs& A, int kf, hipStream_t st);
 // intermediate recompression (slot state -3)
 void launch_face_aca(const CompressArgs& A, hipStream_t st, int resume = 0);
 void launch_face_recomp(const CompressArgs& A, hipStream_t st);
+// faces inside the 3D-ACA loop (Sec. 3.1): after k_face_aca + k_face_recomp of the step's faces
+// (iloop = 1), move the factors to the pool (list: faces (block << 8) | d), reconstruct the
+// faces and their pivot partials (list: tiles (block << 12) | t), and after the last step store
+// the faces as factors (list: blocks)
+void launch_iloop_store(const CompressArgs& A, hipStream_t st);
+void launch_iloop_recon(const CompressArgs& A, hipStream_t st);
+void launch_iloop_finish(const CompressArgs& A, hipStream_t st);
 void launch_copy_segments(const char* src, char* dst, const long long* seg, int nseg, hipStream_t st);
 void launch_aca_matrix(char* H, int m, int n, int fp32, double tol, int cap, int kmax, double* scratch, int* out,
                        hipStream_t st);

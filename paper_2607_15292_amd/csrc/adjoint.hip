@@ -70,6 +70,53 @@ __global__ __launch_bounds__(WG) void k_mf_apply(DevCtx c, int op, int nrhs, con
     }
 }
 
+// y[r][l][3 e + a] = sum_j sum_v (KL_v(e, j, l) g[r][l][node(j, v)])_a, plus the free term
+// 1/2 * 1/3 sum_v g[r][l][node(e, v)]; thread per (e, l), e fastest; right-hand sides in
+// passes of NR.  The three vertex weights of a pair share its kernel evaluations.
+__global__ __launch_bounds__(WG) void k_mf_apply_kl(DevCtx c, const int* __restrict__ tri, int nnodes, int nrhs,
+                                                    const zd* __restrict__ g, zd* __restrict__ y, int free_term)
+{
+    const int K = c.geo.K, L = c.fr.L;
+    const int e = blockIdx.x * WG + threadIdx.x, l = blockIdx.y;
+    if (e >= K) return;
+    const size_t M = 3 * (size_t)K, N = 3 * (size_t)nnodes;
+    for (int r0 = 0; r0 < nrhs; r0 += NR) {
+        const int nr = min(NR, nrhs - r0);
+        zd acc[NR][3];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[rr][a] = {0.0, 0.0};
+        for (int o = 0; o < K; ++o) {
+            blk E[3];
+            entry_kl3(c.geo, e, o, c.fr.s[l], c.fr.sinv[l], c.md, c.qt, E);
+            for (int v = 0; v < 3; ++v) {
+                const int nd = tri[3 * o + v];
+#pragma unroll
+                for (int rr = 0; rr < NR; ++rr) {
+                    if (rr >= nr) break;
+                    const zd* gv = g + ((size_t)(r0 + rr) * L + l) * N + 3 * (size_t)nd;
+                    const zd u[3] = {gv[0], gv[1], gv[2]};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) acc[rr][a] = fma_c(E[v].a[3 * a + b], u[b], acc[rr][a]);
+                }
+            }
+        }
+        for (int rr = 0; rr < nr; ++rr) {
+            if (free_term)
+                for (int v = 0; v < 3; ++v) {
+                    const zd* gv = g + ((size_t)(r0 + rr) * L + l) * N + 3 * (size_t)tri[3 * e + v];
+                    for (int a = 0; a < 3; ++a) acc[rr][a] += gv[a] * (0.5 / 3.0);
+                }
+            zd* yv = y + ((size_t)(r0 + rr) * L + l) * M + 3 * (size_t)e;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) yv[a] = acc[rr][a];
+        }
+    }
+}
+
 // A, B, dA/dR, dB/dR and the speed derivatives of A and B at distance R.
 __device__ __forceinline__ void kernel_adj(double R, double Rinv, zd s, zd sinv, const Mat<double>& M, zd& A, zd& B,
                                            zd& Ad, zd& Bd, zd& A1, zd& A2, zd& B1, zd& B2)
@@ -320,6 +367,16 @@ void launch_mf_apply(const DevCtx& c, int op, bool transpose, int nrhs, const zd
     const dim3 grid((unsigned)((c.geo.K + WG - 1) / WG), (unsigned)c.fr.L);
     if (transpose) hipLaunchKernelGGL(k_mf_apply<true>, grid, dim3(WG), 0, st, c, op, nrhs, x, y);
     else hipLaunchKernelGGL(k_mf_apply<false>, grid, dim3(WG), 0, st, c, op, nrhs, x, y);
+    BEM_HIP_TRY(hipGetLastError());
+}
+
+void launch_mf_apply_kl(const DevCtx& c, const int* tri, int nnodes, int nrhs, const zd* g, zd* y, bool free_term,
+                        hipStream_t st)
+{
+    const int K = c.geo.K;
+    if (K <= 0 || nrhs <= 0) return;
+    hipLaunchKernelGGL(k_mf_apply_kl, dim3((K + WG - 1) / WG, c.fr.L), dim3(WG), 0, st, c, tri, nnodes, nrhs, g, y,
+                       free_term ? 1 : 0);
     BEM_HIP_TRY(hipGetLastError());
 }
 

@@ -396,6 +396,7 @@ int bem_set_mesh(bem_ctx* ctx, const double* nodes, int64_t n_nodes, const int32
         }
         ctx->nodes.assign(nodes, nodes + 3 * n_nodes);
         ctx->tris.assign(tris, tris + 3 * K);
+        ctx->tris_dev.release();  // re-uploaded on first use
         ctx->hgeo = std::move(g);  // one component until bem_set_components
         if (ctx->device >= 0) {
             need_device(ctx);
@@ -530,8 +531,9 @@ int bem_entries(bem_ctx* ctx, int32_t op, int32_t prec, int64_t n, const int32_t
 {
     if (!ctx) return BEM_ERR_ARG;
     return guarded(ctx, [&]() -> int {
-        if (op < 0 || op > 3 || (prec != BEM_PREC_F64 && prec != BEM_PREC_MIXED) || n < 0)
+        if (op < 0 || op > BEM_OP_KL2 || (prec != BEM_PREC_F64 && prec != BEM_PREC_MIXED) || n < 0)
             throw api_error(BEM_ERR_ARG, "bad op, prec or n");
+        if (op >= BEM_OP_KL0 && prec != BEM_PREC_F64) throw api_error(BEM_ERR_ARG, "linear-basis entries are FP64");
         need_state(ctx);
         need_device(ctx);
         if (op == BEM_OP_TABLE && !ctx->table) throw api_error(BEM_ERR_STATE, "no entry table set");
@@ -647,11 +649,11 @@ int bem_compress(bem_ctx* ctx, int32_t op, const bem_aca_opts* opts, bem_op** ou
         need_state(ctx);
         need_device(ctx);
         if (op == BEM_OP_TABLE && !ctx->table) throw api_error(BEM_ERR_STATE, "no entry table set");
-        bem_aca_opts o{1e-6, 0.0, 1.5, 64, BEM_PREC_F64, 1e-5, 0, 48, 0};
+        bem_aca_opts o{1e-6, 0.0, 1.5, 64, BEM_PREC_F64, 1e-5, 0, 48, 0, BEM_FACES_AFTER};
         if (opts) o = *opts;
         if (!(o.eps3d > 0 && o.eps3d < 1) || !(o.eta > 0) || o.leaf < 1 ||
             (o.prec != BEM_PREC_F64 && o.prec != BEM_PREC_MIXED) || o.pool_bytes < 0 || o.far_dense_max < 0 ||
-            o.aca_rounds < 0 || o.aca_rounds > 64)
+            o.aca_rounds < 0 || o.aca_rounds > 64 || (o.face_order != BEM_FACES_AFTER && o.face_order != BEM_FACES_IN_LOOP))
             throw api_error(BEM_ERR_ARG, "bad compression options");
         if (!(o.eps_aca > 0)) o.eps_aca = o.eps3d / 100.0;
         if (!(o.mixed_eps_floor > 0)) o.mixed_eps_floor = 1e-5;
@@ -1026,6 +1028,36 @@ int bem_apply_mf(bem_ctx* ctx, int32_t op, int32_t transpose, int32_t nrhs, cons
         launch_mf_apply(ctx->devctx(ctx->dgeo.geo, nullptr), op, transpose != 0, nrhs, (const zd*)sx.dev, (zd*)sy.dev,
                         st);
         finish_out(sy, y, bytes, dev, st);
+        return BEM_OK;
+    });
+}
+
+int bem_apply_linear_dl(bem_ctx* ctx, int32_t nrhs, const void* g, void* y, int32_t flags)
+{
+    if (!ctx) return BEM_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        need_state(ctx);
+        if (nrhs < 1 || !g || !y) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
+        if (flags & ~(BEM_DEVICE_PTR | BEM_FREE_TERM)) throw api_error(BEM_ERR_ARG, "unknown flags for bem_apply_linear_dl");
+        need_device(ctx);
+        need_one_component(ctx);
+        const bool dev = (flags & BEM_DEVICE_PTR) != 0;
+        const int K = ctx->hgeo.K;
+        const int64_t nn = (int64_t)ctx->nodes.size() / 3;
+        const size_t gb = (size_t)nrhs * ctx->freq.L * 3 * (size_t)nn * sizeof(zd);
+        const size_t yb = (size_t)nrhs * ctx->freq.L * 3 * (size_t)K * sizeof(zd);
+        hipStream_t st = ctx->stream;
+        if (!ctx->tris_dev.p) {
+            ctx->tris_dev.alloc(sizeof(int32_t) * 3 * (size_t)K);
+            BEM_HIP_TRY(hipMemcpyAsync(ctx->tris_dev.p, ctx->tris.data(), sizeof(int32_t) * 3 * (size_t)K,
+                                       hipMemcpyHostToDevice, st));
+        }
+        Staged sg, sy;
+        stage_in(sg, g, gb, dev, st);
+        stage_out(sy, y, yb, dev);
+        launch_mf_apply_kl(ctx->devctx(ctx->dgeo.geo, nullptr), ctx->tris_dev.as<int>(), (int)nn, nrhs,
+                           (const zd*)sg.dev, (zd*)sy.dev, (flags & BEM_FREE_TERM) != 0, st);
+        finish_out(sy, y, yb, dev, st);
         return BEM_OK;
     });
 }

@@ -528,6 +528,17 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     fda_dev.alloc(sizeof(zd) * 9 * (size_t)nb * L);
     tp_dev.alloc(sizeof(double) * 8 * (size_t)ntiles);
     list_dev.alloc(sizeof(int) * std::max<size_t>(3 * (size_t)ntiles + 2 * (size_t)nb + 64, (size_t)n_aca * L + 64));
+    // faces inside the loop (Sec. 3.1 order): the factors of each face, a work list of faces,
+    // tiles and scratch slots, and one scratch slot per ACA block of a launch chunk
+    const bool iloop = o.face_order == BEM_FACES_IN_LOOP && n_aca > 0;
+    DevBuf facoff_dev, fackk_dev, il_list_dev, il_slot_dev;
+    if (iloop) {
+        facoff_dev.alloc(sizeof(long long) * (size_t)nb * L);
+        fackk_dev.alloc(sizeof(int) * (size_t)nb * L);
+        BEM_HIP_TRY(hipMemsetAsync(fackk_dev.p, 0, sizeof(int) * (size_t)nb * L, st));
+        il_list_dev.alloc(sizeof(int) * ((size_t)n_aca + (size_t)ntiles + 64));
+        il_slot_dev.alloc(sizeof(long long) * ((size_t)n_aca + 64));
+    }
     // pool of faces and fibres: sized for POOL_STEPS0 steps of every block (or by the caller)
     // and grown between steps, by a copy of its used part, when the allocations of the next
     // step might not fit
@@ -535,7 +546,8 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         const BlockIn& B = C->blocks[b];
         const size_t zs = B.f32 ? sizeof(zf) : sizeof(zd);
         const size_t fb = (zs * 9 * (size_t)B.rs * B.cs + 15) & ~(size_t)15;
-        return (fb + sizeof(zd) * 9 * (size_t)L + 255) & ~(size_t)255;
+        const size_t fac = iloop && B.aca ? fb + 256 : 0;  // the factors of an in-loop face
+        return (fb + sizeof(zd) * 9 * (size_t)L + 255 + fac) & ~(size_t)255;
     };
     auto avail = [&]() {
         size_t fr = 0, tot = 0;
@@ -608,6 +620,10 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     A.aca_rounds = o.aca_rounds;
     A.scratch = nullptr;
     A.slot_off = nullptr;
+    A.iloop = 0;
+    A.fac_off = iloop ? facoff_dev.as<long long>() : nullptr;
+    A.fac_kk = iloop ? fackk_dev.as<int>() : nullptr;
+    A.blk_slot = nullptr;
     A.pairs = pairs_dev.as<int>();
     A.eps3d = o.eps3d;
     A.eps3d_far = C->mixed ? std::max(o.eps3d, o.mixed_eps_floor) : o.eps3d;
@@ -673,6 +689,28 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     }
     launch_init(A, st);
     A.sel = nullptr;
+    // in-loop order: scratch slots for the ACA blocks of this group, in chunks of at most
+    // ACA_SLOTS faces and the scratch buffer
+    auto il_slot_doubles = [&](int b) {
+        const BlockIn& Bi = C->blocks[b];
+        return (aca_scratch_doubles(Bi.rs, Bi.cs, kmax, ACA_HALVES) + 31) & ~(size_t)31;
+    };
+    DevBuf il_scratch(&ctx->cache);
+    if (iloop) {
+        size_t all = 0, big = 0;
+        for (int b : grp)
+            if (C->blocks[b].aca) {
+                all += il_slot_doubles(b);
+                big = std::max(big, il_slot_doubles(b));
+            }
+        size_t fr = 0, tot = 0;
+        BEM_HIP_TRY(hipMemGetInfo(&fr, &tot));
+        const size_t budget = std::min<size_t>(ACA_SCRATCH_BYTES, (size_t)(0.25 * (double)(fr + ctx->cache.cached)));
+        if (all) il_scratch.alloc(std::max(big * sizeof(double), std::min(all * sizeof(double), budget)));
+    }
+    std::vector<int> il_items, il_tiles, il_n0, il_t0;
+    std::vector<long long> il_soff;
+    std::vector<hipEvent_t> il_ev;
     // phase A: 3D-ACA of every block on dense residual faces, one step d per pass; the
     // face kernels of each step are bracketed by events (read after the next sync)
     bool face_pending = false;
@@ -751,6 +789,68 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         A.list = p_act;
         A.nlist = (int)act.size();
         if (d > 0) launch_final_prev(A, st);  // trace-form terms of step d - 1 came with the faces
+        if (iloop) {
+            // Sec. 3.1 order: the residual faces of this step's ACA blocks are approximated by
+            // the ACA + recompression, and the pivot below is searched on the reconstruction
+            il_items.clear();
+            il_tiles.clear();
+            il_soff.clear();
+            il_n0.clear();
+            il_t0.clear();
+            size_t bytes = 0;
+            for (int b : act) {
+                const BlockIn& Bi = C->blocks[b];
+                if (!Bi.aca) continue;
+                const size_t sz = il_slot_doubles(b);
+                if (il_n0.empty() || il_items.size() - (size_t)il_n0.back() >= ACA_SLOTS ||
+                    (bytes + sz) * sizeof(double) > il_scratch.bytes) {
+                    il_n0.push_back((int)il_items.size());
+                    il_t0.push_back((int)il_tiles.size());
+                    bytes = 0;
+                }
+                il_soff.push_back((long long)bytes);
+                bytes += sz;
+                il_items.push_back((b << 8) | d);
+                for (int t = 0; t < Bi.ntile; ++t) il_tiles.push_back((b << 12) | t);
+            }
+            il_n0.push_back((int)il_items.size());
+            il_t0.push_back((int)il_tiles.size());
+            if (!il_items.empty()) {
+                const int* p_items = put_list(il_list_dev, 0, il_items, st);
+                const int* p_itiles = put_list(il_list_dev, il_items.size(), il_tiles, st);
+                BEM_HIP_TRY(hipMemcpyAsync(il_slot_dev.p, il_soff.data(), il_soff.size() * sizeof(long long),
+                                           hipMemcpyHostToDevice, st));
+                A.scratch = il_scratch.as<double>();
+                A.iloop = 1;
+                for (size_t ci = 0; ci + 1 < il_n0.size(); ++ci) {
+                    hipEvent_t e[4];
+                    for (hipEvent_t& ev : e) {
+                        BEM_HIP_TRY(hipEventCreate(&ev));
+                        il_ev.push_back(ev);
+                    }
+                    A.list = p_items + il_n0[ci];
+                    A.nlist = il_n0[ci + 1] - il_n0[ci];
+                    A.slot_off = il_slot_dev.as<long long>() + il_n0[ci];
+                    BEM_HIP_TRY(hipEventRecord(e[0], st));
+                    launch_face_aca(A, st, 0);
+                    BEM_HIP_TRY(hipEventRecord(e[1], st));
+                    launch_face_recomp(A, st);
+                    BEM_HIP_TRY(hipEventRecord(e[2], st));
+                    launch_iloop_store(A, st);
+                    A.list = p_itiles + il_t0[ci];
+                    A.nlist = il_t0[ci + 1] - il_t0[ci];
+                    launch_iloop_recon(A, st);
+                    BEM_HIP_TRY(hipEventRecord(e[3], st));
+                    ++aca_launches;
+                    ++recomp_launches;
+                }
+                A.iloop = 0;
+                A.scratch = nullptr;
+                A.slot_off = nullptr;
+                A.list = p_act;
+                A.nlist = (int)act.size();
+            }
+        }
         launch_pivot(A, st);
         launch_fibre(A, st);
         launch_advance(A, st);
@@ -790,7 +890,29 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
             launch_fallback_faces(A, kf, st);
         }
     }
+    if (iloop) {
+        // the faces kept as factors replace their reconstructions
+        std::vector<int> ab;
+        for (int b : grp)
+            if (C->blocks[b].aca) ab.push_back(b);
+        if (!ab.empty()) {
+            A.list = put_list(il_list_dev, 0, ab, st);
+            A.nlist = (int)ab.size();
+            launch_iloop_finish(A, st);
+        }
+    }
     BEM_HIP_TRY(hipStreamSynchronize(st));
+    for (size_t e = 0; e < il_ev.size(); e += 4) {
+        float ms = 0.f;
+        BEM_HIP_TRY(hipEventElapsedTime(&ms, il_ev[e], il_ev[e + 1]));
+        aca_kernel_ms += ms;
+        BEM_HIP_TRY(hipEventElapsedTime(&ms, il_ev[e + 1], il_ev[e + 2]));
+        recomp_ms += ms;
+        BEM_HIP_TRY(hipEventElapsedTime(&ms, il_ev[e], il_ev[e + 3]));
+        aca_ms += ms;
+    }
+    for (hipEvent_t e : il_ev) (void)hipEventDestroy(e);
+    il_ev.clear();
     BEM_HIP_TRY(hipMemcpy(&err, err_dev, sizeof(int), hipMemcpyDeviceToHost));
     if (err & 2) {
         (void)hipEventDestroy(ev0);
@@ -804,7 +926,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
     // phase B: per-slice ACA + recompression of the far faces of the ACA blocks, in place
     std::vector<int> items;
     for (int b : grp)
-        if (C->blocks[b].aca && !S[b].fallback)
+        if (C->blocks[b].aca && !S[b].fallback && !iloop)
             for (int d = 0; d < S[b].rank; ++d) items.push_back((b << 8) | d);
     // largest faces first: the long workgroups start early instead of forming the tail
     std::stable_sort(items.begin(), items.end(), [&](int x, int y) {

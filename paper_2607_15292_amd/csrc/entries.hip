@@ -21,12 +21,34 @@ __global__ __launch_bounds__(256) void k_entries(DevCtx c, int op, int64_t n, co
     for (int t = 0; t < 9; ++t) o[t] = b.a[t];
 }
 
+// ENTRY of the double layer weighted by the hat function of vertex op - OP_KL0 of element j
+// (linear basis, FP64 rules)
+__global__ __launch_bounds__(256) void k_entries_kl(DevCtx c, int op, int64_t n, const int32_t* __restrict__ ii,
+                                                    const int32_t* __restrict__ jj, const int32_t* __restrict__ ll,
+                                                    zd* __restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int i = ii[e], j = jj[e], l = ll[e];
+    zd* o = out + e * 9;
+    if (i < 0 || i >= c.geo.K || j < 0 || j >= c.geo.K || l < 0 || l >= c.fr.L) {
+        for (int t = 0; t < 9; ++t) o[t] = {__builtin_nan(""), __builtin_nan("")};
+        return;
+    }
+    blk b[3];
+    entry_kl3(c.geo, i, j, c.fr.s[l], c.fr.sinv[l], c.md, c.qt, b);
+    const int v = op - OP_KL0;
+    for (int t = 0; t < 9; ++t) o[t] = b[v].a[t];
+}
+
 void launch_entries(const DevCtx& c, int op, int mixed, int64_t n, const int32_t* i, const int32_t* j,
                     const int32_t* l, zd* out, hipStream_t st)
 {
     if (n <= 0) return;
     dim3 grid((unsigned)((n + 255) / 256));
-    if (mixed)
+    if (op >= OP_KL0)
+        hipLaunchKernelGGL(k_entries_kl, grid, dim3(256), 0, st, c, op, n, i, j, l, out);
+    else if (mixed)
         hipLaunchKernelGGL(k_entries<true>, grid, dim3(256), 0, st, c, op, n, i, j, l, out);
     else
         hipLaunchKernelGGL(k_entries<false>, grid, dim3(256), 0, st, c, op, n, i, j, l, out);

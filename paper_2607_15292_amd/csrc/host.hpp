@@ -186,6 +186,7 @@ struct bem_ctx {
     bool mesh_set = false;
     std::vector<double> nodes;
     std::vector<int32_t> tris;
+    bem::DevBuf tris_dev;  // tris on the device (linear basis), uploaded on first use
     bem::HostGeo hgeo;
     bem::DevGeo dgeo;
     // material

@@ -248,17 +248,32 @@ struct AccK {
     }
     BEM_HD void add(T rx, T ry, T rz, T nx, T ny, T nz, T w, cx<T> s, cx<T> sinv, const Mat<T>& M)
     {
+        T h[3], rn;
+        cx<T> P1, P2, P3;
+        eval(rx, ry, rz, nx, ny, nz, s, sinv, M, h, rn, P1, P2, P3);
+        accum(h, rn, P1, P2, P3, w);
+    }
+    // the traction kernel's scalars at r = y - x: rh, dr/dn and P1, P2, P3 (4 pi T =
+    // P1 rh_i n_j + P2 (d_ij dr/dn + rh_j n_i) + P3 rh_i rh_j dr/dn)
+    BEM_HD static void eval(T rx, T ry, T rz, T nx, T ny, T nz, cx<T> s, cx<T> sinv, const Mat<T>& M, T h[3], T& rn,
+                            cx<T>& P1, cx<T>& P2, cx<T>& P3)
+    {
         T r2 = rx * rx + ry * ry + rz * rz;
         T rinv = M_<T>::rsq(r2);
         T r = r2 * rinv;
         cx<T> a, b, ad, bd;
         kernel_AB<T, true>(r, rinv, s, sinv, M, a, b, ad, bd);
-        T h[3] = {rx * rinv, ry * rinv, rz * rinv};
-        T rn = h[0] * nx + h[1] * ny + h[2] * nz;
+        h[0] = rx * rinv;
+        h[1] = ry * rinv;
+        h[2] = rz * rinv;
+        rn = h[0] * nx + h[1] * ny + h[2] * nz;
         cx<T> br = b * rinv;
-        cx<T> P1 = M.lamc * (ad + bd + (T)2 * br) + ((T)2 * M.c2s) * br;
-        cx<T> P2 = M.c2s * (ad + br);
-        cx<T> P3 = ((T)2 * M.c2s) * (bd - (T)2 * br);
+        P1 = M.lamc * (ad + bd + (T)2 * br) + ((T)2 * M.c2s) * br;
+        P2 = M.c2s * (ad + br);
+        P3 = ((T)2 * M.c2s) * (bd - (T)2 * br);
+    }
+    BEM_HD void accum(const T h[3], T rn, cx<T> P1, cx<T> P2, cx<T> P3, T w)
+    {
         cx<T> wP1 = w * P1, wP2 = w * P2, wP3 = (w * rn) * P3;
         for (int t = 0; t < 3; ++t) {
             a1[t] += wP1 * h[t];
@@ -490,6 +505,131 @@ BEM_HD void entry_self(const Geo& g, int op, int j, zd s, zd sinv, const Mat<dou
         if (op == 0) self_unit<0>(g, j, u, s, sinv, M, Q, e);
         else self_unit<1>(g, j, u, s, sinv, M, Q, e);
         for (int t = 0; t < 9; ++t) out.a[t] += e.a[t];
+    }
+}
+
+// ---------------------------------------------------------------- double layer, linear basis
+
+// Barycentric coordinate of vertex v of element j at a point y of its plane (the hat function
+// of eqs. (subspace), (basis) of the vertex's node restricted to the element):
+// lambda_v(y) = n . ((P_{v+1} - y) x (P_{v+2} - y)) / (2 A).
+BEM_HD double bary_at(const Geo& g, int j, int v, const double y[3])
+{
+    const int K = g.K, a = (v + 1) % 3, b = (v + 2) % 3;
+    const double p[3] = {g.vx[a * K + j] - y[0], g.vy[a * K + j] - y[1], g.vz[a * K + j] - y[2]};
+    const double q[3] = {g.vx[b * K + j] - y[0], g.vy[b * K + j] - y[1], g.vz[b * K + j] - y[2]};
+    const double cr[3] = {p[1] * q[2] - p[2] * q[1], p[2] * q[0] - p[0] * q[2], p[0] * q[1] - p[1] * q[0]};
+    return (g.nx[j] * cr[0] + g.ny[j] * cr[1] + g.nz[j] * cr[2]) / (2.0 * g.area[j]);
+}
+
+// The double layer of pair (i, j) against the three hat functions of element j's vertices:
+// out[v] = int_{gamma_j} T(x_i, y) lambda_v(y) dy, each kernel evaluation shared by the three
+// weights, with the rule of the pair's class (FP64).  Self pair: the principal value of the
+// leading part g(theta) / rho^2 is taken with the weight lambda_v(x_i) = 1/3; the remainder
+// T (lambda_v(y) - 1/3) is weakly singular and integrated by the polar rule.
+BEM_HD void entry_kl3(const Geo& g, int i, int j, zd s, zd sinv, const Mat<double>& M, const QuadTab& Q, blk out[3])
+{
+    const int K = g.K;
+    const int cls = pair_class(g, i, j, Q);
+    const double x[3] = {g.cx[i], g.cy[i], g.cz[i]};
+    const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+    AccK<double> acc[3];
+    for (int v = 0; v < 3; ++v) acc[v].zero();
+    auto point = [&](const double y[3], double w, const double lw[3]) {
+        double h[3], rn;
+        zd P1, P2, P3;
+        AccK<double>::eval(y[0] - x[0], y[1] - x[1], y[2] - x[2], n[0], n[1], n[2], s, sinv, M, h, rn, P1, P2, P3);
+        for (int v = 0; v < 3; ++v) acc[v].accum(h, rn, P1, P2, P3, w * lw[v]);
+    };
+    for (int v = 0; v < 3; ++v) out[v] = blk_zero();
+    if (cls == CLS_REGULAR) {
+        for (int q = 0; q < 7; ++q) {
+            const int o = q * K + j;
+            const double y[3] = {g.gx[o], g.gy[o], g.gz[o]};
+            const double lw[3] = {Q.b7[3 * q], Q.b7[3 * q + 1], Q.b7[3 * q + 2]};
+            point(y, g.gw[o], lw);
+        }
+    } else if (cls != CLS_SELF) {
+        const int m = cls, nu = 1 << (2 * m);
+        const double wA = g.area[j] / (double)nu;
+        for (int u = 0; u < nu; ++u) {
+            double P[3][3];
+            for (int a = 0; a < 3; ++a) {
+                P[a][0] = g.vx[a * K + j];
+                P[a][1] = g.vy[a * K + j];
+                P[a][2] = g.vz[a * K + j];
+            }
+            for (int lev = m - 1; lev >= 0; --lev) {
+                const int c = (u >> (2 * lev)) & 3;
+                double m01[3], m12[3], m20[3];
+                for (int k = 0; k < 3; ++k) {
+                    m01[k] = 0.5 * (P[0][k] + P[1][k]);
+                    m12[k] = 0.5 * (P[1][k] + P[2][k]);
+                    m20[k] = 0.5 * (P[2][k] + P[0][k]);
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double p0 = P[0][k], p1 = P[1][k], p2 = P[2][k];
+                    if (c == 0) { P[0][k] = p0;     P[1][k] = m01[k]; P[2][k] = m20[k]; }
+                    else if (c == 1) { P[0][k] = m01[k]; P[1][k] = p1;     P[2][k] = m12[k]; }
+                    else if (c == 2) { P[0][k] = m20[k]; P[1][k] = m12[k]; P[2][k] = p2; }
+                    else { P[0][k] = m01[k]; P[1][k] = m12[k]; P[2][k] = m20[k]; }
+                }
+            }
+            for (int q = 0; q < 7; ++q) {
+                const double b0 = Q.b7[3 * q], b1 = Q.b7[3 * q + 1], b2 = Q.b7[3 * q + 2];
+                double y[3];
+                for (int k = 0; k < 3; ++k) y[k] = b0 * P[0][k] + b1 * P[1][k] + b2 * P[2][k];
+                const double lw[3] = {bary_at(g, j, 0, y), bary_at(g, j, 1, y), bary_at(g, j, 2, y)};
+                point(y, Q.w7[q] * wA, lw);
+            }
+        }
+    } else {
+        const double lx[3] = {bary_at(g, j, 0, x), bary_at(g, j, 1, x), bary_at(g, j, 2, x)};
+        for (int a = 0; a < 3; ++a) {
+            const int b = (a + 1) % 3;
+            const double va[3] = {g.vx[a * K + j], g.vy[a * K + j], g.vz[a * K + j]};
+            const double vb[3] = {g.vx[b * K + j], g.vy[b * K + j], g.vz[b * K + j]};
+            double t[3] = {vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]};
+            const double le = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+            for (int k = 0; k < 3; ++k) t[k] /= le;
+            const double proj = (x[0] - va[0]) * t[0] + (x[1] - va[1]) * t[1] + (x[2] - va[2]) * t[2];
+            double foot[3], p[3];
+            for (int k = 0; k < 3; ++k) {
+                foot[k] = va[k] + proj * t[k];
+                p[k] = foot[k] - x[k];
+            }
+            const double d = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+            for (int k = 0; k < 3; ++k) p[k] /= d;
+            const double sa = (va[0] - foot[0]) * t[0] + (va[1] - foot[1]) * t[1] + (va[2] - foot[2]) * t[2];
+            const double sb = (vb[0] - foot[0]) * t[0] + (vb[1] - foot[1]) * t[1] + (vb[2] - foot[2]) * t[2];
+            const double ta = atan2(sa, d), tb = atan2(sb, d);
+            const double hth = 0.5 * (tb - ta), mth = 0.5 * (ta + tb);
+            for (int it = 0; it < Q.nt; ++it) {
+                const double th = mth + hth * Q.tx[it];
+                const double wth = hth * Q.tw[it];
+                double sn, cs;
+                sincos(th, &sn, &cs);
+                const double R = d / cs;
+                const double dir[3] = {cs * p[0] + sn * t[0], cs * p[1] + sn * t[1], cs * p[2] + sn * t[2]};
+                for (int ir = 0; ir < Q.nr; ++ir) {
+                    const double rho = 0.5 * R * (1.0 + Q.rx[ir]);
+                    const double y[3] = {x[0] + rho * dir[0], x[1] + rho * dir[1], x[2] + rho * dir[2]};
+                    const double lw[3] = {bary_at(g, j, 0, y), bary_at(g, j, 1, y), bary_at(g, j, 2, y)};
+                    point(y, wth * (0.5 * R * Q.rw[ir]) * rho, lw);
+                }
+                const double c = wth * (log(R) - Q.crho);
+                for (int ii = 0; ii < 3; ++ii)
+                    for (int jj = 0; jj < 3; ++jj) {
+                        const double gv = M.gcoef * c * (dir[ii] * n[jj] - dir[jj] * n[ii]);
+                        for (int v = 0; v < 3; ++v) out[v].a[3 * ii + jj].re += lx[v] * gv;
+                    }
+            }
+        }
+    }
+    for (int v = 0; v < 3; ++v) {
+        blk e;
+        acc[v].store(e, n[0], n[1], n[2], M.inv4pi);
+        for (int q = 0; q < 9; ++q) out[v].a[q] += e.a[q];
     }
 }
 

@@ -5,7 +5,7 @@
 
 namespace bem {
 
-enum { OP_V = 0, OP_K = 1, OP_HK = 2, OP_TABLE = 3 };
+enum { OP_V = 0, OP_K = 1, OP_HK = 2, OP_TABLE = 3, OP_KL0 = 4 };  // OP_KL0 + v: linear basis, vertex v
 
 // Everything an entry evaluation needs, passed by value to kernels.
 struct DevCtx {
@@ -65,6 +65,11 @@ void launch_dense_apply_t(const zd* A, int M, int L, int nrhs, const zd* x, zd* 
 // y = A(s_l) x (transpose: A(s_l)^T x) for every l with entries recomputed; mesh order
 // [nrhs][L][3K]
 void launch_mf_apply(const DevCtx& c, int op, bool transpose, int nrhs, const zd* x, zd* y, hipStream_t st);
+// y[r][l] = (C + K_lin(s_l)) g[r][l] (free_term) or K_lin(s_l) g[r][l]: the double layer against
+// the nodal hat functions, entries recomputed; g [nrhs][L][3 N] by node, y [nrhs][L][3K] by
+// element (mesh order); tri [K][3] node indices
+void launch_mf_apply_kl(const DevCtx& c, const int* tri, int nnodes, int nrhs, const zd* g, zd* y, bool free_term,
+                        hipStream_t st);
 size_t adjoint_work_doubles(int K);
 void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double h_rel, const Mat<double>& Mp1,
                       const Mat<double>& Mm1, double h1, const Mat<double>& Mp2, const Mat<double>& Mm2, double h2,

@@ -639,13 +639,18 @@ static __device__ double recomp_flops(int stage, int m, int n, int kc, int kq, i
     return f;
 }
 
-// CM (the intermediate recompression of a run that reached the column capacity): the factors
-// go to the slot's other column half (w.U2, w.V2) in complex128 column-major, at most KF_RESUME
-// of them, with no memory rule.
+// MODE 0: the factors overwrite the face (row-major, precision T) when they take less memory
+// than the dense face.  MODE 1 (the intermediate recompression of a run that reached the column
+// capacity): the factors go to the slot's other column half (w.U2, w.V2) in complex128
+// column-major, at most KF_RESUME of them, with no memory rule.  MODE 2 (a face of the 3D-ACA
+// loop): to w.U2, w.V2 as in MODE 1, with the memory rule of MODE 0.  rel > 0: the tolerance
+// is at least rel ||U V^H||_F (eq. (ACA) truncated relative to the face's own norm).
 static constexpr int KF_RESUME = KF_MAX - 12;
-template <typename T, bool CM = false>
-static __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L, double& flop)
+template <typename T, int MODE = 0>
+static __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, int kc, double tol, Rs& L, double& flop,
+                                 double rel = 0.0)
 {
+    constexpr bool CM = MODE != 0;
     zd* Lm = L.m;
     const int ld = kc | 1;
     const int tx = gx(), ty = gy();
@@ -653,12 +658,23 @@ static __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, in
     chol_qr(w.U, 3 * m, kc, w.RU, w.G, L.du, L, ld);
     chol_qr(w.V, 3 * n, kc, w.RV, w.VJ, L.dv, L, ld);
     // M = R_U R_V^H
+    double m2 = 0.0;
     for (int j = ty; j < kc; j += GY)
         for (int i = tx; i < kc; i += 32) {
             zd s = {0.0, 0.0};
             for (int t = max(i, j); t < kc; ++t) s += mul_conj(w.RU[(size_t)t * kc + i], w.RV[(size_t)t * kc + j]);
             Lm[(size_t)j * ld + i] = s;
+            m2 += abs2(s);
         }
+    if (rel > 0.0) {
+        // ||M||_F = ||U V^H||_F: per-wavefront partial sums in L.sv, then every thread adds them
+        m2 = wsum(m2);
+        if (lane == 0) L.sv[wv] = m2;
+        __syncthreads();
+        double tot = 0.0;
+        for (int q = 0; q < NW; ++q) tot += L.sv[q];
+        tol = fmax(tol, rel * sqrt(tot));
+    }
     __syncthreads();
     double rest2 = 0.0;
     const int kq = qrcp(Lm, kc, ld, QRCP_FRAC * tol, L, &rest2);
@@ -709,7 +725,7 @@ static __device__ int recompress(cx<T>* Hout, int m, int n, const AcaWork& w, in
             }
         }
         if (tot > 0.0 && kk == 0) kk = 1;
-        if (CM ? kk > KF_RESUME : (long long)kk * (m + n) >= 3LL * m * n) kk = 0;
+        if (MODE == 1 ? kk > KF_RESUME : (long long)kk * (m + n) >= 3LL * m * n) kk = 0;
         L.piv = kk;
     }
     __syncthreads();
@@ -819,16 +835,23 @@ __global__ __launch_bounds__(R::NT) void k_face_recomp(CompressArgs A)
     aca_select_half(w);
     int kk = 0;
     double flop = 0.0;
-    if (kc > 0 && kc <= R::KF) {
+    if (kc > 0 && kc <= R::KF && A.iloop) {
+        kk = R::template recompress<double, 2>(nullptr, m, n, w, kc, 0.0, L, flop, A.eps_aca_far);
+    } else if (kc > 0 && kc <= R::KF) {
         const double tol = w.tol[0];
         kk = f.fp32 ? R::recompress((cx<float>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop)
                     : R::recompress((cx<double>*)(A.pool + f.face_off), m, n, w, kc, tol, L, flop);
     } else if (BIG && kc == -2) {
-        kk = R::template recompress<double, true>(nullptr, m, n, w, w.info[1], 0.25 * w.tol[0], L, flop);
+        kk = R::template recompress<double, 1>(nullptr, m, n, w, w.info[1], 0.25 * w.tol[0], L, flop);
     }
     if (threadIdx.x == 0) {
         atomicAdd(&A.st[b].recomp_flop, flop);
-        if (kc == -2 && kk > 0) {
+        if (A.iloop) {
+            // factors in the slot's other half (k_iloop_store moves them to the pool)
+            w.info[1] = kk;
+            w.info[2] = kc;
+            w.info[0] = kc > 0 && kk > 0 ? -5 : -4;
+        } else if (kc == -2 && kk > 0) {
             w.info[1] = kk;
             w.info[3] ^= 1;
             w.info[0] = -3;
