@@ -465,6 +465,8 @@ def main():
     ap.add_argument("--batch-nrhs", type=int, default=32)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg (reported apart from value)")
     ap.add_argument("--no-timestep", action="store_true", help="skip the time-stepping leg (reported apart from value)")
+    ap.add_argument("--no-iloop", action="store_true",
+                    help="skip the leg that compresses V and I/2+K in the paper's order of the per-slice ACA")
     ap.add_argument("--sequential", action="store_true",
                     help="timed steps with the operators one at a time (no second stream)")
     ap.add_argument("--no-measure", action="store_true",
@@ -653,6 +655,38 @@ def main():
                           "compression_rate": [v["compression_rate"] for v in st_s]}
         log("fp64 eps %.0e: compress %s ms" % (args.eps_fp64_strict, fp64["strict"]["compress_ms"]))
 
+    # the paper's order of the per-slice ACA (Sec. 3.1: faces approximated inside the 3D-ACA
+    # loop, pivot on the reconstruction), mixed precision, every admissible block through the
+    # ACA; reported apart from value (one operator at a time, after a warm-up compression)
+    iloop = None
+    if not args.no_iloop:
+        fresh_ctxs()
+        iloop = {"workload": "V and I/2+K as in the main step, mixed, eps3d %.0e, face_order in-loop, "
+                             "far_dense_max 0" % args.eps, "ops": {}}
+        ys_il = []
+        for opk in ops_list:
+            with torch.cuda.stream(streams[0]):
+                o = c.compress(opk, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED, pool_bytes=pool,
+                               far_dense_max=0, face_order=B.FACES_IN_LOOP)
+                o.destroy()
+                torch.cuda.synchronize()
+                ti0 = time.perf_counter()
+                o = c.compress(opk, eps3d=args.eps, leaf=64, eta=1.5, prec=B.PREC_MIXED, pool_bytes=pool,
+                               far_dense_max=0, face_order=B.FACES_IN_LOOP)
+                torch.cuda.synchronize()
+                ti1 = time.perf_counter()
+                ys_il.append(o.apply(x).cpu().numpy())
+                v = o.stats()
+                iloop["ops"][str(opk)] = {"seconds": ti1 - ti0, "kernel_ms": v["kernel_ms"], "face_ms": v["face_ms"],
+                                          "aca_ms": v["aca_ms"], "aca_kernel_ms": v["aca_kernel_ms"],
+                                          "recomp_ms": v["recomp_ms"], "compression_rate": v["compression_rate"],
+                                          "n_far_faces": v["n_far_faces"], "n_aca_dense": v["n_aca_dense"],
+                                          "aca_rank_mean": v["aca_rank_mean"], "rank_mean": v["rank_mean"]}
+                o.destroy()
+        iloop["_ys"] = ys_il
+        log("in-loop order:", {k: (round(v["kernel_ms"]), round(v["compression_rate"], 4), v["n_far_faces"])
+                               for k, v in iloop["ops"].items()})
+
     # solve leg (reported apart from value): V(s_l) t_l = (I/2 + K(s_l)) g_l at every contour
     # point for the pulsating sphere; FP64 operators at the strict eps for the residuals and
     # the right-hand side, the mixed V for the inner GMRES runs
@@ -821,6 +855,8 @@ def main():
 
         if ymix is not None:
             errs["mixed"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, ymix)}
+        if iloop is not None:
+            errs["mixed_in_loop"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, iloop["_ys"])}
         if fp64:
             errs["fp64"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, fp64["ys"])}
             errs["fp64_eps%.0e" % args.eps_fp64_strict] = {str(opk): rel(y, refs[opk])
@@ -828,6 +864,8 @@ def main():
     for leg in (batched, timestep):
         if leg is not None:
             leg.pop("_check", None)
+    if iloop is not None:
+        iloop.pop("_ys", None)
     hmv = {str(k): 1e3 / v for k, v in apply_ms.items()}
     out = {
         "metric": METRIC,
@@ -868,6 +906,7 @@ def main():
         "batched": batched,
         "adjoint": adjoint,
         "timestep": timestep,
+        "in_loop_order": iloop,
         "cpu_baseline": cpu,
     }
     if fp64:

@@ -7,7 +7,8 @@ shares no code with it.
 * ``bem_oracle.c`` (plain C99, FP64, optional OpenMP): kernel U and T of the paper's
   Appendix A / Sec. 2.1, collocation entries with the quadrature rules, dense products, and
   the gradient of a single-layer bilinear form with respect to the node coordinates and the
-  material (regular and near pairs by the chain rule, self pairs by central differences).
+  material (regular and near pairs by the chain rule, self pairs as the derivative of the
+  integral).
 * ``aca3d.py`` (numpy): the matrix-valued 3D-ACA of Algorithm 1 (Sec. 3), the matrix-valued
   ACA with QR/SVD recompression of eq. (ACA), and the H-matrix variant of Sec. 3.1 (faces
   approximated inside the loop, pivot on the reconstruction), for small tensors.
@@ -176,11 +177,13 @@ class Problem:
             raise RuntimeError("oracle_point_entries failed with code %d" % rc)
         return (out[..., 0] + 1j * out[..., 1]).reshape(n, 3, 3)
 
-    def adjoint_v(self, w, x, fd_h=1e-5):
+    def adjoint_v(self, w, x, fd_h=0.0):
         """Value S = sum_{r, l} w[r, l]^T V(s_l) x[r, l] of the single layer and the gradient
         of Re S: (S, grad_nodes [n_nodes, 3], grad_mat [rho, c_p, c_s]), pair classes held
-        fixed.  Regular and near pairs by the chain rule, self pairs by central differences of
-        the polar rule (step fd_h relative).  w, x: [nrhs, L, 3K] complex."""
+        fixed.  Regular and near pairs by the chain rule; self pairs as the derivative of the
+        integral (the polar rule applied to grad U (lambda_a - 1/3) and to dU/dc, plus the area
+        term), or with fd_h > 0 by central differences of the polar rule (step fd_h relative).
+        w, x: [nrhs, L, 3K] complex."""
         w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
         x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
         assert w.shape == x.shape

@@ -613,6 +613,65 @@ static int sub_triangles(const double *b0, const double *b1, const double *b2, i
     return sub_triangles(m01, m12, m20, m - 1, out, n);
 }
 
+/* Self pair of the single layer, differentiated as an integral: with the collocation point
+ * x = (v_0 + v_1 + v_2) / 3 and y = sum_a lambda_a(y) v_a on the element,
+ *   d/dv_a int U(y - x) dy = int grad U(y - x) (lambda_a(y) - 1/3) dy + (dA/dv_a / A) int U dy,
+ *   d/dc int U dy = int dU/dc dy,
+ * integrated with the polar rule of self_rule (the first integrand is O(1/|y - x|)).  Adds the
+ * contraction with w, x at (l, element j) to val (complex), gv[a][k] (Re) and gc[2] (Re). */
+static void self_grad(const ctx *C, const element *e, cplx s, const double *w, const double *x, int64_t K,
+                      int32_t L, int32_t nrhs, int32_t l, int64_t j, const double dA[3][3], cplx *val,
+                      double gv[3][3], double gc[2])
+{
+    const double *xc = e->c;
+    cplx vsum = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double *va = e->v[a], *vb = e->v[(a + 1) % 3];
+        double t[3], le = 0.0;
+        for (int k = 0; k < 3; ++k) { t[k] = vb[k] - va[k]; le += t[k] * t[k]; }
+        le = sqrt(le);
+        for (int k = 0; k < 3; ++k) t[k] /= le;
+        double proj = 0.0;
+        for (int k = 0; k < 3; ++k) proj += (xc[k] - va[k]) * t[k];
+        double foot[3], p[3], d = 0.0;
+        for (int k = 0; k < 3; ++k) { foot[k] = va[k] + proj * t[k]; p[k] = foot[k] - xc[k]; d += p[k] * p[k]; }
+        d = sqrt(d);
+        for (int k = 0; k < 3; ++k) p[k] /= d;
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < 3; ++k) { sa += (va[k] - foot[k]) * t[k]; sb += (vb[k] - foot[k]) * t[k]; }
+        double ta = atan2(sa, d), tb = atan2(sb, d);
+        for (int it = 0; it < C->qo.self_nt; ++it) {
+            double th = 0.5 * (ta + tb) + 0.5 * (tb - ta) * C->gl_t[it];
+            double wth = 0.5 * (tb - ta) * C->gl_tw[it];
+            double R = d / cos(th);
+            double dir[3];
+            for (int k = 0; k < 3; ++k) dir[k] = cos(th) * p[k] + sin(th) * t[k];
+            for (int ir = 0; ir < C->qo.self_nr; ++ir) {
+                double rho = 0.5 * R * (1.0 + C->gl_r[ir]);
+                double wq = wth * 0.5 * R * C->gl_rw[ir] * rho;
+                double rv[3], y[3];
+                for (int k = 0; k < 3; ++k) { rv[k] = rho * dir[k]; y[k] = xc[k] + rv[k]; }
+                cplx U[9], G[27], D1[9], D2[9];
+                kernel_U(rv, s, &C->mat, U);
+                kernel_gradU(rv, s, &C->mat, G);
+                kernel_dU_dc(rv, s, &C->mat, D1, D2);
+                vsum += wq * contract(U, w, x, K, L, nrhs, l, j, j);
+                gc[0] += wq * creal(contract(D1, w, x, K, L, nrhs, l, j, j));
+                gc[1] += wq * creal(contract(D2, w, x, K, L, nrhs, l, j, j));
+                for (int k = 0; k < 3; ++k) {
+                    cplx Gk[9];
+                    for (int q = 0; q < 9; ++q) Gk[q] = G[3 * q + k];
+                    double gk = wq * creal(contract(Gk, w, x, K, L, nrhs, l, j, j));
+                    for (int b = 0; b < 3; ++b) gv[b][k] += (bary_weight(e, b, y) - 1.0 / 3.0) * gk;
+                }
+            }
+        }
+    }
+    for (int b = 0; b < 3; ++b)
+        for (int k = 0; k < 3; ++k) gv[b][k] += creal(vsum) * dA[b][k] / e->area;
+    *val += vsum;
+}
+
 /* Value S = sum_{r, l, i, j} w[r][l][i]^T V_ij(s_l) x[r][l][j] of the single layer and the
  * gradient of Re S with respect to the node coordinates and to rho, c_p, c_s: the derivative
  * of the discrete operator, with the pair classes (regular, near level m, self) held fixed.
@@ -620,9 +679,10 @@ static int sub_triangles(const double *b0, const double *b1, const double *b2, i
  * j (beta: the 7-point rule's barycentric point mapped into each of the 4^m sub-triangles, so
  * the points move with the vertices), the collocation point (centroid of element i) and the
  * area of element j (each sub-triangle has a 4^-m share of it), with dU/dy from kernel_gradU
- * and dU/dc from kernel_dU_dc.  Self pairs: central differences of the polar rule in each
- * vertex coordinate of the element (step fd_h times its longest edge) and in c_p, c_s (step
- * fd_h times the speed).  value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho, c_p, c_s). */
+ * and dU/dc from kernel_dU_dc.  Self pairs: with fd_h > 0, central differences of the polar
+ * rule in each vertex coordinate of the element (step fd_h times its longest edge) and in c_p,
+ * c_s (step fd_h times the speed); with fd_h <= 0, the derivative of the integral (self_grad).
+ * value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho, c_p, c_s). */
 int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
                      double rho, double cp, double cs, const double *s, int32_t L, int near_on, double r1,
                      double r2, int self_nt, int self_nr, int32_t nrhs, const double *w, const double *x,
@@ -651,6 +711,31 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
             for (int64_t j = 0; j < K; ++j) {
                 const element *ej = &C.el[j];
                 const int32_t *tj = tris + 3 * j, *ti = tris + 3 * i;
+                if (i == j && fd_h <= 0.0) {
+                    double e1v[3], e2v[3], dA[3][3];
+                    for (int k = 0; k < 3; ++k) { e1v[k] = ej->v[1][k] - ej->v[0][k]; e2v[k] = ej->v[2][k] - ej->v[0][k]; }
+                    const double *n = ej->n;
+                    dA[1][0] = 0.5 * (e2v[1] * n[2] - e2v[2] * n[1]);
+                    dA[1][1] = 0.5 * (e2v[2] * n[0] - e2v[0] * n[2]);
+                    dA[1][2] = 0.5 * (e2v[0] * n[1] - e2v[1] * n[0]);
+                    dA[2][0] = 0.5 * (n[1] * e1v[2] - n[2] * e1v[1]);
+                    dA[2][1] = 0.5 * (n[2] * e1v[0] - n[0] * e1v[2]);
+                    dA[2][2] = 0.5 * (n[0] * e1v[1] - n[1] * e1v[0]);
+                    for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+                    for (int32_t l = 0; l < L; ++l) {
+                        cplx sl = s[2 * l] + I * s[2 * l + 1];
+                        cplx v = 0.0;
+                        double gv[3][3] = {{0.0}}, gc[2] = {0.0, 0.0};
+                        self_grad(&C, ej, sl, w, x, K, L, nrhs, l, j, dA, &v, gv, gc);
+                        gm[2] += creal(v);
+                        gm[3] += cimag(v);
+                        gm[0] += gc[0];
+                        gm[1] += gc[1];
+                        for (int a = 0; a < 3; ++a)
+                            for (int k = 0; k < 3; ++k) g[3 * (int64_t)tj[a] + k] += gv[a][k];
+                    }
+                    continue;
+                }
                 if (i == j) {
                     /* value and material derivatives of the self entry, then the vertices */
                     const double hl = fd_h * sqrt(ej->lmax2);

@@ -644,7 +644,7 @@ __device__ __forceinline__ double uniform_d(double v)
 
 // sigma_3 of a block as a call: its eigenvalue solve (acos, cos) is the register peak of the
 // ACA loop, and a call keeps it out of the loop's allocation
-__device__ __noinline__ double sigma3_call(const blk E) { return blk_sigma3(E); }
+__device__ __noinline__ double sigma3_call(const blk E) { return blk_sigma3_scaled(E); }
 
 // argmax over the wavefront with ties to the smallest index; NaN counts as -inf
 __device__ __forceinline__ void wargmax(double& v, int& idx)
@@ -1137,7 +1137,7 @@ __global__ __launch_bounds__(WG) void k_iloop_recon(CompressArgs A)
                 for (int c = 0; c < 3; ++c) Hd[(size_t)(3 * i + a) * ld + 3 * j + c] = H.a[3 * a + c];
         }
         e2 = blk_fro2(H);
-        s3 = blk_sigma3(H);
+        s3 = blk_sigma3_scaled(H);
         pi = p;
     }
     double v[1] = {e2};

@@ -13,7 +13,7 @@
 // through A and B only: dA/dc1 = -e1r / c1, dA/dc2 = e2r (x2 - 1) / c2, dB/dc1 =
 // e1r (x1 + 1) / c1, dB/dc2 = -e2r (x2 + 1) / c2 with x_a = s R / c_a, e_ar = exp(-x_a) /
 // (c_a^2 R) (both branches of the kernel: in the series branch the lambda-integral
-// contributes -+ e_a / c_a^3).  Self pairs: central differences of the polar rule.
+// contributes -+ e_a / c_a^3).  Self pairs: the derivative of the integral by the polar rule (below).
 #include "lib.hpp"
 
 namespace bem {
@@ -276,77 +276,122 @@ __global__ __launch_bounds__(WG) void k_adjoint_v(DevCtx c, int nrhs, const zd* 
     }
 }
 
-// Re and Im of sum_{r, l} w[r][l][j]^T E_l x[r][l][j] with E_l the single-layer self entry of
-// an element with vertices P (polar rule about its centroid) and material Mm.
-__device__ zd self_form(const double (*P)[3], const DevCtx& c, const Mat<double>& Mm, int nrhs, const zd* w,
-                        const zd* x, int j)
-{
-    const int K = c.geo.K, L = c.fr.L;
-    const size_t M = 3 * (size_t)K;
-    double cx = (P[0][0] + P[1][0] + P[2][0]) / 3.0, cy = (P[0][1] + P[1][1] + P[2][1]) / 3.0,
-           cz = (P[0][2] + P[1][2] + P[2][2]) / 3.0;
-    double vx[3] = {P[0][0], P[1][0], P[2][0]}, vy[3] = {P[0][1], P[1][1], P[2][1]}, vz[3] = {P[0][2], P[1][2], P[2][2]};
-    Geo e{};
-    e.K = 1;
-    e.cx = &cx;
-    e.cy = &cy;
-    e.cz = &cz;
-    e.vx = vx;
-    e.vy = vy;
-    e.vz = vz;
-    zd sum = {0.0, 0.0};
-    for (int l = 0; l < L; ++l) {
-        blk E;
-        entry_self(e, 0, 0, c.fr.s[l], c.fr.sinv[l], Mm, c.qt, E);
-        for (int rr = 0; rr < nrhs; ++rr) {
-            const zd* up = w + ((size_t)rr * L + l) * M + 3 * (size_t)j;
-            const zd* vp = x + ((size_t)rr * L + l) * M + 3 * (size_t)j;
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) sum = fma_c(up[a] * E.a[3 * a + b], vp[b], sum);
-        }
-    }
-    return sum;
-}
-
-// Self pairs: thread per (element j, quantity d): d < 9 vertex a = d / 3, coordinate d % 3
-// (central difference, step h_rel times the longest edge); d = 9, 10: c1, c2 (the materials
-// at c -+ h are passed in); d = 11: the value.  out[j][13]: 9 vertex derivatives, dc1, dc2,
-// Re, Im.
+// Self pairs: the derivative of the integral, taken by hand.  With y = sum_a lambda_a(y) P_a on
+// the element (barycentric coordinates fixed under a perturbation of the vertices) and the
+// collocation point x = (P_0 + P_1 + P_2) / 3, the self entry is E = int U(y - x) dy and
+//   dE/dP_a = int grad_r U(y - x) (lambda_a(y) - 1/3) dy + (dA/dP_a / A) E,
+// whose first integrand is O(1/|y - x|) (lambda_a - 1/3 vanishes at the centroid); dE/dc =
+// int dU/dc dy.  Both are integrated by the polar rule of the forward self entry.  Thread per
+// element j; out[j][13]: 9 vertex derivatives (vertex a, coordinate k at 3 a + k) of Re of the
+// self terms of S, their c1 and c2 derivatives, Re and Im.
 __global__ __launch_bounds__(64) void k_adjoint_self(DevCtx c, int nrhs, const zd* __restrict__ w,
-                                                     const zd* __restrict__ x, double h_rel, Mat<double> Mp1,
-                                                     Mat<double> Mm1, double h1, Mat<double> Mp2, Mat<double> Mm2,
-                                                     double h2, double* __restrict__ out)
+                                                     const zd* __restrict__ x, double* __restrict__ out)
 {
     const Geo& g = c.geo;
-    const int K = g.K;
-    const int t = blockIdx.x * 64 + threadIdx.x;
-    if (t >= 12 * K) return;
-    const int j = t / 12, d = t - 12 * j;
+    const QuadTab& Q = c.qt;
+    const int K = g.K, L = c.fr.L;
+    const size_t M = 3 * (size_t)K;
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= K) return;
+    const double pref = c.md.inv4pirho;
     double P[3][3];
     for (int a = 0; a < 3; ++a) {
         P[a][0] = g.vx[a * K + j];
         P[a][1] = g.vy[a * K + j];
         P[a][2] = g.vz[a * K + j];
     }
-    double* o = out + (size_t)j * 13;
-    if (d < 9) {
-        const double h = h_rel * sqrt(g.lmax2[j]);
-        const int a = d / 3, k = d - 3 * (d / 3);
-        const double p0 = P[a][k];
-        P[a][k] = p0 + h;
-        const zd fp = self_form(P, c, c.md, nrhs, w, x, j);
-        P[a][k] = p0 - h;
-        const zd fm = self_form(P, c, c.md, nrhs, w, x, j);
-        o[d] = (fp.re - fm.re) / (2.0 * h);
-    } else if (d < 11) {
-        const zd fp = self_form(P, c, d == 9 ? Mp1 : Mp2, nrhs, w, x, j);
-        const zd fm = self_form(P, c, d == 9 ? Mm1 : Mm2, nrhs, w, x, j);
-        o[d] = (fp.re - fm.re) / (2.0 * (d == 9 ? h1 : h2));
-    } else {
-        const zd f = self_form(P, c, c.md, nrhs, w, x, j);
-        o[11] = f.re;
-        o[12] = f.im;
+    const double xc[3] = {g.cx[j], g.cy[j], g.cz[j]};
+    const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+    const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+    const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+    double dA[3][3];
+    dA[1][0] = 0.5 * (e2[1] * n[2] - e2[2] * n[1]);
+    dA[1][1] = 0.5 * (e2[2] * n[0] - e2[0] * n[2]);
+    dA[1][2] = 0.5 * (e2[0] * n[1] - e2[1] * n[0]);
+    dA[2][0] = 0.5 * (n[1] * e1[2] - n[2] * e1[1]);
+    dA[2][1] = 0.5 * (n[2] * e1[0] - n[0] * e1[2]);
+    dA[2][2] = 0.5 * (n[0] * e1[1] - n[1] * e1[0]);
+    for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+    double gP[9], V = 0.0, Vi = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int t = 0; t < 9; ++t) gP[t] = 0.0;
+#pragma unroll 1
+    for (int sa = 0; sa < 3; ++sa) {
+        const int sb = (sa + 1) % 3;
+        double t[3] = {P[sb][0] - P[sa][0], P[sb][1] - P[sa][1], P[sb][2] - P[sa][2]};
+        const double le = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        for (int k = 0; k < 3; ++k) t[k] /= le;
+        const double proj = (xc[0] - P[sa][0]) * t[0] + (xc[1] - P[sa][1]) * t[1] + (xc[2] - P[sa][2]) * t[2];
+        double foot[3], p[3];
+        for (int k = 0; k < 3; ++k) {
+            foot[k] = P[sa][k] + proj * t[k];
+            p[k] = foot[k] - xc[k];
+        }
+        const double d = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        for (int k = 0; k < 3; ++k) p[k] /= d;
+        const double qa = (P[sa][0] - foot[0]) * t[0] + (P[sa][1] - foot[1]) * t[1] + (P[sa][2] - foot[2]) * t[2];
+        const double qb = (P[sb][0] - foot[0]) * t[0] + (P[sb][1] - foot[1]) * t[1] + (P[sb][2] - foot[2]) * t[2];
+        const double ta = atan2(qa, d), tb = atan2(qb, d);
+        const double hth = 0.5 * (tb - ta), mth = 0.5 * (ta + tb);
+#pragma unroll 1
+        for (int it = 0; it < Q.nt; ++it) {
+            const double th = mth + hth * Q.tx[it];
+            const double wth = hth * Q.tw[it];
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const double Rl = d / cs;
+            const double rh[3] = {cs * p[0] + sn * t[0], cs * p[1] + sn * t[1], cs * p[2] + sn * t[2]};
+#pragma unroll 1
+            for (int ir = 0; ir < Q.nr; ++ir) {
+                const double rho = 0.5 * Rl * (1.0 + Q.rx[ir]);
+                const double wq = wth * (0.5 * Rl * Q.rw[ir]) * rho * pref;
+                const double y[3] = {xc[0] + rho * rh[0], xc[1] + rho * rh[1], xc[2] + rho * rh[2]};
+                double lam[3];
+                for (int a = 0; a < 3; ++a) lam[a] = bary_at(g, j, a, y) - 1.0 / 3.0;
+                double G[3] = {0.0, 0.0, 0.0}, v0 = 0.0, v1 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll 1
+                for (int l = 0; l < L; ++l) {
+                    zd A, B, Ad, Bd, A1, A2, B1, B2;
+                    kernel_adj(rho, 1.0 / rho, c.fr.s[l], c.fr.sinv[l], c.md, A, B, Ad, Bd, A1, A2, B1, B2);
+                    const zd BR = B * (1.0 / rho);
+#pragma unroll 1
+                    for (int rr = 0; rr < nrhs; ++rr) {
+                        const zd* up = w + ((size_t)rr * L + l) * M + 3 * (size_t)j;
+                        const zd* vp = x + ((size_t)rr * L + l) * M + 3 * (size_t)j;
+                        const zd u[3] = {up[0], up[1], up[2]}, v[3] = {vp[0], vp[1], vp[2]};
+                        const zd uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+                        const zd ur = u[0] * rh[0] + u[1] * rh[1] + u[2] * rh[2];
+                        const zd vr = v[0] * rh[0] + v[1] * rh[1] + v[2] * rh[2];
+                        const zd t2 = ur * vr;
+                        const zd val = A * uv + B * t2;
+                        const double gs = (Ad * uv + Bd * t2).re;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            G[k] += gs * rh[k] + (BR * (vr * u[k] + ur * v[k] - t2 * (2.0 * rh[k]))).re;
+                        v0 += val.re;
+                        v1 += val.im;
+                        d1 += (A1 * uv + B1 * t2).re;
+                        d2 += (A2 * uv + B2 * t2).re;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) gP[3 * a + k] += wq * G[k] * lam[a];
+                V += wq * v0;
+                Vi += wq * v1;
+                m1 += wq * d1;
+                m2 += wq * d2;
+            }
+        }
     }
+    double* o = out + (size_t)j * 13;
+    const double ia = 1.0 / g.area[j];
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) o[3 * a + k] = gP[3 * a + k] + V * dA[a][k] * ia;
+    o[9] = m1;
+    o[10] = m2;
+    o[11] = V;
+    o[12] = Vi;
 }
 
 // out[e][t] = sum over tiles of part[tile][e][t] (fixed order)
@@ -390,9 +435,8 @@ size_t adjoint_work_doubles(int K)
 // vertex derivatives of the regular pairs as column element, then 3 centroid derivatives as
 // row element; tiles[..]: the per-workgroup dc1, dc2, Re S, Im S (ntiles_out of them); self
 // results [K][13].
-void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double h_rel, const Mat<double>& Mp1,
-                      const Mat<double>& Mm1, double h1, const Mat<double>& Mp2, const Mat<double>& Mm2, double h2,
-                      double* work, double** sums, double** tiles, int* ntiles_out, double** self_out,
+void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double* work, double** sums, double** tiles,
+                      int* ntiles_out, double** self_out,
                       hipStream_t st)
 {
     const int K = c.geo.K;
@@ -404,8 +448,7 @@ void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, doubl
     double* sum = so + (size_t)K * 13;
     hipLaunchKernelGGL(k_adjoint_v, dim3(ti, tj), dim3(WG), 0, st, c, nrhs, w, x, gJ, gI, gM);
     BEM_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_adjoint_self, dim3((unsigned)((12 * (size_t)K + 63) / 64)), dim3(64), 0, st, c, nrhs, w, x,
-                       h_rel, Mp1, Mm1, h1, Mp2, Mm2, h2, so);
+    hipLaunchKernelGGL(k_adjoint_self, dim3((unsigned)(((size_t)K + 63) / 64)), dim3(64), 0, st, c, nrhs, w, x, so);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)((9 * (size_t)K + WG - 1) / WG)), dim3(WG), 0, st, gJ, (int)ti,
                        9 * (size_t)K, sum);

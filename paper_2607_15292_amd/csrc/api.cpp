@@ -1079,19 +1079,12 @@ int bem_adjoint_v(bem_ctx* ctx, int32_t nrhs, const void* w, const void* x, int3
         Staged sw, sx;
         stage_in(sw, w, bytes, dev, st);
         stage_in(sx, x, bytes, dev, st);
-        // material tables at c -+ h for the central differences of the self entries
-        const double hrel = 1e-5;
-        const double h1 = hrel * ctx->cp, h2 = hrel * ctx->cs;
-        const Mat<double> Mp1 = make_mat<double>(ctx->rho, ctx->cp + h1, ctx->cs),
-                          Mm1 = make_mat<double>(ctx->rho, ctx->cp - h1, ctx->cs),
-                          Mp2 = make_mat<double>(ctx->rho, ctx->cp, ctx->cs + h2),
-                          Mm2 = make_mat<double>(ctx->rho, ctx->cp, ctx->cs - h2);
         DevBuf work;
         work.alloc(adjoint_work_doubles(K) * sizeof(double));
         double *sums = nullptr, *tiles = nullptr, *self_out = nullptr;
         int ntiles = 0;
-        launch_adjoint_v(ctx->devctx(ctx->dgeo.geo, nullptr), nrhs, (const zd*)sw.dev, (const zd*)sx.dev, hrel, Mp1, Mm1,
-                         h1, Mp2, Mm2, h2, work.as<double>(), &sums, &tiles, &ntiles, &self_out, st);
+        launch_adjoint_v(ctx->devctx(ctx->dgeo.geo, nullptr), nrhs, (const zd*)sw.dev, (const zd*)sx.dev, work.as<double>(),
+                         &sums, &tiles, &ntiles, &self_out, st);
         std::vector<double> hs(12 * (size_t)K), ht(4 * (size_t)ntiles), hself(13 * (size_t)K);
         BEM_HIP_TRY(hipMemcpyAsync(hs.data(), sums, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         BEM_HIP_TRY(hipMemcpyAsync(ht.data(), tiles, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -149,11 +149,30 @@ BEM_HD zd zdiv(zd a, zd b)
     return {(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
 }
 
+// A power of two within a factor 2 of the largest |entry| of A (1 for a zero or non-finite
+// block).  Scaling by it is exact, so a result computed on A / s and rescaled is the one
+// computed on A wherever the latter does not underflow: entries of faces at the largest |s_l|
+// reach exp(-Re(s) r / c2) ~ 1e-60, where det(A) ~ 1e-180 and its square underflow.
+BEM_HD double blk_pow2_scale(const blk& A)
+{
+    double m = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) m = fmax(m, fmax(fabs(A.a[t].re), fabs(A.a[t].im)));
+    if (!(m > 0.0) || !(m < 1e300)) return 1.0;
+    int e;
+    (void)frexp(m, &e);
+    return ldexp(1.0, e);
+}
+
 BEM_HD blk blk_inv(const blk& A)
 {
+    const double sc = blk_pow2_scale(A), isc = 1.0 / sc;
+    blk As;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) As.a[t] = A.a[t] * isc;
     blk adj;
-    zd det = blk_det_adj(A, adj);
-    zd inv = zdiv(zd{1.0, 0.0}, det);
+    zd det = blk_det_adj(As, adj);
+    zd inv = zdiv(zd{isc, 0.0}, det);
 #pragma unroll
     for (int t = 0; t < 9; ++t) adj.a[t] = adj.a[t] * inv;
     return adj;
@@ -205,6 +224,18 @@ BEM_HD double blk_sigma3(const blk& A)
     double l = herm3_lambda_max(G);
     if (!(l > 0.0)) return 0.0;
     return ad / sqrt(l);
+}
+
+// sigma_3 of a block of any magnitude (computed on A / s, s = blk_pow2_scale(A)); the plain
+// blk_sigma3 loses accuracy once the entries fall below ~1e-38 (the Gram of the adjugate
+// holds eighth powers of them)
+BEM_HD double blk_sigma3_scaled(const blk& A)
+{
+    const double sc = blk_pow2_scale(A), isc = 1.0 / sc;
+    blk As;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) As.a[t] = A.a[t] * isc;
+    return sc * blk_sigma3(As);
 }
 
 // ---------------------------------------------------------------- host error plumbing

@@ -71,8 +71,7 @@ void launch_mf_apply(const DevCtx& c, int op, bool transpose, int nrhs, const zd
 void launch_mf_apply_kl(const DevCtx& c, const int* tri, int nnodes, int nrhs, const zd* g, zd* y, bool free_term,
                         hipStream_t st);
 size_t adjoint_work_doubles(int K);
-void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double h_rel, const Mat<double>& Mp1,
-                      const Mat<double>& Mm1, double h1, const Mat<double>& Mp2, const Mat<double>& Mm2, double h2,
-                      double* work, double** sums, double** tiles, int* ntiles, double** self_out, hipStream_t st);
+void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double* work, double** sums, double** tiles,
+                      int* ntiles, double** self_out, hipStream_t st);
 
 }  // namespace bem

@@ -222,6 +222,127 @@ def pulsating_sphere(points, normals, s, rho=1.0, cp=1.0, cs=0.5, a=2.5):
     return u, t
 
 
+def stator_shell(h: float = 0.05, r_out: float = 1.0, r_in: float = 0.7, length: float = 1.5,
+                 n_slots: int = 36, slot_width: float = 0.05, slot_depth: float = 0.1):
+    """Closed surface of an induction-machine-like stator: the solid between coaxial cylinders
+    r = r_in and r = r_out, 0 <= z <= length, with n_slots slots (slot_width wide at the bore,
+    slot_depth deep, radial walls) cut into the inner surface, and annular end caps; element
+    size about h.  Cross-section: each sector holds a tooth (r_in <= r <= r_b = r_in +
+    slot_depth between two slots, a structured grid whose side columns are the slot walls) and
+    the annulus r_b <= r <= r_out above teeth and slot bottoms (a structured ring).  The side
+    walls extrude the slotted inner contour and the outer circle.  Every edge is shared by two
+    triangles; normals point out of the solid.  Returns (nodes [n, 3], tris [K, 3])."""
+    S = n_slots
+    dth = 2.0 * math.pi / S
+    half = 0.5 * slot_width / r_in  # angular half-width of a slot at the bore
+    r_b = r_in + slot_depth
+    th0 = lambda k: k * dth + half          # tooth k from th0(k) to th1(k), slot k + 1 after it
+    th1 = lambda k: (k + 1) * dth - half
+    n_t = max(1, int(round(r_in * (th1(0) - th0(0)) / h)))
+    n_w = max(1, int(round(slot_depth / h)))
+    n_b = max(1, int(round(r_b * 2.0 * half / h)))
+    n_r = max(1, int(round((r_out - r_b) / h)))
+    n_z = max(1, int(round(length / h)))
+
+    def canon(key):
+        if key[0] == "b":  # slot bottom point i of the slot after tooth k
+            _, k, i = key
+            if i == 0:
+                return ("g", k % S, n_t, n_w)
+            if i == n_b:
+                return ("g", (k + 1) % S, 0, n_w)
+            return ("b", k % S, i)
+        if key[0] == "g":
+            return ("g", key[1] % S, key[2], key[3])
+        return key
+
+    def xy(key):
+        if key[0] == "g":  # tooth grid: angle column a, radius level q
+            _, k, a, q = key
+            t = th0(k) + (th1(k) - th0(k)) * a / n_t
+            r = r_in + slot_depth * q / n_w
+        else:  # slot bottom
+            _, k, i = key
+            t = th1(k) + 2.0 * half * i / n_b
+            r = r_b
+        return r * math.cos(t), r * math.sin(t)
+
+    # the slotted inner contour (counter-clockwise) and the ring at r_b
+    contour, ring = [], []
+    for k in range(S):
+        contour += [canon(("g", k, a, 0)) for a in range(n_t)]
+        contour += [canon(("g", k, n_t, q)) for q in range(n_w)]
+        contour += [canon(("b", k, i)) for i in range(n_b)]
+        contour += [canon(("g", k + 1, 0, q)) for q in range(n_w, 0, -1)]
+        ring += [canon(("g", k, a, n_w)) for a in range(n_t)]
+        ring += [canon(("b", k, i)) for i in range(n_b)]
+    ring_th = [math.atan2(*reversed(xy(key))) for key in ring]
+    nodes, idx = [], {}
+
+    def node(key, p):
+        if key not in idx:
+            idx[key] = len(nodes)
+            nodes.append(p)
+        return idx[key]
+
+    def plane(key, z, zi):
+        """Node of a 2D key at height index zi (0 or n_z on the caps, interior on the walls)."""
+        if key[0] == "o":
+            t = ring_th[key[1]]
+            p = (r_out * math.cos(t), r_out * math.sin(t))
+        elif key[0] == "a":  # annulus level q between ring point i and the outer circle
+            _, i, q = key
+            t = ring_th[i]
+            r = r_b + (r_out - r_b) * q / n_r
+            p = (r * math.cos(t), r * math.sin(t))
+        else:
+            p = xy(key)
+        return node((key, zi), (p[0], p[1], z))
+
+    tris = []
+
+    def quad(a, b, c, d, want):
+        for t in ((a, b, c), (a, c, d)):
+            P = [np.asarray(nodes[v]) for v in t]
+            nrm = np.cross(P[1] - P[0], P[2] - P[0])
+            tris.append(t if float(np.dot(nrm, want)) >= 0.0 else (t[0], t[2], t[1]))
+
+    zs = np.linspace(0.0, length, n_z + 1)
+    # inner side wall: outward normal of the solid = left of the counter-clockwise contour
+    Mc = len(contour)
+    for i in range(Mc):
+        k0, k1 = contour[i], contour[(i + 1) % Mc]
+        p0, p1 = np.asarray(xy(k0)), np.asarray(xy(k1))
+        tg = p1 - p0
+        want = np.array([-tg[1], tg[0], 0.0])
+        for j in range(n_z):
+            quad(plane(k0, zs[j], j), plane(k1, zs[j], j), plane(k1, zs[j + 1], j + 1), plane(k0, zs[j + 1], j + 1),
+                 want)
+    # outer side wall
+    Mr = len(ring)
+    for i in range(Mr):
+        i1 = (i + 1) % Mr
+        want = np.array([math.cos(ring_th[i]) + math.cos(ring_th[i1]), math.sin(ring_th[i]) + math.sin(ring_th[i1]), 0.0])
+        for j in range(n_z):
+            quad(plane(("o", i), zs[j], j), plane(("o", i1), zs[j], j), plane(("o", i1), zs[j + 1], j + 1),
+                 plane(("o", i), zs[j + 1], j + 1), want)
+    # caps: teeth and annulus at z = 0 (normal -z) and z = length (+z)
+    for zi, z, sgn in ((0, 0.0, -1.0), (n_z, length, 1.0)):
+        want = np.array([0.0, 0.0, sgn])
+        for k in range(S):
+            for a in range(n_t):
+                for q in range(n_w):
+                    quad(plane(canon(("g", k, a, q)), z, zi), plane(canon(("g", k, a + 1, q)), z, zi),
+                         plane(canon(("g", k, a + 1, q + 1)), z, zi), plane(canon(("g", k, a, q + 1)), z, zi), want)
+        lev = lambda i, q: ring[i] if q == 0 else (("o", i) if q == n_r else ("a", i, q))
+        for i in range(Mr):
+            i1 = (i + 1) % Mr
+            for q in range(n_r):
+                quad(plane(lev(i, q), z, zi), plane(lev(i1, q), z, zi), plane(lev(i1, q + 1), z, zi),
+                     plane(lev(i, q + 1), z, zi), want)
+    return np.asarray(nodes, dtype=np.float64), np.asarray(tris, dtype=np.int32)
+
+
 def batch_meshes():
     """Meshes of the batched-product workload, smallest first: cubes [-1, 1]^3 with 8 and 16
     squares per face edge (768 and 3072 triangles) and icospheres of radius 1 with 1280 and

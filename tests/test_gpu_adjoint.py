@@ -2,8 +2,9 @@
 (bem_adjoint_v) through the C-ABI: the dense products and the transposed products against
 the oracle's dense operator; the value and the gradients with respect to the node
 coordinates and rho, c_p, c_s against the oracle's gradient (oracle.Problem.adjoint_v) and
-against central differences of the GPU's own matrix-free product on random directions; the
-torch.autograd.Function on top."""
+against central differences of the GPU's own matrix-free product on random directions (the
+self pairs differentiated by hand as integrals, so these agree up to the polar rule's
+quadrature error of the derivative); the torch.autograd.Function on top."""
 import numpy as np
 import pytest
 
@@ -73,8 +74,8 @@ def test_adjoint_matches_oracle(torch, mesh, near_on):
     val, gn, gm = c.adjoint_v(torch.tensor(w, device="cuda"), torch.tensor(x, device="cuda"))
     val_o, gn_o, gm_o = oracle.Problem(X, T, s, *mat, near_on=near_on).adjoint_v(w, x)
     assert abs(val - val_o) <= 1e-12 * abs(val_o)
-    # regular and near pairs exact on both sides; self pairs by central differences (relative
-    # step 1e-5)
+    # the same derivatives on both sides (regular and near pairs by the chain rule, self pairs
+    # as the derivative of the integral by the polar rule), written apart
     assert np.abs(gn - gn_o).max() <= 1e-7 * np.abs(gn_o).max()
     assert np.abs(gm - gm_o).max() <= 1e-7 * np.abs(gm_o).max()
 

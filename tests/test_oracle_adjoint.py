@@ -126,3 +126,18 @@ def test_near_rule_translation_invariance():
     X, T, s, w, x = _near_setup()
     _, g, _ = oracle.Problem(X, T, s, near_on=True).adjoint_v(w, x)
     assert np.abs(g.sum(axis=0)).max() <= 1e-8 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("near_on", [False, True])
+def test_self_derivative_of_the_integral_against_the_rule(near_on):
+    # the self pairs differentiated as integrals (polar rule of grad U (lambda_a - 1/3), area
+    # term) against central differences of the polar rule itself: the same derivative up to the
+    # rule's quadrature error (nodes), and identical for the material (the rule's points do not
+    # move with the speeds)
+    X, T, s, w, x = _setup()
+    P = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=near_on)
+    v0, g0, m0 = P.adjoint_v(w, x)
+    v1, g1, m1 = P.adjoint_v(w, x, fd_h=1e-5)
+    assert abs(v0 - v1) <= 1e-13 * abs(v1)
+    assert np.abs(g0 - g1).max() <= 3e-6 * np.abs(g1).max()
+    assert np.abs(m0 - m1).max() <= 1e-9 * np.abs(m1).max()
