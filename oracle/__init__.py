@@ -77,6 +77,12 @@ def lib():
                                        ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int32, dp, dp, ctypes.c_double,
                                        dp, dp, dp]
+        L.oracle_adjoint_k.restype = ctypes.c_int
+        L.oracle_adjoint_k.argtypes = [dp, ctypes.c_int64, ip, ctypes.c_int64,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int32,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int32, dp, dp, ctypes.c_double,
+                                       dp, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -196,6 +202,28 @@ class Problem:
                                     float(fd_h), _d(val), _d(gn), _d(gm))
         if rc != 0:
             raise RuntimeError("oracle_adjoint_v failed with code %d" % rc)
+        return complex(val[0], val[1]), gn, gm
+
+    def adjoint_k(self, w, x, op=OP_K, fd_h=1e-5):
+        """Value S = sum_{r, l} w[r, l]^T A(s_l) x[r, l] of the double layer (op OP_K, or OP_HK
+        with the free term) and the gradient of Re S: (S, grad_nodes [n_nodes, 3], grad_mat
+        [rho, c_p, c_s]; the rho entry is 0, T not depending on rho), pair classes held fixed.
+        Regular and near pairs by the chain rule through the Gauss points, the normal, the
+        area and the collocation point, with the pointwise derivatives of T by central
+        differences of the kernel (step fd_h relative); self pairs by central differences of
+        the principal-value polar rule.  w, x: [nrhs, L, 3K] complex."""
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
+        assert w.shape == x.shape and op in (OP_K, OP_HK)
+        wr = np.ascontiguousarray(np.stack([w.real, w.imag], axis=-1))
+        xr = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
+        val = np.zeros(2)
+        gn = np.zeros((self.nodes.shape[0], 3))
+        gm = np.zeros(3)
+        rc = lib().oracle_adjoint_k(*self._common(), int(op), *self._quad(0)[1:], w.shape[0], _d(wr), _d(xr),
+                                    float(fd_h), _d(val), _d(gn), _d(gm))
+        if rc != 0:
+            raise RuntimeError("oracle_adjoint_k failed with code %d" % rc)
         return complex(val[0], val[1]), gn, gm
 
     def matvec_rows(self, op, rows, x):

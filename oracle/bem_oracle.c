@@ -854,6 +854,203 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
     return 0;
 }
 
+/* Value S = sum_{r, l, i, j} w[r][l][i]^T K_ij(s_l) x[r][l][j] of the double layer (op 1; op 2
+ * adds the free term I/2, whose derivative is zero) and the gradient of Re S with respect to
+ * the node coordinates and c_p, c_s (T does not depend on rho): the derivative of the discrete
+ * operator with the pair classes held fixed.  Regular and near pairs: chain rule through the
+ * Gauss points of element j (they move with its vertices), its normal n_j = N / |N|,
+ * N = (v1 - v0) x (v2 - v0) (dn = (I - n n^T) (dv_a x (v_{a+1} - v_{a+2})) / |N|), its area
+ * and the centroid of element i; the pointwise derivatives of T are taken by central
+ * differences of kernel_T in y (step fd_h |y - x|) and in c_p, c_s (step fd_h c), and T is
+ * linear in n (dT/dn_k = T with n = e_k).  Self pairs: central differences of the polar rule
+ * (principal value) in each vertex coordinate (step fd_h times the longest edge) and in the
+ * speeds.  value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho, c_p, c_s). */
+int oracle_adjoint_k(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
+                     double rho, double cp, double cs, const double *s, int32_t L, int op, int near_on, double r1,
+                     double r2, int self_nt, int self_nr, int32_t nrhs, const double *w, const double *x,
+                     double fd_h, double *value, double *grad_nodes, double *grad_mat)
+{
+    ctx C;
+    int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, near_on, r1, r2, self_nt, self_nr);
+    if (rc) return rc;
+    if (!(fd_h > 0.0)) fd_h = 1e-5;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    double *gbuf = (double *)calloc((size_t)nth * (3 * (size_t)n_nodes + 5), sizeof(double));
+    if (!gbuf) { free((void *)C.el); return -3; }
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *g = gbuf + (size_t)tid * (3 * (size_t)n_nodes + 5);
+        double *gm = g + 3 * (size_t)n_nodes;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < K; ++i) {
+            const element *ei = &C.el[i];
+            for (int64_t j = 0; j < K; ++j) {
+                const element *ej = &C.el[j];
+                const int32_t *tj = tris + 3 * j, *ti = tris + 3 * i;
+                if (i == j) {
+                    const double hl = fd_h * sqrt(ej->lmax2);
+                    for (int32_t l = 0; l < L; ++l) {
+                        cplx sl = s[2 * l] + I * s[2 * l + 1];
+                        cplx E[9] = {0};
+                        self_rule(&C, 1, ej, sl, -1, E);
+                        if (op == 2) { E[0] += 0.5; E[4] += 0.5; E[8] += 0.5; }
+                        cplx v = contract(E, w, x, K, L, nrhs, l, i, j);
+                        gm[2] += creal(v);
+                        gm[3] += cimag(v);
+                        for (int which = 0; which < 2; ++which) {
+                            ctx Cp = C, Cm = C;
+                            double h = fd_h * (which == 0 ? cp : cs);
+                            if (which == 0) { Cp.mat.c1 += h; Cm.mat.c1 -= h; }
+                            else { Cp.mat.c2 += h; Cm.mat.c2 -= h; }
+                            cplx Ep[9] = {0}, Em[9] = {0};
+                            self_rule(&Cp, 1, ej, sl, -1, Ep);
+                            self_rule(&Cm, 1, ej, sl, -1, Em);
+                            cplx D[9];
+                            for (int t = 0; t < 9; ++t) D[t] = (Ep[t] - Em[t]) / (2.0 * h);
+                            gm[which] += creal(contract(D, w, x, K, L, nrhs, l, i, j));
+                        }
+                        for (int a = 0; a < 3; ++a)
+                            for (int k = 0; k < 3; ++k) {
+                                double vp[9], vm[9];
+                                for (int b = 0; b < 3; ++b)
+                                    for (int q = 0; q < 3; ++q) vp[3 * b + q] = vm[3 * b + q] = ej->v[b][q];
+                                vp[3 * a + k] += hl;
+                                vm[3 * a + k] -= hl;
+                                int32_t loc[3] = {0, 1, 2};
+                                element ep, em;
+                                make_element(vp, loc, &ep);
+                                make_element(vm, loc, &em);
+                                cplx Ep[9] = {0}, Em[9] = {0};
+                                self_rule(&C, 1, &ep, sl, -1, Ep);
+                                self_rule(&C, 1, &em, sl, -1, Em);
+                                cplx D[9];
+                                for (int t = 0; t < 9; ++t) D[t] = (Ep[t] - Em[t]) / (2.0 * hl);
+                                g[3 * (int64_t)tj[a] + k] += creal(contract(D, w, x, K, L, nrhs, l, i, j));
+                            }
+                    }
+                    continue;
+                }
+                /* area and normal derivatives of element j */
+                double e1v[3], e2v[3], dA[3][3], Nn = 0.0;
+                for (int k = 0; k < 3; ++k) { e1v[k] = ej->v[1][k] - ej->v[0][k]; e2v[k] = ej->v[2][k] - ej->v[0][k]; }
+                const double *n = ej->n;
+                dA[1][0] = 0.5 * (e2v[1] * n[2] - e2v[2] * n[1]);
+                dA[1][1] = 0.5 * (e2v[2] * n[0] - e2v[0] * n[2]);
+                dA[1][2] = 0.5 * (e2v[0] * n[1] - e2v[1] * n[0]);
+                dA[2][0] = 0.5 * (n[1] * e1v[2] - n[2] * e1v[1]);
+                dA[2][1] = 0.5 * (n[2] * e1v[0] - n[0] * e1v[2]);
+                dA[2][2] = 0.5 * (n[0] * e1v[1] - n[1] * e1v[0]);
+                for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+                Nn = 2.0 * ej->area;
+                /* dn[a][k][m]: derivative of n_m with respect to coordinate k of vertex a */
+                double dn[3][3][3];
+                for (int a = 0; a < 3; ++a) {
+                    const double *pa1 = ej->v[(a + 1) % 3], *pa2 = ej->v[(a + 2) % 3];
+                    double d[3] = {pa1[0] - pa2[0], pa1[1] - pa2[1], pa1[2] - pa2[2]};
+                    for (int k = 0; k < 3; ++k) {
+                        double ek[3] = {0.0, 0.0, 0.0}, cr[3];
+                        ek[k] = 1.0;
+                        cr[0] = ek[1] * d[2] - ek[2] * d[1];
+                        cr[1] = ek[2] * d[0] - ek[0] * d[2];
+                        cr[2] = ek[0] * d[1] - ek[1] * d[0];
+                        double nc = n[0] * cr[0] + n[1] * cr[1] + n[2] * cr[2];
+                        for (int mm = 0; mm < 3; ++mm) dn[a][k][mm] = (cr[mm] - nc * n[mm]) / Nn;
+                    }
+                }
+                int m = 0;
+                if (C.qo.near_on) {
+                    double d2 = 0.0;
+                    for (int k = 0; k < 3; ++k) d2 += (ei->c[k] - ej->c[k]) * (ei->c[k] - ej->c[k]);
+                    if (d2 < C.qo.r1 * C.qo.r1 * ej->lmax2) m = 2;
+                    else if (d2 < C.qo.r2 * C.qo.r2 * ej->lmax2) m = 1;
+                }
+                static const double id[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+                double sub[16][3][3];
+                const int nsub = sub_triangles(id[0], id[1], id[2], m, sub, 0);
+                double gn[3] = {0.0, 0.0, 0.0};  /* Re dS/dn_j summed over the points */
+                for (int qq = 0; qq < 7 * nsub; ++qq) {
+                    const int t = qq / 7, q = qq % 7;
+                    const double *bq = &C.tri_bary[3 * q];
+                    double Bq[3], y[3];
+                    for (int a = 0; a < 3; ++a) Bq[a] = bq[0] * sub[t][0][a] + bq[1] * sub[t][1][a] + bq[2] * sub[t][2][a];
+                    double R = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        y[k] = Bq[0] * ej->v[0][k] + Bq[1] * ej->v[1][k] + Bq[2] * ej->v[2][k];
+                        R += (y[k] - ei->c[k]) * (y[k] - ei->c[k]);
+                    }
+                    R = sqrt(R);
+                    const double wq = C.tri_w[q] / nsub, wA = wq * ej->area;
+                    const double hy = fd_h * R;
+                    for (int32_t l = 0; l < L; ++l) {
+                        cplx sl = s[2 * l] + I * s[2 * l + 1];
+                        cplx T0[9];
+                        kernel_T(ei->c, y, n, sl, &C.mat, T0);
+                        cplx v = contract(T0, w, x, K, L, nrhs, l, i, j);
+                        gm[2] += wA * creal(v);
+                        gm[3] += wA * cimag(v);
+                        for (int k = 0; k < 3; ++k) {
+                            double yp[3] = {y[0], y[1], y[2]}, ym[3] = {y[0], y[1], y[2]};
+                            yp[k] += hy;
+                            ym[k] -= hy;
+                            cplx Tp[9], Tm[9], D[9];
+                            kernel_T(ei->c, yp, n, sl, &C.mat, Tp);
+                            kernel_T(ei->c, ym, n, sl, &C.mat, Tm);
+                            for (int tt = 0; tt < 9; ++tt) D[tt] = (Tp[tt] - Tm[tt]) / (2.0 * hy);
+                            double gk = wA * creal(contract(D, w, x, K, L, nrhs, l, i, j));
+                            for (int a = 0; a < 3; ++a) {
+                                g[3 * (int64_t)tj[a] + k] += Bq[a] * gk;  /* Gauss point of element j */
+                                g[3 * (int64_t)ti[a] + k] -= gk / 3.0;     /* centroid of element i */
+                            }
+                            double ek[3] = {0.0, 0.0, 0.0};
+                            ek[k] = 1.0;
+                            kernel_T(ei->c, y, ek, sl, &C.mat, D);  /* T is linear in n */
+                            gn[k] += wA * creal(contract(D, w, x, K, L, nrhs, l, i, j));
+                        }
+                        for (int which = 0; which < 2; ++which) {
+                            material mp = C.mat, mm_ = C.mat;
+                            double h = fd_h * (which == 0 ? cp : cs);
+                            if (which == 0) { mp.c1 += h; mm_.c1 -= h; }
+                            else { mp.c2 += h; mm_.c2 -= h; }
+                            cplx Tp[9], Tm[9], D[9];
+                            kernel_T(ei->c, y, n, sl, &mp, Tp);
+                            kernel_T(ei->c, y, n, sl, &mm_, Tm);
+                            for (int tt = 0; tt < 9; ++tt) D[tt] = (Tp[tt] - Tm[tt]) / (2.0 * h);
+                            gm[which] += wA * creal(contract(D, w, x, K, L, nrhs, l, i, j));
+                        }
+                        for (int a = 0; a < 3; ++a)
+                            for (int k = 0; k < 3; ++k) g[3 * (int64_t)tj[a] + k] += wq * creal(v) * dA[a][k];
+                    }
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int k = 0; k < 3; ++k)
+                        g[3 * (int64_t)tj[a] + k] += gn[0] * dn[a][k][0] + gn[1] * dn[a][k][1] + gn[2] * dn[a][k][2];
+            }
+        }
+    }
+    for (size_t e = 0; e < 3 * (size_t)n_nodes; ++e) grad_nodes[e] = 0.0;
+    double gmt[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < nth; ++t) {
+        const double *g = gbuf + (size_t)t * (3 * (size_t)n_nodes + 5);
+        for (size_t e = 0; e < 3 * (size_t)n_nodes; ++e) grad_nodes[e] += g[e];
+        for (int k = 0; k < 4; ++k) gmt[k] += g[3 * (size_t)n_nodes + k];
+    }
+    value[0] = gmt[2];
+    value[1] = gmt[3];
+    grad_mat[0] = 0.0;
+    grad_mat[1] = gmt[0];
+    grad_mat[2] = gmt[1];
+    free(gbuf);
+    free((void *)C.el);
+    return 0;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -69,3 +69,31 @@ def test_random_rhs_seeded():
     b = W.random_rhs(0, (2, 5))
     assert a.dtype == np.complex128 and np.array_equal(a, b)
     assert not np.array_equal(a, W.random_rhs(1, (2, 5)))
+
+
+@pytest.mark.parametrize("h", [0.1, 0.05])
+def test_stator_shell_is_a_closed_oriented_surface(h):
+    X, T = W.stator_shell(h)
+    v0, v1, v2 = X[T[:, 0]], X[T[:, 1]], X[T[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(v1 - v0, v2 - v0), axis=1)
+    assert area.min() > 0.1 * h * h
+    # every edge in two triangles, traversed once in each direction (consistent orientation)
+    D = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    _, dcount = np.unique(D, axis=0, return_counts=True)
+    assert dcount.max() == 1
+    E = np.sort(D, axis=1)
+    _, ecount = np.unique(E, axis=0, return_counts=True)
+    assert np.all(ecount == 2)
+    # outward normals: the divergence theorem gives the solid's volume (annulus minus slots),
+    # up to the chords of the circles
+    vol = np.einsum("ij,ij->i", v0, np.cross(v1, v2)).sum() / 6.0
+    exact = 1.5 * (np.pi * (1.0 - 0.49) - 36 * (0.05 / 0.7) * (0.8**2 - 0.7**2) / 2.0)
+    assert abs(vol - exact) < 2e-3 * exact
+    assert np.all(X[:, 2] >= 0.0) and np.all(X[:, 2] <= 1.5)
+    assert np.abs(np.hypot(X[:, 0], X[:, 1])).max() <= 1.0 + 1e-12
+
+
+def test_stator_shell_full_size():
+    # the configuration's ~100k triangles at h = 0.0225
+    X, T = W.stator_shell(0.0225)
+    assert 90000 < len(T) < 115000
