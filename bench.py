@@ -240,6 +240,66 @@ def adjoint_leg(args, dev, torch):
     return out
 
 
+def stator_leg(args, dev, torch):
+    """The stator-shell configuration at a reduced mesh (reported apart from value): coaxial
+    cylinders r = 1 and 0.7, length 1.5, 36 slots 0.05 x 0.1 in the bore, c_p = 1, c_s = 0.55,
+    128 contour points, the single layer compressed in mixed precision at eps3d 1e-5, and the
+    solution of V(s_l) t_l = g_l at every contour point by iterative refinement with the
+    matrix-free FP64 operator as the fine one and the compressed mixed one as the inner one.
+    The full configuration (about 100k triangles) would need the compression rate times
+    184 TB of storage."""
+    from paper_2607_15292_amd import binding as B
+    from paper_2607_15292_amd import workloads as W
+    X, T = W.stator_shell(args.stator_h)
+    K, L = len(T), 128
+    s = W.bdf2_contour(L, 0.1)
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(1.0, 1.0, 0.55)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V = c.compress(B.OP_V, eps3d=1e-5, leaf=64, eta=1.5, prec=B.PREC_MIXED)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = V.stats()
+    x = W.random_rhs(81, (1, L, 3 * K))
+    xd = torch.tensor(x, device=dev)
+    y = V.apply(xd).cpu().numpy()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(3):
+        V.apply(xd)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    Vf = c.matrix_free(B.OP_V)
+    g = torch.tensor(W.random_rhs(82, (1, L, 3 * K)), device=dev)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    tsol, sst = Vf.solve(g, inner=V, tol=1e-6, inner_tol=1e-3)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    rows = np.arange(0, K, max(1, K // 12))[:12]
+    out = {"workload": "stator shell h %.3f: %d triangles (%d DOF), c_s 0.55, 128 BDF2 gCQ points, V mixed eps3d "
+                       "1e-5, leaf 64, eta 1.5; solve with the matrix-free FP64 V as the fine operator" % (args.stator_h, K, 3 * K),
+           "elements": K, "compress_seconds": t1 - t0, "kernel_ms": st["kernel_ms"],
+           "compression_rate": st["compression_rate"], "compressed_gb": st["bytes"] / 1e9,
+           "dense_gb": L * 9.0 * K * K * 16 / 1e9, "rank_mean": st["rank_mean"],
+           "ms_per_product": (t3 - t2) / 3 * 1e3, "solve_seconds": t5 - t4,
+           "solve_refinements": sst["refinements"], "solve_inner_products": sst["iterations"],
+           "solve_rel_residual": sst["rel_residual"], "solve_converged": bool(sst["converged"]),
+           "full_size_dense_tb": 128 * 9.0 * 1e5 ** 2 * 16 / 1e12,
+           "_check": {"X": X, "T": T, "s": s, "rows": rows, "x": x,
+                      "y": y.reshape(1, L, K, 3)[:, :, rows, :].reshape(1, L, -1)}}
+    log("stator: K %d, compress %.2f s (rate %.4f, %.1f GB), product %.1f ms, solve %.2f s (%d refinements)"
+        % (K, t1 - t0, st["compression_rate"], st["bytes"] / 1e9, out["ms_per_product"], t5 - t4, sst["refinements"]))
+    V.destroy()
+    Vf.destroy()
+    c.close()
+    return out
+
+
 def _pair_class(X, T, I, J, r1sq=2.25, r2sq=9.0):
     """Class of the near rule for the pairs (I, J) as the library decides it: 2 if
     |c_i - c_j|^2 < r1^2 lmax_j^2, 1 if < r2^2 lmax_j^2, else 0 (same arithmetic order)."""
@@ -465,6 +525,8 @@ def main():
     ap.add_argument("--batch-nrhs", type=int, default=32)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg (reported apart from value)")
     ap.add_argument("--no-timestep", action="store_true", help="skip the time-stepping leg (reported apart from value)")
+    ap.add_argument("--no-stator", action="store_true", help="skip the stator-shell leg (reported apart from value)")
+    ap.add_argument("--stator-h", type=float, default=0.1, help="element size of the stator-shell leg")
     ap.add_argument("--no-iloop", action="store_true",
                     help="skip the leg that compresses V and I/2+K in the paper's order of the per-slice ACA")
     ap.add_argument("--sequential", action="store_true",
@@ -734,6 +796,7 @@ def main():
     batched = None if args.no_batch else batched_leg(args, dev, torch)
     adjoint = None if args.no_adjoint else adjoint_leg(args, dev, torch)
     timestep = None if args.no_timestep else timestep_leg(args, dev, torch)
+    stator = None if args.no_stator else stator_leg(args, dev, torch)
 
     # roofline of the dominant compression kernel: algorithmic flops over event-timed device
     # time, summed over the timed steps, for the recompression kernel (k_face_recomp) and the
@@ -842,6 +905,13 @@ def main():
                 berr[name] = float(np.max(np.linalg.norm(yg - ref, axis=-1) / np.linalg.norm(ref, axis=-1)))
             batched["rel_err_sampled_rows"] = berr
             log("batched rel err on sampled rows:", berr)
+        if stator is not None:
+            chk = stator["_check"]
+            ref = oracle.Problem(chk["X"], chk["T"], chk["s"], 1.0, 1.0, 0.55, near_on=True).matvec_rows(
+                0, chk["rows"], chk["x"])
+            stator["rel_err_sampled_rows"] = float(np.max(np.linalg.norm(chk["y"] - ref, axis=-1)
+                                                          / np.linalg.norm(ref, axis=-1)))
+            log("stator rel err on sampled rows: %.3e" % stator["rel_err_sampled_rows"])
         if timestep is not None:
             from oracle import cq
             chk = timestep["_check"]
@@ -861,7 +931,7 @@ def main():
             errs["fp64"] = {str(opk): rel(y, refs[opk]) for opk, y in zip(ops_list, fp64["ys"])}
             errs["fp64_eps%.0e" % args.eps_fp64_strict] = {str(opk): rel(y, refs[opk])
                                                            for opk, y in zip(ops_list, fp64["strict"]["ys"])}
-    for leg in (batched, timestep):
+    for leg in (batched, timestep, stator):
         if leg is not None:
             leg.pop("_check", None)
     if iloop is not None:
@@ -907,6 +977,7 @@ def main():
         "adjoint": adjoint,
         "timestep": timestep,
         "in_loop_order": iloop,
+        "stator": stator,
         "cpu_baseline": cpu,
     }
     if fp64:

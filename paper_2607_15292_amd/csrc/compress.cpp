@@ -1046,7 +1046,7 @@ int compress_impl(bem_ctx* ctx, int op, const bem_aca_opts& o, bem_op* out)
         DevBuf np(&ctx->cache), segd;
         bool ok = true;
         try {
-            np.alloc(std::max<long long>(top, 256));
+            np.alloc(std::max<long long>(top, 256), true);
             segd.alloc(std::max<size_t>(seg.size(), 3) * sizeof(long long));
         } catch (const DevBuf::bem_nomem&) {
             ok = false;  // not enough memory for the copy: keep the working pool

@@ -28,12 +28,12 @@ struct MemCache {
     static constexpr size_t MIN_BYTES = (size_t)64 << 20;  // smaller buffers bypass the cache
     std::multimap<size_t, void*> bufs;
     size_t cached = 0;
-    // smallest cached buffer of at least n bytes and (unless any) at most 1.5 n + 64 MiB; null
-    // if none
-    void* take(size_t n, size_t* got, bool any = false)
+    // smallest cached buffer of at least n bytes and at most slack * n + 64 MiB (any size when
+    // slack <= 0); null if none
+    void* take(size_t n, size_t* got, double slack = 1.5)
     {
         auto it = bufs.lower_bound(n);
-        if (it == bufs.end() || (!any && (double)it->first > 1.5 * (double)n + (double)(64 << 20))) return nullptr;
+        if (it == bufs.end() || (slack > 0 && (double)it->first > slack * (double)n + (double)(64 << 20))) return nullptr;
         void* q = it->second;
         *got = it->first;
         cached -= it->first;
@@ -65,13 +65,15 @@ struct DevBuf {
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
-    void alloc(size_t n)
+    // lasting: the buffer outlives the call (an operator's compacted storage): a cached buffer
+    // serves it only when at most 1/16 larger, never a larger one taken to save a mapping
+    void alloc(size_t n, bool lasting = false)
     {
         release();
         if (n == 0) return;
         if (cache && n >= MemCache::MIN_BYTES) {
             size_t got = 0;
-            if (void* q = cache->take(n, &got)) {
+            if (void* q = cache->take(n, &got, lasting ? 1.0625 : 1.5)) {
                 p = q;
                 bytes = got;
                 return;
@@ -82,11 +84,12 @@ struct DevBuf {
             // a kernel with a private segment starts, queues): evict cached buffers, largest
             // first, else refuse
             size_t fr = 0, tot = 0;
-            if (cache && hipMemGetInfo(&fr, &tot) == hipSuccess && fr < n + RESERVE) {
-                // short of memory: a larger cached buffer serves before any is returned to
-                // the driver (freeing and mapping tens of GB takes longer than the kernels)
+            if (cache && !lasting && hipMemGetInfo(&fr, &tot) == hipSuccess && fr < n + RESERVE) {
+                // short of memory: a larger cached buffer serves a working buffer before any
+                // is returned to the driver (freeing and mapping tens of GB takes longer than
+                // the kernels)
                 size_t got = 0;
-                if (void* q = cache->take(n, &got, true)) {
+                if (void* q = cache->take(n, &got, 0.0)) {
                     p = q;
                     bytes = got;
                     return;
