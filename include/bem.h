@@ -421,13 +421,30 @@ int bem_matrix_free(bem_ctx *ctx, int32_t op, bem_op **out);
  * (discrVK) with the context's quadrature (regular, near and self rules), the class of every
  * pair held fixed.  Regular and near pairs are differentiated exactly (chain rule through the
  * Gauss points, also those of the near rule's sub-triangles, the collocation points and the
- * element areas; speeds through the kernel); self pairs by central differences of the polar
- * rule (relative step 1e-5).  Entries are
- * recomputed, never stored.  w, x: [nrhs][L][3K] complex128, mesh order, host or device per
- * flags.  value: [2] (Re, Im S); grad_nodes: [n_nodes][3]; grad_mat: [3] = d/d rho, d/d c_p,
- * d/d c_s; each output may be NULL.  Cost: K^2 L nrhs kernel evaluations with derivatives. */
+ * element areas; speeds through the kernel); self pairs by the derivative of the self integral
+ * (the gradient of U weighted by lambda_a - 1/3, the speed derivatives of U and the area
+ * term, integrated by the polar rule).  Entries are recomputed, never stored.  w, x:
+ * [nrhs][L][3K] complex128, mesh order, host or device per flags.  value: [2] (Re, Im S);
+ * grad_nodes: [n_nodes][3]; grad_mat: [3] = d/d rho, d/d c_p, d/d c_s; each output may be
+ * NULL.  Cost: K^2 L nrhs kernel evaluations with derivatives.  Errors: BEM_ERR_ARG for
+ * nrhs < 1, missing buffers or unknown flags; BEM_ERR_STATE without mesh, material and
+ * contour points or with several components. */
 int bem_adjoint_v(bem_ctx *ctx, int32_t nrhs, const void *w, const void *x, int32_t flags, double *value,
                   double *grad_nodes, double *grad_mat);
+
+/* Adjoint of the double layer (an extension, as bem_adjoint_v): S = sum_{r, l} w[r][l]^T
+ * A(s_l) x[r][l] with A = K (op BEM_OP_K) or I/2 + K (BEM_OP_HK, the free term of eq. (SBIE)
+ * at the centroids, whose derivative is zero), the traction kernel of Sec. 2.1 against the
+ * piecewise-constant basis, and the gradient of Re S with respect to the node coordinates and
+ * the material, pair classes held fixed.  Regular and near pairs: chain rule through the Gauss
+ * points, the element normal n_j (dn = (I - n n^T)(dP_a x (P_{a+1} - P_{a+2})) / |N|), the
+ * area and the collocation point, with the closed-form R- and speed derivatives of the
+ * traction kernel (second R-derivatives of A and B included).  Self pairs (principal values):
+ * central differences of the polar rule, step 1e-5 times the longest edge per vertex
+ * coordinate and 1e-5 times the speed per speed.  T does not depend on rho: grad_mat[0] = 0.
+ * Arguments, layouts and errors as bem_adjoint_v; BEM_ERR_ARG also for another op. */
+int bem_adjoint_k(bem_ctx *ctx, int32_t op, int32_t nrhs, const void *w, const void *x, int32_t flags,
+                  double *value, double *grad_nodes, double *grad_mat);
 
 /* ---- Batched products of several compressed operators ------------------------------------
  * The all-frequency product of bem_apply (the face-fibre form of eq. (3DacaMult) at every

@@ -1,6 +1,6 @@
-"""Differentiable single-layer products and solutions: torch.autograd.Function over the
-library's matrix-free product, transposed solves and adjoint (bem_apply_mf, bem_solve with
-BEM_TRANSPOSE, bem_adjoint_v).  The gradients recompute the entries; nothing of the
+"""Differentiable single- and double-layer products and single-layer solutions:
+torch.autograd.Function over the library's matrix-free product, transposed solves and
+adjoints (bem_apply_mf, bem_solve with BEM_TRANSPOSE, bem_adjoint_v, bem_adjoint_k).  The gradients recompute the entries; nothing of the
 operator is stored for them.
 
     y = single_layer(bem_ctx, nodes, material, x)
@@ -10,7 +10,8 @@ any device; the triangles and contour points are those set on `bem_ctx`), materi
 (rho, c_p, c_s) as a float64 tensor [3], and x complex128 [nrhs, L, 3K] on the GPU.  The
 gradients are those of the discrete operator with the context's quadrature (pair classes of
 the near rule held fixed): the node coordinates and the speeds by the adjoint kernel, x by the
-transposed product.
+transposed product.  double_layer(bem_ctx, nodes, material, x, tris, free_term=True) is the
+same for (I/2 + K(s_l)) x or K(s_l) x.
 """
 from __future__ import annotations
 
@@ -59,6 +60,43 @@ def single_layer(bem_ctx, nodes, material, x, tris):
     """y[r, l] = V(s_l) x[r, l], differentiable in nodes, material and x."""
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     return SingleLayer.apply(bem_ctx, tris, nodes, material, x)
+
+
+class DoubleLayer(torch.autograd.Function):
+    """y[r, l] = A(s_l) x[r, l] with A = K or I/2 + K (matrix-free); backward as SingleLayer
+    with the double layer's adjoint kernel (bem_adjoint_k) and its transposed product."""
+
+    @staticmethod
+    def forward(fctx, bem_ctx, tris, nodes, material, x, op):
+        _load(bem_ctx, tris, nodes, material)
+        y = bem_ctx.apply_mf(op, x.contiguous())
+        fctx.bem = bem_ctx
+        fctx.tris = tris
+        fctx.op = op
+        fctx.save_for_backward(nodes, material, x)
+        return y
+
+    @staticmethod
+    def backward(fctx, gy):
+        nodes, material, x = fctx.saved_tensors
+        bem = fctx.bem
+        _load(bem, fctx.tris, nodes, material)
+        w = gy.conj().resolve_conj().contiguous()
+        g_nodes = g_mat = g_x = None
+        if fctx.needs_input_grad[2] or fctx.needs_input_grad[3]:
+            _, gn, gm = bem.adjoint_k(w, x.contiguous(), op=fctx.op)
+            g_nodes = torch.as_tensor(gn, dtype=nodes.dtype, device=nodes.device)
+            g_mat = torch.as_tensor(gm, dtype=material.dtype, device=material.device)
+        if fctx.needs_input_grad[4]:
+            g_x = bem.apply_mf(fctx.op, w, transpose=True).conj()
+        return None, None, g_nodes, g_mat, g_x, None
+
+
+def double_layer(bem_ctx, nodes, material, x, tris, free_term=True):
+    """y[r, l] = (I/2 + K(s_l)) x[r, l] (free_term) or K(s_l) x[r, l], differentiable in nodes,
+    material and x."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    return DoubleLayer.apply(bem_ctx, tris, nodes, material, x, B.OP_HK if free_term else B.OP_K)
 
 
 class SingleLayerSolve(torch.autograd.Function):

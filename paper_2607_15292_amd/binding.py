@@ -131,6 +131,7 @@ _SIGS = {
     "bem_apply_linear_dl": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32]),
     "bem_matrix_free": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "bem_adjoint_v": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]),
+    "bem_adjoint_k": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]),
     "bem_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "bem_batch_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
@@ -407,6 +408,24 @@ class Context:
         gn = np.zeros((self.n_nodes, 3))
         gm = np.zeros(3)
         self._check(lib().bem_adjoint_v(self.h, int(nrhs), pw, px, fl, val.ctypes.data, gn.ctypes.data,
+                                        gm.ctypes.data))
+        return complex(val[0], val[1]), gn, gm
+
+    def adjoint_k(self, w, x, op=OP_K):
+        """(S, grad_nodes [n_nodes, 3], grad_mat [rho, c_p, c_s]) of S = sum w^T A(s_l) x with
+        A = K (op OP_K) or I/2 + K (OP_HK), gradient of Re S; w, x as adjoint_v."""
+        nrhs = x.shape[0]
+        if _is_torch(x):
+            self._sync_torch_stream()
+        shp = (nrhs, self.L, 3 * self.K)
+        pw, fl = _ptr(w, shp)
+        px, fl2 = _ptr(x, shp)
+        if fl != fl2:
+            raise ValueError("w and x must both be host arrays or both device tensors")
+        val = np.zeros(2)
+        gn = np.zeros((self.n_nodes, 3))
+        gm = np.zeros(3)
+        self._check(lib().bem_adjoint_k(self.h, int(op), int(nrhs), pw, px, fl, val.ctypes.data, gn.ctypes.data,
                                         gm.ctypes.data))
         return complex(val[0], val[1]), gn, gm
 

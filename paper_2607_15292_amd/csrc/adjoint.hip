@@ -394,6 +394,362 @@ __global__ __launch_bounds__(64) void k_adjoint_self(DevCtx c, int nrhs, const z
     o[12] = Vi;
 }
 
+// ---------------------------------------------------------------- double layer
+
+// psi(z) = sum_n (n - 1)(n - 2) (-z)^n / (n! (n + 2)) for both waves: the second derivative of
+// the series part I / r of A and B is (psi(x2) / c2^2 - psi(x1) / c1^2) / r^3.
+BEM_HD void psi2(zd x1, zd x2, zd& p1, zd& p2)
+{
+    constexpr int N = Series<double>::N;
+    const zd w1 = -x1, w2 = -x2;
+    const double cN = (double)((N - 1) * (N - 2)) * ser_c<double>(N, false);
+    zd a = {cN, 0.0}, b = {cN, 0.0};
+#pragma unroll 1
+    for (int n = N - 1; n >= 0; --n) {
+        const zd cn = {(double)((n - 1) * (n - 2)) * ser_c<double>(n, false), 0.0};
+        a = fma_c(a, w1, cn);
+        b = fma_c(b, w2, cn);
+    }
+    p1 = a;
+    p2 = b;
+}
+
+// The traction kernel's scalars and their derivatives at distance R: P1, P2, P3 of 4 pi T =
+// P1 rh n^T + P2 (dr/dn I + n rh^T) + P3 dr/dn rh rh^T, their R-derivatives and their c1 and
+// c2 derivatives.  With u = 1/R, x_a = s R / c_a, e_ar = exp(-x_a) / (c_a^2 R), q_a = y_a +
+// y_a^2, y_a = 1 / x_a:
+//   A'' = u^2 (e2r (x2^2 + 3 x2 + 7 + 12 q2) - e1r (x1 + 5 + 12 q1)),
+//   B'' = u^2 (e1r (x1^2 + 5 x1 + 17 + 36 q1) - e2r (x2^2 + 5 x2 + 17 + 36 q2))
+// (|x2| >= 1; below, A'' = u^2 e2r (x2^2 + 2 x2 + 2) - (I/r)'' and B'' = 3 (I/r)'' + u^2 (e1r
+// (x1^2 + 2 x1 + 2) - e2r (x2^2 + 2 x2 + 2)), the branch of the forward kernel); the speed
+// derivatives of A, B (those of the single layer) differentiated in R:
+//   dA'/dc1 = u (x1 + 1) e1r / c1, dA'/dc2 = u (1 + x2 - x2^2) e2r / c2,
+//   dB'/dc1 = -u (x1^2 + x1 + 1) e1r / c1, dB'/dc2 = u (x2^2 + x2 + 1) e2r / c2.
+// With lamc = c1^2 - 2 c2^2, G = A' + B' + 2 B u: P1 = lamc G + 2 c2^2 B u, P2 = c2^2 (A' + B u),
+// P3 = 2 c2^2 (B' - 2 B u), differentiated term by term (lamc and c2^2 depend on the speeds).
+struct TDer {
+    zd P[3], Pr[3], Pc1[3], Pc2[3];
+};
+
+__device__ __forceinline__ void traction_der(double R, double Rinv, zd s, zd sinv, const Mat<double>& M, TDer& o)
+{
+    zd A, B, Ad, Bd;
+    kernel_AB<double, true>(R, Rinv, s, sinv, M, A, B, Ad, Bd);
+    const zd x1 = s * (R * M.ic1), x2 = s * (R * M.ic2);
+    const zd e1r = M_<double>::cexpm(x1) * (M.ic1s * Rinv), e2r = M_<double>::cexpm(x2) * (M.ic2s * Rinv);
+    const double u = Rinv, u2 = Rinv * Rinv;
+    const zd one = {1.0, 0.0};
+    zd Add, Bdd;
+    if (abs2(x2) < 1.0) {
+        zd p1, p2;
+        psi2(x1, x2, p1, p2);
+        const zd Irr = (p2 * M.ic2s - p1 * M.ic1s) * (u2 * u);
+        const zd f1 = x1 * x1 + 2.0 * x1 + zd{2.0, 0.0}, f2 = x2 * x2 + 2.0 * x2 + zd{2.0, 0.0};
+        Add = (e2r * f2) * u2 - Irr;
+        Bdd = 3.0 * Irr + (e1r * f1 - e2r * f2) * u2;
+    } else {
+        const zd y1 = sinv * (M.c1 * Rinv), y2 = sinv * (M.c2 * Rinv);
+        const zd q1 = y1 + y1 * y1, q2 = y2 + y2 * y2;
+        Add = (e2r * (x2 * x2 + 3.0 * x2 + 12.0 * q2 + zd{7.0, 0.0}) - e1r * (x1 + 12.0 * q1 + zd{5.0, 0.0})) * u2;
+        Bdd = (e1r * (x1 * x1 + 5.0 * x1 + 36.0 * q1 + zd{17.0, 0.0}) -
+               e2r * (x2 * x2 + 5.0 * x2 + 36.0 * q2 + zd{17.0, 0.0})) * u2;
+    }
+    const zd A1 = e1r * (-M.ic1), A2 = (e2r * (x2 - one)) * M.ic2;
+    const zd B1 = (e1r * (x1 + one)) * M.ic1, B2 = (e2r * (x2 + one)) * (-M.ic2);
+    const zd A1d = (e1r * (x1 + one)) * (u * M.ic1), A2d = (e2r * (one + x2 - x2 * x2)) * (u * M.ic2);
+    const zd B1d = (e1r * (x1 * x1 + x1 + one)) * (-u * M.ic1), B2d = (e2r * (x2 * x2 + x2 + one)) * (u * M.ic2);
+    const double lamc = M.lamc, c2s = M.c2s, c1 = M.c1, c2 = M.c2;
+    const zd Bu = B * u, G = Ad + Bd + 2.0 * Bu;
+    o.P[0] = lamc * G + (2.0 * c2s) * Bu;
+    o.P[1] = c2s * (Ad + Bu);
+    o.P[2] = (2.0 * c2s) * (Bd - 2.0 * Bu);
+    o.Pr[0] = lamc * (Add + Bdd + (2.0 * u) * (Bd - Bu)) + (2.0 * c2s * u) * (Bd - Bu);
+    o.Pr[1] = c2s * (Add + u * (Bd - Bu));
+    o.Pr[2] = (2.0 * c2s) * (Bdd - (2.0 * u) * (Bd - Bu));
+    o.Pc1[0] = (2.0 * c1) * G + lamc * (A1d + B1d + (2.0 * u) * B1) + (2.0 * c2s * u) * B1;
+    o.Pc1[1] = c2s * (A1d + u * B1);
+    o.Pc1[2] = (2.0 * c2s) * (B1d - (2.0 * u) * B1);
+    o.Pc2[0] = (-4.0 * c2) * G + lamc * (A2d + B2d + (2.0 * u) * B2) + (4.0 * c2) * Bu + (2.0 * c2s * u) * B2;
+    o.Pc2[1] = (2.0 * c2) * (Ad + Bu) + c2s * (A2d + u * B2);
+    o.Pc2[2] = (4.0 * c2) * (Bd - 2.0 * Bu) + (2.0 * c2s) * (B2d - (2.0 * u) * B2);
+}
+
+// Regular and near pairs of the double layer (i != j; pair classes held fixed), the layout of
+// k_adjoint_v.  With W = w_i x_j^T (one right-hand side), rh = r / R, dr/dn = rh.n and
+// 4 pi v = P1 S1 + P2 S2 + P3 S3, S1 = rh^T W n, S2 = tr(W) dr/dn + n^T W rh, S3 = rh^T W rh dr/dn:
+//   4 pi grad_r v = rh (P1' S1 + P2' S2 + P3' S3) + (cw w_i + cx x_j + cn n - (P1 S1 + P2 S2 +
+//                   3 P3 S3) rh) / R,
+//   cw = P1 (x.n) + P3 dr/dn (x.rh), cx = P2 (w.n) + P3 dr/dn (w.rh), cn = P2 (w.x) + P3 (w.rh)(x.rh);
+//   4 pi grad_n v = P1 (w.rh) x_j + P2 (x.rh) w_i + cn rh,
+// and the normal n_j = N / |N|, N = (P_1 - P_0) x (P_2 - P_0), moves with vertex a as
+// dn = (I - n n^T)(dP_a x (P_{a+1} - P_{a+2})) / |N|.  Outputs as k_adjoint_v.
+__global__ __launch_bounds__(WG) void k_adjoint_k(DevCtx c, int nrhs, const zd* __restrict__ w,
+                                                  const zd* __restrict__ x, double* __restrict__ gJ,
+                                                  double* __restrict__ gI, double* __restrict__ gM)
+{
+    __shared__ double red[WG / 64][9];
+    const Geo& g = c.geo;
+    const int K = g.K, L = c.fr.L;
+    const size_t M = 3 * (size_t)K;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const bool act = i < K;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j0 = blockIdx.y * JB, j1 = min(K, j0 + JB);
+    const double pref = c.md.inv4pi;
+    double ci[3] = {0.0, 0.0, 0.0}, mat[4] = {0.0, 0.0, 0.0, 0.0};
+    const double xi[3] = {act ? g.cx[i] : 0.0, act ? g.cy[i] : 0.0, act ? g.cz[i] : 0.0};
+    for (int j = j0; j < j1; ++j) {
+        double gj[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) gj[t] = 0.0;
+        if (act && i != j) {
+            double P[3][3];
+            for (int a = 0; a < 3; ++a) {
+                P[a][0] = g.vx[a * K + j];
+                P[a][1] = g.vy[a * K + j];
+                P[a][2] = g.vz[a * K + j];
+            }
+            const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+            const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+            const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+            double dA[3][3];
+            dA[1][0] = 0.5 * (e2[1] * n[2] - e2[2] * n[1]);
+            dA[1][1] = 0.5 * (e2[2] * n[0] - e2[0] * n[2]);
+            dA[1][2] = 0.5 * (e2[0] * n[1] - e2[1] * n[0]);
+            dA[2][0] = 0.5 * (n[1] * e1[2] - n[2] * e1[1]);
+            dA[2][1] = 0.5 * (n[2] * e1[0] - n[0] * e1[2]);
+            dA[2][2] = 0.5 * (n[0] * e1[1] - n[1] * e1[0]);
+            for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+            const int m = pair_class(g, i, j, c.qt);
+            const int nsub = 1 << (2 * m);
+            const double wsub = g.area[j] * pref / (double)nsub;
+            double gn[3] = {0.0, 0.0, 0.0};  // d Re S / d n_j of this pair
+#pragma unroll 1
+            for (int u = 0; u < nsub; ++u) {
+            double Sb[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+#pragma unroll 1
+            for (int lev = m - 1; lev >= 0; --lev) {
+                const int ch = (u >> (2 * lev)) & 3;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double p0 = Sb[0][a], p1 = Sb[1][a], p2 = Sb[2][a];
+                    const double m01 = 0.5 * (p0 + p1), m12 = 0.5 * (p1 + p2), m20 = 0.5 * (p2 + p0);
+                    if (ch == 0) { Sb[1][a] = m01; Sb[2][a] = m20; }
+                    else if (ch == 1) { Sb[0][a] = m01; Sb[2][a] = m12; }
+                    else if (ch == 2) { Sb[0][a] = m20; Sb[1][a] = m12; }
+                    else { Sb[0][a] = m01; Sb[1][a] = m12; Sb[2][a] = m20; }
+                }
+            }
+#pragma unroll 1
+            for (int q = 0; q < 7; ++q) {
+                const double* bq = c.qt.b7 + 3 * q;
+                double b[3], y[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) b[a] = bq[0] * Sb[0][a] + bq[1] * Sb[1][a] + bq[2] * Sb[2][a];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) y[k] = b[0] * P[0][k] + b[1] * P[1][k] + b[2] * P[2][k];
+                const double r[3] = {y[0] - xi[0], y[1] - xi[1], y[2] - xi[2]};
+                const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                const double Rinv = 1.0 / sqrt(R2), R = R2 * Rinv;
+                const double rh[3] = {r[0] * Rinv, r[1] * Rinv, r[2] * Rinv};
+                const double rn = rh[0] * n[0] + rh[1] * n[1] + rh[2] * n[2];
+                double Gr[3] = {0.0, 0.0, 0.0}, Gn[3] = {0.0, 0.0, 0.0}, V = 0.0, Vi = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll 1
+                for (int l = 0; l < L; ++l) {
+                    TDer T;
+                    traction_der(R, Rinv, c.fr.s[l], c.fr.sinv[l], c.md, T);
+#pragma unroll 1
+                    for (int rr = 0; rr < nrhs; ++rr) {
+                        const zd* up = w + ((size_t)rr * L + l) * M + 3 * (size_t)i;
+                        const zd* vp = x + ((size_t)rr * L + l) * M + 3 * (size_t)j;
+                        const zd uu[3] = {up[0], up[1], up[2]}, vv[3] = {vp[0], vp[1], vp[2]};
+                        const zd wn = uu[0] * n[0] + uu[1] * n[1] + uu[2] * n[2];
+                        const zd xn = vv[0] * n[0] + vv[1] * n[1] + vv[2] * n[2];
+                        const zd wh = uu[0] * rh[0] + uu[1] * rh[1] + uu[2] * rh[2];
+                        const zd xh = vv[0] * rh[0] + vv[1] * rh[1] + vv[2] * rh[2];
+                        const zd be = uu[0] * vv[0] + uu[1] * vv[1] + uu[2] * vv[2];
+                        const zd de = wh * xh;
+                        const zd S1 = wh * xn, S2 = be * rn + wn * xh, S3 = de * rn;
+                        const zd val = T.P[0] * S1 + T.P[1] * S2 + T.P[2] * S3;
+                        const zd rad = T.Pr[0] * S1 + T.Pr[1] * S2 + T.Pr[2] * S3;
+                        const zd cw = T.P[0] * xn + T.P[2] * (rn * xh);
+                        const zd cxj = T.P[1] * wn + T.P[2] * (rn * wh);
+                        const zd cn = T.P[1] * be + T.P[2] * de;
+                        const zd ch = -(T.P[0] * S1 + T.P[1] * S2 + 3.0 * (T.P[2] * S3));
+                        const zd a1 = T.P[0] * wh, a2 = T.P[1] * xh;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            Gr[k] += rh[k] * rad.re + Rinv * (cw * uu[k] + cxj * vv[k] + ch * rh[k]).re + Rinv * n[k] * cn.re;
+                            Gn[k] += (a1 * vv[k] + a2 * uu[k]).re + rh[k] * cn.re;
+                        }
+                        V += val.re;
+                        Vi += val.im;
+                        m1 += (T.Pc1[0] * S1 + T.Pc1[1] * S2 + T.Pc1[2] * S3).re;
+                        m2 += (T.Pc2[0] * S1 + T.Pc2[1] * S2 + T.Pc2[2] * S3).re;
+                    }
+                }
+                const double w7 = c.qt.w7[q] * pref / (double)nsub, wA = c.qt.w7[q] * wsub;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double gk = wA * Gr[k];
+                    ci[k] -= gk;
+                    gn[k] += wA * Gn[k];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) gj[3 * a + k] += b[a] * gk + w7 * V * dA[a][k];
+                }
+                mat[0] += wA * m1;
+                mat[1] += wA * m2;
+                mat[2] += wA * V;
+                mat[3] += wA * Vi;
+            }
+            }
+            // the normal's motion with the vertices
+            const double iN = 0.5 / g.area[j];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+                const double d[3] = {P[a1][0] - P[a2][0], P[a1][1] - P[a2][1], P[a1][2] - P[a2][2]};
+                // (e_k x d) . gn - (n . (e_k x d)) (n . gn) = e_k . (d x gn - (n.gn) (d x n))
+                const double ng = n[0] * gn[0] + n[1] * gn[1] + n[2] * gn[2];
+                const double dg[3] = {d[1] * gn[2] - d[2] * gn[1], d[2] * gn[0] - d[0] * gn[2], d[0] * gn[1] - d[1] * gn[0]};
+                const double dn[3] = {d[1] * n[2] - d[2] * n[1], d[2] * n[0] - d[0] * n[2], d[0] * n[1] - d[1] * n[0]};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) gj[3 * a + k] += iN * (dg[k] - ng * dn[k]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const double sv = wsum(gj[t]);
+            if (lane == 0) red[wv][t] = sv;
+        }
+        __syncthreads();
+        if (threadIdx.x < 9) {
+            double sv = 0.0;
+            for (int q = 0; q < WG / 64; ++q) sv += red[q][threadIdx.x];
+            gJ[((size_t)blockIdx.x * K + j) * 9 + threadIdx.x] = sv;
+        }
+        __syncthreads();
+    }
+    if (act)
+        for (int k = 0; k < 3; ++k) gI[((size_t)blockIdx.y * K + i) * 3 + k] = ci[k];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double sv = wsum(mat[t]);
+        if (lane == 0) red[wv][t] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double sv = 0.0;
+        for (int q = 0; q < WG / 64; ++q) sv += red[q][threadIdx.x];
+        gM[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = sv;
+    }
+}
+
+// Self pairs of the double layer: sum_{r, l} w_j^T E(s_l) x_j of the principal-value polar rule
+// (the forward rule, geometry explicit) for one perturbed element or material.
+__device__ double kself_value(const DevCtx& c, const double P[3][3], const double xc[3], const double n[3],
+                              const Mat<double>& M, int nrhs, const zd* __restrict__ w, const zd* __restrict__ x,
+                              int j, double* im)
+{
+    const int K = c.geo.K, L = c.fr.L;
+    const size_t Mv = 3 * (size_t)K;
+    zd tot = {0.0, 0.0};
+#pragma unroll 1
+    for (int l = 0; l < L; ++l) {
+        blk E = blk_zero();
+#pragma unroll 1
+        for (int a = 0; a < 3; ++a)
+#pragma unroll 1
+            for (int it = 0; it < c.qt.nt; ++it) {
+                blk e;
+                self_line<1>(xc, P[a], P[(a + 1) % 3], n, it, c.fr.s[l], c.fr.sinv[l], M, c.qt, e);
+                for (int t = 0; t < 9; ++t) E.a[t] += e.a[t];
+            }
+#pragma unroll 1
+        for (int rr = 0; rr < nrhs; ++rr) {
+            const zd* up = w + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
+            const zd* vp = x + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) tot = fma_c(E.a[3 * a + b], up[a] * vp[b], tot);
+        }
+    }
+    if (im) *im = tot.im;
+    return tot.re;
+}
+
+// Self pairs of the double layer by central differences of the principal-value rule: thread
+// per (element j, task t); t = 0: Re and Im of the self terms of S (with the free term I/2
+// when free_term); t = 1 .. 9: vertex a = (t - 1) / 3, coordinate k = (t - 1) % 3, step
+// fd_h * (longest edge), the perturbed element's centroid and normal recomputed; t = 10, 11:
+// c1, c2 (materials m1p, m1m, m2p, m2m at c * (1 +- fd_h)).  out[j][13] as k_adjoint_self.
+__global__ __launch_bounds__(64) void k_adjoint_kself(DevCtx c, Mat<double> m1p, Mat<double> m1m, Mat<double> m2p,
+                                                      Mat<double> m2m, double fd_h, int free_term, int nrhs,
+                                                      const zd* __restrict__ w, const zd* __restrict__ x,
+                                                      double* __restrict__ out)
+{
+    const Geo& g = c.geo;
+    const int K = g.K, L = c.fr.L;
+    const size_t idx = (size_t)blockIdx.x * 64 + threadIdx.x;
+    const int j = (int)(idx / 12), t = (int)(idx % 12);
+    if (j >= K) return;
+    double P[3][3];
+    for (int a = 0; a < 3; ++a) {
+        P[a][0] = g.vx[a * K + j];
+        P[a][1] = g.vy[a * K + j];
+        P[a][2] = g.vz[a * K + j];
+    }
+    double* o = out + (size_t)j * 13;
+    if (t == 0) {
+        const double xc[3] = {g.cx[j], g.cy[j], g.cz[j]}, n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+        double im = 0.0;
+        double re = kself_value(c, P, xc, n, c.md, nrhs, w, x, j, &im);
+        if (free_term) {
+            const size_t Mv = 3 * (size_t)K;
+            zd f = {0.0, 0.0};
+            for (int rr = 0; rr < nrhs; ++rr)
+                for (int l = 0; l < L; ++l) {
+                    const zd* up = w + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
+                    const zd* vp = x + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
+                    for (int a = 0; a < 3; ++a) f = fma_c(up[a], vp[a], f);
+                }
+            re += 0.5 * f.re;
+            im += 0.5 * f.im;
+        }
+        o[11] = re;
+        o[12] = im;
+        return;
+    }
+    if (t >= 10) {
+        const double xc[3] = {g.cx[j], g.cy[j], g.cz[j]}, n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+        const Mat<double>& mp = t == 10 ? m1p : m2p;
+        const Mat<double>& mm = t == 10 ? m1m : m2m;
+        const double h = t == 10 ? m1p.c1 - m1m.c1 : m2p.c2 - m2m.c2;
+        o[t - 1] = (kself_value(c, P, xc, n, mp, nrhs, w, x, j, nullptr) -
+                    kself_value(c, P, xc, n, mm, nrhs, w, x, j, nullptr)) / h;
+        return;
+    }
+    const int a = (t - 1) / 3, k = (t - 1) % 3;
+    const double hl = fd_h * sqrt(g.lmax2[j]);
+    double f[2];
+    for (int sgn = 0; sgn < 2; ++sgn) {
+        double Q[3][3];
+        for (int b = 0; b < 3; ++b)
+            for (int q = 0; q < 3; ++q) Q[b][q] = P[b][q];
+        Q[a][k] += sgn == 0 ? hl : -hl;
+        double xc[3], N[3];
+        for (int q = 0; q < 3; ++q) xc[q] = (Q[0][q] + Q[1][q] + Q[2][q]) / 3.0;
+        const double u1[3] = {Q[1][0] - Q[0][0], Q[1][1] - Q[0][1], Q[1][2] - Q[0][2]};
+        const double u2[3] = {Q[2][0] - Q[0][0], Q[2][1] - Q[0][1], Q[2][2] - Q[0][2]};
+        N[0] = u1[1] * u2[2] - u1[2] * u2[1];
+        N[1] = u1[2] * u2[0] - u1[0] * u2[2];
+        N[2] = u1[0] * u2[1] - u1[1] * u2[0];
+        const double iN = 1.0 / sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        const double n[3] = {N[0] * iN, N[1] * iN, N[2] * iN};
+        f[sgn] = kself_value(c, Q, xc, n, c.md, nrhs, w, x, j, nullptr);
+    }
+    o[t - 1] = (f[0] - f[1]) / (2.0 * hl);
+}
+
 // out[e][t] = sum over tiles of part[tile][e][t] (fixed order)
 __global__ __launch_bounds__(WG) void k_sum_tiles(const double* __restrict__ part, int ntile, size_t n,
                                                   double* __restrict__ out)
@@ -449,6 +805,37 @@ void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, doubl
     hipLaunchKernelGGL(k_adjoint_v, dim3(ti, tj), dim3(WG), 0, st, c, nrhs, w, x, gJ, gI, gM);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_adjoint_self, dim3((unsigned)(((size_t)K + 63) / 64)), dim3(64), 0, st, c, nrhs, w, x, so);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)((9 * (size_t)K + WG - 1) / WG)), dim3(WG), 0, st, gJ, (int)ti,
+                       9 * (size_t)K, sum);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)((3 * (size_t)K + WG - 1) / WG)), dim3(WG), 0, st, gI, (int)tj,
+                       3 * (size_t)K, sum + 9 * (size_t)K);
+    BEM_HIP_TRY(hipGetLastError());
+    *sums = sum;
+    *tiles = gM;
+    *ntiles_out = (int)(ti * tj);
+    *self_out = so;
+}
+
+// The double layer's adjoint (op K, or I/2 + K with free_term), same work layout and outputs
+// as launch_adjoint_v; mats: the materials at c1 (1 +- fd_h) and c2 (1 +- fd_h) for the self
+// pairs' speed differences.
+void launch_adjoint_k(const DevCtx& c, const Mat<double> mats[4], double fd_h, bool free_term, int nrhs, const zd* w,
+                      const zd* x, double* work, double** sums, double** tiles, int* ntiles_out, double** self_out,
+                      hipStream_t st)
+{
+    const int K = c.geo.K;
+    const unsigned ti = (unsigned)((K + WG - 1) / WG), tj = (unsigned)((K + JB - 1) / JB);
+    double* gJ = work;
+    double* gI = gJ + (size_t)ti * K * 9;
+    double* gM = gI + (size_t)tj * K * 3;
+    double* so = gM + (size_t)ti * tj * 4;
+    double* sum = so + (size_t)K * 13;
+    hipLaunchKernelGGL(k_adjoint_k, dim3(ti, tj), dim3(WG), 0, st, c, nrhs, w, x, gJ, gI, gM);
+    BEM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_adjoint_kself, dim3((unsigned)((12 * (size_t)K + 63) / 64)), dim3(64), 0, st, c, mats[0],
+                       mats[1], mats[2], mats[3], fd_h, free_term ? 1 : 0, nrhs, w, x, so);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)((9 * (size_t)K + WG - 1) / WG)), dim3(WG), 0, st, gJ, (int)ti,
                        9 * (size_t)K, sum);

@@ -1062,6 +1062,53 @@ int bem_apply_linear_dl(bem_ctx* ctx, int32_t nrhs, const void* g, void* y, int3
     });
 }
 
+namespace {
+
+// Element results of an adjoint launch to the caller's outputs: per element the 9 vertex
+// derivatives of its pairs as column element plus its self terms, the 3 centroid derivatives
+// as row element spread over its vertices (fixed order: elements ascending); the material and
+// the value from the tiles and the self terms.  drho_scale: d S / d rho = drho_scale * S.
+void adjoint_finish(bem_ctx* ctx, const double* sums, const double* tiles, int ntiles, const double* self_out,
+                    double drho_scale, double* value, double* grad_nodes, double* grad_mat)
+{
+    const int K = ctx->hgeo.K;
+    hipStream_t st = ctx->stream;
+    std::vector<double> hs(12 * (size_t)K), ht(4 * (size_t)ntiles), hself(13 * (size_t)K);
+    BEM_HIP_TRY(hipMemcpyAsync(hs.data(), sums, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    BEM_HIP_TRY(hipMemcpyAsync(ht.data(), tiles, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    BEM_HIP_TRY(hipMemcpyAsync(hself.data(), self_out, hself.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    BEM_HIP_TRY(hipStreamSynchronize(st));
+    const int64_t nn = (int64_t)ctx->nodes.size() / 3;
+    std::vector<double> gn(3 * (size_t)nn, 0.0);
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < ntiles; ++t)
+        for (int k = 0; k < 4; ++k) m[k] += ht[4 * (size_t)t + k];
+    for (int e = 0; e < K; ++e) {
+        const int32_t* tri = &ctx->tris[3 * (size_t)e];
+        const double* gJ = &hs[9 * (size_t)e];
+        const double* gI = &hs[9 * (size_t)K + 3 * (size_t)e];
+        const double* so = &hself[13 * (size_t)e];
+        for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < 3; ++k) gn[3 * (size_t)tri[a] + k] += gJ[3 * a + k] + so[3 * a + k] + gI[k] / 3.0;
+        m[0] += so[9];
+        m[1] += so[10];
+        m[2] += so[11];
+        m[3] += so[12];
+    }
+    if (value) {
+        value[0] = m[2];
+        value[1] = m[3];
+    }
+    if (grad_nodes) std::copy(gn.begin(), gn.end(), grad_nodes);
+    if (grad_mat) {
+        grad_mat[0] = drho_scale * m[2];
+        grad_mat[1] = m[0];
+        grad_mat[2] = m[1];
+    }
+}
+
+}  // namespace
+
 int bem_adjoint_v(bem_ctx* ctx, int32_t nrhs, const void* w, const void* x, int32_t flags, double* value,
                   double* grad_nodes, double* grad_mat)
 {
@@ -1085,39 +1132,43 @@ int bem_adjoint_v(bem_ctx* ctx, int32_t nrhs, const void* w, const void* x, int3
         int ntiles = 0;
         launch_adjoint_v(ctx->devctx(ctx->dgeo.geo, nullptr), nrhs, (const zd*)sw.dev, (const zd*)sx.dev, work.as<double>(),
                          &sums, &tiles, &ntiles, &self_out, st);
-        std::vector<double> hs(12 * (size_t)K), ht(4 * (size_t)ntiles), hself(13 * (size_t)K);
-        BEM_HIP_TRY(hipMemcpyAsync(hs.data(), sums, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        BEM_HIP_TRY(hipMemcpyAsync(ht.data(), tiles, ht.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        BEM_HIP_TRY(hipMemcpyAsync(hself.data(), self_out, hself.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        BEM_HIP_TRY(hipStreamSynchronize(st));
-        // element results to nodes (fixed order: elements ascending)
-        const int64_t nn = (int64_t)ctx->nodes.size() / 3;
-        std::vector<double> gn(3 * (size_t)nn, 0.0);
-        double m[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int t = 0; t < ntiles; ++t)
-            for (int k = 0; k < 4; ++k) m[k] += ht[4 * (size_t)t + k];
-        for (int e = 0; e < K; ++e) {
-            const int32_t* tri = &ctx->tris[3 * (size_t)e];
-            const double* gJ = &hs[9 * (size_t)e];
-            const double* gI = &hs[9 * (size_t)K + 3 * (size_t)e];
-            const double* so = &hself[13 * (size_t)e];
-            for (int a = 0; a < 3; ++a)
-                for (int k = 0; k < 3; ++k) gn[3 * (size_t)tri[a] + k] += gJ[3 * a + k] + so[3 * a + k] + gI[k] / 3.0;
-            m[0] += so[9];
-            m[1] += so[10];
-            m[2] += so[11];
-            m[3] += so[12];
-        }
-        if (value) {
-            value[0] = m[2];
-            value[1] = m[3];
-        }
-        if (grad_nodes) std::copy(gn.begin(), gn.end(), grad_nodes);
-        if (grad_mat) {
-            grad_mat[0] = -m[2] / ctx->rho;
-            grad_mat[1] = m[0];
-            grad_mat[2] = m[1];
-        }
+        // U is proportional to 1 / rho
+        adjoint_finish(ctx, sums, tiles, ntiles, self_out, -1.0 / ctx->rho, value, grad_nodes, grad_mat);
+        return BEM_OK;
+    });
+}
+
+int bem_adjoint_k(bem_ctx* ctx, int32_t op, int32_t nrhs, const void* w, const void* x, int32_t flags, double* value,
+                  double* grad_nodes, double* grad_mat)
+{
+    if (!ctx) return BEM_ERR_ARG;
+    return guarded(ctx, [&]() -> int {
+        need_state(ctx);
+        if (op != BEM_OP_K && op != BEM_OP_HK) throw api_error(BEM_ERR_ARG, "bem_adjoint_k takes BEM_OP_K or BEM_OP_HK");
+        if (nrhs < 1 || !w || !x) throw api_error(BEM_ERR_ARG, "need nrhs >= 1 and buffers");
+        if (flags & ~BEM_DEVICE_PTR) throw api_error(BEM_ERR_ARG, "unknown flags for bem_adjoint_k");
+        need_device(ctx);
+        need_one_component(ctx);
+        const bool dev = (flags & BEM_DEVICE_PTR) != 0;
+        const int K = ctx->hgeo.K;
+        const size_t bytes = (size_t)nrhs * ctx->freq.L * 3 * (size_t)K * sizeof(zd);
+        hipStream_t st = ctx->stream;
+        Staged sw, sx;
+        stage_in(sw, w, bytes, dev, st);
+        stage_in(sx, x, bytes, dev, st);
+        DevBuf work;
+        work.alloc(adjoint_work_doubles(K) * sizeof(double));
+        double *sums = nullptr, *tiles = nullptr, *self_out = nullptr;
+        int ntiles = 0;
+        constexpr double FD_H = 1e-5;  // relative step of the self pairs' central differences
+        const Mat<double> mats[4] = {make_mat<double>(ctx->rho, ctx->cp * (1.0 + FD_H), ctx->cs),
+                                     make_mat<double>(ctx->rho, ctx->cp * (1.0 - FD_H), ctx->cs),
+                                     make_mat<double>(ctx->rho, ctx->cp, ctx->cs * (1.0 + FD_H)),
+                                     make_mat<double>(ctx->rho, ctx->cp, ctx->cs * (1.0 - FD_H))};
+        launch_adjoint_k(ctx->devctx(ctx->dgeo.geo, nullptr), mats, FD_H, op == BEM_OP_HK, nrhs, (const zd*)sw.dev,
+                         (const zd*)sx.dev, work.as<double>(), &sums, &tiles, &ntiles, &self_out, st);
+        // T does not depend on rho
+        adjoint_finish(ctx, sums, tiles, ntiles, self_out, 0.0, value, grad_nodes, grad_mat);
         return BEM_OK;
     });
 }

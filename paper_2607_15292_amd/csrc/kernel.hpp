@@ -413,19 +413,14 @@ BEM_HD void near_unit(const Geo& g, int i, int j, int m, int u, zd s, zd sinv, c
     }
 }
 
-// Self pair, angular line u = (sub-triangle a = u / nt, angle index u % nt) of the polar
-// rule about the centroid; FP64.  For T the principal value of the line is
-// w_theta [sum_rho w_rho rho T + g(theta) (ln R(theta) - crho)], crho = sum_k w_k / rho_k
-// being independent of R for the scaled Gauss-Legendre rule.
+// Self pair, angular line it of the polar rule on the sub-triangle (x, va, vb) about the
+// collocation point x (the centroid), element normal n; FP64.  For T the principal value of
+// the line is w_theta [sum_rho w_rho rho T + g(theta) (ln R(theta) - crho)], crho =
+// sum_k w_k / rho_k being independent of R for the scaled Gauss-Legendre rule.
 template <int KOP>
-BEM_HD void self_unit(const Geo& g, int j, int u, zd s, zd sinv, const Mat<double>& M, const QuadTab& Q, blk& out)
+BEM_HD void self_line(const double x[3], const double va[3], const double vb[3], const double n[3], int it, zd s,
+                      zd sinv, const Mat<double>& M, const QuadTab& Q, blk& out)
 {
-    const int K = g.K;
-    const double x[3] = {g.cx[j], g.cy[j], g.cz[j]};
-    const int a = u / Q.nt, it = u - (u / Q.nt) * Q.nt;
-    const int b = (a + 1) % 3;
-    const double va[3] = {g.vx[a * K + j], g.vy[a * K + j], g.vz[a * K + j]};
-    const double vb[3] = {g.vx[b * K + j], g.vy[b * K + j], g.vz[b * K + j]};
     double t[3] = {vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]};
     const double le = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     for (int k = 0; k < 3; ++k) t[k] /= le;
@@ -457,7 +452,6 @@ BEM_HD void self_unit(const Geo& g, int j, int u, zd s, zd sinv, const Mat<doubl
         }
         acc.store(out, M.inv4pirho);
     } else {
-        const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
         AccK<double> acc;
         acc.zero();
         for (int ir = 0; ir < Q.nr; ++ir) {
@@ -470,6 +464,20 @@ BEM_HD void self_unit(const Geo& g, int j, int u, zd s, zd sinv, const Mat<doubl
         for (int ii = 0; ii < 3; ++ii)
             for (int jj = 0; jj < 3; ++jj) out.a[3 * ii + jj].re += M.gcoef * c * (dir[ii] * n[jj] - dir[jj] * n[ii]);
     }
+}
+
+// Unit u = (sub-triangle a = u / nt, angle index u % nt) of element j's self rule.
+template <int KOP>
+BEM_HD void self_unit(const Geo& g, int j, int u, zd s, zd sinv, const Mat<double>& M, const QuadTab& Q, blk& out)
+{
+    const int K = g.K;
+    const double x[3] = {g.cx[j], g.cy[j], g.cz[j]};
+    const int a = u / Q.nt, it = u - (u / Q.nt) * Q.nt;
+    const int b = (a + 1) % 3;
+    const double va[3] = {g.vx[a * K + j], g.vy[a * K + j], g.vz[a * K + j]};
+    const double vb[3] = {g.vx[b * K + j], g.vy[b * K + j], g.vz[b * K + j]};
+    const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+    self_line<KOP>(x, va, vb, n, it, s, sinv, M, Q, out);
 }
 
 // Unit u of the rule of a near (cls 1, 2) or self (cls 3) pair.

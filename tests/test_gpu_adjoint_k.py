@@ -1,0 +1,150 @@
+"""GPU parity of the double layer's adjoint (bem_adjoint_k) through the C-ABI: the value
+S = sum_{r, l} w^T A(s_l) x (A = K or I/2 + K, eq. (discrVK), the free term of eq. (SBIE)) and
+the gradient of Re S with respect to the node coordinates and c_p, c_s, against the oracle's
+gradient (oracle.Problem.adjoint_k: the kernel's pointwise derivatives there by central
+differences, here in closed form; self pairs on both sides by central differences of the
+principal-value rule) and against central differences of the GPU's own matrix-free double
+layer on random directions."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_15292_amd import binding as B
+from paper_2607_15292_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _ctx(X, T, s, mat=(1.0, 1.0, 0.5), near_on=False):
+    c = B.Context(0)
+    c.set_mesh(X, T)
+    c.set_material(*mat)
+    c.set_frequencies(s)
+    c.set_quadrature(near_on=near_on)
+    return c
+
+
+MESHES = {"sphere80": lambda: W.icosphere(1), "cube48": lambda: W.cube_grid(2, 1.0)}
+
+
+@pytest.mark.parametrize("near_on", [False, True])
+@pytest.mark.parametrize("mesh", list(MESHES))
+def test_adjoint_k_matches_oracle(torch, mesh, near_on):
+    X, T = MESHES[mesh]()
+    s = W.bdf2_contour(8, 0.1)[[0, 2, 5]]
+    mat = (1.3, 1.1, 0.6)
+    c = _ctx(X, T, s, mat=mat, near_on=near_on)
+    w = W.random_rhs(42, (2, 3, 3 * len(T)))
+    x = W.random_rhs(43, (2, 3, 3 * len(T)))
+    P = oracle.Problem(X, T, s, *mat, near_on=near_on)
+    for op in (B.OP_K, B.OP_HK):
+        val, gn, gm = c.adjoint_k(torch.tensor(w, device="cuda"), torch.tensor(x, device="cuda"), op=op)
+        val_o, gn_o, gm_o = P.adjoint_k(w, x, op=op)
+        assert abs(val - val_o) <= 1e-12 * abs(val_o), op
+        assert np.abs(gn - gn_o).max() <= 1e-7 * np.abs(gn_o).max(), (op, np.abs(gn - gn_o).max())
+        assert gm[0] == 0.0
+        assert np.abs(gm - gm_o).max() <= 1e-7 * np.abs(gm_o).max(), (op, gm, gm_o)
+    # the free term changes the value by sum w.x / 2 and not the gradient
+    vk, gk, mk = c.adjoint_k(w, x, op=B.OP_K)
+    vh, gh, mh = c.adjoint_k(w, x, op=B.OP_HK)
+    assert abs(vh - vk - 0.5 * np.sum(w * x)) <= 1e-12 * abs(vh)
+    assert np.array_equal(gk, gh) and np.array_equal(mk, mh)
+
+
+def _class_margin(X, T, r1=1.5, r2=3.0):
+    P = X[T]
+    cc = P.mean(axis=1)
+    e = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 1], P[:, 0] - P[:, 2]], axis=1)
+    l2 = (e ** 2).sum(-1).max(-1)
+    d2 = ((cc[:, None, :] - cc[None, :, :]) ** 2).sum(-1) / l2[None, :]
+    return min(np.abs(d2 - r1 * r1).min(), np.abs(d2 - r2 * r2).min())
+
+
+@pytest.mark.parametrize("near_on", [False, True])
+def test_adjoint_k_matches_central_differences(torch, near_on):
+    X, T = W.icosphere(2)  # 320 triangles
+    h = 1e-5
+    if near_on:
+        # jittered so that the difference steps switch no pair class of the near rule
+        X = X + 0.005 * np.random.default_rng(12).standard_normal(X.shape)
+        h = 1e-6
+        assert _class_margin(X, T) > 1e2 * h
+    s = W.bdf2_contour(8, 0.1)[[1, 4]]
+    c = _ctx(X, T, s, near_on=near_on)
+    w = W.random_rhs(52, (1, 2, 3 * len(T)))
+    x = W.random_rhs(53, (1, 2, 3 * len(T)))
+    _, gn, gm = c.adjoint_k(w, x)
+
+    def S(Xp, mat=(1.0, 1.0, 0.5)):
+        c.set_mesh(Xp, T)
+        c.set_material(*mat)
+        return np.sum(w * c.apply_mf(B.OP_K, x)).real
+
+    rng = np.random.default_rng(19)
+    for _ in range(10):
+        D = rng.standard_normal(X.shape)
+        fd = (S(X + h * D) - S(X - h * D)) / (2 * h)
+        an = float(np.sum(gn * D))
+        assert abs(an - fd) <= 1e-5 * np.linalg.norm(gn) * np.linalg.norm(D), (an, fd)
+    base = [1.0, 1.0, 0.5]
+    for k in range(3):
+        hk = 1e-6 * base[k]
+        p, m = list(base), list(base)
+        p[k] += hk
+        m[k] -= hk
+        fd = (S(X, p) - S(X, m)) / (2 * hk)
+        assert abs(gm[k] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(gm).max()), (k, gm[k], fd)
+
+
+def test_adjoint_k_errors(torch):
+    X, T = W.icosphere(1)
+    s = W.bdf2_contour(4, 0.1)
+    c = _ctx(X, T, s)
+    w = W.random_rhs(1, (1, 4, 3 * len(T)))
+    for op in (B.OP_V, B.OP_TABLE, B.OP_KL0):
+        with pytest.raises(B.BemError):
+            c.adjoint_k(w, w, op=op)
+    with pytest.raises(ValueError):
+        c.adjoint_k(w, w[:, :2].copy())
+
+
+def test_autograd_double_layer(torch):
+    from paper_2607_15292_amd.autograd import double_layer
+    X, T = W.icosphere(1)
+    s = W.bdf2_contour(8, 0.1)[[0, 3]]
+    c = _ctx(X, T, s)
+    nodes = torch.tensor(X, dtype=torch.float64, requires_grad=True)
+    mat = torch.tensor([1.0, 1.0, 0.5], dtype=torch.float64, requires_grad=True)
+    x0 = W.random_rhs(70, (2, 2, 3 * len(T)))
+    x = torch.tensor(x0, device="cuda", requires_grad=True)
+    cw = torch.tensor(W.random_rhs(71, (2, 2, 3 * len(T))), device="cuda")
+    y = double_layer(c, nodes, mat, x, T)
+    loss = (cw.conj() * y).real.sum() + (y.abs() ** 2).sum() * 0.1
+    loss.backward()
+
+    def f(Xp, m, xv):
+        with torch.no_grad():
+            yv = double_layer(c, torch.tensor(Xp, dtype=torch.float64), torch.tensor(m, dtype=torch.float64),
+                              torch.tensor(xv, device="cuda"), T)
+            return float(((cw.conj() * yv).real.sum() + (yv.abs() ** 2).sum() * 0.1).item())
+
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    D = rng.standard_normal(X.shape)
+    fd = (f(X + h * D, [1.0, 1.0, 0.5], x0) - f(X - h * D, [1.0, 1.0, 0.5], x0)) / (2 * h)
+    assert abs(float((nodes.grad.numpy() * D).sum()) - fd) <= 1e-5 * abs(fd)
+    assert mat.grad.numpy()[0] == 0.0
+    dm = np.array([0.0, 0.3, -0.2])
+    fd = (f(X, [1.0, 1.0 + h * 0.3, 0.5 - h * 0.2], x0) - f(X, [1.0, 1.0 - h * 0.3, 0.5 + h * 0.2], x0)) / (2 * h)
+    assert abs(float((mat.grad.numpy() * dm).sum()) - fd) <= 1e-5 * abs(fd)
+    dx = W.random_rhs(72, x0.shape)
+    fd = (f(X, [1.0, 1.0, 0.5], x0 + h * dx) - f(X, [1.0, 1.0, 0.5], x0 - h * dx)) / (2 * h)
+    an = float((x.grad.conj().cpu().numpy() * dx).real.sum())
+    assert abs(an - fd) <= 1e-5 * abs(fd)
