@@ -204,14 +204,16 @@ class Problem:
             raise RuntimeError("oracle_adjoint_v failed with code %d" % rc)
         return complex(val[0], val[1]), gn, gm
 
-    def adjoint_k(self, w, x, op=OP_K, fd_h=1e-5):
+    def adjoint_k(self, w, x, op=OP_K, fd_h=0.0):
         """Value S = sum_{r, l} w[r, l]^T A(s_l) x[r, l] of the double layer (op OP_K, or OP_HK
         with the free term) and the gradient of Re S: (S, grad_nodes [n_nodes, 3], grad_mat
         [rho, c_p, c_s]; the rho entry is 0, T not depending on rho), pair classes held fixed.
         Regular and near pairs by the chain rule through the Gauss points, the normal, the
         area and the collocation point, with the pointwise derivatives of T by central
-        differences of the kernel (step fd_h relative); self pairs by central differences of
-        the principal-value polar rule.  w, x: [nrhs, L, 3K] complex."""
+        differences of the kernel (relative step fd_h, 1e-5 when fd_h <= 0).  Self pairs: the
+        derivative of the principal-value integral by the polar rule (fd_h <= 0), or central
+        differences of the rule itself (fd_h > 0, the derivative of the discrete operator).
+        w, x: [nrhs, L, 3K] complex."""
         w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
         x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(-1, self.L, 3 * self.K))
         assert w.shape == x.shape and op in (OP_K, OP_HK)

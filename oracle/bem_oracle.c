@@ -854,6 +854,136 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
     return 0;
 }
 
+/* Self pair of the double layer differentiated as an integral.  The element stays flat under
+ * a perturbation of its vertices; with x = (v_0 + v_1 + v_2) / 3 and y = sum_a lambda_a(y) v_a,
+ *   d/dv_a E = PV int d_r T(y - x, n) (lambda_a(y) - 1/3) dy + PV int T(y - x, dn/dv_a) dy
+ *              + (dA/dv_a / A) E,
+ *   d/dc E = PV int dT/dc dy
+ * (T is linear in n, so the second integrand is T with n replaced by dn/dv_a).  Each integrand
+ * behaves like G(theta) / rho^2 at x with G odd in the direction: the polar rule of self_rule,
+ * per angular line sum_rho w_rho (rho F - G / rho) + G ln R, with G the same integrand for the
+ * static kernel (s -> 0, homogeneous of degree -2 in y - x) at unit distance.  Pointwise
+ * derivatives in y and in c_p, c_s by central differences of kernel_T (steps h |y - x| and
+ * h c).  Adds the contraction with w, x at (l, element j): gv[a][k] (Re), gc[2] (Re); dn[a][k]
+ * is the derivative of the unit normal with respect to coordinate k of vertex a. */
+static void self_grad_k(const ctx *C, const element *e, cplx s, const double *w, const double *x, int64_t K,
+                        int32_t L, int32_t nrhs, int32_t l, int64_t j, const double dA[3][3],
+                        const double dn[3][3][3], double h, double gv[3][3], double gc[2])
+{
+    const double *xc = e->c, *n = e->n;
+    const cplx s0 = 1e-12;  /* static kernel */
+    static const double unit[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+    const double zero[3] = {0.0, 0.0, 0.0};
+    double sr[3][3] = {{0.0}}, sn[3] = {0.0, 0.0, 0.0}, sc[2] = {0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        const double *va = e->v[a], *vb = e->v[(a + 1) % 3];
+        double t[3], le = 0.0;
+        for (int k = 0; k < 3; ++k) { t[k] = vb[k] - va[k]; le += t[k] * t[k]; }
+        le = sqrt(le);
+        for (int k = 0; k < 3; ++k) t[k] /= le;
+        double proj = 0.0;
+        for (int k = 0; k < 3; ++k) proj += (xc[k] - va[k]) * t[k];
+        double foot[3], p[3], d = 0.0;
+        for (int k = 0; k < 3; ++k) { foot[k] = va[k] + proj * t[k]; p[k] = foot[k] - xc[k]; d += p[k] * p[k]; }
+        d = sqrt(d);
+        for (int k = 0; k < 3; ++k) p[k] /= d;
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < 3; ++k) { sa += (va[k] - foot[k]) * t[k]; sb += (vb[k] - foot[k]) * t[k]; }
+        double ta = atan2(sa, d), tb = atan2(sb, d);
+        for (int it = 0; it < C->qo.self_nt; ++it) {
+            double th = 0.5 * (ta + tb) + 0.5 * (tb - ta) * C->gl_t[it];
+            double wth = 0.5 * (tb - ta) * C->gl_tw[it];
+            double R = d / cos(th);
+            double dir[3];
+            for (int k = 0; k < 3; ++k) dir[k] = cos(th) * p[k] + sin(th) * t[k];
+            /* leading parts at unit distance: the static kernel's y-derivatives, its value
+             * with n replaced by e_m, its speed derivatives */
+            double Gr[3], Gn[3], Gc[2], lam1[3];
+            for (int b = 0; b < 3; ++b) {
+                double y1[3] = {xc[0] + dir[0], xc[1] + dir[1], xc[2] + dir[2]};
+                lam1[b] = bary_weight(e, b, y1) - 1.0 / 3.0;  /* (lambda_b - 1/3) per unit distance */
+            }
+            for (int k = 0; k < 3; ++k) {
+                double yp[3] = {dir[0], dir[1], dir[2]}, ym[3] = {dir[0], dir[1], dir[2]};
+                yp[k] += h;
+                ym[k] -= h;
+                cplx Tp[9], Tm[9], D[9];
+                kernel_T(zero, yp, n, s0, &C->mat, Tp);
+                kernel_T(zero, ym, n, s0, &C->mat, Tm);
+                for (int q = 0; q < 9; ++q) D[q] = (Tp[q] - Tm[q]) / (2.0 * h);
+                Gr[k] = creal(contract(D, w, x, K, L, nrhs, l, j, j));
+                cplx Tn[9];
+                kernel_T(zero, dir, unit[k], s0, &C->mat, Tn);
+                Gn[k] = creal(contract(Tn, w, x, K, L, nrhs, l, j, j));
+            }
+            for (int q = 0; q < 2; ++q) {
+                material mp = C->mat, mm = C->mat;
+                const double hc = h * (q == 0 ? mp.c1 : mp.c2);
+                if (q == 0) { mp.c1 += hc; mm.c1 -= hc; }
+                else { mp.c2 += hc; mm.c2 -= hc; }
+                cplx Tp[9], Tm[9], D[9];
+                kernel_T(zero, dir, n, s0, &mp, Tp);
+                kernel_T(zero, dir, n, s0, &mm, Tm);
+                for (int t2 = 0; t2 < 9; ++t2) D[t2] = (Tp[t2] - Tm[t2]) / (2.0 * hc);
+                Gc[q] = creal(contract(D, w, x, K, L, nrhs, l, j, j));
+            }
+            const double lr = log(R);
+            for (int k = 0; k < 3; ++k) {
+                sn[k] += wth * Gn[k] * lr;
+                for (int b = 0; b < 3; ++b) sr[b][k] += wth * Gr[k] * lam1[b] * lr;
+            }
+            for (int q = 0; q < 2; ++q) sc[q] += wth * Gc[q] * lr;
+            for (int ir = 0; ir < C->qo.self_nr; ++ir) {
+                double rho = 0.5 * R * (1.0 + C->gl_r[ir]);
+                double wr = 0.5 * R * C->gl_rw[ir];
+                double y[3];
+                for (int k = 0; k < 3; ++k) y[k] = xc[k] + rho * dir[k];
+                const double hy = h * rho;
+                for (int k = 0; k < 3; ++k) {
+                    double yp[3] = {y[0], y[1], y[2]}, ym[3] = {y[0], y[1], y[2]};
+                    yp[k] += hy;
+                    ym[k] -= hy;
+                    cplx Tp[9], Tm[9], D[9];
+                    kernel_T(xc, yp, n, s, &C->mat, Tp);
+                    kernel_T(xc, ym, n, s, &C->mat, Tm);
+                    for (int q = 0; q < 9; ++q) D[q] = (Tp[q] - Tm[q]) / (2.0 * hy);
+                    const double dk = creal(contract(D, w, x, K, L, nrhs, l, j, j));
+                    for (int b = 0; b < 3; ++b) {
+                        const double lb = bary_weight(e, b, y) - 1.0 / 3.0;
+                        sr[b][k] += wth * wr * (rho * dk * lb - Gr[k] * lam1[b] / rho);
+                    }
+                    cplx Tn[9];
+                    kernel_T(xc, y, unit[k], s, &C->mat, Tn);
+                    sn[k] += wth * wr * (rho * creal(contract(Tn, w, x, K, L, nrhs, l, j, j)) - Gn[k] / rho);
+                }
+                for (int q = 0; q < 2; ++q) {
+                    material mp = C->mat, mm = C->mat;
+                    const double hc = h * (q == 0 ? mp.c1 : mp.c2);
+                    if (q == 0) { mp.c1 += hc; mm.c1 -= hc; }
+                    else { mp.c2 += hc; mm.c2 -= hc; }
+                    cplx Tp[9], Tm[9], D[9];
+                    kernel_T(xc, y, n, s, &mp, Tp);
+                    kernel_T(xc, y, n, s, &mm, Tm);
+                    for (int t2 = 0; t2 < 9; ++t2) D[t2] = (Tp[t2] - Tm[t2]) / (2.0 * hc);
+                    sc[q] += wth * wr * (rho * creal(contract(D, w, x, K, L, nrhs, l, j, j)) - Gc[q] / rho);
+                }
+            }
+        }
+    }
+    /* the value of the self entry for the area term */
+    cplx E[9] = {0};
+    self_rule(C, 1, e, s, -1, E);
+    const double v = creal(contract(E, w, x, K, L, nrhs, l, j, j));
+    for (int b = 0; b < 3; ++b)
+        for (int k = 0; k < 3; ++k) {
+            double g = sr[b][k] + v * dA[b][k] / e->area;
+            for (int m = 0; m < 3; ++m) g += dn[b][k][m] * sn[m];
+            gv[b][k] += g;
+        }
+    gc[0] += sc[0];
+    gc[1] += sc[1];
+}
+
 /* Value S = sum_{r, l, i, j} w[r][l][i]^T K_ij(s_l) x[r][l][j] of the double layer (op 1; op 2
  * adds the free term I/2, whose derivative is zero) and the gradient of Re S with respect to
  * the node coordinates and c_p, c_s (T does not depend on rho): the derivative of the discrete
@@ -862,9 +992,11 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
  * N = (v1 - v0) x (v2 - v0) (dn = (I - n n^T) (dv_a x (v_{a+1} - v_{a+2})) / |N|), its area
  * and the centroid of element i; the pointwise derivatives of T are taken by central
  * differences of kernel_T in y (step fd_h |y - x|) and in c_p, c_s (step fd_h c), and T is
- * linear in n (dT/dn_k = T with n = e_k).  Self pairs: central differences of the polar rule
- * (principal value) in each vertex coordinate (step fd_h times the longest edge) and in the
- * speeds.  value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho, c_p, c_s). */
+ * linear in n (dT/dn_k = T with n = e_k).  Self pairs: with fd_h > 0, central differences of
+ * the polar rule (principal value) in each vertex coordinate (step fd_h times the longest
+ * edge) and in the speeds; with fd_h <= 0, the derivative of the integral (self_grad_k), and
+ * the pointwise steps are 1e-5.  value: [2]; grad_nodes: [n_nodes][3]; grad_mat: [3] (rho,
+ * c_p, c_s). */
 int oracle_adjoint_k(const double *nodes, int64_t n_nodes, const int32_t *tris, int64_t K,
                      double rho, double cp, double cs, const double *s, int32_t L, int op, int near_on, double r1,
                      double r2, int self_nt, int self_nr, int32_t nrhs, const double *w, const double *x,
@@ -873,7 +1005,8 @@ int oracle_adjoint_k(const double *nodes, int64_t n_nodes, const int32_t *tris, 
     ctx C;
     int rc = setup(&C, nodes, n_nodes, tris, K, rho, cp, cs, near_on, r1, r2, self_nt, self_nr);
     if (rc) return rc;
-    if (!(fd_h > 0.0)) fd_h = 1e-5;
+    const int self_fd = fd_h > 0.0;  /* self pairs by central differences of the rule */
+    if (!self_fd) fd_h = 1e-5;
     int nth = 1;
 #ifdef _OPENMP
     nth = omp_get_max_threads();
@@ -894,6 +1027,47 @@ int oracle_adjoint_k(const double *nodes, int64_t n_nodes, const int32_t *tris, 
             for (int64_t j = 0; j < K; ++j) {
                 const element *ej = &C.el[j];
                 const int32_t *tj = tris + 3 * j, *ti = tris + 3 * i;
+                if (i == j && !self_fd) {
+                    double e1v[3], e2v[3], dA[3][3], dn[3][3][3];
+                    for (int k = 0; k < 3; ++k) { e1v[k] = ej->v[1][k] - ej->v[0][k]; e2v[k] = ej->v[2][k] - ej->v[0][k]; }
+                    const double *n = ej->n;
+                    dA[1][0] = 0.5 * (e2v[1] * n[2] - e2v[2] * n[1]);
+                    dA[1][1] = 0.5 * (e2v[2] * n[0] - e2v[0] * n[2]);
+                    dA[1][2] = 0.5 * (e2v[0] * n[1] - e2v[1] * n[0]);
+                    dA[2][0] = 0.5 * (n[1] * e1v[2] - n[2] * e1v[1]);
+                    dA[2][1] = 0.5 * (n[2] * e1v[0] - n[0] * e1v[2]);
+                    dA[2][2] = 0.5 * (n[0] * e1v[1] - n[1] * e1v[0]);
+                    for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+                    for (int a = 0; a < 3; ++a) {
+                        const double *pa1 = ej->v[(a + 1) % 3], *pa2 = ej->v[(a + 2) % 3];
+                        double d[3] = {pa1[0] - pa2[0], pa1[1] - pa2[1], pa1[2] - pa2[2]};
+                        for (int k = 0; k < 3; ++k) {
+                            double ek[3] = {0.0, 0.0, 0.0}, cr[3];
+                            ek[k] = 1.0;
+                            cr[0] = ek[1] * d[2] - ek[2] * d[1];
+                            cr[1] = ek[2] * d[0] - ek[0] * d[2];
+                            cr[2] = ek[0] * d[1] - ek[1] * d[0];
+                            double nc = n[0] * cr[0] + n[1] * cr[1] + n[2] * cr[2];
+                            for (int mm = 0; mm < 3; ++mm) dn[a][k][mm] = (cr[mm] - nc * n[mm]) / (2.0 * ej->area);
+                        }
+                    }
+                    for (int32_t l = 0; l < L; ++l) {
+                        cplx sl = s[2 * l] + I * s[2 * l + 1];
+                        cplx E[9] = {0};
+                        self_rule(&C, 1, ej, sl, -1, E);
+                        if (op == 2) { E[0] += 0.5; E[4] += 0.5; E[8] += 0.5; }
+                        cplx v = contract(E, w, x, K, L, nrhs, l, i, j);
+                        gm[2] += creal(v);
+                        gm[3] += cimag(v);
+                        double gv[3][3] = {{0.0}}, gc[2] = {0.0, 0.0};
+                        self_grad_k(&C, ej, sl, w, x, K, L, nrhs, l, j, dA, dn, fd_h, gv, gc);
+                        gm[0] += gc[0];
+                        gm[1] += gc[1];
+                        for (int a = 0; a < 3; ++a)
+                            for (int k = 0; k < 3; ++k) g[3 * (int64_t)tj[a] + k] += gv[a][k];
+                    }
+                    continue;
+                }
                 if (i == j) {
                     const double hl = fd_h * sqrt(ej->lmax2);
                     for (int32_t l = 0; l < L; ++l) {

@@ -154,7 +154,7 @@ def _SK(X, T, s, w, x, op=oracle.OP_K, rho=1.3, cp=1.1, cs=0.6, near_on=False):
 def test_double_layer_value_and_node_gradient(op):
     X, T, s, w, x = _setup()
     P = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=False)
-    val, g, gm = P.adjoint_k(w, x, op=op)
+    val, g, gm = P.adjoint_k(w, x, op=op, fd_h=1e-5)  # self pairs: derivative of the rule
     assert abs(val - _SK(X, T, s, w, x, op)) <= 1e-12 * abs(val)
     assert gm[0] == 0.0  # T does not depend on rho
     rng = np.random.default_rng(7)
@@ -167,7 +167,7 @@ def test_double_layer_value_and_node_gradient(op):
 
 def test_double_layer_material_gradient_and_translation():
     X, T, s, w, x = _setup()
-    _, g, gm = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=False).adjoint_k(w, x)
+    _, g, gm = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=False).adjoint_k(w, x, fd_h=1e-5)
     for k, (cp, cs) in ((1, (1.1, 0.6)), (2, (1.1, 0.6))):
         h = 1e-6
         if k == 1:
@@ -184,10 +184,40 @@ def test_double_layer_near_rule_gradient():
     X, T, s, w, x = _setup()
     # jittered so that the difference steps switch no pair class of the near rule
     X = X + 0.01 * np.random.default_rng(3).standard_normal(X.shape)
-    _, g, _ = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=True).adjoint_k(w, x)
+    _, g, _ = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=True).adjoint_k(w, x, fd_h=1e-5)
     rng = np.random.default_rng(8)
     h = 1e-6
     for _ in range(4):
         D = rng.standard_normal(X.shape)
         fd = (_SK(X + h * D, T, s, w, x, near_on=True).real - _SK(X - h * D, T, s, w, x, near_on=True).real) / (2 * h)
         assert abs(float(np.sum(g * D)) - fd) <= 1e-6 * np.linalg.norm(g) * np.linalg.norm(D)
+
+
+@pytest.mark.parametrize("near_on", [False, True])
+@pytest.mark.parametrize("op", [oracle.OP_K, oracle.OP_HK])
+def test_double_layer_self_derivative_of_the_integral(near_on, op):
+    # the self pairs differentiated as principal-value integrals (polar rule of d_r T (lambda_a -
+    # 1/3) and of T with the normal's derivative, leading parts from the static kernel) against
+    # central differences of the polar rule itself: the same derivative up to the rule's
+    # quadrature error; the material derivative identical (the rule's points do not move with
+    # the speeds); and each element's vertex derivatives sum to zero (sum_a (lambda_a - 1/3) = 0,
+    # the normal and the area do not change under a translation)
+    X, T, s, w, x = _setup()
+    P = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=near_on)
+    v0, g0, m0 = P.adjoint_k(w, x, op=op)
+    v1, g1, m1 = P.adjoint_k(w, x, op=op, fd_h=1e-5)
+    assert abs(v0 - v1) <= 1e-13 * abs(v1)
+    assert np.abs(g0 - g1).max() <= 5e-6 * np.abs(g1).max()
+    assert np.abs(m0 - m1).max() <= 1e-8 * np.abs(m1).max()
+    assert np.abs(g0.sum(axis=0)).max() <= 1e-10 * np.abs(g0).max()
+
+
+def test_double_layer_self_derivative_converges_with_the_rule():
+    # with a finer polar rule (16 x 16 points per sub-triangle) the quadrature error between the
+    # derivative of the integral and the derivative of the rule falls from about 1e-6 to the
+    # level of the difference quotients
+    X, T, s, w, x = _setup(L=2, nrhs=1)
+    P = oracle.Problem(X, T, s, 1.3, 1.1, 0.6, near_on=False, self_nt=16, self_nr=16)
+    _, g0, _ = P.adjoint_k(w, x)
+    _, g1, _ = P.adjoint_k(w, x, fd_h=1e-5)
+    assert np.abs(g0 - g1).max() <= 2e-7 * np.abs(g1).max()
