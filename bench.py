@@ -203,10 +203,10 @@ def batched_leg(args, dev, torch):
 
 
 def adjoint_leg(args, dev, torch):
-    """Adjoint of the single layer (reported apart from value): the gradient of
-    Re sum_l w_l^T V(s_l) x_l with respect to all node coordinates and rho, c_p, c_s, entries
-    recomputed (near rule on, pair classes held fixed), and the matrix-free product, on the
-    sphere of 20480 triangles with 64 contour points."""
+    """Adjoints of the single and the double layer (reported apart from value): the gradient of
+    Re sum_l w_l^T A(s_l) x_l (A = V, then I/2 + K) with respect to all node coordinates and
+    rho, c_p, c_s, entries recomputed (near rule on, pair classes held fixed), and the
+    matrix-free products, on the sphere of 20480 triangles with 64 contour points."""
     from paper_2607_15292_amd import binding as B
     from paper_2607_15292_amd import workloads as W
     X, T = W.icosphere(args.adjoint_level)
@@ -227,6 +227,15 @@ def adjoint_leg(args, dev, torch):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     log("adjoint: K %d L %d: gradient %.2f s, matrix-free product %.2f s" % (K, L, t1 - t0, t2 - t1))
+    # the double layer's adjoint (I/2 + K) on the same mesh
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    valk, gnk, gmk = c.adjoint_k(w, x, op=B.OP_HK)
+    t4 = time.perf_counter()
+    y = c.apply_mf(B.OP_HK, x)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    log("adjoint of I/2+K: gradient %.2f s, matrix-free product %.2f s" % (t4 - t3, t5 - t4))
     del w, x, y
     c.close()
     sol = solution_gradient(args, dev, torch, X, T, s)
@@ -236,6 +245,9 @@ def adjoint_leg(args, dev, torch):
            "gradient_seconds": t1 - t0, "pair_freqs_per_s": K * K * L / (t1 - t0),
            "matrix_free_product_seconds": t2 - t1, "matrix_free_entries_per_s": K * K * L / (t2 - t1),
            "grad_norm_nodes": float(np.linalg.norm(gn)), "grad_mat": [float(v) for v in gm],
+           "double_layer": {"operator": "I/2 + K", "gradient_seconds": t4 - t3, "pair_freqs_per_s": K * K * L / (t4 - t3),
+                            "matrix_free_product_seconds": t5 - t4, "grad_norm_nodes": float(np.linalg.norm(gnk)),
+                            "grad_mat": [float(v) for v in gmk]},
            "solution_gradient": sol}
     return out
 

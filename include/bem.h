@@ -439,9 +439,10 @@ int bem_adjoint_v(bem_ctx *ctx, int32_t nrhs, const void *w, const void *x, int3
  * the material, pair classes held fixed.  Regular and near pairs: chain rule through the Gauss
  * points, the element normal n_j (dn = (I - n n^T)(dP_a x (P_{a+1} - P_{a+2})) / |N|), the
  * area and the collocation point, with the closed-form R- and speed derivatives of the
- * traction kernel (second R-derivatives of A and B included).  Self pairs (principal values):
- * central differences of the polar rule, step 1e-5 times the longest edge per vertex
- * coordinate and 1e-5 times the speed per speed.  T does not depend on rho: grad_mat[0] = 0.
+ * traction kernel (second R-derivatives of A and B included).  Self pairs: the derivative of
+ * the principal-value integral (the traction's r-gradient weighted by lambda_a - 1/3, its
+ * normal derivative, its speed derivatives and the area term, by the polar rule with the
+ * leading parts of the static kernel).  T does not depend on rho: grad_mat[0] = 0.
  * Arguments, layouts and errors as bem_adjoint_v; BEM_ERR_ARG also for another op. */
 int bem_adjoint_k(bem_ctx *ctx, int32_t op, int32_t nrhs, const void *w, const void *x, int32_t flags,
                   double *value, double *grad_nodes, double *grad_mat);

@@ -863,8 +863,8 @@ int oracle_adjoint_v(const double *nodes, int64_t n_nodes, const int32_t *tris, 
  * behaves like G(theta) / rho^2 at x with G odd in the direction: the polar rule of self_rule,
  * per angular line sum_rho w_rho (rho F - G / rho) + G ln R, with G the same integrand for the
  * static kernel (s -> 0, homogeneous of degree -2 in y - x) at unit distance.  Pointwise
- * derivatives in y and in c_p, c_s by central differences of kernel_T (steps h |y - x| and
- * h c).  Adds the contraction with w, x at (l, element j): gv[a][k] (Re), gc[2] (Re); dn[a][k]
+ * y-derivatives by central differences of kernel_T (step h |y - x|); the speed derivative as
+ * central differences of the rule in c_p, c_s (step h c).  Adds the contraction with w, x at (l, element j): gv[a][k] (Re), gc[2] (Re); dn[a][k]
  * is the derivative of the unit normal with respect to coordinate k of vertex a. */
 static void self_grad_k(const ctx *C, const element *e, cplx s, const double *w, const double *x, int64_t K,
                         int32_t L, int32_t nrhs, int32_t l, int64_t j, const double dA[3][3],
@@ -874,7 +874,7 @@ static void self_grad_k(const ctx *C, const element *e, cplx s, const double *w,
     const cplx s0 = 1e-12;  /* static kernel */
     static const double unit[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
     const double zero[3] = {0.0, 0.0, 0.0};
-    double sr[3][3] = {{0.0}}, sn[3] = {0.0, 0.0, 0.0}, sc[2] = {0.0, 0.0};
+    double sr[3][3] = {{0.0}}, sn[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < 3; ++a) {
         const double *va = e->v[a], *vb = e->v[(a + 1) % 3];
         double t[3], le = 0.0;
@@ -896,9 +896,9 @@ static void self_grad_k(const ctx *C, const element *e, cplx s, const double *w,
             double R = d / cos(th);
             double dir[3];
             for (int k = 0; k < 3; ++k) dir[k] = cos(th) * p[k] + sin(th) * t[k];
-            /* leading parts at unit distance: the static kernel's y-derivatives, its value
-             * with n replaced by e_m, its speed derivatives */
-            double Gr[3], Gn[3], Gc[2], lam1[3];
+            /* leading parts at unit distance: the static kernel's y-derivatives and its value
+             * with n replaced by e_m */
+            double Gr[3], Gn[3], lam1[3];
             for (int b = 0; b < 3; ++b) {
                 double y1[3] = {xc[0] + dir[0], xc[1] + dir[1], xc[2] + dir[2]};
                 lam1[b] = bary_weight(e, b, y1) - 1.0 / 3.0;  /* (lambda_b - 1/3) per unit distance */
@@ -916,23 +916,11 @@ static void self_grad_k(const ctx *C, const element *e, cplx s, const double *w,
                 kernel_T(zero, dir, unit[k], s0, &C->mat, Tn);
                 Gn[k] = creal(contract(Tn, w, x, K, L, nrhs, l, j, j));
             }
-            for (int q = 0; q < 2; ++q) {
-                material mp = C->mat, mm = C->mat;
-                const double hc = h * (q == 0 ? mp.c1 : mp.c2);
-                if (q == 0) { mp.c1 += hc; mm.c1 -= hc; }
-                else { mp.c2 += hc; mm.c2 -= hc; }
-                cplx Tp[9], Tm[9], D[9];
-                kernel_T(zero, dir, n, s0, &mp, Tp);
-                kernel_T(zero, dir, n, s0, &mm, Tm);
-                for (int t2 = 0; t2 < 9; ++t2) D[t2] = (Tp[t2] - Tm[t2]) / (2.0 * hc);
-                Gc[q] = creal(contract(D, w, x, K, L, nrhs, l, j, j));
-            }
             const double lr = log(R);
             for (int k = 0; k < 3; ++k) {
                 sn[k] += wth * Gn[k] * lr;
                 for (int b = 0; b < 3; ++b) sr[b][k] += wth * Gr[k] * lam1[b] * lr;
             }
-            for (int q = 0; q < 2; ++q) sc[q] += wth * Gc[q] * lr;
             for (int ir = 0; ir < C->qo.self_nr; ++ir) {
                 double rho = 0.5 * R * (1.0 + C->gl_r[ir]);
                 double wr = 0.5 * R * C->gl_rw[ir];
@@ -956,17 +944,6 @@ static void self_grad_k(const ctx *C, const element *e, cplx s, const double *w,
                     kernel_T(xc, y, unit[k], s, &C->mat, Tn);
                     sn[k] += wth * wr * (rho * creal(contract(Tn, w, x, K, L, nrhs, l, j, j)) - Gn[k] / rho);
                 }
-                for (int q = 0; q < 2; ++q) {
-                    material mp = C->mat, mm = C->mat;
-                    const double hc = h * (q == 0 ? mp.c1 : mp.c2);
-                    if (q == 0) { mp.c1 += hc; mm.c1 -= hc; }
-                    else { mp.c2 += hc; mm.c2 -= hc; }
-                    cplx Tp[9], Tm[9], D[9];
-                    kernel_T(xc, y, n, s, &mp, Tp);
-                    kernel_T(xc, y, n, s, &mm, Tm);
-                    for (int t2 = 0; t2 < 9; ++t2) D[t2] = (Tp[t2] - Tm[t2]) / (2.0 * hc);
-                    sc[q] += wth * wr * (rho * creal(contract(D, w, x, K, L, nrhs, l, j, j)) - Gc[q] / rho);
-                }
             }
         }
     }
@@ -980,8 +957,19 @@ static void self_grad_k(const ctx *C, const element *e, cplx s, const double *w,
             for (int m = 0; m < 3; ++m) g += dn[b][k][m] * sn[m];
             gv[b][k] += g;
         }
-    gc[0] += sc[0];
-    gc[1] += sc[1];
+    /* speeds: the rule's points do not move with them, so the central differences of the rule
+     * are its integral of dT/dc (with the leading part's derivative) */
+    for (int q = 0; q < 2; ++q) {
+        ctx Cp = *C, Cm = *C;
+        const double hc = h * (q == 0 ? C->mat.c1 : C->mat.c2);
+        if (q == 0) { Cp.mat.c1 += hc; Cm.mat.c1 -= hc; }
+        else { Cp.mat.c2 += hc; Cm.mat.c2 -= hc; }
+        cplx Ep[9] = {0}, Em[9] = {0}, D[9];
+        self_rule(&Cp, 1, e, s, -1, Ep);
+        self_rule(&Cm, 1, e, s, -1, Em);
+        for (int t2 = 0; t2 < 9; ++t2) D[t2] = (Ep[t2] - Em[t2]) / (2.0 * hc);
+        gc[q] += creal(contract(D, w, x, K, L, nrhs, l, j, j));
+    }
 }
 
 /* Value S = sum_{r, l, i, j} w[r][l][i]^T K_ij(s_l) x[r][l][j] of the double layer (op 1; op 2

@@ -645,109 +645,193 @@ __global__ __launch_bounds__(WG) void k_adjoint_k(DevCtx c, int nrhs, const zd* 
     }
 }
 
-// Self pairs of the double layer: sum_{r, l} w_j^T E(s_l) x_j of the principal-value polar rule
-// (the forward rule, geometry explicit) for one perturbed element or material.
-__device__ double kself_value(const DevCtx& c, const double P[3][3], const double xc[3], const double n[3],
-                              const Mat<double>& M, int nrhs, const zd* __restrict__ w, const zd* __restrict__ x,
-                              int j, double* im)
+// Contraction of 4 pi T(r, n) with a general 3 x 3 W (sum over the right-hand sides of
+// w x^T) and its derivatives: with rh, dr/dn = rh.n, alpha = rh^T W n, beta = tr W, gamma =
+// n^T W rh, delta = rh^T W rh, S = (alpha, beta dr/dn + gamma, delta dr/dn),
+//   val = P.S, grad_r = rh (P'.S) + (P1 (W n - rh alpha) + P2 (beta (n - rh dr/dn) + W^T n -
+//   rh gamma) + P3 (dr/dn ((W + W^T) rh - 2 rh delta) + delta (n - rh dr/dn))) / R,
+//   grad_n = P1 W^T rh + P2 (beta rh + W rh) + P3 delta rh,   d/dc = (dP/dc).S.
+struct TCon {
+    zd val, c1, c2;
+    double gr[3], gn[3];  // real parts
+};
+
+__device__ __forceinline__ void tcontract(const zd W[9], const double rh[3], const double n[3], double Rinv,
+                                          const zd P[3], const zd Pr[3], const zd Pc1[3], const zd Pc2[3], TCon& o)
 {
-    const int K = c.geo.K, L = c.fr.L;
-    const size_t Mv = 3 * (size_t)K;
-    zd tot = {0.0, 0.0};
-#pragma unroll 1
-    for (int l = 0; l < L; ++l) {
-        blk E = blk_zero();
-#pragma unroll 1
-        for (int a = 0; a < 3; ++a)
-#pragma unroll 1
-            for (int it = 0; it < c.qt.nt; ++it) {
-                blk e;
-                self_line<1>(xc, P[a], P[(a + 1) % 3], n, it, c.fr.s[l], c.fr.sinv[l], M, c.qt, e);
-                for (int t = 0; t < 9; ++t) E.a[t] += e.a[t];
-            }
-#pragma unroll 1
-        for (int rr = 0; rr < nrhs; ++rr) {
-            const zd* up = w + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
-            const zd* vp = x + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) tot = fma_c(E.a[3 * a + b], up[a] * vp[b], tot);
-        }
+    zd Wn[3], WTn[3], Wh[3], WTh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Wn[a] = W[3 * a] * n[0] + W[3 * a + 1] * n[1] + W[3 * a + 2] * n[2];
+        Wh[a] = W[3 * a] * rh[0] + W[3 * a + 1] * rh[1] + W[3 * a + 2] * rh[2];
+        WTn[a] = W[a] * n[0] + W[3 + a] * n[1] + W[6 + a] * n[2];
+        WTh[a] = W[a] * rh[0] + W[3 + a] * rh[1] + W[6 + a] * rh[2];
     }
-    if (im) *im = tot.im;
-    return tot.re;
+    const double rn = rh[0] * n[0] + rh[1] * n[1] + rh[2] * n[2];
+    const zd al = rh[0] * Wn[0] + rh[1] * Wn[1] + rh[2] * Wn[2];
+    const zd be = W[0] + W[4] + W[8];
+    const zd ga = n[0] * Wh[0] + n[1] * Wh[1] + n[2] * Wh[2];
+    const zd de = rh[0] * Wh[0] + rh[1] * Wh[1] + rh[2] * Wh[2];
+    const zd S1 = al, S2 = be * rn + ga, S3 = de * rn;
+    o.val = P[0] * S1 + P[1] * S2 + P[2] * S3;
+    o.c1 = Pc1[0] * S1 + Pc1[1] * S2 + Pc1[2] * S3;
+    o.c2 = Pc2[0] * S1 + Pc2[1] * S2 + Pc2[2] * S3;
+    const zd rad = Pr[0] * S1 + Pr[1] * S2 + Pr[2] * S3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const zd t = P[0] * (Wn[k] - rh[k] * al) + P[1] * (be * (n[k] - rh[k] * rn) + WTn[k] - rh[k] * ga) +
+                     P[2] * (rn * (Wh[k] + WTh[k] - (2.0 * rh[k]) * de) + de * (n[k] - rh[k] * rn));
+        o.gr[k] = rh[k] * rad.re + Rinv * t.re;
+        o.gn[k] = (P[0] * WTh[k] + P[1] * (be * rh[k] + Wh[k]) + P[2] * (de * rh[k])).re;
+    }
 }
 
-// Self pairs of the double layer by central differences of the principal-value rule: thread
-// per (element j, task t); t = 0: Re and Im of the self terms of S (with the free term I/2
-// when free_term); t = 1 .. 9: vertex a = (t - 1) / 3, coordinate k = (t - 1) % 3, step
-// fd_h * (longest edge), the perturbed element's centroid and normal recomputed; t = 10, 11:
-// c1, c2 (materials m1p, m1m, m2p, m2m at c * (1 +- fd_h)).  out[j][13] as k_adjoint_self.
-__global__ __launch_bounds__(64) void k_adjoint_kself(DevCtx c, Mat<double> m1p, Mat<double> m1m, Mat<double> m2p,
-                                                      Mat<double> m2m, double fd_h, int free_term, int nrhs,
-                                                      const zd* __restrict__ w, const zd* __restrict__ x,
-                                                      double* __restrict__ out)
+// Self pairs of the double layer, the derivative of the principal-value integral: the element
+// stays flat under a perturbation of its vertices; with the collocation point x (centroid) and
+// y = sum_a lambda_a(y) P_a,
+//   dE/dP_a = PV int grad_r T(y - x, n) (lambda_a(y) - 1/3) dy + PV int grad_n T dy . dn/dP_a
+//             + (dA/dP_a / A) E,   dE/dc = PV int dT/dc dy.
+// Each integrand is G(theta) / rho^2 + O(1) at x with G odd in the direction (T = T_0 / R^2 +
+// O(1): A' and B / R have no 1/R term), so the polar rule of the forward self entry takes it,
+// per angular line w_theta [sum_rho w_rho rho F + G (ln R - crho)], with G from the static
+// coefficients P_0 = (c2^2/c1^2, -c2^2/c1^2, -3 (1 - c2^2/c1^2)), P'_0 = -2 P_0 at unit
+// distance.  Thread per element j, frequencies outermost (W_l = sum_r w x^T of the element);
+// out[j][13] as k_adjoint_self, with the free term I/2 in the value when free_term.
+__global__ __launch_bounds__(64) void k_adjoint_kself(DevCtx c, int free_term, int nrhs, const zd* __restrict__ w,
+                                                      const zd* __restrict__ x, double* __restrict__ out)
 {
     const Geo& g = c.geo;
+    const QuadTab& Q = c.qt;
+    const Mat<double>& Md = c.md;
     const int K = g.K, L = c.fr.L;
-    const size_t idx = (size_t)blockIdx.x * 64 + threadIdx.x;
-    const int j = (int)(idx / 12), t = (int)(idx % 12);
+    const size_t Mv = 3 * (size_t)K;
+    const int j = blockIdx.x * 64 + threadIdx.x;
     if (j >= K) return;
+    const double pref = Md.inv4pi;
     double P[3][3];
     for (int a = 0; a < 3; ++a) {
         P[a][0] = g.vx[a * K + j];
         P[a][1] = g.vy[a * K + j];
         P[a][2] = g.vz[a * K + j];
     }
-    double* o = out + (size_t)j * 13;
-    if (t == 0) {
-        const double xc[3] = {g.cx[j], g.cy[j], g.cz[j]}, n[3] = {g.nx[j], g.ny[j], g.nz[j]};
-        double im = 0.0;
-        double re = kself_value(c, P, xc, n, c.md, nrhs, w, x, j, &im);
-        if (free_term) {
-            const size_t Mv = 3 * (size_t)K;
-            zd f = {0.0, 0.0};
-            for (int rr = 0; rr < nrhs; ++rr)
-                for (int l = 0; l < L; ++l) {
-                    const zd* up = w + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
-                    const zd* vp = x + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
-                    for (int a = 0; a < 3; ++a) f = fma_c(up[a], vp[a], f);
-                }
-            re += 0.5 * f.re;
-            im += 0.5 * f.im;
+    const double xc[3] = {g.cx[j], g.cy[j], g.cz[j]};
+    const double n[3] = {g.nx[j], g.ny[j], g.nz[j]};
+    // static coefficients and their speed derivatives
+    const double gam = Md.c2s * Md.ic1s;
+    const double dg1 = -2.0 * gam * Md.ic1, dg2 = 2.0 * Md.c2 * Md.ic1s;
+    const zd p0[3] = {{gam, 0.0}, {-gam, 0.0}, {-3.0 * (1.0 - gam), 0.0}};
+    const zd p0r[3] = {{-2.0 * gam, 0.0}, {2.0 * gam, 0.0}, {6.0 * (1.0 - gam), 0.0}};
+    const zd p0c1[3] = {{dg1, 0.0}, {-dg1, 0.0}, {3.0 * dg1, 0.0}};
+    const zd p0c2[3] = {{dg2, 0.0}, {-dg2, 0.0}, {3.0 * dg2, 0.0}};
+    double gP[9], gN[3] = {0.0, 0.0, 0.0}, V = 0.0, Vi = 0.0, m1 = 0.0, m2 = 0.0;
+    zd trW = {0.0, 0.0};  // sum_{r, l} w . x of the element (the free term's share)
+    for (int t = 0; t < 9; ++t) gP[t] = 0.0;
+#pragma unroll 1
+    for (int l = 0; l < L; ++l) {
+        zd W[9];
+        for (int t = 0; t < 9; ++t) W[t] = {0.0, 0.0};
+        for (int rr = 0; rr < nrhs; ++rr) {
+            const zd* up = w + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
+            const zd* vp = x + ((size_t)rr * L + l) * Mv + 3 * (size_t)j;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) W[3 * a + b] = fma_c(up[a], vp[b], W[3 * a + b]);
         }
-        o[11] = re;
-        o[12] = im;
-        return;
+        const zd sl = c.fr.s[l], sinvl = c.fr.sinv[l];
+#pragma unroll 1
+        for (int sa = 0; sa < 3; ++sa) {
+            const int sb = (sa + 1) % 3;
+            double t[3] = {P[sb][0] - P[sa][0], P[sb][1] - P[sa][1], P[sb][2] - P[sa][2]};
+            const double le = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+            for (int k = 0; k < 3; ++k) t[k] /= le;
+            const double proj = (xc[0] - P[sa][0]) * t[0] + (xc[1] - P[sa][1]) * t[1] + (xc[2] - P[sa][2]) * t[2];
+            double foot[3], p[3];
+            for (int k = 0; k < 3; ++k) {
+                foot[k] = P[sa][k] + proj * t[k];
+                p[k] = foot[k] - xc[k];
+            }
+            const double d = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+            for (int k = 0; k < 3; ++k) p[k] /= d;
+            const double qa = (P[sa][0] - foot[0]) * t[0] + (P[sa][1] - foot[1]) * t[1] + (P[sa][2] - foot[2]) * t[2];
+            const double qb = (P[sb][0] - foot[0]) * t[0] + (P[sb][1] - foot[1]) * t[1] + (P[sb][2] - foot[2]) * t[2];
+            const double ta = atan2(qa, d), tb = atan2(qb, d);
+            const double hth = 0.5 * (tb - ta), mth = 0.5 * (ta + tb);
+#pragma unroll 1
+            for (int it = 0; it < Q.nt; ++it) {
+                const double th = mth + hth * Q.tx[it];
+                const double wth = hth * Q.tw[it];
+                double sn, cs;
+                sincos(th, &sn, &cs);
+                const double Rl = d / cs;
+                const double rh[3] = {cs * p[0] + sn * t[0], cs * p[1] + sn * t[1], cs * p[2] + sn * t[2]};
+                double lam1[3];  // lambda_b - 1/3 per unit distance along rh
+                {
+                    const double y1[3] = {xc[0] + rh[0], xc[1] + rh[1], xc[2] + rh[2]};
+                    for (int b = 0; b < 3; ++b) lam1[b] = bary_at(g, j, b, y1) - 1.0 / 3.0;
+                }
+                // leading parts: w_theta G (ln R - crho)
+                {
+                    TCon o;
+                    tcontract(W, rh, n, 1.0, p0, p0r, p0c1, p0c2, o);
+                    const double cw = wth * (log(Rl) - Q.crho) * pref;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        gN[k] += cw * o.gn[k];
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) gP[3 * b + k] += cw * o.gr[k] * lam1[b];
+                    }
+                    V += cw * o.val.re;
+                    Vi += cw * o.val.im;
+                    m1 += cw * o.c1.re;
+                    m2 += cw * o.c2.re;
+                }
+#pragma unroll 1
+                for (int ir = 0; ir < Q.nr; ++ir) {
+                    const double rho = 0.5 * Rl * (1.0 + Q.rx[ir]);
+                    const double wq = wth * (0.5 * Rl * Q.rw[ir]) * rho * pref;
+                    TDer T;
+                    traction_der(rho, 1.0 / rho, sl, sinvl, Md, T);
+                    TCon o;
+                    tcontract(W, rh, n, 1.0 / rho, T.P, T.Pr, T.Pc1, T.Pc2, o);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        gN[k] += wq * o.gn[k];
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) gP[3 * b + k] += wq * o.gr[k] * (rho * lam1[b]);
+                    }
+                    V += wq * o.val.re;
+                    Vi += wq * o.val.im;
+                    m1 += wq * o.c1.re;
+                    m2 += wq * o.c2.re;
+                }
+            }
+        }
+        trW += W[0] + W[4] + W[8];
     }
-    if (t >= 10) {
-        const double xc[3] = {g.cx[j], g.cy[j], g.cz[j]}, n[3] = {g.nx[j], g.ny[j], g.nz[j]};
-        const Mat<double>& mp = t == 10 ? m1p : m2p;
-        const Mat<double>& mm = t == 10 ? m1m : m2m;
-        const double h = t == 10 ? m1p.c1 - m1m.c1 : m2p.c2 - m2m.c2;
-        o[t - 1] = (kself_value(c, P, xc, n, mp, nrhs, w, x, j, nullptr) -
-                    kself_value(c, P, xc, n, mm, nrhs, w, x, j, nullptr)) / h;
-        return;
+    // area term (of the integral, without the free term) and the normal's motion
+    const double e1[3] = {P[1][0] - P[0][0], P[1][1] - P[0][1], P[1][2] - P[0][2]};
+    const double e2[3] = {P[2][0] - P[0][0], P[2][1] - P[0][1], P[2][2] - P[0][2]};
+    double dA[3][3];
+    dA[1][0] = 0.5 * (e2[1] * n[2] - e2[2] * n[1]);
+    dA[1][1] = 0.5 * (e2[2] * n[0] - e2[0] * n[2]);
+    dA[1][2] = 0.5 * (e2[0] * n[1] - e2[1] * n[0]);
+    dA[2][0] = 0.5 * (n[1] * e1[2] - n[2] * e1[1]);
+    dA[2][1] = 0.5 * (n[2] * e1[0] - n[0] * e1[2]);
+    dA[2][2] = 0.5 * (n[0] * e1[1] - n[1] * e1[0]);
+    for (int k = 0; k < 3; ++k) dA[0][k] = -(dA[1][k] + dA[2][k]);
+    const double ia = 1.0 / g.area[j], iN = 0.5 * ia;
+    const double ng = n[0] * gN[0] + n[1] * gN[1] + n[2] * gN[2];
+    double* o = out + (size_t)j * 13;
+    for (int a = 0; a < 3; ++a) {
+        const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+        const double dd[3] = {P[a1][0] - P[a2][0], P[a1][1] - P[a2][1], P[a1][2] - P[a2][2]};
+        const double dg[3] = {dd[1] * gN[2] - dd[2] * gN[1], dd[2] * gN[0] - dd[0] * gN[2], dd[0] * gN[1] - dd[1] * gN[0]};
+        const double dn[3] = {dd[1] * n[2] - dd[2] * n[1], dd[2] * n[0] - dd[0] * n[2], dd[0] * n[1] - dd[1] * n[0]};
+        for (int k = 0; k < 3; ++k) o[3 * a + k] = gP[3 * a + k] + V * dA[a][k] * ia + iN * (dg[k] - ng * dn[k]);
     }
-    const int a = (t - 1) / 3, k = (t - 1) % 3;
-    const double hl = fd_h * sqrt(g.lmax2[j]);
-    double f[2];
-    for (int sgn = 0; sgn < 2; ++sgn) {
-        double Q[3][3];
-        for (int b = 0; b < 3; ++b)
-            for (int q = 0; q < 3; ++q) Q[b][q] = P[b][q];
-        Q[a][k] += sgn == 0 ? hl : -hl;
-        double xc[3], N[3];
-        for (int q = 0; q < 3; ++q) xc[q] = (Q[0][q] + Q[1][q] + Q[2][q]) / 3.0;
-        const double u1[3] = {Q[1][0] - Q[0][0], Q[1][1] - Q[0][1], Q[1][2] - Q[0][2]};
-        const double u2[3] = {Q[2][0] - Q[0][0], Q[2][1] - Q[0][1], Q[2][2] - Q[0][2]};
-        N[0] = u1[1] * u2[2] - u1[2] * u2[1];
-        N[1] = u1[2] * u2[0] - u1[0] * u2[2];
-        N[2] = u1[0] * u2[1] - u1[1] * u2[0];
-        const double iN = 1.0 / sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
-        const double n[3] = {N[0] * iN, N[1] * iN, N[2] * iN};
-        f[sgn] = kself_value(c, Q, xc, n, c.md, nrhs, w, x, j, nullptr);
-    }
-    o[t - 1] = (f[0] - f[1]) / (2.0 * hl);
+    o[9] = m1;
+    o[10] = m2;
+    o[11] = V + (free_term ? 0.5 * trW.re : 0.0);
+    o[12] = Vi + (free_term ? 0.5 * trW.im : 0.0);
 }
 
 // out[e][t] = sum over tiles of part[tile][e][t] (fixed order)
@@ -819,11 +903,9 @@ void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, doubl
 }
 
 // The double layer's adjoint (op K, or I/2 + K with free_term), same work layout and outputs
-// as launch_adjoint_v; mats: the materials at c1 (1 +- fd_h) and c2 (1 +- fd_h) for the self
-// pairs' speed differences.
-void launch_adjoint_k(const DevCtx& c, const Mat<double> mats[4], double fd_h, bool free_term, int nrhs, const zd* w,
-                      const zd* x, double* work, double** sums, double** tiles, int* ntiles_out, double** self_out,
-                      hipStream_t st)
+// as launch_adjoint_v.
+void launch_adjoint_k(const DevCtx& c, bool free_term, int nrhs, const zd* w, const zd* x, double* work, double** sums,
+                      double** tiles, int* ntiles_out, double** self_out, hipStream_t st)
 {
     const int K = c.geo.K;
     const unsigned ti = (unsigned)((K + WG - 1) / WG), tj = (unsigned)((K + JB - 1) / JB);
@@ -834,8 +916,8 @@ void launch_adjoint_k(const DevCtx& c, const Mat<double> mats[4], double fd_h, b
     double* sum = so + (size_t)K * 13;
     hipLaunchKernelGGL(k_adjoint_k, dim3(ti, tj), dim3(WG), 0, st, c, nrhs, w, x, gJ, gI, gM);
     BEM_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_adjoint_kself, dim3((unsigned)((12 * (size_t)K + 63) / 64)), dim3(64), 0, st, c, mats[0],
-                       mats[1], mats[2], mats[3], fd_h, free_term ? 1 : 0, nrhs, w, x, so);
+    hipLaunchKernelGGL(k_adjoint_kself, dim3((unsigned)(((size_t)K + 63) / 64)), dim3(64), 0, st, c, free_term ? 1 : 0,
+                       nrhs, w, x, so);
     BEM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_tiles, dim3((unsigned)((9 * (size_t)K + WG - 1) / WG)), dim3(WG), 0, st, gJ, (int)ti,
                        9 * (size_t)K, sum);

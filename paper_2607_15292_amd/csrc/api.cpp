@@ -1160,13 +1160,8 @@ int bem_adjoint_k(bem_ctx* ctx, int32_t op, int32_t nrhs, const void* w, const v
         work.alloc(adjoint_work_doubles(K) * sizeof(double));
         double *sums = nullptr, *tiles = nullptr, *self_out = nullptr;
         int ntiles = 0;
-        constexpr double FD_H = 1e-5;  // relative step of the self pairs' central differences
-        const Mat<double> mats[4] = {make_mat<double>(ctx->rho, ctx->cp * (1.0 + FD_H), ctx->cs),
-                                     make_mat<double>(ctx->rho, ctx->cp * (1.0 - FD_H), ctx->cs),
-                                     make_mat<double>(ctx->rho, ctx->cp, ctx->cs * (1.0 + FD_H)),
-                                     make_mat<double>(ctx->rho, ctx->cp, ctx->cs * (1.0 - FD_H))};
-        launch_adjoint_k(ctx->devctx(ctx->dgeo.geo, nullptr), mats, FD_H, op == BEM_OP_HK, nrhs, (const zd*)sw.dev,
-                         (const zd*)sx.dev, work.as<double>(), &sums, &tiles, &ntiles, &self_out, st);
+        launch_adjoint_k(ctx->devctx(ctx->dgeo.geo, nullptr), op == BEM_OP_HK, nrhs, (const zd*)sw.dev, (const zd*)sx.dev,
+                         work.as<double>(), &sums, &tiles, &ntiles, &self_out, st);
         // T does not depend on rho
         adjoint_finish(ctx, sums, tiles, ntiles, self_out, 0.0, value, grad_nodes, grad_mat);
         return BEM_OK;

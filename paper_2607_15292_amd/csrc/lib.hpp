@@ -73,8 +73,7 @@ void launch_mf_apply_kl(const DevCtx& c, const int* tri, int nnodes, int nrhs, c
 size_t adjoint_work_doubles(int K);
 void launch_adjoint_v(const DevCtx& c, int nrhs, const zd* w, const zd* x, double* work, double** sums, double** tiles,
                       int* ntiles, double** self_out, hipStream_t st);
-void launch_adjoint_k(const DevCtx& c, const Mat<double> mats[4], double fd_h, bool free_term, int nrhs, const zd* w,
-                      const zd* x, double* work, double** sums, double** tiles, int* ntiles, double** self_out,
-                      hipStream_t st);
+void launch_adjoint_k(const DevCtx& c, bool free_term, int nrhs, const zd* w, const zd* x, double* work, double** sums,
+                      double** tiles, int* ntiles, double** self_out, hipStream_t st);
 
 }  // namespace bem
