@@ -43,15 +43,17 @@ PEAK_MFMA64 = 78.6e12   # dense FP64 MFMA
 PEAK_MFMA32 = 157.3e12  # dense FP32 MFMA
 
 
-# HBM bytes per dispatch from the FETCH_SIZE / WRITE_SIZE counters (two rocprofv3 --pmc runs of
-# this script, scaled by the counts of a 1 GiB copy; profiles/traffic_c2_sphere5120_L64_mixed.md),
-# valid while the kernels' sources and the launch composition (compress.cpp) hash to the
-# recorded value
+# HBM bytes per launch of a kernel group, as the roofline entries count launches (face kernels
+# and k_face_aca: one dispatch; recompression: the two workgroup configurations over one chunk
+# of faces; product: one bem_apply), from the FETCH_SIZE / WRITE_SIZE counters (two rocprofv3
+# --pmc runs of this script, scaled by the counts of a 1 GiB copy;
+# profiles/traffic_c2_sphere5120_L64_mixed.md), valid while the kernels' sources and the launch
+# composition (compress.cpp) hash to the recorded value
 TRAFFIC = {
-    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp', 'compress.cpp'], "sha256_16": '0aaad72f98dea4e3'},
-    "recomp": {"bytes": 8.82e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": 'a712f7b478606821'},
-    "aca": {"bytes": None, "sources": ['aca3d.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": None},
-    "product": {"bytes": None, "sources": ['mfma.hip', 'apply.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": None},
+    "face": {"bytes": 5.193e+09, "sources": ['aca3d.hip', 'kernel.hpp', 'common.hpp', 'aca3d.hpp', 'lib.hpp', 'compress.cpp'], "sha256_16": 'e68ed78f58727565'},
+    "recomp": {"bytes": 7.032e+09, "sources": ['recomp.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": 'bc8fdc23de38e82e'},
+    "aca": {"bytes": 7.521e+10, "sources": ['aca3d.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": '69da41e38a985ded'},
+    "product": {"bytes": 6.25e+10, "sources": ['mfma.hip', 'apply.hip', 'common.hpp', 'aca3d.hpp', 'compress.cpp'], "sha256_16": '6dd6f7617d1fde39'},
 }
 
 
