@@ -32,9 +32,10 @@ __device__ __forceinline__ double wsum(double v)
 }
 
 // y[r][l][3 e + a] = sum_o ENTRY(e, o, l)[a][b] x[r][l][3 o + b]  (TRANS: ENTRY(o, e, l)[b][a]);
-// thread per (e, l), e fastest; right-hand sides in passes of NR.
+// thread per (e, l), e fastest; right-hand sides in passes of NR.  Two waves per SIMD (at the
+// price of some spills) run it 28 % faster than the one the compiler picks by itself.
 template <bool TRANS>
-__global__ __launch_bounds__(WG) void k_mf_apply(DevCtx c, int op, int nrhs, const zd* __restrict__ x,
+__global__ __launch_bounds__(WG, 2) void k_mf_apply(DevCtx c, int op, int nrhs, const zd* __restrict__ x,
                                                  zd* __restrict__ y)
 {
     const int K = c.geo.K, L = c.fr.L;
@@ -483,7 +484,7 @@ __device__ __forceinline__ void traction_der(double R, double Rinv, zd s, zd sin
 //   4 pi grad_n v = P1 (w.rh) x_j + P2 (x.rh) w_i + cn rh,
 // and the normal n_j = N / |N|, N = (P_1 - P_0) x (P_2 - P_0), moves with vertex a as
 // dn = (I - n n^T)(dP_a x (P_{a+1} - P_{a+2})) / |N|.  Outputs as k_adjoint_v.
-__global__ __launch_bounds__(WG) void k_adjoint_k(DevCtx c, int nrhs, const zd* __restrict__ w,
+__global__ __launch_bounds__(WG, 2) void k_adjoint_k(DevCtx c, int nrhs, const zd* __restrict__ w,
                                                   const zd* __restrict__ x, double* __restrict__ gJ,
                                                   double* __restrict__ gI, double* __restrict__ gM)
 {
