@@ -6,9 +6,9 @@ shares no code with it.
 
 * ``bem_oracle.c`` (plain C99, FP64, optional OpenMP): kernel U and T of the paper's
   Appendix A / Sec. 2.1, collocation entries with the quadrature rules, dense products, and
-  the gradient of a single-layer bilinear form with respect to the node coordinates and the
-  material (regular and near pairs by the chain rule, self pairs as the derivative of the
-  integral).
+  the gradients of single- and double-layer bilinear forms with respect to the node
+  coordinates and the material (regular and near pairs by the chain rule, self pairs as the
+  derivative of the integral, the double layer's as a principal value).
 * ``aca3d.py`` (numpy): the matrix-valued 3D-ACA of Algorithm 1 (Sec. 3), the matrix-valued
   ACA with QR/SVD recompression of eq. (ACA), and the H-matrix variant of Sec. 3.1 (faces
   approximated inside the loop, pivot on the reconstruction), for small tensors.

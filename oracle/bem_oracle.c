@@ -36,6 +36,11 @@
  *     with the leading part weighted by lambda_v at the centroid (1/3), the remainder
  *     T (lambda_v(y) - 1/3) being weakly singular.  The linear-basis operator sums these over
  *     the elements sharing a node.
+ *   - oracle_adjoint_v / oracle_adjoint_k: the gradient of Re sum_l w_l^T A(s_l) x_l (A = V,
+ *     K or I/2 + K) with respect to the node coordinates and the material, the pair classes
+ *     held fixed: regular and near pairs by the chain rule through the quadrature points, the
+ *     normal, the area and the collocation point; self pairs as the derivative of the
+ *     (principal-value) integral, or by central differences of the polar rule.
  *
  * Everything is written per entry, per quadrature point, per frequency; no blocking,
  * no reuse across frequencies, no shared tables with the GPU library.

@@ -145,3 +145,22 @@ def test_compressed_shared_x_and_ragged_leaf(torch):
     y = op.apply(x, shared_x=True)
     err = relerr(y, np.einsum("lij,rj->rli", D, x))
     assert err < 1e-7, err
+
+
+def test_largest_frequency_count(torch):
+    # the compression's limit of 256 contour points: a full-size fibre set (L = 256) on the
+    # 80-triangle sphere against the dense FP64 oracle, and L = 257 refused before any work
+    X, T = W.icosphere(1)
+    L = 256
+    s = W.bdf2_contour(L, 0.1)
+    c = ctx_for(X, T, s, near_on=True)
+    op = c.compress(B.OP_HK, eps3d=1e-8, leaf=8, prec=B.PREC_F64)
+    st = op.stats()
+    assert st["n_far"] > 0 and st["rank_max"] <= L
+    D = _dense_oracle(X, T, s, B.OP_HK, True)
+    x = W.random_rhs(9, (1, L, 3 * len(T)))
+    err = relerr(op.apply(x), np.einsum("lij,rlj->rli", D, x))
+    assert err < 1e-6, (err, st)
+    c2 = ctx_for(X, T, W.bdf2_contour(L + 1, 0.1))
+    with pytest.raises(B.BemError):
+        c2.compress(B.OP_V)
