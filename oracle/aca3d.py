@@ -17,8 +17,12 @@ Readings of the paper taken here:
     ||f_d|| is the Frobenius norm over all L blocks.
   * r = d - 1 when the test of eq. (precision) fails (the sub-tolerance pair is dropped);
     r = L when every frequency has been used.
-  * "sigma_3 = 0 for all (i, j)" is read as max sigma_3 <= PIVOT_RTOL * max block norm;
-    the block is then kept dense (one face per frequency with a selector fibre), except
+  * "sigma_3 = 0 for all (i, j)" is read as max sigma_3 <= PIVOT_RTOL_3D * scale, the scale
+    being the largest 3x3 block norm of the slices C[k_1], ..., C[k_d] formed so far (the
+    algorithm never sees the others; a smaller scale, e.g. the residual face's, lets
+    rounding noise through as a pivot); in the H-matrix ACA variant the slice is never
+    formed and the reconstructed residual face stands in for it.  The block is then kept
+    dense (one face per frequency with a selector fibre), except
     when d > 1 and the residual face itself is below eps ||C^(d-1)||_F, which means the
     tensor is already reproduced (then r = d - 1).
   * Ties of an argmax go to the smallest index (row-major (i, j); smallest k).
@@ -45,12 +49,21 @@ from __future__ import annotations
 
 import numpy as np
 
-PIVOT_RTOL = 1e-14
+PIVOT_RTOL = 1e-14     # matrix-valued ACA: a residual row without a regular block
+# Algorithm 1: a residual face whose 3x3 blocks are all singular still shows sigma_3 of a few
+# eps times the largest face-fibre product subtracted from it (up to about 1e-14 of the
+# scale on small clusters); the threshold stays two orders above that rounding level
+PIVOT_RTOL_3D = 1e-12
 
 
 def sigma3(B):
     """Smallest singular value of each 3x3 block of B[..., 3, 3]."""
     return np.linalg.svd(B, compute_uv=False)[..., -1]
+
+
+def _blockmax(H):
+    """Largest Frobenius norm of the 3x3 blocks of H[..., 3, 3]."""
+    return float(np.sqrt(np.max(np.sum(np.abs(H) ** 2, axis=(-2, -1)))))
 
 
 def _fro2(A):
@@ -103,11 +116,13 @@ def aca3d(C, eps, eps_aca=None):
     used = np.zeros(L, dtype=bool)
     k = 0
     d = 0
-    blocknorm = np.sqrt(np.max(np.sum(np.abs(C) ** 2, axis=(-2, -1))))
+    scale = 0.0  # largest 3x3 block norm of the slices formed so far
     while True:
         d += 1
         # face at k_d: entries minus the current approximation C^(d-1)
         R = C[k].copy()
+        if eps_aca is None:
+            scale = max(scale, _blockmax(R))
         for Ha, fa in zip(faces, fibres):
             R -= np.einsum("ijab,bc->ijac", Ha, fa[k])
         uv = None
@@ -121,11 +136,13 @@ def aca3d(C, eps, eps_aca=None):
                 Hd = R
         else:
             Hd = R
+        if eps_aca is not None:
+            scale = max(scale, _blockmax(Hd))
         s3 = sigma3(Hd)
         flat = int(np.argmax(s3))
         i_d, j_d = divmod(flat, n)
-        if not (s3[i_d, j_d] > PIVOT_RTOL * blocknorm):
-            if blocknorm == 0.0:
+        if not (s3[i_d, j_d] > PIVOT_RTOL_3D * scale):
+            if not np.any(C):
                 return Approx3D([], [], [], [], dense=False)
             if d > 1 and np.sqrt(_fro2(R)) <= eps * np.sqrt(max(norm2, 0.0)):
                 # the residual face vanishes: the tensor is reproduced, stop with r = d - 1

@@ -34,7 +34,12 @@ namespace bem {
 namespace {
 
 constexpr int WG = 256;
-constexpr double PIVOT_RTOL = 1e-14;
+constexpr double PIVOT_RTOL = 1e-14;     // matrix-valued ACA of a face: no regular block
+// Algorithm 1's "sigma_3 = 0 for all pairs": below this fraction of the block's scale.  A
+// residual face formed after d steps carries rounding noise of a few eps times the largest
+// face-fibre product subtracted from it, up to about 1e-14 of the scale where the residual's
+// 3x3 blocks are all singular; the threshold stays two orders above that noise
+constexpr double PIVOT_RTOL_3D = 1e-12;
 constexpr int MAX_FAIL = 8;
 
 // ---------------------------------------------------------------- workgroup reductions
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(256) void k_init(CompressArgs A)
     s.recomp_flop = 0.0;
     s.aca_flop = 0.0;
     s.aca_bytes = 0.0;
-    s.pad2 = 0.0;
+    s.fref = 0.0;
     for (int t = 0; t < 9; ++t) s.pinv[t] = {0.0, 0.0};
     for (int k = 0; k < A.L; ++k) A.used[(size_t)b * A.L + k] = 0;
     if (!alloc_step(A, b, 0, 0)) s.active = 0;
@@ -390,7 +395,8 @@ __device__ __forceinline__ int tile_pair(const CompressArgs& A, const BlockIn& B
 }
 
 // tile partials: [0] sigma_3 max, [1] pivot pair, [2] sum |H|^2, [3] max block |H|^2,
-//                [4] cross re, [5] t_dd re
+//                [4] cross re, [5] t_dd re, [6] max block |C(k)|^2 of the entries before
+//                the residual is taken
 template <int KOP, int PATH>
 __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
 {
@@ -405,11 +411,12 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
     const FaceDesc* fd = A.faces + (size_t)b * A.L;
     const FaceDesc F = fd[d];
     const int p = tile_pair(A, B, t, threadIdx.x);
-    double s3 = -1.0, e2 = 0.0, cross = 0.0, tdd = 0.0;
+    double s3 = -1.0, e2 = 0.0, cross = 0.0, tdd = 0.0, c2 = 0.0;
     int pi = 0x7fffffff;
     if (p >= 0) {
         const int i = p / n, j = p - (p / n) * n;
         blk E = pair_entry<KOP, PATH>(A, B.rb + i, B.cb + j, k);
+        c2 = blk_fro2(E);
         sub_residual_cross<F32>(E, A.pool, fd, A.Fda + (size_t)b * A.L * 9, d, n, i, j, k, cross, tdd);
         const size_t ld = 3 * (size_t)n;
         if constexpr (F32) {
@@ -437,6 +444,7 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
     double v[3] = {e2, cross, tdd};
     wg_sum<3>(v, S);
     double fm = wg_max(e2, S);
+    double cm = wg_max(c2, S);
     wg_argmax(s3, pi, S);
     if (threadIdx.x == 0) {
         double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
@@ -446,6 +454,7 @@ __global__ __launch_bounds__(WG) void k_face_dense(CompressArgs A)
         tp[3] = fm;
         tp[4] = v[1];  // trace-form terms of step d - 1
         tp[5] = v[2];
+        tp[6] = cm;
         atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(TILE, B.nreg - t * TILE)));
     }
 }
@@ -488,7 +497,7 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
     const int p = valid ? A.pairs[B.pair0 + base + q] : 0;
     const int i = p / n, j = p - (p / n) * n;
     blk E = blk_zero();
-    double cross = 0.0, tdd = 0.0;
+    double cross = 0.0, tdd = 0.0, c2 = 0.0;
     if (valid) {
         const int nu = rule_units(cls, A.c.qt);
         for (int uu = u; uu < nu; uu += lpp) {
@@ -505,8 +514,14 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
             E.a[4].re += 0.5;
             E.a[8].re += 0.5;
         }
-        sub_residual_share_cross(E, A, fd, A.Fda + (size_t)b * A.L * 9, d, n, i, j, k, u, lpp, cross, tdd);
     }
+    {
+        // the entry before the residual is taken: summed over the lanes of the pair
+        blk C = E;
+        group_sum(C, lpp);
+        if (valid && u == 0) c2 = blk_fro2(C);
+    }
+    if (valid) sub_residual_share_cross(E, A, fd, A.Fda + (size_t)b * A.L * 9, d, n, i, j, k, u, lpp, cross, tdd);
     group_sum(E, lpp);
     double s3 = -1.0, e2 = 0.0;
     int pi = 0x7fffffff;
@@ -537,6 +552,7 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
     double v[3] = {e2, cross, tdd};
     wg_sum<3>(v, S);
     double fm = wg_max(e2, S);
+    double cm = wg_max(c2, S);
     wg_argmax(s3, pi, S);
     if (threadIdx.x == 0) {
         double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
@@ -546,6 +562,7 @@ __global__ __launch_bounds__(WG) void k_face_general(CompressArgs A)
         tp[3] = fm;
         tp[4] = v[1];  // trace-form terms of step d - 1
         tp[5] = v[2];
+        tp[6] = cm;
         atomicAdd((unsigned long long*)&A.st[b].entries, (unsigned long long)max(0, min(ppt, cnt - tl * ppt)));
     }
     (void)m;
@@ -1151,6 +1168,7 @@ __global__ __launch_bounds__(WG) void k_iloop_recon(CompressArgs A)
         tp[1] = (double)pi;
         tp[2] = v[0];
         tp[3] = fm;
+        tp[6] = fm;  // the slice itself is never formed: its reconstructed residual stands in
     }
 }
 
@@ -1190,7 +1208,7 @@ __global__ __launch_bounds__(64) void k_pivot(CompressArgs A)
     if (!s.active) return;
     const BlockIn B = A.blocks[b];
     const int d = A.d;
-    double best = -1.0, h2 = 0.0, fm = 0.0;
+    double best = -1.0, h2 = 0.0, fm = 0.0, cm = 0.0;
     int pi = 0x7fffffff;
     for (int t = 0; t < B.ntile; ++t) {
         const double* tp = A.tp + (size_t)(B.tile0 + t) * 8;
@@ -1203,18 +1221,24 @@ __global__ __launch_bounds__(64) void k_pivot(CompressArgs A)
         }
         h2 += tp[2];
         fm = fmax(fm, tp[3]);
+        cm = fmax(cm, tp[6]);
     }
     s.hn2 = h2;
     s.fmax2 = fm;
     s.s3max = best;
     s.stop = 0;
+    // the scale of the pivot test: the block's magnitude, the largest 3x3 block of the
+    // slices C(k_1..k_d) formed so far.  A pivot judged against the shrinking residual face,
+    // or against a slice smaller than a later one, lets rounding noise of a residual of
+    // rank-deficient 3 x 3 blocks through as a pivot
+    s.fref = fmax(s.fref, sqrt(cm));
     const double eps = block_eps(A, B);
     if (d > 0 && sqrt(h2) <= eps * sqrt(fmax(s.norm2, 0.0))) {
         // the residual face vanishes: C^(d-1) reproduces the array; rank d
         s.stop = 1;
         s.active = 0;
         s.rank = d;
-    } else if (!(best > PIVOT_RTOL * sqrt(fm))) {
+    } else if (!(best > PIVOT_RTOL_3D * s.fref)) {
         s.stop = 1;
         s.active = 0;
         s.fallback = 1;

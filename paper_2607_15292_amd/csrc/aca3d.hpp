@@ -57,7 +57,7 @@ struct BlockState {
     double recomp_flop;  // algorithmic flops of this block's face recompressions
     double aca_flop;     // algorithmic flops and HBM bytes of this block's per-slice ACA runs
     double aca_bytes;
-    double pad2;
+    double fref;    // pivot scale: the largest 3x3 block norm of the slices C(k_1..k_d) so far
     zd pinv[9];
 };
 

@@ -202,8 +202,51 @@ BEM_HD double herm3_lambda_max(const blk& M)
     return q + 2.0 * p * cos(phi);
 }
 
+// |r_33| of the Householder QR of a 3x3 complex block with column pivoting: after the first
+// reflection (the column of largest norm) the trailing 2 x 2 block B has |r_22 r_33| =
+// |det B| and |r_22| = the larger column norm of B.  Backward stable (errs by about
+// eps ||A||) and never below sigma_3 (sigma_3 <= ||R_22||, here |r_33|).
+BEM_HD double blk_r33(const blk& A)
+{
+    double n[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) n[j] += abs2(A.a[3 * i + j]);
+    const int p = n[0] >= n[1] ? (n[0] >= n[2] ? 0 : 2) : (n[1] >= n[2] ? 1 : 2);
+    const double al = sqrt(n[p]);
+    if (!(al > 0.0)) return 0.0;
+    // v = x + e^{i arg x_0} ||x|| e_0, H = I - 2 v v^H / (v^H v)
+    zd v[3] = {A.a[p], A.a[3 + p], A.a[6 + p]};
+    const double a0 = sqrt(abs2(v[0]));
+    const zd ph = a0 > 0.0 ? v[0] * (1.0 / a0) : zd{1.0, 0.0};
+    v[0] += ph * al;
+    const double vv = abs2(v[0]) + abs2(v[1]) + abs2(v[2]);
+    zd B[2][2];
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (q == p) continue;
+        const zd y[3] = {A.a[q], A.a[3 + q], A.a[6 + q]};
+        const zd w = conj_mul(v[0], y[0]) + conj_mul(v[1], y[1]) + conj_mul(v[2], y[2]);
+        const zd f = w * (2.0 / vv);
+        B[0][c] = y[1] - v[1] * f;
+        B[1][c] = y[2] - v[2] * f;
+        ++c;
+    }
+    const double m = sqrt(fmax(abs2(B[0][0]) + abs2(B[1][0]), abs2(B[0][1]) + abs2(B[1][1])));
+    if (!(m > 0.0)) return 0.0;
+    const zd det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
+    return sqrt(abs2(det)) / m;
+}
+
 // Smallest singular value of a 3x3 complex block: sigma_3 = |det A| / sigma_1(adj A),
 // since the singular values of adj(A) are sigma_2 sigma_3, sigma_1 sigma_3, sigma_1 sigma_2.
+// The rounding of det is about eps sigma_1^3, so the quotient errs by eps sigma_1^2 / sigma_2:
+// on a block whose sigma_2 is small it is rounding noise far above the true sigma_3.  Two
+// upper bounds of sigma_3 that stay accurate there cap it: |r_33| of the pivoted QR
+// (blk_r33) and sigma_2 <= sqrt(3) sigma_1(adj A) / ||A||_F; neither is below sigma_3, so the
+// quotient stands wherever it is accurate (a well-conditioned block).
 BEM_HD double blk_sigma3(const blk& A)
 {
     blk adj;
@@ -223,7 +266,11 @@ BEM_HD double blk_sigma3(const blk& A)
         }
     double l = herm3_lambda_max(G);
     if (!(l > 0.0)) return 0.0;
-    return ad / sqrt(l);
+    const double sa = sqrt(l);
+    double f2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) f2 += abs2(A.a[t]);
+    return fmin(fmin(ad / sa, 1.7320508075688772 * sa / sqrt(f2)), blk_r33(A));
 }
 
 // sigma_3 of a block of any magnitude (computed on A / s, s = blk_pow2_scale(A)); the plain

@@ -154,7 +154,7 @@ def test_largest_frequency_count(torch):
     L = 256
     s = W.bdf2_contour(L, 0.1)
     c = ctx_for(X, T, s, near_on=True)
-    op = c.compress(B.OP_HK, eps3d=1e-8, leaf=8, prec=B.PREC_F64)
+    op = c.compress(B.OP_HK, eps3d=1e-8, leaf=4, prec=B.PREC_F64)
     st = op.stats()
     assert st["n_far"] > 0 and st["rank_max"] <= L
     D = _dense_oracle(X, T, s, B.OP_HK, True)
@@ -164,3 +164,30 @@ def test_largest_frequency_count(torch):
     c2 = ctx_for(X, T, W.bdf2_contour(L + 1, 0.1))
     with pytest.raises(B.BemError):
         c2.compress(B.OP_V)
+
+
+def test_small_clusters_fall_back_like_the_oracle(torch):
+    # clusters of 2-3 elements (leaf 4 on the 80-triangle sphere): residual faces whose 3 x 3
+    # blocks all have numerical rank 1 or 2 leave no regular pivot ("sigma_3 = 0 for all" of
+    # Algorithm 1) and the block is stored dense.  sigma_3 of such a block must not be
+    # rounding noise of its determinant: every block takes the oracle's decision, and the
+    # product matches the dense oracle
+    X, T = W.icosphere(1)
+    K, L = len(T), 16
+    s = W.bdf2_contour(L, 0.1)
+    D = _dense_oracle(X, T, s, B.OP_V, False)
+    Ct = np.ascontiguousarray(D.reshape(L, K, 3, K, 3).transpose(0, 1, 3, 2, 4))
+    c = ctx_for(X, T, s)
+    c.set_entry_table(torch.tensor(Ct, device="cuda"))
+    op = c.compress(B.OP_TABLE, eps3d=1e-8, leaf=4)
+    rows, perm = op.blocks()
+    nfb = 0
+    for r in rows:
+        rb, rs, cb, cs = (int(v) for v in r[:4])
+        ap = A3.aca3d(Ct[:, perm[rb:rb + rs]][:, :, perm[cb:cb + cs]], 1e-8)
+        assert bool(r[6]) == ap.dense, (r, ap.rank)
+        nfb += int(r[6])
+    assert nfb > 0
+    x = W.random_rhs(10, (1, L, 3 * K))
+    err = relerr(op.apply(x), np.einsum("lij,rlj->rli", D, x))
+    assert err < 1e-9, err
