@@ -206,53 +206,56 @@ BEM_HD double herm3_lambda_max(const blk& M)
 // reflection (the column of largest norm) the trailing 2 x 2 block B has |r_22 r_33| =
 // |det B| and |r_22| = the larger column norm of B.  Backward stable (errs by about
 // eps ||A||) and never below sigma_3 (sigma_3 <= ||R_22||, here |r_33|).
+template <int P>
+BEM_HD double blk_r33_piv(const blk& A, double al)
+{
+    // pivot column x = A e_P, the other two columns y = A e_Q, z = A e_R (static indices: no
+    // copies of the block, no indexed access)
+    constexpr int Q = P == 0 ? 1 : 0, R = P == 2 ? 1 : 2;
+    // v = x + e^{i arg x_0} ||x|| e_0, H = I - 2 v v^H / (v^H v)
+    const zd x0 = A.a[P];
+    const double a0 = sqrt(abs2(x0));
+    const zd v0 = x0 + (a0 > 0.0 ? x0 * (al / a0) : zd{al, 0.0});
+    const zd v1 = A.a[3 + P], v2 = A.a[6 + P];
+    const double g = 2.0 / (abs2(v0) + abs2(v1) + abs2(v2));
+    const zd fy = (conj_mul(v0, A.a[Q]) + conj_mul(v1, A.a[3 + Q]) + conj_mul(v2, A.a[6 + Q])) * g;
+    const zd fz = (conj_mul(v0, A.a[R]) + conj_mul(v1, A.a[3 + R]) + conj_mul(v2, A.a[6 + R])) * g;
+    // trailing 2 x 2 block [b00 b01; b10 b11] of H [y z]
+    const zd b00 = A.a[3 + Q] - v1 * fy, b10 = A.a[6 + Q] - v2 * fy;
+    const zd b01 = A.a[3 + R] - v1 * fz, b11 = A.a[6 + R] - v2 * fz;
+    const double m = sqrt(fmax(abs2(b00) + abs2(b10), abs2(b01) + abs2(b11)));
+    if (!(m > 0.0)) return 0.0;
+    return sqrt(abs2(b00 * b11 - b01 * b10)) / m;
+}
+
 BEM_HD double blk_r33(const blk& A)
 {
-    double n[3] = {0.0, 0.0, 0.0};
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0;
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) n[j] += abs2(A.a[3 * i + j]);
-    const int p = n[0] >= n[1] ? (n[0] >= n[2] ? 0 : 2) : (n[1] >= n[2] ? 1 : 2);
-    const double al = sqrt(n[p]);
-    if (!(al > 0.0)) return 0.0;
-    // v = x + e^{i arg x_0} ||x|| e_0, H = I - 2 v v^H / (v^H v)
-    zd v[3] = {A.a[p], A.a[3 + p], A.a[6 + p]};
-    const double a0 = sqrt(abs2(v[0]));
-    const zd ph = a0 > 0.0 ? v[0] * (1.0 / a0) : zd{1.0, 0.0};
-    v[0] += ph * al;
-    const double vv = abs2(v[0]) + abs2(v[1]) + abs2(v[2]);
-    zd B[2][2];
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        if (q == p) continue;
-        const zd y[3] = {A.a[q], A.a[3 + q], A.a[6 + q]};
-        const zd w = conj_mul(v[0], y[0]) + conj_mul(v[1], y[1]) + conj_mul(v[2], y[2]);
-        const zd f = w * (2.0 / vv);
-        B[0][c] = y[1] - v[1] * f;
-        B[1][c] = y[2] - v[2] * f;
-        ++c;
+    for (int i = 0; i < 3; ++i) {
+        n0 += abs2(A.a[3 * i]);
+        n1 += abs2(A.a[3 * i + 1]);
+        n2 += abs2(A.a[3 * i + 2]);
     }
-    const double m = sqrt(fmax(abs2(B[0][0]) + abs2(B[1][0]), abs2(B[0][1]) + abs2(B[1][1])));
-    if (!(m > 0.0)) return 0.0;
-    const zd det = B[0][0] * B[1][1] - B[0][1] * B[1][0];
-    return sqrt(abs2(det)) / m;
+    if (n0 >= n1 && n0 >= n2) return n0 > 0.0 ? blk_r33_piv<0>(A, sqrt(n0)) : 0.0;
+    if (n1 >= n2) return blk_r33_piv<1>(A, sqrt(n1));
+    return blk_r33_piv<2>(A, sqrt(n2));
 }
 
 // Smallest singular value of a 3x3 complex block: sigma_3 = |det A| / sigma_1(adj A),
 // since the singular values of adj(A) are sigma_2 sigma_3, sigma_1 sigma_3, sigma_1 sigma_2.
 // The rounding of det is about eps sigma_1^3, so the quotient errs by eps sigma_1^2 / sigma_2:
-// on a block whose sigma_2 is small it is rounding noise far above the true sigma_3.  Two
-// upper bounds of sigma_3 that stay accurate there cap it: |r_33| of the pivoted QR
-// (blk_r33) and sigma_2 <= sqrt(3) sigma_1(adj A) / ||A||_F; neither is below sigma_3, so the
-// quotient stands wherever it is accurate (a well-conditioned block).
+// on a block whose sigma_2 is small it is rounding noise far above the true sigma_3.  |r_33|
+// of the pivoted QR (blk_r33) caps it: an upper bound of sigma_3 that stays within a factor
+// 3 of it and is backward stable, so the quotient stands wherever it is accurate.
 BEM_HD double blk_sigma3(const blk& A)
 {
+    // |r_33| first, and tested at once: A is not needed after the adjugate
+    const double r33 = blk_r33(A);
     blk adj;
     zd det = blk_det_adj(A, adj);
     double ad = sqrt(abs2(det));
-    if (!(ad > 0.0)) return 0.0;
+    if (!(ad > 0.0) || !(r33 > 0.0)) return 0.0;
     // G = adj^H adj
     blk G;
 #pragma unroll
@@ -266,11 +269,7 @@ BEM_HD double blk_sigma3(const blk& A)
         }
     double l = herm3_lambda_max(G);
     if (!(l > 0.0)) return 0.0;
-    const double sa = sqrt(l);
-    double f2 = 0.0;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) f2 += abs2(A.a[t]);
-    return fmin(fmin(ad / sa, 1.7320508075688772 * sa / sqrt(f2)), blk_r33(A));
+    return fmin(ad / sqrt(l), r33);
 }
 
 // sigma_3 of a block of any magnitude (computed on A / s, s = blk_pow2_scale(A)); the plain
