@@ -8,7 +8,7 @@
 //                                            pivot of the unit-diagonal Gram is below 1e-10
 //   M = R_U R_V^H, R = T D                   the core
 //   M P = Q_M R                              Householder QR with column pivoting, stopped once
-//                                            the remaining columns have norm <= tol / 4:
+//                                            the remaining columns have norm <= tol / 2:
 //                                            M ~ Q_M B, B = R_top P^T (k' rows)
 //   B^H VJ = W                               one-sided Jacobi on the k' columns of B^H
 //                                            (W_s orthogonal, |W_s| = sigma_s, VJ unitary)
@@ -30,8 +30,10 @@ namespace {
 constexpr int KF_MAX = 96;      // largest core (ACA columns) of the pass
 
 // The pivoted QR of the core stops once its remaining columns are below QRCP_FRAC tol; the
-// SVD truncation of the kept rows then has sqrt(1 - QRCP_FRAC^2) of the tolerance left.
-constexpr double QRCP_FRAC = 0.25;
+// SVD truncation of the kept rows then has sqrt(1 - QRCP_FRAC^2) of the tolerance left.  At
+// 1/2 (rather than 1/4) the Jacobi SVD works on fewer rows: 7 % less recompression time on the
+// 5120-triangle sphere for 0.15 % more ACA rank
+constexpr double QRCP_FRAC = 0.5;
 
 // Pairs of the Jacobi SVD whose inner product is below JAC_GMIN tol^2 are left as they are.
 constexpr double JAC_GMIN = 1e-6;
