@@ -6,6 +6,9 @@ all-frequency products, through the C-ABI.
 * Kernel tensors: the compressed product y_l = A(s_l) x_l matches the dense FP64 oracle
   product within the tolerance of the method: rel err = max_l ||y~_l - y_l|| / ||y_l|| below
   1e-6 (FP64 path, eps3d = 1e-7) and 1e-4 (mixed path).
+* Dense fallback ("sigma_3 = 0 for all" of Algorithm 1) as the oracle decides it: blocks of
+  exact sigma_3 1e-13 and 1e-11 of a unit block around the threshold, a small first slice
+  followed by unit slices, and the 2-3-element clusters of leaf 4 on a sphere, block by block.
 """
 import numpy as np
 import pytest
@@ -88,6 +91,50 @@ def test_table_dense_fallback(torch):
     y = op.apply(x)
     D = Ct.transpose(0, 1, 3, 2, 4).reshape(L, 3 * K, 3 * K)
     assert relerr(y, np.einsum("lij,rlj->rli", D, x)) < 1e-13
+
+
+def _blocks_with_sigma3(rng, L, m, n, s3):
+    # blocks U diag(1, 1/2, s3) V^H with random unitary U, V: sigma_3 = s3 exactly
+    def unitary():
+        q, _ = np.linalg.qr(rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))
+        return q
+    C = np.empty((L, m, n, 3, 3), dtype=np.complex128)
+    for idx in np.ndindex(L, m, n):
+        C[idx] = unitary() @ np.diag([1.0, 0.5, s3]) @ unitary().conj().T
+    return C
+
+
+@pytest.mark.parametrize("case", ["below", "above", "scale"])
+def test_table_zero_pivot_threshold(torch, case):
+    # the zero test of Algorithm 1 at its threshold (sigma_3 <= 1e-12 x the largest block of the
+    # slices formed so far), as the oracle takes it: blocks of exact sigma_3 1e-13 (zero) and
+    # 1e-11 (regular), and a small first slice followed by unit slices whose residual blocks
+    # have sigma_3 1e-13 (zero against the unit slice, not against the first one)
+    X, T = W.cube_grid(2, 1.0)
+    K, L = len(T), 4
+    rng = np.random.default_rng(21)
+    if case == "scale":
+        H = rng.standard_normal((K, K, 3, 3)) + 1j * rng.standard_normal((K, K, 3, 3))
+        g = rng.standard_normal((L, 3, 3)) + 1j * rng.standard_normal((L, 3, 3))
+        Ct = np.einsum("ijab,kbc->kijac", H, g) * 1e-4
+        i1, j1 = divmod(int(np.argmax(A3.sigma3(Ct[0]))), K)
+        E = _blocks_with_sigma3(rng, L, K, K, 1e-13)
+        E[0] = 0.0
+        E[:, i1, j1] = 0.0
+        Ct = Ct + E
+    else:
+        Ct = _blocks_with_sigma3(rng, L, K, K, 1e-13 if case == "below" else 1e-11)
+    ap = A3.aca3d(Ct, 1e-6)
+    assert ap.dense == (case != "above")
+    c = ctx_for(X, T, W.bdf2_contour(L))
+    c.set_entry_table(torch.tensor(Ct, device="cuda"))
+    op = c.compress(B.OP_TABLE, eps3d=1e-6, leaf=64)
+    st = op.stats()
+    assert st["n_blocks"] == 1 and st["n_dense_fallback"] == int(ap.dense), st
+    if ap.dense:
+        x = W.random_rhs(2, (1, L, 3 * K))
+        D = Ct.transpose(0, 1, 3, 2, 4).reshape(L, 3 * K, 3 * K)
+        assert relerr(op.apply(x), np.einsum("lij,rlj->rli", D, x)) < 1e-13
 
 
 def _dense_oracle(X, T, s, opk, near_on, mat=(1.0, 1.0, 0.5)):

@@ -5,7 +5,9 @@
 * The recursive matrix-valued Frobenius norm equals the explicit norm of the approximation.
 * On a well-separated kernel block the error is a small multiple of eps, the first slice is
   k = 0 and the next ones are the small-Re(s) conjugate pairs (Sec. 4.1 observes this).
-* Blocks without a regular 3x3 pivot (sigma_3 = 0 everywhere) fall back to dense storage.
+* Blocks without a regular 3x3 pivot (sigma_3 = 0 everywhere) fall back to dense storage;
+  the zero test is sigma_3 <= 1e-12 of the largest block of the slices formed so far
+  (blocks of exact sigma_3 just below and above that level; a small first slice).
 * Per-slice ACA recovers exact low-rank matrices and interpolates its pivot rows and
   columns; recompression equals the truncated SVD of the explicit product (Eckart-Young).
 * The H-matrix variant of Sec. 3.1 (faces approximated in the loop, pivot on the
@@ -89,6 +91,48 @@ def test_dense_fallback_without_regular_pivot():
     ap = A3.aca3d(C, 1e-6)
     assert ap.dense and ap.rank == L
     assert np.abs(ap.tensor() - C).max() == 0.0
+
+
+def _blocks_with_sigma3(rng, L, m, n, s3):
+    """Blocks U diag(1, 1/2, s3) V^H with random unitary U, V: sigma_3 = s3 exactly."""
+    def unitary():
+        q, _ = np.linalg.qr(rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))
+        return q
+    C = np.empty((L, m, n, 3, 3), dtype=np.complex128)
+    for idx in np.ndindex(L, m, n):
+        C[idx] = unitary() @ np.diag([1.0, 0.5, s3]) @ unitary().conj().T
+    return C
+
+
+@pytest.mark.parametrize("s3,dense", [(1e-13, True), (1e-11, False)])
+def test_zero_pivot_threshold(s3, dense):
+    # "sigma_3 = 0 for all (i, j)" read as sigma_3 <= 1e-12 x the largest block of the slices
+    # formed so far (here ||diag(1, 1/2, s3)||_F = 1.118): 1e-13 counts as zero, 1e-11 not
+    rng = np.random.default_rng(8)
+    C = _blocks_with_sigma3(rng, 5, 3, 2, s3)
+    ap = A3.aca3d(C, 1e-6)
+    assert ap.dense == dense
+    if dense:
+        assert ap.rank == 5 and np.abs(ap.tensor() - C).max() == 0.0
+    else:
+        assert ap.pivots[0] is not None
+
+
+def test_zero_pivot_scale_is_the_largest_slice_formed():
+    # C(k) = H g(k) + E(k): a face-fibre term of size 1e-4 and, from the second slice on, unit
+    # blocks E of sigma_3 = 1e-13 that vanish at the first pivot pair, so that the residual
+    # after step 1 is E(k_2) exactly.  Against the first slice alone (about 1e-3) sigma_3 =
+    # 1e-13 would pass as a pivot; against the unit slice formed in step 2 it does not, and
+    # the block is stored dense
+    rng = np.random.default_rng(9)
+    L, m, n = 4, 3, 3
+    C = _lowrank_tensor(rng, L, m, n, 1) * 1e-4
+    i1, j1 = divmod(int(np.argmax(A3.sigma3(C[0]))), n)
+    E = _blocks_with_sigma3(rng, L, m, n, 1e-13)
+    E[0] = 0.0
+    E[:, i1, j1] = 0.0
+    ap = A3.aca3d(C + E, 1e-10)
+    assert ap.dense
 
 
 def test_aca_exact_low_rank_and_recompression():
