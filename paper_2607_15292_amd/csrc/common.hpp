@@ -246,12 +246,20 @@ BEM_HD double blk_r33(const blk& A)
 // since the singular values of adj(A) are sigma_2 sigma_3, sigma_1 sigma_3, sigma_1 sigma_2.
 // The rounding of det is about eps sigma_1^3, so the quotient errs by eps sigma_1^2 / sigma_2:
 // on a block whose sigma_2 is small it is rounding noise far above the true sigma_3.  |r_33|
-// of the pivoted QR (blk_r33) caps it: an upper bound of sigma_3 that stays within a factor
-// 3 of it and is backward stable, so the quotient stands wherever it is accurate.
+// of the pivoted QR (blk_r33) caps it there: an upper bound of sigma_3 that stays within a
+// factor 3 of it and is backward stable, so the quotient stands wherever it is accurate.
 BEM_HD double blk_sigma3(const blk& A)
 {
-    // |r_33| first, and tested at once: A is not needed after the adjugate
-    const double r33 = blk_r33(A);
+    // The quotient errs by at most about eps ||A||_F^3 / |det A| relative, so |r_33| is only
+    // needed where |det A| < 1e-8 ||A||_F^3; it is taken before the adjugate (A is not needed
+    // after it), and tested at once
+    double f2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) f2 += abs2(A.a[t]);
+    const zd d0 = A.a[0] * (A.a[4] * A.a[8] - A.a[5] * A.a[7]) + A.a[1] * (A.a[5] * A.a[6] - A.a[3] * A.a[8]) +
+                  A.a[2] * (A.a[3] * A.a[7] - A.a[4] * A.a[6]);
+    double r33 = 1.0e300;
+    if (abs2(d0) < 1e-16 * f2 * f2 * f2) r33 = blk_r33(A);
     blk adj;
     zd det = blk_det_adj(A, adj);
     double ad = sqrt(abs2(det));
