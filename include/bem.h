@@ -279,7 +279,8 @@ int bem_op_dense_copy(const bem_op *op, void *dst, int32_t flags);
  * exceeds opts->far_dense_max, to the absolute tolerance eps_aca ||C^(r)||_F / ||f_d||_F
  * (each face-fibre term errs by at most about eps_aca ||C^(r)||_F); a face stays dense when
  * its ACA does not resolve it within the column cap or its factors would not save memory.
- * Dense fallback when no regular pivot exists.
+ * Dense fallback when no regular pivot exists (Algorithm 1's "sigma_3 = 0 for all pairs",
+ * taken as sigma_3 <= 1e-12 x the largest 3x3 block of the slices formed so far).
  * opts may be NULL (eps3d = 1e-6, eps_aca = eps3d / 100, eta = 1.5, leaf = 64, F64). */
 int bem_compress(bem_ctx *ctx, int32_t op, const bem_aca_opts *opts, bem_op **out);
 
