@@ -93,23 +93,25 @@ def test_table_dense_fallback(torch):
     assert relerr(y, np.einsum("lij,rlj->rli", D, x)) < 1e-13
 
 
-def _blocks_with_sigma3(rng, L, m, n, s3):
-    # blocks U diag(1, 1/2, s3) V^H with random unitary U, V: sigma_3 = s3 exactly
+def _blocks_with_sigma3(rng, L, m, n, s3, s2=0.5):
+    # blocks U diag(1, s2, s3) V^H with random unitary U, V: sigma_3 = s3 exactly
     def unitary():
         q, _ = np.linalg.qr(rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))
         return q
     C = np.empty((L, m, n, 3, 3), dtype=np.complex128)
     for idx in np.ndindex(L, m, n):
-        C[idx] = unitary() @ np.diag([1.0, 0.5, s3]) @ unitary().conj().T
+        C[idx] = unitary() @ np.diag([1.0, s2, s3]) @ unitary().conj().T
     return C
 
 
-@pytest.mark.parametrize("case", ["below", "above", "scale"])
+@pytest.mark.parametrize("case", ["below", "above", "scale", "rank1"])
 def test_table_zero_pivot_threshold(torch, case):
     # the zero test of Algorithm 1 at its threshold (sigma_3 <= 1e-12 x the largest block of the
     # slices formed so far), as the oracle takes it: blocks of exact sigma_3 1e-13 (zero) and
     # 1e-11 (regular), and a small first slice followed by unit slices whose residual blocks
-    # have sigma_3 1e-13 (zero against the unit slice, not against the first one)
+    # have sigma_3 1e-13 (zero against the unit slice, not against the first one); blocks of
+    # numerical rank 1 (sigma = 1, 1e-9, 1e-13), where |det| / sigma_1(adj) from cofactors
+    # alone would read rounding noise of 1e-9 to 1e-8 as sigma_3
     X, T = W.cube_grid(2, 1.0)
     K, L = len(T), 4
     rng = np.random.default_rng(21)
@@ -122,6 +124,8 @@ def test_table_zero_pivot_threshold(torch, case):
         E[0] = 0.0
         E[:, i1, j1] = 0.0
         Ct = Ct + E
+    elif case == "rank1":
+        Ct = _blocks_with_sigma3(rng, L, K, K, 1e-13, s2=1e-9)
     else:
         Ct = _blocks_with_sigma3(rng, L, K, K, 1e-13 if case == "below" else 1e-11)
     ap = A3.aca3d(Ct, 1e-6)

@@ -93,14 +93,14 @@ def test_dense_fallback_without_regular_pivot():
     assert np.abs(ap.tensor() - C).max() == 0.0
 
 
-def _blocks_with_sigma3(rng, L, m, n, s3):
-    """Blocks U diag(1, 1/2, s3) V^H with random unitary U, V: sigma_3 = s3 exactly."""
+def _blocks_with_sigma3(rng, L, m, n, s3, s2=0.5):
+    """Blocks U diag(1, s2, s3) V^H with random unitary U, V: sigma_3 = s3 exactly."""
     def unitary():
         q, _ = np.linalg.qr(rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))
         return q
     C = np.empty((L, m, n, 3, 3), dtype=np.complex128)
     for idx in np.ndindex(L, m, n):
-        C[idx] = unitary() @ np.diag([1.0, 0.5, s3]) @ unitary().conj().T
+        C[idx] = unitary() @ np.diag([1.0, s2, s3]) @ unitary().conj().T
     return C
 
 
@@ -116,6 +116,17 @@ def test_zero_pivot_threshold(s3, dense):
         assert ap.rank == 5 and np.abs(ap.tensor() - C).max() == 0.0
     else:
         assert ap.pivots[0] is not None
+
+
+def test_zero_pivot_on_numerically_rank_one_blocks():
+    # sigma = (1, 1e-9, 1e-13): the oracle's SVD sees sigma_3 = 1e-13 (zero), although the
+    # determinant over the adjugate's norm, both from cofactors, carries rounding noise of
+    # 1e-9 to 1e-8
+    rng = np.random.default_rng(10)
+    C = _blocks_with_sigma3(rng, 5, 3, 2, 1e-13, s2=1e-9)
+    assert np.all(A3.sigma3(C) < 2e-13)
+    ap = A3.aca3d(C, 1e-6)
+    assert ap.dense and ap.rank == 5
 
 
 def test_zero_pivot_scale_is_the_largest_slice_formed():
