@@ -202,17 +202,18 @@ BEM_HD double herm3_lambda_max(const blk& M)
     return q + 2.0 * p * cos(phi);
 }
 
-// |r_33| of the Householder QR of a 3x3 complex block with column pivoting: after the first
-// reflection (the column of largest norm) the trailing 2 x 2 block B has |r_22 r_33| =
-// |det B| and |r_22| = the larger column norm of B.  Backward stable (errs by about
-// eps ||A||) and never below sigma_3 (sigma_3 <= ||R_22||, here |r_33|).
+// sigma_3 through the Householder QR with column pivoting, A P = Q R (backward stable: R is
+// exact for a block within about eps ||A|| of A).  Then sigma_3 = |r_11 r_22 r_33| /
+// sigma_1(adj R): the determinant is a product without cancellation, and the adjugate's
+// largest singular value sigma_1 sigma_2 is dominated by its large entries, so the quotient
+// is accurate down to the rounding level eps ||A|| even on blocks of numerical rank 1 or 2.
+// P: the pivot column of the first step (static indices: no copies of the block, no indexed
+// access); al = its norm.
 template <int P>
-BEM_HD double blk_r33_piv(const blk& A, double al)
+BEM_HD double blk_sigma3_qr_piv(const blk& A, double al)
 {
-    // pivot column x = A e_P, the other two columns y = A e_Q, z = A e_R (static indices: no
-    // copies of the block, no indexed access)
     constexpr int Q = P == 0 ? 1 : 0, R = P == 2 ? 1 : 2;
-    // v = x + e^{i arg x_0} ||x|| e_0, H = I - 2 v v^H / (v^H v)
+    // first reflection H = I - g v v^H, v = x + e^{i arg x_0} ||x|| e_0 on the pivot column x
     const zd x0 = A.a[P];
     const double a0 = sqrt(abs2(x0));
     const zd v0 = x0 + (a0 > 0.0 ? x0 * (al / a0) : zd{al, 0.0});
@@ -220,15 +221,52 @@ BEM_HD double blk_r33_piv(const blk& A, double al)
     const double g = 2.0 / (abs2(v0) + abs2(v1) + abs2(v2));
     const zd fy = (conj_mul(v0, A.a[Q]) + conj_mul(v1, A.a[3 + Q]) + conj_mul(v2, A.a[6 + Q])) * g;
     const zd fz = (conj_mul(v0, A.a[R]) + conj_mul(v1, A.a[3 + R]) + conj_mul(v2, A.a[6 + R])) * g;
-    // trailing 2 x 2 block [b00 b01; b10 b11] of H [y z]
-    const zd b00 = A.a[3 + Q] - v1 * fy, b10 = A.a[6 + Q] - v2 * fy;
-    const zd b01 = A.a[3 + R] - v1 * fz, b11 = A.a[6 + R] - v2 * fz;
-    const double m = sqrt(fmax(abs2(b00) + abs2(b10), abs2(b01) + abs2(b11)));
-    if (!(m > 0.0)) return 0.0;
-    return sqrt(abs2(b00 * b11 - b01 * b10)) / m;
+    // first row of R (|r_11| = al) and the trailing 2 x 2 block [b00 b01; b10 b11] of H [y z]
+    zd r12 = A.a[Q] - v0 * fy, r13 = A.a[R] - v0 * fz;
+    zd b00 = A.a[3 + Q] - v1 * fy, b10 = A.a[6 + Q] - v2 * fy;
+    zd b01 = A.a[3 + R] - v1 * fz, b11 = A.a[6 + R] - v2 * fz;
+    // second step: the larger column of the 2 x 2 block first
+    const double ny = abs2(b00) + abs2(b10), nz = abs2(b01) + abs2(b11);
+    if (nz > ny) {
+        zd t = b00; b00 = b01; b01 = t;
+        t = b10; b10 = b11; b11 = t;
+        t = r12; r12 = r13; r13 = t;
+    }
+    const double a2 = sqrt(fmax(ny, nz));
+    if (!(a2 > 0.0)) return 0.0;
+    const double c0 = sqrt(abs2(b00));
+    const zd w0 = b00 + (c0 > 0.0 ? b00 * (a2 / c0) : zd{a2, 0.0});
+    const zd ph2 = c0 > 0.0 ? b00 * (-1.0 / c0) : zd{-1.0, 0.0};
+    const double g2 = 2.0 / (abs2(w0) + abs2(b10));
+    const zd f = (conj_mul(w0, b01) + conj_mul(b10, b11)) * g2;
+    const zd r23 = b01 - w0 * f, r33 = b11 - b10 * f;
+    // R = [r11 r12 r13; 0 r22 r23; 0 0 r33] with r11 = -e^{i arg x_0} al, r22 = e^{i arg b00} (-a2)
+    const zd ph1 = a0 > 0.0 ? x0 * (-1.0 / a0) : zd{-1.0, 0.0};
+    const zd r11 = ph1 * al, r22 = ph2 * a2;
+    // adj(R), upper triangular
+    blk C = blk_zero();
+    C.a[0] = r22 * r33;
+    C.a[1] = zd{0.0, 0.0} - r12 * r33;
+    C.a[2] = r12 * r23 - r13 * r22;
+    C.a[4] = r11 * r33;
+    C.a[5] = zd{0.0, 0.0} - r11 * r23;
+    C.a[8] = r11 * r22;
+    blk G;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            zd s = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s += conj_mul(C.a[3 * k + i], C.a[3 * k + j]);
+            G.a[3 * i + j] = s;
+        }
+    const double l = herm3_lambda_max(G);
+    if (!(l > 0.0)) return 0.0;
+    return al * a2 * sqrt(abs2(r33)) / sqrt(l);
 }
 
-BEM_HD double blk_r33(const blk& A)
+BEM_HD double blk_sigma3_qr(const blk& A)
 {
     double n0 = 0.0, n1 = 0.0, n2 = 0.0;
 #pragma unroll
@@ -237,33 +275,30 @@ BEM_HD double blk_r33(const blk& A)
         n1 += abs2(A.a[3 * i + 1]);
         n2 += abs2(A.a[3 * i + 2]);
     }
-    if (n0 >= n1 && n0 >= n2) return n0 > 0.0 ? blk_r33_piv<0>(A, sqrt(n0)) : 0.0;
-    if (n1 >= n2) return blk_r33_piv<1>(A, sqrt(n1));
-    return blk_r33_piv<2>(A, sqrt(n2));
+    if (n0 >= n1 && n0 >= n2) return n0 > 0.0 ? blk_sigma3_qr_piv<0>(A, sqrt(n0)) : 0.0;
+    if (n1 >= n2) return blk_sigma3_qr_piv<1>(A, sqrt(n1));
+    return blk_sigma3_qr_piv<2>(A, sqrt(n2));
 }
 
 // Smallest singular value of a 3x3 complex block: sigma_3 = |det A| / sigma_1(adj A),
 // since the singular values of adj(A) are sigma_2 sigma_3, sigma_1 sigma_3, sigma_1 sigma_2.
-// The rounding of det is about eps sigma_1^3, so the quotient errs by eps sigma_1^2 / sigma_2:
-// on a block whose sigma_2 is small it is rounding noise far above the true sigma_3.  |r_33|
-// of the pivoted QR (blk_r33) caps it there: an upper bound of sigma_3 that stays within a
-// factor 3 of it and is backward stable, so the quotient stands wherever it is accurate.
+// With determinant and adjugate from cofactors, the 2 x 2 minors err by eps sigma_1^2 and the
+// quotient by about eps sigma_1^2 / sigma_2 <= eps ||A||_F^3 / |det A| relative: exact enough
+// where |det A| >= 1e-8 ||A||_F^3.  Below that (blocks of numerical rank 1 or 2, where the
+// quotient is rounding noise) the block goes through the pivoted QR (blk_sigma3_qr), a rare
+// branch taken before the adjugate so that A is not kept live through it.
 BEM_HD double blk_sigma3(const blk& A)
 {
-    // The quotient errs by at most about eps ||A||_F^3 / |det A| relative, so |r_33| is only
-    // needed where |det A| < 1e-8 ||A||_F^3; it is taken before the adjugate (A is not needed
-    // after it), and tested at once
     double f2 = 0.0;
 #pragma unroll
     for (int t = 0; t < 9; ++t) f2 += abs2(A.a[t]);
     const zd d0 = A.a[0] * (A.a[4] * A.a[8] - A.a[5] * A.a[7]) + A.a[1] * (A.a[5] * A.a[6] - A.a[3] * A.a[8]) +
                   A.a[2] * (A.a[3] * A.a[7] - A.a[4] * A.a[6]);
-    double r33 = 1.0e300;
-    if (abs2(d0) < 1e-16 * f2 * f2 * f2) r33 = blk_r33(A);
+    if (abs2(d0) < 1e-16 * f2 * f2 * f2) return blk_sigma3_qr(A);
     blk adj;
     zd det = blk_det_adj(A, adj);
     double ad = sqrt(abs2(det));
-    if (!(ad > 0.0) || !(r33 > 0.0)) return 0.0;
+    if (!(ad > 0.0)) return 0.0;
     // G = adj^H adj
     blk G;
 #pragma unroll
@@ -277,7 +312,7 @@ BEM_HD double blk_sigma3(const blk& A)
         }
     double l = herm3_lambda_max(G);
     if (!(l > 0.0)) return 0.0;
-    return fmin(ad / sqrt(l), r33);
+    return ad / sqrt(l);
 }
 
 // sigma_3 of a block of any magnitude (computed on A / s, s = blk_pow2_scale(A)); the plain
